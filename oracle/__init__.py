@@ -1,0 +1,11 @@
+"""FP64 CPU oracle for the off-axis digital-holography hot path.
+
+TEST INFRASTRUCTURE ONLY. Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import anything from this package.
+The GPU library never calls it and shares no code with it.
+"""
+from .holo_oracle import (  # noqa: F401
+    DEG, w_max_rad, tilt_bins, radius_bins, ifft_size, mode_list, mode_count,
+    window_origin, mask_bins, geometry, hermite_gauss_1d, spectrum_window,
+    field_from_window, overlap, power_normalise, process_frame, process_batch,
+)

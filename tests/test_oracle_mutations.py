@@ -1,0 +1,107 @@
+"""Plant plausible mistakes in a copy of the oracle (on the CPU) and check
+that the pins catch each one: a dropped term, a wrong sign or index, a
+transposed operand, a wrong scale, a wrong ordering."""
+import math
+import os
+import types
+
+import numpy as np
+import pytest
+
+import dh_synth
+
+SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                   "oracle", "holo_oracle.py")
+
+MUTATIONS = {
+    "drop_defocus": ('+ np.pi * gp["defocus"] * (xk[None, :] ** 2 + yl[:, None] ** 2) / lam', ''),
+    "tilt_sign": ('phi = (2 * np.pi * (gp["ax"]', 'phi = (-2 * np.pi * (gp["ax"]'),
+    "other_cross_term": ('((uu + ax) / rx) ** 2', '((uu - ax) / rx) ** 2'),
+    "field_pitch": ('px2=nx * p / wx', 'px2=p'),
+    "pixel_origin": ('xj = (np.arange(nx) - nx / 2.0) * p', 'xj = (np.arange(nx) - nx / 2.0 + 1) * p'),
+    "subpixel_sign": ('* p - gp["dx"]', '* p + gp["dx"]'),
+    "hermite_recurrence": ('- math.sqrt(n / (n + 1)) * psi_prev', '+ math.sqrt(n / (n + 1)) * psi_prev'),
+    "hg_norm": ("out * (2.0 ** 0.25 / math.sqrt(waist))", "out * (2.0 ** 0.5 / math.sqrt(waist))"),
+    "mode_transpose": ('cm[n, m] for (m, n)', 'cm[m, n] for (m, n)'),
+    "mode_order": ('for m in range(g, -1, -1):', 'for m in range(0, g + 1):'),
+    "ifft_scale": ('@ gx / (nx * ny)', '@ gx'),
+    "ifft_sign": ('gx = np.exp(2j', 'gx = np.exp(-2j'),
+    "quadrature_weight": ('* (g["px2"] * g["py2"])', '* (g["px2"])'),
+    "mask_radius": ('** 2 <= 1.0', '** 2 <= 0.8'),
+    "ifft_size_rule": ('need = int(math.floor(2.0 * r_bins)) + 1', 'need = int(math.floor(r_bins)) + 1'),
+    "tilt_axis_swap": ('ay = tilt_bins(params["tilt_deg"][pol][1], ny, p, lam)',
+                       'ay = tilt_bins(params["tilt_deg"][pol][0], ny, p, lam)'),
+    "power_norm": ('c / math.sqrt(pw)', 'c / pw'),
+}
+
+
+def _mutant(name):
+    src = open(SRC).read()
+    old, new = MUTATIONS[name]
+    assert src.count(old) == 1, name
+    mod = types.ModuleType("oracle_mutant_" + name)
+    exec(compile(src.replace(old, new), SRC + ":" + name, "exec"), mod.__dict__)
+    return mod
+
+
+def _checks(o):
+    """The pins, run against module `o`; returns the names that fail."""
+    bad = []
+    # closed-form recovery with defocus, tilt differing per axis, sub-pixel
+    # centre, two pols and non-square windows
+    cfg = dh_synth.config(1)
+    truth = dict(cfg["truth"], defocus=[0.2, -0.15], tilt_deg=[[1.45, 1.55], [1.52, 1.47]],
+                 beam_centre=[[0.3 * 20e-6, -0.2 * 20e-6], [-0.4 * 20e-6, 0.1 * 20e-6]])
+    cfg = dict(cfg, truth=truth)
+    f, c = dh_synth.make_frames(cfg, n_frames=1, quantise=False)
+    try:
+        r = o.process_frame(f[0], truth)
+        if not np.abs(r["coefs_norm"] - c[0]).max() < 1e-8:
+            bad.append("recovery")
+        # raw scale: unit-power coefficients times A = max|S|; ||c|| = A here
+        amp = math.sqrt(float(np.sum(np.abs(r["coefs"]) ** 2)))
+        ref_amp = _amp(truth, c[0])
+        if not abs(amp - ref_amp) < 1e-8 * ref_amp:
+            bad.append("scale")
+    except Exception:
+        bad.append("crash")
+    # paper's FFT/IFFT size pairs
+    lam, pix = 1565e-9, 20e-6
+    wmax_deg = o.w_max_rad(pix, lam) / o.DEG
+    for fft, ifft in [(64, 32), (128, 48), (256, 96), (512, 176), (1024, 336)]:
+        if o.ifft_size(o.radius_bins(0.32 * wmax_deg, fft, pix, lam)) != ifft:
+            bad.append("sizes")
+            break
+    # mask area equals the window ellipse
+    g = o.geometry(truth)
+    m = g["pols"][0]["mask"]
+    if abs(m.sum() - math.pi * g["rx"] * g["ry"]) > 0.02 * math.pi * g["rx"] * g["ry"]:
+        bad.append("mask_area")
+    # mode list order printed in the tests
+    if o.mode_list(3) != [(0, 0), (1, 0), (0, 1), (2, 0), (1, 1), (0, 2)]:
+        bad.append("order")
+    return bad
+
+
+def _amp(truth, c):
+    half = truth["frame_w"] // truth["pol_count"]
+    best = 0.0
+    modes = [(m, g - m) for g in range(truth["max_mg"]) for m in range(g, -1, -1)]
+    for pol in range(truth["pol_count"]):
+        x = (np.arange(half) - half // 2) * truth["pixel_size"] - truth["beam_centre"][pol][0]
+        y = (np.arange(truth["frame_h"]) - truth["frame_h"] // 2) * truth["pixel_size"] - truth["beam_centre"][pol][1]
+        s = sum(c[pol][k] * np.outer(dh_synth.hg_closed_form(n, y, truth["waist"]),
+                                     dh_synth.hg_closed_form(m, x, truth["waist"]))
+                for k, (m, n) in enumerate(modes))
+        best = max(best, float(np.abs(s).max()))
+    return best
+
+
+def test_unmutated_oracle_passes_the_checks():
+    from oracle import holo_oracle
+    assert _checks(holo_oracle) == []
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_mutation_is_caught(name):
+    assert _checks(_mutant(name)) != [], name

@@ -1,0 +1,298 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Nothing here compares the oracle with itself: each check uses a printed
+value, a closed form, an independent evaluation (the synthesiser's HG closed
+form, scipy/numpy library routines) or an invariant of the definition.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import special
+
+import dh_synth
+import oracle
+from oracle import holo_oracle as ho
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _read_table(name):
+    rows = []
+    with open(os.path.join(GOLD, name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append(line.split())
+    return rows
+
+
+# ---------------------------------------------------------------- geometry
+def test_worked_geometry_numbers():
+    g = {k: v for k, v, _ in _read_table("worked_geometry.txt")}
+    lam, pix = float(g["wavelength_m"]), float(g["pixel_m"])
+    wmax_deg = oracle.w_max_rad(pix, lam) / oracle.DEG
+    assert round(wmax_deg, 2) == float(g["w_max_deg"])
+    # the printed ratio is 1/3.12, the printed formula sqrt2/(3+sqrt2) is 0.32038
+    assert abs(float(g["window_ratio"]) - 1 / 3.12) < 1e-6
+    assert abs(math.sqrt(2) / (3 + math.sqrt(2)) - 0.320377) < 1e-6
+    # the printed 0.719 and 1.525 carry a last-digit rounding slip
+    # (0.3205 * 2.2417 = 0.7185); pin them to within one printed unit
+    wc = 0.3205 * wmax_deg
+    assert abs(wc - float(g["window_radius_deg"])) <= 1e-3
+    tilt = 3 * wc / math.sqrt(2)
+    assert abs(tilt - float(g["tilt_deg"])) <= 2e-3
+    # wrap variant: positive root of 8w^2 + 4w - 2 = 0 (the printed form is garbled)
+    assert round((-2 + math.sqrt(68)) / 16, 4) == float(g["wrap_ratio"])
+
+
+def test_tilt_and_radius_bins():
+    # at the paper's geometry the 1.525 deg tilt sits at 3 w_c / sqrt2 of the window
+    lam, pix, n = 1565e-9, 20e-6, 128
+    wmax_deg = oracle.w_max_rad(pix, lam) / oracle.DEG
+    a = oracle.tilt_bins(wmax_deg, n, pix, lam)
+    assert abs(a - n / 2) < 1e-12          # w_max maps to the Nyquist bin
+    r = oracle.radius_bins(wmax_deg, n, pix, lam)
+    assert abs(r - n / 2) < 1e-12
+    assert abs(oracle.radius_bins(0.32 * wmax_deg, n, pix, lam) - 20.48) < 1e-12
+
+
+@pytest.mark.parametrize("ratio", [0.32, 0.320513, 0.320377])
+def test_benchmark_fft_ifft_pairs(ratio):
+    lam, pix = 1565e-9, 20e-6
+    wmax_deg = oracle.w_max_rad(pix, lam) / oracle.DEG
+    for fft, ifft in _read_table("benchmark_sizes.txt"):
+        r = oracle.radius_bins(ratio * wmax_deg, int(fft), pix, lam)
+        assert oracle.ifft_size(r) == int(ifft), (fft, ratio)
+
+
+def test_ifft_size_rule_edges():
+    assert oracle.ifft_size(0.2) == 16
+    assert oracle.ifft_size(7.99) == 16
+    assert oracle.ifft_size(8.0) == 32      # 2r+1 = 17 bins need more than 16
+    assert oracle.ifft_size(163.84) == 336  # 16*21
+    assert oracle.ifft_size(327.68) == 672  # 656 = 16*41 has a prime factor 41
+
+
+def test_mode_counts_and_order():
+    assert oracle.mode_count(0) == 0
+    assert oracle.mode_list(1) == [(0, 0)]   # groupCount=1: fundamental only
+    for g, n in [(4, 10), (9, 45), (20, 210), (30, 465)]:
+        assert oracle.mode_count(g) == n == g * (g + 1) // 2
+    assert oracle.mode_list(3) == [(0, 0), (1, 0), (0, 1), (2, 0), (1, 1), (0, 2)]
+
+
+def test_window_origin():
+    p = dh_synth.config(1)["params"]
+    assert oracle.window_origin(p, 0)[:2] == (0, 0)
+    assert oracle.window_origin(p, 1)[:2] == (320, 0)
+    q = dict(p, beam_centre=[[3.4 * 20e-6, -1.6 * 20e-6], [0, 0]], fft_w=256)
+    x0, y0, dx, dy = oracle.window_origin(q, 0)
+    assert (x0, y0) == (160 + 3 - 128, 256 - 2 - 256)
+    assert abs(dx - 0.4 * 20e-6) < 1e-18 and abs(dy - 0.4 * 20e-6) < 1e-18
+
+
+# ---------------------------------------------------------------- HG basis
+def test_hg_matches_explicit_hermite_polynomials():
+    x = np.linspace(-1e-3, 1e-3, 101)
+    w = 300e-6
+    u = oracle.hermite_gauss_1d(4, x, w)
+    s = math.sqrt(2) * x / w
+    hs = [np.ones_like(s), 2 * s, 4 * s ** 2 - 2, 8 * s ** 3 - 12 * s]
+    for n in range(4):
+        ref = (2 / math.pi) ** 0.25 / math.sqrt(2 ** n * math.factorial(n) * w) * hs[n] * np.exp(-x * x / w / w)
+        assert np.allclose(u[n], ref, rtol=1e-13, atol=1e-13 * np.abs(ref).max())
+
+
+def test_hg_matches_scipy_to_order_30():
+    x = np.linspace(-3e-3, 3e-3, 401)
+    w = 500e-6
+    u = oracle.hermite_gauss_1d(30, x, w)
+    s = math.sqrt(2) * x / w
+    for n in range(30):
+        ref = special.eval_hermite(n, s) * np.exp(
+            0.25 * math.log(2 / math.pi) - 0.5 * (n * math.log(2) + math.lgamma(n + 1) + math.log(w)) - x * x / w / w)
+        assert np.abs(u[n] - ref).max() < 1e-10 * np.abs(ref).max(), n
+
+
+@pytest.mark.parametrize("idx,groups", [(0, 4), (1, 9), (2, 20), (4, 30)])
+def test_hg_discrete_orthonormality(idx, groups):
+    cfg = dh_synth.config(idx)
+    g = oracle.geometry(cfg["params"])
+    w = cfg["params"]["waist"]
+    for n_pts, dp in [(g["wx"], g["px2"]), (g["wy"], g["py2"])]:
+        x = (np.arange(n_pts) - n_pts / 2) * dp
+        u = oracle.hermite_gauss_1d(groups, x, w)
+        gram = u @ u.T * dp
+        tol = 1e-12 if groups <= 9 else 2e-4   # high orders reach the grid edge at 128 px
+        assert np.abs(gram - np.eye(groups)).max() < tol
+
+
+def test_gaussian_overlap_closed_form():
+    x = np.linspace(-5e-3, 5e-3, 20001)
+    dx = x[1] - x[0]
+    w1, w2 = 300e-6, 470e-6
+    u1 = oracle.hermite_gauss_1d(1, x, w1)[0]
+    u2 = oracle.hermite_gauss_1d(1, x, w2)[0]
+    assert abs(np.sum(u1 * u2) * dx - math.sqrt(2 * w1 * w2 / (w1 ** 2 + w2 ** 2))) < 1e-12
+
+
+# ---------------------------------------------------------------- spectrum
+def _tone_params(n=128):
+    p = dh_synth.config(0)["params"]
+    return dict(p, frame_w=n, frame_h=n, fft_w=n, fft_h=n, max_mg=0)
+
+
+def test_pure_tone_lands_in_one_bin():
+    p = _tone_params()
+    g = oracle.geometry(p)
+    gp = g["pols"][0]
+    u0, v0 = 40, 45                    # tone whose conjugate bin (-40,-45) is in the window
+    assert gp["mask"][list(gp["vs"]).index(-v0), list(gp["us"]).index(-u0)]
+    j = np.arange(128)
+    frame = np.cos(2 * np.pi * (u0 * j[None, :] / 128 + v0 * j[:, None] / 128))
+    win = oracle.spectrum_window(frame, g, 0)
+    q = (-v0 % g["wy"], -u0 % g["wx"])
+    expect = 128 * 128 / 2 * (-1) ** (u0 + v0)
+    assert abs(win[q] - expect) < 1e-8
+    win[q] = 0
+    assert np.abs(win).max() < 1e-8
+
+
+def test_spectrum_matches_numpy_fft():
+    rng = np.random.default_rng(5)
+    p = dict(dh_synth.config(1)["params"], beam_centre=[[0, 0], [0, 0]])
+    frame = rng.random((512, 640))
+    g = oracle.geometry(p)
+    for pol in range(2):
+        gp = g["pols"][pol]
+        win = oracle.spectrum_window(frame, g, pol)
+        sub = frame[:, pol * 320:(pol + 1) * 320]
+        f = np.fft.fft2(sub)
+        for iv, v in enumerate(gp["vs"]):
+            for iu, u in enumerate(gp["us"]):
+                ref = f[v % 512, u % 320] * (1 - 2 * (int(u + v) % 2)) if gp["mask"][iv, iu] else 0
+                assert abs(win[v % g["wy"], u % g["wx"]] - ref) < 1e-8 * 512 * 320
+
+
+def test_mask_is_the_paper_circle_and_does_not_alias():
+    for idx in (0, 1, 4):
+        p = dh_synth.config(idx)["truth"]
+        g = oracle.geometry(p)
+        for gp in g["pols"]:
+            m = gp["mask"]
+            cols = gp["us"][m.any(axis=0)]
+            rows = gp["vs"][m.any(axis=1)]
+            assert len(set(cols % g["wx"])) == len(cols)
+            assert len(set(rows % g["wy"])) == len(rows)
+            # area of the ellipse in bins
+            area = math.pi * g["rx"] * g["ry"]
+            assert abs(m.sum() - area) / area < 0.02
+
+
+# ---------------------------------------------------------------- field
+def test_single_bin_at_the_cross_term_gives_a_flat_field():
+    p = _tone_params()
+    p["tilt_deg"] = [[oracle.DEG ** -1 * 43 * 1565e-9 / (128 * 20e-6)] * 2, [0, 0]]   # a = 43 bins
+    g = oracle.geometry(p)
+    assert abs(g["pols"][0]["ax"] - 43) < 1e-9
+    j = np.arange(128)
+    frame = np.cos(2 * np.pi * (43 * j[None, :] / 128 + 43 * j[:, None] / 128))
+    res = oracle.process_frame(frame, p, g)
+    e = res["field"][0]
+    assert np.abs(e - 0.5).max() < 1e-10
+
+
+# ---------------------------------------------------------------- end to end
+@pytest.mark.parametrize("idx,cam", [(0, 0), (1, 0), (3, 0), (3, 1), (4, 0)])
+def test_closed_form_recovery(idx, cam):
+    cfg = dh_synth.config(idx, cam)
+    truth = cfg["truth"]
+    frames, coefs = dh_synth.make_frames(cfg, n_frames=1, quantise=False)
+    res = oracle.process_frame(frames[0], truth)
+    assert np.abs(res["coefs_norm"] - coefs[0]).max() < 1e-9
+    # raw scale: the field is A * S with A = max|S| over the frame
+    amp = _signal_amplitude(truth, coefs[0])
+    assert np.abs(res["coefs"] - amp * coefs[0]).max() < 1e-9 * amp
+
+
+def _signal_amplitude(truth, c):
+    # max|S| recomputed independently of the hologram: |S+R|^2 - |R|^2 ... use
+    # the synthesiser's own modes through its public closed form
+    fw, fh, npol = truth["frame_w"], truth["frame_h"], truth["pol_count"]
+    half = fw // npol
+    best = 0.0
+    modes = ho.mode_list(truth["max_mg"])
+    for pol in range(npol):
+        x = (np.arange(half) - half // 2) * truth["pixel_size"] - truth["beam_centre"][pol][0]
+        y = (np.arange(fh) - fh // 2) * truth["pixel_size"] - truth["beam_centre"][pol][1]
+        s = 0
+        for k, (m, n) in enumerate(modes):
+            s = s + c[pol][k] * np.outer(dh_synth.hg_closed_form(n, y, truth["waist"]),
+                                         dh_synth.hg_closed_form(m, x, truth["waist"]))
+        best = max(best, float(np.abs(s).max()))
+    return best
+
+
+def test_identity_transfer_one_mode_per_frame():
+    # frame i carries HG mode i alone: the coefficient matrix is the identity
+    cfg = dh_synth.config(0)
+    truth = cfg["truth"]
+    nm = oracle.mode_count(truth["max_mg"])
+    mat = np.zeros((nm, nm), dtype=complex)
+    for i in range(nm):
+        c = np.zeros((1, nm), dtype=complex)
+        c[0, i] = 1.0
+        f = dh_synth.forward_hologram(truth, c)
+        mat[i] = oracle.process_frame(f, truth)["coefs_norm"][0]
+    assert np.abs(mat - np.eye(nm)).max() < 1e-9
+
+
+def test_defocus_and_subpixel_centre_are_removed():
+    cfg = dh_synth.config(0)
+    truth = dict(cfg["truth"], defocus=[0.3, 0.0],
+                 beam_centre=[[0.3 * 20e-6, -0.45 * 20e-6], [0, 0]])
+    cfg = dict(cfg, truth=truth)
+    frames, coefs = dh_synth.make_frames(cfg, n_frames=1, quantise=False)
+    ok = oracle.process_frame(frames[0], truth)["coefs_norm"]
+    assert np.abs(ok - coefs[0]).max() < 1e-8
+    wrong = oracle.process_frame(frames[0], dict(truth, defocus=[0.0, 0.0]))["coefs_norm"]
+    assert np.abs(wrong - coefs[0]).max() > 1e-2
+
+
+def test_wrong_cross_term_is_not_selected():
+    # a reference tilted the other way puts S*R where SR* is expected
+    cfg = dh_synth.config(0)
+    truth = cfg["truth"]
+    frames, coefs = dh_synth.make_frames(cfg, n_frames=1, quantise=False)
+    flipped = dict(truth, tilt_deg=[[-1.5, -1.5], [0, 0]])
+    f2 = dh_synth.forward_hologram(flipped, coefs[0])
+    res = oracle.process_frame(f2, truth)["coefs_norm"]
+    assert np.abs(res - coefs[0]).max() > 0.1
+
+
+def test_linearity_constant_frame_and_truncation():
+    cfg = dh_synth.config(0)
+    p = cfg["params"]
+    f, _ = dh_synth.make_frames(cfg, n_frames=2, quantise=False)
+    a = oracle.process_frame(f[0], p)["coefs"]
+    b = oracle.process_frame(f[1], p)["coefs"]
+    ab = oracle.process_frame(2.5 * f[0] - 0.75 * f[1], p)["coefs"]
+    assert np.abs(ab - (2.5 * a - 0.75 * b)).max() < 1e-10 * np.abs(a).max()
+    z = oracle.process_frame(np.full((128, 128), 1234.0), p)["coefs"]
+    assert np.abs(z).max() < 1e-9
+    t = oracle.process_frame(f[0], dict(p, max_mg=3))["coefs"]
+    assert np.abs(t[0] - a[0][:6]).max() < 1e-12 * np.abs(a).max()
+
+
+def test_swapping_pol_halves_swaps_outputs():
+    cfg = dh_synth.config(1)
+    p = dict(cfg["params"], tilt_deg=[[1.5, 1.5], [1.45, 1.55]], defocus=[0.02, -0.03])
+    cfg = dict(cfg, truth=p, noise=False)
+    f, _ = dh_synth.make_frames(cfg, n_frames=1, quantise=False)
+    r = oracle.process_frame(f[0], p)
+    sw = np.concatenate([f[0][:, 320:], f[0][:, :320]], axis=1)
+    q = dict(p, tilt_deg=p["tilt_deg"][::-1], defocus=p["defocus"][::-1])
+    r2 = oracle.process_frame(sw, q)
+    assert np.allclose(r2["coefs"][::-1], r["coefs"], rtol=0, atol=1e-9 * np.abs(r["coefs"]).max())
