@@ -1,0 +1,201 @@
+/*
+ * dh.h - C ABI of the MI355X off-axis digital-holography library (libdh.so).
+ *
+ * The library runs the per-frame pipeline of the digHolo user guide
+ * (arXiv 2204.02348, Background, "digHolo processing pipeline"):
+ *   1. FFT of the camera-frame window(s) around the beam centre;
+ *   2. selection of the off-axis SR* term inside a circular Fourier window
+ *      around the reference-tilt position, inverse FFT at the Fourier-window
+ *      size (IFFT resolution mode 1), and removal of the reference tilt and
+ *      defocus (API section "Alignment");
+ *   3. projection of the field on Hermite-Gaussian modes HG(m,n), m+n < G
+ *      (API section "Modal basis"), plus a per-frame power normalisation.
+ * Every step runs in hand-written gfx950 kernels on the caller's HIP stream.
+ *
+ * Conventions (all fixed by the plan; see each field):
+ *   - frames are row-major [batch][frame_h][frame_w], x fastest;
+ *   - two polarisations occupy the left and right halves of the frame width
+ *     (pipeline step 1); each has its own FFT window of fft_w x fft_h;
+ *   - angles in degrees, lengths in metres, defocus in dioptre ("units");
+ *   - complex values are {float re, im} pairs (complex64);
+ *   - coefficient layout [batch][pol][mode]: one block of modes per
+ *     polarisation (HHH..VVV), as digHoloBasisGetCoefs returns them;
+ *   - mode order: group g = m+n ascending, inside a group m descending
+ *     (m is the x order, n the y order).
+ *
+ * Error codes keep the paper's numbering ("Error codes").
+ * Thread safety: calls on different handles may run concurrently; a handle
+ * is used by one host thread at a time.
+ */
+#ifndef DH_H
+#define DH_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DH_SUCCESS 0
+#define DH_ERR_ERROR 1
+#define DH_ERR_INVALIDHANDLE 2
+#define DH_ERR_NULLPOINTER 3
+#define DH_ERR_INVALIDDIMENSION 5
+#define DH_ERR_INVALIDPOLARISATION 6
+#define DH_ERR_INVALIDAXIS 7
+#define DH_ERR_INVALIDARGUMENT 8
+#define DH_ERR_MEMORYALLOCATION 9
+
+#define DH_INPUT_F32 0  /* frames are float32 */
+#define DH_INPUT_U16 1  /* frames are uint16 camera counts */
+
+#define DH_PREC_FP32 0       /* HG overlap on FP32 MFMA */
+#define DH_PREC_SPLIT_BF16 1 /* HG overlap as split hi/lo BF16 MFMA, FP32 accumulate */
+#define DH_PREC_SPLIT_FP16 2 /* HG overlap as split hi/lo FP16 MFMA, FP32 accumulate */
+
+typedef struct dh_c64 {
+  float re, im;
+} dh_c64;
+
+typedef int dh_handle;
+
+/* Plan parameters: the paper's statement of the problem. */
+typedef struct dh_params {
+  int frame_w, frame_h;       /* camera frame, pixels; multiples of 16 ("Frame buffer") */
+  int pol_count;              /* 1 or 2 polarisations ("Frame buffer", PolCount) */
+  int fft_w, fft_h;           /* FFT window per polarisation, floored to a multiple of 16
+                                 ("Window sizes", fftWindowSizeX/Y) */
+  double pixel_size;          /* camera pixel pitch, m */
+  double wavelength;          /* m */
+  double beam_centre[2][2];   /* [pol][x,y], m, from the centre pixel (index half/2) of the
+                                 pol's half of the frame ("Alignment", BeamCentre) */
+  double window_radius_deg;   /* Fourier window radius w_c, degrees ("Window sizes") */
+  double tilt_deg[2][2];      /* [pol][x,y] reference tilt, degrees ("Alignment") */
+  double defocus[2];          /* [pol] reference defocus, dioptre ("Alignment") */
+  double waist;               /* HG waist (1/e^2 intensity radius), m, shared by both pols */
+  int max_mg;                 /* G: modes HG(m,n) with m+n < G; 0 = no decomposition */
+  int input_dtype;            /* DH_INPUT_F32 or DH_INPUT_U16 */
+  int precision;              /* DH_PREC_* */
+  int ifft_mode;              /* 1: IFFT at the Fourier-window size (the only mode built) */
+  int keep_window;            /* nonzero: store each frame's Fourier window (dh_get_window) */
+  int keep_fields;            /* nonzero: store each frame's field (dh_get_fields) */
+} dh_params;
+
+/* Geometry derived by the plan (all FP64 on the host). */
+typedef struct dh_plan_info {
+  int fft_w, fft_h;           /* effective FFT window (after flooring) */
+  int ifft_w, ifft_h;         /* field size W: smallest multiple of 16 with prime factors
+                                 <= 13 that is >= floor(2 r) + 1 bins */
+  int box_w, box_h;           /* spectrum bins spanned by the Fourier window (max over pols) */
+  int modes;                  /* modes per polarisation, G (G+1) / 2 */
+  int x0[2], y0[2];           /* window origins in the frame, pixels */
+  double ax[2], ay[2];        /* cross-term position: SR* sits at bins (-ax, -ay) */
+  double rx, ry;              /* window radius in bins along x, y */
+  double pitch_x, pitch_y;    /* field sample pitch p' = N p / W, m */
+  size_t device_bytes;        /* device memory the plan allocates */
+  int chunk;                  /* frames per internal launch chunk */
+} dh_plan_info;
+
+/*
+ * Validate `p` and derive the plan geometry on the host; touches no GPU.
+ * Returns DH_SUCCESS and fills *info (if non-NULL), or:
+ *   DH_ERR_NULLPOINTER        p is NULL;
+ *   DH_ERR_INVALIDDIMENSION   frame or window size not a positive multiple of 16,
+ *                             window outside the frame, or an FFT/IFFT length
+ *                             this build does not provide;
+ *   DH_ERR_INVALIDPOLARISATION pol_count not 1 or 2;
+ *   DH_ERR_INVALIDARGUMENT    pixel/wavelength/radius/waist not > 0, max_mg outside
+ *                             0..32, unknown dtype/precision/ifft_mode, or a Fourier
+ *                             window wider than the spectrum.
+ * max_batch < 1 is taken as 1 (the paper clamps batchCount the same way).
+ */
+int dh_plan_check(const dh_params* p, int max_batch, dh_plan_info* info);
+
+/*
+ * Build a plan: validates like dh_plan_check, then allocates every device
+ * table and workspace on the current HIP device and builds the tables
+ * (phase tables and masks in FP64 on the host, HG tables by an FP64
+ * recurrence on the GPU). The library owns all of it until dh_destroy.
+ * hbm_budget: if nonzero and the plan would need more device bytes,
+ * DH_ERR_MEMORYALLOCATION is returned before anything is allocated (also on
+ * an allocation failure). Writes the new handle to *out.
+ */
+int dh_plan(const dh_params* p, int max_batch, size_t hbm_budget, dh_handle* out);
+
+/*
+ * Process `batch` frames (device pointer, [batch][frame_h][frame_w] of the
+ * plan's input_dtype) asynchronously on `stream` (a hipStream_t; NULL = the
+ * default stream). The caller keeps ownership of `frames`; they must stay
+ * valid and unchanged until the stream has passed this work. batch < 1 is
+ * taken as 1; batch > max_batch returns DH_ERR_INVALIDDIMENSION.
+ * Errors: DH_ERR_INVALIDHANDLE, DH_ERR_NULLPOINTER, DH_ERR_ERROR (launch).
+ */
+int dh_process_batch(dh_handle h, const void* frames, int batch, void* stream);
+
+/*
+ * Coefficients of the last processed batch, [batch][pol][mode] complex64.
+ * host_out non-NULL: waits for the stream of the last dh_process_batch and
+ * copies batch*pols*modes values. dev_out non-NULL: receives the library's
+ * device buffer (valid until the next process call or dh_destroy).
+ * normalised nonzero: each frame divided by the square root of its total
+ * power over both polarisations (computed in FP64); 0: raw coefficients, in
+ * field units. batch, modes, pols (each may be NULL) receive the sizes. With
+ * max_mg = 0 this succeeds with modes = 0 and *dev_out = NULL.
+ */
+int dh_mode_coefs(dh_handle h, dh_c64* host_out, const dh_c64** dev_out, int* batch, int* modes,
+                  int* pols, int normalised);
+
+/*
+ * Fourier windows of the last batch (needs keep_window): [batch][pol][ifft_h][ifft_w]
+ * complex64; bin (u, v) of the beam-centred spectrum is stored at
+ * (v mod ifft_h, u mod ifft_w) when it lies inside the window, zero elsewhere
+ * ("Fourier plane window", digHoloGetFourierPlaneWindow). Sizes as above;
+ * DH_ERR_ERROR if the plan does not keep windows.
+ */
+int dh_get_window(dh_handle h, dh_c64* host_out, const dh_c64** dev_out, int* batch, int* pols,
+                  int* width, int* height);
+
+/*
+ * Reconstructed fields of the last batch (needs keep_fields):
+ * [batch][pol][ifft_h][ifft_w] complex64 on the grid x'_k = (k - W/2) p'
+ * around the beam centre (digHoloGetFields, here in FP32 rather than int16).
+ */
+int dh_get_fields(dh_handle h, dh_c64* host_out, const dh_c64** dev_out, int* batch, int* pols,
+                  int* width, int* height);
+
+/* Copy of the plan's parameters / derived geometry. */
+int dh_get_params(dh_handle h, dh_params* out);
+int dh_get_plan_info(dh_handle h, dh_plan_info* out);
+
+/*
+ * Per-stage timing, the counterpart of the paper's per-stage benchmark rates
+ * ("Multi-threading, performance and benchmarking"): while enabled, every
+ * dh_process_batch records a HIP event on its stream after each kernel
+ * launch. dh_stage_times waits for the last of them and returns, per stage,
+ * the summed milliseconds and the number of launches since timing was
+ * enabled or last read, then starts a new count. Stages:
+ *   0 DH_STAGE_FFT   frame load + FFT along x (row pass)
+ *   1 DH_STAGE_CROP  FFT along y + window crop/mask + IFFT along y
+ *   2 DH_STAGE_FIELD IFFT along x + tilt/defocus removal + HG overlap
+ *   3 DH_STAGE_NORM  per-frame FP64 power normalisation
+ * ms and launches point to DH_STAGE_COUNT entries each.
+ */
+#define DH_STAGE_FFT 0
+#define DH_STAGE_CROP 1
+#define DH_STAGE_FIELD 2
+#define DH_STAGE_NORM 3
+#define DH_STAGE_COUNT 4
+int dh_set_stage_timing(dh_handle h, int enabled);
+int dh_stage_times(dh_handle h, double* ms, int* launches);
+
+/* Error code of the last failing call on h (0 if none), 2 for a bad handle. */
+int dh_last_error(dh_handle h);
+
+/* Free every device allocation of h; the handle becomes invalid. */
+int dh_destroy(dh_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DH_H */

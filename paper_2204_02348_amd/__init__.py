@@ -1,0 +1,248 @@
+"""Python binding of libdh.so (argument marshalling only).
+
+Every step of the holography path runs in the library's gfx950 kernels; this
+module converts arguments and results. It raises if the library is missing:
+there is no fallback path.
+
+Device memory and streams come from the caller (e.g. PyTorch tensors and
+streams): pass anything with ``data_ptr()`` (or an int address) as frames and
+a ``torch.cuda.Stream`` (or an int hipStream_t, or None) as stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libdh.so")
+
+SUCCESS = 0
+ERR_ERROR = 1
+ERR_INVALIDHANDLE = 2
+ERR_NULLPOINTER = 3
+ERR_INVALIDDIMENSION = 5
+ERR_INVALIDPOLARISATION = 6
+ERR_INVALIDAXIS = 7
+ERR_INVALIDARGUMENT = 8
+ERR_MEMORYALLOCATION = 9
+
+INPUT_F32 = 0
+INPUT_U16 = 1
+PREC_FP32 = 0
+PREC_SPLIT_BF16 = 1
+PREC_SPLIT_FP16 = 2
+
+EXPORTS = ["dh_plan_check", "dh_plan", "dh_process_batch", "dh_mode_coefs", "dh_get_window",
+           "dh_get_fields", "dh_get_params", "dh_get_plan_info", "dh_set_stage_timing", "dh_stage_times",
+           "dh_last_error", "dh_destroy"]
+STAGES = ["fft_x", "fft_y_crop_ifft_y", "ifft_x_tilt_overlap", "power_norm"]
+
+
+class DhError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what} failed with error {code}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("frame_w", C.c_int), ("frame_h", C.c_int), ("pol_count", C.c_int),
+        ("fft_w", C.c_int), ("fft_h", C.c_int),
+        ("pixel_size", C.c_double), ("wavelength", C.c_double),
+        ("beam_centre", (C.c_double * 2) * 2), ("window_radius_deg", C.c_double),
+        ("tilt_deg", (C.c_double * 2) * 2), ("defocus", C.c_double * 2), ("waist", C.c_double),
+        ("max_mg", C.c_int), ("input_dtype", C.c_int), ("precision", C.c_int),
+        ("ifft_mode", C.c_int), ("keep_window", C.c_int), ("keep_fields", C.c_int),
+    ]
+
+
+class PlanInfo(C.Structure):
+    _fields_ = [
+        ("fft_w", C.c_int), ("fft_h", C.c_int), ("ifft_w", C.c_int), ("ifft_h", C.c_int),
+        ("box_w", C.c_int), ("box_h", C.c_int), ("modes", C.c_int),
+        ("x0", C.c_int * 2), ("y0", C.c_int * 2),
+        ("ax", C.c_double * 2), ("ay", C.c_double * 2), ("rx", C.c_double), ("ry", C.c_double),
+        ("pitch_x", C.c_double), ("pitch_y", C.c_double),
+        ("device_bytes", C.c_size_t), ("chunk", C.c_int),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libdh.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2204_02348_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        c64p = C.c_void_p
+        L.dh_plan_check.argtypes = [C.POINTER(Params), C.c_int, C.POINTER(PlanInfo)]
+        L.dh_plan.argtypes = [C.POINTER(Params), C.c_int, C.c_size_t, C.POINTER(C.c_int)]
+        L.dh_process_batch.argtypes = [C.c_int, C.c_void_p, C.c_int, C.c_void_p]
+        L.dh_mode_coefs.argtypes = [C.c_int, c64p, C.POINTER(C.c_void_p), C.POINTER(C.c_int),
+                                    C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_int]
+        for f in (L.dh_get_window, L.dh_get_fields):
+            f.argtypes = [C.c_int, c64p, C.POINTER(C.c_void_p), C.POINTER(C.c_int), C.POINTER(C.c_int),
+                          C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.dh_get_params.argtypes = [C.c_int, C.POINTER(Params)]
+        L.dh_get_plan_info.argtypes = [C.c_int, C.POINTER(PlanInfo)]
+        L.dh_set_stage_timing.argtypes = [C.c_int, C.c_int]
+        L.dh_stage_times.argtypes = [C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)]
+        L.dh_last_error.argtypes = [C.c_int]
+        L.dh_destroy.argtypes = [C.c_int]
+        for name in EXPORTS:
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+_DTYPES = {"f32": INPUT_F32, "u16": INPUT_U16, INPUT_F32: INPUT_F32, INPUT_U16: INPUT_U16}
+_PRECS = {"fp32": PREC_FP32, "split_bf16": PREC_SPLIT_BF16, "split_fp16": PREC_SPLIT_FP16,
+          PREC_FP32: PREC_FP32, PREC_SPLIT_BF16: PREC_SPLIT_BF16, PREC_SPLIT_FP16: PREC_SPLIT_FP16}
+
+
+def make_params(d: dict) -> Params:
+    """dh_params from a dict with the field names of include/dh.h (the
+    recipes' keys); input_dtype 'f32'/'u16', precision 'fp32'/'split_bf16'/
+    'split_fp16' or the numeric codes."""
+    p = Params()
+    p.frame_w, p.frame_h, p.pol_count = d["frame_w"], d["frame_h"], d["pol_count"]
+    p.fft_w, p.fft_h = d["fft_w"], d["fft_h"]
+    p.pixel_size, p.wavelength = d["pixel_size"], d["wavelength"]
+    for q in range(2):
+        for a in range(2):
+            p.beam_centre[q][a] = d["beam_centre"][q][a] if q < len(d["beam_centre"]) else 0.0
+            p.tilt_deg[q][a] = d["tilt_deg"][q][a] if q < len(d["tilt_deg"]) else 0.0
+        p.defocus[q] = d["defocus"][q] if q < len(d["defocus"]) else 0.0
+    p.window_radius_deg = d["window_radius_deg"]
+    p.waist = d["waist"]
+    p.max_mg = d["max_mg"]
+    dt, pr = d.get("input_dtype", "f32"), d.get("precision", "fp32")
+    p.input_dtype = dt if isinstance(dt, int) else _DTYPES[dt]
+    p.precision = pr if isinstance(pr, int) else _PRECS[pr]
+    p.ifft_mode = d.get("ifft_mode", 1)
+    p.keep_window = int(bool(d.get("keep_window", 0)))
+    p.keep_fields = int(bool(d.get("keep_fields", 0)))
+    return p
+
+
+def plan_check(d: dict, max_batch: int = 1):
+    """(error code, PlanInfo) from the host-only validation; no GPU needed."""
+    info = PlanInfo()
+    p = make_params(d)
+    rc = lib().dh_plan_check(C.byref(p), max_batch, C.byref(info))
+    return rc, info
+
+
+def _ptr(x) -> int:
+    if x is None:
+        return 0
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    if hasattr(x, "cuda_stream"):
+        return x.cuda_stream
+    raise TypeError(type(x))
+
+
+def _stream(s) -> int:
+    if s is None:
+        return 0
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+class Plan:
+    """A dh_plan handle: tables and workspaces resident on the current device."""
+
+    def __init__(self, d: dict, max_batch: int = 1, hbm_budget: int = 0):
+        self._p = make_params(d)
+        h = C.c_int(-1)
+        rc = lib().dh_plan(C.byref(self._p), max_batch, hbm_budget, C.byref(h))
+        if rc != SUCCESS:
+            raise DhError(rc, "dh_plan")
+        self.handle = h.value
+        self.max_batch = max_batch
+        info = PlanInfo()
+        rc = lib().dh_get_plan_info(self.handle, C.byref(info))
+        if rc != SUCCESS:
+            raise DhError(rc, "dh_get_plan_info")
+        self.info = info
+
+    def process(self, frames, batch: int, stream=None):
+        rc = lib().dh_process_batch(self.handle, C.c_void_p(_ptr(frames)), batch, C.c_void_p(_stream(stream)))
+        if rc != SUCCESS:
+            raise DhError(rc, "dh_process_batch")
+
+    def coefs(self, normalised: bool = True) -> np.ndarray:
+        """[batch][pol][mode] complex64 on the host (waits for the stream)."""
+        b, m, p = C.c_int(), C.c_int(), C.c_int()
+        dev = C.c_void_p()
+        rc = lib().dh_mode_coefs(self.handle, None, C.byref(dev), C.byref(b), C.byref(m), C.byref(p), int(normalised))
+        if rc != SUCCESS:
+            raise DhError(rc, "dh_mode_coefs")
+        out = np.empty((b.value, p.value, m.value), dtype=np.complex64)
+        if m.value:
+            rc = lib().dh_mode_coefs(self.handle, out.ctypes.data_as(C.c_void_p), None, None, None, None,
+                                     int(normalised))
+            if rc != SUCCESS:
+                raise DhError(rc, "dh_mode_coefs")
+        return out
+
+    def coefs_device_ptr(self, normalised: bool = True) -> int:
+        dev = C.c_void_p()
+        rc = lib().dh_mode_coefs(self.handle, None, C.byref(dev), None, None, None, int(normalised))
+        if rc != SUCCESS:
+            raise DhError(rc, "dh_mode_coefs")
+        return dev.value or 0
+
+    def _plane(self, fn, what) -> np.ndarray:
+        b, p, w, h = C.c_int(), C.c_int(), C.c_int(), C.c_int()
+        rc = fn(self.handle, None, None, C.byref(b), C.byref(p), C.byref(w), C.byref(h))
+        if rc != SUCCESS:
+            raise DhError(rc, what)
+        out = np.empty((b.value, p.value, h.value, w.value), dtype=np.complex64)
+        rc = fn(self.handle, out.ctypes.data_as(C.c_void_p), None, None, None, None, None)
+        if rc != SUCCESS:
+            raise DhError(rc, what)
+        return out
+
+    def window(self) -> np.ndarray:
+        return self._plane(lib().dh_get_window, "dh_get_window")
+
+    def fields(self) -> np.ndarray:
+        return self._plane(lib().dh_get_fields, "dh_get_fields")
+
+    def set_stage_timing(self, on: bool):
+        rc = lib().dh_set_stage_timing(self.handle, int(on))
+        if rc != SUCCESS:
+            raise DhError(rc, "dh_set_stage_timing")
+
+    def stage_times(self) -> dict:
+        """{stage: (ms summed, launches)} since timing was enabled or last read."""
+        ms = (C.c_double * 4)()
+        n = (C.c_int * 4)()
+        rc = lib().dh_stage_times(self.handle, ms, n)
+        if rc != SUCCESS:
+            raise DhError(rc, "dh_stage_times")
+        return {STAGES[k]: (ms[k], n[k]) for k in range(4)}
+
+    def last_error(self) -> int:
+        return lib().dh_last_error(self.handle)
+
+    def destroy(self):
+        if getattr(self, "handle", -1) >= 0:
+            lib().dh_destroy(self.handle)
+            self.handle = -1
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

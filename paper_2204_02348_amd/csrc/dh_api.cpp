@@ -1,0 +1,588 @@
+// Host side of libdh: parameter validation, FP64 plan geometry and tables,
+// device allocation, launch sequencing, and the C ABI of include/dh.h.
+#include "dh.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "dh_internal.hpp"
+
+namespace {
+
+using cd = std::complex<double>;
+constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr double kDeg = kPi / 180.0;
+
+bool smooth13(int n) {
+  for (int f : {2, 3, 5, 7, 11, 13})
+    while (n % f == 0) n /= f;
+  return n == 1;
+}
+
+// IFFT (field) length for a Fourier window of radius r bins: the smallest
+// multiple of 16 with prime factors <= 13 that holds floor(2r)+1 bins.
+int field_len(double r) {
+  const int need = (int)std::floor(2.0 * r) + 1;
+  int w = 16;
+  while (w < need || !smooth13(w)) w += 16;
+  return w;
+}
+
+struct PolGeom {
+  double ax, ay;         // cross-term position (bins): SR* at (-ax, -ay)
+  int x0, y0;            // window origin
+  double dx, dy;         // sub-pixel beam-centre remainder, m
+  int uhi, ulo, vhi, vlo;
+  std::vector<int> row_lo, row_hi;  // per box row i (v = vhi - i): mask u-range
+};
+
+struct Geom {
+  int nx, ny, wx, wy, wyp, bx, by, G, gp, nmodes;
+  double rx, ry, pxp, pyp;
+  PolGeom pol[2];
+};
+
+bool inside(double u, double v, double ax, double ay, double rx, double ry) {
+  const double a = (u + ax) / rx, b = (v + ay) / ry;
+  return a * a + b * b <= 1.0;
+}
+
+int derive(const dh_params* p, Geom* g) {
+  if (!p) return DH_ERR_NULLPOINTER;
+  if (p->pol_count != 1 && p->pol_count != 2) return DH_ERR_INVALIDPOLARISATION;
+  if (p->frame_w <= 0 || p->frame_h <= 0 || p->frame_w % 16 || p->frame_h % 16) return DH_ERR_INVALIDDIMENSION;
+  const int nx = (p->fft_w / 16) * 16, ny = (p->fft_h / 16) * 16;
+  if (nx <= 0 || ny <= 0) return DH_ERR_INVALIDDIMENSION;
+  if (!(p->pixel_size > 0) || !(p->wavelength > 0) || !(p->window_radius_deg > 0)) return DH_ERR_INVALIDARGUMENT;
+  if (p->max_mg < 0 || p->max_mg > 32) return DH_ERR_INVALIDARGUMENT;
+  if (p->max_mg > 0 && !(p->waist > 0)) return DH_ERR_INVALIDARGUMENT;
+  if (p->input_dtype != DH_INPUT_F32 && p->input_dtype != DH_INPUT_U16) return DH_ERR_INVALIDARGUMENT;
+  if (p->precision != DH_PREC_FP32 && p->precision != DH_PREC_SPLIT_BF16 && p->precision != DH_PREC_SPLIT_FP16)
+    return DH_ERR_INVALIDARGUMENT;
+  if (p->ifft_mode != 1) return DH_ERR_INVALIDARGUMENT;
+  for (int q = 0; q < p->pol_count; ++q) {
+    for (int a = 0; a < 2; ++a)
+      if (!std::isfinite(p->tilt_deg[q][a]) || !std::isfinite(p->beam_centre[q][a])) return DH_ERR_INVALIDARGUMENT;
+    if (!std::isfinite(p->defocus[q])) return DH_ERR_INVALIDARGUMENT;
+  }
+  const double pix = p->pixel_size, lam = p->wavelength;
+  const double wmax = lam / (2.0 * pix);
+  g->nx = nx;
+  g->ny = ny;
+  g->rx = (p->window_radius_deg * kDeg / wmax) * (nx / 2.0);
+  g->ry = (p->window_radius_deg * kDeg / wmax) * (ny / 2.0);
+  if (2.0 * g->rx + 1.0 >= nx || 2.0 * g->ry + 1.0 >= ny) return DH_ERR_INVALIDARGUMENT;
+  g->wx = field_len(g->rx);
+  g->wy = field_len(g->ry);
+  g->wyp = (g->wy + 15) / 16 * 16;
+  g->pxp = nx * pix / g->wx;
+  g->pyp = ny * pix / g->wy;
+  g->G = p->max_mg;
+  g->gp = g->G <= 16 ? 16 : 32;
+  g->nmodes = g->G * (g->G + 1) / 2;
+  const int half = p->frame_w / p->pol_count;
+  g->bx = g->by = 0;
+  for (int q = 0; q < p->pol_count; ++q) {
+    PolGeom& P = g->pol[q];
+    P.ax = p->tilt_deg[q][0] * kDeg * nx * pix / lam;
+    P.ay = p->tilt_deg[q][1] * kDeg * ny * pix / lam;
+    const int ix = (int)std::floor(p->beam_centre[q][0] / pix + 0.5);
+    const int iy = (int)std::floor(p->beam_centre[q][1] / pix + 0.5);
+    P.x0 = q * half + half / 2 + ix - nx / 2;
+    P.y0 = p->frame_h / 2 + iy - ny / 2;
+    P.dx = p->beam_centre[q][0] - ix * pix;
+    P.dy = p->beam_centre[q][1] - iy * pix;
+    if (P.x0 < 0 || P.x0 + nx > p->frame_w || P.y0 < 0 || P.y0 + ny > p->frame_h) return DH_ERR_INVALIDDIMENSION;
+    // bounding box of the bins inside the window
+    const int u_a = (int)std::floor(-P.ax - g->rx) - 1, u_b = (int)std::ceil(-P.ax + g->rx) + 1;
+    const int v_a = (int)std::floor(-P.ay - g->ry) - 1, v_b = (int)std::ceil(-P.ay + g->ry) + 1;
+    P.ulo = u_b; P.uhi = u_a; P.vlo = v_b; P.vhi = v_a;
+    for (int v = v_a; v <= v_b; ++v)
+      for (int u = u_a; u <= u_b; ++u)
+        if (inside(u, v, P.ax, P.ay, g->rx, g->ry)) {
+          P.ulo = std::min(P.ulo, u); P.uhi = std::max(P.uhi, u);
+          P.vlo = std::min(P.vlo, v); P.vhi = std::max(P.vhi, v);
+        }
+    if (P.uhi < P.ulo || P.vhi < P.vlo) return DH_ERR_INVALIDARGUMENT;  // empty window
+    const int bxq = P.uhi - P.ulo + 1, byq = P.vhi - P.vlo + 1;
+    if (bxq > g->wx || byq > g->wy) return DH_ERR_INVALIDARGUMENT;
+    g->bx = std::max(g->bx, bxq);
+    g->by = std::max(g->by, byq);
+    P.row_lo.assign(byq, 1);
+    P.row_hi.assign(byq, 0);
+    for (int i = 0; i < byq; ++i) {
+      const int v = P.vhi - i;
+      int lo = INT32_MAX, hi = INT32_MIN;
+      for (int u = P.ulo; u <= P.uhi; ++u)
+        if (inside(u, v, P.ax, P.ay, g->rx, g->ry)) { lo = std::min(lo, u); hi = std::max(hi, u); }
+      if (lo <= hi) { P.row_lo[i] = lo; P.row_hi[i] = hi; }
+      else { P.row_lo[i] = 1; P.row_hi[i] = 0; }
+    }
+  }
+  if (!dh::sizes_supported(nx, ny, g->wx, g->wy)) return DH_ERR_INVALIDDIMENSION;
+  return DH_SUCCESS;
+}
+
+size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+
+int chunk_for(const Geom& g, int npol, int max_batch) {
+  // keep the two intermediates of one chunk within ~96 MB (a last-level
+  // cache sized working set); DH_CHUNK_FRAMES overrides the frame count
+  const size_t per = (size_t)npol * ((size_t)g.ny + g.wy) * g.bx * 8;
+  long c = (long)(96ull * 1024 * 1024 / (per ? per : 1));
+  if (const char* env = std::getenv("DH_CHUNK_FRAMES")) {
+    const long v = std::strtol(env, nullptr, 10);
+    if (v > 0) c = v;
+  }
+  if (c < 1) c = 1;
+  if (c > max_batch) c = max_batch;
+  return (int)c;
+}
+
+struct Layout {  // byte offsets inside one device allocation
+  size_t tw_nx, tw_ny, tw_wx, tw_wy, modes, total_tables;
+  size_t pol_mrow[2], pol_qrow[2], pol_qcol[2], pol_rhox[2], pol_rhoy[2], pol_tx[2], pol_ty[2], pol_ux[2], pol_uy[2];
+  size_t t1, f2, partial, coefs, coefs_norm, window, fields, total;
+};
+
+Layout layout(const Geom& g, const dh_params* p, int max_batch, int chunk) {
+  Layout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o += align256(bytes); return r; };
+  L.tw_nx = take(g.nx * 8); L.tw_ny = take(g.ny * 8); L.tw_wx = take(g.wx * 8); L.tw_wy = take(g.wy * 8);
+  L.modes = take((g.nmodes > 0 ? g.nmodes : 1) * 4);
+  for (int q = 0; q < p->pol_count; ++q) {
+    L.pol_mrow[q] = take(g.by * 8);
+    L.pol_qrow[q] = take(g.wy * 2);
+    L.pol_qcol[q] = take(g.wx * 2);
+    L.pol_rhox[q] = take(g.bx * 8);
+    L.pol_rhoy[q] = take(g.by * 8);
+    L.pol_tx[q] = take(g.wx * 8);
+    L.pol_ty[q] = take(g.wy * 8);
+    L.pol_ux[q] = take((size_t)g.wx * g.gp * 4);
+    L.pol_uy[q] = take((size_t)g.wyp * g.gp * 4);
+  }
+  L.total_tables = o;
+  const size_t P = p->pol_count;
+  L.t1 = take((size_t)chunk * P * g.ny * g.bx * 8);
+  L.f2 = take((size_t)chunk * P * g.wy * g.bx * 8);
+  L.partial = take((size_t)chunk * P * (g.wyp / 16) * (g.nmodes > 0 ? g.nmodes : 1) * 8);
+  const size_t nm = g.nmodes > 0 ? g.nmodes : 1;
+  L.coefs = take((size_t)max_batch * P * nm * 8);
+  L.coefs_norm = take((size_t)max_batch * P * nm * 8);
+  L.window = p->keep_window ? take((size_t)max_batch * P * g.wy * g.wx * 8) : 0;
+  L.fields = p->keep_fields ? take((size_t)max_batch * P * g.wy * g.wx * 8) : 0;
+  L.total = o;
+  return L;
+}
+
+struct Plan {
+  dh_params params;
+  Geom g;
+  Layout L;
+  int max_batch = 1, chunk = 1, last_batch = 0, last_error = 0;
+  int device = 0;
+  char* mem = nullptr;
+  hipStream_t last_stream = nullptr;
+  dh::KArgs ka{};
+  // per-stage timing: events recorded around every launch while enabled
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<int> ev_stage;   // stage of the launch that ends at event i (i >= 1); -1: a batch start
+  size_t ev_used = 0;
+};
+
+hipEvent_t next_event(Plan* pl, int stage) {
+  if (pl->ev_used == pl->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    pl->ev_pool.push_back(e);
+  }
+  if (pl->ev_stage.size() <= pl->ev_used) pl->ev_stage.resize(pl->ev_used + 1);
+  pl->ev_stage[pl->ev_used] = stage;
+  return pl->ev_pool[pl->ev_used++];
+}
+
+// record the end of a launch of `stage` (or a batch start, stage -1)
+hipError_t mark(Plan* pl, int stage, hipStream_t s) {
+  if (!pl->timing) return hipSuccess;
+  hipEvent_t e = next_event(pl, stage);
+  if (!e) return hipErrorOutOfMemory;
+  return hipEventRecord(e, s);
+}
+
+std::mutex g_mu;
+std::vector<Plan*> g_plans;
+
+Plan* get(dh_handle h) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (h < 0 || (size_t)h >= g_plans.size()) return nullptr;
+  return g_plans[h];
+}
+
+template <typename T>
+void put(std::vector<char>& host, size_t off, const std::vector<T>& v) {
+  std::memcpy(host.data() + off, v.data(), v.size() * sizeof(T));
+}
+
+// Twiddles of the FFT passes after the first, in FP64 rounded to FP32:
+// for a pass of radix R after earlier radices with product NS, entry
+// (r-1)*NS + k = e^{-2 pi i k r / (NS R)}; the passes follow each other.
+std::vector<float2> twiddles(int n) {
+  int r[3];
+  dh::fft_radices(n, r);
+  std::vector<float2> t;
+  int ns = r[0];
+  for (int s = 1; s < 3 && r[s] > 1; ++s) {
+    for (int rr = 1; rr < r[s]; ++rr)
+      for (int k = 0; k < ns; ++k) {
+        const double a = -2.0 * kPi * (double)k * rr / ((double)ns * r[s]);
+        t.push_back(make_float2((float)std::cos(a), (float)std::sin(a)));
+      }
+    ns *= r[s];
+  }
+  if (t.empty()) t.push_back(make_float2(1.f, 0.f));
+  return t;
+}
+
+int build_tables(Plan* pl) {
+  const Geom& g = pl->g;
+  const dh_params* p = &pl->params;
+  const Layout& L = pl->L;
+  std::vector<char> host(L.total_tables, 0);
+  put(host, L.tw_nx, twiddles(g.nx));
+  put(host, L.tw_ny, twiddles(g.ny));
+  put(host, L.tw_wx, twiddles(g.wx));
+  put(host, L.tw_wy, twiddles(g.wy));
+  std::vector<short2> modes;
+  for (int gg = 0; gg < g.G; ++gg)
+    for (int m = gg; m >= 0; --m) modes.push_back(make_short2((short)m, (short)(gg - m)));
+  put(host, L.modes, modes);
+  const double pix = p->pixel_size, lam = p->wavelength;
+  for (int q = 0; q < p->pol_count; ++q) {
+    const PolGeom& P = g.pol[q];
+    const int byq = P.vhi - P.vlo + 1;
+    std::vector<int2> mrow(g.by, make_int2(1, 0));
+    for (int i = 0; i < byq; ++i)
+      if (P.row_lo[i] <= P.row_hi[i]) mrow[i] = make_int2(P.uhi - P.row_hi[i], P.uhi - P.row_lo[i]);
+    std::vector<short> qrow(g.wy, -1), qcol(g.wx, -1);
+    for (int i = 0; i < byq; ++i) {
+      const int v = P.vhi - i;
+      qrow[((v % g.wy) + g.wy) % g.wy] = (short)i;
+    }
+    const int bxq = P.uhi - P.ulo + 1;
+    for (int j = 0; j < bxq; ++j) {
+      const int u = P.uhi - j;
+      qcol[((u % g.wx) + g.wx) % g.wx] = (short)j;
+    }
+    std::vector<float2> rhox(g.bx), rhoy(g.by), tx(g.wx), ty(g.wy);
+    for (int j = 0; j < g.bx; ++j) {
+      const int u = P.uhi - j;
+      const cd r = std::exp(cd(0, 2.0 * kPi * u * P.dx / (pix * g.nx)));
+      rhox[j] = make_float2((float)r.real(), (float)r.imag());
+    }
+    const double inv = 1.0 / ((double)g.nx * g.ny);
+    for (int i = 0; i < g.by; ++i) {
+      const int v = P.vhi - i;
+      const cd r = std::exp(cd(0, 2.0 * kPi * v * P.dy / (pix * g.ny))) * inv;
+      rhoy[i] = make_float2((float)r.real(), (float)r.imag());
+    }
+    for (int k = 0; k < g.wx; ++k) {
+      const double x = (k - g.wx / 2.0) * g.pxp;
+      const double ph = 2.0 * kPi * P.ax * (k - g.wx / 2.0) / g.wx + kPi * p->defocus[q] * x * x / lam;
+      tx[k] = make_float2((float)std::cos(ph), (float)std::sin(ph));
+    }
+    for (int l = 0; l < g.wy; ++l) {
+      const double y = (l - g.wy / 2.0) * g.pyp;
+      const double ph = 2.0 * kPi * P.ay * (l - g.wy / 2.0) / g.wy + kPi * p->defocus[q] * y * y / lam;
+      ty[l] = make_float2((float)std::cos(ph), (float)std::sin(ph));
+    }
+    put(host, L.pol_mrow[q], mrow);
+    put(host, L.pol_qrow[q], qrow);
+    put(host, L.pol_qcol[q], qcol);
+    put(host, L.pol_rhox[q], rhox);
+    put(host, L.pol_rhoy[q], rhoy);
+    put(host, L.pol_tx[q], tx);
+    put(host, L.pol_ty[q], ty);
+  }
+  if (hipMemcpy(pl->mem, host.data(), L.total_tables, hipMemcpyHostToDevice) != hipSuccess) return DH_ERR_ERROR;
+  for (int q = 0; q < p->pol_count; ++q) {
+    if (dh::launch_hg(g.pxp, g.wx, g.wx, p->waist > 0 ? p->waist : 1.0, g.G, g.gp, (float*)(pl->mem + L.pol_ux[q]), 0) != hipSuccess)
+      return DH_ERR_ERROR;
+    if (dh::launch_hg(g.pyp, g.wy, g.wyp, p->waist > 0 ? p->waist : 1.0, g.G, g.gp, (float*)(pl->mem + L.pol_uy[q]), 0) != hipSuccess)
+      return DH_ERR_ERROR;
+  }
+  if (hipDeviceSynchronize() != hipSuccess) return DH_ERR_ERROR;
+  return DH_SUCCESS;
+}
+
+void fill_kargs(Plan* pl) {
+  const Geom& g = pl->g;
+  const dh_params* p = &pl->params;
+  const Layout& L = pl->L;
+  dh::KArgs& a = pl->ka;
+  char* m = pl->mem;
+  a.frame_w = p->frame_w; a.frame_h = p->frame_h; a.npol = p->pol_count;
+  a.nx = g.nx; a.ny = g.ny; a.wx = g.wx; a.wy = g.wy; a.wyp = g.wyp;
+  a.bx = g.bx; a.by = g.by; a.G = g.G; a.gp = g.gp; a.nmodes = g.nmodes;
+  a.nxny = (float)((double)g.nx * g.ny);
+  for (int q = 0; q < p->pol_count; ++q) {
+    const PolGeom& P = g.pol[q];
+    dh::PolTab& t = a.pol[q];
+    t.x0 = P.x0; t.y0 = P.y0;
+    t.k0 = -P.uhi; t.ky0 = -P.vhi;
+    t.mrow = (const int2*)(m + L.pol_mrow[q]);
+    t.qrow = (const short*)(m + L.pol_qrow[q]);
+    t.qcol = (const short*)(m + L.pol_qcol[q]);
+    t.rhox = (const float2*)(m + L.pol_rhox[q]);
+    t.rhoy = (const float2*)(m + L.pol_rhoy[q]);
+    t.tx = (const float2*)(m + L.pol_tx[q]);
+    t.ty = (const float2*)(m + L.pol_ty[q]);
+    t.ux = (const float*)(m + L.pol_ux[q]);
+    t.uy = (const float*)(m + L.pol_uy[q]);
+  }
+  a.modes = (const short2*)(m + L.modes);
+  a.tw_nx = (const float2*)(m + L.tw_nx);
+  a.tw_ny = (const float2*)(m + L.tw_ny);
+  a.tw_wx = (const float2*)(m + L.tw_wx);
+  a.tw_wy = (const float2*)(m + L.tw_wy);
+  a.t1 = (float2*)(m + L.t1);
+  a.f2 = (float2*)(m + L.f2);
+  a.partial = (float2*)(m + L.partial);
+  a.nblk = g.wyp / 16;
+  a.coefs = (float2*)(m + L.coefs);
+  a.coefs_norm = (float2*)(m + L.coefs_norm);
+  a.window = p->keep_window ? (float2*)(m + L.window) : nullptr;
+  a.fields = p->keep_fields ? (float2*)(m + L.fields) : nullptr;
+}
+
+int set_err(Plan* pl, int e) {
+  if (pl) pl->last_error = e;
+  return e;
+}
+
+int copy_out(Plan* pl, void* host_out, size_t bytes, const void* dev) {
+  if (!host_out) return DH_SUCCESS;
+  if (hipStreamSynchronize(pl->last_stream) != hipSuccess) return DH_ERR_ERROR;
+  if (hipMemcpy(host_out, dev, bytes, hipMemcpyDeviceToHost) != hipSuccess) return DH_ERR_ERROR;
+  return DH_SUCCESS;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dh_plan_check(const dh_params* p, int max_batch, dh_plan_info* info) {
+  Geom g;
+  const int e = derive(p, &g);
+  if (e != DH_SUCCESS) return e;
+  if (max_batch < 1) max_batch = 1;
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    const int chunk = chunk_for(g, p->pol_count, max_batch);
+    const Layout L = layout(g, p, max_batch, chunk);
+    info->fft_w = g.nx; info->fft_h = g.ny;
+    info->ifft_w = g.wx; info->ifft_h = g.wy;
+    info->box_w = g.bx; info->box_h = g.by;
+    info->modes = g.nmodes;
+    for (int q = 0; q < p->pol_count; ++q) {
+      info->x0[q] = g.pol[q].x0; info->y0[q] = g.pol[q].y0;
+      info->ax[q] = g.pol[q].ax; info->ay[q] = g.pol[q].ay;
+    }
+    info->rx = g.rx; info->ry = g.ry;
+    info->pitch_x = g.pxp; info->pitch_y = g.pyp;
+    info->device_bytes = L.total;
+    info->chunk = chunk;
+  }
+  return DH_SUCCESS;
+}
+
+int dh_plan(const dh_params* p, int max_batch, size_t hbm_budget, dh_handle* out) {
+  if (!p || !out) return DH_ERR_NULLPOINTER;
+  Geom g;
+  int e = derive(p, &g);
+  if (e != DH_SUCCESS) return e;
+  if (max_batch < 1) max_batch = 1;
+  Plan* pl = new Plan();
+  pl->params = *p;
+  pl->params.fft_w = g.nx;
+  pl->params.fft_h = g.ny;
+  pl->g = g;
+  pl->max_batch = max_batch;
+  pl->chunk = chunk_for(g, p->pol_count, max_batch);
+  pl->L = layout(g, p, max_batch, pl->chunk);
+  if (hbm_budget && pl->L.total > hbm_budget) {
+    delete pl;
+    return DH_ERR_MEMORYALLOCATION;
+  }
+  if (hipGetDevice(&pl->device) != hipSuccess || hipMalloc(&pl->mem, pl->L.total) != hipSuccess) {
+    (void)hipGetLastError();
+    delete pl;
+    return DH_ERR_MEMORYALLOCATION;
+  }
+  e = build_tables(pl);
+  if (e != DH_SUCCESS) {
+    (void)hipFree(pl->mem);
+    delete pl;
+    return e;
+  }
+  fill_kargs(pl);
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_plans.push_back(pl);
+  *out = (dh_handle)(g_plans.size() - 1);
+  return DH_SUCCESS;
+}
+
+int dh_process_batch(dh_handle h, const void* frames, int batch, void* stream) {
+  Plan* pl = get(h);
+  if (!pl) return DH_ERR_INVALIDHANDLE;
+  if (!frames) return set_err(pl, DH_ERR_NULLPOINTER);
+  if (batch < 1) batch = 1;
+  if (batch > pl->max_batch) return set_err(pl, DH_ERR_INVALIDDIMENSION);
+  hipStream_t s = (hipStream_t)stream;
+  const dh::KArgs& a = pl->ka;
+  const int u16 = pl->params.input_dtype == DH_INPUT_U16;
+  if (a.window && dh::launch_zero(a.window, (size_t)batch * a.npol * a.wy * a.wx, s) != hipSuccess)
+    return set_err(pl, DH_ERR_ERROR);
+  if (mark(pl, -1, s) != hipSuccess) return set_err(pl, DH_ERR_ERROR);
+  for (int b0 = 0; b0 < batch; b0 += pl->chunk) {
+    const int nb = std::min(pl->chunk, batch - b0);
+    if (dh::launch_row(a, frames, u16, b0, nb, s) != hipSuccess || mark(pl, 0, s) != hipSuccess)
+      return set_err(pl, DH_ERR_ERROR);
+    if (dh::launch_col(a, b0, nb, s) != hipSuccess || mark(pl, 1, s) != hipSuccess)
+      return set_err(pl, DH_ERR_ERROR);
+    if (a.G > 0 || a.fields) {
+      if (dh::launch_fld(a, b0, nb, s) != hipSuccess || mark(pl, 2, s) != hipSuccess)
+        return set_err(pl, DH_ERR_ERROR);
+    }
+    if (a.G > 0 && (dh::launch_norm(a, b0, nb, s) != hipSuccess || mark(pl, 3, s) != hipSuccess))
+      return set_err(pl, DH_ERR_ERROR);
+  }
+  pl->last_batch = batch;
+  pl->last_stream = s;
+  return set_err(pl, DH_SUCCESS);
+}
+
+int dh_mode_coefs(dh_handle h, dh_c64* host_out, const dh_c64** dev_out, int* batch, int* modes, int* pols,
+                  int normalised) {
+  Plan* pl = get(h);
+  if (!pl) {
+    if (batch) *batch = 0;
+    if (modes) *modes = 0;
+    if (pols) *pols = 0;
+    if (dev_out) *dev_out = nullptr;
+    return DH_ERR_INVALIDHANDLE;
+  }
+  const int nm = pl->g.nmodes;
+  if (batch) *batch = pl->last_batch;
+  if (modes) *modes = nm;
+  if (pols) *pols = pl->params.pol_count;
+  const float2* src = normalised ? pl->ka.coefs_norm : pl->ka.coefs;
+  if (dev_out) *dev_out = nm > 0 ? (const dh_c64*)src : nullptr;
+  if (nm == 0) return set_err(pl, DH_SUCCESS);
+  const size_t bytes = (size_t)pl->last_batch * pl->params.pol_count * nm * sizeof(dh_c64);
+  return set_err(pl, copy_out(pl, host_out, bytes, src));
+}
+
+static int get_plane(dh_handle h, bool win, dh_c64* host_out, const dh_c64** dev_out, int* batch, int* pols,
+                     int* width, int* height) {
+  Plan* pl = get(h);
+  if (!pl) return DH_ERR_INVALIDHANDLE;
+  const float2* src = win ? pl->ka.window : pl->ka.fields;
+  if (batch) *batch = pl->last_batch;
+  if (pols) *pols = pl->params.pol_count;
+  if (width) *width = pl->g.wx;
+  if (height) *height = pl->g.wy;
+  if (dev_out) *dev_out = (const dh_c64*)src;
+  if (!src) return set_err(pl, DH_ERR_ERROR);
+  const size_t bytes = (size_t)pl->last_batch * pl->params.pol_count * pl->g.wx * pl->g.wy * sizeof(dh_c64);
+  return set_err(pl, copy_out(pl, host_out, bytes, src));
+}
+
+int dh_get_window(dh_handle h, dh_c64* host_out, const dh_c64** dev_out, int* batch, int* pols, int* width,
+                  int* height) {
+  return get_plane(h, true, host_out, dev_out, batch, pols, width, height);
+}
+
+int dh_get_fields(dh_handle h, dh_c64* host_out, const dh_c64** dev_out, int* batch, int* pols, int* width,
+                  int* height) {
+  return get_plane(h, false, host_out, dev_out, batch, pols, width, height);
+}
+
+int dh_get_params(dh_handle h, dh_params* out) {
+  Plan* pl = get(h);
+  if (!pl) return DH_ERR_INVALIDHANDLE;
+  if (!out) return set_err(pl, DH_ERR_NULLPOINTER);
+  *out = pl->params;
+  return DH_SUCCESS;
+}
+
+int dh_get_plan_info(dh_handle h, dh_plan_info* out) {
+  Plan* pl = get(h);
+  if (!pl) return DH_ERR_INVALIDHANDLE;
+  if (!out) return set_err(pl, DH_ERR_NULLPOINTER);
+  return dh_plan_check(&pl->params, pl->max_batch, out);
+}
+
+int dh_set_stage_timing(dh_handle h, int enabled) {
+  Plan* pl = get(h);
+  if (!pl) return DH_ERR_INVALIDHANDLE;
+  pl->timing = enabled != 0;
+  pl->ev_used = 0;
+  return set_err(pl, DH_SUCCESS);
+}
+
+int dh_stage_times(dh_handle h, double* ms, int* launches) {
+  Plan* pl = get(h);
+  if (!pl) return DH_ERR_INVALIDHANDLE;
+  if (!ms || !launches) return set_err(pl, DH_ERR_NULLPOINTER);
+  for (int k = 0; k < DH_STAGE_COUNT; ++k) {
+    ms[k] = 0.0;
+    launches[k] = 0;
+  }
+  if (pl->ev_used > 0 && hipEventSynchronize(pl->ev_pool[pl->ev_used - 1]) != hipSuccess)
+    return set_err(pl, DH_ERR_ERROR);
+  for (size_t i = 1; i < pl->ev_used; ++i) {
+    const int st = pl->ev_stage[i];
+    if (st < 0) continue;  // gap between batches
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, pl->ev_pool[i - 1], pl->ev_pool[i]) != hipSuccess) return set_err(pl, DH_ERR_ERROR);
+    ms[st] += t;
+    launches[st] += 1;
+  }
+  pl->ev_used = 0;
+  return set_err(pl, DH_SUCCESS);
+}
+
+int dh_last_error(dh_handle h) {
+  Plan* pl = get(h);
+  return pl ? pl->last_error : DH_ERR_INVALIDHANDLE;
+}
+
+int dh_destroy(dh_handle h) {
+  Plan* pl;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (h < 0 || (size_t)h >= g_plans.size() || !g_plans[h]) return DH_ERR_INVALIDHANDLE;
+    pl = g_plans[h];
+    g_plans[h] = nullptr;
+  }
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipSetDevice(pl->device);
+  (void)hipDeviceSynchronize();
+  (void)hipFree(pl->mem);
+  for (hipEvent_t e : pl->ev_pool) (void)hipEventDestroy(e);
+  (void)hipSetDevice(dev);
+  delete pl;
+  return DH_SUCCESS;
+}
+
+}  // extern "C"

@@ -1,0 +1,314 @@
+// Device FFT building blocks for gfx950: compile-time mixed-radix Stockham
+// passes through LDS, with each pass's radix-R DFT done in registers.
+//
+// A length-N transform is factored N = R0 * R1 (* R2); pass s reads R
+// elements spaced N/R apart, multiplies by e^{-2 pi i k r/(Ns R)} (Ns = the
+// product of the earlier radices, k = butterfly index mod Ns), runs a radix-R
+// DFT in registers and writes the results Ns apart (self-sorting: natural
+// order in, natural order out). Composite radices (16, 20, 21, 32, ...) are
+// themselves split Cooley-Tukey style with constant twiddles, fully unrolled,
+// so one LDS round trip covers several radix stages.
+//
+// All transforms here are forward (e^{-i}); an inverse transform is done as
+// conj(FFT(conj(x))), with both conjugations folded into the surrounding
+// loads and stores.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace dh {
+
+// ------------------------------------------------------------------ constexpr trig
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+constexpr double ct_sin_reduced(double x) {  // |x| <= pi/4
+  double term = x, sum = x;
+  for (int n = 1; n < 14; ++n) {
+    term *= -x * x / ((2.0 * n) * (2.0 * n + 1.0));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double ct_cos_reduced(double x) {  // |x| <= pi/4
+  double term = 1.0, sum = 1.0;
+  for (int n = 1; n < 14; ++n) {
+    term *= -x * x / ((2.0 * n - 1.0) * (2.0 * n));
+    sum += term;
+  }
+  return sum;
+}
+// cos and sin of 2 pi num/den for integers, exact octant reduction
+constexpr double ct_cos2pi(long num, long den) {
+  long n = ((num % den) + den) % den;       // [0, den)
+  // reduce with symmetries on 8*n/den
+  long o = (8 * n) / den;                   // octant 0..7
+  double x = 2.0 * kPi * double(n) / double(den);
+  switch (o) {
+    case 0: return ct_cos_reduced(x);
+    case 1: return ct_sin_reduced(kPi / 2 - x);
+    case 2: return -ct_sin_reduced(x - kPi / 2);
+    case 3: return -ct_cos_reduced(kPi - x);
+    case 4: return -ct_cos_reduced(x - kPi);
+    case 5: return -ct_sin_reduced(3 * kPi / 2 - x);
+    case 6: return ct_sin_reduced(x - 3 * kPi / 2);
+    default: return ct_cos_reduced(2 * kPi - x);
+  }
+}
+constexpr double ct_sin2pi(long num, long den) { return ct_cos2pi(num * 4 - den, 4 * den); }
+
+// ------------------------------------------------------------------ complex helpers
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+__device__ __forceinline__ float2 conjf2(float2 a) { return make_float2(a.x, -a.y); }
+__device__ __forceinline__ float2 mul_mi(float2 a) { return make_float2(a.y, -a.x); }  // * (-i)
+
+// multiply by the constant e^{-2 pi i e/R}
+template <int E, int R>
+__device__ __forceinline__ float2 twc(float2 a) {
+  constexpr int e = ((E % R) + R) % R;
+  if constexpr (e == 0) {
+    return a;
+  } else if constexpr (2 * e == R) {
+    return make_float2(-a.x, -a.y);
+  } else if constexpr (4 * e == R) {
+    return mul_mi(a);
+  } else if constexpr (4 * e == 3 * R) {
+    return make_float2(-a.y, a.x);
+  } else {
+    constexpr float c = (float)ct_cos2pi(e, R);
+    constexpr float s = (float)(-ct_sin2pi(e, R));
+    return make_float2(fmaf(a.x, c, -a.y * s), fmaf(a.x, s, a.y * c));
+  }
+}
+
+// ------------------------------------------------------------------ base butterflies (forward)
+__device__ __forceinline__ void dft2(float2* v) {
+  float2 a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+__device__ __forceinline__ void dft4(float2* v) {
+  float2 a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+  float2 c = cadd(v[1], v[3]), d = mul_mi(csub(v[1], v[3]));
+  v[0] = cadd(a, c);
+  v[2] = csub(a, c);
+  v[1] = cadd(b, d);
+  v[3] = csub(b, d);
+}
+__device__ __forceinline__ void dft8(float2* v) {
+  float2 e[4] = {v[0], v[2], v[4], v[6]};
+  float2 o[4] = {v[1], v[3], v[5], v[7]};
+  dft4(e);
+  dft4(o);
+  constexpr float h = 0.70710678118654752440f;
+  float2 o1 = make_float2(h * (o[1].x + o[1].y), h * (o[1].y - o[1].x));
+  float2 o2 = mul_mi(o[2]);
+  float2 o3 = make_float2(h * (o[3].y - o[3].x), -h * (o[3].x + o[3].y));
+  v[0] = cadd(e[0], o[0]);
+  v[4] = csub(e[0], o[0]);
+  v[1] = cadd(e[1], o1);
+  v[5] = csub(e[1], o1);
+  v[2] = cadd(e[2], o2);
+  v[6] = csub(e[2], o2);
+  v[3] = cadd(e[3], o3);
+  v[7] = csub(e[3], o3);
+}
+// cos / sin of 2 pi m / R, m < R, evaluated at compile time
+template <int R>
+struct RootTable {
+  float c[R], s[R];
+  constexpr RootTable() : c(), s() {
+    for (int m = 0; m < R; ++m) {
+      c[m] = (float)ct_cos2pi(m, R);
+      s[m] = (float)ct_sin2pi(m, R);
+    }
+  }
+};
+
+// odd prime radix: y_k = x0 + sum_j [(x_j + x_{R-j}) cos - i (x_j - x_{R-j}) sin]
+template <int R>
+__device__ __forceinline__ void dft_odd(float2* v) {
+  constexpr int H = (R - 1) / 2;
+  constexpr RootTable<R> K{};
+  float2 s[H + 1], d[H + 1];
+#pragma unroll
+  for (int j = 1; j <= H; ++j) {
+    s[j] = cadd(v[j], v[R - j]);
+    d[j] = csub(v[j], v[R - j]);
+  }
+  float2 x0 = v[0];
+  float2 y0 = x0;
+#pragma unroll
+  for (int j = 1; j <= H; ++j) y0 = cadd(y0, s[j]);
+  float2 out[R];
+  out[0] = y0;
+#pragma unroll
+  for (int k = 1; k <= H; ++k) {
+    float2 a = x0, b = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int j = 1; j <= H; ++j) {
+      const float c = K.c[(j * k) % R];
+      const float sn = K.s[(j * k) % R];
+      a.x = fmaf(c, s[j].x, a.x);
+      a.y = fmaf(c, s[j].y, a.y);
+      b.x = fmaf(sn, d[j].x, b.x);
+      b.y = fmaf(sn, d[j].y, b.y);
+    }
+    out[k] = make_float2(a.x + b.y, a.y - b.x);
+    out[R - k] = make_float2(a.x - b.y, a.y + b.x);
+  }
+#pragma unroll
+  for (int k = 0; k < R; ++k) v[k] = out[k];
+}
+
+constexpr bool is_base_radix(int r) {
+  return r == 1 || r == 2 || r == 3 || r == 4 || r == 5 || r == 7 || r == 8 || r == 11 || r == 13;
+}
+constexpr int split_radix(int r) {
+  return (r % 8 == 0 && r != 16) ? 8 : (r % 4 == 0) ? 4 : (r % 2 == 0) ? 2 : (r % 3 == 0) ? 3 : (r % 5 == 0) ? 5 : (r % 7 == 0) ? 7 : (r % 11 == 0) ? 11 : 13;
+}
+
+template <int R, int R1, int R2, int I = 0>
+__device__ __forceinline__ void static_for_tw(float2* y) {
+  if constexpr (I < R1 * R2) {
+    constexpr int n2 = I / R1, k1 = I % R1;
+    y[I] = twc<n2 * k1, R>(y[I]);
+    static_for_tw<R, R1, R2, I + 1>(y);
+  }
+}
+
+// radix-R DFT of v[0..R) in registers (forward)
+template <int R>
+__device__ __forceinline__ void dft(float2* v) {
+  if constexpr (R == 1) {
+  } else if constexpr (R == 2) {
+    dft2(v);
+  } else if constexpr (R == 4) {
+    dft4(v);
+  } else if constexpr (R == 8) {
+    dft8(v);
+  } else if constexpr (is_base_radix(R)) {
+    dft_odd<R>(v);
+  } else {
+    constexpr int R1 = split_radix(R);
+    constexpr int R2 = R / R1;
+    float2 y[R];
+    // inner length-R1 DFTs over n1 for each n2 (x index n = R2 n1 + n2)
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) {
+      float2 t[R1];
+#pragma unroll
+      for (int n1 = 0; n1 < R1; ++n1) t[n1] = v[R2 * n1 + n2];
+      dft<R1>(t);
+#pragma unroll
+      for (int k1 = 0; k1 < R1; ++k1) y[n2 * R1 + k1] = t[k1];
+    }
+    // twiddles e^{-2 pi i n2 k1 / R}
+    static_for_tw<R, R1, R2>(y);
+    // outer length-R2 DFTs over n2 for each k1; output index k1 + R1 k2
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) {
+      float2 t[R2];
+#pragma unroll
+      for (int n2 = 0; n2 < R2; ++n2) t[n2] = y[n2 * R1 + k1];
+      dft<R2>(t);
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2) v[k1 + R1 * k2] = t[k2];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ Stockham pass over NTR transforms
+// LDS layout of one transform: element i lives at i + i / PAD (one spare slot
+// after every PAD elements, PAD = the first radix), which makes the strided
+// writes of the first pass and the reads of every pass bank-conflict free;
+// transform t starts at t * STRIDE (an odd stride >= the padded length).
+template <int PAD>
+__device__ __forceinline__ int padi(int i) { return i + i / PAD; }
+
+// buf: LDS; tw: this pass's twiddle table (see fft_lds).
+template <int N, int R, int NS, int NTR, int STRIDE, int TPB, int PAD>
+__device__ __forceinline__ void stockham_pass(float2* buf, const float2* __restrict__ tw, int tid) {
+  constexpr int NB = N / R;
+  constexpr int TOTAL = NTR * NB;
+  constexpr int IT = (TOTAL + TPB - 1) / TPB;
+  float2 v[IT][R];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int g = tid + it * TPB;
+    if (TOTAL % TPB == 0 || g < TOTAL) {
+      const int tr = g / NB, b = g % NB;
+      const float2* src = buf + tr * STRIDE;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[it][r] = src[padi<PAD>(b + r * NB)];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int g = tid + it * TPB;
+    if (TOTAL % TPB == 0 || g < TOTAL) {
+      const int tr = g / NB, b = g % NB;
+      const int k = b % NS;
+      if constexpr (NS > 1) {
+        // this pass's twiddles e^{-2 pi i k r/(NS R)}, stored [r-1][k]
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[it][r] = cmul(v[it][r], tw[(r - 1) * NS + k]);
+      }
+      dft<R>(v[it]);
+      float2* dst = buf + tr * STRIDE;
+      const int base = (b / NS) * NS * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst[padi<PAD>(base + r * NS)] = v[it][r];
+    }
+  }
+  __syncthreads();
+}
+
+// Factorisations (radices per pass) of the supported lengths.
+template <int N> struct FftPlan;
+template <> struct FftPlan<16>   { static constexpr int R0 = 16, R1 = 1,  R2 = 1; };
+template <> struct FftPlan<32>   { static constexpr int R0 = 8,  R1 = 4,  R2 = 1; };
+template <> struct FftPlan<48>   { static constexpr int R0 = 6,  R1 = 8,  R2 = 1; };
+template <> struct FftPlan<64>   { static constexpr int R0 = 8,  R1 = 8,  R2 = 1; };
+template <> struct FftPlan<96>   { static constexpr int R0 = 12, R1 = 8,  R2 = 1; };
+template <> struct FftPlan<112>  { static constexpr int R0 = 16, R1 = 7,  R2 = 1; };
+template <> struct FftPlan<128>  { static constexpr int R0 = 16, R1 = 8,  R2 = 1; };
+template <> struct FftPlan<176>  { static constexpr int R0 = 16, R1 = 11, R2 = 1; };
+template <> struct FftPlan<208>  { static constexpr int R0 = 16, R1 = 13, R2 = 1; };
+template <> struct FftPlan<256>  { static constexpr int R0 = 16, R1 = 16, R2 = 1; };
+template <> struct FftPlan<320>  { static constexpr int R0 = 16, R1 = 20, R2 = 1; };
+template <> struct FftPlan<336>  { static constexpr int R0 = 16, R1 = 21, R2 = 1; };
+template <> struct FftPlan<512>  { static constexpr int R0 = 8,  R1 = 8,  R2 = 8; };
+template <> struct FftPlan<640>  { static constexpr int R0 = 8,  R1 = 8,  R2 = 10; };
+template <> struct FftPlan<672>  { static constexpr int R0 = 32, R1 = 21, R2 = 1; };
+template <> struct FftPlan<1024> { static constexpr int R0 = 16, R1 = 8,  R2 = 8; };
+template <> struct FftPlan<2048> { static constexpr int R0 = 16, R1 = 16, R2 = 8; };
+
+// padded layout of a length-N transform in LDS
+template <int N> struct Lds {
+  static constexpr int PAD = FftPlan<N>::R0;
+  static constexpr int SPAN = N + (N - 1) / PAD + 1;            // padded length
+  static constexpr int STRIDE = SPAN | 1;                        // odd transform stride
+  __device__ static __forceinline__ int at(int i) { return padi<PAD>(i); }
+};
+
+// forward FFT of NTR transforms of length N held in LDS (padded layout of
+// Lds<N>, transform t at buf + t * STRIDE). tw holds the twiddles of pass 2
+// then pass 3: entry (r-1)*NS + k = e^{-2 pi i k r / (NS R)}, so the lanes of
+// a wave (consecutive k) read consecutive entries.
+template <int N, int NTR, int STRIDE, int TPB>
+__device__ __forceinline__ void fft_lds(float2* buf, const float2* __restrict__ tw, int tid) {
+  using P = FftPlan<N>;
+  constexpr int PAD = Lds<N>::PAD;
+  static_assert(P::R0 * P::R1 * P::R2 == N, "bad factorisation");
+  static_assert(STRIDE >= Lds<N>::SPAN, "stride too small");
+  stockham_pass<N, P::R0, 1, NTR, STRIDE, TPB, PAD>(buf, tw, tid);
+  if constexpr (P::R1 > 1) stockham_pass<N, P::R1, P::R0, NTR, STRIDE, TPB, PAD>(buf, tw, tid);
+  constexpr int OFF2 = (P::R1 - 1) * P::R0;
+  if constexpr (P::R2 > 1) stockham_pass<N, P::R2, P::R0 * P::R1, NTR, STRIDE, TPB, PAD>(buf, tw + OFF2, tid);
+}
+
+}  // namespace dh

@@ -1,0 +1,61 @@
+// Internal interface between the host plan (dh_api.cpp) and the gfx950
+// kernels (dh_kernels.hip). Not part of the public C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+
+namespace dh {
+
+// Per-polarisation plan tables (device pointers) and window geometry.
+//
+// "Box": the rectangle of spectrum bins that holds every bin of the Fourier
+// window (mask). Box column j is row-pass bin k = k0 + j, i.e. window bin
+// u = -(k0 + j); box row i is column-pass bin v' = ky0 + i, i.e. v = -(ky0 + i).
+// The mask bins of the SR* term at (u, v) are read as conj(F(-u, -v)) from the
+// real-input spectrum F of the frame window.
+struct PolTab {
+  int x0, y0;             // window origin in the frame (pixels)
+  int k0, ky0;            // first row-pass bin / first column-pass bin of the box
+  const int2* mrow;       // [by] mask interval of box row i in box columns (lo > hi: empty)
+  const short* qrow;      // [wy] box row held by IFFT row q (v mod wy), -1 if none
+  const short* qcol;      // [wx] box column held by IFFT column q (u mod wx), -1 if none
+  const float2* rhox;     // [bx] sub-pixel beam-centre ramp along x
+  const float2* rhoy;     // [by] same along y, times 1/(Nx Ny)
+  const float2* tx;       // [wx] exp(i phi_R) along x (tilt + defocus)
+  const float2* ty;       // [wy] same along y
+  const float* ux;        // [wx][gp] u_m(x'_k) p'_x, zero for m >= G
+  const float* uy;        // [wyp][gp] u_n(y'_l) p'_y, zero for n >= G or l >= wy
+};
+
+struct KArgs {
+  int frame_w, frame_h, npol;
+  int nx, ny, wx, wy, wyp;  // FFT window, IFFT window, IFFT rows rounded up to 16
+  int bx, by;               // box size (max over pols)
+  int G, gp, nmodes;        // groups, padded group count (16 or 32), modes per pol
+  float nxny;               // Nx * Ny
+  PolTab pol[2];
+  const short2* modes;      // [nmodes] (m, n)
+  const float2* tw_nx;      // per-pass twiddle tables of each transform length (see fft_lds)
+  const float2* tw_ny;
+  const float2* tw_wx;
+  const float2* tw_wy;
+  float2* t1;               // [chunk][P][ny][bx] row-pass spectrum at the box columns
+  float2* f2;               // [chunk][P][wy][bx] column pass + crop + y-IFFT
+  float2* partial;          // [chunk][nblk][P][nmodes] per-row-block share of each coefficient
+  int nblk;                 // 16-row blocks of the field (wyp / 16)
+  float2* coefs;            // [max_batch][P][nmodes] raw coefficients
+  float2* coefs_norm;       // [max_batch][P][nmodes] power-normalised
+  float2* window;           // [max_batch][P][wy][wx] or null
+  float2* fields;           // [max_batch][P][wy][wx] or null
+};
+
+bool sizes_supported(int nx, int ny, int wx, int wy);
+void fft_radices(int n, int r[3]);   // radices of the passes of a supported length
+hipError_t launch_row(const KArgs& a, const void* frames, int u16, int b0, int nb, hipStream_t s);
+hipError_t launch_col(const KArgs& a, int b0, int nb, hipStream_t s);
+hipError_t launch_fld(const KArgs& a, int b0, int nb, hipStream_t s);
+hipError_t launch_norm(const KArgs& a, int b0, int nb, hipStream_t s);
+hipError_t launch_zero(float2* p, size_t n, hipStream_t s);
+hipError_t launch_hg(double pitch, int w, int wpad, double waist, int G, int gp, float* out, hipStream_t s);
+
+}  // namespace dh

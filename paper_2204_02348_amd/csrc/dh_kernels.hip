@@ -1,0 +1,432 @@
+// gfx950 kernels of the off-axis holography path.
+//
+//   k_row   pipeline step 1: frame window load (u16/f32 -> f32), real FFT
+//           along x of two rows at a time (packed as one complex row), and
+//           only the spectrum columns that hold the Fourier window are kept.
+//   k_col   pipeline step 2, first half: FFT along y of the kept columns,
+//           crop of the window rows around the reference-tilt peak, the
+//           circular window (mask), the beam-centre ramp, and the inverse
+//           FFT along y at the Fourier-window size (IFFT resolution mode 1).
+//   k_fld   pipeline step 2, second half + step 3: inverse FFT along x,
+//           removal of the reference tilt and defocus, and the separable
+//           Hermite-Gaussian overlap as two real MFMA contractions per
+//           16-row block (x first, then y), in FP32.
+//   k_norm  per-frame total power over both polarisations in FP64 and the
+//           power-normalised coefficients.
+//   k_hg    Hermite-Gaussian 1D tables by the normalised FP64 recurrence.
+//
+// Layouts: frames [b][frame_h][frame_w] row-major (x fastest); spectra and
+// fields complex64 interleaved; every intermediate row-major with the
+// contiguous axis the one the next kernel reads along.
+#include "dh_fft.hpp"
+#include "dh_internal.hpp"
+
+namespace dh {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kTPB = 256;
+
+template <typename T>
+__device__ __forceinline__ float load_px(const T* p) { return (float)(*p); }
+
+// ---------------------------------------------------------------------------
+// k_row: grid (ceil(ny / (2 TR)), npol, nb); TR complex transforms of NX,
+// each the pair of real rows (2t, 2t+1) packed as re + i im.
+// t1[b][p][y][j] = sum_x I[y][x] e^{-2 pi i k x / NX}, k = k0 + j (mod NX)
+template <int NX, int TR, typename TIn>
+__global__ void __launch_bounds__(kTPB) k_row(KArgs A, const TIn* __restrict__ frames, int b0) {
+  using L = Lds<NX>;
+  __shared__ float2 buf[TR * L::STRIDE];
+  const int tid = threadIdx.x;
+  const int p = blockIdx.y;
+  const int bl = blockIdx.z;                 // frame within the chunk
+  const PolTab& P = A.pol[p];
+  const int ybase = blockIdx.x * (2 * TR);
+  const TIn* win = frames + (size_t)(b0 + bl) * A.frame_h * A.frame_w + (size_t)P.y0 * A.frame_w + P.x0;
+  for (int e = tid; e < TR * NX; e += kTPB) {
+    const int t = e / NX, c = e % NX;
+    const int y = ybase + 2 * t;
+    float v0 = 0.f, v1 = 0.f;
+    if (y < A.ny) v0 = load_px(win + (size_t)y * A.frame_w + c);
+    if (y + 1 < A.ny) v1 = load_px(win + (size_t)(y + 1) * A.frame_w + c);
+    buf[t * L::STRIDE + L::at(c)] = make_float2(v0, v1);
+  }
+  __syncthreads();
+  fft_lds<NX, TR, L::STRIDE, kTPB>(buf, A.tw_nx, tid);
+  float2* out = A.t1 + ((size_t)(bl * A.npol + p) * A.ny) * A.bx;
+  for (int e = tid; e < 2 * TR * A.bx; e += kTPB) {
+    const int r = e / A.bx, j = e % A.bx;
+    const int y = ybase + r;
+    if (y >= A.ny) continue;
+    int k = (P.k0 + j) % NX;
+    if (k < 0) k += NX;
+    const int km = (NX - k) % NX;
+    const float2* tb = buf + (r >> 1) * L::STRIDE;
+    const float2 z1 = tb[L::at(k)];
+    const float2 z2 = conjf2(tb[L::at(km)]);
+    float2 x;
+    if ((r & 1) == 0) {
+      x = make_float2(0.5f * (z1.x + z2.x), 0.5f * (z1.y + z2.y));
+    } else {
+      const float2 d = csub(z1, z2);  // d / (2i)
+      x = make_float2(0.5f * d.y, -0.5f * d.x);
+    }
+    out[(size_t)y * A.bx + j] = x;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_col: grid (ceil(bx / CG), npol, nb). CG box columns per block: FFT along
+// y, gather of the masked window rows (stored as conj of the IFFT input),
+// IFFT along y at the window size.
+template <int NY, int WY, int CG>
+__global__ void __launch_bounds__(kTPB) k_col(KArgs A, int b0) {
+  using LN = Lds<NY>;
+  using LW = Lds<WY>;
+  constexpr int ST = (LN::STRIDE > LW::STRIDE) ? LN::STRIDE : LW::STRIDE;
+  __shared__ float2 buf[CG * ST];
+  const int tid = threadIdx.x;
+  const int p = blockIdx.y;
+  const int bl = blockIdx.z;
+  const PolTab& P = A.pol[p];
+  const int jc0 = blockIdx.x * CG;
+  const float2* in = A.t1 + ((size_t)(bl * A.npol + p) * NY) * A.bx;
+  for (int e = tid; e < CG * NY; e += kTPB) {
+    const int c = e % CG, y = e / CG;
+    const int j = jc0 + c;
+    buf[c * ST + LN::at(y)] = (j < A.bx) ? in[(size_t)y * A.bx + j] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  fft_lds<NY, CG, ST, kTPB>(buf, A.tw_ny, tid);
+  constexpr int NE = (CG * WY + kTPB - 1) / kTPB;
+  float2 z[NE];
+  const bool keep_win = A.window != nullptr;
+  float2* win = keep_win ? A.window + ((size_t)(b0 + bl) * A.npol + p) * A.wy * A.wx : nullptr;
+#pragma unroll
+  for (int it = 0; it < NE; ++it) {
+    const int e = tid + it * kTPB;
+    float2 val = make_float2(0.f, 0.f);
+    if (e < CG * WY) {
+      const int c = e / WY, q = e % WY;
+      const int j = jc0 + c;
+      const int i = P.qrow[q];
+      if (i >= 0 && j < A.bx) {
+        const int2 mr = P.mrow[i];
+        if (j >= mr.x && j <= mr.y) {
+          int vv = (P.ky0 + i) % NY;
+          if (vv < 0) vv += NY;
+          const float2 f = buf[c * ST + LN::at(vv)];
+          const float2 rho = cmul(P.rhox[j], P.rhoy[i]);
+          val = cmul(f, conjf2(rho));
+          if (keep_win) {
+            // window = M * I~ = conj(val) (-1)^(u+v) Nx Ny at (v mod wy, u mod wx)
+            const int u = -(P.k0 + j), v = -(P.ky0 + i);
+            int qu = u % A.wx;
+            if (qu < 0) qu += A.wx;
+            const float sg = ((u + v) & 1) ? -A.nxny : A.nxny;
+            win[(size_t)q * A.wx + qu] = make_float2(sg * val.x, -sg * val.y);
+          }
+        }
+      }
+    }
+    z[it] = val;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < NE; ++it) {
+    const int e = tid + it * kTPB;
+    if (e < CG * WY) buf[(e / WY) * ST + LW::at(e % WY)] = z[it];
+  }
+  __syncthreads();
+  fft_lds<WY, CG, ST, kTPB>(buf, A.tw_wy, tid);
+  float2* out = A.f2 + ((size_t)(bl * A.npol + p) * WY) * A.bx;
+  for (int e = tid; e < CG * WY; e += kTPB) {
+    const int c = e % CG, l = e / CG;
+    const int j = jc0 + c;
+    if (j < A.bx) out[(size_t)l * A.bx + j] = conjf2(buf[c * ST + LW::at(l)]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_fld: grid (nblk, npol, nb); one block of 16 field rows per workgroup,
+// 4 waves: x-IFFT of the 16 rows, tilt/defocus removal, then
+// T = E Ux (MFMA 16x16x4 f32, each wave a quarter of x) and
+// C = Uy^T T (MFMA, T taken straight from the accumulators); the four waves'
+// partial C tiles are summed in LDS and written per block.
+template <int WX, int MT>
+__global__ void __launch_bounds__(kTPB) k_fld(KArgs A, int b0) {
+  using L = Lds<WX>;
+  constexpr int ST = L::STRIDE;
+  constexpr int NPAIR = (MT == 1) ? 1 : 3;        // (n-tile, m-tile) pairs that can hold m+n < 32
+  __shared__ float2 buf[16 * ST];
+  __shared__ float red[4][NPAIR][2][256];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int rb = blockIdx.x;
+  const int p = blockIdx.y;
+  const int bl = blockIdx.z;
+  const int bg = b0 + bl;
+  const PolTab& P = A.pol[p];
+  const float2* in = A.f2 + ((size_t)(bl * A.npol + p) * A.wy) * A.bx;
+  float2* fld = A.fields ? A.fields + ((size_t)bg * A.npol + p) * A.wy * WX : nullptr;
+  const int gp = A.gp;
+  constexpr int XS = WX / 4;    // x columns per wave
+  constexpr int KS = XS / 4;    // MFMA k-steps per wave
+  for (int e = tid; e < 16 * WX; e += kTPB) {
+    const int r = e / WX, q = e % WX;
+    const int y = rb * 16 + r;
+    float2 v = make_float2(0.f, 0.f);
+    if (y < A.wy) {
+      const int j = P.qcol[q];
+      if (j >= 0) v = conjf2(in[(size_t)y * A.bx + j]);
+    }
+    buf[r * ST + L::at(q)] = v;
+  }
+  __syncthreads();
+  fft_lds<WX, 16, ST, kTPB>(buf, A.tw_wx, tid);
+  for (int e = tid; e < 16 * WX; e += kTPB) {
+    const int r = e / WX, q = e % WX;
+    const int y = rb * 16 + r;
+    float2 ev = make_float2(0.f, 0.f);
+    if (y < A.wy) {
+      ev = cmul(cmul(conjf2(buf[r * ST + L::at(q)]), P.tx[q]), P.ty[y]);
+      if (fld) fld[(size_t)y * WX + q] = ev;
+    }
+    buf[r * ST + L::at(q)] = ev;
+  }
+  __syncthreads();
+  // T[y][m] = sum_x E[y][x] Ux[x][m] over this wave's quarter of x
+  floatx4 tre[MT], tim[MT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    tre[mt] = floatx4{0.f, 0.f, 0.f, 0.f};
+    tim[mt] = floatx4{0.f, 0.f, 0.f, 0.f};
+  }
+#pragma unroll 4
+  for (int s = 0; s < KS; ++s) {
+    const int x = wv * XS + 4 * s + (lane >> 4);
+    const float2 ev = buf[(lane & 15) * ST + L::at(x)];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const float ub = P.ux[x * gp + mt * 16 + (lane & 15)];
+      tre[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ev.x, ub, tre[mt], 0, 0, 0);
+      tim[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ev.y, ub, tim[mt], 0, 0, 0);
+    }
+  }
+  // C[n][m] = sum_y Uy[y][n] T[y][m]; k-step r covers y = rb*16 + 4*(lane/16) + r
+  floatx4 cre[NPAIR], cim[NPAIR];
+#pragma unroll
+  for (int q = 0; q < NPAIR; ++q) {
+    cre[q] = floatx4{0.f, 0.f, 0.f, 0.f};
+    cim[q] = floatx4{0.f, 0.f, 0.f, 0.f};
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int y = rb * 16 + 4 * (lane >> 4) + r;
+#pragma unroll
+    for (int q = 0; q < NPAIR; ++q) {
+      const int nt = (q == 2) ? 1 : 0;
+      const int mt = (q == 1) ? 1 : 0;
+      const float ua = P.uy[y * gp + nt * 16 + (lane & 15)];
+      cre[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ua, tre[mt][r], cre[q], 0, 0, 0);
+      cim[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ua, tim[mt][r], cim[q], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NPAIR; ++q) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int n = 4 * (lane >> 4) + r, m = lane & 15;
+      red[wv][q][0][n * 16 + m] = cre[q][r];
+      red[wv][q][1][n * 16 + m] = cim[q][r];
+    }
+  }
+  __syncthreads();
+  // partial[bl][rb][p][mode]: this block's share of every coefficient, the
+  // four waves summed in order
+  float2* part = A.partial + ((size_t)(bl * A.nblk + rb) * A.npol + p) * A.nmodes;
+  for (int i = tid; i < A.nmodes; i += kTPB) {
+    const short2 mn = A.modes[i];
+    const int m = mn.x, n = mn.y;
+    const int q = (n >= 16) ? 2 : (m >= 16) ? 1 : 0;
+    const int el = (n & 15) * 16 + (m & 15);
+    part[i] = make_float2(((red[0][q][0][el] + red[1][q][0][el]) + red[2][q][0][el]) + red[3][q][0][el],
+                          ((red[0][q][1][el] + red[1][q][1][el]) + red[2][q][1][el]) + red[3][q][1][el]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_norm: one workgroup per frame: coefficient (m, n) of pol p = the sum of
+// the row-block partials in block order; then the FP64 power over both pols
+// and the normalised coefficients.
+__global__ void __launch_bounds__(kTPB) k_norm(KArgs A, int b0) {
+  __shared__ double wsum[kTPB / 64];
+  const int bl = blockIdx.x, tid = threadIdx.x;
+  const int bg = b0 + bl;
+  const int per = A.npol * A.nmodes;
+  float2* raw = A.coefs + (size_t)bg * per;
+  const float2* part = A.partial + (size_t)bl * A.nblk * per;
+  double s = 0.0;
+  for (int i = tid; i < per; i += kTPB) {
+    float re = 0.f, im = 0.f;
+    for (int rb = 0; rb < A.nblk; ++rb) {
+      const float2 v = part[(size_t)rb * per + i];
+      re += v.x;
+      im += v.y;
+    }
+    raw[i] = make_float2(re, im);
+    s += (double)re * re + (double)im * im;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((tid & 63) == 0) wsum[tid >> 6] = s;
+  __syncthreads();
+  double tot = 0.0;
+#pragma unroll
+  for (int w = 0; w < kTPB / 64; ++w) tot += wsum[w];
+  const double inv = tot > 0.0 ? 1.0 / sqrt(tot) : 0.0;
+  float2* o = A.coefs_norm + (size_t)bg * per;
+  for (int i = tid; i < per; i += kTPB) {
+    const float2 c = raw[i];
+    o[i] = make_float2((float)(c.x * inv), (float)(c.y * inv));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_hg: out[k][n] = u_n(x_k) * pitch, x_k = (k - w/2) pitch, FP64 recurrence
+__global__ void k_hg(double pitch, int w, int wpad, double waist, int G, int gp, float* __restrict__ out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= wpad) return;
+  float* o = out + (size_t)k * gp;
+  if (k >= w) {
+    for (int n = 0; n < gp; ++n) o[n] = 0.f;
+    return;
+  }
+  const double x = (k - 0.5 * w) * pitch;
+  const double s = 1.4142135623730950488 * x / waist;
+  const double scale = 1.1892071150027210667 / sqrt(waist) * pitch;   // 2^(1/4) w^(-1/2) p'
+  double prev = 0.0;
+  double cur = 0.75112554446494248286 * exp(-0.5 * s * s);             // pi^(-1/4)
+  for (int n = 0; n < gp; ++n) {
+    o[n] = (n < G) ? (float)(cur * scale) : 0.f;
+    const double nxt = sqrt(2.0 / (n + 1)) * s * cur - sqrt((double)n / (n + 1)) * prev;
+    prev = cur;
+    cur = nxt;
+  }
+}
+
+__global__ void k_zero(float2* p, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = make_float2(0.f, 0.f);
+}
+
+// ---------------------------------------------------------------------------
+// dispatch over the supported sizes
+// transforms per row-pass block and columns per column-pass block (~32-80 KB of LDS)
+template <int N> constexpr int row_tr() { return N >= 2048 ? 1 : N >= 1024 ? 2 : N >= 512 ? 4 : N >= 256 ? 8 : 16; }
+template <int N> constexpr int col_cg() { return N >= 2048 ? 4 : N >= 1024 ? 8 : 16; }
+
+template <int NX>
+static hipError_t row_n(const KArgs& a, const void* frames, int u16, int b0, int nb, hipStream_t s) {
+  constexpr int TR = row_tr<NX>();
+  dim3 grid((a.ny + 2 * TR - 1) / (2 * TR), a.npol, nb);
+  if (u16)
+    hipLaunchKernelGGL((k_row<NX, TR, unsigned short>), grid, dim3(kTPB), 0, s, a, (const unsigned short*)frames, b0);
+  else
+    hipLaunchKernelGGL((k_row<NX, TR, float>), grid, dim3(kTPB), 0, s, a, (const float*)frames, b0);
+  return hipGetLastError();
+}
+
+template <int NY, int WY>
+static hipError_t col_nw(const KArgs& a, int b0, int nb, hipStream_t s) {
+  constexpr int CG = col_cg<NY>();
+  dim3 grid((a.bx + CG - 1) / CG, a.npol, nb);
+  hipLaunchKernelGGL((k_col<NY, WY, CG>), grid, dim3(kTPB), 0, s, a, b0);
+  return hipGetLastError();
+}
+
+template <int WX>
+static hipError_t fld_w(const KArgs& a, int b0, int nb, hipStream_t s) {
+  dim3 grid(a.nblk, a.npol, nb);
+  if (a.gp <= 16)
+    hipLaunchKernelGGL((k_fld<WX, 1>), grid, dim3(kTPB), 0, s, a, b0);
+  else
+    hipLaunchKernelGGL((k_fld<WX, 2>), grid, dim3(kTPB), 0, s, a, b0);
+  return hipGetLastError();
+}
+
+#define DH_FFT_SIZES(X) X(64) X(128) X(256) X(320) X(512) X(640) X(1024) X(2048)
+#define DH_IFFT_SIZES(X) X(32) X(48) X(96) X(112) X(176) X(208) X(336) X(672)
+// (FFT length, IFFT length) pairs along y: the window-radius rule at ratios up to 0.32
+#define DH_COL_PAIRS(X) \
+  X(64, 32) X(128, 32) X(128, 48) X(256, 48) X(256, 96) X(320, 96) X(320, 112) X(512, 96) X(512, 176) \
+  X(640, 176) X(640, 208) X(1024, 176) X(1024, 336) X(2048, 336) X(2048, 672)
+
+static bool fft_ok(int n) {
+#define X(N) if (n == N) return true;
+  DH_FFT_SIZES(X)
+#undef X
+  return false;
+}
+static bool ifft_ok(int n) {
+#define X(N) if (n == N) return true;
+  DH_IFFT_SIZES(X)
+#undef X
+  return false;
+}
+static bool pair_ok(int n, int w) {
+#define X(N, W) if (n == N && w == W) return true;
+  DH_COL_PAIRS(X)
+#undef X
+  return false;
+}
+
+void fft_radices(int n, int r[3]) {
+  r[0] = r[1] = r[2] = 0;
+#define X(N) if (n == N) { r[0] = FftPlan<N>::R0; r[1] = FftPlan<N>::R1; r[2] = FftPlan<N>::R2; return; }
+  DH_FFT_SIZES(X)
+  DH_IFFT_SIZES(X)
+#undef X
+}
+
+bool sizes_supported(int nx, int ny, int wx, int wy) {
+  return fft_ok(nx) && fft_ok(ny) && ifft_ok(wx) && ifft_ok(wy) && pair_ok(ny, wy);
+}
+
+hipError_t launch_row(const KArgs& a, const void* frames, int u16, int b0, int nb, hipStream_t s) {
+#define X(N) if (a.nx == N) return row_n<N>(a, frames, u16, b0, nb, s);
+  DH_FFT_SIZES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+hipError_t launch_col(const KArgs& a, int b0, int nb, hipStream_t s) {
+#define X(N, W) if (a.ny == N && a.wy == W) return col_nw<N, W>(a, b0, nb, s);
+  DH_COL_PAIRS(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+hipError_t launch_fld(const KArgs& a, int b0, int nb, hipStream_t s) {
+#define X(W) if (a.wx == W) return fld_w<W>(a, b0, nb, s);
+  DH_IFFT_SIZES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+hipError_t launch_norm(const KArgs& a, int b0, int nb, hipStream_t s) {
+  hipLaunchKernelGGL(k_norm, dim3(nb), dim3(kTPB), 0, s, a, b0);
+  return hipGetLastError();
+}
+hipError_t launch_zero(float2* p, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+hipError_t launch_hg(double pitch, int w, int wpad, double waist, int G, int gp, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_hg, dim3((wpad + 63) / 64), dim3(64), 0, s, pitch, w, wpad, waist, G, gp, out);
+  return hipGetLastError();
+}
+
+}  // namespace dh

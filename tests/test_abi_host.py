@@ -1,0 +1,109 @@
+"""Host-only checks of the C ABI: the library loads, exports what
+include/dh.h declares, validates parameters with the paper's error codes and
+derives the same geometry as the oracle. No GPU work is launched."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import dh_synth
+import oracle
+import paper_2204_02348_amd as dh
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "dh.h")).read()
+    return sorted(set(re.findall(r"^\w[\w\s\*]*?\b(dh_\w+)\s*\(", txt, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared()
+    assert "dh_plan" in names and "dh_process_batch" in names and "dh_mode_coefs" in names
+    L = ctypes.CDLL(dh.LIB_PATH)
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(dh.EXPORTS) == names
+
+
+def _p(idx=1, **kw):
+    d = dict(dh_synth.config(idx)["params"])
+    d.update(kw)
+    return d
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(pol_count=3), dh.ERR_INVALIDPOLARISATION),
+    (dict(pol_count=0), dh.ERR_INVALIDPOLARISATION),
+    (dict(frame_w=650), dh.ERR_INVALIDDIMENSION),
+    (dict(frame_h=0), dh.ERR_INVALIDDIMENSION),
+    (dict(fft_w=8), dh.ERR_INVALIDDIMENSION),
+    (dict(fft_w=336), dh.ERR_INVALIDDIMENSION),          # window 0 would leave the frame
+    (dict(pixel_size=0.0), dh.ERR_INVALIDARGUMENT),
+    (dict(wavelength=-1.0), dh.ERR_INVALIDARGUMENT),
+    (dict(window_radius_deg=0.0), dh.ERR_INVALIDARGUMENT),
+    (dict(window_radius_deg=5.0), dh.ERR_INVALIDARGUMENT),  # wider than the spectrum
+    (dict(waist=0.0), dh.ERR_INVALIDARGUMENT),
+    (dict(max_mg=-1), dh.ERR_INVALIDARGUMENT),
+    (dict(max_mg=33), dh.ERR_INVALIDARGUMENT),
+    (dict(input_dtype=7), dh.ERR_INVALIDARGUMENT),
+    (dict(precision=9), dh.ERR_INVALIDARGUMENT),
+    (dict(ifft_mode=0), dh.ERR_INVALIDARGUMENT),
+    (dict(beam_centre=[[400 * 20e-6, 0], [0, 0]]), dh.ERR_INVALIDDIMENSION),
+])
+def test_validation_error_codes(kw, code):
+    rc, _ = dh.plan_check(_p(**kw))
+    assert rc == code
+
+
+def test_null_pointer():
+    assert dh.lib().dh_plan_check(None, 1, None) == dh.ERR_NULLPOINTER
+    h = ctypes.c_int()
+    assert dh.lib().dh_plan(None, 1, 0, ctypes.byref(h)) == dh.ERR_NULLPOINTER
+
+
+def test_invalid_handles_without_gpu():
+    L = dh.lib()
+    assert L.dh_destroy(12345) == dh.ERR_INVALIDHANDLE
+    assert L.dh_last_error(-1) == dh.ERR_INVALIDHANDLE
+    b = ctypes.c_int(7)
+    m = ctypes.c_int(7)
+    assert L.dh_mode_coefs(999, None, None, ctypes.byref(b), ctypes.byref(m), None, 1) == dh.ERR_INVALIDHANDLE
+    assert b.value == 0 and m.value == 0   # getters zero their outputs on a bad handle
+
+
+def test_window_size_floored_to_16():
+    rc, info = dh.plan_check(_p(0, fft_w=130, fft_h=143))
+    assert rc == 0 and info.fft_w == 128 and info.fft_h == 128
+
+
+@pytest.mark.parametrize("idx,cam", [(0, 0), (1, 0), (2, 0), (3, 0), (3, 1), (3, 2), (3, 3), (4, 0)])
+def test_plan_geometry_matches_oracle(idx, cam):
+    cfg = dh_synth.config(idx, cam)
+    d = cfg["truth"]
+    rc, info = dh.plan_check(d, cfg["frames"])
+    assert rc == 0
+    g = oracle.geometry(d)
+    assert (info.ifft_w, info.ifft_h) == (g["wx"], g["wy"])
+    assert info.modes == oracle.mode_count(d["max_mg"])
+    assert math.isclose(info.rx, g["rx"], rel_tol=1e-14) and math.isclose(info.ry, g["ry"], rel_tol=1e-14)
+    assert math.isclose(info.pitch_x, g["px2"], rel_tol=1e-14)
+    bw = 0
+    for pol, gp in enumerate(g["pols"]):
+        assert (info.x0[pol], info.y0[pol]) == (gp["x0"], gp["y0"])
+        assert math.isclose(info.ax[pol], gp["ax"], rel_tol=1e-14)
+        cols = gp["us"][gp["mask"].any(axis=0)]
+        bw = max(bw, cols.max() - cols.min() + 1)
+    assert info.box_w == bw
+    assert info.device_bytes > 0 and info.chunk >= 1
+
+
+def test_hbm_budget_is_checked_before_allocating():
+    # the budget check happens before any device call, so it runs here too
+    h = ctypes.c_int(-1)
+    p = dh.make_params(_p())
+    assert dh.lib().dh_plan(ctypes.byref(p), 1000, 1024, ctypes.byref(h)) == dh.ERR_MEMORYALLOCATION

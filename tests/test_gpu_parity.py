@@ -1,0 +1,164 @@
+"""GPU path vs the FP64 oracle, element by element, through the C ABI.
+
+Tolerance (FP32 path): relative L2 error <= 1e-5 per frame and polarisation
+on the Fourier window, the field and the coefficients (raw and normalised).
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import dh_synth
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(autouse=True, scope="module")
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _rel(a, b):
+    n = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (n if n > 0 else 1.0)
+
+
+def run_gpu(params, frames, keep=True, chunk=None, stream=True):
+    torch = _torch()
+    import paper_2204_02348_amd as dh
+    d = dict(params, keep_window=int(keep), keep_fields=int(keep))
+    if chunk:
+        os.environ["DH_CHUNK_FRAMES"] = str(chunk)
+    try:
+        plan = dh.Plan(d, max_batch=frames.shape[0])
+    finally:
+        os.environ.pop("DH_CHUNK_FRAMES", None)
+    ft = torch.from_numpy(np.ascontiguousarray(frames)).cuda()
+    s = torch.cuda.Stream() if stream else None
+    if s is not None:
+        s.wait_stream(torch.cuda.current_stream())
+    plan.process(ft, frames.shape[0], s)
+    out = dict(coefs=plan.coefs(False), coefs_norm=plan.coefs(True), info=plan.info)
+    if keep:
+        out["window"] = plan.window()
+        out["field"] = plan.fields()
+    torch.cuda.synchronize()
+    plan.destroy()
+    return out
+
+
+def check_frames(params, frames, gpu, idx, keep=True, tol=TOL):
+    worst = {}
+    for i in idx:
+        ref = oracle.process_frame(frames[i].astype(np.float64), params)
+        keys = ["coefs", "coefs_norm"] + (["window", "field"] if keep else [])
+        for k in keys:
+            for pol in range(params["pol_count"]):
+                if params["max_mg"] == 0 and k.startswith("coefs"):
+                    continue
+                e = _rel(gpu[k][i][pol].astype(np.complex128), ref[k][pol])
+                worst[k] = max(worst.get(k, 0.0), e)
+    _say("worst rel-L2", {k: f"{v:.2e}" for k, v in worst.items()})
+    for k, v in worst.items():
+        assert v <= tol, (k, v)
+    return worst
+
+
+def _frames(idx, cam=0, n=None, first=0):
+    cfg = dh_synth.config(idx, cam)
+    f, c = dh_synth.make_frames(cfg, n_frames=n, first=first)
+    return cfg, f, c
+
+
+def test_config0_single_frame():
+    cfg, f, _ = _frames(0)
+    _say("config0 128x128 G=4 batch 1")
+    gpu = run_gpu(cfg["params"], f)
+    check_frames(cfg["params"], f, gpu, [0])
+
+
+def test_config1_small_batch_ragged_chunks():
+    cfg, f, _ = _frames(1, n=7)
+    _say("config1 640x512 2 pols G=9 batch 7 chunk 3")
+    gpu = run_gpu(cfg["params"], f, chunk=3)
+    check_frames(cfg["params"], f, gpu, range(7))
+
+
+def test_config1_full_batch_sampled():
+    cfg, pool, _ = _frames(1, n=100)
+    f = dh_synth.tile_pool(pool, 1000)
+    _say("config1 batch 1000 (bench launch configuration), sampled frames")
+    gpu = run_gpu(cfg["params"], f, keep=False)
+    check_frames(cfg["params"], f, gpu, [0, 1, 85, 86, 511, 998, 999], keep=False)
+
+
+def test_config2_g20():
+    cfg, f, _ = _frames(2)
+    _say("config2 128x128 G=20")
+    gpu = run_gpu(cfg["params"], f)
+    check_frames(cfg["params"], f, gpu, [0])
+
+
+@pytest.mark.parametrize("cam", [0, 1, 2, 3])
+def test_config3_cameras_u16(cam):
+    cfg, f, _ = _frames(3, cam=cam, n=3 if cam < 3 else 2)
+    assert f.dtype == np.uint16
+    _say("config3 camera", cam, f.shape)
+    gpu = run_gpu(cfg["params"], f)
+    check_frames(cfg["params"], f, gpu, range(f.shape[0]))
+
+
+def test_config4_alignment_shape():
+    cfg, f, _ = _frames(4, n=3)
+    _say("config4 1024x1024 2 pols G=30 at the true parameters")
+    gpu = run_gpu(cfg["truth"], f)
+    check_frames(cfg["truth"], f, gpu, range(3))
+
+
+def test_subpixel_centre_defocus_and_per_pol_tilt():
+    cfg = dh_synth.config(1)
+    # 256x256 windows inside the 320x512 halves, so the beam centres can move
+    truth = dict(cfg["truth"], fft_w=256, fft_h=256, defocus=[0.15, -0.1],
+                 tilt_deg=[[1.45, 1.55], [1.52, 1.47]],
+                 beam_centre=[[0.3 * 20e-6, -2.2 * 20e-6], [-1.4 * 20e-6, 0.1 * 20e-6]])
+    cfg = dict(cfg, truth=truth)
+    f, c = dh_synth.make_frames(cfg, n_frames=2)
+    _say("sub-pixel centre / defocus / per-pol tilt")
+    gpu = run_gpu(truth, f)
+    check_frames(truth, f, gpu, range(2))
+
+
+def test_no_decomposition_fields_only():
+    cfg, f, _ = _frames(0)
+    p = dict(cfg["params"], max_mg=0)
+    _say("G=0 fields only")
+    gpu = run_gpu(p, f)
+    assert gpu["coefs"].shape[2] == 0
+    check_frames(p, f, gpu, [0])
+
+
+def test_frame_alone_equals_frame_in_batch():
+    cfg, f, _ = _frames(1, n=6)
+    _say("determinism: alone vs in batch")
+    alone = run_gpu(cfg["params"], f[3:4], keep=False)
+    batch = run_gpu(cfg["params"], f, keep=False, chunk=4)
+    assert np.array_equal(alone["coefs"][0], batch["coefs"][3])
+    assert np.array_equal(alone["coefs_norm"][0], batch["coefs_norm"][3])
