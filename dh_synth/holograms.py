@@ -95,7 +95,30 @@ def config(idx: int, camera: int = 0) -> dict:
     return c
 
 
-def forward_hologram(truth: dict, coefs: np.ndarray) -> np.ndarray:
+def _plane_cache(truth: dict) -> list:
+    """Per-pol coordinate axes, HG tables and reference-phase factors, which
+    every frame of a recipe shares."""
+    fw, fh, npol = truth["frame_w"], truth["frame_h"], truth["pol_count"]
+    pix, lam, waist = truth["pixel_size"], truth["wavelength"], truth["waist"]
+    half = fw // npol
+    modes = _modes(truth["max_mg"])
+    gmax = max(max(m, n) for m, n in modes) + 1 if modes else 0
+    out = []
+    for pol in range(npol):
+        bcx, bcy = truth["beam_centre"][pol]
+        x = (np.arange(half) - half // 2) * pix - bcx
+        y = (np.arange(fh) - fh // 2) * pix - bcy
+        hx = np.stack([hg_closed_form(m, x, waist) for m in range(gmax)]) if gmax else None
+        hy = np.stack([hg_closed_form(n, y, waist) for n in range(gmax)]) if gmax else None
+        tx, ty = (t * math.pi / 180.0 for t in truth["tilt_deg"][pol])
+        d = truth["defocus"][pol]
+        phi = (2 * math.pi * (tx * x[None, :] + ty * y[:, None]) / lam
+               + math.pi * d * (x[None, :] ** 2 + y[:, None] ** 2) / lam)
+        out.append(dict(hx=hx, hy=hy, gmax=gmax, cos=np.cos(phi), sin=np.sin(phi)))
+    return out
+
+
+def forward_hologram(truth: dict, coefs: np.ndarray, cache: list | None = None) -> np.ndarray:
     """|S_p + R_p|^2 on every pixel of the frame (FP64, before scaling).
 
     coefs: [pol][mode] complex, modes ordered by group ascending then m
@@ -104,41 +127,74 @@ def forward_hologram(truth: dict, coefs: np.ndarray) -> np.ndarray:
     with x, y measured from the pol's beam centre (in metres relative to the
     centre pixel of its half-frame)."""
     fw, fh, npol = truth["frame_w"], truth["frame_h"], truth["pol_count"]
-    pix, lam, waist = truth["pixel_size"], truth["wavelength"], truth["waist"]
     half = fw // npol
     modes = _modes(truth["max_mg"])
-    fields = []
+    if cache is None:
+        cache = _plane_cache(truth)
+    sig = []
     for pol in range(npol):
-        bcx, bcy = truth["beam_centre"][pol]
-        x = (np.arange(half) - half // 2) * pix - bcx
-        y = (np.arange(fh) - fh // 2) * pix - bcy
-        gmax = max(max(m, n) for m, n in modes) + 1 if modes else 0
-        hx = np.stack([hg_closed_form(m, x, waist) for m in range(gmax)]) if gmax else None
-        hy = np.stack([hg_closed_form(n, y, waist) for n in range(gmax)]) if gmax else None
-        cmat = np.zeros((gmax, gmax), dtype=np.complex128)
-        for k, (m, n) in enumerate(modes):
-            cmat[n, m] = coefs[pol][k]
-        s = hy.T @ cmat @ hx if gmax else np.zeros((fh, half), dtype=np.complex128)
-        fields.append((s, x, y))
-    amp = max(float(np.abs(s).max()) for s, _, _ in fields)
-    frame = np.zeros((fh, fw), dtype=np.float64)
-    for pol, (s, x, y) in enumerate(fields):
-        tx, ty = (t * math.pi / 180.0 for t in truth["tilt_deg"][pol])
-        d = truth["defocus"][pol]
-        phi = (2 * math.pi * (tx * x[None, :] + ty * y[:, None]) / lam
-               + math.pi * d * (x[None, :] ** 2 + y[:, None] ** 2) / lam)
-        r = amp * np.exp(1j * phi)
-        frame[:, pol * half:(pol + 1) * half] = np.abs(s + r) ** 2
+        c = cache[pol]
+        g = c["gmax"]
+        if g:
+            cmat = np.zeros((g, g), dtype=np.complex128)
+            for k, (m, n) in enumerate(modes):
+                cmat[n, m] = coefs[pol][k]
+            sig.append(c["hy"].T @ cmat @ c["hx"])
+        else:
+            sig.append(np.zeros((fh, half), dtype=np.complex128))
+    amp = max(float(np.abs(s).max()) for s in sig)
+    frame = np.empty((fh, fw), dtype=np.float64)
+    for pol, s in enumerate(sig):
+        c = cache[pol]
+        re = s.real + amp * c["cos"]
+        im = s.imag + amp * c["sin"]
+        frame[:, pol * half:(pol + 1) * half] = re * re + im * im
     return frame
 
 
+def _frame_job(args):
+    cfg, kid, quantise, nm, cache = args
+    truth = cfg["truth"]
+    npol = truth["pol_count"]
+    rng = np.random.Generator(np.random.PCG64(kid))
+    c = (rng.standard_normal((npol, nm)) + 1j * rng.standard_normal((npol, nm))) / math.sqrt(2)
+    pw = float(np.sum(np.abs(c) ** 2))
+    c = c / math.sqrt(pw) if pw > 0 else c
+    f = forward_hologram(truth, c, cache)
+    if not quantise:
+        return f, c
+    level = 4095.0 * f / f.max()
+    if cfg["noise"]:
+        level = rng.poisson(0.9 * level).astype(np.float64) + rng.normal(0.0, 2.0, size=level.shape)
+    out_dtype = np.uint16 if cfg["dtype"] == "u16" else np.float32
+    return np.clip(np.rint(level), 0, 4095).astype(out_dtype), c
+
+
+_POOL_ARGS = None
+
+
+def _pool_init():
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except Exception:
+        pass
+
+
+def _pool_job(i):
+    cfg, kids, quantise, nm, cache = _POOL_ARGS
+    return _frame_job((cfg, kids[i], quantise, nm, cache))
+
+
 def make_frames(cfg: dict, n_frames: int | None = None, quantise: bool = True,
-                first: int = 0):
+                first: int = 0, workers: int = 1):
     """Frames i = first .. first+n-1 of recipe `cfg`: (frames, coefs).
 
     frames: [n][frame_h][frame_w], float32 (or uint16 for u16 recipes; FP64
     when quantise is False); coefs: [n][pol][mode] complex128 true
-    coefficients, unit power per frame over both pols."""
+    coefficients, unit power per frame over both pols. workers > 1 forks a
+    process pool (only call it before the process has touched a GPU)."""
+    global _POOL_ARGS
     truth = cfg["truth"]
     n = cfg["frames"] if n_frames is None else n_frames
     ss = np.random.SeedSequence(BASE_SEED + cfg["index"] + 1000 * cfg.get("camera", 0))
@@ -149,20 +205,17 @@ def make_frames(cfg: dict, n_frames: int | None = None, quantise: bool = True,
     out_dtype = np.float64 if not quantise else (np.uint16 if cfg["dtype"] == "u16" else np.float32)
     frames = np.empty((n, truth["frame_h"], truth["frame_w"]), dtype=out_dtype)
     coefs = np.empty((n, npol, nm), dtype=np.complex128)
-    for i, kid in enumerate(kids):
-        rng = np.random.Generator(np.random.PCG64(kid))
-        c = (rng.standard_normal((npol, nm)) + 1j * rng.standard_normal((npol, nm))) / math.sqrt(2)
-        pw = float(np.sum(np.abs(c) ** 2))
-        c = c / math.sqrt(pw) if pw > 0 else c
-        coefs[i] = c
-        f = forward_hologram(truth, c)
-        if not quantise:
-            frames[i] = f
-            continue
-        level = 4095.0 * f / f.max()
-        if cfg["noise"]:
-            level = rng.poisson(0.9 * level).astype(np.float64) + rng.normal(0.0, 2.0, size=level.shape)
-        frames[i] = np.clip(np.rint(level), 0, 4095).astype(out_dtype)
+    cache = _plane_cache(truth)
+    if workers > 1 and n > 1:
+        import multiprocessing as mp
+        _POOL_ARGS = (cfg, kids, quantise, nm, cache)
+        with mp.get_context("fork").Pool(workers, initializer=_pool_init) as pool:
+            for i, (f, c) in enumerate(pool.imap(_pool_job, range(n), chunksize=8)):
+                frames[i], coefs[i] = f, c
+        _POOL_ARGS = None
+    else:
+        for i, kid in enumerate(kids):
+            frames[i], coefs[i] = _frame_job((cfg, kid, quantise, nm, cache))
     return frames, coefs
 
 
