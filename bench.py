@@ -42,6 +42,27 @@ def stage_bytes(info, params, frames):
     }
 
 
+STAGE_KERNEL = {"fft_x": "dh::k_row", "fft_y_crop_ifft_y": "dh::k_col", "ifft_x_tilt_overlap": "dh::k_fld",
+                "power_norm": "dh::k_norm"}
+
+
+def counter_traffic(stage, frames_per_launch):
+    """HBM bytes per launch of `stage`'s kernel from the committed counter
+    summary (profiles/traffic_c2_640x512.json), or None if the kernel sources
+    changed since the counters were taken."""
+    path = os.path.join(HERE, "profiles", "traffic_c2_640x512.json")
+    if not os.path.exists(path):
+        return None
+    import bench_traffic
+    t = json.load(open(path))
+    if t.get("fingerprint") != bench_traffic.source_fingerprint():
+        return None
+    for name, k in t["kernels"].items():
+        if name.startswith(STAGE_KERNEL[stage]):
+            return round((k["read_bytes_per_frame"] + k["write_bytes_per_frame"]) * frames_per_launch)
+    return None
+
+
 def cpu_baseline(cfg, frames, seconds):
     """The FP64 oracle, as it stands, on a bounded sample of the same frames."""
     import oracle
@@ -71,7 +92,19 @@ def main():
     ap.add_argument("--frames", type=int, default=1000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device-to-device copy of 512 MiB (HBM counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        n = 512 * 1024 * 1024 // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4}), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(frames shard with no exchange; see the design notes).", file=sys.stderr)
@@ -120,8 +153,12 @@ def main():
     ms_dom, n_dom = stages[dom]
     per_launch_bytes = sb[dom] / (n_dom / args.steps)
     achieved = per_launch_bytes / (ms_dom / n_dom / 1e3) / 1e9
+    frames_per_launch = B / (n_dom / args.steps)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": counter_traffic(dom, frames_per_launch) if B == 1000 else None,
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "algorithmic_bytes": round(per_launch_bytes), "kernel": dom,
                 "launch_ms": round(ms_dom / n_dom, 4), "launches_per_step": n_dom // args.steps}
     frame_bytes = frames[0].nbytes
     out = {

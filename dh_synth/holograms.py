@@ -170,31 +170,14 @@ def _frame_job(args):
     return np.clip(np.rint(level), 0, 4095).astype(out_dtype), c
 
 
-_POOL_ARGS = None
-
-
-def _pool_init():
-    try:
-        from threadpoolctl import threadpool_limits
-        threadpool_limits(1)
-    except Exception:
-        pass
-
-
-def _pool_job(i):
-    cfg, kids, quantise, nm, cache = _POOL_ARGS
-    return _frame_job((cfg, kids[i], quantise, nm, cache))
-
-
 def make_frames(cfg: dict, n_frames: int | None = None, quantise: bool = True,
                 first: int = 0, workers: int = 1):
     """Frames i = first .. first+n-1 of recipe `cfg`: (frames, coefs).
 
     frames: [n][frame_h][frame_w], float32 (or uint16 for u16 recipes; FP64
     when quantise is False); coefs: [n][pol][mode] complex128 true
-    coefficients, unit power per frame over both pols. workers > 1 forks a
-    process pool (only call it before the process has touched a GPU)."""
-    global _POOL_ARGS
+    coefficients, unit power per frame over both pols. workers > 1 uses a
+    thread pool; the frames do not depend on it."""
     truth = cfg["truth"]
     n = cfg["frames"] if n_frames is None else n_frames
     ss = np.random.SeedSequence(BASE_SEED + cfg["index"] + 1000 * cfg.get("camera", 0))
@@ -207,12 +190,12 @@ def make_frames(cfg: dict, n_frames: int | None = None, quantise: bool = True,
     coefs = np.empty((n, npol, nm), dtype=np.complex128)
     cache = _plane_cache(truth)
     if workers > 1 and n > 1:
-        import multiprocessing as mp
-        _POOL_ARGS = (cfg, kids, quantise, nm, cache)
-        with mp.get_context("fork").Pool(workers, initializer=_pool_init) as pool:
-            for i, (f, c) in enumerate(pool.imap(_pool_job, range(n), chunksize=8)):
+        # threads, not processes: safe in a process that already holds a GPU
+        # context (numpy releases the GIL in the large array operations)
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(max_workers=workers) as ex:
+            for i, (f, c) in enumerate(ex.map(lambda kid: _frame_job((cfg, kid, quantise, nm, cache)), kids)):
                 frames[i], coefs[i] = f, c
-        _POOL_ARGS = None
     else:
         for i, kid in enumerate(kids):
             frames[i], coefs[i] = _frame_job((cfg, kid, quantise, nm, cache))

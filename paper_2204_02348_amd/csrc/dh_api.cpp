@@ -132,27 +132,44 @@ int derive(const dh_params* p, Geom* g) {
 
 size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
 
-int chunk_for(const Geom& g, int npol, int max_batch) {
-  // keep the two intermediates of one chunk within ~96 MB (a last-level
-  // cache sized working set); DH_CHUNK_FRAMES overrides the frame count
-  const size_t per = (size_t)npol * ((size_t)g.ny + g.wy) * g.bx * 8;
-  long c = (long)(96ull * 1024 * 1024 / (per ? per : 1));
-  if (const char* env = std::getenv("DH_CHUNK_FRAMES")) {
+int env_int(const char* name, int dflt) {
+  if (const char* env = std::getenv(name)) {
     const long v = std::strtol(env, nullptr, 10);
-    if (v > 0) c = v;
+    if (v > 0) return (int)v;
   }
+  return dflt;
+}
+
+int chunk_for(const Geom& g, int npol, int max_batch) {
+  // Frames per launch. Larger launches amortise the partly filled last wave
+  // of workgroups; whether the intermediates stay in the last-level cache was
+  // measured not to matter, so a chunk is as large as a 2 GiB workspace
+  // allows. DH_CHUNK_FRAMES overrides the frame count.
+  const size_t per = (size_t)npol * ((size_t)g.ny + (size_t)g.wy + g.wy / 8) * ((g.bx + 15) / 16 * 16) * 8;
+  long c = (long)((2ull << 30) / (per ? per : 1));
+  c = env_int("DH_CHUNK_FRAMES", (int)std::min<long>(c, 1 << 30));
   if (c < 1) c = 1;
   if (c > max_batch) c = max_batch;
   return (int)c;
 }
 
+// chunks in flight at once, each on its own internal stream with its own
+// workspace (DH_STREAMS overrides; 1 = everything on the caller's stream)
+int streams_for(int max_batch, int chunk) {
+  int n = env_int("DH_STREAMS", 2);
+  const int chunks = (max_batch + chunk - 1) / chunk;
+  if (n > chunks) n = chunks;
+  if (n > 4) n = 4;
+  return n < 1 ? 1 : n;
+}
+
 struct Layout {  // byte offsets inside one device allocation
   size_t tw_nx, tw_ny, tw_wx, tw_wy, modes, total_tables;
   size_t pol_mrow[2], pol_qrow[2], pol_qcol[2], pol_rhox[2], pol_rhoy[2], pol_tx[2], pol_ty[2], pol_ux[2], pol_uy[2];
-  size_t t1, f2, partial, coefs, coefs_norm, window, fields, total;
+  size_t t1[4], f2[4], partial[4], coefs, coefs_norm, window, fields, total;
 };
 
-Layout layout(const Geom& g, const dh_params* p, int max_batch, int chunk) {
+Layout layout(const Geom& g, const dh_params* p, int max_batch, int chunk, int nws) {
   Layout L{};
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o += align256(bytes); return r; };
@@ -171,10 +188,12 @@ Layout layout(const Geom& g, const dh_params* p, int max_batch, int chunk) {
   }
   L.total_tables = o;
   const size_t P = p->pol_count;
-  L.t1 = take((size_t)chunk * P * g.ny * g.bx * 8);
-  L.f2 = take((size_t)chunk * P * g.wy * g.bx * 8);
-  L.partial = take((size_t)chunk * P * (g.wyp / 16) * (g.nmodes > 0 ? g.nmodes : 1) * 8);
   const size_t nm = g.nmodes > 0 ? g.nmodes : 1;
+  for (int w = 0; w < nws; ++w) {
+    L.t1[w] = take((size_t)chunk * P * g.ny * g.bx * 8);
+    L.f2[w] = take((size_t)chunk * P * g.wy * ((g.bx + 15) / 16 * 16) * 8);
+    L.partial[w] = take((size_t)chunk * P * (g.wyp / 16) * nm * 8);
+  }
   L.coefs = take((size_t)max_batch * P * nm * 8);
   L.coefs_norm = take((size_t)max_batch * P * nm * 8);
   L.window = p->keep_window ? take((size_t)max_batch * P * g.wy * g.wx * 8) : 0;
@@ -187,35 +206,30 @@ struct Plan {
   dh_params params;
   Geom g;
   Layout L;
-  int max_batch = 1, chunk = 1, last_batch = 0, last_error = 0;
+  int max_batch = 1, chunk = 1, nws = 1, last_batch = 0, last_error = 0;
   int device = 0;
   char* mem = nullptr;
   hipStream_t last_stream = nullptr;
-  dh::KArgs ka{};
-  // per-stage timing: events recorded around every launch while enabled
+  dh::KArgs ka[4]{};                 // one per workspace
+  hipStream_t str[4]{};              // internal streams (nws > 1)
+  hipEvent_t fork = nullptr, join[4]{};
+  // per-stage timing: a start and an end event around every launch, on the
+  // stream the kernel runs on
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
-  std::vector<int> ev_stage;   // stage of the launch that ends at event i (i >= 1); -1: a batch start
-  size_t ev_used = 0;
+  std::vector<int> ev_stage;         // stage of launch i (events 2i, 2i+1)
+  size_t ev_used = 0;                // events used
 };
 
-hipEvent_t next_event(Plan* pl, int stage) {
+hipError_t timed_event(Plan* pl, hipStream_t s, int stage, bool start) {
+  if (!pl->timing) return hipSuccess;
   if (pl->ev_used == pl->ev_pool.size()) {
     hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return hipErrorOutOfMemory;
     pl->ev_pool.push_back(e);
   }
-  if (pl->ev_stage.size() <= pl->ev_used) pl->ev_stage.resize(pl->ev_used + 1);
-  pl->ev_stage[pl->ev_used] = stage;
-  return pl->ev_pool[pl->ev_used++];
-}
-
-// record the end of a launch of `stage` (or a batch start, stage -1)
-hipError_t mark(Plan* pl, int stage, hipStream_t s) {
-  if (!pl->timing) return hipSuccess;
-  hipEvent_t e = next_event(pl, stage);
-  if (!e) return hipErrorOutOfMemory;
-  return hipEventRecord(e, s);
+  if (start) pl->ev_stage.push_back(stage);
+  return hipEventRecord(pl->ev_pool[pl->ev_used++], s);
 }
 
 std::mutex g_mu;
@@ -323,15 +337,15 @@ int build_tables(Plan* pl) {
   return DH_SUCCESS;
 }
 
-void fill_kargs(Plan* pl) {
+void fill_kargs(Plan* pl, int w) {
   const Geom& g = pl->g;
   const dh_params* p = &pl->params;
   const Layout& L = pl->L;
-  dh::KArgs& a = pl->ka;
+  dh::KArgs& a = pl->ka[w];
   char* m = pl->mem;
   a.frame_w = p->frame_w; a.frame_h = p->frame_h; a.npol = p->pol_count;
   a.nx = g.nx; a.ny = g.ny; a.wx = g.wx; a.wy = g.wy; a.wyp = g.wyp;
-  a.bx = g.bx; a.by = g.by; a.G = g.G; a.gp = g.gp; a.nmodes = g.nmodes;
+  a.bx = g.bx; a.by = g.by; a.bxp = (g.bx + 15) / 16 * 16; a.G = g.G; a.gp = g.gp; a.nmodes = g.nmodes;
   a.nxny = (float)((double)g.nx * g.ny);
   for (int q = 0; q < p->pol_count; ++q) {
     const PolGeom& P = g.pol[q];
@@ -353,9 +367,9 @@ void fill_kargs(Plan* pl) {
   a.tw_ny = (const float2*)(m + L.tw_ny);
   a.tw_wx = (const float2*)(m + L.tw_wx);
   a.tw_wy = (const float2*)(m + L.tw_wy);
-  a.t1 = (float2*)(m + L.t1);
-  a.f2 = (float2*)(m + L.f2);
-  a.partial = (float2*)(m + L.partial);
+  a.t1 = (float2*)(m + L.t1[w]);
+  a.f2 = (float2*)(m + L.f2[w]);
+  a.partial = (float2*)(m + L.partial[w]);
   a.nblk = g.wyp / 16;
   a.coefs = (float2*)(m + L.coefs);
   a.coefs_norm = (float2*)(m + L.coefs_norm);
@@ -375,6 +389,22 @@ int copy_out(Plan* pl, void* host_out, size_t bytes, const void* dev) {
   return DH_SUCCESS;
 }
 
+void release(Plan* pl) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipSetDevice(pl->device);
+  (void)hipDeviceSynchronize();
+  for (int w = 0; w < 4; ++w) {
+    if (pl->str[w]) (void)hipStreamDestroy(pl->str[w]);
+    if (pl->join[w]) (void)hipEventDestroy(pl->join[w]);
+  }
+  if (pl->fork) (void)hipEventDestroy(pl->fork);
+  for (hipEvent_t e : pl->ev_pool) (void)hipEventDestroy(e);
+  if (pl->mem) (void)hipFree(pl->mem);
+  (void)hipSetDevice(dev);
+  delete pl;
+}
+
 }  // namespace
 
 extern "C" {
@@ -387,7 +417,7 @@ int dh_plan_check(const dh_params* p, int max_batch, dh_plan_info* info) {
   if (info) {
     std::memset(info, 0, sizeof(*info));
     const int chunk = chunk_for(g, p->pol_count, max_batch);
-    const Layout L = layout(g, p, max_batch, chunk);
+    const Layout L = layout(g, p, max_batch, chunk, streams_for(max_batch, chunk));
     info->fft_w = g.nx; info->fft_h = g.ny;
     info->ifft_w = g.wx; info->ifft_h = g.wy;
     info->box_w = g.bx; info->box_h = g.by;
@@ -417,7 +447,8 @@ int dh_plan(const dh_params* p, int max_batch, size_t hbm_budget, dh_handle* out
   pl->g = g;
   pl->max_batch = max_batch;
   pl->chunk = chunk_for(g, p->pol_count, max_batch);
-  pl->L = layout(g, p, max_batch, pl->chunk);
+  pl->nws = streams_for(max_batch, pl->chunk);
+  pl->L = layout(g, p, max_batch, pl->chunk, pl->nws);
   if (hbm_budget && pl->L.total > hbm_budget) {
     delete pl;
     return DH_ERR_MEMORYALLOCATION;
@@ -433,7 +464,17 @@ int dh_plan(const dh_params* p, int max_batch, size_t hbm_budget, dh_handle* out
     delete pl;
     return e;
   }
-  fill_kargs(pl);
+  for (int w = 0; w < pl->nws; ++w) fill_kargs(pl, w);
+  if (pl->nws > 1) {
+    bool ok = hipEventCreateWithFlags(&pl->fork, hipEventDisableTiming) == hipSuccess;
+    for (int w = 0; w < pl->nws && ok; ++w)
+      ok = hipStreamCreateWithFlags(&pl->str[w], hipStreamNonBlocking) == hipSuccess &&
+           hipEventCreateWithFlags(&pl->join[w], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+      release(pl);
+      return DH_ERR_ERROR;
+    }
+  }
   std::lock_guard<std::mutex> lk(g_mu);
   g_plans.push_back(pl);
   *out = (dh_handle)(g_plans.size() - 1);
@@ -447,23 +488,41 @@ int dh_process_batch(dh_handle h, const void* frames, int batch, void* stream) {
   if (batch < 1) batch = 1;
   if (batch > pl->max_batch) return set_err(pl, DH_ERR_INVALIDDIMENSION);
   hipStream_t s = (hipStream_t)stream;
-  const dh::KArgs& a = pl->ka;
   const int u16 = pl->params.input_dtype == DH_INPUT_U16;
-  if (a.window && dh::launch_zero(a.window, (size_t)batch * a.npol * a.wy * a.wx, s) != hipSuccess)
+  const dh::KArgs& a0 = pl->ka[0];
+  if (a0.window && dh::launch_zero(a0.window, (size_t)batch * a0.npol * a0.wy * a0.wx, s) != hipSuccess)
     return set_err(pl, DH_ERR_ERROR);
-  if (mark(pl, -1, s) != hipSuccess) return set_err(pl, DH_ERR_ERROR);
-  for (int b0 = 0; b0 < batch; b0 += pl->chunk) {
+  const int nchunks = (batch + pl->chunk - 1) / pl->chunk;
+  const int nws = std::min(pl->nws, nchunks);
+  if (nws > 1) {  // fork: every internal stream starts after the caller's prior work
+    if (hipEventRecord(pl->fork, s) != hipSuccess) return set_err(pl, DH_ERR_ERROR);
+    for (int w = 0; w < nws; ++w)
+      if (hipStreamWaitEvent(pl->str[w], pl->fork, 0) != hipSuccess) return set_err(pl, DH_ERR_ERROR);
+  }
+  for (int c = 0; c < nchunks; ++c) {
+    const int b0 = c * pl->chunk;
     const int nb = std::min(pl->chunk, batch - b0);
-    if (dh::launch_row(a, frames, u16, b0, nb, s) != hipSuccess || mark(pl, 0, s) != hipSuccess)
-      return set_err(pl, DH_ERR_ERROR);
-    if (dh::launch_col(a, b0, nb, s) != hipSuccess || mark(pl, 1, s) != hipSuccess)
-      return set_err(pl, DH_ERR_ERROR);
-    if (a.G > 0 || a.fields) {
-      if (dh::launch_fld(a, b0, nb, s) != hipSuccess || mark(pl, 2, s) != hipSuccess)
+    const int w = c % nws;
+    const dh::KArgs& a = pl->ka[w];
+    hipStream_t st = nws > 1 ? pl->str[w] : s;
+    bool ok = timed_event(pl, st, DH_STAGE_FFT, true) == hipSuccess &&
+              dh::launch_row(a, frames, u16, b0, nb, st) == hipSuccess &&
+              timed_event(pl, st, DH_STAGE_FFT, false) == hipSuccess &&
+              timed_event(pl, st, DH_STAGE_CROP, true) == hipSuccess &&
+              dh::launch_col(a, b0, nb, st) == hipSuccess &&
+              timed_event(pl, st, DH_STAGE_CROP, false) == hipSuccess;
+    if (ok && (a.G > 0 || a.fields))
+      ok = timed_event(pl, st, DH_STAGE_FIELD, true) == hipSuccess && dh::launch_fld(a, b0, nb, st) == hipSuccess &&
+           timed_event(pl, st, DH_STAGE_FIELD, false) == hipSuccess;
+    if (ok && a.G > 0)
+      ok = timed_event(pl, st, DH_STAGE_NORM, true) == hipSuccess && dh::launch_norm(a, b0, nb, st) == hipSuccess &&
+           timed_event(pl, st, DH_STAGE_NORM, false) == hipSuccess;
+    if (!ok) return set_err(pl, DH_ERR_ERROR);
+  }
+  if (nws > 1) {  // join: the caller's stream continues after every chunk
+    for (int w = 0; w < nws; ++w)
+      if (hipEventRecord(pl->join[w], pl->str[w]) != hipSuccess || hipStreamWaitEvent(s, pl->join[w], 0) != hipSuccess)
         return set_err(pl, DH_ERR_ERROR);
-    }
-    if (a.G > 0 && (dh::launch_norm(a, b0, nb, s) != hipSuccess || mark(pl, 3, s) != hipSuccess))
-      return set_err(pl, DH_ERR_ERROR);
   }
   pl->last_batch = batch;
   pl->last_stream = s;
@@ -484,7 +543,7 @@ int dh_mode_coefs(dh_handle h, dh_c64* host_out, const dh_c64** dev_out, int* ba
   if (batch) *batch = pl->last_batch;
   if (modes) *modes = nm;
   if (pols) *pols = pl->params.pol_count;
-  const float2* src = normalised ? pl->ka.coefs_norm : pl->ka.coefs;
+  const float2* src = normalised ? pl->ka[0].coefs_norm : pl->ka[0].coefs;
   if (dev_out) *dev_out = nm > 0 ? (const dh_c64*)src : nullptr;
   if (nm == 0) return set_err(pl, DH_SUCCESS);
   const size_t bytes = (size_t)pl->last_batch * pl->params.pol_count * nm * sizeof(dh_c64);
@@ -495,7 +554,7 @@ static int get_plane(dh_handle h, bool win, dh_c64* host_out, const dh_c64** dev
                      int* width, int* height) {
   Plan* pl = get(h);
   if (!pl) return DH_ERR_INVALIDHANDLE;
-  const float2* src = win ? pl->ka.window : pl->ka.fields;
+  const float2* src = win ? pl->ka[0].window : pl->ka[0].fields;
   if (batch) *batch = pl->last_batch;
   if (pols) *pols = pl->params.pol_count;
   if (width) *width = pl->g.wx;
@@ -534,8 +593,10 @@ int dh_get_plan_info(dh_handle h, dh_plan_info* out) {
 int dh_set_stage_timing(dh_handle h, int enabled) {
   Plan* pl = get(h);
   if (!pl) return DH_ERR_INVALIDHANDLE;
+  if (hipDeviceSynchronize() != hipSuccess) return set_err(pl, DH_ERR_ERROR);
   pl->timing = enabled != 0;
   pl->ev_used = 0;
+  pl->ev_stage.clear();
   return set_err(pl, DH_SUCCESS);
 }
 
@@ -547,17 +608,16 @@ int dh_stage_times(dh_handle h, double* ms, int* launches) {
     ms[k] = 0.0;
     launches[k] = 0;
   }
-  if (pl->ev_used > 0 && hipEventSynchronize(pl->ev_pool[pl->ev_used - 1]) != hipSuccess)
-    return set_err(pl, DH_ERR_ERROR);
-  for (size_t i = 1; i < pl->ev_used; ++i) {
-    const int st = pl->ev_stage[i];
-    if (st < 0) continue;  // gap between batches
+  for (size_t i = 0; i < pl->ev_stage.size(); ++i) {
     float t = 0.f;
-    if (hipEventElapsedTime(&t, pl->ev_pool[i - 1], pl->ev_pool[i]) != hipSuccess) return set_err(pl, DH_ERR_ERROR);
-    ms[st] += t;
-    launches[st] += 1;
+    if (hipEventSynchronize(pl->ev_pool[2 * i + 1]) != hipSuccess ||
+        hipEventElapsedTime(&t, pl->ev_pool[2 * i], pl->ev_pool[2 * i + 1]) != hipSuccess)
+      return set_err(pl, DH_ERR_ERROR);
+    ms[pl->ev_stage[i]] += t;
+    launches[pl->ev_stage[i]] += 1;
   }
   pl->ev_used = 0;
+  pl->ev_stage.clear();
   return set_err(pl, DH_SUCCESS);
 }
 
@@ -574,14 +634,7 @@ int dh_destroy(dh_handle h) {
     pl = g_plans[h];
     g_plans[h] = nullptr;
   }
-  int dev = 0;
-  (void)hipGetDevice(&dev);
-  (void)hipSetDevice(pl->device);
-  (void)hipDeviceSynchronize();
-  (void)hipFree(pl->mem);
-  for (hipEvent_t e : pl->ev_pool) (void)hipEventDestroy(e);
-  (void)hipSetDevice(dev);
-  delete pl;
+  release(pl);
   return DH_SUCCESS;
 }
 

@@ -295,6 +295,47 @@ template <int N> struct Lds {
   __device__ static __forceinline__ int at(int i) { return padi<PAD>(i); }
 };
 
+// ---------------------------------------------------------------------------
+// Pass 1 with its operands already in registers. For butterfly g = tid + it*TPB
+// (< NTR * N/R0): transform tr = g / (N/R0), b = g % (N/R0), and v[it][r] must
+// hold element b + r * N/R0 of transform tr. Runs the radix-R0 DFT and writes
+// the results to LDS (padded layout of Lds<N>); no barrier.
+template <int N, int NTR, int TPB>
+struct Pass1 {
+  static constexpr int R0 = FftPlan<N>::R0;
+  static constexpr int NB = N / R0;
+  static constexpr int TOTAL = NTR * NB;
+  static constexpr int IT = (TOTAL + TPB - 1) / TPB;
+};
+
+template <int N, int NTR, int STRIDE, int TPB>
+__device__ __forceinline__ void fft_pass1_regs(float2 (*v)[FftPlan<N>::R0], float2* buf, int tid) {
+  using Q = Pass1<N, NTR, TPB>;
+  constexpr int R0 = Q::R0, NB = Q::NB;
+#pragma unroll
+  for (int it = 0; it < Q::IT; ++it) {
+    const int g = tid + it * TPB;
+    if (Q::TOTAL % TPB == 0 || g < Q::TOTAL) {
+      const int tr = g / NB, b = g % NB;
+      dft<R0>(v[it]);
+      float2* dst = buf + tr * STRIDE + padi<R0>(b * R0);
+#pragma unroll
+      for (int r = 0; r < R0; ++r) dst[r] = v[it][r];   // padi(b R0 + r) = padi(b R0) + r
+    }
+  }
+}
+
+// Passes 2.. of the transform (starts and ends with a barrier).
+template <int N, int NTR, int STRIDE, int TPB>
+__device__ __forceinline__ void fft_rest(float2* buf, const float2* __restrict__ tw, int tid) {
+  using P = FftPlan<N>;
+  constexpr int PAD = P::R0;
+  __syncthreads();
+  if constexpr (P::R1 > 1) stockham_pass<N, P::R1, P::R0, NTR, STRIDE, TPB, PAD>(buf, tw, tid);
+  constexpr int OFF2 = (P::R1 - 1) * P::R0;
+  if constexpr (P::R2 > 1) stockham_pass<N, P::R2, P::R0 * P::R1, NTR, STRIDE, TPB, PAD>(buf, tw + OFF2, tid);
+}
+
 // forward FFT of NTR transforms of length N held in LDS (padded layout of
 // Lds<N>, transform t at buf + t * STRIDE). tw holds the twiddles of pass 2
 // then pass 3: entry (r-1)*NS + k = e^{-2 pi i k r / (NS R)}, so the lanes of

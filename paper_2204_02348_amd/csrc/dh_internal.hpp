@@ -31,6 +31,7 @@ struct KArgs {
   int frame_w, frame_h, npol;
   int nx, ny, wx, wy, wyp;  // FFT window, IFFT window, IFFT rows rounded up to 16
   int bx, by;               // box size (max over pols)
+  int bxp;                  // f2 row pitch: bx rounded up to 16
   int G, gp, nmodes;        // groups, padded group count (16 or 32), modes per pol
   float nxny;               // Nx * Ny
   PolTab pol[2];
@@ -39,8 +40,8 @@ struct KArgs {
   const float2* tw_ny;
   const float2* tw_wx;
   const float2* tw_wy;
-  float2* t1;               // [chunk][P][ny][bx] row-pass spectrum at the box columns
-  float2* f2;               // [chunk][P][wy][bx] column pass + crop + y-IFFT
+  float2* t1;               // [chunk][P][bx][ny] row-pass spectrum at the box columns (column-major)
+  float2* f2;               // [chunk][P][wy][bxp] column pass + crop + y-IFFT
   float2* partial;          // [chunk][nblk][P][nmodes] per-row-block share of each coefficient
   int nblk;                 // 16-row blocks of the field (wyp / 16)
   float2* coefs;            // [max_batch][P][nmodes] raw coefficients

@@ -31,12 +31,16 @@ template <typename T>
 __device__ __forceinline__ float load_px(const T* p) { return (float)(*p); }
 
 // ---------------------------------------------------------------------------
-// k_row: grid (ceil(ny / (2 TR)), npol, nb); TR complex transforms of NX,
-// each the pair of real rows (2t, 2t+1) packed as re + i im.
-// t1[b][p][y][j] = sum_x I[y][x] e^{-2 pi i k x / NX}, k = k0 + j (mod NX)
+// k_row: grid (ceil(ny / (2 TR)), npol, nb), TPB = TR * NX / R0 threads: TR
+// complex transforms of NX, each the pair of real rows (2t, 2t+1) packed as
+// re + i im. The first pass takes its operands straight from the frame.
+// t1[b][p][j][y] = sum_x I[y][x] e^{-2 pi i k x / NX}, k = k0 + j (mod NX)
 template <int NX, int TR, typename TIn>
-__global__ void __launch_bounds__(kTPB) k_row(KArgs A, const TIn* __restrict__ frames, int b0) {
+__global__ void __launch_bounds__(TR * NX / FftPlan<NX>::R0) k_row(KArgs A, const TIn* __restrict__ frames, int b0) {
   using L = Lds<NX>;
+  using Q = Pass1<NX, TR, TR * NX / FftPlan<NX>::R0>;
+  constexpr int TPB = TR * NX / FftPlan<NX>::R0;
+  static_assert(Q::IT == 1, "one first-pass butterfly per thread");
   __shared__ float2 buf[TR * L::STRIDE];
   const int tid = threadIdx.x;
   const int p = blockIdx.y;
@@ -44,46 +48,54 @@ __global__ void __launch_bounds__(kTPB) k_row(KArgs A, const TIn* __restrict__ f
   const PolTab& P = A.pol[p];
   const int ybase = blockIdx.x * (2 * TR);
   const TIn* win = frames + (size_t)(b0 + bl) * A.frame_h * A.frame_w + (size_t)P.y0 * A.frame_w + P.x0;
-  for (int e = tid; e < TR * NX; e += kTPB) {
-    const int t = e / NX, c = e % NX;
+  {
+    const int t = tid / Q::NB, b = tid % Q::NB;
     const int y = ybase + 2 * t;
-    float v0 = 0.f, v1 = 0.f;
-    if (y < A.ny) v0 = load_px(win + (size_t)y * A.frame_w + c);
-    if (y + 1 < A.ny) v1 = load_px(win + (size_t)(y + 1) * A.frame_w + c);
-    buf[t * L::STRIDE + L::at(c)] = make_float2(v0, v1);
+    const TIn* r0 = win + (size_t)y * A.frame_w + b;
+    const TIn* r1 = r0 + A.frame_w;
+    const bool ok0 = y < A.ny, ok1 = y + 1 < A.ny;
+    float2 v[1][Q::R0];
+#pragma unroll
+    for (int r = 0; r < Q::R0; ++r) {
+      v[0][r].x = ok0 ? load_px(r0 + r * Q::NB) : 0.f;
+      v[0][r].y = ok1 ? load_px(r1 + r * Q::NB) : 0.f;
+    }
+    fft_pass1_regs<NX, TR, L::STRIDE, TPB>(v, buf, tid);
   }
-  __syncthreads();
-  fft_lds<NX, TR, L::STRIDE, kTPB>(buf, A.tw_nx, tid);
-  float2* out = A.t1 + ((size_t)(bl * A.npol + p) * A.ny) * A.bx;
-  for (int e = tid; e < 2 * TR * A.bx; e += kTPB) {
-    const int r = e / A.bx, j = e % A.bx;
-    const int y = ybase + r;
+  fft_rest<NX, TR, L::STRIDE, TPB>(buf, A.tw_nx, tid);
+  // two-for-one split at the kept bins: both rows of a pair from Z[k], Z[NX-k]
+  float2* out = A.t1 + (size_t)(bl * A.npol + p) * A.bx * A.ny;
+  for (int e = tid; e < TR * A.bx; e += TPB) {
+    const int t = e % TR, j = e / TR;
+    const int y = ybase + 2 * t;
     if (y >= A.ny) continue;
-    int k = (P.k0 + j) % NX;
-    if (k < 0) k += NX;
-    const int km = (NX - k) % NX;
-    const float2* tb = buf + (r >> 1) * L::STRIDE;
+    int k = P.k0 + j;
+    k = (k >= NX) ? k - NX : (k < 0 ? k + NX : k);
+    const int km = (k == 0) ? 0 : NX - k;
+    const float2* tb = buf + t * L::STRIDE;
     const float2 z1 = tb[L::at(k)];
     const float2 z2 = conjf2(tb[L::at(km)]);
-    float2 x;
-    if ((r & 1) == 0) {
-      x = make_float2(0.5f * (z1.x + z2.x), 0.5f * (z1.y + z2.y));
+    const float2 d = csub(z1, z2);
+    const float4 x = make_float4(0.5f * (z1.x + z2.x), 0.5f * (z1.y + z2.y), 0.5f * d.y, -0.5f * d.x);
+    float2* o = out + (size_t)j * A.ny + y;
+    if (y + 1 < A.ny) {
+      *reinterpret_cast<float4*>(o) = x;
     } else {
-      const float2 d = csub(z1, z2);  // d / (2i)
-      x = make_float2(0.5f * d.y, -0.5f * d.x);
+      *o = make_float2(x.x, x.y);
     }
-    out[(size_t)y * A.bx + j] = x;
   }
 }
 
 // ---------------------------------------------------------------------------
 // k_col: grid (ceil(bx / CG), npol, nb). CG box columns per block: FFT along
-// y, gather of the masked window rows (stored as conj of the IFFT input),
-// IFFT along y at the window size.
+// y (first pass straight from the column-major t1), gather of the masked
+// window rows (stored as conj of the IFFT input), IFFT along y at the window
+// size; f2 rows have pitch bxp.
 template <int NY, int WY, int CG>
 __global__ void __launch_bounds__(kTPB) k_col(KArgs A, int b0) {
   using LN = Lds<NY>;
   using LW = Lds<WY>;
+  using Q = Pass1<NY, CG, kTPB>;
   constexpr int ST = (LN::STRIDE > LW::STRIDE) ? LN::STRIDE : LW::STRIDE;
   __shared__ float2 buf[CG * ST];
   const int tid = threadIdx.x;
@@ -91,14 +103,22 @@ __global__ void __launch_bounds__(kTPB) k_col(KArgs A, int b0) {
   const int bl = blockIdx.z;
   const PolTab& P = A.pol[p];
   const int jc0 = blockIdx.x * CG;
-  const float2* in = A.t1 + ((size_t)(bl * A.npol + p) * NY) * A.bx;
-  for (int e = tid; e < CG * NY; e += kTPB) {
-    const int c = e % CG, y = e / CG;
-    const int j = jc0 + c;
-    buf[c * ST + LN::at(y)] = (j < A.bx) ? in[(size_t)y * A.bx + j] : make_float2(0.f, 0.f);
+  const float2* in = A.t1 + ((size_t)(bl * A.npol + p) * A.bx) * NY;
+  {
+    float2 v[Q::IT][Q::R0];
+#pragma unroll
+    for (int it = 0; it < Q::IT; ++it) {
+      const int g = tid + it * kTPB;
+      const int c = g / Q::NB, b = g % Q::NB;
+      const int j = jc0 + c;
+      const bool ok = (Q::TOTAL % kTPB == 0 || g < Q::TOTAL) && j < A.bx;
+      const float2* col = in + (size_t)j * NY + b;
+#pragma unroll
+      for (int r = 0; r < Q::R0; ++r) v[it][r] = ok ? col[r * Q::NB] : make_float2(0.f, 0.f);
+    }
+    fft_pass1_regs<NY, CG, ST, kTPB>(v, buf, tid);
   }
-  __syncthreads();
-  fft_lds<NY, CG, ST, kTPB>(buf, A.tw_ny, tid);
+  fft_rest<NY, CG, ST, kTPB>(buf, A.tw_ny, tid);
   constexpr int NE = (CG * WY + kTPB - 1) / kTPB;
   float2 z[NE];
   const bool keep_win = A.window != nullptr;
@@ -140,11 +160,11 @@ __global__ void __launch_bounds__(kTPB) k_col(KArgs A, int b0) {
   }
   __syncthreads();
   fft_lds<WY, CG, ST, kTPB>(buf, A.tw_wy, tid);
-  float2* out = A.f2 + ((size_t)(bl * A.npol + p) * WY) * A.bx;
+  float2* out = A.f2 + ((size_t)(bl * A.npol + p) * WY) * A.bxp;
   for (int e = tid; e < CG * WY; e += kTPB) {
     const int c = e % CG, l = e / CG;
     const int j = jc0 + c;
-    if (j < A.bx) out[(size_t)l * A.bx + j] = conjf2(buf[c * ST + LW::at(l)]);
+    if (j < A.bx) out[(size_t)l * A.bxp + j] = conjf2(buf[c * ST + LW::at(l)]);
   }
 }
 
@@ -168,7 +188,7 @@ __global__ void __launch_bounds__(kTPB) k_fld(KArgs A, int b0) {
   const int bl = blockIdx.z;
   const int bg = b0 + bl;
   const PolTab& P = A.pol[p];
-  const float2* in = A.f2 + ((size_t)(bl * A.npol + p) * A.wy) * A.bx;
+  const float2* in = A.f2 + ((size_t)(bl * A.npol + p) * A.wy) * A.bxp;
   float2* fld = A.fields ? A.fields + ((size_t)bg * A.npol + p) * A.wy * WX : nullptr;
   const int gp = A.gp;
   constexpr int XS = WX / 4;    // x columns per wave
@@ -179,7 +199,7 @@ __global__ void __launch_bounds__(kTPB) k_fld(KArgs A, int b0) {
     float2 v = make_float2(0.f, 0.f);
     if (y < A.wy) {
       const int j = P.qcol[q];
-      if (j >= 0) v = conjf2(in[(size_t)y * A.bx + j]);
+      if (j >= 0) v = conjf2(in[(size_t)y * A.bxp + j]);
     }
     buf[r * ST + L::at(q)] = v;
   }
@@ -270,10 +290,17 @@ __global__ void __launch_bounds__(kTPB) k_norm(KArgs A, int b0) {
   double s = 0.0;
   for (int i = tid; i < per; i += kTPB) {
     float re = 0.f, im = 0.f;
-    for (int rb = 0; rb < A.nblk; ++rb) {
-      const float2 v = part[(size_t)rb * per + i];
-      re += v.x;
-      im += v.y;
+    // blocks summed in order, eight loads in flight at a time
+    for (int rb0 = 0; rb0 < A.nblk; rb0 += 8) {
+      float2 v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        v[u] = (rb0 + u < A.nblk) ? part[(size_t)(rb0 + u) * per + i] : make_float2(0.f, 0.f);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        re += v[u].x;
+        im += v[u].y;
+      }
     }
     raw[i] = make_float2(re, im);
     s += (double)re * re + (double)im * im;
@@ -325,17 +352,20 @@ __global__ void k_zero(float2* p, size_t n) {
 // ---------------------------------------------------------------------------
 // dispatch over the supported sizes
 // transforms per row-pass block and columns per column-pass block (~32-80 KB of LDS)
-template <int N> constexpr int row_tr() { return N >= 2048 ? 1 : N >= 1024 ? 2 : N >= 512 ? 4 : N >= 256 ? 8 : 16; }
-template <int N> constexpr int col_cg() { return N >= 2048 ? 4 : N >= 1024 ? 8 : 16; }
+// row pass: TR transforms per block so that TR * N / R0 (the block size) is 256 or 320
+template <int N> constexpr int row_tr() { return 256 / (N / FftPlan<N>::R0) > 0 ? (N == 320 ? 16 : N == 640 ? 4 : 256 / (N / FftPlan<N>::R0)) : 1; }
+template <int N> constexpr int col_cg() { return N >= 2048 ? 4 : N >= 1024 ? 4 : N >= 512 ? 8 : 16; }
 
 template <int NX>
 static hipError_t row_n(const KArgs& a, const void* frames, int u16, int b0, int nb, hipStream_t s) {
   constexpr int TR = row_tr<NX>();
+  constexpr int TPB = TR * NX / FftPlan<NX>::R0;
+  static_assert(TPB % 64 == 0 && TPB <= 512, "row-pass block size");
   dim3 grid((a.ny + 2 * TR - 1) / (2 * TR), a.npol, nb);
   if (u16)
-    hipLaunchKernelGGL((k_row<NX, TR, unsigned short>), grid, dim3(kTPB), 0, s, a, (const unsigned short*)frames, b0);
+    hipLaunchKernelGGL((k_row<NX, TR, unsigned short>), grid, dim3(TPB), 0, s, a, (const unsigned short*)frames, b0);
   else
-    hipLaunchKernelGGL((k_row<NX, TR, float>), grid, dim3(kTPB), 0, s, a, (const float*)frames, b0);
+    hipLaunchKernelGGL((k_row<NX, TR, float>), grid, dim3(TPB), 0, s, a, (const float*)frames, b0);
   return hipGetLastError();
 }
 
