@@ -63,6 +63,31 @@ def counter_traffic(stage, frames_per_launch):
     return None
 
 
+def time_forms(dh, torch, cfg, ft, B, stream, steps=10, warmup=3):
+    """frames/s and overlap-kernel time of the three overlap forms (plain FP32,
+    split BF16, split FP16) on the same frames, at G=9 and G=20."""
+    out = {}
+    for groups in (9, 20):
+        for prec in ("fp32", "split_bf16", "split_fp16"):
+            plan = dh.Plan(dict(cfg["params"], max_mg=groups, precision=prec), max_batch=B)
+            for _ in range(warmup):
+                plan.process(ft, B, stream)
+            stream.synchronize()
+            plan.set_stage_timing(True)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(steps):
+                plan.process(ft, B, stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            st = plan.stage_times()
+            plan.destroy()
+            ms = e0.elapsed_time(e1)
+            out[f"G{groups}_{prec}"] = {"frames_per_s": round(steps * B / (ms / 1e3), 1),
+                                        "overlap_kernel_ms": round(st["ifft_x_tilt_overlap"][0] / steps, 4)}
+    return out
+
+
 def cpu_baseline(cfg, frames, seconds):
     """The FP64 oracle, as it stands, on a bounded sample of the same frames."""
     import oracle
@@ -92,6 +117,7 @@ def main():
     ap.add_argument("--frames", type=int, default=1000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the FP32 / split BF16 / split FP16 comparison")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device-to-device copy of 512 MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -174,9 +200,11 @@ def main():
         "path_hbm_frac": round(frame_bytes * value / 1e9 / HBM_PEAK_GBS, 4),
         "roofline": roofline,
     }
+    plan.destroy()
+    if not args.no_forms:
+        out["forms"] = time_forms(dh, torch, cfg, ft, B, stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, frames, args.cpu_seconds)
-    plan.destroy()
     print(json.dumps(out), flush=True)
 
 

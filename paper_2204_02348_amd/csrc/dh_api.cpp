@@ -166,6 +166,7 @@ int streams_for(int max_batch, int chunk) {
 struct Layout {  // byte offsets inside one device allocation
   size_t tw_nx, tw_ny, tw_wx, tw_wy, modes, total_tables;
   size_t pol_mrow[2], pol_qrow[2], pol_qcol[2], pol_rhox[2], pol_rhoy[2], pol_tx[2], pol_ty[2], pol_ux[2], pol_uy[2];
+  size_t pol_uxs[2][4], pol_uys[2][4];   // split tables: bf16 hi, bf16 lo, fp16 hi, fp16 lo
   size_t t1[4], f2[4], partial[4], coefs, coefs_norm, window, fields, total;
 };
 
@@ -185,6 +186,10 @@ Layout layout(const Geom& g, const dh_params* p, int max_batch, int chunk, int n
     L.pol_ty[q] = take(g.wy * 8);
     L.pol_ux[q] = take((size_t)g.wx * g.gp * 4);
     L.pol_uy[q] = take((size_t)g.wyp * g.gp * 4);
+    for (int t = 0; t < 4; ++t) {
+      L.pol_uxs[q][t] = take((size_t)g.wx * g.gp * 2);
+      L.pol_uys[q][t] = take((size_t)g.wyp * g.gp * 2);
+    }
   }
   L.total_tables = o;
   const size_t P = p->pol_count;
@@ -208,6 +213,7 @@ struct Plan {
   Layout L;
   int max_batch = 1, chunk = 1, nws = 1, last_batch = 0, last_error = 0;
   int device = 0;
+  float s_uh = 1.f;
   char* mem = nullptr;
   hipStream_t last_stream = nullptr;
   dh::KArgs ka[4]{};                 // one per workspace
@@ -264,6 +270,16 @@ std::vector<float2> twiddles(int n) {
   }
   if (t.empty()) t.push_back(make_float2(1.f, 0.f));
   return t;
+}
+
+// Power of two that maps the largest possible HG table entry close below
+// 2^14: |psi_n| <= pi^(-1/4) for every n (Cramer's bound), so
+// |u_n(x) p'| <= 2^(1/4) pi^(-1/4) w^(-1/2) p'.
+double hg_fp16_scale(double waist, double pitch) {
+  const double bound = std::pow(2.0, 0.25) * std::pow(kPi, -0.25) / std::sqrt(waist) * pitch;
+  int e;
+  std::frexp(bound, &e);
+  return std::ldexp(1.0, 14 - e);
 }
 
 int build_tables(Plan* pl) {
@@ -327,10 +343,17 @@ int build_tables(Plan* pl) {
     put(host, L.pol_ty[q], ty);
   }
   if (hipMemcpy(pl->mem, host.data(), L.total_tables, hipMemcpyHostToDevice) != hipSuccess) return DH_ERR_ERROR;
+  const double waist = p->waist > 0 ? p->waist : 1.0;
+  pl->s_uh = (float)hg_fp16_scale(waist, std::max(g.pxp, g.pyp));
   for (int q = 0; q < p->pol_count; ++q) {
-    if (dh::launch_hg(g.pxp, g.wx, g.wx, p->waist > 0 ? p->waist : 1.0, g.G, g.gp, (float*)(pl->mem + L.pol_ux[q]), 0) != hipSuccess)
+    char* m = pl->mem;
+    if (dh::launch_hg(g.pxp, g.wx, g.wx, waist, g.G, g.gp, (float*)(m + L.pol_ux[q]),
+                      (unsigned short*)(m + L.pol_uxs[q][0]), (unsigned short*)(m + L.pol_uxs[q][1]),
+                      (_Float16*)(m + L.pol_uxs[q][2]), (_Float16*)(m + L.pol_uxs[q][3]), pl->s_uh, 0) != hipSuccess)
       return DH_ERR_ERROR;
-    if (dh::launch_hg(g.pyp, g.wy, g.wyp, p->waist > 0 ? p->waist : 1.0, g.G, g.gp, (float*)(pl->mem + L.pol_uy[q]), 0) != hipSuccess)
+    if (dh::launch_hg(g.pyp, g.wy, g.wyp, waist, g.G, g.gp, (float*)(m + L.pol_uy[q]),
+                      (unsigned short*)(m + L.pol_uys[q][0]), (unsigned short*)(m + L.pol_uys[q][1]),
+                      (_Float16*)(m + L.pol_uys[q][2]), (_Float16*)(m + L.pol_uys[q][3]), pl->s_uh, 0) != hipSuccess)
       return DH_ERR_ERROR;
   }
   if (hipDeviceSynchronize() != hipSuccess) return DH_ERR_ERROR;
@@ -347,6 +370,8 @@ void fill_kargs(Plan* pl, int w) {
   a.nx = g.nx; a.ny = g.ny; a.wx = g.wx; a.wy = g.wy; a.wyp = g.wyp;
   a.bx = g.bx; a.by = g.by; a.bxp = (g.bx + 15) / 16 * 16; a.G = g.G; a.gp = g.gp; a.nmodes = g.nmodes;
   a.nxny = (float)((double)g.nx * g.ny);
+  a.prec = p->precision;
+  a.s_uh = pl->s_uh;
   for (int q = 0; q < p->pol_count; ++q) {
     const PolGeom& P = g.pol[q];
     dh::PolTab& t = a.pol[q];
@@ -361,6 +386,14 @@ void fill_kargs(Plan* pl, int w) {
     t.ty = (const float2*)(m + L.pol_ty[q]);
     t.ux = (const float*)(m + L.pol_ux[q]);
     t.uy = (const float*)(m + L.pol_uy[q]);
+    t.ux_bh = (const unsigned short*)(m + L.pol_uxs[q][0]);
+    t.ux_bl = (const unsigned short*)(m + L.pol_uxs[q][1]);
+    t.ux_hh = (const _Float16*)(m + L.pol_uxs[q][2]);
+    t.ux_hl = (const _Float16*)(m + L.pol_uxs[q][3]);
+    t.uy_bh = (const unsigned short*)(m + L.pol_uys[q][0]);
+    t.uy_bl = (const unsigned short*)(m + L.pol_uys[q][1]);
+    t.uy_hh = (const _Float16*)(m + L.pol_uys[q][2]);
+    t.uy_hl = (const _Float16*)(m + L.pol_uys[q][3]);
   }
   a.modes = (const short2*)(m + L.modes);
   a.tw_nx = (const float2*)(m + L.tw_nx);

@@ -25,6 +25,16 @@ struct PolTab {
   const float2* ty;       // [wy] same along y
   const float* ux;        // [wx][gp] u_m(x'_k) p'_x, zero for m >= G
   const float* uy;        // [wyp][gp] u_n(y'_l) p'_y, zero for n >= G or l >= wy
+  // the same tables split as hi + lo for the precision form, packed
+  // [k/4][mode][k%4] (four consecutive samples of one mode together):
+  const unsigned short* ux_bh;  // bf16 hi / lo
+  const unsigned short* ux_bl;
+  const unsigned short* uy_bh;
+  const unsigned short* uy_bl;
+  const _Float16* ux_hh;        // fp16 hi / lo of the table times KArgs::s_uh
+  const _Float16* ux_hl;
+  const _Float16* uy_hh;
+  const _Float16* uy_hl;
 };
 
 struct KArgs {
@@ -34,6 +44,8 @@ struct KArgs {
   int bxp;                  // f2 row pitch: bx rounded up to 16
   int G, gp, nmodes;        // groups, padded group count (16 or 32), modes per pol
   float nxny;               // Nx * Ny
+  int prec;                 // DH_PREC_FP32 / SPLIT_BF16 / SPLIT_FP16
+  float s_uh;               // power-of-two prescale of the fp16 split HG tables
   PolTab pol[2];
   const short2* modes;      // [nmodes] (m, n)
   const float2* tw_nx;      // per-pass twiddle tables of each transform length (see fft_lds)
@@ -57,6 +69,10 @@ hipError_t launch_col(const KArgs& a, int b0, int nb, hipStream_t s);
 hipError_t launch_fld(const KArgs& a, int b0, int nb, hipStream_t s);
 hipError_t launch_norm(const KArgs& a, int b0, int nb, hipStream_t s);
 hipError_t launch_zero(float2* p, size_t n, hipStream_t s);
-hipError_t launch_hg(double pitch, int w, int wpad, double waist, int G, int gp, float* out, hipStream_t s);
+// HG tables: out[k][n] in FP32 and, if the split pointers are non-null, the
+// packed hi/lo tables (bf16, and fp16 of the value times fp16_scale)
+hipError_t launch_hg(double pitch, int w, int wpad, double waist, int G, int gp, float* out,
+                     unsigned short* bh, unsigned short* bl, _Float16* hh, _Float16* hl, double fp16_scale,
+                     hipStream_t s);
 
 }  // namespace dh

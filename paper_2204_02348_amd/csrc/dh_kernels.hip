@@ -27,8 +27,20 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kTPB = 256;
 
+typedef short shortx4 __attribute__((ext_vector_type(4)));
+typedef _Float16 halfx4 __attribute__((ext_vector_type(4)));
+
 template <typename T>
 __device__ __forceinline__ float load_px(const T* p) { return (float)(*p); }
+
+// round-to-nearest-even FP32 -> BF16 (finite inputs)
+__device__ __forceinline__ unsigned short bf16_rne(float x) {
+  unsigned int u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(unsigned short b) { return __uint_as_float((unsigned int)b << 16); }
+
 
 // ---------------------------------------------------------------------------
 // k_row: grid (ceil(ny / (2 TR)), npol, nb), TPB = TR * NX / R0 threads: TR
@@ -170,17 +182,88 @@ __global__ void __launch_bounds__(kTPB) k_col(KArgs A, int b0) {
 
 // ---------------------------------------------------------------------------
 // k_fld: grid (nblk, npol, nb); one block of 16 field rows per workgroup,
-// 4 waves: x-IFFT of the 16 rows, tilt/defocus removal, then
-// T = E Ux (MFMA 16x16x4 f32, each wave a quarter of x) and
-// C = Uy^T T (MFMA, T taken straight from the accumulators); the four waves'
-// partial C tiles are summed in LDS and written per block.
-template <int WX, int MT>
+// 4 waves: x-IFFT of the 16 rows, tilt/defocus removal, then the separable
+// HG overlap as two real MFMA contractions: T = E Ux over this wave's share
+// of x, then C = Uy^T T with T taken straight from the accumulators. The four
+// waves' partial C tiles are summed in LDS, in wave order.
+//   PREC 0: FP32 MFMA 16x16x4.
+//   PREC 1/2: split BF16 / FP16 MFMA 16x16x16, x = hi + lo for both operands,
+//   products hi*hi + hi*lo + lo*hi accumulated in FP32. FP16 operands carry
+//   power-of-two prescales (field: block max; T: wave max; tables: static)
+//   that are divided out exactly.
+template <int PREC>
+struct Split4 {
+  shortx4 bh, bl;
+  halfx4 hh, hl;
+};
+
+template <int PREC>
+__device__ __forceinline__ void split4(const float* v, float s, Split4<PREC>& o) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if constexpr (PREC == 1) {
+      const unsigned short h = bf16_rne(v[j]);
+      o.bh[j] = (short)h;
+      o.bl[j] = (short)bf16_rne(v[j] - bf16_to_f32(h));
+    } else {
+      const float x = v[j] * s;
+      const _Float16 h = (_Float16)x;
+      o.hh[j] = h;
+      o.hl[j] = (_Float16)(x - (float)h);
+    }
+  }
+}
+
+template <int PREC>
+__device__ __forceinline__ floatx4 mfma3(const Split4<PREC>& a, const Split4<PREC>& b, floatx4 c) {
+  if constexpr (PREC == 1) {
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.bh, b.bh, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.bh, b.bl, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.bl, b.bh, c, 0, 0, 0);
+  } else {
+    c = __builtin_amdgcn_mfma_f32_16x16x16f16(a.hh, b.hh, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x16f16(a.hh, b.hl, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x16f16(a.hl, b.hh, c, 0, 0, 0);
+  }
+  return c;
+}
+
+// four consecutive samples (k0..k0+3) of mode `mode` from a packed split table
+template <int PREC>
+__device__ __forceinline__ void table4(const unsigned short* bh, const unsigned short* bl, const _Float16* hh,
+                                       const _Float16* hl, int k0, int gp, int mode, Split4<PREC>& o) {
+  const size_t at = ((size_t)(k0 >> 2) * gp + mode) * 4;
+  if constexpr (PREC == 1) {
+    o.bh = *reinterpret_cast<const shortx4*>(bh + at);
+    o.bl = *reinterpret_cast<const shortx4*>(bl + at);
+  } else {
+    o.hh = *reinterpret_cast<const halfx4*>(hh + at);
+    o.hl = *reinterpret_cast<const halfx4*>(hl + at);
+  }
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// power of two s with max * s in [2^13, 2^14) (1 if max is 0)
+__device__ __forceinline__ float fp16_prescale(float mx) {
+  if (!(mx > 0.f)) return 1.f;
+  int e;
+  frexpf(mx, &e);            // mx = f 2^e, f in [0.5, 1)
+  return ldexpf(1.f, 14 - e);
+}
+
+template <int WX, int MT, int PREC>
 __global__ void __launch_bounds__(kTPB) k_fld(KArgs A, int b0) {
   using L = Lds<WX>;
   constexpr int ST = L::STRIDE;
   constexpr int NPAIR = (MT == 1) ? 1 : 3;        // (n-tile, m-tile) pairs that can hold m+n < 32
   __shared__ float2 buf[16 * ST];
   __shared__ float red[4][NPAIR][2][256];
+  __shared__ float bmax[4];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const int rb = blockIdx.x;
@@ -191,8 +274,6 @@ __global__ void __launch_bounds__(kTPB) k_fld(KArgs A, int b0) {
   const float2* in = A.f2 + ((size_t)(bl * A.npol + p) * A.wy) * A.bxp;
   float2* fld = A.fields ? A.fields + ((size_t)bg * A.npol + p) * A.wy * WX : nullptr;
   const int gp = A.gp;
-  constexpr int XS = WX / 4;    // x columns per wave
-  constexpr int KS = XS / 4;    // MFMA k-steps per wave
   for (int e = tid; e < 16 * WX; e += kTPB) {
     const int r = e / WX, q = e % WX;
     const int y = rb * 16 + r;
@@ -205,6 +286,7 @@ __global__ void __launch_bounds__(kTPB) k_fld(KArgs A, int b0) {
   }
   __syncthreads();
   fft_lds<WX, 16, ST, kTPB>(buf, A.tw_wx, tid);
+  float emax = 0.f;
   for (int e = tid; e < 16 * WX; e += kTPB) {
     const int r = e / WX, q = e % WX;
     const int y = rb * 16 + r;
@@ -214,43 +296,110 @@ __global__ void __launch_bounds__(kTPB) k_fld(KArgs A, int b0) {
       if (fld) fld[(size_t)y * WX + q] = ev;
     }
     buf[r * ST + L::at(q)] = ev;
+    if constexpr (PREC == 2) emax = fmaxf(emax, fmaxf(fabsf(ev.x), fabsf(ev.y)));
+  }
+  float sE = 1.f;
+  if constexpr (PREC == 2) {
+    emax = wave_max(emax);
+    if (lane == 0) bmax[wv] = emax;
   }
   __syncthreads();
-  // T[y][m] = sum_x E[y][x] Ux[x][m] over this wave's quarter of x
+  if constexpr (PREC == 2) sE = fp16_prescale(fmaxf(fmaxf(bmax[0], bmax[1]), fmaxf(bmax[2], bmax[3])));
   floatx4 tre[MT], tim[MT];
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) {
     tre[mt] = floatx4{0.f, 0.f, 0.f, 0.f};
     tim[mt] = floatx4{0.f, 0.f, 0.f, 0.f};
   }
+  if constexpr (PREC == 0) {
+    // T[y][m] = sum_x E[y][x] Ux[x][m] over this wave's quarter of x
+    constexpr int XS = WX / 4;    // x columns per wave
+    constexpr int KS = XS / 4;    // k-steps of 4
 #pragma unroll 4
-  for (int s = 0; s < KS; ++s) {
-    const int x = wv * XS + 4 * s + (lane >> 4);
-    const float2 ev = buf[(lane & 15) * ST + L::at(x)];
+    for (int s = 0; s < KS; ++s) {
+      const int x = wv * XS + 4 * s + (lane >> 4);
+      const float2 ev = buf[(lane & 15) * ST + L::at(x)];
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-      const float ub = P.ux[x * gp + mt * 16 + (lane & 15)];
-      tre[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ev.x, ub, tre[mt], 0, 0, 0);
-      tim[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ev.y, ub, tim[mt], 0, 0, 0);
+      for (int mt = 0; mt < MT; ++mt) {
+        const float ub = P.ux[x * gp + mt * 16 + (lane & 15)];
+        tre[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ev.x, ub, tre[mt], 0, 0, 0);
+        tim[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ev.y, ub, tim[mt], 0, 0, 0);
+      }
+    }
+  } else {
+    // k-steps of 16 x values, dealt to the waves round robin; lane holds
+    // x = 16 s + 4 (lane/16) + j, j = 0..3 of row lane%16
+    constexpr int KT = WX / 16;
+    for (int s = wv; s < KT; s += 4) {
+      const int x0 = 16 * s + 4 * (lane >> 4);
+      float re[4], im[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float2 ev = buf[(lane & 15) * ST + L::at(x0 + j)];
+        re[j] = ev.x;
+        im[j] = ev.y;
+      }
+      Split4<PREC> ar, ai;
+      split4<PREC>(re, sE, ar);
+      split4<PREC>(im, sE, ai);
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        Split4<PREC> u;
+        table4<PREC>(P.ux_bh, P.ux_bl, P.ux_hh, P.ux_hl, x0, gp, mt * 16 + (lane & 15), u);
+        tre[mt] = mfma3<PREC>(ar, u, tre[mt]);
+        tim[mt] = mfma3<PREC>(ai, u, tim[mt]);
+      }
     }
   }
-  // C[n][m] = sum_y Uy[y][n] T[y][m]; k-step r covers y = rb*16 + 4*(lane/16) + r
+  // C[n][m] = sum_y Uy[y][n] T[y][m]; lane holds y = rb*16 + 4*(lane/16) + r
   floatx4 cre[NPAIR], cim[NPAIR];
 #pragma unroll
   for (int q = 0; q < NPAIR; ++q) {
     cre[q] = floatx4{0.f, 0.f, 0.f, 0.f};
     cim[q] = floatx4{0.f, 0.f, 0.f, 0.f};
   }
+  float unscale = 1.f;
+  if constexpr (PREC == 0) {
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int y = rb * 16 + 4 * (lane >> 4) + r;
+    for (int r = 0; r < 4; ++r) {
+      const int y = rb * 16 + 4 * (lane >> 4) + r;
+#pragma unroll
+      for (int q = 0; q < NPAIR; ++q) {
+        const int nt = (q == 2) ? 1 : 0;
+        const int mt = (q == 1) ? 1 : 0;
+        const float ua = P.uy[y * gp + nt * 16 + (lane & 15)];
+        cre[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ua, tre[mt][r], cre[q], 0, 0, 0);
+        cim[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ua, tim[mt][r], cim[q], 0, 0, 0);
+      }
+    }
+  } else {
+    float sT = 1.f;
+    if constexpr (PREC == 2) {
+      float tm = 0.f;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) tm = fmaxf(tm, fmaxf(fabsf(tre[mt][r]), fabsf(tim[mt][r])));
+      sT = fp16_prescale(wave_max(tm));
+      unscale = 1.f / (sE * A.s_uh * sT * A.s_uh);   // exact: powers of two
+    }
+    const int y0 = rb * 16 + 4 * (lane >> 4);
+    Split4<PREC> br[MT], bi[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      float vr[4] = {tre[mt][0], tre[mt][1], tre[mt][2], tre[mt][3]};
+      float vi[4] = {tim[mt][0], tim[mt][1], tim[mt][2], tim[mt][3]};
+      split4<PREC>(vr, sT, br[mt]);
+      split4<PREC>(vi, sT, bi[mt]);
+    }
 #pragma unroll
     for (int q = 0; q < NPAIR; ++q) {
       const int nt = (q == 2) ? 1 : 0;
       const int mt = (q == 1) ? 1 : 0;
-      const float ua = P.uy[y * gp + nt * 16 + (lane & 15)];
-      cre[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ua, tre[mt][r], cre[q], 0, 0, 0);
-      cim[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ua, tim[mt][r], cim[q], 0, 0, 0);
+      Split4<PREC> u;
+      table4<PREC>(P.uy_bh, P.uy_bl, P.uy_hh, P.uy_hl, y0, gp, nt * 16 + (lane & 15), u);
+      cre[q] = mfma3<PREC>(u, br[mt], cre[q]);
+      cim[q] = mfma3<PREC>(u, bi[mt], cim[q]);
     }
   }
 #pragma unroll
@@ -258,8 +407,8 @@ __global__ void __launch_bounds__(kTPB) k_fld(KArgs A, int b0) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int n = 4 * (lane >> 4) + r, m = lane & 15;
-      red[wv][q][0][n * 16 + m] = cre[q][r];
-      red[wv][q][1][n * 16 + m] = cim[q][r];
+      red[wv][q][0][n * 16 + m] = cre[q][r] * unscale;
+      red[wv][q][1][n * 16 + m] = cim[q][r] * unscale;
     }
   }
   __syncthreads();
@@ -321,22 +470,32 @@ __global__ void __launch_bounds__(kTPB) k_norm(KArgs A, int b0) {
 }
 
 // ---------------------------------------------------------------------------
-// k_hg: out[k][n] = u_n(x_k) * pitch, x_k = (k - w/2) pitch, FP64 recurrence
-__global__ void k_hg(double pitch, int w, int wpad, double waist, int G, int gp, float* __restrict__ out) {
+// k_hg: out[k][n] = u_n(x_k) * pitch, x_k = (k - w/2) pitch, by the normalised
+// FP64 recurrence; optionally the split hi/lo tables from the same FP64 value.
+__global__ void k_hg(double pitch, int w, int wpad, double waist, int G, int gp, float* __restrict__ out,
+                     unsigned short* __restrict__ bh, unsigned short* __restrict__ bl, _Float16* __restrict__ hh,
+                     _Float16* __restrict__ hl, double fp16_scale) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= wpad) return;
   float* o = out + (size_t)k * gp;
-  if (k >= w) {
-    for (int n = 0; n < gp; ++n) o[n] = 0.f;
-    return;
-  }
   const double x = (k - 0.5 * w) * pitch;
   const double s = 1.4142135623730950488 * x / waist;
   const double scale = 1.1892071150027210667 / sqrt(waist) * pitch;   // 2^(1/4) w^(-1/2) p'
   double prev = 0.0;
   double cur = 0.75112554446494248286 * exp(-0.5 * s * s);             // pi^(-1/4)
   for (int n = 0; n < gp; ++n) {
-    o[n] = (n < G) ? (float)(cur * scale) : 0.f;
+    const double v = (k < w && n < G) ? cur * scale : 0.0;
+    o[n] = (float)v;
+    if (bh) {
+      const size_t pk = ((size_t)(k >> 2) * gp + n) * 4 + (k & 3);
+      const unsigned short b1 = bf16_rne((float)v);
+      bh[pk] = b1;
+      bl[pk] = bf16_rne((float)(v - (double)bf16_to_f32(b1)));
+      const double vs = v * fp16_scale;
+      const _Float16 h1 = (_Float16)vs;
+      hh[pk] = h1;
+      hl[pk] = (_Float16)(vs - (double)h1);
+    }
     const double nxt = sqrt(2.0 / (n + 1)) * s * cur - sqrt((double)n / (n + 1)) * prev;
     prev = cur;
     cur = nxt;
@@ -377,13 +536,23 @@ static hipError_t col_nw(const KArgs& a, int b0, int nb, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int WX, int MT>
+static void fld_wm(const KArgs& a, dim3 grid, int b0, hipStream_t s) {
+  if (a.prec == 1)
+    hipLaunchKernelGGL((k_fld<WX, MT, 1>), grid, dim3(kTPB), 0, s, a, b0);
+  else if (a.prec == 2)
+    hipLaunchKernelGGL((k_fld<WX, MT, 2>), grid, dim3(kTPB), 0, s, a, b0);
+  else
+    hipLaunchKernelGGL((k_fld<WX, MT, 0>), grid, dim3(kTPB), 0, s, a, b0);
+}
+
 template <int WX>
 static hipError_t fld_w(const KArgs& a, int b0, int nb, hipStream_t s) {
   dim3 grid(a.nblk, a.npol, nb);
   if (a.gp <= 16)
-    hipLaunchKernelGGL((k_fld<WX, 1>), grid, dim3(kTPB), 0, s, a, b0);
+    fld_wm<WX, 1>(a, grid, b0, s);
   else
-    hipLaunchKernelGGL((k_fld<WX, 2>), grid, dim3(kTPB), 0, s, a, b0);
+    fld_wm<WX, 2>(a, grid, b0, s);
   return hipGetLastError();
 }
 
@@ -454,8 +623,11 @@ hipError_t launch_zero(float2* p, size_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
   return hipGetLastError();
 }
-hipError_t launch_hg(double pitch, int w, int wpad, double waist, int G, int gp, float* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_hg, dim3((wpad + 63) / 64), dim3(64), 0, s, pitch, w, wpad, waist, G, gp, out);
+hipError_t launch_hg(double pitch, int w, int wpad, double waist, int G, int gp, float* out,
+                     unsigned short* bh, unsigned short* bl, _Float16* hh, _Float16* hl, double fp16_scale,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_hg, dim3((wpad + 63) / 64), dim3(64), 0, s, pitch, w, wpad, waist, G, gp, out, bh, bl, hh, hl,
+                     fp16_scale);
   return hipGetLastError();
 }
 

@@ -162,3 +162,37 @@ def test_frame_alone_equals_frame_in_batch():
     batch = run_gpu(cfg["params"], f, keep=False, chunk=4)
     assert np.array_equal(alone["coefs"][0], batch["coefs"][3])
     assert np.array_equal(alone["coefs_norm"][0], batch["coefs_norm"][3])
+
+
+# ---------------------------------------------------------------- precision form
+TOL_SPLIT = 1e-4
+
+
+@pytest.mark.parametrize("prec", ["split_bf16", "split_fp16"])
+@pytest.mark.parametrize("idx,n,groups", [(2, 1, 20), (0, 1, 4), (1, 3, 9), (1, 3, 20), (4, 2, 30)])
+def test_precision_forms(prec, idx, n, groups):
+    cfg = dh_synth.config(idx)
+    p = dict(cfg["truth"], max_mg=groups, precision=prec)
+    f, _ = dh_synth.make_frames(cfg, n_frames=n)
+    _say("precision form", prec, "recipe", idx, "G", groups)
+    gpu = run_gpu(p, f)
+    check_frames(p, f, gpu, range(n), tol=TOL_SPLIT)
+
+
+def test_precision_report_per_result():
+    """Per-frame coefficient error of each form vs the FP64 oracle at the
+    G=20 shapes (128x128 and 640x512): max and p99 over the frames."""
+    rows = []
+    for idx, n in [(2, 1), (1, 8)]:
+        cfg = dh_synth.config(idx)
+        f, _ = dh_synth.make_frames(cfg, n_frames=n)
+        base = dict(cfg["truth"], max_mg=20)
+        refs = [oracle.process_frame(f[i].astype(np.float64), base)["coefs_norm"] for i in range(n)]
+        for prec in ["fp32", "split_bf16", "split_fp16"]:
+            gpu = run_gpu(dict(base, precision=prec), f, keep=False)
+            errs = np.array([_rel(gpu["coefs_norm"][i].astype(np.complex128), refs[i]) for i in range(n)])
+            rows.append((idx, prec, float(errs.max()), float(np.percentile(errs, 99))))
+    for r in rows:
+        _say("precision report recipe %d %-10s max %.2e p99 %.2e" % r)
+    for idx, prec, mx, _ in rows:
+        assert mx <= (TOL if prec == "fp32" else TOL_SPLIT), (idx, prec, mx)
