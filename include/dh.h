@@ -188,6 +188,50 @@ int dh_get_plan_info(dh_handle h, dh_plan_info* out);
 int dh_set_stage_timing(dh_handle h, int enabled);
 int dh_stage_times(dh_handle h, double* ms, int* launches);
 
+/*
+ * Automatic alignment (the paper's digHoloAutoAlign, "Automatic (AutoAlign)"
+ * and "AutoAlign operation modes"): searches the reference tilt, defocus and
+ * the HG waist that maximise the goal below, on `batch` frames (device
+ * pointer as in dh_process_batch), and leaves the plan at the result.
+ *   mode: DH_ALIGN_FULL (snap, then tweak), DH_ALIGN_TWEAK (refine from the
+ *         current parameters), DH_ALIGN_ESTIMATE (snap only);
+ *   what: bitmask of DH_ALIGN_TILT, DH_ALIGN_DEFOCUS, DH_ALIGN_WAIST
+ *         (DH_ALIGN_CENTRE, beam-centre search, is not provided:
+ *         DH_ERR_INVALIDARGUMENT);
+ *   tol:  stop when a full sweep over the parameters improves the goal by
+ *         less than tol (dB), as the paper's AutoAlignTol.
+ * Goal: captured power, 10 log10(sum |c|^2 / sum |E|^2 p'x p'y) over the batch
+ * and both polarisations, computed in FP64 (0 dB: the field is exactly a
+ * combination of the basis modes). The snap puts the tilt at the centroid of
+ * the batch power spectrum (above its mean) near the current tilt; the tweak
+ * is a coordinate search. Tilts stay within 0.6 window radii of their start.
+ * Each trial re-runs the window gather, the IFFTs and the overlap from a
+ * spectrum computed once per call and kept on the device.
+ * The returned value is the goal in dB; -FLT_MAX on failure, with the reason
+ * in dh_last_error (DH_ERR_INVALIDHANDLE, NULLPOINTER, INVALIDDIMENSION,
+ * INVALIDARGUMENT, MEMORYALLOCATION, ERROR). Synchronises the device.
+ */
+#define DH_ALIGN_FULL 0
+#define DH_ALIGN_TWEAK 1
+#define DH_ALIGN_ESTIMATE 2
+#define DH_ALIGN_TILT 1u
+#define DH_ALIGN_DEFOCUS 2u
+#define DH_ALIGN_WAIST 4u
+#define DH_ALIGN_CENTRE 8u
+float dh_autoalign(dh_handle h, const void* frames, int batch, int mode, unsigned what, float tol, void* stream);
+
+typedef struct dh_align_report {
+  int evaluations;             /* trials of the goal */
+  int sweeps;                  /* tweak sweeps over the parameters */
+  double start_goal_db;        /* goal after the snap (before the tweak) */
+  double goal_db;              /* final goal */
+  double captured;             /* final goal as a power fraction */
+  double snap_tilt_deg[2][2];  /* tilt found by the snap ([pol][x,y]) */
+} dh_align_report;
+
+/* Report of the last dh_autoalign on h. */
+int dh_get_align_report(dh_handle h, dh_align_report* out);
+
 /* Error code of the last failing call on h (0 if none), 2 for a bad handle. */
 int dh_last_error(dh_handle h);
 

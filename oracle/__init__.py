@@ -7,5 +7,5 @@ The GPU library never calls it and shares no code with it.
 from .holo_oracle import (  # noqa: F401
     DEG, w_max_rad, tilt_bins, radius_bins, ifft_size, mode_list, mode_count,
     window_origin, mask_bins, geometry, hermite_gauss_1d, spectrum_window,
-    field_from_window, overlap, power_normalise, process_frame, process_batch,
+    field_from_window, overlap, power_normalise, process_frame, process_batch, captured_power, goal_db,
 )

@@ -287,6 +287,35 @@ def process_frame(frame: np.ndarray, params: dict, g: dict | None = None) -> dic
                 coefs_norm=power_normalise(c.reshape(-1)).reshape(c.shape))
 
 
+def captured_power(frame: np.ndarray, params: dict, g: dict | None = None):
+    """Alignment goal terms ("Automatic (AutoAlign)": the batch insertion loss,
+    read as the share of the field's power the HG basis holds): per pol the
+    mode power sum |c|^2 and the field power sum |E|^2 p'_x p'_y. Returns two
+    arrays [pol]."""
+    if g is None:
+        g = geometry(params)
+    mp, fp = [], []
+    for pol in range(params["pol_count"]):
+        w = spectrum_window(frame, g, pol)
+        e = field_from_window(w, g, pol)
+        c = overlap(e, g, params["waist"], params["max_mg"])
+        mp.append(float(np.sum(np.abs(c) ** 2)))
+        fp.append(float(np.sum(np.abs(e) ** 2)) * g["px2"] * g["py2"])
+    return np.array(mp), np.array(fp)
+
+
+def goal_db(frames, params, indices=None) -> float:
+    """10 log10(sum over frames and pols of mode power / field power)."""
+    g = geometry(params)
+    idx = range(frames.shape[0]) if indices is None else indices
+    m = f = 0.0
+    for i in idx:
+        a, b = captured_power(np.asarray(frames[i], dtype=np.float64), params, g)
+        m += a.sum()
+        f += b.sum()
+    return 10.0 * math.log10(m / f)
+
+
 def process_batch(frames: np.ndarray, params: dict, indices=None) -> dict:
     """process_frame over frames[i] for i in `indices` (all by default)."""
     g = geometry(params)

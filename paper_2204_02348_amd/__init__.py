@@ -36,7 +36,9 @@ PREC_SPLIT_FP16 = 2
 
 EXPORTS = ["dh_plan_check", "dh_plan", "dh_process_batch", "dh_mode_coefs", "dh_get_window",
            "dh_get_fields", "dh_get_params", "dh_get_plan_info", "dh_set_stage_timing", "dh_stage_times",
-           "dh_last_error", "dh_destroy"]
+           "dh_autoalign", "dh_get_align_report", "dh_last_error", "dh_destroy"]
+ALIGN_FULL, ALIGN_TWEAK, ALIGN_ESTIMATE = 0, 1, 2
+ALIGN_TILT, ALIGN_DEFOCUS, ALIGN_WAIST, ALIGN_CENTRE = 1, 2, 4, 8
 STAGES = ["fft_x", "fft_y_crop_ifft_y", "ifft_x_tilt_overlap", "power_norm"]
 
 
@@ -56,6 +58,11 @@ class Params(C.Structure):
         ("max_mg", C.c_int), ("input_dtype", C.c_int), ("precision", C.c_int),
         ("ifft_mode", C.c_int), ("keep_window", C.c_int), ("keep_fields", C.c_int),
     ]
+
+
+class AlignReport(C.Structure):
+    _fields_ = [("evaluations", C.c_int), ("sweeps", C.c_int), ("start_goal_db", C.c_double),
+                ("goal_db", C.c_double), ("captured", C.c_double), ("snap_tilt_deg", (C.c_double * 2) * 2)]
 
 
 class PlanInfo(C.Structure):
@@ -92,10 +99,13 @@ def lib():
         L.dh_get_plan_info.argtypes = [C.c_int, C.POINTER(PlanInfo)]
         L.dh_set_stage_timing.argtypes = [C.c_int, C.c_int]
         L.dh_stage_times.argtypes = [C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)]
+        L.dh_autoalign.argtypes = [C.c_int, C.c_void_p, C.c_int, C.c_int, C.c_uint, C.c_float, C.c_void_p]
+        L.dh_get_align_report.argtypes = [C.c_int, C.POINTER(AlignReport)]
         L.dh_last_error.argtypes = [C.c_int]
         L.dh_destroy.argtypes = [C.c_int]
         for name in EXPORTS:
             getattr(L, name).restype = C.c_int
+        L.dh_autoalign.restype = C.c_float
         _lib = L
     return _lib
 
@@ -232,6 +242,31 @@ class Plan:
         if rc != SUCCESS:
             raise DhError(rc, "dh_stage_times")
         return {STAGES[k]: (ms[k], n[k]) for k in range(4)}
+
+    def autoalign(self, frames, batch: int, mode: int = ALIGN_FULL,
+                  what: int = ALIGN_TILT | ALIGN_DEFOCUS | ALIGN_WAIST, tol: float = 1e-4, stream=None) -> float:
+        """Goal in dB after alignment; the plan keeps the aligned parameters."""
+        g = lib().dh_autoalign(self.handle, C.c_void_p(_ptr(frames)), batch, mode, what, tol,
+                               C.c_void_p(_stream(stream)))
+        if g == -3.4028234663852886e38:
+            raise DhError(self.last_error(), "dh_autoalign")
+        return g
+
+    def align_report(self) -> AlignReport:
+        r = AlignReport()
+        rc = lib().dh_get_align_report(self.handle, C.byref(r))
+        if rc != SUCCESS:
+            raise DhError(rc, "dh_get_align_report")
+        return r
+
+    def params(self) -> dict:
+        p = Params()
+        rc = lib().dh_get_params(self.handle, C.byref(p))
+        if rc != SUCCESS:
+            raise DhError(rc, "dh_get_params")
+        return {"tilt_deg": [[p.tilt_deg[q][a] for a in range(2)] for q in range(2)],
+                "defocus": [p.defocus[0], p.defocus[1]], "waist": p.waist,
+                "beam_centre": [[p.beam_centre[q][a] for a in range(2)] for q in range(2)]}
 
     def last_error(self) -> int:
         return lib().dh_last_error(self.handle)

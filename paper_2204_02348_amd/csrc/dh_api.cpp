@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cfloat>
 #include <cmath>
 #include <complex>
 #include <cstdint>
@@ -54,6 +55,49 @@ bool inside(double u, double v, double ax, double ay, double rx, double ry) {
   return a * a + b * b <= 1.0;
 }
 
+// Tilt- and centre-dependent geometry of polarisation q: window origin,
+// cross-term position, the box of bins inside the Fourier window and each box
+// row's mask interval (FP64, inclusive ellipse in bins).
+int derive_pol(const dh_params* p, Geom* g, int q) {
+  const double pix = p->pixel_size, lam = p->wavelength;
+  const int nx = g->nx, ny = g->ny;
+  const int half = p->frame_w / p->pol_count;
+  PolGeom& P = g->pol[q];
+  P.ax = p->tilt_deg[q][0] * kDeg * nx * pix / lam;
+  P.ay = p->tilt_deg[q][1] * kDeg * ny * pix / lam;
+  const int ix = (int)std::floor(p->beam_centre[q][0] / pix + 0.5);
+  const int iy = (int)std::floor(p->beam_centre[q][1] / pix + 0.5);
+  P.x0 = q * half + half / 2 + ix - nx / 2;
+  P.y0 = p->frame_h / 2 + iy - ny / 2;
+  P.dx = p->beam_centre[q][0] - ix * pix;
+  P.dy = p->beam_centre[q][1] - iy * pix;
+  if (P.x0 < 0 || P.x0 + nx > p->frame_w || P.y0 < 0 || P.y0 + ny > p->frame_h) return DH_ERR_INVALIDDIMENSION;
+  // bounding box of the bins inside the window
+  const int u_a = (int)std::floor(-P.ax - g->rx) - 1, u_b = (int)std::ceil(-P.ax + g->rx) + 1;
+  const int v_a = (int)std::floor(-P.ay - g->ry) - 1, v_b = (int)std::ceil(-P.ay + g->ry) + 1;
+  P.ulo = u_b; P.uhi = u_a; P.vlo = v_b; P.vhi = v_a;
+  for (int v = v_a; v <= v_b; ++v)
+    for (int u = u_a; u <= u_b; ++u)
+      if (inside(u, v, P.ax, P.ay, g->rx, g->ry)) {
+        P.ulo = std::min(P.ulo, u); P.uhi = std::max(P.uhi, u);
+        P.vlo = std::min(P.vlo, v); P.vhi = std::max(P.vhi, v);
+      }
+  if (P.uhi < P.ulo || P.vhi < P.vlo) return DH_ERR_INVALIDARGUMENT;  // empty window
+  const int bxq = P.uhi - P.ulo + 1, byq = P.vhi - P.vlo + 1;
+  if (bxq > g->bx || byq > g->by) return DH_ERR_INVALIDARGUMENT;
+  P.row_lo.assign(byq, 1);
+  P.row_hi.assign(byq, 0);
+  for (int i = 0; i < byq; ++i) {
+    const int v = P.vhi - i;
+    int lo = INT32_MAX, hi = INT32_MIN;
+    for (int u = P.ulo; u <= P.uhi; ++u)
+      if (inside(u, v, P.ax, P.ay, g->rx, g->ry)) { lo = std::min(lo, u); hi = std::max(hi, u); }
+    if (lo <= hi) { P.row_lo[i] = lo; P.row_hi[i] = hi; }
+    else { P.row_lo[i] = 1; P.row_hi[i] = 0; }
+  }
+  return DH_SUCCESS;
+}
+
 int derive(const dh_params* p, Geom* g) {
   if (!p) return DH_ERR_NULLPOINTER;
   if (p->pol_count != 1 && p->pol_count != 2) return DH_ERR_INVALIDPOLARISATION;
@@ -87,44 +131,14 @@ int derive(const dh_params* p, Geom* g) {
   g->G = p->max_mg;
   g->gp = g->G <= 16 ? 16 : 32;
   g->nmodes = g->G * (g->G + 1) / 2;
-  const int half = p->frame_w / p->pol_count;
-  g->bx = g->by = 0;
+  // every window position fits a box of floor(2r)+1 bins per axis, so the
+  // workspaces do not change when the tilt does (alignment)
+  g->bx = (int)std::floor(2.0 * g->rx) + 1;
+  g->by = (int)std::floor(2.0 * g->ry) + 1;
+  if (g->bx > g->wx || g->by > g->wy) return DH_ERR_INVALIDARGUMENT;
   for (int q = 0; q < p->pol_count; ++q) {
-    PolGeom& P = g->pol[q];
-    P.ax = p->tilt_deg[q][0] * kDeg * nx * pix / lam;
-    P.ay = p->tilt_deg[q][1] * kDeg * ny * pix / lam;
-    const int ix = (int)std::floor(p->beam_centre[q][0] / pix + 0.5);
-    const int iy = (int)std::floor(p->beam_centre[q][1] / pix + 0.5);
-    P.x0 = q * half + half / 2 + ix - nx / 2;
-    P.y0 = p->frame_h / 2 + iy - ny / 2;
-    P.dx = p->beam_centre[q][0] - ix * pix;
-    P.dy = p->beam_centre[q][1] - iy * pix;
-    if (P.x0 < 0 || P.x0 + nx > p->frame_w || P.y0 < 0 || P.y0 + ny > p->frame_h) return DH_ERR_INVALIDDIMENSION;
-    // bounding box of the bins inside the window
-    const int u_a = (int)std::floor(-P.ax - g->rx) - 1, u_b = (int)std::ceil(-P.ax + g->rx) + 1;
-    const int v_a = (int)std::floor(-P.ay - g->ry) - 1, v_b = (int)std::ceil(-P.ay + g->ry) + 1;
-    P.ulo = u_b; P.uhi = u_a; P.vlo = v_b; P.vhi = v_a;
-    for (int v = v_a; v <= v_b; ++v)
-      for (int u = u_a; u <= u_b; ++u)
-        if (inside(u, v, P.ax, P.ay, g->rx, g->ry)) {
-          P.ulo = std::min(P.ulo, u); P.uhi = std::max(P.uhi, u);
-          P.vlo = std::min(P.vlo, v); P.vhi = std::max(P.vhi, v);
-        }
-    if (P.uhi < P.ulo || P.vhi < P.vlo) return DH_ERR_INVALIDARGUMENT;  // empty window
-    const int bxq = P.uhi - P.ulo + 1, byq = P.vhi - P.vlo + 1;
-    if (bxq > g->wx || byq > g->wy) return DH_ERR_INVALIDARGUMENT;
-    g->bx = std::max(g->bx, bxq);
-    g->by = std::max(g->by, byq);
-    P.row_lo.assign(byq, 1);
-    P.row_hi.assign(byq, 0);
-    for (int i = 0; i < byq; ++i) {
-      const int v = P.vhi - i;
-      int lo = INT32_MAX, hi = INT32_MIN;
-      for (int u = P.ulo; u <= P.uhi; ++u)
-        if (inside(u, v, P.ax, P.ay, g->rx, g->ry)) { lo = std::min(lo, u); hi = std::max(hi, u); }
-      if (lo <= hi) { P.row_lo[i] = lo; P.row_hi[i] = hi; }
-      else { P.row_lo[i] = 1; P.row_hi[i] = 0; }
-    }
+    const int e = derive_pol(p, g, q);
+    if (e != DH_SUCCESS) return e;
   }
   if (!dh::sizes_supported(nx, ny, g->wx, g->wy)) return DH_ERR_INVALIDDIMENSION;
   return DH_SUCCESS;
@@ -167,7 +181,7 @@ struct Layout {  // byte offsets inside one device allocation
   size_t tw_nx, tw_ny, tw_wx, tw_wy, modes, total_tables;
   size_t pol_mrow[2], pol_qrow[2], pol_qcol[2], pol_rhox[2], pol_rhoy[2], pol_tx[2], pol_ty[2], pol_ux[2], pol_uy[2];
   size_t pol_uxs[2][4], pol_uys[2][4];   // split tables: bf16 hi, bf16 lo, fp16 hi, fp16 lo
-  size_t t1[4], f2[4], partial[4], coefs, coefs_norm, window, fields, total;
+  size_t t1[4], f2[4], partial[4], capt, coefs, coefs_norm, window, fields, total;
 };
 
 Layout layout(const Geom& g, const dh_params* p, int max_batch, int chunk, int nws) {
@@ -184,6 +198,9 @@ Layout layout(const Geom& g, const dh_params* p, int max_batch, int chunk, int n
     L.pol_rhoy[q] = take(g.by * 8);
     L.pol_tx[q] = take(g.wx * 8);
     L.pol_ty[q] = take(g.wy * 8);
+  }
+  L.total_tables = o;   // host-built tables end here; the HG tables (built on the GPU) follow
+  for (int q = 0; q < p->pol_count; ++q) {
     L.pol_ux[q] = take((size_t)g.wx * g.gp * 4);
     L.pol_uy[q] = take((size_t)g.wyp * g.gp * 4);
     for (int t = 0; t < 4; ++t) {
@@ -191,14 +208,14 @@ Layout layout(const Geom& g, const dh_params* p, int max_batch, int chunk, int n
       L.pol_uys[q][t] = take((size_t)g.wyp * g.gp * 2);
     }
   }
-  L.total_tables = o;
   const size_t P = p->pol_count;
   const size_t nm = g.nmodes > 0 ? g.nmodes : 1;
   for (int w = 0; w < nws; ++w) {
     L.t1[w] = take((size_t)chunk * P * g.ny * g.bx * 8);
     L.f2[w] = take((size_t)chunk * P * g.wy * ((g.bx + 15) / 16 * 16) * 8);
-    L.partial[w] = take((size_t)chunk * P * (g.wyp / 16) * nm * 8);
+    L.partial[w] = take((size_t)chunk * P * (g.wyp / 16) * (nm + 1) * 8);
   }
+  L.capt = take((size_t)max_batch * P * 2 * 8);
   L.coefs = take((size_t)max_batch * P * nm * 8);
   L.coefs_norm = take((size_t)max_batch * P * nm * 8);
   L.window = p->keep_window ? take((size_t)max_batch * P * g.wy * g.wx * 8) : 0;
@@ -221,6 +238,10 @@ struct Plan {
   hipEvent_t fork = nullptr, join[4]{};
   // per-stage timing: a start and an end event around every launch, on the
   // stream the kernel runs on
+  // alignment: device scratch reused across calls, and the last report
+  char* amem = nullptr;
+  size_t amem_bytes = 0;
+  dh_align_report rep{};
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
   std::vector<int> ev_stage;         // stage of launch i (events 2i, 2i+1)
@@ -282,7 +303,7 @@ double hg_fp16_scale(double waist, double pitch) {
   return std::ldexp(1.0, 14 - e);
 }
 
-int build_tables(Plan* pl) {
+int build_tables(Plan* pl, bool hg = true) {
   const Geom& g = pl->g;
   const dh_params* p = &pl->params;
   const Layout& L = pl->L;
@@ -343,6 +364,7 @@ int build_tables(Plan* pl) {
     put(host, L.pol_ty[q], ty);
   }
   if (hipMemcpy(pl->mem, host.data(), L.total_tables, hipMemcpyHostToDevice) != hipSuccess) return DH_ERR_ERROR;
+  if (!hg) return DH_SUCCESS;
   const double waist = p->waist > 0 ? p->waist : 1.0;
   pl->s_uh = (float)hg_fp16_scale(waist, std::max(g.pxp, g.pyp));
   for (int q = 0; q < p->pol_count; ++q) {
@@ -372,6 +394,8 @@ void fill_kargs(Plan* pl, int w) {
   a.nxny = (float)((double)g.nx * g.ny);
   a.prec = p->precision;
   a.s_uh = pl->s_uh;
+  a.capt = nullptr;
+  a.cell = g.pxp * g.pyp;
   for (int q = 0; q < p->pol_count; ++q) {
     const PolGeom& P = g.pol[q];
     dh::PolTab& t = a.pol[q];
@@ -434,6 +458,7 @@ void release(Plan* pl) {
   if (pl->fork) (void)hipEventDestroy(pl->fork);
   for (hipEvent_t e : pl->ev_pool) (void)hipEventDestroy(e);
   if (pl->mem) (void)hipFree(pl->mem);
+  if (pl->amem) (void)hipFree(pl->amem);
   (void)hipSetDevice(dev);
   delete pl;
 }
@@ -672,3 +697,268 @@ int dh_destroy(dh_handle h) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Alignment (digHoloAutoAlign): snap + tweak of tilt, defocus and waist.
+//
+// Goal: captured power, 10 log10(sum |c|^2 / sum |E|^2 p'x p'y) over the
+// batch and both polarisations: the share of the reconstructed field's power
+// that the HG basis holds (0 dB when the field is exactly a combination of the
+// modes; our reading of the paper's insertion-loss goal for one batch).
+// The row pass and the column FFT run once over an extended box that covers
+// every window position within the search margin; each trial re-runs only the
+// window gather, the IFFTs and the overlap from the stored spectrum.
+namespace {
+
+struct AlignCtx {
+  Plan* pl;
+  hipStream_t s;
+  int batch;
+  int bxe, bye;
+  int k0e[2], ky0e[2];
+  float2* spec;
+  double* capt;
+  int evals = 0;
+};
+
+// one trial with the plan's current parameters: per-pol mode and field power
+// summed over the batch (FP64), or false if the window left the stored region
+bool align_eval(AlignCtx& c, bool hg, double mp[2], double fp[2]) {
+  Plan* pl = c.pl;
+  Geom& g = pl->g;
+  const int np = pl->params.pol_count;
+  int offj[2] = {0, 0}, offi[2] = {0, 0};
+  for (int q = 0; q < np; ++q) {
+    if (derive_pol(&pl->params, &g, q) != DH_SUCCESS) return false;
+    offj[q] = -g.pol[q].uhi - c.k0e[q];
+    offi[q] = -g.pol[q].vhi - c.ky0e[q];
+    if (offj[q] < 0 || offj[q] + g.bx > c.bxe || offi[q] < 0 || offi[q] + g.by > c.bye) return false;
+  }
+  if (build_tables(pl, hg) != DH_SUCCESS) return false;
+  for (int w = 0; w < pl->nws; ++w) fill_kargs(pl, w);
+  dh::KArgs k = pl->ka[0];
+  k.capt = c.capt;
+  const size_t per_frame = (size_t)np * c.bxe * c.bye;
+  for (int b0 = 0; b0 < c.batch; b0 += pl->chunk) {
+    const int nb = std::min(pl->chunk, c.batch - b0);
+    if (dh::launch_gather(k, c.spec + b0 * per_frame, c.bxe, c.bye, offj, offi, nb, c.s) != hipSuccess ||
+        dh::launch_fld(k, b0, nb, c.s) != hipSuccess || dh::launch_norm(k, b0, nb, c.s) != hipSuccess)
+      return false;
+  }
+  std::vector<double> h((size_t)c.batch * np * 2);
+  if (hipMemcpyAsync(h.data(), c.capt, h.size() * 8, hipMemcpyDeviceToHost, c.s) != hipSuccess ||
+      hipStreamSynchronize(c.s) != hipSuccess)
+    return false;
+  for (int q = 0; q < 2; ++q) mp[q] = fp[q] = 0.0;
+  for (int b = 0; b < c.batch; ++b)
+    for (int q = 0; q < np; ++q) {
+      mp[q] += h[((size_t)b * np + q) * 2];
+      fp[q] += h[((size_t)b * np + q) * 2 + 1];
+    }
+  ++c.evals;
+  return true;
+}
+
+double db(double m, double f) { return (m > 0 && f > 0) ? 10.0 * std::log10(m / f) : -300.0; }
+
+}  // namespace
+
+extern "C" float dh_autoalign(dh_handle h, const void* frames, int batch, int mode, unsigned what, float tol,
+                              void* stream) {
+  Plan* pl = get(h);
+  if (!pl) return -FLT_MAX;
+  if (!frames) return (set_err(pl, DH_ERR_NULLPOINTER), -FLT_MAX);
+  if (batch < 1) batch = 1;
+  if (batch > pl->max_batch) return (set_err(pl, DH_ERR_INVALIDDIMENSION), -FLT_MAX);
+  if (mode < DH_ALIGN_FULL || mode > DH_ALIGN_ESTIMATE || (what & DH_ALIGN_CENTRE) ||
+      (mode != DH_ALIGN_ESTIMATE && pl->g.G == 0) || !(tol >= 0.f))
+    return (set_err(pl, DH_ERR_INVALIDARGUMENT), -FLT_MAX);
+  hipStream_t s = (hipStream_t)stream;
+  if (hipDeviceSynchronize() != hipSuccess) return (set_err(pl, DH_ERR_ERROR), -FLT_MAX);
+  dh_params& P = pl->params;
+  Geom& g = pl->g;
+  const int np = P.pol_count;
+  const double pix = P.pixel_size, lam = P.wavelength;
+  const double binx = lam / (g.nx * pix) / kDeg, biny = lam / (g.ny * pix) / kDeg;   // one bin in degrees
+  const dh_params start = P;
+  // search margin around the starting tilt: 0.6 w_c, within the spectrum
+  const double mdeg = 0.6 * P.window_radius_deg;
+  AlignCtx c{pl, s, batch};
+  c.bxe = c.bye = 0;
+  double tlo[2][2], thi[2][2];
+  for (int q = 0; q < np; ++q) {
+    const double ax = P.tilt_deg[q][0] / binx, ay = P.tilt_deg[q][1] / biny;
+    const double mx = mdeg / binx, my = mdeg / biny;
+    c.k0e[q] = (int)std::floor(ax - mx - g.rx) - 2;
+    c.ky0e[q] = (int)std::floor(ay - my - g.ry) - 2;
+    c.bxe = std::max(c.bxe, (int)std::ceil(ax + mx + g.rx) + 2 - c.k0e[q] + 1);
+    c.bye = std::max(c.bye, (int)std::ceil(ay + my + g.ry) + 2 - c.ky0e[q] + 1);
+    tlo[q][0] = P.tilt_deg[q][0] - mdeg; thi[q][0] = P.tilt_deg[q][0] + mdeg;
+    tlo[q][1] = P.tilt_deg[q][1] - mdeg; thi[q][1] = P.tilt_deg[q][1] + mdeg;
+  }
+  if (c.bxe >= g.nx || c.bye >= g.ny) return (set_err(pl, DH_ERR_INVALIDARGUMENT), -FLT_MAX);
+  // scratch: extended row pass, stored spectrum, power map, captured power
+  const size_t t1b = align256((size_t)batch * np * c.bxe * g.ny * 8);
+  const size_t spb = align256((size_t)batch * np * c.bxe * c.bye * 8);
+  const size_t pwb = align256((size_t)np * c.bxe * c.bye * 4);
+  const size_t cpb = align256((size_t)batch * np * 2 * 8);
+  const size_t need = t1b + spb + pwb + cpb;
+  if (need > pl->amem_bytes) {
+    if (pl->amem) (void)hipFree(pl->amem);
+    pl->amem = nullptr;
+    pl->amem_bytes = 0;
+    if (hipMalloc(&pl->amem, need) != hipSuccess) {
+      (void)hipGetLastError();
+      return (set_err(pl, DH_ERR_MEMORYALLOCATION), -FLT_MAX);
+    }
+    pl->amem_bytes = need;
+  }
+  float2* t1e = (float2*)pl->amem;
+  c.spec = (float2*)(pl->amem + t1b);
+  float* pw = (float*)(pl->amem + t1b + spb);
+  c.capt = (double*)(pl->amem + t1b + spb + pwb);
+  {
+    dh::KArgs ke = pl->ka[0];
+    ke.bx = c.bxe;
+    ke.t1 = t1e;
+    for (int q = 0; q < np; ++q) {
+      ke.pol[q].k0 = c.k0e[q];
+      ke.pol[q].ky0 = c.ky0e[q];
+    }
+    if (dh::launch_row(ke, frames, P.input_dtype == DH_INPUT_U16, 0, batch, s) != hipSuccess ||
+        dh::launch_spec(ke, c.spec, c.bye, batch, s) != hipSuccess)
+      return (set_err(pl, DH_ERR_ERROR), -FLT_MAX);
+  }
+  dh_align_report rep{};
+  // snap: tilt at the centroid of the batch power spectrum above its mean
+  if (mode != DH_ALIGN_TWEAK && (what & DH_ALIGN_TILT)) {
+    const size_t plane = (size_t)c.bxe * c.bye;
+    std::vector<float> hp(np * plane);
+    if (dh::launch_psum(c.spec, batch, np, plane, pw, s) != hipSuccess ||
+        hipMemcpyAsync(hp.data(), pw, hp.size() * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return (set_err(pl, DH_ERR_ERROR), -FLT_MAX);
+    for (int q = 0; q < np; ++q) {
+      const float* m = hp.data() + q * plane;
+      double mean = 0.0;
+      for (size_t e = 0; e < plane; ++e) mean += m[e];
+      mean /= (double)plane;
+      double sw = 0.0, sj = 0.0, si = 0.0;
+      for (int j = 0; j < c.bxe; ++j)
+        for (int i = 0; i < c.bye; ++i) {
+          const double w = std::max(0.0, (double)m[(size_t)j * c.bye + i] - mean);
+          sw += w; sj += w * j; si += w * i;
+        }
+      if (sw > 0) {
+        P.tilt_deg[q][0] = std::min(thi[q][0], std::max(tlo[q][0], (c.k0e[q] + sj / sw) * binx));
+        P.tilt_deg[q][1] = std::min(thi[q][1], std::max(tlo[q][1], (c.ky0e[q] + si / sw) * biny));
+      }
+      rep.snap_tilt_deg[q][0] = P.tilt_deg[q][0];
+      rep.snap_tilt_deg[q][1] = P.tilt_deg[q][1];
+    }
+  }
+  double mp[2], fp[2];
+  if (pl->g.G == 0) {  // estimate only, nothing to evaluate
+    for (int q = 0; q < np; ++q) derive_pol(&P, &g, q);
+    if (build_tables(pl, false) != DH_SUCCESS) return (set_err(pl, DH_ERR_ERROR), -FLT_MAX);
+    pl->rep = rep;
+    set_err(pl, DH_SUCCESS);
+    return 0.f;
+  }
+  if (!align_eval(c, true, mp, fp)) return (P = start, build_tables(pl), set_err(pl, DH_ERR_ERROR), -FLT_MAX);
+  double best_pol[2] = {db(mp[0], fp[0]), np > 1 ? db(mp[1], fp[1]) : 0.0};
+  double goal = db(mp[0] + (np > 1 ? mp[1] : 0.0), fp[0] + (np > 1 ? fp[1] : 0.0));
+  rep.start_goal_db = goal;
+  // tweak: coordinate search, a parabola through three trials per coordinate;
+  // per-pol parameters of both pols move together (each pol's captured power
+  // depends only on its own tilt and defocus), the shared waist on the joint goal
+  if (mode != DH_ALIGN_ESTIMATE) {
+    struct Coord { int kind; int axis; double h; };   // kind 0 tilt, 1 defocus, 2 waist
+    std::vector<Coord> coords;
+    if (what & DH_ALIGN_TILT) { coords.push_back({0, 0, 0.5 * binx}); coords.push_back({0, 1, 0.5 * biny}); }
+    if (what & DH_ALIGN_DEFOCUS) coords.push_back({1, 0, 0.02});
+    if (what & DH_ALIGN_WAIST) coords.push_back({2, 0, 0.03 * P.waist});
+    auto get = [&](const Coord& k, int q) -> double& {
+      return k.kind == 0 ? P.tilt_deg[q][k.axis] : k.kind == 1 ? P.defocus[q] : P.waist;
+    };
+    auto clampv = [&](const Coord& k, int q, double v) {
+      if (k.kind == 0) return std::min(thi[q][k.axis], std::max(tlo[q][k.axis], v));
+      if (k.kind == 2) return std::max(0.25 * start.waist, v);
+      return v;
+    };
+    for (int sweep = 0; sweep < 60 && !coords.empty(); ++sweep) {
+      const double goal0 = goal;
+      for (Coord& k : coords) {
+        const int nq = k.kind == 2 ? 1 : np;      // the waist is one shared value
+        double x0[2], f0[2], fm[2], fpl[2];
+        for (int q = 0; q < nq; ++q) x0[q] = get(k, q);
+        auto trial = [&](const double* v, double* out) -> bool {
+          for (int q = 0; q < nq; ++q) get(k, q) = v[q];
+          if (!align_eval(c, k.kind == 2, mp, fp)) return false;
+          if (k.kind == 2) out[0] = db(mp[0] + (np > 1 ? mp[1] : 0.0), fp[0] + (np > 1 ? fp[1] : 0.0));
+          else for (int q = 0; q < nq; ++q) out[q] = db(mp[q], fp[q]);
+          return true;
+        };
+        for (int q = 0; q < nq; ++q) f0[q] = k.kind == 2 ? goal : best_pol[q];
+        double vp[2], vm[2];
+        for (int q = 0; q < nq; ++q) { vp[q] = clampv(k, q, x0[q] + k.h); vm[q] = clampv(k, q, x0[q] - k.h); }
+        bool okp = trial(vp, fpl), okm = trial(vm, fm);
+        double vn[2], fn[2];
+        for (int q = 0; q < nq; ++q) {
+          if (!okp) fpl[q] = -1e300;
+          if (!okm) fm[q] = -1e300;
+          const double cv = fpl[q] + fm[q] - 2.0 * f0[q];
+          double d;
+          if (okp && okm && cv < 0) d = 0.5 * k.h * (fm[q] - fpl[q]) / cv;
+          else d = (fpl[q] > fm[q]) ? 2.0 * k.h : -2.0 * k.h;
+          d = std::max(-2.0 * k.h, std::min(2.0 * k.h, d));
+          vn[q] = clampv(k, q, x0[q] + d);
+        }
+        const bool okn = trial(vn, fn);
+        // keep the best of the four trials per pol; the step grows when the
+        // best trial is the far one and shrinks when no trial beat the centre
+        bool moved = false, far = false;
+        for (int q = 0; q < nq; ++q) {
+          double bv = x0[q], bf = f0[q];
+          if (okp && fpl[q] > bf) { bv = vp[q]; bf = fpl[q]; }
+          if (okm && fm[q] > bf) { bv = vm[q]; bf = fm[q]; }
+          if (okn && fn[q] > bf) { bv = vn[q]; bf = fn[q]; }
+          get(k, q) = bv;
+          if (k.kind == 2) goal = bf; else best_pol[q] = bf;
+          moved |= bv != x0[q];
+          far |= std::fabs(bv - x0[q]) > 1.5 * k.h;
+        }
+        k.h *= far ? 2.0 : moved ? 1.0 : 0.5;
+        if (k.kind != 2) {
+          if (!align_eval(c, false, mp, fp)) return (P = start, build_tables(pl), set_err(pl, DH_ERR_ERROR), -FLT_MAX);
+          goal = db(mp[0] + (np > 1 ? mp[1] : 0.0), fp[0] + (np > 1 ? fp[1] : 0.0));
+        } else if (moved) {
+          if (!align_eval(c, true, mp, fp)) return (P = start, build_tables(pl), set_err(pl, DH_ERR_ERROR), -FLT_MAX);
+          for (int q = 0; q < np; ++q) best_pol[q] = db(mp[q], fp[q]);
+        }
+      }
+      rep.sweeps = sweep + 1;
+      if (sweep >= 1 && goal - goal0 < tol) break;
+    }
+  }
+  // leave the plan at the final parameters with complete tables
+  if (!align_eval(c, true, mp, fp)) return (P = start, build_tables(pl), set_err(pl, DH_ERR_ERROR), -FLT_MAX);
+  goal = db(mp[0] + (np > 1 ? mp[1] : 0.0), fp[0] + (np > 1 ? fp[1] : 0.0));
+  for (int w = 0; w < pl->nws; ++w) fill_kargs(pl, w);
+  rep.goal_db = goal;
+  rep.captured = std::pow(10.0, goal / 10.0);
+  rep.evaluations = c.evals;
+  pl->rep = rep;
+  pl->last_batch = batch;
+  pl->last_stream = s;
+  set_err(pl, DH_SUCCESS);
+  return (float)goal;
+}
+
+extern "C" int dh_get_align_report(dh_handle h, dh_align_report* out) {
+  Plan* pl = get(h);
+  if (!pl) return DH_ERR_INVALIDHANDLE;
+  if (!out) return set_err(pl, DH_ERR_NULLPOINTER);
+  *out = pl->rep;
+  return DH_SUCCESS;
+}

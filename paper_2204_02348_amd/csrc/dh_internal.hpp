@@ -54,7 +54,10 @@ struct KArgs {
   const float2* tw_wy;
   float2* t1;               // [chunk][P][bx][ny] row-pass spectrum at the box columns (column-major)
   float2* f2;               // [chunk][P][wy][bxp] column pass + crop + y-IFFT
-  float2* partial;          // [chunk][nblk][P][nmodes] per-row-block share of each coefficient
+  float2* partial;          // [chunk][nblk][P][nmodes + 1] per-row-block share of each coefficient,
+                            // then the block's field power sum |E|^2 (if capt)
+  double* capt;             // [max_batch][P][2] mode power, field power (FP64), or null
+  double cell;              // p'_x p'_y, the field power's quadrature weight
   int nblk;                 // 16-row blocks of the field (wyp / 16)
   float2* coefs;            // [max_batch][P][nmodes] raw coefficients
   float2* coefs_norm;       // [max_batch][P][nmodes] power-normalised
@@ -69,6 +72,12 @@ hipError_t launch_col(const KArgs& a, int b0, int nb, hipStream_t s);
 hipError_t launch_fld(const KArgs& a, int b0, int nb, hipStream_t s);
 hipError_t launch_norm(const KArgs& a, int b0, int nb, hipStream_t s);
 hipError_t launch_zero(float2* p, size_t n, hipStream_t s);
+// alignment: column FFT of an extended box stored as spec[b][p][j][i] (nrow rows
+// from ky0); gather of the current window from it; batch power spectrum
+hipError_t launch_spec(const KArgs& a, float2* spec, int nrow, int nb, hipStream_t s);
+hipError_t launch_gather(const KArgs& a, const float2* spec, int bxe, int nrow, const int* offj, const int* offi,
+                         int nb, hipStream_t s);
+hipError_t launch_psum(const float2* spec, int nb, int npol, size_t plane, float* pw, hipStream_t s);
 // HG tables: out[k][n] in FP32 and, if the split pointers are non-null, the
 // packed hi/lo tables (bf16, and fp16 of the value times fp16_scale)
 hipError_t launch_hg(double pitch, int w, int wpad, double waist, int G, int gp, float* out,

@@ -181,6 +181,111 @@ __global__ void __launch_bounds__(kTPB) k_col(KArgs A, int b0) {
 }
 
 // ---------------------------------------------------------------------------
+// Alignment: the spectrum around the cross term is computed once per batch
+// and kept; every trial of tilt / defocus / waist re-runs only the window
+// gather, the IFFTs and the overlap from it.
+//
+// k_spec: grid (ceil(bx / CG), npol, nb): FFT along y of CG columns of the
+// (extended) row-pass result, rows v' = ky0 + i (mod NY), i < nrow, stored
+// to spec[b][p][j][i].
+template <int NY, int CG>
+__global__ void __launch_bounds__(kTPB) k_spec(KArgs A, float2* __restrict__ spec, int nrow) {
+  using LN = Lds<NY>;
+  using Q = Pass1<NY, CG, kTPB>;
+  constexpr int ST = LN::STRIDE;
+  __shared__ float2 buf[CG * ST];
+  const int tid = threadIdx.x;
+  const int p = blockIdx.y;
+  const int bl = blockIdx.z;
+  const PolTab& P = A.pol[p];
+  const int jc0 = blockIdx.x * CG;
+  const float2* in = A.t1 + ((size_t)(bl * A.npol + p) * A.bx) * NY;
+  {
+    float2 v[Q::IT][Q::R0];
+#pragma unroll
+    for (int it = 0; it < Q::IT; ++it) {
+      const int g = tid + it * kTPB;
+      const int c = g / Q::NB, b = g % Q::NB;
+      const int j = jc0 + c;
+      const bool ok = (Q::TOTAL % kTPB == 0 || g < Q::TOTAL) && j < A.bx;
+      const float2* col = in + (size_t)j * NY + b;
+#pragma unroll
+      for (int r = 0; r < Q::R0; ++r) v[it][r] = ok ? col[r * Q::NB] : make_float2(0.f, 0.f);
+    }
+    fft_pass1_regs<NY, CG, ST, kTPB>(v, buf, tid);
+  }
+  fft_rest<NY, CG, ST, kTPB>(buf, A.tw_ny, tid);
+  for (int c = 0; c < CG; ++c) {
+    const int j = jc0 + c;
+    if (j >= A.bx) break;
+    float2* o = spec + ((size_t)(bl * A.npol + p) * A.bx + j) * nrow;
+    for (int i = tid; i < nrow; i += kTPB) {
+      int vv = (P.ky0 + i) % NY;
+      if (vv < 0) vv += NY;
+      o[i] = buf[c * ST + LN::at(vv)];
+    }
+  }
+}
+
+// k_gather: grid (ceil(bx / CG), npol, nb): the window of the current plan
+// gathered from the stored spectrum (box column j, row i of pol p at spectrum
+// column offj[p] + j, row offi[p] + i), then the IFFT along y, as in k_col.
+struct SpecRef {
+  const float2* spec;
+  int bxe, nrow;
+  int offj[2], offi[2];
+};
+
+template <int WY, int CG>
+__global__ void __launch_bounds__(kTPB) k_gather(KArgs A, SpecRef S) {
+  using LW = Lds<WY>;
+  constexpr int ST = LW::STRIDE;
+  __shared__ float2 buf[CG * ST];
+  const int tid = threadIdx.x;
+  const int p = blockIdx.y;
+  const int bl = blockIdx.z;
+  const PolTab& P = A.pol[p];
+  const int jc0 = blockIdx.x * CG;
+  const float2* sp = S.spec + (size_t)(bl * A.npol + p) * S.bxe * S.nrow;
+  for (int e = tid; e < CG * WY; e += kTPB) {
+    const int c = e / WY, q = e % WY;
+    const int j = jc0 + c;
+    const int i = P.qrow[q];
+    float2 val = make_float2(0.f, 0.f);
+    if (i >= 0 && j < A.bx) {
+      const int2 mr = P.mrow[i];
+      if (j >= mr.x && j <= mr.y) {
+        const float2 f = sp[(size_t)(S.offj[p] + j) * S.nrow + S.offi[p] + i];
+        val = cmul(f, conjf2(cmul(P.rhox[j], P.rhoy[i])));
+      }
+    }
+    buf[c * ST + LW::at(q)] = val;
+  }
+  __syncthreads();
+  fft_lds<WY, CG, ST, kTPB>(buf, A.tw_wy, tid);
+  float2* out = A.f2 + ((size_t)(bl * A.npol + p) * WY) * A.bxp;
+  for (int e = tid; e < CG * WY; e += kTPB) {
+    const int c = e % CG, l = e / CG;
+    const int j = jc0 + c;
+    if (j < A.bx) out[(size_t)l * A.bxp + j] = conjf2(buf[c * ST + LW::at(l)]);
+  }
+}
+
+// k_psum: pw[p][j][i] = sum over frames of |spec[b][p][j][i]|^2
+__global__ void k_psum(const float2* __restrict__ spec, int nb, int npol, size_t plane, float* __restrict__ pw) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= npol * plane) return;
+  const int p = (int)(e / plane);
+  const size_t k = e - (size_t)p * plane;
+  float s = 0.f;
+  for (int b = 0; b < nb; ++b) {
+    const float2 v = spec[((size_t)b * npol + p) * plane + k];
+    s = fmaf(v.x, v.x, fmaf(v.y, v.y, s));
+  }
+  pw[e] = s;
+}
+
+// ---------------------------------------------------------------------------
 // k_fld: grid (nblk, npol, nb); one block of 16 field rows per workgroup,
 // 4 waves: x-IFFT of the 16 rows, tilt/defocus removal, then the separable
 // HG overlap as two real MFMA contractions: T = E Ux over this wave's share
@@ -264,6 +369,7 @@ __global__ void __launch_bounds__(kTPB) k_fld(KArgs A, int b0) {
   __shared__ float2 buf[16 * ST];
   __shared__ float red[4][NPAIR][2][256];
   __shared__ float bmax[4];
+  __shared__ float bpow[4];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const int rb = blockIdx.x;
@@ -302,6 +408,17 @@ __global__ void __launch_bounds__(kTPB) k_fld(KArgs A, int b0) {
   if constexpr (PREC == 2) {
     emax = wave_max(emax);
     if (lane == 0) bmax[wv] = emax;
+  }
+  if (A.capt) {
+    // field power of the block, sum |E|^2 (FP32 within a block)
+    float pw = 0.f;
+    for (int e = tid; e < 16 * WX; e += kTPB) {
+      const float2 ev = buf[(e / WX) * ST + L::at(e % WX)];
+      pw = fmaf(ev.x, ev.x, fmaf(ev.y, ev.y, pw));
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) pw += __shfl_xor(pw, off, 64);
+    if (lane == 0) bpow[wv] = pw;
   }
   __syncthreads();
   if constexpr (PREC == 2) sE = fp16_prescale(fmaxf(fmaxf(bmax[0], bmax[1]), fmaxf(bmax[2], bmax[3])));
@@ -414,7 +531,9 @@ __global__ void __launch_bounds__(kTPB) k_fld(KArgs A, int b0) {
   __syncthreads();
   // partial[bl][rb][p][mode]: this block's share of every coefficient, the
   // four waves summed in order
-  float2* part = A.partial + ((size_t)(bl * A.nblk + rb) * A.npol + p) * A.nmodes;
+  const int pstride = A.nmodes + 1;
+  float2* part = A.partial + ((size_t)(bl * A.nblk + rb) * A.npol + p) * pstride;
+  if (tid == 0) part[A.nmodes] = make_float2(A.capt ? ((bpow[0] + bpow[1]) + bpow[2]) + bpow[3] : 0.f, 0.f);
   for (int i = tid; i < A.nmodes; i += kTPB) {
     const short2 mn = A.modes[i];
     const int m = mn.x, n = mn.y;
@@ -431,20 +550,24 @@ __global__ void __launch_bounds__(kTPB) k_fld(KArgs A, int b0) {
 // and the normalised coefficients.
 __global__ void __launch_bounds__(kTPB) k_norm(KArgs A, int b0) {
   __shared__ double wsum[kTPB / 64];
+  __shared__ double wpol[kTPB / 64][2];
   const int bl = blockIdx.x, tid = threadIdx.x;
   const int bg = b0 + bl;
   const int per = A.npol * A.nmodes;
+  const int pstride = A.nmodes + 1;                 // partial: modes + the block's field power
+  const int bstride = A.npol * pstride;
   float2* raw = A.coefs + (size_t)bg * per;
-  const float2* part = A.partial + (size_t)bl * A.nblk * per;
-  double s = 0.0;
+  const float2* part = A.partial + (size_t)bl * A.nblk * bstride;
+  double s = 0.0, spol0 = 0.0, spol1 = 0.0;
   for (int i = tid; i < per; i += kTPB) {
+    const int p = i / A.nmodes, md = i - p * A.nmodes;
     float re = 0.f, im = 0.f;
     // blocks summed in order, eight loads in flight at a time
     for (int rb0 = 0; rb0 < A.nblk; rb0 += 8) {
       float2 v[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u)
-        v[u] = (rb0 + u < A.nblk) ? part[(size_t)(rb0 + u) * per + i] : make_float2(0.f, 0.f);
+        v[u] = (rb0 + u < A.nblk) ? part[(size_t)(rb0 + u) * bstride + p * pstride + md] : make_float2(0.f, 0.f);
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         re += v[u].x;
@@ -452,12 +575,30 @@ __global__ void __launch_bounds__(kTPB) k_norm(KArgs A, int b0) {
       }
     }
     raw[i] = make_float2(re, im);
-    s += (double)re * re + (double)im * im;
+    const double pw = (double)re * re + (double)im * im;
+    s += pw;
+    if (p == 0) spol0 += pw; else spol1 += pw;
   }
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-  if ((tid & 63) == 0) wsum[tid >> 6] = s;
+  for (int off = 32; off > 0; off >>= 1) {
+    s += __shfl_xor(s, off, 64);
+    spol0 += __shfl_xor(spol0, off, 64);
+    spol1 += __shfl_xor(spol1, off, 64);
+  }
+  if ((tid & 63) == 0) {
+    wsum[tid >> 6] = s;
+    wpol[tid >> 6][0] = spol0;
+    wpol[tid >> 6][1] = spol1;
+  }
   __syncthreads();
+  if (A.capt && tid < A.npol) {
+    // captured power of pol tid: mode power and field power (blocks in order, FP64)
+    double mp = 0.0, fp = 0.0;
+    for (int w = 0; w < kTPB / 64; ++w) mp += wpol[w][tid];
+    for (int rb = 0; rb < A.nblk; ++rb) fp += (double)part[(size_t)rb * bstride + tid * pstride + A.nmodes].x;
+    A.capt[((size_t)bg * A.npol + tid) * 2 + 0] = mp;
+    A.capt[((size_t)bg * A.npol + tid) * 2 + 1] = fp * A.cell;
+  }
   double tot = 0.0;
 #pragma unroll
   for (int w = 0; w < kTPB / 64; ++w) tot += wsum[w];
@@ -612,6 +753,45 @@ hipError_t launch_fld(const KArgs& a, int b0, int nb, hipStream_t s) {
 #undef X
   return hipErrorInvalidValue;
 }
+template <int NY>
+static hipError_t spec_n(const KArgs& a, float2* spec, int nrow, int nb, hipStream_t s) {
+  constexpr int CG = col_cg<NY>();
+  dim3 grid((a.bx + CG - 1) / CG, a.npol, nb);
+  hipLaunchKernelGGL((k_spec<NY, CG>), grid, dim3(kTPB), 0, s, a, spec, nrow);
+  return hipGetLastError();
+}
+
+hipError_t launch_spec(const KArgs& a, float2* spec, int nrow, int nb, hipStream_t s) {
+#define X(N) if (a.ny == N) return spec_n<N>(a, spec, nrow, nb, s);
+  DH_FFT_SIZES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+template <int WY>
+static hipError_t gather_w(const KArgs& a, const float2* spec, int bxe, int nrow, const int* offj, const int* offi,
+                           int nb, hipStream_t s) {
+  constexpr int CG = 8;
+  SpecRef r{spec, bxe, nrow, {offj[0], offj[1]}, {offi[0], offi[1]}};
+  dim3 grid((a.bx + CG - 1) / CG, a.npol, nb);
+  hipLaunchKernelGGL((k_gather<WY, CG>), grid, dim3(kTPB), 0, s, a, r);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const KArgs& a, const float2* spec, int bxe, int nrow, const int* offj, const int* offi,
+                         int nb, hipStream_t s) {
+#define X(W) if (a.wy == W) return gather_w<W>(a, spec, bxe, nrow, offj, offi, nb, s);
+  DH_IFFT_SIZES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_psum(const float2* spec, int nb, int npol, size_t plane, float* pw, hipStream_t s) {
+  const size_t n = (size_t)npol * plane;
+  hipLaunchKernelGGL(k_psum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, spec, nb, npol, plane, pw);
+  return hipGetLastError();
+}
+
 hipError_t launch_norm(const KArgs& a, int b0, int nb, hipStream_t s) {
   hipLaunchKernelGGL(k_norm, dim3(nb), dim3(kTPB), 0, s, a, b0);
   return hipGetLastError();

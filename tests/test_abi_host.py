@@ -98,7 +98,8 @@ def test_plan_geometry_matches_oracle(idx, cam):
         assert math.isclose(info.ax[pol], gp["ax"], rel_tol=1e-14)
         cols = gp["us"][gp["mask"].any(axis=0)]
         bw = max(bw, cols.max() - cols.min() + 1)
-    assert info.box_w == bw
+    # the box is the fixed bound floor(2r)+1 of every window position
+    assert info.box_w == math.floor(2 * g["rx"]) + 1 >= bw
     assert info.device_bytes > 0 and info.chunk >= 1
 
 

@@ -196,3 +196,79 @@ def test_precision_report_per_result():
         _say("precision report recipe %d %-10s max %.2e p99 %.2e" % r)
     for idx, prec, mx, _ in rows:
         assert mx <= (TOL if prec == "fp32" else TOL_SPLIT), (idx, prec, mx)
+
+
+# ---------------------------------------------------------------- alignment
+def _align_plan(params, f):
+    torch = _torch()
+    import paper_2204_02348_amd as dh
+    plan = dh.Plan(params, max_batch=f.shape[0])
+    ft = torch.from_numpy(np.ascontiguousarray(f)).cuda()
+    return dh, plan, ft
+
+
+def test_alignment_goal_matches_oracle():
+    cfg = dh_synth.config(4)
+    f, _ = dh_synth.make_frames(cfg, n_frames=3)
+    truth = cfg["truth"]
+    off = dict(truth, tilt_deg=[[truth["tilt_deg"][0][0] + 0.01, truth["tilt_deg"][0][1]], truth["tilt_deg"][1]],
+               defocus=[truth["defocus"][0], truth["defocus"][1] + 0.03], waist=truth["waist"] * 1.02)
+    for p in (truth, off):
+        _say("alignment goal parity", p["tilt_deg"], p["defocus"], p["waist"])
+        dh, plan, ft = _align_plan(p, f)
+        g = plan.autoalign(ft, f.shape[0], mode=dh.ALIGN_TWEAK, what=0)
+        ref = oracle.goal_db(f, p)
+        plan.destroy()
+        _say("goal gpu %.7f dB oracle %.7f dB" % (g, ref))
+        assert abs(10 ** (g / 10) - 10 ** (ref / 10)) <= 1e-5 * 10 ** (ref / 10)
+
+
+def test_alignment_snap_finds_the_tilt():
+    cfg = dh_synth.config(4)
+    f, _ = dh_synth.make_frames(cfg, n_frames=10)
+    dh, plan, ft = _align_plan(cfg["params"], f)
+    _say("alignment snap from nominal")
+    plan.autoalign(ft, f.shape[0], mode=dh.ALIGN_ESTIMATE, what=dh.ALIGN_TILT)
+    got = plan.params()["tilt_deg"]
+    plan.destroy()
+    bins = [1565e-9 / (512 * 20e-6) / oracle.DEG, 1565e-9 / (1024 * 20e-6) / oracle.DEG]
+    for q in range(2):
+        for a in range(2):
+            err = abs(got[q][a] - cfg["truth"]["tilt_deg"][q][a]) / bins[a]
+            _say("snap pol %d axis %d error %.2f bins" % (q, a, err))
+            assert err < 3.0
+
+
+def test_alignment_recovers_truth_and_then_processes():
+    cfg = dh_synth.config(4)
+    n = 20
+    f, _ = dh_synth.make_frames(cfg, n_frames=n)
+    truth = cfg["truth"]
+    dh, plan, ft = _align_plan(cfg["params"], f)
+    _say("alignment full from nominal, %d frames" % n)
+    g = plan.autoalign(ft, n, mode=dh.ALIGN_FULL, what=dh.ALIGN_TILT | dh.ALIGN_DEFOCUS | dh.ALIGN_WAIST, tol=1e-5)
+    rep = plan.align_report()
+    got = plan.params()
+    bins = [1565e-9 / (512 * 20e-6) / oracle.DEG, 1565e-9 / (1024 * 20e-6) / oracle.DEG]
+    _say("goal %.5f dB (after snap %.5f), %d trials, %d sweeps" % (g, rep.start_goal_db, rep.evaluations, rep.sweeps))
+    for q in range(2):
+        _say("pol %d tilt err %.3f / %.3f bins, defocus err %.4f D" % (
+            q, (got["tilt_deg"][q][0] - truth["tilt_deg"][q][0]) / bins[0],
+            (got["tilt_deg"][q][1] - truth["tilt_deg"][q][1]) / bins[1], got["defocus"][q] - truth["defocus"][q]))
+    _say("waist err %.4f %%" % (100 * (got["waist"] / truth["waist"] - 1)))
+    ref_truth = oracle.goal_db(f, truth, indices=range(4))
+    _say("oracle goal at the truth (4 frames) %.5f dB" % ref_truth)
+    for q in range(2):
+        assert abs(got["tilt_deg"][q][0] - truth["tilt_deg"][q][0]) < 0.3 * bins[0]
+        assert abs(got["tilt_deg"][q][1] - truth["tilt_deg"][q][1]) < 0.3 * bins[1]
+        assert abs(got["defocus"][q] - truth["defocus"][q]) < 0.01
+    assert abs(got["waist"] / truth["waist"] - 1) < 0.01
+    # the aligned plan processes frames; its coefficients match the oracle at the aligned parameters
+    aligned = dict(truth, tilt_deg=got["tilt_deg"], defocus=got["defocus"], waist=got["waist"])
+    plan.process(ft, n, None)
+    coefs = plan.coefs(False)
+    plan.destroy()
+    for i in (0, n - 1):
+        ref = oracle.process_frame(f[i].astype(np.float64), aligned)["coefs"]
+        for pol in range(2):
+            assert _rel(coefs[i][pol].astype(np.complex128), ref[pol]) <= TOL

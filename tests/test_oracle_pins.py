@@ -296,3 +296,19 @@ def test_swapping_pol_halves_swaps_outputs():
     q = dict(p, tilt_deg=p["tilt_deg"][::-1], defocus=p["defocus"][::-1])
     r2 = oracle.process_frame(sw, q)
     assert np.allclose(r2["coefs"][::-1], r["coefs"], rtol=0, atol=1e-9 * np.abs(r["coefs"]).max())
+
+
+# ---------------------------------------------------------------- alignment goal
+def test_captured_power_is_one_at_the_truth_and_drops_off_it():
+    cfg = dh_synth.config(4)
+    truth = cfg["truth"]
+    f, _ = dh_synth.make_frames(dict(cfg, noise=False), n_frames=1, quantise=False)
+    mp, fp = oracle.captured_power(f[0], truth)
+    assert np.all(np.abs(mp / fp - 1.0) < 1e-9)          # the field is exactly in the basis span
+    g0 = oracle.goal_db(f, truth)
+    assert abs(g0) < 1e-8
+    bin_deg = 1565e-9 / (512 * 20e-6) / oracle.DEG
+    for change in [dict(tilt_deg=[[truth["tilt_deg"][0][0] + bin_deg, truth["tilt_deg"][0][1]], truth["tilt_deg"][1]]),
+                   dict(defocus=[truth["defocus"][0] + 0.05, truth["defocus"][1]]),
+                   dict(waist=truth["waist"] * 1.05)]:
+        assert oracle.goal_db(f, dict(truth, **change)) < -1e-3
