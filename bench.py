@@ -88,6 +88,105 @@ def time_forms(dh, torch, cfg, ft, B, stream, steps=10, warmup=3):
     return out
 
 
+def serving_bench(dh, torch, workers, seconds=10.0, warm=1.0, rate=5000.0, seed=220402348):
+    """Serving form on the four uint16 cameras: Poisson arrivals at `rate` per
+    camera from resident pools of 64 frames, continuous batching (lanes admitted
+    by a 16 GiB budget, hipGraph launches). Latency = completion - arrival for
+    requests arriving after the warm-up; plus the saturated rate (all requests
+    at once) next to a loop that processes one request at a time."""
+    cams = [dh_synth.config(3, c) for c in range(4)]
+    pools = []
+    for cfg in cams:
+        f, _ = dh_synth.make_frames(cfg, n_frames=64, workers=workers)
+        pools.append(torch.from_numpy(f).to("cuda:0"))
+    plans = [dh.Plan(cfg["params"], max_batch=256) for cfg in cams]
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(seed)
+    ts, cs, ps = [], [], []
+    for c in range(4):
+        t = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * (seconds + warm) * 1.2)))
+        t = t[t < seconds + warm]
+        ts.append(t)
+        cs.append(np.full(t.size, c, dtype=np.int32))
+        idx = rng.integers(0, 64, size=t.size)
+        base = pools[c].data_ptr()
+        ps.append(base + idx.astype(np.uint64) * np.uint64(pools[c][0].nbytes))
+    order = np.argsort(np.concatenate(ts), kind="stable")
+    t = np.concatenate(ts)[order]
+    cam = np.concatenate(cs)[order]
+    ptr = np.concatenate(ps)[order]
+    out = {"workload": "4 cameras uint16 (320x256 G5, 640x512 G9, 1024^2 G15, 2048^2 G20), 1 pol each, "
+                       f"Poisson {rate:.0f} frames/s per camera, {warm:.0f} s warm-up + {seconds:.0f} s measured"}
+    srv = dh.Server(plans, max_batch=256, hbm_budget=16 << 30, use_graphs=True)
+    out["lanes"] = [srv.info(c)[0] for c in range(4)]
+    done = srv.replay(t, cam, ptr)
+    b, f = srv.stats()
+    lat = (done - t) * 1e3
+    m = t >= warm
+    out["frames_per_s"] = round(float(m.sum() / (done[m].max() - warm)), 1)
+    out["p50_ms"] = round(float(np.percentile(lat[m], 50)), 4)
+    out["p99_ms"] = round(float(np.percentile(lat[m], 99)), 4)
+    out["per_camera"] = {str(c): {"p50_ms": round(float(np.percentile(lat[m & (cam == c)], 50)), 4),
+                                  "p99_ms": round(float(np.percentile(lat[m & (cam == c)], 99)), 4),
+                                  "frames": int((m & (cam == c)).sum())} for c in range(4)}
+    out["mean_batch"] = round(f / max(b, 1), 2)
+    # saturation: every request of a 20000-request trace present at once
+    n = 20000
+    tz = np.zeros(n)
+    done = srv.replay(tz, cam[:n], ptr[:n])
+    out["saturated_frames_per_s"] = round(n / float(done.max()), 1)
+    srv.destroy()
+    # the same 20000 requests one at a time through dh_process_batch (batch 1, waiting for each)
+    t0 = time.perf_counter()
+    for k in range(2000):
+        c = int(cam[k])
+        plans[c].process(int(ptr[k]), 1, None)
+        plans[c].coefs(True)
+    out["one_at_a_time_frames_per_s"] = round(2000 / (time.perf_counter() - t0), 1)
+    for p in plans:
+        p.destroy()
+    return out
+
+
+def alignment_bench(dh, torch, workers, align_frames=50, decomp_frames=5000):
+    """Alignment workload: align 50 frames 1024x1024 (2 pols, G=30) from the
+    nominal tilt/defocus/waist, then decompose 5000 frames (a pool of 250
+    distinct frames tiled x20) at the aligned parameters."""
+    cfg = dh_synth.config(4)
+    truth = cfg["truth"]
+    pool, _ = dh_synth.make_frames(cfg, n_frames=250, workers=workers)
+    dev = torch.from_numpy(pool).to("cuda:0")
+    frames = dev.repeat(decomp_frames // 250, 1, 1)
+    plan = dh.Plan(cfg["params"], max_batch=decomp_frames)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    goal = plan.autoalign(frames, align_frames, dh.ALIGN_FULL, dh.ALIGN_TILT | dh.ALIGN_DEFOCUS | dh.ALIGN_WAIST, 1e-5)
+    wall = time.perf_counter() - t0
+    rep = plan.align_report()
+    got = plan.params()
+    bins = [1565e-9 / (512 * 20e-6) * 180 / np.pi, 1565e-9 / (1024 * 20e-6) * 180 / np.pi]
+    out = {"workload": "align 50 frames 1024x1024 f32, 2 pols, G=30 from nominal; decompose 5000 frames",
+           "align_wall_s": round(wall, 4), "goal_db": round(goal, 6), "trials": rep.evaluations,
+           "sweeps": rep.sweeps,
+           "tilt_err_bins": [[round((got["tilt_deg"][q][a] - truth["tilt_deg"][q][a]) / bins[a], 4)
+                              for a in range(2)] for q in range(2)],
+           "defocus_err_D": [round(got["defocus"][q] - truth["defocus"][q], 5) for q in range(2)],
+           "waist_err_pct": round(100 * (got["waist"] / truth["waist"] - 1), 3)}
+    stream = torch.cuda.Stream()
+    for _ in range(2):
+        plan.process(frames, decomp_frames, stream)
+    stream.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(5):
+        plan.process(frames, decomp_frames, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    out["decompose_frames_per_s"] = round(5 * decomp_frames / (e0.elapsed_time(e1) / 1e3), 1)
+    plan.destroy()
+    return out
+
+
 def cpu_baseline(cfg, frames, seconds):
     """The FP64 oracle, as it stands, on a bounded sample of the same frames."""
     import oracle
@@ -118,6 +217,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the FP32 / split BF16 / split FP16 comparison")
+    ap.add_argument("--no-serving", action="store_true", help="skip the four-camera serving run")
+    ap.add_argument("--no-align", action="store_true", help="skip the alignment workload")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device-to-device copy of 512 MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -203,6 +304,13 @@ def main():
     plan.destroy()
     if not args.no_forms:
         out["forms"] = time_forms(dh, torch, cfg, ft, B, stream)
+    del ft
+    if not args.no_serving:
+        out["serving"] = serving_bench(dh, torch, workers)
+        print("[bench] serving done", file=sys.stderr, flush=True)
+    if not args.no_align:
+        out["alignment"] = alignment_bench(dh, torch, workers)
+        print("[bench] alignment done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, frames, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -232,6 +232,51 @@ typedef struct dh_align_report {
 /* Report of the last dh_autoalign on h. */
 int dh_get_align_report(dh_handle h, dh_align_report* out);
 
+/*
+ * Serving form: continuous batching of frames from several cameras, each a
+ * resident plan (tables, bases and alignment state stay on the device).
+ *
+ * dh_serve_create: a server over `ncam` plans (their handles stay owned by the
+ * caller and must outlive the server). Every camera gets "lanes" - in-flight
+ * batch slots of up to max_batch frames, each with its own HIP stream,
+ * workspace, frame-pointer array and pinned result buffer - made round robin
+ * over the cameras while their device bytes fit hbm_budget (0: no limit;
+ * at least one lane per camera, else DH_ERR_MEMORYALLOCATION; at most four).
+ * use_graphs: capture each lane's launch sequence once per batch size as a
+ * hipGraph and replay it. normalised: results are the power-normalised
+ * coefficients (else raw). Writes the server handle to *out.
+ *
+ * Admission: a request waits in its camera's queue until a lane of that
+ * camera is free; the lane then takes every waiting request (up to max_batch)
+ * as one batch. Batches therefore grow with the load, requests that arrive
+ * while others are on the GPU start as soon as a lane frees up, and the lanes
+ * of all cameras run concurrently. Each frame's result does not depend on the
+ * batch it ran in (no reductions across frames).
+ *
+ * dh_serve_submit: queue one frame (device pointer, the camera's frame layout
+ * and dtype, kept unchanged until its result is done); when it completes its
+ * [pol][mode] coefficients are copied to `result` (host, may be NULL).
+ * dh_serve_progress: one scheduling round from the calling thread - retire
+ * finished batches, start batches on free lanes; *completed = requests done.
+ * dh_serve_replay: drive the loop in real time over a trace of n requests:
+ * request i arrives t_arrival[i] seconds after the call starts (ascending),
+ * for camera[i], frame frames[i], result results[i] (results may be NULL);
+ * returns when all are done with t_done[i] = completion time (same clock).
+ * dh_serve_info / dh_serve_stats: lanes and bytes per camera; batches and
+ * frames processed. dh_serve_destroy: waits for the device, frees the lanes.
+ * One host thread drives a server at a time.
+ */
+typedef int dh_server;
+int dh_serve_create(const dh_handle* plans, int ncam, int max_batch, size_t hbm_budget, int use_graphs,
+                    int normalised, dh_server* out);
+int dh_serve_info(dh_server s, int camera, int* lanes, size_t* lane_bytes, int* per_result);
+int dh_serve_submit(dh_server s, int camera, const void* frame, dh_c64* result);
+int dh_serve_progress(dh_server s, int* completed);
+int dh_serve_replay(dh_server s, int n, const double* t_arrival, const int* camera, const void* const* frames,
+                    dh_c64* const* results, double* t_done, double* t_start);
+int dh_serve_stats(dh_server s, long long* batches, long long* frames);
+int dh_serve_destroy(dh_server s);
+
 /* Error code of the last failing call on h (0 if none), 2 for a bad handle. */
 int dh_last_error(dh_handle h);
 

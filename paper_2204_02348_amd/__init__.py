@@ -36,7 +36,9 @@ PREC_SPLIT_FP16 = 2
 
 EXPORTS = ["dh_plan_check", "dh_plan", "dh_process_batch", "dh_mode_coefs", "dh_get_window",
            "dh_get_fields", "dh_get_params", "dh_get_plan_info", "dh_set_stage_timing", "dh_stage_times",
-           "dh_autoalign", "dh_get_align_report", "dh_last_error", "dh_destroy"]
+           "dh_autoalign", "dh_get_align_report", "dh_serve_create", "dh_serve_info", "dh_serve_submit",
+           "dh_serve_progress", "dh_serve_replay", "dh_serve_stats", "dh_serve_destroy",
+           "dh_last_error", "dh_destroy"]
 ALIGN_FULL, ALIGN_TWEAK, ALIGN_ESTIMATE = 0, 1, 2
 ALIGN_TILT, ALIGN_DEFOCUS, ALIGN_WAIST, ALIGN_CENTRE = 1, 2, 4, 8
 STAGES = ["fft_x", "fft_y_crop_ifft_y", "ifft_x_tilt_overlap", "power_norm"]
@@ -101,6 +103,15 @@ def lib():
         L.dh_stage_times.argtypes = [C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)]
         L.dh_autoalign.argtypes = [C.c_int, C.c_void_p, C.c_int, C.c_int, C.c_uint, C.c_float, C.c_void_p]
         L.dh_get_align_report.argtypes = [C.c_int, C.POINTER(AlignReport)]
+        L.dh_serve_create.argtypes = [C.POINTER(C.c_int), C.c_int, C.c_int, C.c_size_t, C.c_int, C.c_int,
+                                      C.POINTER(C.c_int)]
+        L.dh_serve_info.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_size_t), C.POINTER(C.c_int)]
+        L.dh_serve_submit.argtypes = [C.c_int, C.c_int, C.c_void_p, C.c_void_p]
+        L.dh_serve_progress.argtypes = [C.c_int, C.POINTER(C.c_int)]
+        L.dh_serve_replay.argtypes = [C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.c_void_p]
+        L.dh_serve_stats.argtypes = [C.c_int, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]
+        L.dh_serve_destroy.argtypes = [C.c_int]
         L.dh_last_error.argtypes = [C.c_int]
         L.dh_destroy.argtypes = [C.c_int]
         for name in EXPORTS:
@@ -274,6 +285,76 @@ class Plan:
     def destroy(self):
         if getattr(self, "handle", -1) >= 0:
             lib().dh_destroy(self.handle)
+            self.handle = -1
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+class Server:
+    """dh_serve_*: continuous batching over several camera plans."""
+
+    def __init__(self, plans, max_batch: int = 256, hbm_budget: int = 0, use_graphs: bool = True,
+                 normalised: bool = True):
+        hs = (C.c_int * len(plans))(*[p.handle for p in plans])
+        h = C.c_int(-1)
+        rc = lib().dh_serve_create(hs, len(plans), max_batch, hbm_budget, int(use_graphs), int(normalised),
+                                   C.byref(h))
+        if rc != SUCCESS:
+            raise DhError(rc, "dh_serve_create")
+        self.handle = h.value
+        self.plans = list(plans)
+
+    def info(self, camera: int):
+        lanes, nbytes, per = C.c_int(), C.c_size_t(), C.c_int()
+        rc = lib().dh_serve_info(self.handle, camera, C.byref(lanes), C.byref(nbytes), C.byref(per))
+        if rc != SUCCESS:
+            raise DhError(rc, "dh_serve_info")
+        return lanes.value, nbytes.value, per.value
+
+    def replay(self, t_arrival, camera, frame_ptrs, results=None) -> np.ndarray:
+        """Real-time replay of a request trace; returns completion times (s).
+        results: optional list of complex64 host arrays, one per request."""
+        t = np.ascontiguousarray(t_arrival, dtype=np.float64)
+        cam = np.ascontiguousarray(camera, dtype=np.int32)
+        fp = np.ascontiguousarray(frame_ptrs, dtype=np.uint64)
+        n = t.size
+        done = np.zeros(n, dtype=np.float64)
+        outs = None
+        if results is not None:
+            outs = np.array([r.ctypes.data for r in results], dtype=np.uint64)
+        rc = lib().dh_serve_replay(self.handle, n, t.ctypes.data, cam.ctypes.data, fp.ctypes.data,
+                                   outs.ctypes.data if outs is not None else None, done.ctypes.data, None)
+        if rc != SUCCESS:
+            raise DhError(rc, "dh_serve_replay")
+        return done
+
+    def submit(self, camera: int, frame, result=None):
+        rc = lib().dh_serve_submit(self.handle, camera, C.c_void_p(_ptr(frame)),
+                                   None if result is None else result.ctypes.data)
+        if rc != SUCCESS:
+            raise DhError(rc, "dh_serve_submit")
+
+    def progress(self) -> int:
+        n = C.c_int()
+        rc = lib().dh_serve_progress(self.handle, C.byref(n))
+        if rc != SUCCESS:
+            raise DhError(rc, "dh_serve_progress")
+        return n.value
+
+    def stats(self):
+        b, f = C.c_longlong(), C.c_longlong()
+        rc = lib().dh_serve_stats(self.handle, C.byref(b), C.byref(f))
+        if rc != SUCCESS:
+            raise DhError(rc, "dh_serve_stats")
+        return b.value, f.value
+
+    def destroy(self):
+        if getattr(self, "handle", -1) >= 0:
+            lib().dh_serve_destroy(self.handle)
             self.handle = -1
 
     def __del__(self):

@@ -5,6 +5,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
+#include <chrono>
+#include <deque>
+#include <map>
 #include <cmath>
 #include <complex>
 #include <cstdint>
@@ -242,6 +245,7 @@ struct Plan {
   char* amem = nullptr;
   size_t amem_bytes = 0;
   dh_align_report rep{};
+  int version = 0;                   // bumped whenever the tables are rebuilt
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
   std::vector<int> ev_stage;         // stage of launch i (events 2i, 2i+1)
@@ -304,6 +308,7 @@ double hg_fp16_scale(double waist, double pitch) {
 }
 
 int build_tables(Plan* pl, bool hg = true) {
+  ++pl->version;
   const Geom& g = pl->g;
   const dh_params* p = &pl->params;
   const Layout& L = pl->L;
@@ -396,6 +401,7 @@ void fill_kargs(Plan* pl, int w) {
   a.s_uh = pl->s_uh;
   a.capt = nullptr;
   a.cell = g.pxp * g.pyp;
+  a.fptr = nullptr;
   for (int q = 0; q < p->pol_count; ++q) {
     const PolGeom& P = g.pol[q];
     dh::PolTab& t = a.pol[q];
@@ -962,3 +968,352 @@ extern "C" int dh_get_align_report(dh_handle h, dh_align_report* out) {
   *out = pl->rep;
   return DH_SUCCESS;
 }
+
+// ---------------------------------------------------------------------------
+// Serving: continuous batching of frames from several cameras.
+//
+// Each camera is a resident plan (tables, HG bases, alignment state stay on
+// the device). Its "lanes" are independent in-flight batch slots: a HIP
+// stream, a workspace for up to max_batch frames, a device array of frame
+// pointers and pinned result buffers. As many lanes are made as the HBM budget
+// allows (at least one, at most four per camera). A request waits in its
+// camera's queue until a lane of that camera is free; the lane then takes
+// every waiting request (up to max_batch) as one batch, so batches grow with
+// the load and requests that arrive while others are on the GPU join the next
+// free lane. Lanes of all cameras run concurrently on the device. The launch
+// sequence of a batch is captured once per (lane, batch size) as a hipGraph
+// and replayed.
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Req {
+  const void* frame;
+  dh_c64* out;
+  int idx;
+};
+
+struct Lane {
+  int version = -1;              // plan version the arguments and graphs were made for
+  size_t off[6] = {0, 0, 0, 0, 0, 0};
+  hipStream_t s = nullptr;
+  hipEvent_t done = nullptr;
+  char* mem = nullptr;
+  const void** hptr = nullptr;   // pinned host copy of the frame pointers
+  float2* hres = nullptr;        // pinned host results
+  dh::KArgs k{};
+  std::vector<Req> batch;
+  bool busy = false;
+  std::map<int, hipGraphExec_t> graphs;
+};
+
+struct Camera {
+  Plan* pl = nullptr;
+  std::deque<Req> pending;
+  std::vector<Lane> lanes;
+  size_t lane_bytes = 0;
+  int per_result = 0;            // complex values per request: pols x modes
+};
+
+struct Server {
+  std::vector<Camera> cams;
+  int max_batch = 1;
+  bool graphs = true, normalised = true;
+  Clock::time_point t0;
+  double* t_done = nullptr;      // replay: completion time per request index
+  long long batches = 0, frames = 0;
+  int last_error = 0;
+};
+
+std::mutex g_smu;
+std::vector<Server*> g_servers;
+
+Server* sget(dh_server h) {
+  std::lock_guard<std::mutex> lk(g_smu);
+  if (h < 0 || (size_t)h >= g_servers.size()) return nullptr;
+  return g_servers[h];
+}
+
+size_t lane_layout(const Plan* pl, int mb, size_t off[6]) {
+  const Geom& g = pl->g;
+  const size_t P = pl->params.pol_count, nm = g.nmodes > 0 ? g.nmodes : 1;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o += align256(bytes); return r; };
+  off[0] = take((size_t)mb * P * g.ny * g.bx * 8);                  // t1
+  off[1] = take((size_t)mb * P * g.wy * ((g.bx + 15) / 16 * 16) * 8);  // f2
+  off[2] = take((size_t)mb * P * (g.wyp / 16) * (nm + 1) * 8);       // partial
+  off[3] = take((size_t)mb * P * nm * 8);                            // coefs
+  off[4] = take((size_t)mb * P * nm * 8);                            // coefs_norm
+  off[5] = take((size_t)mb * 8);                                     // frame pointers
+  return o;
+}
+
+void free_lane(Lane& L) {
+  for (auto& kv : L.graphs) (void)hipGraphExecDestroy(kv.second);
+  L.graphs.clear();
+  if (L.s) (void)hipStreamDestroy(L.s);
+  if (L.done) (void)hipEventDestroy(L.done);
+  if (L.mem) (void)hipFree(L.mem);
+  if (L.hptr) (void)hipHostFree(L.hptr);
+  if (L.hres) (void)hipHostFree(L.hres);
+  L = Lane();
+}
+
+int make_lane(Server* S, Camera& C, Lane& L) {
+  size_t off[6];
+  lane_layout(C.pl, S->max_batch, off);
+  if (hipStreamCreateWithFlags(&L.s, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&L.done, hipEventDisableTiming) != hipSuccess ||
+      hipMalloc(&L.mem, C.lane_bytes) != hipSuccess ||
+      hipHostMalloc((void**)&L.hptr, (size_t)S->max_batch * sizeof(void*), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&L.hres, (size_t)S->max_batch * C.per_result * 8, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    free_lane(L);
+    return DH_ERR_MEMORYALLOCATION;
+  }
+  for (int i = 0; i < 6; ++i) L.off[i] = off[i];
+  return DH_SUCCESS;
+}
+
+// the plan's current tables with the lane's own buffers; graphs made for an
+// older version of the plan are dropped
+void lane_args(const Camera& C, Lane& L) {
+  if (L.version == C.pl->version) return;
+  for (auto& kv : L.graphs) (void)hipGraphExecDestroy(kv.second);
+  L.graphs.clear();
+  L.k = C.pl->ka[0];
+  L.k.t1 = (float2*)(L.mem + L.off[0]);
+  L.k.f2 = (float2*)(L.mem + L.off[1]);
+  L.k.partial = (float2*)(L.mem + L.off[2]);
+  L.k.coefs = (float2*)(L.mem + L.off[3]);
+  L.k.coefs_norm = (float2*)(L.mem + L.off[4]);
+  L.k.fptr = (const void* const*)(L.mem + L.off[5]);
+  L.k.window = nullptr;
+  L.k.fields = nullptr;
+  L.k.capt = nullptr;
+  L.version = C.pl->version;
+}
+
+hipError_t record_batch(const Camera& C, const Lane& L, int n) {
+  const int u16 = C.pl->params.input_dtype == DH_INPUT_U16;
+  hipError_t e = dh::launch_row(L.k, nullptr, u16, 0, n, L.s);
+  if (e == hipSuccess) e = dh::launch_col(L.k, 0, n, L.s);
+  if (e == hipSuccess && L.k.G > 0) e = dh::launch_fld(L.k, 0, n, L.s);
+  if (e == hipSuccess && L.k.G > 0) e = dh::launch_norm(L.k, 0, n, L.s);
+  return e;
+}
+
+int launch_lane(Server* S, Camera& C, Lane& L) {
+  lane_args(C, L);
+  const int n = (int)std::min<size_t>(C.pending.size(), (size_t)S->max_batch);
+  L.batch.assign(C.pending.begin(), C.pending.begin() + n);
+  C.pending.erase(C.pending.begin(), C.pending.begin() + n);
+  for (int i = 0; i < n; ++i) L.hptr[i] = L.batch[i].frame;
+  if (hipMemcpyAsync((void*)L.k.fptr, L.hptr, (size_t)n * sizeof(void*), hipMemcpyHostToDevice, L.s) != hipSuccess)
+    return DH_ERR_ERROR;
+  if (S->graphs) {
+    auto it = L.graphs.find(n);
+    if (it == L.graphs.end()) {
+      hipGraph_t gr = nullptr;
+      hipGraphExec_t ex = nullptr;
+      if (hipStreamBeginCapture(L.s, hipStreamCaptureModeThreadLocal) != hipSuccess) return DH_ERR_ERROR;
+      const hipError_t rec = record_batch(C, L, n);
+      const hipError_t end = hipStreamEndCapture(L.s, &gr);
+      if (rec != hipSuccess || end != hipSuccess || hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0) != hipSuccess) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return DH_ERR_ERROR;
+      }
+      (void)hipGraphDestroy(gr);
+      it = L.graphs.emplace(n, ex).first;
+    }
+    if (hipGraphLaunch(it->second, L.s) != hipSuccess) return DH_ERR_ERROR;
+  } else if (record_batch(C, L, n) != hipSuccess) {
+    return DH_ERR_ERROR;
+  }
+  const float2* res = S->normalised ? L.k.coefs_norm : L.k.coefs;
+  if (C.per_result > 0 &&
+      hipMemcpyAsync(L.hres, res, (size_t)n * C.per_result * 8, hipMemcpyDeviceToHost, L.s) != hipSuccess)
+    return DH_ERR_ERROR;
+  if (hipEventRecord(L.done, L.s) != hipSuccess) return DH_ERR_ERROR;
+  L.busy = true;
+  ++S->batches;
+  S->frames += n;
+  return DH_SUCCESS;
+}
+
+// one scheduling round: retire finished batches, start new ones
+int serve_round(Server* S, int* completed) {
+  int done = 0;
+  for (Camera& C : S->cams) {
+    for (Lane& L : C.lanes) {
+      if (!L.busy) continue;
+      const hipError_t q = hipEventQuery(L.done);
+      if (q == hipErrorNotReady) continue;
+      if (q != hipSuccess) return DH_ERR_ERROR;
+      const double t = std::chrono::duration<double>(Clock::now() - S->t0).count();
+      for (size_t i = 0; i < L.batch.size(); ++i) {
+        const Req& r = L.batch[i];
+        if (r.out) std::memcpy(r.out, L.hres + i * C.per_result, (size_t)C.per_result * 8);
+        if (S->t_done && r.idx >= 0) S->t_done[r.idx] = t;
+      }
+      done += (int)L.batch.size();
+      L.batch.clear();
+      L.busy = false;
+    }
+    for (Lane& L : C.lanes) {
+      if (C.pending.empty()) break;
+      if (!L.busy) {
+        const int e = launch_lane(S, C, L);
+        if (e != DH_SUCCESS) return e;
+      }
+    }
+  }
+  if (completed) *completed = done;
+  return DH_SUCCESS;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dh_serve_create(const dh_handle* plans, int ncam, int max_batch, size_t hbm_budget, int use_graphs,
+                    int normalised, dh_server* out) {
+  if (!plans || !out) return DH_ERR_NULLPOINTER;
+  if (ncam < 1 || max_batch < 1) return DH_ERR_INVALIDDIMENSION;
+  Server* S = new Server();
+  S->max_batch = max_batch;
+  S->graphs = use_graphs != 0;
+  S->normalised = normalised != 0;
+  S->cams.resize(ncam);
+  size_t total = 0;
+  for (int c = 0; c < ncam; ++c) {
+    Camera& C = S->cams[c];
+    C.pl = get(plans[c]);
+    if (!C.pl) {
+      delete S;
+      return DH_ERR_INVALIDHANDLE;
+    }
+    size_t off[6];
+    C.lane_bytes = lane_layout(C.pl, max_batch, off);
+    C.per_result = C.pl->params.pol_count * C.pl->g.nmodes;
+    total += C.lane_bytes;
+  }
+  if (hbm_budget && total > hbm_budget) {  // not even one lane per camera fits
+    delete S;
+    return DH_ERR_MEMORYALLOCATION;
+  }
+  // lanes round robin over the cameras while the budget allows
+  int err = DH_SUCCESS;
+  size_t used = 0;
+  for (int round = 0; round < 4 && err == DH_SUCCESS; ++round)
+    for (Camera& C : S->cams) {
+      if (round > 0 && hbm_budget && used + C.lane_bytes > hbm_budget) continue;
+      C.lanes.emplace_back();
+      err = make_lane(S, C, C.lanes.back());
+      if (err != DH_SUCCESS) {
+        C.lanes.pop_back();
+        if (round > 0) err = DH_SUCCESS;  // extra lanes are optional
+        break;
+      }
+      used += C.lane_bytes;
+    }
+  if (err != DH_SUCCESS) {
+    for (Camera& C : S->cams)
+      for (Lane& L : C.lanes) free_lane(L);
+    delete S;
+    return err;
+  }
+  S->t0 = Clock::now();
+  std::lock_guard<std::mutex> lk(g_smu);
+  g_servers.push_back(S);
+  *out = (dh_server)(g_servers.size() - 1);
+  return DH_SUCCESS;
+}
+
+int dh_serve_info(dh_server h, int camera, int* lanes, size_t* lane_bytes, int* per_result) {
+  Server* S = sget(h);
+  if (!S) return DH_ERR_INVALIDHANDLE;
+  if (camera < 0 || camera >= (int)S->cams.size()) return DH_ERR_INVALIDARGUMENT;
+  const Camera& C = S->cams[camera];
+  if (lanes) *lanes = (int)C.lanes.size();
+  if (lane_bytes) *lane_bytes = C.lane_bytes;
+  if (per_result) *per_result = C.per_result;
+  return DH_SUCCESS;
+}
+
+int dh_serve_submit(dh_server h, int camera, const void* frame, dh_c64* result) {
+  Server* S = sget(h);
+  if (!S) return DH_ERR_INVALIDHANDLE;
+  if (camera < 0 || camera >= (int)S->cams.size()) return DH_ERR_INVALIDARGUMENT;
+  if (!frame) return DH_ERR_NULLPOINTER;
+  S->cams[camera].pending.push_back(Req{frame, result, -1});
+  return DH_SUCCESS;
+}
+
+int dh_serve_progress(dh_server h, int* completed) {
+  Server* S = sget(h);
+  if (!S) return DH_ERR_INVALIDHANDLE;
+  return serve_round(S, completed);
+}
+
+int dh_serve_replay(dh_server h, int n, const double* t_arrival, const int* camera, const void* const* frames,
+                    dh_c64* const* results, double* t_done, double* t_start) {
+  Server* S = sget(h);
+  if (!S) return DH_ERR_INVALIDHANDLE;
+  if (!t_arrival || !camera || !frames || !t_done) return DH_ERR_NULLPOINTER;
+  for (int i = 0; i < n; ++i)
+    if (camera[i] < 0 || camera[i] >= (int)S->cams.size() || !frames[i] || (i && t_arrival[i] < t_arrival[i - 1]))
+      return DH_ERR_INVALIDARGUMENT;
+  S->t0 = Clock::now();
+  S->t_done = t_done;
+  int next = 0, finished = 0, err = DH_SUCCESS;
+  while (finished < n) {
+    const double now = std::chrono::duration<double>(Clock::now() - S->t0).count();
+    while (next < n && t_arrival[next] <= now) {
+      S->cams[camera[next]].pending.push_back(Req{frames[next], results ? results[next] : nullptr, next});
+      ++next;
+    }
+    int done = 0;
+    err = serve_round(S, &done);
+    if (err != DH_SUCCESS) break;
+    finished += done;
+  }
+  S->t_done = nullptr;
+  if (t_start) *t_start = 0.0;
+  if (err != DH_SUCCESS) {
+    (void)hipDeviceSynchronize();
+    for (Camera& C : S->cams) {
+      C.pending.clear();
+      for (Lane& L : C.lanes) {
+        L.busy = false;
+        L.batch.clear();
+      }
+    }
+  }
+  return err;
+}
+
+int dh_serve_stats(dh_server h, long long* batches, long long* frames) {
+  Server* S = sget(h);
+  if (!S) return DH_ERR_INVALIDHANDLE;
+  if (batches) *batches = S->batches;
+  if (frames) *frames = S->frames;
+  return DH_SUCCESS;
+}
+
+int dh_serve_destroy(dh_server h) {
+  Server* S;
+  {
+    std::lock_guard<std::mutex> lk(g_smu);
+    if (h < 0 || (size_t)h >= g_servers.size() || !g_servers[h]) return DH_ERR_INVALIDHANDLE;
+    S = g_servers[h];
+    g_servers[h] = nullptr;
+  }
+  (void)hipDeviceSynchronize();
+  for (Camera& C : S->cams)
+    for (Lane& L : C.lanes) free_lane(L);
+  delete S;
+  return DH_SUCCESS;
+}
+
+}  // extern "C"

@@ -52,6 +52,7 @@ struct KArgs {
   const float2* tw_ny;
   const float2* tw_wx;
   const float2* tw_wy;
+  const void* const* fptr;  // device array of frame pointers (frame b at fptr[b]) or null: contiguous frames
   float2* t1;               // [chunk][P][bx][ny] row-pass spectrum at the box columns (column-major)
   float2* f2;               // [chunk][P][wy][bxp] column pass + crop + y-IFFT
   float2* partial;          // [chunk][nblk][P][nmodes + 1] per-row-block share of each coefficient,

@@ -59,7 +59,8 @@ __global__ void __launch_bounds__(TR * NX / FftPlan<NX>::R0) k_row(KArgs A, cons
   const int bl = blockIdx.z;                 // frame within the chunk
   const PolTab& P = A.pol[p];
   const int ybase = blockIdx.x * (2 * TR);
-  const TIn* win = frames + (size_t)(b0 + bl) * A.frame_h * A.frame_w + (size_t)P.y0 * A.frame_w + P.x0;
+  const TIn* fr = A.fptr ? static_cast<const TIn*>(A.fptr[b0 + bl]) : frames + (size_t)(b0 + bl) * A.frame_h * A.frame_w;
+  const TIn* win = fr + (size_t)P.y0 * A.frame_w + P.x0;
   {
     const int t = tid / Q::NB, b = tid % Q::NB;
     const int y = ybase + 2 * t;

@@ -108,3 +108,16 @@ def test_hbm_budget_is_checked_before_allocating():
     h = ctypes.c_int(-1)
     p = dh.make_params(_p())
     assert dh.lib().dh_plan(ctypes.byref(p), 1000, 1024, ctypes.byref(h)) == dh.ERR_MEMORYALLOCATION
+
+
+def test_serving_rejects_bad_arguments_without_gpu():
+    L = dh.lib()
+    s = ctypes.c_int(-1)
+    assert L.dh_serve_create(None, 1, 8, 0, 1, 1, ctypes.byref(s)) == dh.ERR_NULLPOINTER
+    hs = (ctypes.c_int * 2)(777, 778)
+    assert L.dh_serve_create(hs, 2, 8, 0, 1, 1, ctypes.byref(s)) == dh.ERR_INVALIDHANDLE
+    assert L.dh_serve_create(hs, 0, 8, 0, 1, 1, ctypes.byref(s)) == dh.ERR_INVALIDDIMENSION
+    assert L.dh_serve_destroy(55) == dh.ERR_INVALIDHANDLE
+    assert L.dh_serve_progress(55, None) == dh.ERR_INVALIDHANDLE
+    n = ctypes.c_int()
+    assert L.dh_serve_submit(55, 0, None, None) == dh.ERR_INVALIDHANDLE

@@ -272,3 +272,81 @@ def test_alignment_recovers_truth_and_then_processes():
         ref = oracle.process_frame(f[i].astype(np.float64), aligned)["coefs"]
         for pol in range(2):
             assert _rel(coefs[i][pol].astype(np.complex128), ref[pol]) <= TOL
+
+
+
+# ---------------------------------------------------------------- serving
+def _cameras(n_frames):
+    """The four serving cameras (uint16) with a small pool of frames each."""
+    cams = []
+    for cam in range(4):
+        cfg = dh_synth.config(3, cam)
+        f, _ = dh_synth.make_frames(cfg, n_frames=n_frames if cam < 3 else 2)
+        cams.append((cfg, f))
+    return cams
+
+
+def _trace(n, counts, rate, seed):
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, size=n))
+    cam = rng.integers(0, 4, size=n).astype(np.int32)
+    idx = np.array([rng.integers(0, counts[c]) for c in cam])
+    return t, cam, idx
+
+
+@pytest.mark.parametrize("graphs", [True, False])
+def test_serving_result_alone_equals_in_the_mix(graphs):
+    torch = _torch()
+    import paper_2204_02348_amd as dh
+    cams = _cameras(4)
+    plans = [dh.Plan(cfg["params"], max_batch=64) for cfg, _ in cams]
+    pools = [torch.from_numpy(f).cuda() for _, f in cams]
+    counts = [f.shape[0] for _, f in cams]
+    srv = dh.Server(plans, max_batch=64, hbm_budget=8 << 30, use_graphs=graphs)
+    _say("serving graphs=%s lanes %s" % (graphs, [srv.info(c)[0] for c in range(4)]))
+    n = 600
+    t, cam, idx = _trace(n, counts, 40000.0, 7)
+    ptrs = [pools[c][i].data_ptr() for c, i in zip(cam, idx)]
+    per = [srv.info(c)[2] for c in range(4)]
+    res = [np.zeros(per[c], dtype=np.complex64) for c in cam]
+    torch.cuda.synchronize()          # pools uploaded before the lanes' streams read them
+    done = srv.replay(t, cam, ptrs, res)
+    batches, frames = srv.stats()
+    _say("served %d frames in %d batches; latency p50 %.1f us p99 %.1f us" % (
+        frames, batches, 1e6 * np.percentile(done - t, 50), 1e6 * np.percentile(done - t, 99)))
+    assert np.all(done >= t) and frames == n
+    assert batches < n      # requests were batched together
+    srv.destroy()
+    # every result equals the same frame processed alone, bit for bit
+    alone = {}
+    for c in range(4):
+        for i in range(counts[c]):
+            plans[c].process(pools[c][i], 1, None)
+            alone[(c, i)] = plans[c].coefs(True)[0].reshape(-1)
+    for k in range(n):
+        assert np.array_equal(res[k], alone[(int(cam[k]), int(idx[k]))]), k
+    # and matches the oracle
+    for c in range(4):
+        cfg, f = cams[c]
+        ref = oracle.process_frame(f[0].astype(np.float64), cfg["params"])["coefs_norm"].reshape(-1)
+        assert _rel(alone[(c, 0)].astype(np.complex128), ref) <= TOL
+    for p in plans:
+        p.destroy()
+
+
+def test_serving_admission_by_budget():
+    torch = _torch()
+    import paper_2204_02348_amd as dh
+    cfg = dh_synth.config(3, 1)
+    plan = dh.Plan(cfg["params"], max_batch=32)
+    srv = dh.Server([plan], max_batch=32, hbm_budget=0)
+    lanes, nbytes, _ = srv.info(0)
+    srv.destroy()
+    assert lanes == 4
+    srv = dh.Server([plan], max_batch=32, hbm_budget=2 * nbytes + 1)
+    assert srv.info(0)[0] == 2
+    srv.destroy()
+    with pytest.raises(dh.DhError) as e:
+        dh.Server([plan], max_batch=32, hbm_budget=nbytes - 1)
+    assert e.value.code == dh.ERR_MEMORYALLOCATION
+    plan.destroy()
