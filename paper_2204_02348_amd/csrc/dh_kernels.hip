@@ -42,6 +42,15 @@ __device__ __forceinline__ unsigned short bf16_rne(float x) {
 __device__ __forceinline__ float bf16_to_f32(unsigned short b) { return __uint_as_float((unsigned int)b << 16); }
 
 
+// Twiddle tables of a transform length (entries after the first pass), staged
+// into LDS once per workgroup; their loads overlap the first pass's operands.
+template <int N> constexpr int twn() { return N > FftPlan<N>::R0 ? N - FftPlan<N>::R0 : 1; }
+
+template <int N, int TPB>
+__device__ __forceinline__ void stage_twiddles(float2* dst, const float2* __restrict__ src, int tid) {
+  for (int e = tid; e < twn<N>(); e += TPB) dst[e] = src[e];
+}
+
 // ---------------------------------------------------------------------------
 // k_row: grid (ceil(ny / (2 TR)), npol, nb), TPB = TR * NX / R0 threads: TR
 // complex transforms of NX, each the pair of real rows (2t, 2t+1) packed as
@@ -54,11 +63,13 @@ __global__ void __launch_bounds__(TR * NX / FftPlan<NX>::R0) k_row(KArgs A, cons
   constexpr int TPB = TR * NX / FftPlan<NX>::R0;
   static_assert(Q::IT == 1, "one first-pass butterfly per thread");
   __shared__ float2 buf[TR * L::STRIDE];
+  __shared__ float2 tws[twn<NX>()];
   const int tid = threadIdx.x;
   const int p = blockIdx.y;
   const int bl = blockIdx.z;                 // frame within the chunk
   const PolTab& P = A.pol[p];
   const int ybase = blockIdx.x * (2 * TR);
+  stage_twiddles<NX, TPB>(tws, A.tw_nx, tid);
   const TIn* fr = A.fptr ? static_cast<const TIn*>(A.fptr[b0 + bl]) : frames + (size_t)(b0 + bl) * A.frame_h * A.frame_w;
   const TIn* win = fr + (size_t)P.y0 * A.frame_w + P.x0;
   {
@@ -75,7 +86,7 @@ __global__ void __launch_bounds__(TR * NX / FftPlan<NX>::R0) k_row(KArgs A, cons
     }
     fft_pass1_regs<NX, TR, L::STRIDE, TPB>(v, buf, tid);
   }
-  fft_rest<NX, TR, L::STRIDE, TPB>(buf, A.tw_nx, tid);
+  fft_rest<NX, TR, L::STRIDE, TPB>(buf, tws, tid);
   // two-for-one split at the kept bins: both rows of a pair from Z[k], Z[NX-k]
   float2* out = A.t1 + (size_t)(bl * A.npol + p) * A.bx * A.ny;
   for (int e = tid; e < TR * A.bx; e += TPB) {
@@ -111,11 +122,25 @@ __global__ void __launch_bounds__(kTPB) k_col(KArgs A, int b0) {
   using Q = Pass1<NY, CG, kTPB>;
   constexpr int ST = (LN::STRIDE > LW::STRIDE) ? LN::STRIDE : LW::STRIDE;
   __shared__ float2 buf[CG * ST];
+  __shared__ float2 twy[twn<NY>()];
+  __shared__ float2 tww[twn<WY>()];
+  __shared__ short s_qrow[WY];
+  __shared__ int2 s_mrow[WY];
+  __shared__ float2 s_crx[CG];              // conj(rho_x) of this block's columns
+  __shared__ float2 s_cry[WY];              // conj(rho_y) by box row
   const int tid = threadIdx.x;
   const int p = blockIdx.y;
   const int bl = blockIdx.z;
   const PolTab& P = A.pol[p];
   const int jc0 = blockIdx.x * CG;
+  stage_twiddles<NY, kTPB>(twy, A.tw_ny, tid);
+  stage_twiddles<WY, kTPB>(tww, A.tw_wy, tid);
+  for (int e = tid; e < WY; e += kTPB) {
+    s_qrow[e] = P.qrow[e];
+    s_mrow[e] = e < A.by ? P.mrow[e] : make_int2(1, 0);
+  }
+  for (int e = tid; e < WY; e += kTPB) s_cry[e] = e < A.by ? conjf2(P.rhoy[e]) : make_float2(0.f, 0.f);
+  if (tid < CG) s_crx[tid] = jc0 + tid < A.bx ? conjf2(P.rhox[jc0 + tid]) : make_float2(0.f, 0.f);
   const float2* in = A.t1 + ((size_t)(bl * A.npol + p) * A.bx) * NY;
   {
     float2 v[Q::IT][Q::R0];
@@ -131,7 +156,7 @@ __global__ void __launch_bounds__(kTPB) k_col(KArgs A, int b0) {
     }
     fft_pass1_regs<NY, CG, ST, kTPB>(v, buf, tid);
   }
-  fft_rest<NY, CG, ST, kTPB>(buf, A.tw_ny, tid);
+  fft_rest<NY, CG, ST, kTPB>(buf, twy, tid);
   constexpr int NE = (CG * WY + kTPB - 1) / kTPB;
   float2 z[NE];
   const bool keep_win = A.window != nullptr;
@@ -143,15 +168,14 @@ __global__ void __launch_bounds__(kTPB) k_col(KArgs A, int b0) {
     if (e < CG * WY) {
       const int c = e / WY, q = e % WY;
       const int j = jc0 + c;
-      const int i = P.qrow[q];
+      const int i = s_qrow[q];
       if (i >= 0 && j < A.bx) {
-        const int2 mr = P.mrow[i];
+        const int2 mr = s_mrow[i];
         if (j >= mr.x && j <= mr.y) {
           int vv = (P.ky0 + i) % NY;
           if (vv < 0) vv += NY;
           const float2 f = buf[c * ST + LN::at(vv)];
-          const float2 rho = cmul(P.rhox[j], P.rhoy[i]);
-          val = cmul(f, conjf2(rho));
+          val = cmul(cmul(f, s_crx[c]), s_cry[i]);
           if (keep_win) {
             // window = M * I~ = conj(val) (-1)^(u+v) Nx Ny at (v mod wy, u mod wx)
             const int u = -(P.k0 + j), v = -(P.ky0 + i);
@@ -172,7 +196,7 @@ __global__ void __launch_bounds__(kTPB) k_col(KArgs A, int b0) {
     if (e < CG * WY) buf[(e / WY) * ST + LW::at(e % WY)] = z[it];
   }
   __syncthreads();
-  fft_lds<WY, CG, ST, kTPB>(buf, A.tw_wy, tid);
+  fft_lds<WY, CG, ST, kTPB>(buf, tww, tid);
   float2* out = A.f2 + ((size_t)(bl * A.npol + p) * WY) * A.bxp;
   for (int e = tid; e < CG * WY; e += kTPB) {
     const int c = e % CG, l = e / CG;
@@ -371,6 +395,9 @@ __global__ void __launch_bounds__(kTPB) k_fld(KArgs A, int b0) {
   __shared__ float red[4][NPAIR][2][256];
   __shared__ float bmax[4];
   __shared__ float bpow[4];
+  __shared__ float2 tww[twn<WX>()];
+  __shared__ float2 s_tx[WX];
+  __shared__ float2 s_ty[16];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const int rb = blockIdx.x;
@@ -381,6 +408,9 @@ __global__ void __launch_bounds__(kTPB) k_fld(KArgs A, int b0) {
   const float2* in = A.f2 + ((size_t)(bl * A.npol + p) * A.wy) * A.bxp;
   float2* fld = A.fields ? A.fields + ((size_t)bg * A.npol + p) * A.wy * WX : nullptr;
   const int gp = A.gp;
+  stage_twiddles<WX, kTPB>(tww, A.tw_wx, tid);
+  for (int e = tid; e < WX; e += kTPB) s_tx[e] = P.tx[e];
+  if (tid < 16) s_ty[tid] = (rb * 16 + tid < A.wy) ? P.ty[rb * 16 + tid] : make_float2(0.f, 0.f);
   for (int e = tid; e < 16 * WX; e += kTPB) {
     const int r = e / WX, q = e % WX;
     const int y = rb * 16 + r;
@@ -392,14 +422,14 @@ __global__ void __launch_bounds__(kTPB) k_fld(KArgs A, int b0) {
     buf[r * ST + L::at(q)] = v;
   }
   __syncthreads();
-  fft_lds<WX, 16, ST, kTPB>(buf, A.tw_wx, tid);
+  fft_lds<WX, 16, ST, kTPB>(buf, tww, tid);
   float emax = 0.f;
   for (int e = tid; e < 16 * WX; e += kTPB) {
     const int r = e / WX, q = e % WX;
     const int y = rb * 16 + r;
     float2 ev = make_float2(0.f, 0.f);
     if (y < A.wy) {
-      ev = cmul(cmul(conjf2(buf[r * ST + L::at(q)]), P.tx[q]), P.ty[y]);
+      ev = cmul(cmul(conjf2(buf[r * ST + L::at(q)]), s_tx[q]), s_ty[r]);
       if (fld) fld[(size_t)y * WX + q] = ev;
     }
     buf[r * ST + L::at(q)] = ev;
