@@ -407,6 +407,7 @@ void fill_kargs(Plan* pl, int w) {
     dh::PolTab& t = a.pol[q];
     t.x0 = P.x0; t.y0 = P.y0;
     t.k0 = -P.uhi; t.ky0 = -P.vhi;
+    t.bxq = P.uhi - P.ulo + 1; t.byq = P.vhi - P.vlo + 1;
     t.mrow = (const int2*)(m + L.pol_mrow[q]);
     t.qrow = (const short*)(m + L.pol_qrow[q]);
     t.qcol = (const short*)(m + L.pol_qcol[q]);

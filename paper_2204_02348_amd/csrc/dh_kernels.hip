@@ -42,6 +42,15 @@ __device__ __forceinline__ unsigned short bf16_rne(float x) {
 __device__ __forceinline__ float bf16_to_f32(unsigned short b) { return __uint_as_float((unsigned int)b << 16); }
 
 
+// Box row / column held by IFFT row / column q: bin u sits at q = u mod W and
+// box index j = u_hi - u, so j = (u_hi - q) mod W; -1 if j is outside the pol's
+// box. (u_hi = -k0, v_hi = -ky0.)
+__device__ __forceinline__ int box_of(int uhi, int q, int w, int nbox) {
+  int j = (uhi - q) % w;
+  if (j < 0) j += w;
+  return j < nbox ? j : -1;
+}
+
 // Twiddle tables of a transform length (entries after the first pass), staged
 // into LDS once per workgroup; their loads overlap the first pass's operands.
 template <int N> constexpr int twn() { return N > FftPlan<N>::R0 ? N - FftPlan<N>::R0 : 1; }
@@ -124,7 +133,6 @@ __global__ void __launch_bounds__(kTPB) k_col(KArgs A, int b0) {
   __shared__ float2 buf[CG * ST];
   __shared__ float2 twy[twn<NY>()];
   __shared__ float2 tww[twn<WY>()];
-  __shared__ short s_qrow[WY];
   __shared__ int2 s_mrow[WY];
   __shared__ float2 s_crx[CG];              // conj(rho_x) of this block's columns
   __shared__ float2 s_cry[WY];              // conj(rho_y) by box row
@@ -136,7 +144,6 @@ __global__ void __launch_bounds__(kTPB) k_col(KArgs A, int b0) {
   stage_twiddles<NY, kTPB>(twy, A.tw_ny, tid);
   stage_twiddles<WY, kTPB>(tww, A.tw_wy, tid);
   for (int e = tid; e < WY; e += kTPB) {
-    s_qrow[e] = P.qrow[e];
     s_mrow[e] = e < A.by ? P.mrow[e] : make_int2(1, 0);
   }
   for (int e = tid; e < WY; e += kTPB) s_cry[e] = e < A.by ? conjf2(P.rhoy[e]) : make_float2(0.f, 0.f);
@@ -168,7 +175,7 @@ __global__ void __launch_bounds__(kTPB) k_col(KArgs A, int b0) {
     if (e < CG * WY) {
       const int c = e / WY, q = e % WY;
       const int j = jc0 + c;
-      const int i = s_qrow[q];
+      const int i = box_of(-P.ky0, q, WY, P.byq);
       if (i >= 0 && j < A.bx) {
         const int2 mr = s_mrow[i];
         if (j >= mr.x && j <= mr.y) {
@@ -275,7 +282,7 @@ __global__ void __launch_bounds__(kTPB) k_gather(KArgs A, SpecRef S) {
   for (int e = tid; e < CG * WY; e += kTPB) {
     const int c = e / WY, q = e % WY;
     const int j = jc0 + c;
-    const int i = P.qrow[q];
+    const int i = box_of(-P.ky0, q, WY, P.byq);
     float2 val = make_float2(0.f, 0.f);
     if (i >= 0 && j < A.bx) {
       const int2 mr = P.mrow[i];
@@ -408,6 +415,24 @@ __global__ void __launch_bounds__(kTPB) k_fld(KArgs A, int b0) {
   const float2* in = A.f2 + ((size_t)(bl * A.npol + p) * A.wy) * A.bxp;
   float2* fld = A.fields ? A.fields + ((size_t)bg * A.npol + p) * A.wy * WX : nullptr;
   const int gp = A.gp;
+  // the FP32 path's HG operands, loaded before the IFFT so their latency hides
+  constexpr int KSP = (PREC == 0 && (WX / 16) * MT <= 16) ? WX / 16 : 1;
+  float ubp[MT][KSP];
+  float uap[NPAIR][4];
+  if constexpr (PREC == 0) {
+    if constexpr ((WX / 16) * MT <= 16) {
+#pragma unroll
+      for (int s = 0; s < KSP; ++s)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+          ubp[mt][s] = P.ux[(wv * (WX / 4) + 4 * s + (lane >> 4)) * gp + mt * 16 + (lane & 15)];
+    }
+#pragma unroll
+    for (int q = 0; q < NPAIR; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        uap[q][r] = P.uy[(rb * 16 + 4 * (lane >> 4) + r) * gp + ((q == 2) ? 16 : 0) + (lane & 15)];
+  }
   stage_twiddles<WX, kTPB>(tww, A.tw_wx, tid);
   for (int e = tid; e < WX; e += kTPB) s_tx[e] = P.tx[e];
   if (tid < 16) s_ty[tid] = (rb * 16 + tid < A.wy) ? P.ty[rb * 16 + tid] : make_float2(0.f, 0.f);
@@ -416,7 +441,7 @@ __global__ void __launch_bounds__(kTPB) k_fld(KArgs A, int b0) {
     const int y = rb * 16 + r;
     float2 v = make_float2(0.f, 0.f);
     if (y < A.wy) {
-      const int j = P.qcol[q];
+      const int j = box_of(-P.k0, q, WX, P.bxq);
       if (j >= 0) v = conjf2(in[(size_t)y * A.bxp + j]);
     }
     buf[r * ST + L::at(q)] = v;
@@ -463,15 +488,28 @@ __global__ void __launch_bounds__(kTPB) k_fld(KArgs A, int b0) {
     // T[y][m] = sum_x E[y][x] Ux[x][m] over this wave's quarter of x
     constexpr int XS = WX / 4;    // x columns per wave
     constexpr int KS = XS / 4;    // k-steps of 4
-#pragma unroll 4
-    for (int s = 0; s < KS; ++s) {
-      const int x = wv * XS + 4 * s + (lane >> 4);
-      const float2 ev = buf[(lane & 15) * ST + L::at(x)];
+    if constexpr (KS * MT <= 16) {
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        const float ub = P.ux[x * gp + mt * 16 + (lane & 15)];
-        tre[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ev.x, ub, tre[mt], 0, 0, 0);
-        tim[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ev.y, ub, tim[mt], 0, 0, 0);
+      for (int s = 0; s < KS; ++s) {
+        const int x = wv * XS + 4 * s + (lane >> 4);
+        const float2 ev = buf[(lane & 15) * ST + L::at(x)];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          tre[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ev.x, ubp[mt][s], tre[mt], 0, 0, 0);
+          tim[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ev.y, ubp[mt][s], tim[mt], 0, 0, 0);
+        }
+      }
+    } else {
+#pragma unroll 4
+      for (int s = 0; s < KS; ++s) {
+        const int x = wv * XS + 4 * s + (lane >> 4);
+        const float2 ev = buf[(lane & 15) * ST + L::at(x)];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          const float ub = P.ux[x * gp + mt * 16 + (lane & 15)];
+          tre[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ev.x, ub, tre[mt], 0, 0, 0);
+          tim[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ev.y, ub, tim[mt], 0, 0, 0);
+        }
       }
     }
   } else {
@@ -510,14 +548,11 @@ __global__ void __launch_bounds__(kTPB) k_fld(KArgs A, int b0) {
   if constexpr (PREC == 0) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int y = rb * 16 + 4 * (lane >> 4) + r;
 #pragma unroll
       for (int q = 0; q < NPAIR; ++q) {
-        const int nt = (q == 2) ? 1 : 0;
         const int mt = (q == 1) ? 1 : 0;
-        const float ua = P.uy[y * gp + nt * 16 + (lane & 15)];
-        cre[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ua, tre[mt][r], cre[q], 0, 0, 0);
-        cim[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ua, tim[mt][r], cim[q], 0, 0, 0);
+        cre[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(uap[q][r], tre[mt][r], cre[q], 0, 0, 0);
+        cim[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(uap[q][r], tim[mt][r], cim[q], 0, 0, 0);
       }
     }
   } else {
