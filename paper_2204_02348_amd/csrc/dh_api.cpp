@@ -182,7 +182,7 @@ int streams_for(int max_batch, int chunk) {
 
 struct Layout {  // byte offsets inside one device allocation
   size_t tw_nx, tw_ny, tw_wx, tw_wy, modes, total_tables;
-  size_t pol_mrow[2], pol_qrow[2], pol_qcol[2], pol_rhox[2], pol_rhoy[2], pol_tx[2], pol_ty[2], pol_ux[2], pol_uy[2];
+  size_t pol_mrow[2], pol_rhox[2], pol_rhoy[2], pol_tx[2], pol_ty[2], pol_ux[2], pol_uy[2];
   size_t pol_uxs[2][4], pol_uys[2][4];   // split tables: bf16 hi, bf16 lo, fp16 hi, fp16 lo
   size_t t1[4], f2[4], partial[4], capt, coefs, coefs_norm, window, fields, total;
 };
@@ -195,8 +195,6 @@ Layout layout(const Geom& g, const dh_params* p, int max_batch, int chunk, int n
   L.modes = take((g.nmodes > 0 ? g.nmodes : 1) * 4);
   for (int q = 0; q < p->pol_count; ++q) {
     L.pol_mrow[q] = take(g.by * 8);
-    L.pol_qrow[q] = take(g.wy * 2);
-    L.pol_qcol[q] = take(g.wx * 2);
     L.pol_rhox[q] = take(g.bx * 8);
     L.pol_rhoy[q] = take(g.by * 8);
     L.pol_tx[q] = take(g.wx * 8);
@@ -328,16 +326,6 @@ int build_tables(Plan* pl, bool hg = true) {
     std::vector<int2> mrow(g.by, make_int2(1, 0));
     for (int i = 0; i < byq; ++i)
       if (P.row_lo[i] <= P.row_hi[i]) mrow[i] = make_int2(P.uhi - P.row_hi[i], P.uhi - P.row_lo[i]);
-    std::vector<short> qrow(g.wy, -1), qcol(g.wx, -1);
-    for (int i = 0; i < byq; ++i) {
-      const int v = P.vhi - i;
-      qrow[((v % g.wy) + g.wy) % g.wy] = (short)i;
-    }
-    const int bxq = P.uhi - P.ulo + 1;
-    for (int j = 0; j < bxq; ++j) {
-      const int u = P.uhi - j;
-      qcol[((u % g.wx) + g.wx) % g.wx] = (short)j;
-    }
     std::vector<float2> rhox(g.bx), rhoy(g.by), tx(g.wx), ty(g.wy);
     for (int j = 0; j < g.bx; ++j) {
       const int u = P.uhi - j;
@@ -361,8 +349,6 @@ int build_tables(Plan* pl, bool hg = true) {
       ty[l] = make_float2((float)std::cos(ph), (float)std::sin(ph));
     }
     put(host, L.pol_mrow[q], mrow);
-    put(host, L.pol_qrow[q], qrow);
-    put(host, L.pol_qcol[q], qcol);
     put(host, L.pol_rhox[q], rhox);
     put(host, L.pol_rhoy[q], rhoy);
     put(host, L.pol_tx[q], tx);
@@ -409,8 +395,6 @@ void fill_kargs(Plan* pl, int w) {
     t.k0 = -P.uhi; t.ky0 = -P.vhi;
     t.bxq = P.uhi - P.ulo + 1; t.byq = P.vhi - P.vlo + 1;
     t.mrow = (const int2*)(m + L.pol_mrow[q]);
-    t.qrow = (const short*)(m + L.pol_qrow[q]);
-    t.qcol = (const short*)(m + L.pol_qcol[q]);
     t.rhox = (const float2*)(m + L.pol_rhox[q]);
     t.rhoy = (const float2*)(m + L.pol_rhoy[q]);
     t.tx = (const float2*)(m + L.pol_tx[q]);

@@ -16,10 +16,9 @@ namespace dh {
 struct PolTab {
   int x0, y0;             // window origin in the frame (pixels)
   int k0, ky0;            // first row-pass bin / first column-pass bin of the box
-  int bxq, byq;           // this pol's own box size (<= KArgs bx, by)
+  int bxq, byq;           // this pol's own box size (<= KArgs bx, by); IFFT column q holds box
+                          // column j = (-k0 - q) mod wx if j < bxq, else none (rows alike)
   const int2* mrow;       // [by] mask interval of box row i in box columns (lo > hi: empty)
-  const short* qrow;      // [wy] box row held by IFFT row q (v mod wy), -1 if none
-  const short* qcol;      // [wx] box column held by IFFT column q (u mod wx), -1 if none
   const float2* rhox;     // [bx] sub-pixel beam-centre ramp along x
   const float2* rhoy;     // [by] same along y, times 1/(Nx Ny)
   const float2* tx;       // [wx] exp(i phi_R) along x (tilt + defocus)
