@@ -30,8 +30,30 @@ constexpr int kTPB = 256;
 typedef short shortx4 __attribute__((ext_vector_type(4)));
 typedef _Float16 halfx4 __attribute__((ext_vector_type(4)));
 
+// Streamed intermediates (t1 into the column pass, f2 written by the column
+// pass and read once by the field pass) use non-temporal loads and stores:
+// each element is touched once, and keeping it out of the caches measured a
+// few per cent faster. (Frame loads are ordinary: several load instructions
+// share each cache line.)
+typedef float floatx2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2 ld_nt(const float2* p) {
+  const floatx2 t = __builtin_nontemporal_load(reinterpret_cast<const floatx2*>(p));
+  return make_float2(t.x, t.y);
+}
+__device__ __forceinline__ void st_nt(float2* p, float2 v) {
+  const floatx2 t = {v.x, v.y};
+  __builtin_nontemporal_store(t, reinterpret_cast<floatx2*>(p));
+}
+// Pointers the compiler cannot place in the global address space (loaded from
+// memory, or a select between such pointers) would be accessed with flat
+// instructions, which also hold the LDS counter; the frames are always global.
 template <typename T>
-__device__ __forceinline__ float load_px(const T* p) { return (float)(*p); }
+using gptr = const __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> as_global(const T* p) { return (gptr<T>)p; }
+
+template <typename T>
+__device__ __forceinline__ float load_px(gptr<T> p) { return (float)(*p); }
 
 // round-to-nearest-even FP32 -> BF16 (finite inputs)
 __device__ __forceinline__ unsigned short bf16_rne(float x) {
@@ -60,12 +82,37 @@ __device__ __forceinline__ void stage_twiddles(float2* dst, const float2* __rest
   for (int e = tid; e < twn<N>(); e += TPB) dst[e] = src[e];
 }
 
+// A small table bound for LDS, held in registers between its loads and its
+// LDS stores: the loads are issued ahead of a kernel's main operand loads and
+// the stores wait only for them, so the table costs one memory latency that
+// overlaps the main loads. Entries [n, N) get `fill`; n >= 1.
+template <typename T, int N, int TPB>
+struct Staged {
+  static constexpr int IT = (N + TPB - 1) / TPB;
+  T v[IT];
+  __device__ __forceinline__ void load(const T* __restrict__ src, int n, int tid) {
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const int e = tid + i * TPB;
+      v[i] = src[e < n ? e : n - 1];
+    }
+  }
+  __device__ __forceinline__ void store(T* dst, int n, T fill, int tid) const {
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const int e = tid + i * TPB;
+      if (N % TPB == 0 || e < N) dst[e] = e < n ? v[i] : fill;
+    }
+  }
+};
+
 // ---------------------------------------------------------------------------
-// k_row: grid (ceil(ny / (2 TR)), npol, nb), TPB = TR * NX / R0 threads: TR
-// complex transforms of NX, each the pair of real rows (2t, 2t+1) packed as
-// re + i im. The first pass takes its operands straight from the frame.
+// k_row: grid (ceil(ny / (2 TR TT)), npol, nb), TPB = TR * NX / R0 threads;
+// TT row tiles per workgroup, each TR complex transforms of NX, each the pair
+// of real rows (2t, 2t+1) packed as re + i im. The first pass takes its
+// operands straight from the frame; all tiles' loads are issued up front.
 // t1[b][p][j][y] = sum_x I[y][x] e^{-2 pi i k x / NX}, k = k0 + j (mod NX)
-template <int NX, int TR, typename TIn>
+template <int NX, int TR, typename TIn, int TT>
 __global__ void __launch_bounds__(TR * NX / FftPlan<NX>::R0) k_row(KArgs A, const TIn* __restrict__ frames, int b0) {
   using L = Lds<NX>;
   using Q = Pass1<NX, TR, TR * NX / FftPlan<NX>::R0>;
@@ -77,44 +124,53 @@ __global__ void __launch_bounds__(TR * NX / FftPlan<NX>::R0) k_row(KArgs A, cons
   const int p = blockIdx.y;
   const int bl = blockIdx.z;                 // frame within the chunk
   const PolTab& P = A.pol[p];
-  const int ybase = blockIdx.x * (2 * TR);
   stage_twiddles<NX, TPB>(tws, A.tw_nx, tid);
   const TIn* fr = A.fptr ? static_cast<const TIn*>(A.fptr[b0 + bl]) : frames + (size_t)(b0 + bl) * A.frame_h * A.frame_w;
-  const TIn* win = fr + (size_t)P.y0 * A.frame_w + P.x0;
+  const gptr<TIn> win = as_global(fr) + ((size_t)P.y0 * A.frame_w + P.x0);
+  // the operands of every tile are requested up front: later tiles' loads are
+  // in flight while the earlier tiles' transforms run
+  float2 v[TT][Q::R0];
   {
     const int t = tid / Q::NB, b = tid % Q::NB;
-    const int y = ybase + 2 * t;
-    const TIn* r0 = win + (size_t)y * A.frame_w + b;
-    const TIn* r1 = r0 + A.frame_w;
-    const bool ok0 = y < A.ny, ok1 = y + 1 < A.ny;
-    float2 v[1][Q::R0];
 #pragma unroll
-    for (int r = 0; r < Q::R0; ++r) {
-      v[0][r].x = ok0 ? load_px(r0 + r * Q::NB) : 0.f;
-      v[0][r].y = ok1 ? load_px(r1 + r * Q::NB) : 0.f;
+    for (int tt = 0; tt < TT; ++tt) {
+      const int y = (blockIdx.x * TT + tt) * (2 * TR) + 2 * t;
+      const gptr<TIn> r0 = win + ((size_t)y * A.frame_w + b);
+      const gptr<TIn> r1 = r0 + A.frame_w;
+      const bool ok0 = y < A.ny, ok1 = y + 1 < A.ny;
+#pragma unroll
+      for (int r = 0; r < Q::R0; ++r) {
+        v[tt][r].x = ok0 ? load_px(r0 + r * Q::NB) : 0.f;
+        v[tt][r].y = ok1 ? load_px(r1 + r * Q::NB) : 0.f;
+      }
     }
-    fft_pass1_regs<NX, TR, L::STRIDE, TPB>(v, buf, tid);
   }
-  fft_rest<NX, TR, L::STRIDE, TPB>(buf, tws, tid);
-  // two-for-one split at the kept bins: both rows of a pair from Z[k], Z[NX-k]
   float2* out = A.t1 + (size_t)(bl * A.npol + p) * A.bx * A.ny;
-  for (int e = tid; e < TR * A.bx; e += TPB) {
-    const int t = e % TR, j = e / TR;
-    const int y = ybase + 2 * t;
-    if (y >= A.ny) continue;
-    int k = P.k0 + j;
-    k = (k >= NX) ? k - NX : (k < 0 ? k + NX : k);
-    const int km = (k == 0) ? 0 : NX - k;
-    const float2* tb = buf + t * L::STRIDE;
-    const float2 z1 = tb[L::at(k)];
-    const float2 z2 = conjf2(tb[L::at(km)]);
-    const float2 d = csub(z1, z2);
-    const float4 x = make_float4(0.5f * (z1.x + z2.x), 0.5f * (z1.y + z2.y), 0.5f * d.y, -0.5f * d.x);
-    float2* o = out + (size_t)j * A.ny + y;
-    if (y + 1 < A.ny) {
-      *reinterpret_cast<float4*>(o) = x;
-    } else {
-      *o = make_float2(x.x, x.y);
+#pragma unroll
+  for (int tt = 0; tt < TT; ++tt) {
+    const int ybase = (blockIdx.x * TT + tt) * (2 * TR);
+    if (tt > 0) __syncthreads();           // the previous tile's split has read buf
+    fft_pass1_regs<NX, TR, L::STRIDE, TPB>(v + tt, buf, tid);
+    fft_rest<NX, TR, L::STRIDE, TPB>(buf, tws, tid);
+    // two-for-one split at the kept bins: both rows of a pair from Z[k], Z[NX-k]
+    for (int e = tid; e < TR * A.bx; e += TPB) {
+      const int t = e % TR, j = e / TR;
+      const int y = ybase + 2 * t;
+      if (y >= A.ny) continue;
+      int k = P.k0 + j;
+      k = (k >= NX) ? k - NX : (k < 0 ? k + NX : k);
+      const int km = (k == 0) ? 0 : NX - k;
+      const float2* tb = buf + t * L::STRIDE;
+      const float2 z1 = tb[L::at(k)];
+      const float2 z2 = conjf2(tb[L::at(km)]);
+      const float2 d = csub(z1, z2);
+      const float4 x = make_float4(0.5f * (z1.x + z2.x), 0.5f * (z1.y + z2.y), 0.5f * d.y, -0.5f * d.x);
+      float2* o = out + (size_t)j * A.ny + y;
+      if (y + 1 < A.ny) {
+        *reinterpret_cast<float4*>(o) = x;
+      } else {
+        *o = make_float2(x.x, x.y);
+      }
     }
   }
 }
@@ -141,13 +197,17 @@ __global__ void __launch_bounds__(kTPB) k_col(KArgs A, int b0) {
   const int bl = blockIdx.z;
   const PolTab& P = A.pol[p];
   const int jc0 = blockIdx.x * CG;
-  stage_twiddles<NY, kTPB>(twy, A.tw_ny, tid);
-  stage_twiddles<WY, kTPB>(tww, A.tw_wy, tid);
-  for (int e = tid; e < WY; e += kTPB) {
-    s_mrow[e] = e < A.by ? P.mrow[e] : make_int2(1, 0);
-  }
-  for (int e = tid; e < WY; e += kTPB) s_cry[e] = e < A.by ? conjf2(P.rhoy[e]) : make_float2(0.f, 0.f);
-  if (tid < CG) s_crx[tid] = jc0 + tid < A.bx ? conjf2(P.rhox[jc0 + tid]) : make_float2(0.f, 0.f);
+  Staged<float2, twn<NY>(), kTPB> stwy;
+  Staged<float2, twn<WY>(), kTPB> stww;
+  Staged<int2, WY, kTPB> smr;
+  Staged<float2, WY, kTPB> scy;
+  Staged<float2, CG, kTPB> scx;
+  stwy.load(A.tw_ny, twn<NY>(), tid);
+  stww.load(A.tw_wy, twn<WY>(), tid);
+  smr.load(P.mrow, A.by, tid);
+  scy.load(P.rhoy, A.by, tid);
+  const int ncx = A.bx - jc0 < CG ? A.bx - jc0 : CG;
+  scx.load(P.rhox + jc0, ncx, tid);
   const float2* in = A.t1 + ((size_t)(bl * A.npol + p) * A.bx) * NY;
   {
     float2 v[Q::IT][Q::R0];
@@ -157,10 +217,22 @@ __global__ void __launch_bounds__(kTPB) k_col(KArgs A, int b0) {
       const int c = g / Q::NB, b = g % Q::NB;
       const int j = jc0 + c;
       const bool ok = (Q::TOTAL % kTPB == 0 || g < Q::TOTAL) && j < A.bx;
-      const float2* col = in + (size_t)j * NY + b;
+      const float2* col = in + (size_t)(ok ? j : 0) * NY + b;
 #pragma unroll
-      for (int r = 0; r < Q::R0; ++r) v[it][r] = ok ? col[r * Q::NB] : make_float2(0.f, 0.f);
+      for (int r = 0; r < Q::R0; ++r) {
+        const float2 f = ld_nt(col + r * Q::NB);
+        v[it][r] = ok ? f : make_float2(0.f, 0.f);
+      }
     }
+#pragma unroll
+    for (int i = 0; i < scy.IT; ++i) scy.v[i] = conjf2(scy.v[i]);
+#pragma unroll
+    for (int i = 0; i < scx.IT; ++i) scx.v[i] = conjf2(scx.v[i]);
+    stwy.store(twy, twn<NY>(), make_float2(0.f, 0.f), tid);
+    stww.store(tww, twn<WY>(), make_float2(0.f, 0.f), tid);
+    smr.store(s_mrow, A.by, make_int2(1, 0), tid);
+    scy.store(s_cry, A.by, make_float2(0.f, 0.f), tid);
+    scx.store(s_crx, ncx, make_float2(0.f, 0.f), tid);
     fft_pass1_regs<NY, CG, ST, kTPB>(v, buf, tid);
   }
   fft_rest<NY, CG, ST, kTPB>(buf, twy, tid);
@@ -205,10 +277,20 @@ __global__ void __launch_bounds__(kTPB) k_col(KArgs A, int b0) {
   __syncthreads();
   fft_lds<WY, CG, ST, kTPB>(buf, tww, tid);
   float2* out = A.f2 + ((size_t)(bl * A.npol + p) * WY) * A.bxp;
-  for (int e = tid; e < CG * WY; e += kTPB) {
+  constexpr int NO = (CG * WY + kTPB - 1) / kTPB;
+  float2 ov[NO];
+#pragma unroll
+  for (int it = 0; it < NO; ++it) {
+    const int e = tid + it * kTPB;
+    const int c = e % CG, l = e / CG;
+    if ((CG * WY) % kTPB == 0 || e < CG * WY) ov[it] = buf[c * ST + LW::at(l)];
+  }
+#pragma unroll
+  for (int it = 0; it < NO; ++it) {
+    const int e = tid + it * kTPB;
     const int c = e % CG, l = e / CG;
     const int j = jc0 + c;
-    if (j < A.bx) out[(size_t)l * A.bxp + j] = conjf2(buf[c * ST + LW::at(l)]);
+    if (((CG * WY) % kTPB == 0 || e < CG * WY) && j < A.bx) st_nt(out + (size_t)l * A.bxp + j, conjf2(ov[it]));
   }
 }
 
@@ -299,7 +381,7 @@ __global__ void __launch_bounds__(kTPB) k_gather(KArgs A, SpecRef S) {
   for (int e = tid; e < CG * WY; e += kTPB) {
     const int c = e % CG, l = e / CG;
     const int j = jc0 + c;
-    if (j < A.bx) out[(size_t)l * A.bxp + j] = conjf2(buf[c * ST + LW::at(l)]);
+    if (j < A.bx) st_nt(out + (size_t)l * A.bxp + j, conjf2(buf[c * ST + LW::at(l)]));
   }
 }
 
@@ -404,7 +486,6 @@ __global__ void __launch_bounds__(kTPB) k_fld(KArgs A, int b0) {
   __shared__ float bpow[4];
   __shared__ float2 tww[twn<WX>()];
   __shared__ float2 s_tx[WX];
-  __shared__ float2 s_ty[16];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const int rb = blockIdx.x;
@@ -433,32 +514,63 @@ __global__ void __launch_bounds__(kTPB) k_fld(KArgs A, int b0) {
       for (int r = 0; r < 4; ++r)
         uap[q][r] = P.uy[(rb * 16 + 4 * (lane >> 4) + r) * gp + ((q == 2) ? 16 : 0) + (lane & 15)];
   }
-  stage_twiddles<WX, kTPB>(tww, A.tw_wx, tid);
-  for (int e = tid; e < WX; e += kTPB) s_tx[e] = P.tx[e];
-  if (tid < 16) s_ty[tid] = (rb * 16 + tid < A.wy) ? P.ty[rb * 16 + tid] : make_float2(0.f, 0.f);
-  for (int e = tid; e < 16 * WX; e += kTPB) {
-    const int r = e / WX, q = e % WX;
-    const int y = rb * 16 + r;
-    float2 v = make_float2(0.f, 0.f);
-    if (y < A.wy) {
-      const int j = box_of(-P.k0, q, WX, P.bxq);
-      if (j >= 0) v = conjf2(in[(size_t)y * A.bxp + j]);
+  static_assert(WX % 16 == 0 && kTPB == 256, "tilt pass: 16 rows x 16 lanes");
+  Staged<float2, twn<WX>(), kTPB> stw;
+  Staged<float2, WX, kTPB> stx;
+  stw.load(A.tw_wx, twn<WX>(), tid);
+  stx.load(P.tx, WX, tid);
+  // tilt pass mapping: thread (row r_t, lane c_t) takes columns c_t + 16 k
+  const int r_t = tid >> 4, c_t = tid & 15;
+  const int y_t = rb * 16 + r_t;
+  const bool yok = y_t < A.wy;
+  const float2 tyr = P.ty[yok ? y_t : A.wy - 1];
+  {
+    // IFFT along x, first pass straight from f2: butterfly (row tr, b) takes
+    // IFFT columns q = b + NB s, i.e. box columns j = (u_hi - q) mod WX,
+    // conjugated (inverse transform as conj FFT conj)
+    using Q = Pass1<WX, 16, kTPB>;
+    float2 v[Q::IT][Q::R0];
+    const int uhi = -P.k0;
+#pragma unroll
+    for (int it = 0; it < Q::IT; ++it) {
+      const int g = tid + it * kTPB;
+      if (Q::TOTAL % kTPB == 0 || g < Q::TOTAL) {
+        const int tr = g / Q::NB, b = g % Q::NB;
+        const int y = rb * 16 + tr;
+        const bool rok = y < A.wy;
+        const float2* row = in + (size_t)(rok ? y : 0) * A.bxp;
+        int j = (uhi - b) % WX;
+        if (j < 0) j += WX;
+#pragma unroll
+        for (int s2 = 0; s2 < Q::R0; ++s2) {
+          const bool ok = rok && j < P.bxq;
+          const float2 f = ld_nt(row + (ok ? j : 0));
+          v[it][s2] = ok ? conjf2(f) : make_float2(0.f, 0.f);
+          j -= Q::NB;
+          if (j < 0) j += WX;
+        }
+      }
     }
-    buf[r * ST + L::at(q)] = v;
+    stw.store(tww, twn<WX>(), make_float2(0.f, 0.f), tid);
+    stx.store(s_tx, WX, make_float2(0.f, 0.f), tid);
+    fft_pass1_regs<WX, 16, ST, kTPB>(v, buf, tid);
   }
-  __syncthreads();
-  fft_lds<WX, 16, ST, kTPB>(buf, tww, tid);
-  float emax = 0.f;
-  for (int e = tid; e < 16 * WX; e += kTPB) {
-    const int r = e / WX, q = e % WX;
-    const int y = rb * 16 + r;
-    float2 ev = make_float2(0.f, 0.f);
-    if (y < A.wy) {
-      ev = cmul(cmul(conjf2(buf[r * ST + L::at(q)]), s_tx[q]), s_ty[r]);
-      if (fld) fld[(size_t)y * WX + q] = ev;
+  fft_rest<WX, 16, ST, kTPB>(buf, tww, tid);
+  float emax = 0.f, pw = 0.f;
+  {
+    float2* brow = buf + r_t * ST;
+#pragma unroll
+    for (int k = 0; k < WX / 16; ++k) {
+      const int q = c_t + 16 * k;
+      float2 ev = make_float2(0.f, 0.f);
+      if (yok) {
+        ev = cmul(cmul(conjf2(brow[L::at(q)]), s_tx[q]), tyr);
+        if (fld) fld[(size_t)y_t * WX + q] = ev;
+      }
+      brow[L::at(q)] = ev;
+      if constexpr (PREC == 2) emax = fmaxf(emax, fmaxf(fabsf(ev.x), fabsf(ev.y)));
+      pw = fmaf(ev.x, ev.x, fmaf(ev.y, ev.y, pw));   // field power of the block (FP32)
     }
-    buf[r * ST + L::at(q)] = ev;
-    if constexpr (PREC == 2) emax = fmaxf(emax, fmaxf(fabsf(ev.x), fabsf(ev.y)));
   }
   float sE = 1.f;
   if constexpr (PREC == 2) {
@@ -466,12 +578,6 @@ __global__ void __launch_bounds__(kTPB) k_fld(KArgs A, int b0) {
     if (lane == 0) bmax[wv] = emax;
   }
   if (A.capt) {
-    // field power of the block, sum |E|^2 (FP32 within a block)
-    float pw = 0.f;
-    for (int e = tid; e < 16 * WX; e += kTPB) {
-      const float2 ev = buf[(e / WX) * ST + L::at(e % WX)];
-      pw = fmaf(ev.x, ev.x, fmaf(ev.y, ev.y, pw));
-    }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) pw += __shfl_xor(pw, off, 64);
     if (lane == 0) bpow[wv] = pw;
@@ -727,11 +833,23 @@ static hipError_t row_n(const KArgs& a, const void* frames, int u16, int b0, int
   constexpr int TR = row_tr<NX>();
   constexpr int TPB = TR * NX / FftPlan<NX>::R0;
   static_assert(TPB % 64 == 0 && TPB <= 512, "row-pass block size");
-  dim3 grid((a.ny + 2 * TR - 1) / (2 * TR), a.npol, nb);
-  if (u16)
-    hipLaunchKernelGGL((k_row<NX, TR, unsigned short>), grid, dim3(TPB), 0, s, a, (const unsigned short*)frames, b0);
-  else
-    hipLaunchKernelGGL((k_row<NX, TR, float>), grid, dim3(TPB), 0, s, a, (const float*)frames, b0);
+  // two row tiles per workgroup (the second tile's loads overlap the first
+  // tile's transform) when that still leaves the chip well filled; one tile
+  // for small batches, where latency matters more
+  const int nyb = (a.ny + 2 * TR - 1) / (2 * TR);
+  const bool two = (long)((nyb + 1) / 2) * a.npol * nb >= 4096;
+  dim3 grid(two ? (nyb + 1) / 2 : nyb, a.npol, nb);
+  if (u16) {
+    if (two)
+      hipLaunchKernelGGL((k_row<NX, TR, unsigned short, 2>), grid, dim3(TPB), 0, s, a, (const unsigned short*)frames, b0);
+    else
+      hipLaunchKernelGGL((k_row<NX, TR, unsigned short, 1>), grid, dim3(TPB), 0, s, a, (const unsigned short*)frames, b0);
+  } else {
+    if (two)
+      hipLaunchKernelGGL((k_row<NX, TR, float, 2>), grid, dim3(TPB), 0, s, a, (const float*)frames, b0);
+    else
+      hipLaunchKernelGGL((k_row<NX, TR, float, 1>), grid, dim3(TPB), 0, s, a, (const float*)frames, b0);
+  }
   return hipGetLastError();
 }
 
