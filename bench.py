@@ -3,9 +3,11 @@
 
 One step = dh_process_batch over a batch of 1000 synthetic 640x512 float32
 frames, two polarisations (320x512 windows), HG groups G=9 (45 modes per
-pol), FP32 path: row FFT -> column FFT + window crop + IFFT along y ->
-IFFT along x + tilt/defocus removal + HG overlap -> FP64 power norm. Frames
-are resident in HBM before the timed region. Prints one JSON line.
+pol), plain FP32: row FFT -> column FFT + window crop -> (field path) IFFT
+along y, IFFT along x + tilt/defocus removal + HG overlap, or (spectral path,
+the default here) the window contracted with the folded IFFT/tilt/HG tables
+-> FP64 power norm. Frames are resident in HBM before the timed region.
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -26,27 +28,36 @@ METRIC = "frames/s (FFT→IFFT→HG coefs) 640×512 maxMG=9, vs FP32 plain; p50/
 HBM_PEAK_GBS = 8000.0
 
 
+def col_cg(ny):
+    """Box columns per column-pass workgroup (the library's rule)."""
+    return 4 if ny >= 1024 else 8 if ny >= 512 else 16
+
+
 def stage_bytes(info, params, frames):
     """Algorithmic bytes per launch stage for `frames` frames: what each
-    kernel must read and write (frame window in, its result out)."""
+    kernel must read and write (its input once, its result once)."""
     P = params["pol_count"]
     nx, ny, wx, wy = info.fft_w, info.fft_h, info.ifft_w, info.ifft_h
     bx = info.box_w
     px = 2 if params.get("input_dtype", "f32") == "u16" else 4
     nm = info.modes
+    spectral = info.path == 2
+    nblk = -(-bx // col_cg(ny)) if spectral else -(-wy // 16)
     return {
-        "fft_x": frames * P * ny * (nx * px + bx * 8),
-        "fft_y_crop_ifft_y": frames * P * bx * 8 * (ny + wy),
-        "ifft_x_tilt_overlap": frames * P * (wy * bx * 8 + nm * 8),
-        "power_norm": frames * P * nm * 16,
+        "row_fft": frames * P * ny * (nx * px + bx * 8),
+        # t1 columns in; f2 rows out (field) or per-column-block partials out (spectral)
+        "column_fft_window": frames * P * (bx * ny * 8 + (nblk * (nm + 1) * 8 if spectral else wy * bx * 8)),
+        "field_overlap": 0 if spectral else frames * P * (wy * bx * 8 + nblk * (nm + 1) * 8),
+        "power_norm": frames * P * (nblk + 2) * (nm + 1) * 8,
     }
 
 
-STAGE_KERNEL = {"fft_x": "dh::k_row", "fft_y_crop_ifft_y": "dh::k_col", "ifft_x_tilt_overlap": "dh::k_fld",
-                "power_norm": "dh::k_norm"}
+def stage_kernel(stage, info):
+    return {"row_fft": "dh::k_row", "column_fft_window": "dh::k_cspec" if info.path == 2 else "dh::k_col",
+            "field_overlap": "dh::k_fld", "power_norm": "dh::k_norm"}[stage]
 
 
-def counter_traffic(stage, frames_per_launch):
+def counter_traffic(stage, info, frames_per_launch):
     """HBM bytes per launch of `stage`'s kernel from the committed counter
     summary (profiles/traffic_c2_640x512.json), or None if the kernel sources
     changed since the counters were taken."""
@@ -58,18 +69,23 @@ def counter_traffic(stage, frames_per_launch):
     if t.get("fingerprint") != bench_traffic.source_fingerprint():
         return None
     for name, k in t["kernels"].items():
-        if name.startswith(STAGE_KERNEL[stage]):
+        if name.startswith(stage_kernel(stage, info)):
             return round((k["read_bytes_per_frame"] + k["write_bytes_per_frame"]) * frames_per_launch)
     return None
 
 
 def time_forms(dh, torch, cfg, ft, B, stream, steps=10, warmup=3):
-    """frames/s and overlap-kernel time of the three overlap forms (plain FP32,
-    split BF16, split FP16) on the same frames, at G=9 and G=20."""
+    """frames/s and per-stage time of the coefficient forms on the same frames,
+    at G=9 and G=20: plain FP32 on the field path and (where it applies) on
+    the spectral path, split BF16 and split FP16 (field path)."""
     out = {}
     for groups in (9, 20):
-        for prec in ("fp32", "split_bf16", "split_fp16"):
-            plan = dh.Plan(dict(cfg["params"], max_mg=groups, precision=prec), max_batch=B)
+        forms = [("fp32", "field"), ("fp32", "spectral"), ("split_bf16", "field"), ("split_fp16", "field")]
+        for prec, path in forms:
+            d = dict(cfg["params"], max_mg=groups, precision=prec, path=path)
+            if dh.plan_check(d, B)[0] != dh.SUCCESS:
+                continue
+            plan = dh.Plan(d, max_batch=B)
             for _ in range(warmup):
                 plan.process(ft, B, stream)
             stream.synchronize()
@@ -83,8 +99,9 @@ def time_forms(dh, torch, cfg, ft, B, stream, steps=10, warmup=3):
             st = plan.stage_times()
             plan.destroy()
             ms = e0.elapsed_time(e1)
-            out[f"G{groups}_{prec}"] = {"frames_per_s": round(steps * B / (ms / 1e3), 1),
-                                        "overlap_kernel_ms": round(st["ifft_x_tilt_overlap"][0] / steps, 4)}
+            out[f"G{groups}_{prec}_{path}"] = {
+                "frames_per_s": round(steps * B / (ms / 1e3), 1),
+                "stages_ms": {k: round(v[0] / steps, 4) for k, v in st.items() if v[1]}}
     return out
 
 
@@ -283,7 +300,7 @@ def main():
     frames_per_launch = B / (n_dom / args.steps)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": counter_traffic(dom, frames_per_launch) if B == 1000 else None,
+                "traffic": counter_traffic(dom, info, frames_per_launch) if B == 1000 else None,
                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "algorithmic_bytes": round(per_launch_bytes), "kernel": dom,
                 "launch_ms": round(ms_dom / n_dom, 4), "launches_per_step": n_dom // args.steps}
@@ -294,8 +311,9 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "1000 frames 640x512 f32, 2 pols (320x512 windows), G=9 (45 modes/pol), "
-                               "defocus, shot+read noise; plain FP32 path",
-                   "frames": B, "frame": "640x512", "pols": 2, "max_mg": 9, "precision": "fp32"},
+                               "defocus, shot+read noise; plain FP32",
+                   "frames": B, "frame": "640x512", "pols": 2, "max_mg": 9, "precision": "fp32",
+                   "path": {1: "field", 2: "spectral"}[info.path]},
         "p50_ms": round(float(np.percentile(lat, 50)), 4), "p99_ms": round(float(np.percentile(lat, 99)), 4),
         "stages_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in stages.items()},
         "path_hbm_frac": round(frame_bytes * value / 1e9 / HBM_PEAK_GBS, 4),

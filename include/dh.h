@@ -53,6 +53,23 @@ extern "C" {
 #define DH_PREC_SPLIT_BF16 1 /* HG overlap as split hi/lo BF16 MFMA, FP32 accumulate */
 #define DH_PREC_SPLIT_FP16 2 /* HG overlap as split hi/lo FP16 MFMA, FP32 accumulate */
 
+/* How the coefficients are formed from the masked spectrum (dh_params.path).
+ * Both give the same c_mn up to rounding: the inverse DFT of the window, the
+ * tilt/defocus removal and the HG quadrature are linear maps, so
+ *   c_mn = sum_{u,v} W(u,v) X_m(u) Y_n(v),
+ *   X_m(u) = sum_k e^{i phi_x(x'_k)} u_m(x'_k) p'_x e^{2 pi i u x'_k / (Nx p)}
+ * (Y alike), with W the masked, normalised window of the cross term.
+ *   FIELD:    inverse FFT to the field, tilt/defocus removal, overlap
+ *             (the paper's order; needed for dh_get_fields and the split
+ *             precision forms).
+ *   SPECTRAL: the window contracted with the FP64-built tables X and Y on
+ *             FP32 MFMA; no field is formed.
+ *   AUTO:     SPECTRAL for the FP32 form without keep_fields where this build
+ *             provides it (G <= 16 and ceil(W_y / 16) <= 16), else FIELD. */
+#define DH_PATH_AUTO 0
+#define DH_PATH_FIELD 1
+#define DH_PATH_SPECTRAL 2
+
 typedef struct dh_c64 {
   float re, im;
 } dh_c64;
@@ -79,6 +96,8 @@ typedef struct dh_params {
   int ifft_mode;              /* 1: IFFT at the Fourier-window size (the only mode built) */
   int keep_window;            /* nonzero: store each frame's Fourier window (dh_get_window) */
   int keep_fields;            /* nonzero: store each frame's field (dh_get_fields) */
+  int path;                   /* DH_PATH_*; SPECTRAL with keep_fields, a split precision or
+                                 a size it does not cover is DH_ERR_INVALIDARGUMENT */
 } dh_params;
 
 /* Geometry derived by the plan (all FP64 on the host). */
@@ -94,6 +113,7 @@ typedef struct dh_plan_info {
   double pitch_x, pitch_y;    /* field sample pitch p' = N p / W, m */
   size_t device_bytes;        /* device memory the plan allocates */
   int chunk;                  /* frames per internal launch chunk */
+  int path;                   /* DH_PATH_FIELD or DH_PATH_SPECTRAL: the path the plan runs */
 } dh_plan_info;
 
 /*
@@ -105,8 +125,9 @@ typedef struct dh_plan_info {
  *                             this build does not provide;
  *   DH_ERR_INVALIDPOLARISATION pol_count not 1 or 2;
  *   DH_ERR_INVALIDARGUMENT    pixel/wavelength/radius/waist not > 0, max_mg outside
- *                             0..32, unknown dtype/precision/ifft_mode, or a Fourier
- *                             window wider than the spectrum.
+ *                             0..32, unknown dtype/precision/ifft_mode/path, a Fourier
+ *                             window wider than the spectrum, or DH_PATH_SPECTRAL
+ *                             where it does not apply (see DH_PATH_*).
  * max_batch < 1 is taken as 1 (the paper clamps batchCount the same way).
  */
 int dh_plan_check(const dh_params* p, int max_batch, dh_plan_info* info);
@@ -175,8 +196,9 @@ int dh_get_plan_info(dh_handle h, dh_plan_info* out);
  * the summed milliseconds and the number of launches since timing was
  * enabled or last read, then starts a new count. Stages:
  *   0 DH_STAGE_FFT   frame load + FFT along x (row pass)
- *   1 DH_STAGE_CROP  FFT along y + window crop/mask + IFFT along y
- *   2 DH_STAGE_FIELD IFFT along x + tilt/defocus removal + HG overlap
+ *   1 DH_STAGE_CROP  FFT along y + window crop/mask, then the IFFT along y (field
+ *                    path) or the contraction with the folded tables (spectral path)
+ *   2 DH_STAGE_FIELD IFFT along x + tilt/defocus removal + HG overlap (field path)
  *   3 DH_STAGE_NORM  per-frame FP64 power normalisation
  * ms and launches point to DH_STAGE_COUNT entries each.
  */

@@ -33,6 +33,9 @@ INPUT_U16 = 1
 PREC_FP32 = 0
 PREC_SPLIT_BF16 = 1
 PREC_SPLIT_FP16 = 2
+PATH_AUTO = 0
+PATH_FIELD = 1
+PATH_SPECTRAL = 2
 
 EXPORTS = ["dh_plan_check", "dh_plan", "dh_process_batch", "dh_mode_coefs", "dh_get_window",
            "dh_get_fields", "dh_get_params", "dh_get_plan_info", "dh_set_stage_timing", "dh_stage_times",
@@ -41,7 +44,10 @@ EXPORTS = ["dh_plan_check", "dh_plan", "dh_process_batch", "dh_mode_coefs", "dh_
            "dh_last_error", "dh_destroy"]
 ALIGN_FULL, ALIGN_TWEAK, ALIGN_ESTIMATE = 0, 1, 2
 ALIGN_TILT, ALIGN_DEFOCUS, ALIGN_WAIST, ALIGN_CENTRE = 1, 2, 4, 8
-STAGES = ["fft_x", "fft_y_crop_ifft_y", "ifft_x_tilt_overlap", "power_norm"]
+# launch stages (DH_STAGE_*): row pass; column pass (FFT along y + window,
+# then the IFFT along y on the field path or the contraction with the folded
+# tables on the spectral path); field pass (field path only); power norm
+STAGES = ["row_fft", "column_fft_window", "field_overlap", "power_norm"]
 
 
 class DhError(RuntimeError):
@@ -58,7 +64,7 @@ class Params(C.Structure):
         ("beam_centre", (C.c_double * 2) * 2), ("window_radius_deg", C.c_double),
         ("tilt_deg", (C.c_double * 2) * 2), ("defocus", C.c_double * 2), ("waist", C.c_double),
         ("max_mg", C.c_int), ("input_dtype", C.c_int), ("precision", C.c_int),
-        ("ifft_mode", C.c_int), ("keep_window", C.c_int), ("keep_fields", C.c_int),
+        ("ifft_mode", C.c_int), ("keep_window", C.c_int), ("keep_fields", C.c_int), ("path", C.c_int),
     ]
 
 
@@ -74,7 +80,7 @@ class PlanInfo(C.Structure):
         ("x0", C.c_int * 2), ("y0", C.c_int * 2),
         ("ax", C.c_double * 2), ("ay", C.c_double * 2), ("rx", C.c_double), ("ry", C.c_double),
         ("pitch_x", C.c_double), ("pitch_y", C.c_double),
-        ("device_bytes", C.c_size_t), ("chunk", C.c_int),
+        ("device_bytes", C.c_size_t), ("chunk", C.c_int), ("path", C.c_int),
     ]
 
 
@@ -126,10 +132,13 @@ _PRECS = {"fp32": PREC_FP32, "split_bf16": PREC_SPLIT_BF16, "split_fp16": PREC_S
           PREC_FP32: PREC_FP32, PREC_SPLIT_BF16: PREC_SPLIT_BF16, PREC_SPLIT_FP16: PREC_SPLIT_FP16}
 
 
+_PATHS = {"auto": PATH_AUTO, "field": PATH_FIELD, "spectral": PATH_SPECTRAL}
+
+
 def make_params(d: dict) -> Params:
     """dh_params from a dict with the field names of include/dh.h (the
     recipes' keys); input_dtype 'f32'/'u16', precision 'fp32'/'split_bf16'/
-    'split_fp16' or the numeric codes."""
+    'split_fp16', path 'auto'/'field'/'spectral' or the numeric codes."""
     p = Params()
     p.frame_w, p.frame_h, p.pol_count = d["frame_w"], d["frame_h"], d["pol_count"]
     p.fft_w, p.fft_h = d["fft_w"], d["fft_h"]
@@ -148,6 +157,8 @@ def make_params(d: dict) -> Params:
     p.ifft_mode = d.get("ifft_mode", 1)
     p.keep_window = int(bool(d.get("keep_window", 0)))
     p.keep_fields = int(bool(d.get("keep_fields", 0)))
+    pa = d.get("path", "auto")
+    p.path = pa if isinstance(pa, int) else _PATHS[pa]
     return p
 
 

@@ -50,8 +50,17 @@ struct PolGeom {
 struct Geom {
   int nx, ny, wx, wy, wyp, bx, by, G, gp, nmodes;
   double rx, ry, pxp, pyp;
+  bool spec = false;     // the plan runs the spectral path (DH_PATH_SPECTRAL)
+  int byp = 16;          // by rounded up to 16
   PolGeom pol[2];
 };
+
+// blocks with a coefficient partial per frame and pol: 16-row field blocks
+// (field path, also used by alignment) or column blocks (spectral path)
+int field_blocks(const Geom& g) { return g.wyp / 16; }
+int partial_blocks(const Geom& g) {
+  return g.spec ? std::max(field_blocks(g), dh::spectral_blocks(g.ny, g.bx)) : field_blocks(g);
+}
 
 bool inside(double u, double v, double ax, double ay, double rx, double ry) {
   const double a = (u + ax) / rx, b = (v + ay) / ry;
@@ -114,6 +123,7 @@ int derive(const dh_params* p, Geom* g) {
   if (p->precision != DH_PREC_FP32 && p->precision != DH_PREC_SPLIT_BF16 && p->precision != DH_PREC_SPLIT_FP16)
     return DH_ERR_INVALIDARGUMENT;
   if (p->ifft_mode != 1) return DH_ERR_INVALIDARGUMENT;
+  if (p->path < DH_PATH_AUTO || p->path > DH_PATH_SPECTRAL) return DH_ERR_INVALIDARGUMENT;
   for (int q = 0; q < p->pol_count; ++q) {
     for (int a = 0; a < 2; ++a)
       if (!std::isfinite(p->tilt_deg[q][a]) || !std::isfinite(p->beam_centre[q][a])) return DH_ERR_INVALIDARGUMENT;
@@ -144,6 +154,11 @@ int derive(const dh_params* p, Geom* g) {
     if (e != DH_SUCCESS) return e;
   }
   if (!dh::sizes_supported(nx, ny, g->wx, g->wy)) return DH_ERR_INVALIDDIMENSION;
+  g->byp = (g->by + 15) / 16 * 16;
+  const bool can_spec = p->precision == DH_PREC_FP32 && !p->keep_fields && g->G > 0 &&
+                        dh::spectral_supported(ny, g->wy, g->gp);
+  if (p->path == DH_PATH_SPECTRAL && !can_spec) return DH_ERR_INVALIDARGUMENT;
+  g->spec = p->path == DH_PATH_SPECTRAL || (p->path == DH_PATH_AUTO && can_spec);
   return DH_SUCCESS;
 }
 
@@ -184,6 +199,7 @@ struct Layout {  // byte offsets inside one device allocation
   size_t tw_nx, tw_ny, tw_wx, tw_wy, modes, total_tables;
   size_t pol_mrow[2], pol_rhox[2], pol_rhoy[2], pol_tx[2], pol_ty[2], pol_ux[2], pol_uy[2];
   size_t pol_uxs[2][4], pol_uys[2][4];   // split tables: bf16 hi, bf16 lo, fp16 hi, fp16 lo
+  size_t pol_xs[2], pol_ys[2];           // spectral path tables
   size_t t1[4], f2[4], partial[4], capt, coefs, coefs_norm, window, fields, total;
 };
 
@@ -208,13 +224,15 @@ Layout layout(const Geom& g, const dh_params* p, int max_batch, int chunk, int n
       L.pol_uxs[q][t] = take((size_t)g.wx * g.gp * 2);
       L.pol_uys[q][t] = take((size_t)g.wyp * g.gp * 2);
     }
+    L.pol_xs[q] = take(g.spec ? (size_t)g.bx * g.gp * 8 : 0);
+    L.pol_ys[q] = take(g.spec ? (size_t)g.byp * g.gp * 8 : 0);
   }
   const size_t P = p->pol_count;
   const size_t nm = g.nmodes > 0 ? g.nmodes : 1;
   for (int w = 0; w < nws; ++w) {
     L.t1[w] = take((size_t)chunk * P * g.ny * g.bx * 8);
     L.f2[w] = take((size_t)chunk * P * g.wy * ((g.bx + 15) / 16 * 16) * 8);
-    L.partial[w] = take((size_t)chunk * P * (g.wyp / 16) * (nm + 1) * 8);
+    L.partial[w] = take((size_t)chunk * P * partial_blocks(g) * (nm + 1) * 8);
   }
   L.capt = take((size_t)max_batch * P * 2 * 8);
   L.coefs = take((size_t)max_batch * P * nm * 8);
@@ -305,7 +323,84 @@ double hg_fp16_scale(double waist, double pitch) {
   return std::ldexp(1.0, 14 - e);
 }
 
-int build_tables(Plan* pl, bool hg = true) {
+// u_n(x'_k) p' for k < w, n < G (FP64, the normalised Hermite recurrence of
+// k_hg), [k][n]
+std::vector<double> hg_host(double pitch, int w, double waist, int G) {
+  std::vector<double> t((size_t)w * std::max(G, 1), 0.0);
+  const double scale = std::pow(2.0, 0.25) / std::sqrt(waist) * pitch;
+  for (int k = 0; k < w; ++k) {
+    const double s = std::sqrt(2.0) * (k - 0.5 * w) * pitch / waist;
+    double prev = 0.0, cur = std::pow(kPi, -0.25) * std::exp(-0.5 * s * s);
+    for (int n = 0; n < G; ++n) {
+      t[(size_t)k * G + n] = cur * scale;
+      const double nxt = std::sqrt(2.0 / (n + 1)) * s * cur - std::sqrt((double)n / (n + 1)) * prev;
+      prev = cur;
+      cur = nxt;
+    }
+  }
+  return t;
+}
+
+// Spectral path tables (FP64, stored FP32): the inverse DFT along one axis,
+// the tilt/defocus phase, the HG quadrature weights, the sub-pixel centre
+// ramp (and along y the 1/(Nx Ny) of the inverse transform) folded into
+//   t[j][m] = rho(j) sum_k e^{i phi(k)} u_m(x'_k) p' e^{2 pi i u_j k / W},  u_j = u_hi - j.
+std::vector<float2> spectral_axis(int nbox, int npad, int gp, int G, int uhi, int w, double pitch, double tilt_bins,
+                                  double defocus, double lam, double sub, double pix, int nfft, double norm,
+                                  const std::vector<double>& hg) {
+  std::vector<cd> ph(w), root(w);
+  for (int k = 0; k < w; ++k) {
+    const double x = (k - w / 2.0) * pitch;
+    ph[k] = std::exp(cd(0, 2.0 * kPi * tilt_bins * (k - w / 2.0) / w + kPi * defocus * x * x / lam));
+    root[k] = std::exp(cd(0, 2.0 * kPi * k / w));
+  }
+  std::vector<float2> t((size_t)npad * gp, make_float2(0.f, 0.f));
+  std::vector<cd> acc(G);
+  for (int j = 0; j < nbox; ++j) {
+    const long long u = uhi - j;
+    std::fill(acc.begin(), acc.end(), cd(0, 0));
+    for (int k = 0; k < w; ++k) {
+      long long e = (u * k) % w;
+      if (e < 0) e += w;
+      const cd f = ph[k] * root[(size_t)e];
+      const double* h = hg.data() + (size_t)k * G;
+      for (int m = 0; m < G; ++m) acc[m] += f * h[m];
+    }
+    const cd rho = std::exp(cd(0, 2.0 * kPi * (double)u * sub / (pix * nfft))) * norm;
+    for (int m = 0; m < G; ++m) {
+      const cd v = rho * acc[m];
+      t[(size_t)j * gp + m] = make_float2((float)v.real(), (float)v.imag());
+    }
+  }
+  return t;
+}
+
+int build_spectral(Plan* pl) {
+  const Geom& g = pl->g;
+  if (!g.spec) return DH_SUCCESS;
+  const dh_params* p = &pl->params;
+  const Layout& L = pl->L;
+  const double waist = p->waist > 0 ? p->waist : 1.0;
+  const std::vector<double> hx = hg_host(g.pxp, g.wx, waist, g.G), hy = hg_host(g.pyp, g.wy, waist, g.G);
+  for (int q = 0; q < p->pol_count; ++q) {
+    const PolGeom& P = g.pol[q];
+    const std::vector<float2> xs =
+        spectral_axis(g.bx, g.bx, g.gp, g.G, P.uhi, g.wx, g.pxp, P.ax, p->defocus[q], p->wavelength, P.dx,
+                      p->pixel_size, g.nx, 1.0, hx);
+    const std::vector<float2> ys =
+        spectral_axis(g.by, g.byp, g.gp, g.G, P.vhi, g.wy, g.pyp, P.ay, p->defocus[q], p->wavelength, P.dy,
+                      p->pixel_size, g.ny, 1.0 / ((double)g.nx * g.ny), hy);
+    if (hipMemcpy(pl->mem + L.pol_xs[q], xs.data(), xs.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(pl->mem + L.pol_ys[q], ys.data(), ys.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess)
+      return DH_ERR_ERROR;
+  }
+  return DH_SUCCESS;
+}
+
+// Device tables of the current parameters. hg: also the HG tables (a new
+// waist); spec: also the spectral path tables (alignment trials, which run
+// the field path, skip them).
+int build_tables(Plan* pl, bool hg = true, bool spec = true) {
   ++pl->version;
   const Geom& g = pl->g;
   const dh_params* p = &pl->params;
@@ -355,6 +450,10 @@ int build_tables(Plan* pl, bool hg = true) {
     put(host, L.pol_ty[q], ty);
   }
   if (hipMemcpy(pl->mem, host.data(), L.total_tables, hipMemcpyHostToDevice) != hipSuccess) return DH_ERR_ERROR;
+  if (spec) {
+    const int e = build_spectral(pl);
+    if (e != DH_SUCCESS) return e;
+  }
   if (!hg) return DH_SUCCESS;
   const double waist = p->waist > 0 ? p->waist : 1.0;
   pl->s_uh = (float)hg_fp16_scale(waist, std::max(g.pxp, g.pyp));
@@ -388,6 +487,8 @@ void fill_kargs(Plan* pl, int w) {
   a.capt = nullptr;
   a.cell = g.pxp * g.pyp;
   a.fptr = nullptr;
+  a.byp = g.byp;
+  a.spow = (float)((double)g.wx * g.wy / (((double)g.nx * g.ny) * ((double)g.nx * g.ny)));
   for (int q = 0; q < p->pol_count; ++q) {
     const PolGeom& P = g.pol[q];
     dh::PolTab& t = a.pol[q];
@@ -409,6 +510,8 @@ void fill_kargs(Plan* pl, int w) {
     t.uy_bl = (const unsigned short*)(m + L.pol_uys[q][1]);
     t.uy_hh = (const _Float16*)(m + L.pol_uys[q][2]);
     t.uy_hl = (const _Float16*)(m + L.pol_uys[q][3]);
+    t.xs = (const float2*)(m + L.pol_xs[q]);
+    t.ys = (const float2*)(m + L.pol_ys[q]);
   }
   a.modes = (const short2*)(m + L.modes);
   a.tw_nx = (const float2*)(m + L.tw_nx);
@@ -418,7 +521,7 @@ void fill_kargs(Plan* pl, int w) {
   a.t1 = (float2*)(m + L.t1[w]);
   a.f2 = (float2*)(m + L.f2[w]);
   a.partial = (float2*)(m + L.partial[w]);
-  a.nblk = g.wyp / 16;
+  a.nblk = g.spec ? dh::spectral_blocks(g.ny, g.bx) : field_blocks(g);
   a.coefs = (float2*)(m + L.coefs);
   a.coefs_norm = (float2*)(m + L.coefs_norm);
   a.window = p->keep_window ? (float2*)(m + L.window) : nullptr;
@@ -479,6 +582,7 @@ int dh_plan_check(const dh_params* p, int max_batch, dh_plan_info* info) {
     info->pitch_x = g.pxp; info->pitch_y = g.pyp;
     info->device_bytes = L.total;
     info->chunk = chunk;
+    info->path = g.spec ? DH_PATH_SPECTRAL : DH_PATH_FIELD;
   }
   return DH_SUCCESS;
 }
@@ -558,9 +662,9 @@ int dh_process_batch(dh_handle h, const void* frames, int batch, void* stream) {
               dh::launch_row(a, frames, u16, b0, nb, st) == hipSuccess &&
               timed_event(pl, st, DH_STAGE_FFT, false) == hipSuccess &&
               timed_event(pl, st, DH_STAGE_CROP, true) == hipSuccess &&
-              dh::launch_col(a, b0, nb, st) == hipSuccess &&
+              (pl->g.spec ? dh::launch_cspec(a, b0, nb, st) : dh::launch_col(a, b0, nb, st)) == hipSuccess &&
               timed_event(pl, st, DH_STAGE_CROP, false) == hipSuccess;
-    if (ok && (a.G > 0 || a.fields))
+    if (ok && !pl->g.spec && (a.G > 0 || a.fields))
       ok = timed_event(pl, st, DH_STAGE_FIELD, true) == hipSuccess && dh::launch_fld(a, b0, nb, st) == hipSuccess &&
            timed_event(pl, st, DH_STAGE_FIELD, false) == hipSuccess;
     if (ok && a.G > 0)
@@ -725,10 +829,11 @@ bool align_eval(AlignCtx& c, bool hg, double mp[2], double fp[2]) {
     offi[q] = -g.pol[q].vhi - c.ky0e[q];
     if (offj[q] < 0 || offj[q] + g.bx > c.bxe || offi[q] < 0 || offi[q] + g.by > c.bye) return false;
   }
-  if (build_tables(pl, hg) != DH_SUCCESS) return false;
+  if (build_tables(pl, hg, false) != DH_SUCCESS) return false;
   for (int w = 0; w < pl->nws; ++w) fill_kargs(pl, w);
   dh::KArgs k = pl->ka[0];
   k.capt = c.capt;
+  k.nblk = field_blocks(g);      // trials run the field path
   const size_t per_frame = (size_t)np * c.bxe * c.bye;
   for (int b0 = 0; b0 < c.batch; b0 += pl->chunk) {
     const int nb = std::min(pl->chunk, c.batch - b0);
@@ -934,6 +1039,7 @@ extern "C" float dh_autoalign(dh_handle h, const void* frames, int batch, int mo
   }
   // leave the plan at the final parameters with complete tables
   if (!align_eval(c, true, mp, fp)) return (P = start, build_tables(pl), set_err(pl, DH_ERR_ERROR), -FLT_MAX);
+  if (build_spectral(pl) != DH_SUCCESS) return (P = start, build_tables(pl), set_err(pl, DH_ERR_ERROR), -FLT_MAX);
   goal = db(mp[0] + (np > 1 ? mp[1] : 0.0), fp[0] + (np > 1 ? fp[1] : 0.0));
   for (int w = 0; w < pl->nws; ++w) fill_kargs(pl, w);
   rep.goal_db = goal;
@@ -1025,8 +1131,9 @@ size_t lane_layout(const Plan* pl, int mb, size_t off[6]) {
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o += align256(bytes); return r; };
   off[0] = take((size_t)mb * P * g.ny * g.bx * 8);                  // t1
-  off[1] = take((size_t)mb * P * g.wy * ((g.bx + 15) / 16 * 16) * 8);  // f2
-  off[2] = take((size_t)mb * P * (g.wyp / 16) * (nm + 1) * 8);       // partial
+  off[1] = take(g.spec ? 0 : (size_t)mb * P * g.wy * ((g.bx + 15) / 16 * 16) * 8);  // f2
+  const int nblk = g.spec ? dh::spectral_blocks(g.ny, g.bx) : field_blocks(g);
+  off[2] = take((size_t)mb * P * nblk * (nm + 1) * 8);               // partial
   off[3] = take((size_t)mb * P * nm * 8);                            // coefs
   off[4] = take((size_t)mb * P * nm * 8);                            // coefs_norm
   off[5] = take((size_t)mb * 8);                                     // frame pointers
@@ -1081,9 +1188,10 @@ void lane_args(const Camera& C, Lane& L) {
 
 hipError_t record_batch(const Camera& C, const Lane& L, int n) {
   const int u16 = C.pl->params.input_dtype == DH_INPUT_U16;
+  const bool spec = C.pl->g.spec;
   hipError_t e = dh::launch_row(L.k, nullptr, u16, 0, n, L.s);
-  if (e == hipSuccess) e = dh::launch_col(L.k, 0, n, L.s);
-  if (e == hipSuccess && L.k.G > 0) e = dh::launch_fld(L.k, 0, n, L.s);
+  if (e == hipSuccess) e = spec ? dh::launch_cspec(L.k, 0, n, L.s) : dh::launch_col(L.k, 0, n, L.s);
+  if (e == hipSuccess && !spec && L.k.G > 0) e = dh::launch_fld(L.k, 0, n, L.s);
   if (e == hipSuccess && L.k.G > 0) e = dh::launch_norm(L.k, 0, n, L.s);
   return e;
 }

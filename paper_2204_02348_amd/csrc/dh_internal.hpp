@@ -35,6 +35,14 @@ struct PolTab {
   const _Float16* ux_hl;
   const _Float16* uy_hh;
   const _Float16* uy_hl;
+  // spectral path: the HG overlap, tilt/defocus, centre ramps and 1/(Nx Ny)
+  // folded into two tables over the box (FP64-built, FP32):
+  //   xs[j][m] = rho_x(j) sum_k tx[k] ux[k][m] e^{2 pi i u_j k / wx}, u_j = -(k0 + j)
+  //   ys[i][n] = rho_y(i) sum_l ty[l] uy[l][n] e^{2 pi i v_i l / wy}, v_i = -(ky0 + i)
+  // so that c_mn = sum_{j,i} mask(j,i) conj(S[j][i]) xs[j][m] ys[i][n], S the
+  // column-pass spectrum at box (j, i)
+  const float2* xs;       // [bx][gp]
+  const float2* ys;       // [byp][gp], zero rows i >= by
 };
 
 struct KArgs {
@@ -59,7 +67,10 @@ struct KArgs {
                             // then the block's field power sum |E|^2 (if capt)
   double* capt;             // [max_batch][P][2] mode power, field power (FP64), or null
   double cell;              // p'_x p'_y, the field power's quadrature weight
-  int nblk;                 // 16-row blocks of the field (wyp / 16)
+  int nblk;                 // blocks with a partial per frame and pol: 16-row blocks of the
+                            // field (wyp / 16), or column blocks of the spectral path
+  int byp;                  // by rounded up to 16 (spectral path contraction length)
+  float spow;               // spectral path: wx wy / (Nx Ny)^2, field power per |S|^2
   float2* coefs;            // [max_batch][P][nmodes] raw coefficients
   float2* coefs_norm;       // [max_batch][P][nmodes] power-normalised
   float2* window;           // [max_batch][P][wy][wx] or null
@@ -72,6 +83,11 @@ hipError_t launch_row(const KArgs& a, const void* frames, int u16, int b0, int n
 hipError_t launch_col(const KArgs& a, int b0, int nb, hipStream_t s);
 hipError_t launch_fld(const KArgs& a, int b0, int nb, hipStream_t s);
 hipError_t launch_norm(const KArgs& a, int b0, int nb, hipStream_t s);
+// spectral path: column FFT + masked window contracted with the xs / ys
+// tables into per-column-block partials (replaces launch_col + launch_fld)
+bool spectral_supported(int ny, int wy, int gp);
+int spectral_blocks(int ny, int bx);     // column blocks per frame and pol
+hipError_t launch_cspec(const KArgs& a, int b0, int nb, hipStream_t s);
 hipError_t launch_zero(float2* p, size_t n, hipStream_t s);
 // alignment: column FFT of an extended box stored as spec[b][p][j][i] (nrow rows
 // from ky0); gather of the current window from it; batch power spectrum

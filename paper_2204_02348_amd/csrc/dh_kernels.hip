@@ -295,6 +295,192 @@ __global__ void __launch_bounds__(kTPB) k_col(KArgs A, int b0) {
 }
 
 // ---------------------------------------------------------------------------
+// k_cspec (spectral path): grid (ceil(bx / CG), npol, nb). The column FFT as
+// in k_col, then the block's masked window contracted with the folded tables
+// (PolTab::xs, ys):
+//   Q[j][n] = sum_i mask(j, i) conj(S[j][i]) ys[i][n]   FP32 MFMA, K = box rows
+//   c[m][n] = sum_j xs[j][m] Q[j][n]                    this block's share
+// MFMA operands (16x16x4): A row r = part CG + j (part 0: Re S, 1: Im S) in
+// tiles of 16 rows, column k = box row i = 4 s + k of step s; the steps go to
+// the four waves round robin. B = Re ys and Im ys of the same rows. With
+// S = a + ib and ys = c + id, conj(S) ys = (ac + bd) + i(ad - bc).
+// The block's field power follows from Parseval: sum |E|^2 = wx wy sum |S|^2 / (Nx Ny)^2.
+template <int NY, int WY, int CG, int NT>
+__global__ void __launch_bounds__(kTPB) k_cspec(KArgs A, int b0) {
+  using LN = Lds<NY>;
+  using Q = Pass1<NY, CG, kTPB>;
+  constexpr int ST = LN::STRIDE;
+  constexpr int MT = (2 * CG + 15) / 16;          // A-row tiles
+  constexpr int WYP = (WY + 15) / 16 * 16;
+  constexpr int KSW = WYP / 16;                    // K steps per wave, at most
+  constexpr int GP = 16 * NT;
+  constexpr int NRED = 4 * MT * NT * 2 * 256;      // floats: the waves' MFMA results
+  constexpr int NQ = CG * GP;                      // float2: Q
+  constexpr bool IN_BUF = NRED * 4 + NQ * 8 <= CG * ST * 8;
+  static_assert(KSW * NT <= 16, "B operands are held in registers");
+  __shared__ float2 buf[CG * ST];
+  __shared__ float2 twy[twn<NY>()];
+  __shared__ int2 s_mrow[WYP];
+  __shared__ float2 s_x[CG * GP];                  // xs rows of the block's columns
+  __shared__ float s_pw[4];
+  __shared__ float2 s_spill[IN_BUF ? 1 : (NRED / 2 + NQ)];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int p = blockIdx.y;
+  const int bl = blockIdx.z;
+  const PolTab& P = A.pol[p];
+  const int jc0 = blockIdx.x * CG;
+  // tables first: their loads are in flight with the column loads
+  Staged<float2, twn<NY>(), kTPB> stwy;
+  Staged<int2, WYP, kTPB> smr;
+  Staged<float2, CG * GP, kTPB> sx;
+  stwy.load(A.tw_ny, twn<NY>(), tid);
+  smr.load(P.mrow, A.by, tid);
+  const int ncx = A.bx - jc0 < CG ? A.bx - jc0 : CG;
+  sx.load(P.xs + (size_t)jc0 * GP, ncx * GP, tid);
+  // this wave's B operands: steps s = wv + 4 t, box rows i = 4 s + lane / 16
+  const int nstep = A.byp / 4;
+  float bre[KSW][NT], bim[KSW][NT];
+#pragma unroll
+  for (int t = 0; t < KSW; ++t) {
+    const int st = wv + 4 * t;
+    const bool ok = st < nstep;
+    const int i = ok ? 4 * st + (lane >> 4) : 0;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const float2 y = P.ys[(size_t)i * GP + nt * 16 + (lane & 15)];
+      bre[t][nt] = ok ? y.x : 0.f;
+      bim[t][nt] = ok ? y.y : 0.f;
+    }
+  }
+  const float2* in = A.t1 + ((size_t)(bl * A.npol + p) * A.bx) * NY;
+  {
+    float2 v[Q::IT][Q::R0];
+#pragma unroll
+    for (int it = 0; it < Q::IT; ++it) {
+      const int g = tid + it * kTPB;
+      const int c = g / Q::NB, b = g % Q::NB;
+      const int j = jc0 + c;
+      const bool ok = (Q::TOTAL % kTPB == 0 || g < Q::TOTAL) && j < A.bx;
+      const float2* col = in + (size_t)(ok ? j : 0) * NY + b;
+#pragma unroll
+      for (int r = 0; r < Q::R0; ++r) {
+        const float2 f = ld_nt(col + r * Q::NB);
+        v[it][r] = ok ? f : make_float2(0.f, 0.f);
+      }
+    }
+    stwy.store(twy, twn<NY>(), make_float2(0.f, 0.f), tid);
+    smr.store(s_mrow, A.by, make_int2(1, 0), tid);
+    sx.store(s_x, ncx * GP, make_float2(0.f, 0.f), tid);
+    fft_pass1_regs<NY, CG, ST, kTPB>(v, buf, tid);
+  }
+  fft_rest<NY, CG, ST, kTPB>(buf, twy, tid);
+  if (A.window) {
+    // window = M * I~ = conj(val) (-1)^(u+v) Nx Ny at (v mod wy, u mod wx), as in k_col
+    float2* win = A.window + ((size_t)(b0 + bl) * A.npol + p) * A.wy * A.wx;
+    for (int e = tid; e < CG * WY; e += kTPB) {
+      const int c = e / WY, q = e % WY;
+      const int j = jc0 + c;
+      const int i = box_of(-P.ky0, q, WY, P.byq);
+      if (i < 0 || j >= A.bx) continue;
+      const int2 mr = s_mrow[i];
+      if (j < mr.x || j > mr.y) continue;
+      int vv = (P.ky0 + i) % NY;
+      if (vv < 0) vv += NY;
+      const float2 val = cmul(cmul(buf[c * ST + LN::at(vv)], conjf2(P.rhox[j])), conjf2(P.rhoy[i]));
+      const int u = -(P.k0 + j), v = -(P.ky0 + i);
+      int qu = u % A.wx;
+      if (qu < 0) qu += A.wx;
+      const float sg = ((u + v) & 1) ? -A.nxny : A.nxny;
+      win[(size_t)q * A.wx + qu] = make_float2(sg * val.x, -sg * val.y);
+    }
+  }
+  floatx4 d1[MT][NT], d2[MT][NT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      d1[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+      d2[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+    }
+  float pw = 0.f;
+  {
+    int i = 4 * wv + (lane >> 4);                 // box row of step s = wv
+    int vv = (P.ky0 + i) % NY;                    // its column-FFT bin
+    if (vv < 0) vv += NY;
+#pragma unroll
+    for (int t = 0; t < KSW; ++t) {
+      if (wv + 4 * t < nstep) {                   // uniform over the wave
+        const int2 mr = s_mrow[i];                // i < byp <= WYP; rows >= by are empty
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          const int r = mt * 16 + (lane & 15);
+          const int part = r / CG, j = r % CG;
+          const int ja = jc0 + j;
+          const bool ok = part < 2 && ja >= mr.x && ja <= mr.y;
+          const float2 f = buf[j * ST + LN::at(vv)];
+          const float a = ok ? (part ? f.y : f.x) : 0.f;
+          pw = fmaf(a, a, pw);
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) {
+            d1[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bre[t][nt], d1[mt][nt], 0, 0, 0);
+            d2[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bim[t][nt], d2[mt][nt], 0, 0, 0);
+          }
+        }
+      }
+      i += 16;
+      vv += 16;
+      if (vv >= NY) vv -= NY;
+    }
+  }
+  __syncthreads();                                // every wave is done with buf
+  float* red = IN_BUF ? reinterpret_cast<float*>(buf) : reinterpret_cast<float*>(s_spill);
+  float2* s_q = reinterpret_cast<float2*>(red + NRED);
+  // red[(((w MT + mt) NT + nt) 2 + h) 256 + row 16 + n], h = 0: d1, 1: d2
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int el = (4 * (lane >> 4) + r) * 16 + (lane & 15);
+        red[(((wv * MT + mt) * NT + nt) * 2 + 0) * 256 + el] = d1[mt][nt][r];
+        red[(((wv * MT + mt) * NT + nt) * 2 + 1) * 256 + el] = d2[mt][nt][r];
+      }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) pw += __shfl_xor(pw, off, 64);
+  if (lane == 0) s_pw[wv] = pw;
+  __syncthreads();
+  // Q[j][n], the four waves summed in order
+  for (int e = tid; e < NQ; e += kTPB) {
+    const int j = e / GP, n = e % GP;
+    const int nt = n >> 4, nn = n & 15;
+    const int r0 = j, r1 = CG + j;                // rows of Re S and Im S
+    float qr = 0.f, qi = 0.f;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const float* b0r = red + (((w * MT + (r0 >> 4)) * NT + nt) * 2) * 256 + (r0 & 15) * 16 + nn;
+      const float* b1r = red + (((w * MT + (r1 >> 4)) * NT + nt) * 2) * 256 + (r1 & 15) * 16 + nn;
+      qr += b0r[0] + b1r[256];                    // a c + b d
+      qi += b0r[256] - b1r[0];                    // a d - b c
+    }
+    s_q[e] = make_float2(qr, qi);
+  }
+  __syncthreads();
+  const int pstride = A.nmodes + 1;
+  float2* part = A.partial + ((size_t)(bl * A.nblk + blockIdx.x) * A.npol + p) * pstride;
+  if (tid == 0)
+    part[A.nmodes] = make_float2(A.capt ? (((s_pw[0] + s_pw[1]) + s_pw[2]) + s_pw[3]) * A.spow : 0.f, 0.f);
+  for (int e = tid; e < A.nmodes; e += kTPB) {
+    const short2 mn = A.modes[e];
+    float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int j = 0; j < CG; ++j) acc = cadd(acc, cmul(s_x[j * GP + mn.x], s_q[j * GP + mn.y]));
+    part[e] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Alignment: the spectrum around the cross term is computed once per batch
 // and kept; every trial of tilt / defocus / waist re-runs only the window
 // gather, the IFFTs and the overlap from it.
@@ -931,6 +1117,45 @@ hipError_t launch_col(const KArgs& a, int b0, int nb, hipStream_t s) {
 #undef X
   return hipErrorInvalidValue;
 }
+template <int NY, int WY, int NT>
+constexpr bool cspec_fits() { return ((WY + 15) / 16) * NT <= 16; }
+
+bool spectral_supported(int ny, int wy, int gp) {
+  const int nt = gp / 16;
+#define X(N, W) if (ny == N && wy == W) return nt == 1 ? cspec_fits<N, W, 1>() : cspec_fits<N, W, 2>();
+  DH_COL_PAIRS(X)
+#undef X
+  return false;
+}
+
+int spectral_blocks(int ny, int bx) {
+  int cg = 16;
+#define X(N) if (ny == N) cg = col_cg<N>();
+  DH_FFT_SIZES(X)
+#undef X
+  return (bx + cg - 1) / cg;
+}
+
+template <int NY, int WY, int NT>
+static hipError_t cspec_nwt(const KArgs& a, int b0, int nb, hipStream_t s) {
+  if constexpr (cspec_fits<NY, WY, NT>()) {
+    constexpr int CG = col_cg<NY>();
+    dim3 grid((a.bx + CG - 1) / CG, a.npol, nb);
+    hipLaunchKernelGGL((k_cspec<NY, WY, CG, NT>), grid, dim3(kTPB), 0, s, a, b0);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_cspec(const KArgs& a, int b0, int nb, hipStream_t s) {
+#define X(N, W) \
+  if (a.ny == N && a.wy == W) return a.gp == 16 ? cspec_nwt<N, W, 1>(a, b0, nb, s) : cspec_nwt<N, W, 2>(a, b0, nb, s);
+  DH_COL_PAIRS(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_fld(const KArgs& a, int b0, int nb, hipStream_t s) {
 #define X(W) if (a.wx == W) return fld_w<W>(a, b0, nb, s);
   DH_IFFT_SIZES(X)

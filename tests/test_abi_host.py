@@ -53,6 +53,12 @@ def _p(idx=1, **kw):
     (dict(input_dtype=7), dh.ERR_INVALIDARGUMENT),
     (dict(precision=9), dh.ERR_INVALIDARGUMENT),
     (dict(ifft_mode=0), dh.ERR_INVALIDARGUMENT),
+    (dict(path=3), dh.ERR_INVALIDARGUMENT),
+    (dict(path=-1), dh.ERR_INVALIDARGUMENT),
+    (dict(path="spectral", keep_fields=1), dh.ERR_INVALIDARGUMENT),
+    (dict(path="spectral", precision="split_bf16"), dh.ERR_INVALIDARGUMENT),
+    (dict(path="spectral", max_mg=0), dh.ERR_INVALIDARGUMENT),
+    (dict(path="spectral", max_mg=20), dh.ERR_INVALIDARGUMENT),   # 640x512 at G=20: 11 steps x 2 tiles
     (dict(beam_centre=[[400 * 20e-6, 0], [0, 0]]), dh.ERR_INVALIDDIMENSION),
 ])
 def test_validation_error_codes(kw, code):
@@ -121,3 +127,21 @@ def test_serving_rejects_bad_arguments_without_gpu():
     assert L.dh_serve_progress(55, None) == dh.ERR_INVALIDHANDLE
     n = ctypes.c_int()
     assert L.dh_serve_submit(55, 0, None, None) == dh.ERR_INVALIDHANDLE
+
+
+@pytest.mark.parametrize("idx,cam,kw,path", [
+    (1, 0, {}, dh.PATH_SPECTRAL),                                  # 640x512 G=9 FP32: spectral
+    (1, 0, dict(keep_fields=1), dh.PATH_FIELD),                    # fields requested
+    (1, 0, dict(precision="split_bf16"), dh.PATH_FIELD),           # split forms run on the field
+    (1, 0, dict(path="field"), dh.PATH_FIELD),
+    (1, 0, dict(max_mg=0), dh.PATH_FIELD),
+    (0, 0, dict(max_mg=20), dh.PATH_SPECTRAL),                     # 128x128, two n-tiles, 3 steps
+    (4, 0, {}, dh.PATH_FIELD),                                     # 1024x1024 G=30: too many steps
+    (3, 2, {}, dh.PATH_FIELD),                                     # 1024x1024 camera G=15
+    (3, 0, {}, dh.PATH_SPECTRAL),
+])
+def test_path_resolution(idx, cam, kw, path):
+    d = dict(dh_synth.config(idx, cam)["params"])
+    d.update(kw)
+    rc, info = dh.plan_check(d)
+    assert rc == dh.SUCCESS and info.path == path

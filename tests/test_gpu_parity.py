@@ -41,10 +41,13 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / (n if n > 0 else 1.0)
 
 
-def run_gpu(params, frames, keep=True, chunk=None, stream=True):
+def run_gpu(params, frames, keep=True, chunk=None, stream=True, path="auto"):
+    """Process `frames` through the C ABI. keep: also return the Fourier
+    window and (where the path forms it) the field."""
     torch = _torch()
     import paper_2204_02348_amd as dh
-    d = dict(params, keep_window=int(keep), keep_fields=int(keep))
+    fields = keep and path != "spectral"
+    d = dict(params, keep_window=int(keep), keep_fields=int(fields), path=path)
     if chunk:
         os.environ["DH_CHUNK_FRAMES"] = str(chunk)
     try:
@@ -59,6 +62,7 @@ def run_gpu(params, frames, keep=True, chunk=None, stream=True):
     out = dict(coefs=plan.coefs(False), coefs_norm=plan.coefs(True), info=plan.info)
     if keep:
         out["window"] = plan.window()
+    if fields:
         out["field"] = plan.fields()
     torch.cuda.synchronize()
     plan.destroy()
@@ -69,7 +73,7 @@ def check_frames(params, frames, gpu, idx, keep=True, tol=TOL):
     worst = {}
     for i in idx:
         ref = oracle.process_frame(frames[i].astype(np.float64), params)
-        keys = ["coefs", "coefs_norm"] + (["window", "field"] if keep else [])
+        keys = ["coefs", "coefs_norm"] + [k for k in ("window", "field") if keep and k in gpu]
         for k in keys:
             for pol in range(params["pol_count"]):
                 if params["max_mg"] == 0 and k.startswith("coefs"):
@@ -162,6 +166,46 @@ def test_frame_alone_equals_frame_in_batch():
     batch = run_gpu(cfg["params"], f, keep=False, chunk=4)
     assert np.array_equal(alone["coefs"][0], batch["coefs"][3])
     assert np.array_equal(alone["coefs_norm"][0], batch["coefs_norm"][3])
+
+
+# ---------------------------------------------------------------- spectral path
+@pytest.mark.parametrize("idx,cam,n,chunk", [
+    (0, 0, 1, None),      # 128x128 G=4
+    (1, 0, 7, 3),         # 640x512 2 pols G=9, ragged chunks
+    (2, 0, 1, None),      # 128x128 G=20: two n-tiles
+    (3, 0, 3, None),      # 320x256 uint16 G=5
+    (3, 1, 3, None),      # 640x512 uint16 G=9
+])
+def test_spectral_path_vs_oracle(idx, cam, n, chunk):
+    import paper_2204_02348_amd as dh
+    cfg, f, _ = _frames(idx, cam=cam, n=n)
+    _say("spectral path recipe", idx, "camera", cam, f.shape)
+    gpu = run_gpu(cfg["params"], f, chunk=chunk, path="spectral")
+    assert gpu["info"].path == dh.PATH_SPECTRAL
+    check_frames(cfg["params"], f, gpu, range(n))
+
+
+def test_spectral_path_subpixel_centre_defocus_per_pol_tilt():
+    cfg = dh_synth.config(1)
+    truth = dict(cfg["truth"], fft_w=256, fft_h=256, defocus=[0.15, -0.1],
+                 tilt_deg=[[1.45, 1.55], [1.52, 1.47]],
+                 beam_centre=[[0.3 * 20e-6, -2.2 * 20e-6], [-1.4 * 20e-6, 0.1 * 20e-6]])
+    f, _ = dh_synth.make_frames(dict(cfg, truth=truth), n_frames=2)
+    _say("spectral path: sub-pixel centre / defocus / per-pol tilt")
+    gpu = run_gpu(truth, f, path="spectral")
+    check_frames(truth, f, gpu, range(2))
+
+
+def test_field_and_spectral_paths_agree():
+    cfg, pool, _ = _frames(1, n=50)
+    f = dh_synth.tile_pool(pool, 300)
+    _say("field vs spectral path, 640x512 batch 300")
+    a = run_gpu(cfg["params"], f, keep=False, path="field")
+    b = run_gpu(cfg["params"], f, keep=False, path="spectral")
+    worst = max(_rel(b["coefs"][i][q].astype(np.complex128), a["coefs"][i][q].astype(np.complex128))
+                for i in range(f.shape[0]) for q in range(2))
+    _say("worst rel-L2 between the paths %.2e" % worst)
+    assert worst <= 2 * TOL
 
 
 # ---------------------------------------------------------------- precision form
