@@ -61,7 +61,8 @@ struct KArgs {
   const float2* tw_wx;
   const float2* tw_wy;
   const void* const* fptr;  // device array of frame pointers (frame b at fptr[b]) or null: contiguous frames
-  float2* t1;               // [chunk][P][bx][ny] row-pass spectrum at the box columns (column-major)
+  float2* t1;               // [chunk][P][ny/16][bx][16] row-pass spectrum at the box columns, in
+                            // tiles of 16 rows (row-pass blocks write whole tiles)
   float2* f2;               // [chunk][P][wy][bxp] column pass + crop + y-IFFT
   float2* partial;          // [chunk][nblk][P][nmodes + 1] per-row-block share of each coefficient,
                             // then the block's field power sum |E|^2 (if capt)

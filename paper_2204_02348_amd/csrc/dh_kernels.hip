@@ -64,6 +64,10 @@ __device__ __forceinline__ unsigned short bf16_rne(float x) {
 __device__ __forceinline__ float bf16_to_f32(unsigned short b) { return __uint_as_float((unsigned int)b << 16); }
 
 
+// t1 element (box column j, row y) of one frame and pol: tiles of 16 rows,
+// [y / 16][j][y % 16], so that a row-pass block's writes are contiguous
+__device__ __forceinline__ size_t t1_at(int j, int y, int bx) { return ((size_t)(y >> 4) * bx + j) * 16 + (y & 15); }
+
 // Box row / column held by IFFT row / column q: bin u sits at q = u mod W and
 // box index j = u_hi - u, so j = (u_hi - q) mod W; -1 if j is outside the pol's
 // box. (u_hi = -k0, v_hi = -ky0.)
@@ -111,7 +115,8 @@ struct Staged {
 // TT row tiles per workgroup, each TR complex transforms of NX, each the pair
 // of real rows (2t, 2t+1) packed as re + i im. The first pass takes its
 // operands straight from the frame; all tiles' loads are issued up front.
-// t1[b][p][j][y] = sum_x I[y][x] e^{-2 pi i k x / NX}, k = k0 + j (mod NX)
+// t1 at (box column j, row y) = sum_x I[y][x] e^{-2 pi i k x / NX},
+// k = k0 + j (mod NX), stored at t1_at(j, y)
 template <int NX, int TR, typename TIn, int TT>
 __global__ void __launch_bounds__(TR * NX / FftPlan<NX>::R0) k_row(KArgs A, const TIn* __restrict__ frames, int b0) {
   using L = Lds<NX>;
@@ -165,7 +170,7 @@ __global__ void __launch_bounds__(TR * NX / FftPlan<NX>::R0) k_row(KArgs A, cons
       const float2 z2 = conjf2(tb[L::at(km)]);
       const float2 d = csub(z1, z2);
       const float4 x = make_float4(0.5f * (z1.x + z2.x), 0.5f * (z1.y + z2.y), 0.5f * d.y, -0.5f * d.x);
-      float2* o = out + (size_t)j * A.ny + y;
+      float2* o = out + t1_at(j, y, A.bx);
       if (y + 1 < A.ny) {
         *reinterpret_cast<float4*>(o) = x;
       } else {
@@ -177,7 +182,7 @@ __global__ void __launch_bounds__(TR * NX / FftPlan<NX>::R0) k_row(KArgs A, cons
 
 // ---------------------------------------------------------------------------
 // k_col: grid (ceil(bx / CG), npol, nb). CG box columns per block: FFT along
-// y (first pass straight from the column-major t1), gather of the masked
+// y (first pass straight from the tiled t1), gather of the masked
 // window rows (stored as conj of the IFFT input), IFFT along y at the window
 // size; f2 rows have pitch bxp.
 template <int NY, int WY, int CG>
@@ -217,10 +222,9 @@ __global__ void __launch_bounds__(kTPB) k_col(KArgs A, int b0) {
       const int c = g / Q::NB, b = g % Q::NB;
       const int j = jc0 + c;
       const bool ok = (Q::TOTAL % kTPB == 0 || g < Q::TOTAL) && j < A.bx;
-      const float2* col = in + (size_t)(ok ? j : 0) * NY + b;
 #pragma unroll
       for (int r = 0; r < Q::R0; ++r) {
-        const float2 f = ld_nt(col + r * Q::NB);
+        const float2 f = ld_nt(in + t1_at(ok ? j : 0, b + r * Q::NB, A.bx));
         v[it][r] = ok ? f : make_float2(0.f, 0.f);
       }
     }
@@ -362,10 +366,9 @@ __global__ void __launch_bounds__(kTPB) k_cspec(KArgs A, int b0) {
       const int c = g / Q::NB, b = g % Q::NB;
       const int j = jc0 + c;
       const bool ok = (Q::TOTAL % kTPB == 0 || g < Q::TOTAL) && j < A.bx;
-      const float2* col = in + (size_t)(ok ? j : 0) * NY + b;
 #pragma unroll
       for (int r = 0; r < Q::R0; ++r) {
-        const float2 f = ld_nt(col + r * Q::NB);
+        const float2 f = ld_nt(in + t1_at(ok ? j : 0, b + r * Q::NB, A.bx));
         v[it][r] = ok ? f : make_float2(0.f, 0.f);
       }
     }
@@ -508,9 +511,8 @@ __global__ void __launch_bounds__(kTPB) k_spec(KArgs A, float2* __restrict__ spe
       const int c = g / Q::NB, b = g % Q::NB;
       const int j = jc0 + c;
       const bool ok = (Q::TOTAL % kTPB == 0 || g < Q::TOTAL) && j < A.bx;
-      const float2* col = in + (size_t)j * NY + b;
 #pragma unroll
-      for (int r = 0; r < Q::R0; ++r) v[it][r] = ok ? col[r * Q::NB] : make_float2(0.f, 0.f);
+      for (int r = 0; r < Q::R0; ++r) v[it][r] = ok ? in[t1_at(j, b + r * Q::NB, A.bx)] : make_float2(0.f, 0.f);
     }
     fft_pass1_regs<NY, CG, ST, kTPB>(v, buf, tid);
   }
@@ -1010,15 +1012,17 @@ __global__ void k_zero(float2* p, size_t n) {
 // ---------------------------------------------------------------------------
 // dispatch over the supported sizes
 // transforms per row-pass block and columns per column-pass block (~32-80 KB of LDS)
-// row pass: TR transforms per block so that TR * N / R0 (the block size) is 256 or 320
-template <int N> constexpr int row_tr() { return 256 / (N / FftPlan<N>::R0) > 0 ? (N == 320 ? 16 : N == 640 ? 4 : 256 / (N / FftPlan<N>::R0)) : 1; }
+// row pass: TR transforms per block so that TR * N / R0 (the block size) is 256
+// or 320; at N = 320, 8 transforms (160 threads, 22 KB of LDS: 7 blocks per CU)
+// measured faster than 16 (320 threads, 3 blocks per CU)
+template <int N> constexpr int row_tr() { return 256 / (N / FftPlan<N>::R0) > 0 ? (N == 320 ? 8 : N == 640 ? 4 : 256 / (N / FftPlan<N>::R0)) : 1; }
 template <int N> constexpr int col_cg() { return N >= 2048 ? 4 : N >= 1024 ? 4 : N >= 512 ? 8 : 16; }
 
 template <int NX>
 static hipError_t row_n(const KArgs& a, const void* frames, int u16, int b0, int nb, hipStream_t s) {
   constexpr int TR = row_tr<NX>();
   constexpr int TPB = TR * NX / FftPlan<NX>::R0;
-  static_assert(TPB % 64 == 0 && TPB <= 512, "row-pass block size");
+  static_assert(TPB % 32 == 0 && TPB <= 512, "row-pass block size");
   // two row tiles per workgroup (the second tile's loads overlap the first
   // tile's transform) when that still leaves the chip well filled; one tile
   // for small batches, where latency matters more
