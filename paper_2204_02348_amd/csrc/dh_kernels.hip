@@ -30,11 +30,11 @@ constexpr int kTPB = 256;
 typedef short shortx4 __attribute__((ext_vector_type(4)));
 typedef _Float16 halfx4 __attribute__((ext_vector_type(4)));
 
-// Streamed intermediates (t1 into the column pass, f2 written by the column
-// pass and read once by the field pass) use non-temporal loads and stores:
-// each element is touched once, and keeping it out of the caches measured a
-// few per cent faster. (Frame loads are ordinary: several load instructions
-// share each cache line.)
+// Streamed intermediates (t1 written by the row pass and read by the column
+// pass, f2 written by the column pass and read by the field pass) use
+// non-temporal loads and stores: each element is touched once, and keeping it
+// out of the caches measured a few per cent faster. Frame loads are ordinary:
+// several load instructions share each cache line.
 typedef float floatx2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ float2 ld_nt(const float2* p) {
   const floatx2 t = __builtin_nontemporal_load(reinterpret_cast<const floatx2*>(p));
@@ -129,25 +129,28 @@ __global__ void __launch_bounds__(TR * NX / FftPlan<NX>::R0) k_row(KArgs A, cons
   const int p = blockIdx.y;
   const int bl = blockIdx.z;                 // frame within the chunk
   const PolTab& P = A.pol[p];
-  stage_twiddles<NX, TPB>(tws, A.tw_nx, tid);
+  Staged<float2, twn<NX>(), TPB> stw;
+  stw.load(A.tw_nx, twn<NX>(), tid);
   const TIn* fr = A.fptr ? static_cast<const TIn*>(A.fptr[b0 + bl]) : frames + (size_t)(b0 + bl) * A.frame_h * A.frame_w;
   const gptr<TIn> win = as_global(fr) + ((size_t)P.y0 * A.frame_w + P.x0);
   // the operands of every tile are requested up front: later tiles' loads are
-  // in flight while the earlier tiles' transforms run
+  // in flight while the earlier tiles' transforms run. A tile past the last
+  // row (odd tile count) loads row pair 0 instead and stores nothing.
   float2 v[TT][Q::R0];
   {
     const int t = tid / Q::NB, b = tid % Q::NB;
 #pragma unroll
     for (int tt = 0; tt < TT; ++tt) {
-      const int y = (blockIdx.x * TT + tt) * (2 * TR) + 2 * t;
+      const int y0 = (blockIdx.x * TT + tt) * (2 * TR);
+      const int y = (y0 < A.ny ? y0 : 0) + 2 * t;      // ny is a multiple of 2 TR
       const gptr<TIn> r0 = win + ((size_t)y * A.frame_w + b);
       const gptr<TIn> r1 = r0 + A.frame_w;
-      const bool ok0 = y < A.ny, ok1 = y + 1 < A.ny;
 #pragma unroll
       for (int r = 0; r < Q::R0; ++r) {
-        v[tt][r].x = ok0 ? load_px(r0 + r * Q::NB) : 0.f;
-        v[tt][r].y = ok1 ? load_px(r1 + r * Q::NB) : 0.f;
+        v[tt][r].x = load_px(r0 + r * Q::NB);
+        v[tt][r].y = load_px(r1 + r * Q::NB);
       }
+      if (tt == 0) stw.store(tws, twn<NX>(), make_float2(0.f, 0.f), tid);
     }
   }
   float2* out = A.t1 + (size_t)(bl * A.npol + p) * A.bx * A.ny;
@@ -172,9 +175,10 @@ __global__ void __launch_bounds__(TR * NX / FftPlan<NX>::R0) k_row(KArgs A, cons
       const float4 x = make_float4(0.5f * (z1.x + z2.x), 0.5f * (z1.y + z2.y), 0.5f * d.y, -0.5f * d.x);
       float2* o = out + t1_at(j, y, A.bx);
       if (y + 1 < A.ny) {
-        *reinterpret_cast<float4*>(o) = x;
+        const floatx4 t4 = {x.x, x.y, x.z, x.w};
+        __builtin_nontemporal_store(t4, reinterpret_cast<floatx4*>(o));
       } else {
-        *o = make_float2(x.x, x.y);
+        st_nt(o, make_float2(x.x, x.y));
       }
     }
   }
@@ -223,10 +227,7 @@ __global__ void __launch_bounds__(kTPB) k_col(KArgs A, int b0) {
       const int j = jc0 + c;
       const bool ok = (Q::TOTAL % kTPB == 0 || g < Q::TOTAL) && j < A.bx;
 #pragma unroll
-      for (int r = 0; r < Q::R0; ++r) {
-        const float2 f = ld_nt(in + t1_at(ok ? j : 0, b + r * Q::NB, A.bx));
-        v[it][r] = ok ? f : make_float2(0.f, 0.f);
-      }
+      for (int r = 0; r < Q::R0; ++r) v[it][r] = ld_nt(in + t1_at(ok ? j : 0, b + r * Q::NB, A.bx));
     }
 #pragma unroll
     for (int i = 0; i < scy.IT; ++i) scy.v[i] = conjf2(scy.v[i]);
@@ -367,10 +368,7 @@ __global__ void __launch_bounds__(kTPB) k_cspec(KArgs A, int b0) {
       const int j = jc0 + c;
       const bool ok = (Q::TOTAL % kTPB == 0 || g < Q::TOTAL) && j < A.bx;
 #pragma unroll
-      for (int r = 0; r < Q::R0; ++r) {
-        const float2 f = ld_nt(in + t1_at(ok ? j : 0, b + r * Q::NB, A.bx));
-        v[it][r] = ok ? f : make_float2(0.f, 0.f);
-      }
+      for (int r = 0; r < Q::R0; ++r) v[it][r] = ld_nt(in + t1_at(ok ? j : 0, b + r * Q::NB, A.bx));
     }
     stwy.store(twy, twn<NY>(), make_float2(0.f, 0.f), tid);
     smr.store(s_mrow, A.by, make_int2(1, 0), tid);
@@ -408,32 +406,39 @@ __global__ void __launch_bounds__(kTPB) k_cspec(KArgs A, int b0) {
     }
   float pw = 0.f;
   {
+    // every step's operands are read first (all addresses are valid: rows
+    // past the box have empty mask intervals, and steps past the last have
+    // zero B operands), then the mask is applied as a select
+    int2 mv[KSW];
+    float2 fv[KSW][MT];
     int i = 4 * wv + (lane >> 4);                 // box row of step s = wv
     int vv = (P.ky0 + i) % NY;                    // its column-FFT bin
     if (vv < 0) vv += NY;
 #pragma unroll
     for (int t = 0; t < KSW; ++t) {
-      if (wv + 4 * t < nstep) {                   // uniform over the wave
-        const int2 mr = s_mrow[i];                // i < byp <= WYP; rows >= by are empty
+      mv[t] = s_mrow[i];                          // i < 16 KSW = WYP
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-          const int r = mt * 16 + (lane & 15);
-          const int part = r / CG, j = r % CG;
-          const int ja = jc0 + j;
-          const bool ok = part < 2 && ja >= mr.x && ja <= mr.y;
-          const float2 f = buf[j * ST + LN::at(vv)];
-          const float a = ok ? (part ? f.y : f.x) : 0.f;
-          pw = fmaf(a, a, pw);
-#pragma unroll
-          for (int nt = 0; nt < NT; ++nt) {
-            d1[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bre[t][nt], d1[mt][nt], 0, 0, 0);
-            d2[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bim[t][nt], d2[mt][nt], 0, 0, 0);
-          }
-        }
-      }
+      for (int mt = 0; mt < MT; ++mt) fv[t][mt] = buf[((mt * 16 + (lane & 15)) % CG) * ST + LN::at(vv)];
       i += 16;
       vv += 16;
       if (vv >= NY) vv -= NY;
+    }
+#pragma unroll
+    for (int t = 0; t < KSW; ++t) {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const int r = mt * 16 + (lane & 15);
+        const int part = r / CG;
+        const int ja = jc0 + r % CG;
+        const bool ok = part < 2 && ja >= mv[t].x && ja <= mv[t].y;
+        const float a = ok ? (part ? fv[t][mt].y : fv[t][mt].x) : 0.f;
+        pw = fmaf(a, a, pw);
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          d1[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bre[t][nt], d1[mt][nt], 0, 0, 0);
+          d2[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bim[t][nt], d2[mt][nt], 0, 0, 0);
+        }
+      }
     }
   }
   __syncthreads();                                // every wave is done with buf
