@@ -225,7 +225,7 @@ Layout layout(const Geom& g, const dh_params* p, int max_batch, int chunk, int n
       L.pol_uys[q][t] = take((size_t)g.wyp * g.gp * 2);
     }
     L.pol_xs[q] = take(g.spec ? (size_t)g.bx * g.gp * 8 : 0);
-    L.pol_ys[q] = take(g.spec ? (size_t)g.byp * g.gp * 8 : 0);
+    L.pol_ys[q] = take(g.spec ? (size_t)g.wyp * g.gp * 8 : 0);
   }
   const size_t P = p->pol_count;
   const size_t nm = g.nmodes > 0 ? g.nmodes : 1;
@@ -388,7 +388,7 @@ int build_spectral(Plan* pl) {
         spectral_axis(g.bx, g.bx, g.gp, g.G, P.uhi, g.wx, g.pxp, P.ax, p->defocus[q], p->wavelength, P.dx,
                       p->pixel_size, g.nx, 1.0, hx);
     const std::vector<float2> ys =
-        spectral_axis(g.by, g.byp, g.gp, g.G, P.vhi, g.wy, g.pyp, P.ay, p->defocus[q], p->wavelength, P.dy,
+        spectral_axis(g.by, g.wyp, g.gp, g.G, P.vhi, g.wy, g.pyp, P.ay, p->defocus[q], p->wavelength, P.dy,
                       p->pixel_size, g.ny, 1.0 / ((double)g.nx * g.ny), hy);
     if (hipMemcpy(pl->mem + L.pol_xs[q], xs.data(), xs.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(pl->mem + L.pol_ys[q], ys.data(), ys.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess)

@@ -42,7 +42,7 @@ struct PolTab {
   // so that c_mn = sum_{j,i} mask(j,i) conj(S[j][i]) xs[j][m] ys[i][n], S the
   // column-pass spectrum at box (j, i)
   const float2* xs;       // [bx][gp]
-  const float2* ys;       // [byp][gp], zero rows i >= by
+  const float2* ys;       // [wyp][gp], zero rows i >= by
 };
 
 struct KArgs {

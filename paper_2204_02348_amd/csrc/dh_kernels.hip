@@ -64,6 +64,15 @@ __device__ __forceinline__ unsigned short bf16_rne(float x) {
 __device__ __forceinline__ float bf16_to_f32(unsigned short b) { return __uint_as_float((unsigned int)b << 16); }
 
 
+// Raw buffer access (32-bit lane offsets; the per-load stride goes in the
+// scalar offset): descriptor word 3 of the gfx9 family, non-temporal loads.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float2 buf_ld_nt(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 2));
+}
+
 // t1 element (box column j, row y) of one frame and pol: tiles of 16 rows,
 // [y / 16][j][y % 16], so that a row-pass block's writes are contiguous
 __device__ __forceinline__ size_t t1_at(int j, int y, int bx) { return ((size_t)(y >> 4) * bx + j) * 16 + (y & 15); }
@@ -220,14 +229,24 @@ __global__ void __launch_bounds__(kTPB) k_col(KArgs A, int b0) {
   const float2* in = A.t1 + ((size_t)(bl * A.npol + p) * A.bx) * NY;
   {
     float2 v[Q::IT][Q::R0];
+    // element (j, b + r NB) of the tiled t1 at byte t1_at * 8; where NB is a
+    // multiple of 16 the row tile advances by NB / 16 per r at a fixed offset
+    // within the tile, and that step goes in the scalar offset
+    const __amdgpu_buffer_rsrc_t rt = make_rsrc(in, (unsigned)(A.bx * NY * 8));
 #pragma unroll
     for (int it = 0; it < Q::IT; ++it) {
       const int g = tid + it * kTPB;
       const int c = g / Q::NB, b = g % Q::NB;
-      const int j = jc0 + c;
-      const bool ok = (Q::TOTAL % kTPB == 0 || g < Q::TOTAL) && j < A.bx;
+      const int j = (Q::TOTAL % kTPB == 0 || g < Q::TOTAL) && jc0 + c < A.bx ? jc0 + c : 0;
+      if constexpr (Q::NB % 16 == 0) {
+        const int voff = ((b >> 4) * A.bx + j) * 128 + (b & 15) * 8;
+        const int rstride = (Q::NB / 16) * A.bx * 128;
 #pragma unroll
-      for (int r = 0; r < Q::R0; ++r) v[it][r] = ld_nt(in + t1_at(ok ? j : 0, b + r * Q::NB, A.bx));
+        for (int r = 0; r < Q::R0; ++r) v[it][r] = buf_ld_nt(rt, voff, r * rstride);
+      } else {
+#pragma unroll
+        for (int r = 0; r < Q::R0; ++r) v[it][r] = buf_ld_nt(rt, (int)t1_at(j, b + r * Q::NB, A.bx) * 8, 0);
+      }
     }
 #pragma unroll
     for (int i = 0; i < scy.IT; ++i) scy.v[i] = conjf2(scy.v[i]);
@@ -343,32 +362,41 @@ __global__ void __launch_bounds__(kTPB) k_cspec(KArgs A, int b0) {
   smr.load(P.mrow, A.by, tid);
   const int ncx = A.bx - jc0 < CG ? A.bx - jc0 : CG;
   sx.load(P.xs + (size_t)jc0 * GP, ncx * GP, tid);
-  // this wave's B operands: steps s = wv + 4 t, box rows i = 4 s + lane / 16
-  const int nstep = A.byp / 4;
+  // this wave's B operands: steps s = wv + 4 t, box rows i = 4 s + lane / 16;
+  // the ys table has 16 KSW rows (wy rounded up to 16), zero from row by on
   float bre[KSW][NT], bim[KSW][NT];
+  {
+    const float2* yrow = P.ys + (4 * wv + (lane >> 4)) * GP + (lane & 15);
 #pragma unroll
-  for (int t = 0; t < KSW; ++t) {
-    const int st = wv + 4 * t;
-    const bool ok = st < nstep;
-    const int i = ok ? 4 * st + (lane >> 4) : 0;
+    for (int t = 0; t < KSW; ++t)
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-      const float2 y = P.ys[(size_t)i * GP + nt * 16 + (lane & 15)];
-      bre[t][nt] = ok ? y.x : 0.f;
-      bim[t][nt] = ok ? y.y : 0.f;
-    }
+      for (int nt = 0; nt < NT; ++nt) {
+        const float2 y = yrow[t * 16 * GP + nt * 16];
+        bre[t][nt] = y.x;
+        bim[t][nt] = y.y;
+      }
   }
   const float2* in = A.t1 + ((size_t)(bl * A.npol + p) * A.bx) * NY;
   {
     float2 v[Q::IT][Q::R0];
+    // element (j, b + r NB) of the tiled t1 at byte t1_at * 8; where NB is a
+    // multiple of 16 the row tile advances by NB / 16 per r at a fixed offset
+    // within the tile, and that step goes in the scalar offset
+    const __amdgpu_buffer_rsrc_t rt = make_rsrc(in, (unsigned)(A.bx * NY * 8));
 #pragma unroll
     for (int it = 0; it < Q::IT; ++it) {
       const int g = tid + it * kTPB;
       const int c = g / Q::NB, b = g % Q::NB;
-      const int j = jc0 + c;
-      const bool ok = (Q::TOTAL % kTPB == 0 || g < Q::TOTAL) && j < A.bx;
+      const int j = (Q::TOTAL % kTPB == 0 || g < Q::TOTAL) && jc0 + c < A.bx ? jc0 + c : 0;
+      if constexpr (Q::NB % 16 == 0) {
+        const int voff = ((b >> 4) * A.bx + j) * 128 + (b & 15) * 8;
+        const int rstride = (Q::NB / 16) * A.bx * 128;
 #pragma unroll
-      for (int r = 0; r < Q::R0; ++r) v[it][r] = ld_nt(in + t1_at(ok ? j : 0, b + r * Q::NB, A.bx));
+        for (int r = 0; r < Q::R0; ++r) v[it][r] = buf_ld_nt(rt, voff, r * rstride);
+      } else {
+#pragma unroll
+        for (int r = 0; r < Q::R0; ++r) v[it][r] = buf_ld_nt(rt, (int)t1_at(j, b + r * Q::NB, A.bx) * 8, 0);
+      }
     }
     stwy.store(twy, twn<NY>(), make_float2(0.f, 0.f), tid);
     smr.store(s_mrow, A.by, make_int2(1, 0), tid);
