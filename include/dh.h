@@ -64,8 +64,8 @@ extern "C" {
  *             precision forms).
  *   SPECTRAL: the window contracted with the FP64-built tables X and Y on
  *             FP32 MFMA; no field is formed.
- *   AUTO:     SPECTRAL for the FP32 form without keep_fields where this build
- *             provides it (G <= 16 and ceil(W_y / 16) <= 16), else FIELD. */
+ *   AUTO:     SPECTRAL for the FP32 form with G > 0 and without keep_fields,
+ *             else FIELD. */
 #define DH_PATH_AUTO 0
 #define DH_PATH_FIELD 1
 #define DH_PATH_SPECTRAL 2
@@ -97,7 +97,7 @@ typedef struct dh_params {
   int keep_window;            /* nonzero: store each frame's Fourier window (dh_get_window) */
   int keep_fields;            /* nonzero: store each frame's field (dh_get_fields) */
   int path;                   /* DH_PATH_*; SPECTRAL with keep_fields, a split precision or
-                                 a size it does not cover is DH_ERR_INVALIDARGUMENT */
+                                 G = 0 is DH_ERR_INVALIDARGUMENT */
 } dh_params;
 
 /* Geometry derived by the plan (all FP64 on the host). */

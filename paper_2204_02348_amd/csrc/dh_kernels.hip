@@ -341,7 +341,7 @@ __global__ void __launch_bounds__(kTPB) k_cspec(KArgs A, int b0) {
   constexpr int NRED = 4 * MT * NT * 2 * 256;      // floats: the waves' MFMA results
   constexpr int NQ = CG * GP;                      // float2: Q
   constexpr bool IN_BUF = NRED * 4 + NQ * 8 <= CG * ST * 8;
-  static_assert(KSW * NT <= 16, "B operands are held in registers");
+  static_assert(KSW * NT <= 96, "B operands are held in registers");
   __shared__ float2 buf[CG * ST];
   __shared__ float2 twy[twn<NY>()];
   __shared__ int2 s_mrow[WYP];
@@ -1155,7 +1155,7 @@ hipError_t launch_col(const KArgs& a, int b0, int nb, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 template <int NY, int WY, int NT>
-constexpr bool cspec_fits() { return ((WY + 15) / 16) * NT <= 16; }
+constexpr bool cspec_fits() { return ((WY + 15) / 16) * NT <= 96; }
 
 bool spectral_supported(int ny, int wy, int gp) {
   const int nt = gp / 16;

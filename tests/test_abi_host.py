@@ -58,7 +58,6 @@ def _p(idx=1, **kw):
     (dict(path="spectral", keep_fields=1), dh.ERR_INVALIDARGUMENT),
     (dict(path="spectral", precision="split_bf16"), dh.ERR_INVALIDARGUMENT),
     (dict(path="spectral", max_mg=0), dh.ERR_INVALIDARGUMENT),
-    (dict(path="spectral", max_mg=20), dh.ERR_INVALIDARGUMENT),   # 640x512 at G=20: 11 steps x 2 tiles
     (dict(beam_centre=[[400 * 20e-6, 0], [0, 0]]), dh.ERR_INVALIDDIMENSION),
 ])
 def test_validation_error_codes(kw, code):
@@ -135,10 +134,12 @@ def test_serving_rejects_bad_arguments_without_gpu():
     (1, 0, dict(precision="split_bf16"), dh.PATH_FIELD),           # split forms run on the field
     (1, 0, dict(path="field"), dh.PATH_FIELD),
     (1, 0, dict(max_mg=0), dh.PATH_FIELD),
-    (0, 0, dict(max_mg=20), dh.PATH_SPECTRAL),                     # 128x128, two n-tiles, 3 steps
-    (4, 0, {}, dh.PATH_FIELD),                                     # 1024x1024 G=30: too many steps
-    (3, 2, {}, dh.PATH_FIELD),                                     # 1024x1024 camera G=15
-    (3, 0, {}, dh.PATH_SPECTRAL),
+    (0, 0, dict(max_mg=20), dh.PATH_SPECTRAL),                     # 128x128, two n-tiles
+    (1, 0, dict(max_mg=20), dh.PATH_SPECTRAL),
+    (4, 0, {}, dh.PATH_SPECTRAL),                                  # 1024x1024 G=30
+    (3, 2, {}, dh.PATH_SPECTRAL),                                  # 1024x1024 camera G=15
+    (3, 3, {}, dh.PATH_SPECTRAL),                                  # 2048x2048 camera G=20
+    (3, 0, dict(max_mg=0), dh.PATH_FIELD),
 ])
 def test_path_resolution(idx, cam, kw, path):
     d = dict(dh_synth.config(idx, cam)["params"])

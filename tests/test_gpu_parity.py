@@ -175,6 +175,9 @@ def test_frame_alone_equals_frame_in_batch():
     (2, 0, 1, None),      # 128x128 G=20: two n-tiles
     (3, 0, 3, None),      # 320x256 uint16 G=5
     (3, 1, 3, None),      # 640x512 uint16 G=9
+    (3, 2, 2, None),      # 1024x1024 uint16 G=15
+    (3, 3, 1, None),      # 2048x2048 uint16 G=20
+    (4, 0, 2, None),      # 1024x1024 2 pols G=30
 ])
 def test_spectral_path_vs_oracle(idx, cam, n, chunk):
     import paper_2204_02348_amd as dh
