@@ -183,11 +183,14 @@ __global__ void __launch_bounds__(TR * NX / FftPlan<NX>::R0) k_row(KArgs A, cons
       const float2 d = csub(z1, z2);
       const float4 x = make_float4(0.5f * (z1.x + z2.x), 0.5f * (z1.y + z2.y), 0.5f * d.y, -0.5f * d.x);
       float2* o = out + t1_at(j, y, A.bx);
-      if (y + 1 < A.ny) {
+      // rows y, y+1 (ny is even). A workgroup writes 2 TR rows of each
+      // 16-row tile per phase: from 64 B on, non-temporal stores are faster;
+      // the 32 B pieces of TR = 2 need the cache to merge them into lines
+      if constexpr (2 * TR >= 8) {
         const floatx4 t4 = {x.x, x.y, x.z, x.w};
         __builtin_nontemporal_store(t4, reinterpret_cast<floatx4*>(o));
       } else {
-        st_nt(o, make_float2(x.x, x.y));
+        *reinterpret_cast<float4*>(o) = x;
       }
     }
   }
@@ -363,19 +366,20 @@ __global__ void __launch_bounds__(kTPB) k_cspec(KArgs A, int b0) {
   const int ncx = A.bx - jc0 < CG ? A.bx - jc0 : CG;
   sx.load(P.xs + (size_t)jc0 * GP, ncx * GP, tid);
   // this wave's B operands: steps s = wv + 4 t, box rows i = 4 s + lane / 16;
-  // the ys table has 16 KSW rows (wy rounded up to 16), zero from row by on
+  // the ys table has 16 KSW rows (wy rounded up to 16), zero from row by on.
+  // The first DB steps' operands are loaded before the column FFT, the rest
+  // DB steps ahead of their use (DB = KSW where they all fit in registers)
+  constexpr int DB = KSW * NT <= 24 ? KSW : 12 / NT;
   float bre[KSW][NT], bim[KSW][NT];
-  {
-    const float2* yrow = P.ys + (4 * wv + (lane >> 4)) * GP + (lane & 15);
+  const float2* yrow = P.ys + (4 * wv + (lane >> 4)) * GP + (lane & 15);
 #pragma unroll
-    for (int t = 0; t < KSW; ++t)
+  for (int t = 0; t < DB; ++t)
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        const float2 y = yrow[t * 16 * GP + nt * 16];
-        bre[t][nt] = y.x;
-        bim[t][nt] = y.y;
-      }
-  }
+    for (int nt = 0; nt < NT; ++nt) {
+      const float2 y = yrow[t * 16 * GP + nt * 16];
+      bre[t][nt] = y.x;
+      bim[t][nt] = y.y;
+    }
   const float2* in = A.t1 + ((size_t)(bl * A.npol + p) * A.bx) * NY;
   {
     float2 v[Q::IT][Q::R0];
@@ -434,37 +438,49 @@ __global__ void __launch_bounds__(kTPB) k_cspec(KArgs A, int b0) {
     }
   float pw = 0.f;
   {
-    // every step's operands are read first (all addresses are valid: rows
-    // past the box have empty mask intervals, and steps past the last have
-    // zero B operands), then the mask is applied as a select
+    // the A operands (mask interval and spectrum value of each step) are read
+    // DA steps ahead of their MFMAs (all of them first where they fit in
+    // registers); every address is valid: rows past the box have empty mask
+    // intervals and zero B operands. The mask is applied as a select.
+    constexpr int DA = KSW <= 16 ? KSW : 12;
     int2 mv[KSW];
     float2 fv[KSW][MT];
-    int i = 4 * wv + (lane >> 4);                 // box row of step s = wv
+    int i = 4 * wv + (lane >> 4);                 // box row of the next step to read
     int vv = (P.ky0 + i) % NY;                    // its column-FFT bin
     if (vv < 0) vv += NY;
 #pragma unroll
-    for (int t = 0; t < KSW; ++t) {
-      mv[t] = s_mrow[i];                          // i < 16 KSW = WYP
+    for (int t = 0; t < KSW + DA; ++t) {
+      if (t < KSW) {                              // read step t (compile-time after unrolling)
+        mv[t] = s_mrow[i];                        // i < 16 KSW = WYP
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) fv[t][mt] = buf[((mt * 16 + (lane & 15)) % CG) * ST + LN::at(vv)];
-      i += 16;
-      vv += 16;
-      if (vv >= NY) vv -= NY;
-    }
+        for (int mt = 0; mt < MT; ++mt) fv[t][mt] = buf[((mt * 16 + (lane & 15)) % CG) * ST + LN::at(vv)];
+        i += 16;
+        vv += 16;
+        if (vv >= NY) vv -= NY;
+      }
+      const int u = t - DA;                       // step whose MFMAs run now
+      if (u >= 0) {
+        if (u + DB < KSW) {
 #pragma unroll
-    for (int t = 0; t < KSW; ++t) {
+          for (int nt = 0; nt < NT; ++nt) {
+            const float2 y = yrow[(u + DB) * 16 * GP + nt * 16];
+            bre[u + DB][nt] = y.x;
+            bim[u + DB][nt] = y.y;
+          }
+        }
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        const int r = mt * 16 + (lane & 15);
-        const int part = r / CG;
-        const int ja = jc0 + r % CG;
-        const bool ok = part < 2 && ja >= mv[t].x && ja <= mv[t].y;
-        const float a = ok ? (part ? fv[t][mt].y : fv[t][mt].x) : 0.f;
-        pw = fmaf(a, a, pw);
+        for (int mt = 0; mt < MT; ++mt) {
+          const int r = mt * 16 + (lane & 15);
+          const int part = r / CG;
+          const int ja = jc0 + r % CG;
+          const bool ok = part < 2 && ja >= mv[u].x && ja <= mv[u].y;
+          const float a = ok ? (part ? fv[u][mt].y : fv[u][mt].x) : 0.f;
+          pw = fmaf(a, a, pw);
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-          d1[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bre[t][nt], d1[mt][nt], 0, 0, 0);
-          d2[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bim[t][nt], d2[mt][nt], 0, 0, 0);
+          for (int nt = 0; nt < NT; ++nt) {
+            d1[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bre[u][nt], d1[mt][nt], 0, 0, 0);
+            d2[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bim[u][nt], d2[mt][nt], 0, 0, 0);
+          }
         }
       }
     }
