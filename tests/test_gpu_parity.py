@@ -211,6 +211,26 @@ def test_field_and_spectral_paths_agree():
     assert worst <= 2 * TOL
 
 
+@pytest.mark.parametrize("path", ["spectral", "field"])
+def test_row_pass_ragged_tile_count(path):
+    """128x64 frames: the row pass's one 64-row tile per frame and pol, with two
+    tiles per workgroup on a grid this large, so every workgroup's second tile
+    is past the last row (loads clamped, nothing stored). Each frame equals the
+    same frame processed alone (one tile per workgroup), bit for bit, and the
+    oracle."""
+    cfg = dh_synth.config(0)
+    p = dict(cfg["params"], frame_h=64, fft_h=64)
+    pool, _ = dh_synth.make_frames(dict(cfg, params=p, truth=p), n_frames=8)
+    f = dh_synth.tile_pool(pool, 4100)
+    _say("ragged tile count: 4100 frames 128x64,", path)
+    big = run_gpu(dict(p, path=path), f, keep=False, path=path)
+    for i in range(8):
+        alone = run_gpu(dict(p, path=path), f[i:i + 1], keep=False, path=path)
+        for k in (i, i + 8 * 256, i + 8 * 511):
+            assert np.array_equal(big["coefs"][k], alone["coefs"][0]), (i, k)
+    check_frames(p, f, big, [0, 4099], keep=False)
+
+
 # ---------------------------------------------------------------- precision form
 TOL_SPLIT = 1e-4
 
