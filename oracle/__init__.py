@@ -9,3 +9,4 @@ from .holo_oracle import (  # noqa: F401
     window_origin, mask_bins, geometry, hermite_gauss_1d, spectrum_window,
     field_from_window, overlap, power_normalise, process_frame, process_batch, captured_power, goal_db,
 )
+from .transfer_metrics import METRICS, transfer_matrix, column_keys, transfer_metrics  # noqa: F401,E402

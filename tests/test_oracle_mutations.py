@@ -105,3 +105,51 @@ def test_unmutated_oracle_passes_the_checks():
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
 def test_mutation_is_caught(name):
     assert _checks(_mutant(name)) != [], name
+
+
+# ---------------------------------------------------------------- transfer-matrix metrics
+TM_SRC = os.path.join(os.path.dirname(SRC), "transfer_metrics.py")
+
+TM_MUTATIONS = {
+    "il_sum": ("np.mean(s2)", "np.sum(s2)"),
+    "mdl_inverse": ("s2.min() / s2.max())", "s2.max() / s2.min())"),
+    "mdl_amplitude": ("np.linalg.svd(a, compute_uv=False) ** 2", "np.linalg.svd(a, compute_uv=False)"),
+    "pol_independence_ignored": ("    if not pol_independent:\n", "    if True:\n"),
+    "diag_amplitude": ("p = np.abs(d) ** 2", "p = np.abs(d)"),
+    "aa_star_transposed": ("a @ a.conj().T if mul_conj_trans", "a.conj().T @ a if mul_conj_trans"),
+    "snr_row_total": ("diag[i] / (rows[i] - diag[i])", "diag[i] / rows[i]"),
+    "snrmg_ignores_pol": ("p * (group_count + 1) + groups", "groups"),
+}
+
+
+def _tm_mutant(name):
+    import oracle
+    src = open(TM_SRC).read()
+    old, new = TM_MUTATIONS[name]
+    assert src.count(old) == 1, name
+    src = src.replace(old, new).replace("from .holo_oracle import mode_list\n", "")
+    mod = types.ModuleType("tm_mutant_" + name)
+    mod.__dict__["mode_list"] = oracle.mode_list
+    exec(compile(src, TM_SRC + ":" + name, "exec"), mod.__dict__)
+    return mod
+
+
+@pytest.mark.parametrize("name", sorted(TM_MUTATIONS))
+def test_metric_pins_catch_planted_mistake(name, monkeypatch):
+    import oracle
+    import tests.test_oracle_pins as pins
+    mut = _tm_mutant(name)
+    monkeypatch.setattr(oracle, "transfer_metrics", mut.transfer_metrics)
+    failed = 0
+    for t in [pins.test_metrics_identity_and_scaled_unitary,
+              pins.test_metrics_il_mdl_closed_form_from_chosen_singular_values,
+              pins.test_metrics_diagonal_and_snr_closed_forms,
+              pins.test_metrics_mode_group_snr_counts_coupling_inside_a_group,
+              pins.test_metrics_missing_polarisation_combined_vs_independent,
+              pins.test_metrics_aa_star_of_a_wide_matrix_and_two_pol_groups]:
+        try:
+            with np.errstate(divide="ignore", invalid="ignore"):
+                t()
+        except (AssertionError, FloatingPointError, ZeroDivisionError, ValueError):
+            failed += 1
+    assert failed > 0, name

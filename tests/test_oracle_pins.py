@@ -312,3 +312,109 @@ def test_captured_power_is_one_at_the_truth_and_drops_off_it():
                    dict(defocus=[truth["defocus"][0] + 0.05, truth["defocus"][1]]),
                    dict(waist=truth["waist"] * 1.05)]:
         assert oracle.goal_db(f, dict(truth, **change)) < -1e-3
+
+
+# ---------------------------------------------------------------- transfer-matrix metrics
+def _unitary(n, seed):
+    rng = np.random.default_rng(seed)
+    q, r = np.linalg.qr(rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n)))
+    return q * (np.diag(r) / np.abs(np.diag(r)))
+
+
+def test_metrics_identity_and_scaled_unitary():
+    n = 10                                   # G = 4: 10 modes, one pol
+    m = oracle.transfer_metrics(np.eye(n, dtype=complex).reshape(n, 1, n), 4)
+    for k in ("IL", "MDL", "DIAG", "DIAGBEST", "DIAGWORST"):
+        assert m[k] == 0.0, k
+    for k in ("SNRAVG", "SNRBEST", "SNRWORST", "SNRMG"):
+        assert m[k] == math.inf, k
+    g = 0.37
+    m = oracle.transfer_metrics((g * _unitary(n, 3)).reshape(n, 1, n), 4)
+    assert abs(m["IL"] - 20 * math.log10(g)) < 1e-12
+    assert abs(m["MDL"]) < 1e-12
+
+
+def test_metrics_il_mdl_closed_form_from_chosen_singular_values():
+    n = 15                                   # G = 5: 15 modes
+    sig = np.linspace(0.2, 1.3, n)
+    a = _unitary(n, 5) @ np.diag(sig) @ _unitary(n, 6).conj().T
+    m = oracle.transfer_metrics(a.reshape(n, 1, n), 5)
+    assert abs(m["IL"] - 10 * math.log10(np.mean(sig ** 2))) < 1e-10
+    assert abs(m["MDL"] - 10 * math.log10(0.2 ** 2 / 1.3 ** 2)) < 1e-10
+    # mean of s^2 is the Frobenius power over min(rows, cols): a wide 6 x 15 matrix
+    w = a[:6]
+    m = oracle.transfer_metrics(w.reshape(6, 1, n), 5)
+    assert abs(m["IL"] - 10 * math.log10(np.sum(np.abs(w) ** 2) / 6)) < 1e-10
+
+
+def test_metrics_diagonal_and_snr_closed_forms():
+    n = 10
+    d = np.linspace(0.5, 1.4, n) * np.exp(1j * np.arange(n))
+    e = 0.03 * np.exp(0.4j)
+    a = np.full((n, n), e, dtype=complex)
+    np.fill_diagonal(a, d)
+    m = oracle.transfer_metrics(a.reshape(n, 1, n), 4)
+    p = np.abs(d) ** 2
+    off = (n - 1) * abs(e) ** 2
+    assert abs(m["DIAG"] - 10 * math.log10(p.mean())) < 1e-10
+    assert abs(m["DIAGBEST"] - 10 * math.log10(p.max())) < 1e-10
+    assert abs(m["DIAGWORST"] - 10 * math.log10(p.min())) < 1e-10
+    assert abs(m["SNRAVG"] - 10 * math.log10(p.sum() / (n * off))) < 1e-10
+    assert abs(m["SNRBEST"] - 10 * math.log10(p.max() / off)) < 1e-10
+    assert abs(m["SNRWORST"] - 10 * math.log10(p.min() / off)) < 1e-10
+    # AA* of g U: g^2 I, so its diagonal power is g^4 and nothing is off it
+    g = 0.6
+    m = oracle.transfer_metrics((g * _unitary(n, 8)).reshape(n, 1, n), 4, mul_conj_trans=True)
+    assert abs(m["DIAG"] - 40 * math.log10(g)) < 1e-9
+    assert m["SNRAVG"] > 200
+
+
+def test_metrics_mode_group_snr_counts_coupling_inside_a_group():
+    # G = 4: groups {0}, {1, 2}, {3, 4, 5}, {6..9} in mode order
+    groups = [m + n for m, n in oracle.mode_list(4)]
+    n = len(groups)
+    rng = np.random.default_rng(2)
+    a = np.zeros((n, n), dtype=complex)
+    for i in range(n):
+        for j in range(n):
+            if groups[i] == groups[j]:
+                a[i, j] = rng.normal() + 1j * rng.normal()
+    m = oracle.transfer_metrics(a.reshape(n, 1, n), 4)
+    assert m["SNRMG"] == math.inf and math.isfinite(m["SNRAVG"])
+    # one cross-group entry of power q: SNRMG = total in-group power / q
+    a[0, 9] = 0.1
+    m = oracle.transfer_metrics(a.reshape(n, 1, n), 4)
+    assert abs(m["SNRMG"] - 10 * math.log10((np.sum(np.abs(a) ** 2) - 0.01) / 0.01)) < 1e-9
+
+
+def test_metrics_missing_polarisation_combined_vs_independent():
+    # the paper's own example: one polarisation absent leaves the combined
+    # matrix's MDL finite and drives the independent one's to -inf
+    n = 10
+    c = np.zeros((n, 2, n), dtype=complex)
+    c[:, 0, :] = _unitary(n, 11)
+    assert abs(oracle.transfer_metrics(c, 4)["MDL"]) < 1e-12
+    assert oracle.transfer_metrics(c, 4, pol_independent=True)["MDL"] == -math.inf
+    # both present, independent: block-diagonal, singular values of both blocks
+    c[:, 1, :] = 0.5 * _unitary(n, 12)
+    m = oracle.transfer_metrics(c, 4, pol_independent=True)
+    assert abs(m["MDL"] - 20 * math.log10(0.5)) < 1e-10
+    assert abs(m["IL"] - 10 * math.log10((1 + 0.25) / 2)) < 1e-10
+
+
+def test_metrics_aa_star_of_a_wide_matrix_and_two_pol_groups():
+    # 6 orthonormal rows of a 15 x 15 unitary, scaled: A A* = g^2 I_6 (A* A is not)
+    g = 0.8
+    w = g * _unitary(15, 21)[:6]
+    m = oracle.transfer_metrics(w.reshape(6, 1, 15), 5, mul_conj_trans=True)
+    assert abs(m["DIAG"] - 40 * math.log10(g)) < 1e-9 and m["SNRAVG"] > 100
+    # two pols (G = 2: modes (0,0) | (1,0) (0,1)): coupling between the pols
+    # inside one group is noise for SNRMG
+    c = np.zeros((6, 2, 3), dtype=complex)
+    c[:, 0, :] = 0.0
+    a = np.zeros((6, 6), dtype=complex)
+    a[1, 2] = a[2, 1] = a[1, 1] = a[2, 2] = 1.0      # pol 0, group 1: signal
+    a[0, 0] = a[3, 3] = 1.0
+    a[1, 4] = 0.2                                    # pol 0 group 1 -> pol 1 group 1: noise
+    m = oracle.transfer_metrics(a.reshape(6, 2, 3), 2)
+    assert abs(m["SNRMG"] - 10 * math.log10(6.0 / 0.04)) < 1e-9
