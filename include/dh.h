@@ -153,6 +153,37 @@ int dh_plan(const dh_params* p, int max_batch, size_t hbm_budget, dh_handle* out
  */
 int dh_process_batch(dh_handle h, const void* frames, int batch, void* stream);
 
+/* Transfer-matrix metrics ("Transfer matrix analysis parameters"; AutoAlign
+ * goal metrics), all in dB. */
+#define DH_METRIC_IL 0        /* insertion loss: 10 log10 of the mean squared singular value */
+#define DH_METRIC_MDL 1       /* mode dependent loss: 10 log10(min s^2 / max s^2), <= 0 */
+#define DH_METRIC_DIAG 2      /* mean power of the diagonal entries */
+#define DH_METRIC_SNRAVG 3    /* diagonal power / off-diagonal power */
+#define DH_METRIC_DIAGBEST 4  /* largest diagonal power */
+#define DH_METRIC_DIAGWORST 5 /* smallest diagonal power */
+#define DH_METRIC_SNRBEST 6   /* largest diagonal / off-diagonal power of one row (batch element) */
+#define DH_METRIC_SNRWORST 7  /* smallest of the same */
+#define DH_METRIC_SNRMG 8     /* as SNRAVG, power between modes of one pol and HG group counted as signal */
+#define DH_METRIC_COUNT 9
+
+/*
+ * The nine metrics of the last processed batch's transfer matrix A, written
+ * to out[DH_METRIC_COUNT] (host memory). A is built from the raw coefficients:
+ * pol_independent 0: batch x (pol x mode), row b = frame b; 1: (pol x batch)
+ * x (pol x mode), row p*batch + b holds frame b's pol-p coefficients in pol
+ * p's columns and zeros in the other pol's (a missing pol gives MDL = -inf).
+ * IL and MDL come from the singular values of A (eigenvalues of the smaller
+ * Gram matrix, FP64, rocSOLVER); the diagonal and SNR metrics from D = A
+ * (mul_conj_trans 0) or D = A A^H (1), with entry (i, i) as the diagonal for
+ * i < min(rows, cols of D); row i of A stands for the mode of column i, which
+ * is what SNRMG compares. Values are +inf / -inf where a ratio's denominator
+ * or numerator is zero. Waits for the stream of the last dh_process_batch and
+ * runs there; allocates a workspace on first use (kept until dh_destroy).
+ * Errors: DH_ERR_INVALIDHANDLE, DH_ERR_NULLPOINTER, DH_ERR_ERROR (no batch
+ * processed, G = 0, or the eigen-solver failed), DH_ERR_MEMORYALLOCATION.
+ */
+int dh_transfer_metrics(dh_handle h, int pol_independent, int mul_conj_trans, double* out);
+
 /*
  * Coefficients of the last processed batch, [batch][pol][mode] complex64.
  * host_out non-NULL: waits for the stream of the last dh_process_batch and

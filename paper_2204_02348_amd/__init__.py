@@ -33,6 +33,7 @@ INPUT_U16 = 1
 PREC_FP32 = 0
 PREC_SPLIT_BF16 = 1
 PREC_SPLIT_FP16 = 2
+METRICS = ["IL", "MDL", "DIAG", "SNRAVG", "DIAGBEST", "DIAGWORST", "SNRBEST", "SNRWORST", "SNRMG"]
 PATH_AUTO = 0
 PATH_FIELD = 1
 PATH_SPECTRAL = 2
@@ -41,7 +42,7 @@ EXPORTS = ["dh_plan_check", "dh_plan", "dh_process_batch", "dh_mode_coefs", "dh_
            "dh_get_fields", "dh_get_params", "dh_get_plan_info", "dh_set_stage_timing", "dh_stage_times",
            "dh_autoalign", "dh_get_align_report", "dh_serve_create", "dh_serve_info", "dh_serve_submit",
            "dh_serve_progress", "dh_serve_replay", "dh_serve_stats", "dh_serve_destroy",
-           "dh_last_error", "dh_destroy"]
+           "dh_last_error", "dh_transfer_metrics", "dh_destroy"]
 ALIGN_FULL, ALIGN_TWEAK, ALIGN_ESTIMATE = 0, 1, 2
 ALIGN_TILT, ALIGN_DEFOCUS, ALIGN_WAIST, ALIGN_CENTRE = 1, 2, 4, 8
 # launch stages (DH_STAGE_*): row pass; column pass (FFT along y + window,
@@ -118,6 +119,7 @@ def lib():
                                       C.c_void_p]
         L.dh_serve_stats.argtypes = [C.c_int, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]
         L.dh_serve_destroy.argtypes = [C.c_int]
+        L.dh_transfer_metrics.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double)]
         L.dh_last_error.argtypes = [C.c_int]
         L.dh_destroy.argtypes = [C.c_int]
         for name in EXPORTS:
@@ -226,6 +228,14 @@ class Plan:
             if rc != SUCCESS:
                 raise DhError(rc, "dh_mode_coefs")
         return out
+
+    def transfer_metrics(self, pol_independent: bool = False, mul_conj_trans: bool = False) -> dict:
+        """The nine metrics (dB) of the last batch's transfer matrix (dh_transfer_metrics)."""
+        out = (C.c_double * len(METRICS))()
+        rc = lib().dh_transfer_metrics(self.handle, int(pol_independent), int(mul_conj_trans), out)
+        if rc != SUCCESS:
+            raise DhError(rc, "dh_transfer_metrics")
+        return {k: float(out[i]) for i, k in enumerate(METRICS)}
 
     def coefs_device_ptr(self, normalised: bool = True) -> int:
         dev = C.c_void_p()

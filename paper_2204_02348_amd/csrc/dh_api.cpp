@@ -3,6 +3,7 @@
 #include "dh.h"
 
 #include <hip/hip_runtime.h>
+#include <rocsolver/rocsolver.h>
 
 #include <cfloat>
 #include <chrono>
@@ -259,6 +260,11 @@ struct Plan {
   // stream the kernel runs on
   // alignment: device scratch reused across calls, and the last report
   char* amem = nullptr;
+  // transfer-matrix metrics: workspace (grown on demand) and the rocBLAS
+  // handle rocSOLVER runs on
+  char* tm_mem = nullptr;
+  size_t tm_bytes = 0;
+  rocblas_handle blas = nullptr;
   size_t amem_bytes = 0;
   dh_align_report rep{};
   int version = 0;                   // bumped whenever the tables are rebuilt
@@ -553,6 +559,8 @@ void release(Plan* pl) {
   for (hipEvent_t e : pl->ev_pool) (void)hipEventDestroy(e);
   if (pl->mem) (void)hipFree(pl->mem);
   if (pl->amem) (void)hipFree(pl->amem);
+  if (pl->tm_mem) (void)hipFree(pl->tm_mem);
+  if (pl->blas) (void)rocblas_destroy_handle(pl->blas);
   (void)hipSetDevice(dev);
   delete pl;
 }
@@ -1050,6 +1058,109 @@ extern "C" float dh_autoalign(dh_handle h, const void* frames, int batch, int mo
   pl->last_stream = s;
   set_err(pl, DH_SUCCESS);
   return (float)goal;
+}
+
+namespace {
+double db10(double x) {
+  if (!(x > 0.0)) return -HUGE_VAL;
+  if (std::isinf(x)) return HUGE_VAL;
+  return 10.0 * std::log10(x);
+}
+}  // namespace
+
+extern "C" int dh_transfer_metrics(dh_handle h, int pol_independent, int mul_conj_trans, double* out) {
+  Plan* pl = get(h);
+  if (!pl) return DH_ERR_INVALIDHANDLE;
+  if (!out) return set_err(pl, DH_ERR_NULLPOINTER);
+  const int B = pl->last_batch, P = pl->params.pol_count, M = pl->g.nmodes;
+  if (B < 1 || M < 1) return set_err(pl, DH_ERR_ERROR);
+  dh::TmArgs t{};
+  t.c = pl->ka[0].coefs;
+  t.modes = pl->ka[0].modes;
+  t.B = B; t.P = P; t.M = M;
+  t.indep = pol_independent ? 1 : 0;
+  t.rows = t.indep ? P * B : B;
+  t.cols = P * M;
+  // singular values: eigenvalues of the smaller Gram matrix
+  const int byrows = t.rows <= t.cols;
+  const int n = byrows ? t.rows : t.cols;
+  // the matrix of the diagonal metrics: A (rows x cols) or A A^H (rows x rows)
+  const bool aa = mul_conj_trans != 0;
+  const bool extra = aa && !byrows;            // A A^H besides the Gram of the SVD
+  const int ncol = aa ? t.rows : t.cols;
+  const int nd = std::min(t.rows, ncol);
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o += align256(bytes); return r; };
+  const size_t og = take((size_t)n * n * 16), od = extra ? take((size_t)t.rows * t.rows * 16) : 0;
+  const size_t oe = take((size_t)n * 8), ow = take((size_t)n * 8), oi = take(8);
+  const size_t orow = take((size_t)t.rows * 8), odg = take((size_t)nd * 8), osm = take((size_t)nd * 8);
+  if (o > pl->tm_bytes) {
+    if (pl->tm_mem) (void)hipFree(pl->tm_mem);
+    pl->tm_mem = nullptr;
+    pl->tm_bytes = 0;
+    if (hipMalloc(&pl->tm_mem, o) != hipSuccess) {
+      (void)hipGetLastError();
+      return set_err(pl, DH_ERR_MEMORYALLOCATION);
+    }
+    pl->tm_bytes = o;
+  }
+  char* m = pl->tm_mem;
+  double2* g = (double2*)(m + og);
+  double2* gd = extra ? (double2*)(m + od) : g;
+  hipStream_t s = pl->last_stream;
+  if (!pl->blas && rocblas_create_handle(&pl->blas) != rocblas_status_success) {
+    pl->blas = nullptr;
+    return set_err(pl, DH_ERR_ERROR);
+  }
+  if (rocblas_set_stream(pl->blas, s) != rocblas_status_success) return set_err(pl, DH_ERR_ERROR);
+  // the row statistics read the Gram matrix before the eigen-solver overwrites it
+  if (dh::launch_tm_gram(t, byrows, n, g, s) != hipSuccess ||
+      (extra && dh::launch_tm_gram(t, 1, t.rows, gd, s) != hipSuccess) ||
+      dh::launch_tm_rows(t, aa ? gd : nullptr, t.rows, ncol, nd, (double*)(m + orow), (double*)(m + odg),
+                         (double*)(m + osm), s) != hipSuccess)
+    return set_err(pl, DH_ERR_ERROR);
+  if (rocsolver_zheevd(pl->blas, rocblas_evect_none, rocblas_fill_upper, n, (rocblas_double_complex*)g, n,
+                       (double*)(m + oe), (double*)(m + ow), (rocblas_int*)(m + oi)) != rocblas_status_success)
+    return set_err(pl, DH_ERR_ERROR);
+  std::vector<double> eig(n), rowp(t.rows), dg(nd), sm(nd);
+  int info = 0;
+  if (hipMemcpyAsync(eig.data(), m + oe, (size_t)n * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(rowp.data(), m + orow, (size_t)t.rows * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(dg.data(), m + odg, (size_t)nd * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(sm.data(), m + osm, (size_t)nd * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(&info, m + oi, 4, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+    return set_err(pl, DH_ERR_ERROR);
+  if (info != 0) return set_err(pl, DH_ERR_ERROR);
+  // IL, MDL from s^2 = the Gram's eigenvalues (rounding can leave tiny negatives)
+  double smin = HUGE_VAL, smax = 0.0, ssum = 0.0;
+  for (double e : eig) {
+    const double v = std::max(e, 0.0);
+    smin = std::min(smin, v);
+    smax = std::max(smax, v);
+    ssum += v;
+  }
+  out[DH_METRIC_IL] = db10(ssum / n);
+  out[DH_METRIC_MDL] = smax > 0.0 ? db10(smin / smax) : -HUGE_VAL;
+  double total = 0.0, dsum = 0.0, ssame = 0.0, dmax = 0.0, dmin = HUGE_VAL, rmax = -1.0, rmin = HUGE_VAL;
+  for (int i = 0; i < t.rows; ++i) total += rowp[i];
+  for (int i = 0; i < nd; ++i) {
+    dsum += dg[i];
+    ssame += sm[i];
+    dmax = std::max(dmax, dg[i]);
+    dmin = std::min(dmin, dg[i]);
+    const double off = rowp[i] - dg[i];
+    const double r = off > 0.0 ? dg[i] / off : HUGE_VAL;
+    rmax = std::max(rmax, r);
+    rmin = std::min(rmin, r);
+  }
+  out[DH_METRIC_DIAG] = db10(dsum / nd);
+  out[DH_METRIC_SNRAVG] = total > dsum ? db10(dsum / (total - dsum)) : HUGE_VAL;
+  out[DH_METRIC_DIAGBEST] = db10(dmax);
+  out[DH_METRIC_DIAGWORST] = db10(dmin);
+  out[DH_METRIC_SNRBEST] = db10(rmax);
+  out[DH_METRIC_SNRWORST] = db10(rmin);
+  out[DH_METRIC_SNRMG] = total > ssame ? db10(ssame / (total - ssame)) : HUGE_VAL;
+  return set_err(pl, DH_SUCCESS);
 }
 
 extern "C" int dh_get_align_report(dh_handle h, dh_align_report* out) {

@@ -102,4 +102,19 @@ hipError_t launch_hg(double pitch, int w, int wpad, double waist, int G, int gp,
                      unsigned short* bh, unsigned short* bl, _Float16* hh, _Float16* hl, double fp16_scale,
                      hipStream_t s);
 
+// transfer-matrix metrics (FP64): A from the coefficients [B][P][M]
+struct TmArgs {
+  const float2* c;          // raw coefficients of the batch
+  const short2* modes;      // [M] (m, n)
+  int B, P, M;
+  int indep;                // pol-independent rows (p B + b), cross-pol entries zero
+  int rows, cols;           // B (or P B) x P M
+};
+// Gram X X^H (n x n, column-major) with X = A (by_rows) or A^H
+hipError_t launch_tm_gram(const TmArgs& t, int by_rows, int n, double2* g, hipStream_t s);
+// per row of D (A if g is null, else the rows x rows Gram in g): row power,
+// and for rows < nd the diagonal power and the power sharing the row's mode key
+hipError_t launch_tm_rows(const TmArgs& t, const double2* g, int nrow, int ncol, int nd, double* rowpow, double* diag,
+                          double* same, hipStream_t s);
+
 }  // namespace dh

@@ -3,6 +3,7 @@
 Tolerance (FP32 path): relative L2 error <= 1e-5 per frame and polarisation
 on the Fourier window, the field and the coefficients (raw and normalised).
 """
+import math
 import os
 import sys
 
@@ -417,3 +418,38 @@ def test_serving_admission_by_budget():
         dh.Server([plan], max_batch=32, hbm_budget=nbytes - 1)
     assert e.value.code == dh.ERR_MEMORYALLOCATION
     plan.destroy()
+
+
+# ---------------------------------------------------------------- transfer-matrix metrics
+@pytest.mark.parametrize("n", [90, 1000])
+def test_transfer_metrics_match_oracle(n):
+    """The nine metrics of the batch transfer matrix (640x512, 2 pols, G=9:
+    90 columns) on the GPU, against the oracle's metrics of the same
+    coefficients (both FP64) for every option, and against the oracle's own
+    coefficients for the default options."""
+    torch = _torch()
+    import paper_2204_02348_amd as dh
+    cfg, pool, _ = _frames(1, n=min(n, 90))
+    f = dh_synth.tile_pool(pool, n) if n > 90 else pool
+    plan = dh.Plan(cfg["params"], max_batch=n)
+    ft = torch.from_numpy(np.ascontiguousarray(f)).cuda()
+    plan.process(ft, n, None)
+    coefs = plan.coefs(False).astype(np.complex128)
+    got = {}
+    for indep in (False, True):
+        for aa in (False, True):
+            got[(indep, aa)] = plan.transfer_metrics(indep, aa)
+    plan.destroy()
+    for (indep, aa), g in got.items():
+        ref = oracle.transfer_metrics(coefs, 9, pol_independent=indep, mul_conj_trans=aa)
+        _say("metrics n=%d indep=%d aa=%d" % (n, indep, aa), {k: "%.6f" % v for k, v in g.items()})
+        for k in oracle.METRICS:
+            if math.isinf(ref[k]):
+                assert g[k] == ref[k], (indep, aa, k)
+            else:
+                assert abs(g[k] - ref[k]) <= 1e-6, (indep, aa, k, g[k], ref[k])
+    if n == 90:
+        oc = np.stack([oracle.process_frame(f[i].astype(np.float64), cfg["params"])["coefs"] for i in range(n)])
+        ref = oracle.transfer_metrics(oc, 9)
+        for k in oracle.METRICS:
+            assert abs(got[(False, False)][k] - ref[k]) <= 1e-3, k
