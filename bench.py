@@ -189,6 +189,23 @@ def alignment_bench(dh, torch, workers, align_frames=50, decomp_frames=5000):
                               for a in range(2)] for q in range(2)],
            "defocus_err_D": [round(got["defocus"][q] - truth["defocus"][q], 5) for q in range(2)],
            "waist_err_pct": round(100 * (got["waist"] / truth["waist"] - 1), 3)}
+    # the same alignment with the insertion loss of the batch transfer matrix
+    # as the goal (each pol's tilt and defocus its own coordinate)
+    plan_il = dh.Plan(cfg["params"], max_batch=align_frames)
+    plan_il.set_align_goal("IL")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    il = plan_il.autoalign(frames, align_frames, dh.ALIGN_FULL, dh.ALIGN_TILT | dh.ALIGN_DEFOCUS | dh.ALIGN_WAIST, 1e-5)
+    wall = time.perf_counter() - t0
+    rep = plan_il.align_report()
+    got = plan_il.params()
+    plan_il.destroy()
+    out["il_goal"] = {"align_wall_s": round(wall, 4), "il_db": round(il, 6), "trials": rep.evaluations,
+                      "sweeps": rep.sweeps, "mdl_db": round(rep.metrics[1], 4),
+                      "tilt_err_bins": [[round((got["tilt_deg"][q][a] - truth["tilt_deg"][q][a]) / bins[a], 4)
+                                         for a in range(2)] for q in range(2)],
+                      "defocus_err_D": [round(got["defocus"][q] - truth["defocus"][q], 5) for q in range(2)],
+                      "waist_err_pct": round(100 * (got["waist"] / truth["waist"] - 1), 3)}
     stream = torch.cuda.Stream()
     for _ in range(2):
         plan.process(frames, decomp_frames, stream)

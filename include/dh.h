@@ -253,9 +253,12 @@ int dh_stage_times(dh_handle h, double* ms, int* launches);
  *         DH_ERR_INVALIDARGUMENT);
  *   tol:  stop when a full sweep over the parameters improves the goal by
  *         less than tol (dB), as the paper's AutoAlignTol.
- * Goal: captured power, 10 log10(sum |c|^2 / sum |E|^2 p'x p'y) over the batch
- * and both polarisations, computed in FP64 (0 dB: the field is exactly a
- * combination of the basis modes). The snap puts the tilt at the centroid of
+ * Goal (dh_set_align_goal): by default the captured power,
+ * 10 log10(sum |c|^2 / sum |E|^2 p'x p'y) over the batch and both
+ * polarisations, computed in FP64 (0 dB: the field is exactly a combination
+ * of the basis modes); or one transfer-matrix metric (DH_METRIC_*) of the
+ * batch's raw coefficients. With a metric goal every trial evaluates that
+ * metric, and each polarisation's tilt and defocus is a coordinate of its own. The snap puts the tilt at the centroid of
  * the batch power spectrum (above its mean) near the current tilt; the tweak
  * is a coordinate search. Tilts stay within 0.6 window radii of their start.
  * Each trial re-runs the window gather, the IFFTs and the overlap from a
@@ -273,13 +276,25 @@ int dh_stage_times(dh_handle h, double* ms, int* launches);
 #define DH_ALIGN_CENTRE 8u
 float dh_autoalign(dh_handle h, const void* frames, int batch, int mode, unsigned what, float tol, void* stream);
 
+#define DH_GOAL_CAPTURED (-1)
+/*
+ * Goal of the following dh_autoalign calls on h: DH_GOAL_CAPTURED (default)
+ * or a DH_METRIC_* index, with the transfer-matrix options of
+ * dh_transfer_metrics (the paper's AutoAlignGoalIdx, AutoAlignPolIndependence,
+ * AutoAlignBasisMulConjTrans). Errors: DH_ERR_INVALIDHANDLE,
+ * DH_ERR_INVALIDARGUMENT (goal outside -1..DH_METRIC_COUNT-1).
+ */
+int dh_set_align_goal(dh_handle h, int goal, int pol_independent, int mul_conj_trans);
+
 typedef struct dh_align_report {
   int evaluations;             /* trials of the goal */
   int sweeps;                  /* tweak sweeps over the parameters */
   double start_goal_db;        /* goal after the snap (before the tweak) */
-  double goal_db;              /* final goal */
-  double captured;             /* final goal as a power fraction */
+  double goal_db;              /* final goal (dB) */
+  double captured;             /* final captured power as a fraction */
   double snap_tilt_deg[2][2];  /* tilt found by the snap ([pol][x,y]) */
+  int goal;                    /* the goal optimised: DH_GOAL_CAPTURED or DH_METRIC_* */
+  double metrics[DH_METRIC_COUNT];  /* every metric at the final parameters (dh_transfer_metrics) */
 } dh_align_report;
 
 /* Report of the last dh_autoalign on h. */

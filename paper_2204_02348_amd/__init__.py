@@ -34,6 +34,7 @@ PREC_FP32 = 0
 PREC_SPLIT_BF16 = 1
 PREC_SPLIT_FP16 = 2
 METRICS = ["IL", "MDL", "DIAG", "SNRAVG", "DIAGBEST", "DIAGWORST", "SNRBEST", "SNRWORST", "SNRMG"]
+GOAL_CAPTURED = -1
 PATH_AUTO = 0
 PATH_FIELD = 1
 PATH_SPECTRAL = 2
@@ -42,7 +43,7 @@ EXPORTS = ["dh_plan_check", "dh_plan", "dh_process_batch", "dh_mode_coefs", "dh_
            "dh_get_fields", "dh_get_params", "dh_get_plan_info", "dh_set_stage_timing", "dh_stage_times",
            "dh_autoalign", "dh_get_align_report", "dh_serve_create", "dh_serve_info", "dh_serve_submit",
            "dh_serve_progress", "dh_serve_replay", "dh_serve_stats", "dh_serve_destroy",
-           "dh_last_error", "dh_transfer_metrics", "dh_destroy"]
+           "dh_last_error", "dh_transfer_metrics", "dh_set_align_goal", "dh_destroy"]
 ALIGN_FULL, ALIGN_TWEAK, ALIGN_ESTIMATE = 0, 1, 2
 ALIGN_TILT, ALIGN_DEFOCUS, ALIGN_WAIST, ALIGN_CENTRE = 1, 2, 4, 8
 # launch stages (DH_STAGE_*): row pass; column pass (FFT along y + window,
@@ -71,7 +72,8 @@ class Params(C.Structure):
 
 class AlignReport(C.Structure):
     _fields_ = [("evaluations", C.c_int), ("sweeps", C.c_int), ("start_goal_db", C.c_double),
-                ("goal_db", C.c_double), ("captured", C.c_double), ("snap_tilt_deg", (C.c_double * 2) * 2)]
+                ("goal_db", C.c_double), ("captured", C.c_double), ("snap_tilt_deg", (C.c_double * 2) * 2),
+                ("goal", C.c_int), ("metrics", C.c_double * 9)]
 
 
 class PlanInfo(C.Structure):
@@ -120,6 +122,7 @@ def lib():
         L.dh_serve_stats.argtypes = [C.c_int, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]
         L.dh_serve_destroy.argtypes = [C.c_int]
         L.dh_transfer_metrics.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double)]
+        L.dh_set_align_goal.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int]
         L.dh_last_error.argtypes = [C.c_int]
         L.dh_destroy.argtypes = [C.c_int]
         for name in EXPORTS:
@@ -228,6 +231,13 @@ class Plan:
             if rc != SUCCESS:
                 raise DhError(rc, "dh_mode_coefs")
         return out
+
+    def set_align_goal(self, goal, pol_independent: bool = False, mul_conj_trans: bool = False):
+        """Goal of later autoalign calls: GOAL_CAPTURED, a METRICS index or name."""
+        g = METRICS.index(goal) if isinstance(goal, str) else int(goal)
+        rc = lib().dh_set_align_goal(self.handle, g, int(pol_independent), int(mul_conj_trans))
+        if rc != SUCCESS:
+            raise DhError(rc, "dh_set_align_goal")
 
     def transfer_metrics(self, pol_independent: bool = False, mul_conj_trans: bool = False) -> dict:
         """The nine metrics (dB) of the last batch's transfer matrix (dh_transfer_metrics)."""

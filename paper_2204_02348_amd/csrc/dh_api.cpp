@@ -265,6 +265,8 @@ struct Plan {
   char* tm_mem = nullptr;
   size_t tm_bytes = 0;
   rocblas_handle blas = nullptr;
+  int goal = DH_GOAL_CAPTURED;       // alignment goal and its transfer-matrix options
+  int goal_indep = 0, goal_aa = 0;
   size_t amem_bytes = 0;
   dh_align_report rep{};
   int version = 0;                   // bumped whenever the tables are rebuilt
@@ -813,6 +815,105 @@ int dh_destroy(dh_handle h) {
 // window gather, the IFFTs and the overlap from the stored spectrum.
 namespace {
 
+double db10(double x) {
+  if (!(x > 0.0)) return -HUGE_VAL;
+  if (std::isinf(x)) return HUGE_VAL;
+  return 10.0 * std::log10(x);
+}
+
+// The nine metrics of the transfer matrix of the B frames whose raw
+// coefficients are in ka[0].coefs, on stream s (synchronises it).
+int tm_compute(Plan* pl, int B, int pol_independent, int mul_conj_trans, hipStream_t s, double* out) {
+  const int P = pl->params.pol_count, M = pl->g.nmodes;
+  if (B < 1 || M < 1) return DH_ERR_ERROR;
+  dh::TmArgs t{};
+  t.c = pl->ka[0].coefs;
+  t.modes = pl->ka[0].modes;
+  t.B = B; t.P = P; t.M = M;
+  t.indep = pol_independent ? 1 : 0;
+  t.rows = t.indep ? P * B : B;
+  t.cols = P * M;
+  // singular values: eigenvalues of the smaller Gram matrix
+  const int byrows = t.rows <= t.cols;
+  const int n = byrows ? t.rows : t.cols;
+  // the matrix of the diagonal metrics: A (rows x cols) or A A^H (rows x rows)
+  const bool aa = mul_conj_trans != 0;
+  const bool extra = aa && !byrows;            // A A^H besides the Gram of the SVD
+  const int ncol = aa ? t.rows : t.cols;
+  const int nd = std::min(t.rows, ncol);
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o += align256(bytes); return r; };
+  const size_t og = take((size_t)n * n * 16), od = extra ? take((size_t)t.rows * t.rows * 16) : 0;
+  const size_t oe = take((size_t)n * 8), ow = take((size_t)n * 8), oi = take(8);
+  const size_t orow = take((size_t)t.rows * 8), odg = take((size_t)nd * 8), osm = take((size_t)nd * 8);
+  if (o > pl->tm_bytes) {
+    if (pl->tm_mem) (void)hipFree(pl->tm_mem);
+    pl->tm_mem = nullptr;
+    pl->tm_bytes = 0;
+    if (hipMalloc(&pl->tm_mem, o) != hipSuccess) {
+      (void)hipGetLastError();
+      return DH_ERR_MEMORYALLOCATION;
+    }
+    pl->tm_bytes = o;
+  }
+  char* m = pl->tm_mem;
+  double2* g = (double2*)(m + og);
+  double2* gd = extra ? (double2*)(m + od) : g;
+  if (!pl->blas && rocblas_create_handle(&pl->blas) != rocblas_status_success) {
+    pl->blas = nullptr;
+    return DH_ERR_ERROR;
+  }
+  if (rocblas_set_stream(pl->blas, s) != rocblas_status_success) return DH_ERR_ERROR;
+  // the row statistics read the Gram matrix before the eigen-solver overwrites it
+  if (dh::launch_tm_gram(t, byrows, n, g, s) != hipSuccess ||
+      (extra && dh::launch_tm_gram(t, 1, t.rows, gd, s) != hipSuccess) ||
+      dh::launch_tm_rows(t, aa ? gd : nullptr, t.rows, ncol, nd, (double*)(m + orow), (double*)(m + odg),
+                         (double*)(m + osm), s) != hipSuccess)
+    return DH_ERR_ERROR;
+  if (rocsolver_zheevd(pl->blas, rocblas_evect_none, rocblas_fill_upper, n, (rocblas_double_complex*)g, n,
+                       (double*)(m + oe), (double*)(m + ow), (rocblas_int*)(m + oi)) != rocblas_status_success)
+    return DH_ERR_ERROR;
+  std::vector<double> eig(n), rowp(t.rows), dg(nd), sm(nd);
+  int info = 0;
+  if (hipMemcpyAsync(eig.data(), m + oe, (size_t)n * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(rowp.data(), m + orow, (size_t)t.rows * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(dg.data(), m + odg, (size_t)nd * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(sm.data(), m + osm, (size_t)nd * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(&info, m + oi, 4, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+    return DH_ERR_ERROR;
+  if (info != 0) return DH_ERR_ERROR;
+  // IL, MDL from s^2 = the Gram's eigenvalues (rounding can leave tiny negatives)
+  double smin = HUGE_VAL, smax = 0.0, ssum = 0.0;
+  for (double e : eig) {
+    const double v = std::max(e, 0.0);
+    smin = std::min(smin, v);
+    smax = std::max(smax, v);
+    ssum += v;
+  }
+  out[DH_METRIC_IL] = db10(ssum / n);
+  out[DH_METRIC_MDL] = smax > 0.0 ? db10(smin / smax) : -HUGE_VAL;
+  double total = 0.0, dsum = 0.0, ssame = 0.0, dmax = 0.0, dmin = HUGE_VAL, rmax = -1.0, rmin = HUGE_VAL;
+  for (int i = 0; i < t.rows; ++i) total += rowp[i];
+  for (int i = 0; i < nd; ++i) {
+    dsum += dg[i];
+    ssame += sm[i];
+    dmax = std::max(dmax, dg[i]);
+    dmin = std::min(dmin, dg[i]);
+    const double off = rowp[i] - dg[i];
+    const double r = off > 0.0 ? dg[i] / off : HUGE_VAL;
+    rmax = std::max(rmax, r);
+    rmin = std::min(rmin, r);
+  }
+  out[DH_METRIC_DIAG] = db10(dsum / nd);
+  out[DH_METRIC_SNRAVG] = total > dsum ? db10(dsum / (total - dsum)) : HUGE_VAL;
+  out[DH_METRIC_DIAGBEST] = db10(dmax);
+  out[DH_METRIC_DIAGWORST] = db10(dmin);
+  out[DH_METRIC_SNRBEST] = db10(rmax);
+  out[DH_METRIC_SNRWORST] = db10(rmin);
+  out[DH_METRIC_SNRMG] = total > ssame ? db10(ssame / (total - ssame)) : HUGE_VAL;
+  return DH_SUCCESS;
+}
+
 struct AlignCtx {
   Plan* pl;
   hipStream_t s;
@@ -965,23 +1066,45 @@ extern "C" float dh_autoalign(dh_handle h, const void* frames, int batch, int mo
   if (pl->g.G == 0) {  // estimate only, nothing to evaluate
     for (int q = 0; q < np; ++q) derive_pol(&P, &g, q);
     if (build_tables(pl, false) != DH_SUCCESS) return (set_err(pl, DH_ERR_ERROR), -FLT_MAX);
+    rep.goal = pl->goal;
     pl->rep = rep;
     set_err(pl, DH_SUCCESS);
     return 0.f;
   }
-  if (!align_eval(c, true, mp, fp)) return (P = start, build_tables(pl), set_err(pl, DH_ERR_ERROR), -FLT_MAX);
+  // goal: captured power (per pol and joint), or one transfer-matrix metric
+  // of the batch's coefficients (joint only)
+  const bool metric_goal = pl->goal >= 0;
+  auto captured = [&]() { return db(mp[0] + (np > 1 ? mp[1] : 0.0), fp[0] + (np > 1 ? fp[1] : 0.0)); };
+  auto eval_goal = [&](bool hg, double& gv) -> bool {
+    if (!align_eval(c, hg, mp, fp)) return false;
+    if (!metric_goal) {
+      gv = captured();
+      return true;
+    }
+    double m[DH_METRIC_COUNT];
+    if (tm_compute(pl, c.batch, pl->goal_indep, pl->goal_aa, s, m) != DH_SUCCESS) return false;
+    gv = std::max(-1000.0, std::min(1000.0, m[pl->goal]));   // finite for the parabola
+    return true;
+  };
+  double goal;
+  if (!eval_goal(true, goal)) return (P = start, build_tables(pl), set_err(pl, DH_ERR_ERROR), -FLT_MAX);
   double best_pol[2] = {db(mp[0], fp[0]), np > 1 ? db(mp[1], fp[1]) : 0.0};
-  double goal = db(mp[0] + (np > 1 ? mp[1] : 0.0), fp[0] + (np > 1 ? fp[1] : 0.0));
   rep.start_goal_db = goal;
-  // tweak: coordinate search, a parabola through three trials per coordinate;
-  // per-pol parameters of both pols move together (each pol's captured power
-  // depends only on its own tilt and defocus), the shared waist on the joint goal
+  // tweak: coordinate search, a parabola through three trials per coordinate.
+  // Captured-power goal: the per-pol parameters of both pols move together,
+  // each pol on its own captured power (it depends only on its own tilt and
+  // defocus). Metric goal (couples the pols): one coordinate per pol, on the
+  // joint goal. The shared waist is always one coordinate on the joint goal.
   if (mode != DH_ALIGN_ESTIMATE) {
-    struct Coord { int kind; int axis; double h; };   // kind 0 tilt, 1 defocus, 2 waist
+    struct Coord { int kind; int axis; int pol; double h; };   // kind 0 tilt, 1 defocus, 2 waist; pol -1: all
     std::vector<Coord> coords;
-    if (what & DH_ALIGN_TILT) { coords.push_back({0, 0, 0.5 * binx}); coords.push_back({0, 1, 0.5 * biny}); }
-    if (what & DH_ALIGN_DEFOCUS) coords.push_back({1, 0, 0.02});
-    if (what & DH_ALIGN_WAIST) coords.push_back({2, 0, 0.03 * P.waist});
+    auto add = [&](int kind, int axis, double h) {
+      if (kind == 2 || !metric_goal) coords.push_back({kind, axis, -1, h});
+      else for (int q = 0; q < np; ++q) coords.push_back({kind, axis, q, h});
+    };
+    if (what & DH_ALIGN_TILT) { add(0, 0, 0.5 * binx); add(0, 1, 0.5 * biny); }
+    if (what & DH_ALIGN_DEFOCUS) add(1, 0, 0.02);
+    if (what & DH_ALIGN_WAIST) add(2, 0, 0.03 * P.waist);
     auto get = [&](const Coord& k, int q) -> double& {
       return k.kind == 0 ? P.tilt_deg[q][k.axis] : k.kind == 1 ? P.defocus[q] : P.waist;
     };
@@ -993,65 +1116,73 @@ extern "C" float dh_autoalign(dh_handle h, const void* frames, int batch, int mo
     for (int sweep = 0; sweep < 60 && !coords.empty(); ++sweep) {
       const double goal0 = goal;
       for (Coord& k : coords) {
-        const int nq = k.kind == 2 ? 1 : np;      // the waist is one shared value
-        double x0[2], f0[2], fm[2], fpl[2];
-        for (int q = 0; q < nq; ++q) x0[q] = get(k, q);
+        const bool joint = k.kind == 2 || metric_goal;   // one value, on the joint goal
+        const int nq = joint ? 1 : np;
+        auto pq = [&](int i) { return joint ? (k.pol < 0 ? 0 : k.pol) : i; };   // pol of value i
+        double x0[2], f0[2], fm[2], fpl[2], last[2];
+        for (int i = 0; i < nq; ++i) x0[i] = get(k, pq(i));
         auto trial = [&](const double* v, double* out) -> bool {
-          for (int q = 0; q < nq; ++q) get(k, q) = v[q];
-          if (!align_eval(c, k.kind == 2, mp, fp)) return false;
-          if (k.kind == 2) out[0] = db(mp[0] + (np > 1 ? mp[1] : 0.0), fp[0] + (np > 1 ? fp[1] : 0.0));
-          else for (int q = 0; q < nq; ++q) out[q] = db(mp[q], fp[q]);
+          for (int i = 0; i < nq; ++i) get(k, pq(i)) = last[i] = v[i];
+          if (joint) return eval_goal(k.kind == 2, out[0]);
+          if (!align_eval(c, false, mp, fp)) return false;
+          for (int q = 0; q < nq; ++q) out[q] = db(mp[q], fp[q]);
           return true;
         };
-        for (int q = 0; q < nq; ++q) f0[q] = k.kind == 2 ? goal : best_pol[q];
+        for (int i = 0; i < nq; ++i) f0[i] = joint ? goal : best_pol[i];
         double vp[2], vm[2];
-        for (int q = 0; q < nq; ++q) { vp[q] = clampv(k, q, x0[q] + k.h); vm[q] = clampv(k, q, x0[q] - k.h); }
+        for (int i = 0; i < nq; ++i) { vp[i] = clampv(k, pq(i), x0[i] + k.h); vm[i] = clampv(k, pq(i), x0[i] - k.h); }
         bool okp = trial(vp, fpl), okm = trial(vm, fm);
         double vn[2], fn[2];
-        for (int q = 0; q < nq; ++q) {
-          if (!okp) fpl[q] = -1e300;
-          if (!okm) fm[q] = -1e300;
-          const double cv = fpl[q] + fm[q] - 2.0 * f0[q];
+        for (int i = 0; i < nq; ++i) {
+          if (!okp) fpl[i] = -1e300;
+          if (!okm) fm[i] = -1e300;
+          const double cv = fpl[i] + fm[i] - 2.0 * f0[i];
           double d;
-          if (okp && okm && cv < 0) d = 0.5 * k.h * (fm[q] - fpl[q]) / cv;
-          else d = (fpl[q] > fm[q]) ? 2.0 * k.h : -2.0 * k.h;
+          if (okp && okm && cv < 0) d = 0.5 * k.h * (fm[i] - fpl[i]) / cv;
+          else d = (fpl[i] > fm[i]) ? 2.0 * k.h : -2.0 * k.h;
           d = std::max(-2.0 * k.h, std::min(2.0 * k.h, d));
-          vn[q] = clampv(k, q, x0[q] + d);
+          vn[i] = clampv(k, pq(i), x0[i] + d);
         }
         const bool okn = trial(vn, fn);
-        // keep the best of the four trials per pol; the step grows when the
+        // keep the best of the four trials per value; the step grows when the
         // best trial is the far one and shrinks when no trial beat the centre
-        bool moved = false, far = false;
-        for (int q = 0; q < nq; ++q) {
-          double bv = x0[q], bf = f0[q];
-          if (okp && fpl[q] > bf) { bv = vp[q]; bf = fpl[q]; }
-          if (okm && fm[q] > bf) { bv = vm[q]; bf = fm[q]; }
-          if (okn && fn[q] > bf) { bv = vn[q]; bf = fn[q]; }
-          get(k, q) = bv;
-          if (k.kind == 2) goal = bf; else best_pol[q] = bf;
-          moved |= bv != x0[q];
-          far |= std::fabs(bv - x0[q]) > 1.5 * k.h;
+        bool moved = false, far = false, stale = false;
+        for (int i = 0; i < nq; ++i) {
+          double bv = x0[i], bf = f0[i];
+          if (okp && fpl[i] > bf) { bv = vp[i]; bf = fpl[i]; }
+          if (okm && fm[i] > bf) { bv = vm[i]; bf = fm[i]; }
+          if (okn && fn[i] > bf) { bv = vn[i]; bf = fn[i]; }
+          get(k, pq(i)) = bv;
+          if (joint) goal = bf; else best_pol[i] = bf;
+          moved |= bv != x0[i];
+          far |= std::fabs(bv - x0[i]) > 1.5 * k.h;
+          stale |= bv != last[i];
         }
         k.h *= far ? 2.0 : moved ? 1.0 : 0.5;
-        if (k.kind != 2) {
+        if (!joint) {
+          // the kept per-pol values come from different trials: the joint goal anew
           if (!align_eval(c, false, mp, fp)) return (P = start, build_tables(pl), set_err(pl, DH_ERR_ERROR), -FLT_MAX);
-          goal = db(mp[0] + (np > 1 ? mp[1] : 0.0), fp[0] + (np > 1 ? fp[1] : 0.0));
-        } else if (moved) {
-          if (!align_eval(c, true, mp, fp)) return (P = start, build_tables(pl), set_err(pl, DH_ERR_ERROR), -FLT_MAX);
-          for (int q = 0; q < np; ++q) best_pol[q] = db(mp[q], fp[q]);
+          goal = captured();
+        } else if (stale) {
+          // the tables (HG tables for the waist) still hold the last trial's value
+          double gv;
+          if (!eval_goal(k.kind == 2, gv)) return (P = start, build_tables(pl), set_err(pl, DH_ERR_ERROR), -FLT_MAX);
+          if (!metric_goal) for (int q = 0; q < np; ++q) best_pol[q] = db(mp[q], fp[q]);
         }
       }
       rep.sweeps = sweep + 1;
       if (sweep >= 1 && goal - goal0 < tol) break;
     }
   }
-  // leave the plan at the final parameters with complete tables
-  if (!align_eval(c, true, mp, fp)) return (P = start, build_tables(pl), set_err(pl, DH_ERR_ERROR), -FLT_MAX);
-  if (build_spectral(pl) != DH_SUCCESS) return (P = start, build_tables(pl), set_err(pl, DH_ERR_ERROR), -FLT_MAX);
-  goal = db(mp[0] + (np > 1 ? mp[1] : 0.0), fp[0] + (np > 1 ? fp[1] : 0.0));
+  // leave the plan at the final parameters with complete tables; all the
+  // metrics of the final coefficients go in the report
+  if (!eval_goal(true, goal) || build_spectral(pl) != DH_SUCCESS ||
+      tm_compute(pl, c.batch, pl->goal_indep, pl->goal_aa, s, rep.metrics) != DH_SUCCESS)
+    return (P = start, build_tables(pl), set_err(pl, DH_ERR_ERROR), -FLT_MAX);
   for (int w = 0; w < pl->nws; ++w) fill_kargs(pl, w);
+  rep.goal = pl->goal;
   rep.goal_db = goal;
-  rep.captured = std::pow(10.0, goal / 10.0);
+  rep.captured = std::pow(10.0, captured() / 10.0);
   rep.evaluations = c.evals;
   pl->rep = rep;
   pl->last_batch = batch;
@@ -1060,106 +1191,20 @@ extern "C" float dh_autoalign(dh_handle h, const void* frames, int batch, int mo
   return (float)goal;
 }
 
-namespace {
-double db10(double x) {
-  if (!(x > 0.0)) return -HUGE_VAL;
-  if (std::isinf(x)) return HUGE_VAL;
-  return 10.0 * std::log10(x);
-}
-}  // namespace
-
 extern "C" int dh_transfer_metrics(dh_handle h, int pol_independent, int mul_conj_trans, double* out) {
   Plan* pl = get(h);
   if (!pl) return DH_ERR_INVALIDHANDLE;
   if (!out) return set_err(pl, DH_ERR_NULLPOINTER);
-  const int B = pl->last_batch, P = pl->params.pol_count, M = pl->g.nmodes;
-  if (B < 1 || M < 1) return set_err(pl, DH_ERR_ERROR);
-  dh::TmArgs t{};
-  t.c = pl->ka[0].coefs;
-  t.modes = pl->ka[0].modes;
-  t.B = B; t.P = P; t.M = M;
-  t.indep = pol_independent ? 1 : 0;
-  t.rows = t.indep ? P * B : B;
-  t.cols = P * M;
-  // singular values: eigenvalues of the smaller Gram matrix
-  const int byrows = t.rows <= t.cols;
-  const int n = byrows ? t.rows : t.cols;
-  // the matrix of the diagonal metrics: A (rows x cols) or A A^H (rows x rows)
-  const bool aa = mul_conj_trans != 0;
-  const bool extra = aa && !byrows;            // A A^H besides the Gram of the SVD
-  const int ncol = aa ? t.rows : t.cols;
-  const int nd = std::min(t.rows, ncol);
-  size_t o = 0;
-  auto take = [&](size_t bytes) { size_t r = o; o += align256(bytes); return r; };
-  const size_t og = take((size_t)n * n * 16), od = extra ? take((size_t)t.rows * t.rows * 16) : 0;
-  const size_t oe = take((size_t)n * 8), ow = take((size_t)n * 8), oi = take(8);
-  const size_t orow = take((size_t)t.rows * 8), odg = take((size_t)nd * 8), osm = take((size_t)nd * 8);
-  if (o > pl->tm_bytes) {
-    if (pl->tm_mem) (void)hipFree(pl->tm_mem);
-    pl->tm_mem = nullptr;
-    pl->tm_bytes = 0;
-    if (hipMalloc(&pl->tm_mem, o) != hipSuccess) {
-      (void)hipGetLastError();
-      return set_err(pl, DH_ERR_MEMORYALLOCATION);
-    }
-    pl->tm_bytes = o;
-  }
-  char* m = pl->tm_mem;
-  double2* g = (double2*)(m + og);
-  double2* gd = extra ? (double2*)(m + od) : g;
-  hipStream_t s = pl->last_stream;
-  if (!pl->blas && rocblas_create_handle(&pl->blas) != rocblas_status_success) {
-    pl->blas = nullptr;
-    return set_err(pl, DH_ERR_ERROR);
-  }
-  if (rocblas_set_stream(pl->blas, s) != rocblas_status_success) return set_err(pl, DH_ERR_ERROR);
-  // the row statistics read the Gram matrix before the eigen-solver overwrites it
-  if (dh::launch_tm_gram(t, byrows, n, g, s) != hipSuccess ||
-      (extra && dh::launch_tm_gram(t, 1, t.rows, gd, s) != hipSuccess) ||
-      dh::launch_tm_rows(t, aa ? gd : nullptr, t.rows, ncol, nd, (double*)(m + orow), (double*)(m + odg),
-                         (double*)(m + osm), s) != hipSuccess)
-    return set_err(pl, DH_ERR_ERROR);
-  if (rocsolver_zheevd(pl->blas, rocblas_evect_none, rocblas_fill_upper, n, (rocblas_double_complex*)g, n,
-                       (double*)(m + oe), (double*)(m + ow), (rocblas_int*)(m + oi)) != rocblas_status_success)
-    return set_err(pl, DH_ERR_ERROR);
-  std::vector<double> eig(n), rowp(t.rows), dg(nd), sm(nd);
-  int info = 0;
-  if (hipMemcpyAsync(eig.data(), m + oe, (size_t)n * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipMemcpyAsync(rowp.data(), m + orow, (size_t)t.rows * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipMemcpyAsync(dg.data(), m + odg, (size_t)nd * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipMemcpyAsync(sm.data(), m + osm, (size_t)nd * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipMemcpyAsync(&info, m + oi, 4, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
-    return set_err(pl, DH_ERR_ERROR);
-  if (info != 0) return set_err(pl, DH_ERR_ERROR);
-  // IL, MDL from s^2 = the Gram's eigenvalues (rounding can leave tiny negatives)
-  double smin = HUGE_VAL, smax = 0.0, ssum = 0.0;
-  for (double e : eig) {
-    const double v = std::max(e, 0.0);
-    smin = std::min(smin, v);
-    smax = std::max(smax, v);
-    ssum += v;
-  }
-  out[DH_METRIC_IL] = db10(ssum / n);
-  out[DH_METRIC_MDL] = smax > 0.0 ? db10(smin / smax) : -HUGE_VAL;
-  double total = 0.0, dsum = 0.0, ssame = 0.0, dmax = 0.0, dmin = HUGE_VAL, rmax = -1.0, rmin = HUGE_VAL;
-  for (int i = 0; i < t.rows; ++i) total += rowp[i];
-  for (int i = 0; i < nd; ++i) {
-    dsum += dg[i];
-    ssame += sm[i];
-    dmax = std::max(dmax, dg[i]);
-    dmin = std::min(dmin, dg[i]);
-    const double off = rowp[i] - dg[i];
-    const double r = off > 0.0 ? dg[i] / off : HUGE_VAL;
-    rmax = std::max(rmax, r);
-    rmin = std::min(rmin, r);
-  }
-  out[DH_METRIC_DIAG] = db10(dsum / nd);
-  out[DH_METRIC_SNRAVG] = total > dsum ? db10(dsum / (total - dsum)) : HUGE_VAL;
-  out[DH_METRIC_DIAGBEST] = db10(dmax);
-  out[DH_METRIC_DIAGWORST] = db10(dmin);
-  out[DH_METRIC_SNRBEST] = db10(rmax);
-  out[DH_METRIC_SNRWORST] = db10(rmin);
-  out[DH_METRIC_SNRMG] = total > ssame ? db10(ssame / (total - ssame)) : HUGE_VAL;
+  return set_err(pl, tm_compute(pl, pl->last_batch, pol_independent, mul_conj_trans, pl->last_stream, out));
+}
+
+extern "C" int dh_set_align_goal(dh_handle h, int goal, int pol_independent, int mul_conj_trans) {
+  Plan* pl = get(h);
+  if (!pl) return DH_ERR_INVALIDHANDLE;
+  if (goal < DH_GOAL_CAPTURED || goal >= DH_METRIC_COUNT) return set_err(pl, DH_ERR_INVALIDARGUMENT);
+  pl->goal = goal;
+  pl->goal_indep = pol_independent != 0;
+  pl->goal_aa = mul_conj_trans != 0;
   return set_err(pl, DH_SUCCESS);
 }
 

@@ -79,6 +79,9 @@ def test_invalid_handles_without_gpu():
     m = ctypes.c_int(7)
     assert L.dh_mode_coefs(999, None, None, ctypes.byref(b), ctypes.byref(m), None, 1) == dh.ERR_INVALIDHANDLE
     assert b.value == 0 and m.value == 0   # getters zero their outputs on a bad handle
+    assert L.dh_set_align_goal(999, 0, 0, 0) == dh.ERR_INVALIDHANDLE
+    out = (ctypes.c_double * 9)()
+    assert L.dh_transfer_metrics(999, 0, 0, out) == dh.ERR_INVALIDHANDLE
 
 
 def test_window_size_floored_to_16():

@@ -420,6 +420,67 @@ def test_serving_admission_by_budget():
     plan.destroy()
 
 
+def test_alignment_metric_goal_matches_oracle():
+    """With a transfer-matrix metric as the goal and nothing to tweak, the
+    goal is that metric of the oracle's coefficients at the plan's
+    parameters; the report carries all nine (1024x1024, 2 pols, G=30)."""
+    cfg = dh_synth.config(4)
+    f, _ = dh_synth.make_frames(cfg, n_frames=3)
+    p = cfg["truth"]
+    oc = np.stack([oracle.process_frame(f[i].astype(np.float64), p)["coefs"] for i in range(f.shape[0])])
+    for goal, indep, aa in (("IL", False, False), ("MDL", False, False), ("SNRMG", True, True)):
+        ref = oracle.transfer_metrics(oc, 30, pol_independent=indep, mul_conj_trans=aa)
+        _say("metric goal %s indep=%d aa=%d" % (goal, indep, aa))
+        dh, plan, ft = _align_plan(p, f)
+        plan.set_align_goal(goal, indep, aa)
+        g = plan.autoalign(ft, f.shape[0], mode=dh.ALIGN_TWEAK, what=0)
+        rep = plan.align_report()
+        plan.destroy()
+        _say("goal gpu %.6f dB oracle %.6f dB" % (g, ref[goal]))
+        assert rep.goal == oracle.METRICS.index(goal)
+        assert abs(g - ref[goal]) <= 1e-3
+        for i, k in enumerate(oracle.METRICS):
+            if math.isinf(ref[k]):
+                assert rep.metrics[i] == ref[k], k
+            else:
+                assert abs(rep.metrics[i] - ref[k]) <= 1e-3, (k, rep.metrics[i], ref[k])
+
+
+def test_alignment_il_goal_recovers_truth():
+    """AutoAlign on the insertion loss of the batch transfer matrix (each
+    pol's tilt and defocus a coordinate of its own) finds the parameters the
+    frames were made with; the report's metrics are those of the aligned
+    plan's processed coefficients."""
+    cfg = dh_synth.config(4)
+    n = 20
+    f, _ = dh_synth.make_frames(cfg, n_frames=n)
+    truth = cfg["truth"]
+    dh, plan, ft = _align_plan(cfg["params"], f)
+    plan.set_align_goal("IL")
+    _say("alignment on IL from nominal, %d frames" % n)
+    g = plan.autoalign(ft, n, mode=dh.ALIGN_FULL, what=dh.ALIGN_TILT | dh.ALIGN_DEFOCUS | dh.ALIGN_WAIST, tol=1e-5)
+    rep = plan.align_report()
+    got = plan.params()
+    bins = [1565e-9 / (512 * 20e-6) / oracle.DEG, 1565e-9 / (1024 * 20e-6) / oracle.DEG]
+    _say("IL %.5f dB (after snap %.5f), %d trials, %d sweeps" % (g, rep.start_goal_db, rep.evaluations, rep.sweeps))
+    for q in range(2):
+        _say("pol %d tilt err %.3f / %.3f bins, defocus err %.4f D" % (
+            q, (got["tilt_deg"][q][0] - truth["tilt_deg"][q][0]) / bins[0],
+            (got["tilt_deg"][q][1] - truth["tilt_deg"][q][1]) / bins[1], got["defocus"][q] - truth["defocus"][q]))
+    _say("waist err %.4f %%" % (100 * (got["waist"] / truth["waist"] - 1)))
+    assert rep.goal == oracle.METRICS.index("IL") and g == pytest.approx(rep.metrics[0], abs=1e-4)
+    for q in range(2):
+        assert abs(got["tilt_deg"][q][0] - truth["tilt_deg"][q][0]) < 0.3 * bins[0]
+        assert abs(got["tilt_deg"][q][1] - truth["tilt_deg"][q][1]) < 0.3 * bins[1]
+        assert abs(got["defocus"][q] - truth["defocus"][q]) < 0.01
+    assert abs(got["waist"] / truth["waist"] - 1) < 0.01
+    plan.process(ft, n, None)
+    after = plan.transfer_metrics()
+    plan.destroy()
+    for i, k in enumerate(oracle.METRICS):
+        assert abs(after[k] - rep.metrics[i]) <= 1e-3, (k, after[k], rep.metrics[i])
+
+
 # ---------------------------------------------------------------- transfer-matrix metrics
 @pytest.mark.parametrize("n", [90, 1000])
 def test_transfer_metrics_match_oracle(n):
