@@ -10,3 +10,4 @@ from .holo_oracle import (  # noqa: F401
     field_from_window, overlap, power_normalise, process_frame, process_batch, captured_power, goal_db,
 )
 from .transfer_metrics import METRICS, transfer_matrix, column_keys, transfer_metrics  # noqa: F401,E402
+from .align_snap import field_moments, batch_moments, snap_centre_waist  # noqa: F401,E402

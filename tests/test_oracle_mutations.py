@@ -153,3 +153,49 @@ def test_metric_pins_catch_planted_mistake(name, monkeypatch):
         except (AssertionError, FloatingPointError, ZeroDivisionError, ValueError):
             failed += 1
     assert failed > 0, name
+
+
+# ---------------------------------------------------------------- alignment snap
+SNAP_SRC = os.path.join(os.path.dirname(SRC), "align_snap.py")
+
+SNAP_MUTATIONS = {
+    "centre_sign": ("cx + sx / s, cy + sy / s", "cx - sx / s, cy - sy / s"),
+    "centre_axes_swapped": ("cx + sx / s, cy + sy / s", "cx + sy / s, cy + sx / s"),
+    "not_central": ("mxx += sxx - sx * sx / s", "mxx += sxx"),
+    "group_factor": ("(2 * g + 1)", "(2 * g - 1)"),
+    "grid_origin": ("(np.arange(wx) - wx / 2.0)", "np.arange(wx)"),
+    "amplitude_not_intensity": ("i = np.abs(np.asarray(field, dtype=np.complex128)) ** 2",
+                                "i = np.abs(np.asarray(field, dtype=np.complex128))"),
+    "pol_not_own": ("cx, cy = params[\"beam_centre\"][pol]", "cx, cy = params[\"beam_centre\"][0]"),
+}
+
+
+def _snap_mutant(name):
+    import oracle
+    src = open(SNAP_SRC).read()
+    old, new = SNAP_MUTATIONS[name]
+    assert src.count(old) == 1, name
+    src = src.replace(old, new).replace("from .holo_oracle import field_from_window, geometry, spectrum_window\n", "")
+    mod = types.ModuleType("snap_mutant_" + name)
+    for k in ("field_from_window", "geometry", "spectrum_window"):
+        mod.__dict__[k] = getattr(oracle, k)
+    exec(compile(src, SNAP_SRC + ":" + name, "exec"), mod.__dict__)
+    return mod
+
+
+@pytest.mark.parametrize("name", sorted(SNAP_MUTATIONS))
+def test_snap_pins_catch_planted_mistake(name, monkeypatch):
+    import oracle
+    import tests.test_oracle_pins as pins
+    mut = _snap_mutant(name)
+    monkeypatch.setattr(oracle, "snap_centre_waist", mut.snap_centre_waist)
+    monkeypatch.setattr(oracle, "batch_moments", mut.batch_moments)
+    failed = 0
+    for t in [pins.test_snap_centre_is_the_offset_of_a_shifted_gaussian,
+              pins.test_snap_waist_from_every_mode_of_g_groups,
+              pins.test_snap_centre_per_polarisation]:
+        try:
+            t()
+        except AssertionError:
+            failed += 1
+    assert failed > 0, name

@@ -418,3 +418,67 @@ def test_metrics_aa_star_of_a_wide_matrix_and_two_pol_groups():
     a[1, 4] = 0.2                                    # pol 0 group 1 -> pol 1 group 1: noise
     m = oracle.transfer_metrics(a.reshape(6, 2, 3), 2)
     assert abs(m["SNRMG"] - 10 * math.log10(6.0 / 0.04)) < 1e-9
+
+
+# ---------------------------------------------------------------- alignment snap (centre, waist)
+def _one_mode_frames(truth, modes):
+    """One noiseless frame per entry of `modes`: a list, per frame, of
+    (pol, mode index) pairs holding unit amplitude. Each hologram is divided
+    by its reference amplitude max|S| (found independently of the oracle), so
+    that the field each frame carries is S itself: unit power per mode."""
+    nm = oracle.mode_count(truth["max_mg"])
+    out = []
+    for entry in modes:
+        c = np.zeros((truth["pol_count"], nm), dtype=complex)
+        for pol, k in entry:
+            c[pol, k] = 1.0
+        out.append(dh_synth.forward_hologram(truth, c) / _signal_amplitude(truth, c))
+    return np.stack(out)
+
+
+def test_snap_centre_is_the_offset_of_a_shifted_gaussian():
+    # HG00 displaced by (0.7, -1.3) pixels: the intensity centroid of the field
+    # reconstructed about the nominal centre is that displacement
+    truth = dict(dh_synth.config(0)["truth"])
+    pix = truth["pixel_size"]
+    truth["beam_centre"] = [[0.7 * pix, -1.3 * pix]]
+    f = _one_mode_frames(truth, [[(0, 0)]])
+    centre, _ = oracle.snap_centre_waist(f, dict(truth, beam_centre=[[0.0, 0.0]]))
+    assert abs(centre[0][0] / pix - 0.7) < 1e-6
+    assert abs(centre[0][1] / pix + 1.3) < 1e-6
+
+
+def test_snap_waist_from_every_mode_of_g_groups():
+    # one frame per HG mode of G groups at unit power: the pooled second moment
+    # is w^2 (2G + 1) / 12 per axis, whatever the centre offset
+    truth = dict(dh_synth.config(0)["truth"])
+    pix = truth["pixel_size"]
+    nm = oracle.mode_count(truth["max_mg"])
+    for off in ([0.0, 0.0], [2.4 * pix, 0.9 * pix]):
+        t = dict(truth, beam_centre=[off])
+        f = _one_mode_frames(t, [[(0, k)] for k in range(nm)])
+        centre, w = oracle.snap_centre_waist(f, dict(t, beam_centre=[[0.0, 0.0]]))
+        assert abs(w / truth["waist"] - 1.0) < 1e-6
+        assert abs(centre[0][0] - off[0]) < 1e-6 * pix and abs(centre[0][1] - off[1]) < 1e-6 * pix
+    # the moments of HG_mn alone: <x^2> = w^2 (2m + 1) / 4 (m the x order)
+    g = oracle.geometry(truth)
+    for k, (m, n) in enumerate(oracle.mode_list(truth["max_mg"])):
+        f = _one_mode_frames(truth, [[(0, k)]])
+        mom = oracle.batch_moments(f, truth)[0]
+        assert abs(mom[3] / mom[0] / (truth["waist"] ** 2 * (2 * m + 1) / 4) - 1) < 1e-6, (m, n)
+        assert abs(mom[4] / mom[0] / (truth["waist"] ** 2 * (2 * n + 1) / 4) - 1) < 1e-6, (m, n)
+        assert g["wx"] > 0
+
+
+def test_snap_centre_per_polarisation():
+    # two pols displaced differently: each pol's centre comes from its own field
+    truth = dict(dh_synth.config(1)["truth"], defocus=[0.0, 0.0], max_mg=2, fft_w=256, fft_h=256)
+    pix = truth["pixel_size"]
+    truth["beam_centre"] = [[1.6 * pix, -0.4 * pix], [-2.2 * pix, 3.1 * pix]]
+    f = _one_mode_frames(truth, [[(0, 0), (1, 0)]])
+    # from a start that differs per pol, the estimate is still the truth
+    start = [[0.5 * pix, 0.0], [-1.0 * pix, 1.0 * pix]]
+    centre, _ = oracle.snap_centre_waist(f, dict(truth, beam_centre=start))
+    for q in range(2):
+        for a in range(2):
+            assert abs(centre[q][a] - truth["beam_centre"][q][a]) < 1e-6 * pix, (q, a)
