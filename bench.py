@@ -167,7 +167,7 @@ def serving_bench(dh, torch, workers, seconds=10.0, warm=1.0, rate=5000.0, seed=
 
 def alignment_bench(dh, torch, workers, align_frames=50, decomp_frames=5000):
     """Alignment workload: align 50 frames 1024x1024 (2 pols, G=30) from the
-    nominal tilt/defocus/waist, then decompose 5000 frames (a pool of 250
+    nominal tilt/defocus/waist/beam centre, then decompose 5000 frames (a pool of 250
     distinct frames tiled x20) at the aligned parameters."""
     cfg = dh_synth.config(4)
     truth = cfg["truth"]
@@ -177,17 +177,21 @@ def alignment_bench(dh, torch, workers, align_frames=50, decomp_frames=5000):
     plan = dh.Plan(cfg["params"], max_batch=decomp_frames)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    goal = plan.autoalign(frames, align_frames, dh.ALIGN_FULL, dh.ALIGN_TILT | dh.ALIGN_DEFOCUS | dh.ALIGN_WAIST, 1e-5)
+    what = dh.ALIGN_TILT | dh.ALIGN_DEFOCUS | dh.ALIGN_WAIST | dh.ALIGN_CENTRE
+    goal = plan.autoalign(frames, align_frames, dh.ALIGN_FULL, what, 1e-5)
     wall = time.perf_counter() - t0
     rep = plan.align_report()
     got = plan.params()
     bins = [1565e-9 / (512 * 20e-6) * 180 / np.pi, 1565e-9 / (1024 * 20e-6) * 180 / np.pi]
-    out = {"workload": "align 50 frames 1024x1024 f32, 2 pols, G=30 from nominal; decompose 5000 frames",
+    out = {"workload": "align 50 frames 1024x1024 f32, 2 pols, G=30 from nominal (tilt, defocus, waist, "
+                       "beam centre); decompose 5000 frames",
            "align_wall_s": round(wall, 4), "goal_db": round(goal, 6), "trials": rep.evaluations,
            "sweeps": rep.sweeps,
            "tilt_err_bins": [[round((got["tilt_deg"][q][a] - truth["tilt_deg"][q][a]) / bins[a], 4)
                               for a in range(2)] for q in range(2)],
            "defocus_err_D": [round(got["defocus"][q] - truth["defocus"][q], 5) for q in range(2)],
+           "centre_err_px": [[round((got["beam_centre"][q][a] - truth["beam_centre"][q][a]) / 20e-6, 4)
+                              for a in range(2)] for q in range(2)],
            "waist_err_pct": round(100 * (got["waist"] / truth["waist"] - 1), 3)}
     # the same alignment with the insertion loss of the batch transfer matrix
     # as the goal (each pol's tilt and defocus its own coordinate)
@@ -195,7 +199,7 @@ def alignment_bench(dh, torch, workers, align_frames=50, decomp_frames=5000):
     plan_il.set_align_goal("IL")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    il = plan_il.autoalign(frames, align_frames, dh.ALIGN_FULL, dh.ALIGN_TILT | dh.ALIGN_DEFOCUS | dh.ALIGN_WAIST, 1e-5)
+    il = plan_il.autoalign(frames, align_frames, dh.ALIGN_FULL, what, 1e-5)
     wall = time.perf_counter() - t0
     rep = plan_il.align_report()
     got = plan_il.params()

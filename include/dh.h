@@ -243,14 +243,14 @@ int dh_stage_times(dh_handle h, double* ms, int* launches);
 
 /*
  * Automatic alignment (the paper's digHoloAutoAlign, "Automatic (AutoAlign)"
- * and "AutoAlign operation modes"): searches the reference tilt, defocus and
- * the HG waist that maximise the goal below, on `batch` frames (device
- * pointer as in dh_process_batch), and leaves the plan at the result.
+ * and "AutoAlign operation modes"): searches the reference tilt and defocus,
+ * the beam centre and the HG waist that maximise the goal below, on `batch`
+ * frames (device pointer as in dh_process_batch), and leaves the plan at the
+ * result.
  *   mode: DH_ALIGN_FULL (snap, then tweak), DH_ALIGN_TWEAK (refine from the
  *         current parameters), DH_ALIGN_ESTIMATE (snap only);
- *   what: bitmask of DH_ALIGN_TILT, DH_ALIGN_DEFOCUS, DH_ALIGN_WAIST
- *         (DH_ALIGN_CENTRE, beam-centre search, is not provided:
- *         DH_ERR_INVALIDARGUMENT);
+ *   what: bitmask of DH_ALIGN_TILT, DH_ALIGN_DEFOCUS, DH_ALIGN_WAIST,
+ *         DH_ALIGN_CENTRE;
  *   tol:  stop when a full sweep over the parameters improves the goal by
  *         less than tol (dB), as the paper's AutoAlignTol.
  * Goal (dh_set_align_goal): by default the captured power,
@@ -258,11 +258,19 @@ int dh_stage_times(dh_handle h, double* ms, int* launches);
  * polarisations, computed in FP64 (0 dB: the field is exactly a combination
  * of the basis modes); or one transfer-matrix metric (DH_METRIC_*) of the
  * batch's raw coefficients. With a metric goal every trial evaluates that
- * metric, and each polarisation's tilt and defocus is a coordinate of its own. The snap puts the tilt at the centroid of
- * the batch power spectrum (above its mean) near the current tilt; the tweak
- * is a coordinate search. Tilts stay within 0.6 window radii of their start.
- * Each trial re-runs the window gather, the IFFTs and the overlap from a
- * spectrum computed once per call and kept on the device.
+ * metric, and each polarisation's tilt, defocus and centre is a coordinate of
+ * its own (pol locks: dh_set_pol_lock).
+ * Snap: the tilt at the centroid of the batch power spectrum (above its mean)
+ * near the current tilt; then, from the fields reconstructed there (G > 0),
+ * the beam centre at the centroid of the batch intensity |E|^2 and the waist
+ * from its pooled central second moment, w = sqrt(6 (<x^2> + <y^2>) / (2G + 1))
+ * (exact when the power is spread evenly over the modes of G groups).
+ * Defocus is not snapped. Tweak: a coordinate search. Tilts stay within 0.6
+ * window radii and beam centres within an eighth of the FFT window of their
+ * start; a centre that moves the FFT window out of the frame is a failed
+ * trial. Each trial re-runs the window gather, the IFFTs and the overlap from
+ * a spectrum kept on the device, computed again only when a centre moves the
+ * window by whole pixels.
  * The returned value is the goal in dB; -FLT_MAX on failure, with the reason
  * in dh_last_error (DH_ERR_INVALIDHANDLE, NULLPOINTER, INVALIDDIMENSION,
  * INVALIDARGUMENT, MEMORYALLOCATION, ERROR). Synchronises the device.
@@ -295,7 +303,19 @@ typedef struct dh_align_report {
   double snap_tilt_deg[2][2];  /* tilt found by the snap ([pol][x,y]) */
   int goal;                    /* the goal optimised: DH_GOAL_CAPTURED or DH_METRIC_* */
   double metrics[DH_METRIC_COUNT];  /* every metric at the final parameters (dh_transfer_metrics) */
+  double snap_centre[2][2];    /* beam centre found by the snap ([pol][x,y], metres) */
+  double snap_waist;           /* waist found by the snap (metres) */
 } dh_align_report;
+
+/*
+ * Polarisation locks of later dh_autoalign calls ("Alignment": PolLockTilt,
+ * PolLockDefocus, PolLockBasisWaist): a bitmask of DH_ALIGN_TILT and
+ * DH_ALIGN_DEFOCUS; a locked parameter of pol 1 takes pol 0's value after the
+ * snap and both move as one coordinate. DH_ALIGN_WAIST is accepted and has no
+ * effect: both pols always share one waist here. Errors: DH_ERR_INVALIDHANDLE,
+ * DH_ERR_INVALIDARGUMENT (other bits).
+ */
+int dh_set_pol_lock(dh_handle h, unsigned lock);
 
 /* Report of the last dh_autoalign on h. */
 int dh_get_align_report(dh_handle h, dh_align_report* out);

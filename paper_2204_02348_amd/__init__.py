@@ -43,7 +43,7 @@ EXPORTS = ["dh_plan_check", "dh_plan", "dh_process_batch", "dh_mode_coefs", "dh_
            "dh_get_fields", "dh_get_params", "dh_get_plan_info", "dh_set_stage_timing", "dh_stage_times",
            "dh_autoalign", "dh_get_align_report", "dh_serve_create", "dh_serve_info", "dh_serve_submit",
            "dh_serve_progress", "dh_serve_replay", "dh_serve_stats", "dh_serve_destroy",
-           "dh_last_error", "dh_transfer_metrics", "dh_set_align_goal", "dh_destroy"]
+           "dh_last_error", "dh_transfer_metrics", "dh_set_align_goal", "dh_set_pol_lock", "dh_destroy"]
 ALIGN_FULL, ALIGN_TWEAK, ALIGN_ESTIMATE = 0, 1, 2
 ALIGN_TILT, ALIGN_DEFOCUS, ALIGN_WAIST, ALIGN_CENTRE = 1, 2, 4, 8
 # launch stages (DH_STAGE_*): row pass; column pass (FFT along y + window,
@@ -73,7 +73,8 @@ class Params(C.Structure):
 class AlignReport(C.Structure):
     _fields_ = [("evaluations", C.c_int), ("sweeps", C.c_int), ("start_goal_db", C.c_double),
                 ("goal_db", C.c_double), ("captured", C.c_double), ("snap_tilt_deg", (C.c_double * 2) * 2),
-                ("goal", C.c_int), ("metrics", C.c_double * 9)]
+                ("goal", C.c_int), ("metrics", C.c_double * 9), ("snap_centre", (C.c_double * 2) * 2),
+                ("snap_waist", C.c_double)]
 
 
 class PlanInfo(C.Structure):
@@ -123,6 +124,7 @@ def lib():
         L.dh_serve_destroy.argtypes = [C.c_int]
         L.dh_transfer_metrics.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double)]
         L.dh_set_align_goal.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int]
+        L.dh_set_pol_lock.argtypes = [C.c_int, C.c_uint]
         L.dh_last_error.argtypes = [C.c_int]
         L.dh_destroy.argtypes = [C.c_int]
         for name in EXPORTS:
@@ -238,6 +240,12 @@ class Plan:
         rc = lib().dh_set_align_goal(self.handle, g, int(pol_independent), int(mul_conj_trans))
         if rc != SUCCESS:
             raise DhError(rc, "dh_set_align_goal")
+
+    def set_pol_lock(self, lock: int):
+        """Lock pol 1's tilt and/or defocus (ALIGN_TILT | ALIGN_DEFOCUS) to pol 0's in autoalign."""
+        rc = lib().dh_set_pol_lock(self.handle, int(lock))
+        if rc != SUCCESS:
+            raise DhError(rc, "dh_set_pol_lock")
 
     def transfer_metrics(self, pol_independent: bool = False, mul_conj_trans: bool = False) -> dict:
         """The nine metrics (dB) of the last batch's transfer matrix (dh_transfer_metrics)."""

@@ -265,6 +265,7 @@ struct Plan {
   char* tm_mem = nullptr;
   size_t tm_bytes = 0;
   rocblas_handle blas = nullptr;
+  unsigned lock = 0;                 // DH_ALIGN_TILT / DH_ALIGN_DEFOCUS: pol 1 takes pol 0's value
   int goal = DH_GOAL_CAPTURED;       // alignment goal and its transfer-matrix options
   int goal_indep = 0, goal_aa = 0;
   size_t amem_bytes = 0;
@@ -918,12 +919,34 @@ struct AlignCtx {
   Plan* pl;
   hipStream_t s;
   int batch;
+  const void* frames;
+  int u16;
   int bxe, bye;
   int k0e[2], ky0e[2];
+  int ox[2] = {0, 0}, oy[2] = {0, 0};   // window origins the stored spectrum was made at
+  float2* t1e;
   float2* spec;
   double* capt;
+  float2* fields = nullptr;             // set: trials also write the fields here
   int evals = 0;
 };
+
+// the extended row pass and column FFT of the batch at the plan's current
+// window origins, stored as the resident spectrum
+bool align_fft(AlignCtx& c) {
+  Plan* pl = c.pl;
+  dh::KArgs ke = pl->ka[0];
+  ke.bx = c.bxe;
+  ke.t1 = c.t1e;
+  for (int q = 0; q < pl->params.pol_count; ++q) {
+    ke.pol[q].k0 = c.k0e[q];
+    ke.pol[q].ky0 = c.ky0e[q];
+    c.ox[q] = pl->g.pol[q].x0;
+    c.oy[q] = pl->g.pol[q].y0;
+  }
+  return dh::launch_row(ke, c.frames, c.u16, 0, c.batch, c.s) == hipSuccess &&
+         dh::launch_spec(ke, c.spec, c.bye, c.batch, c.s) == hipSuccess;
+}
 
 // one trial with the plan's current parameters: per-pol mode and field power
 // summed over the batch (FP64), or false if the window left the stored region
@@ -940,8 +963,13 @@ bool align_eval(AlignCtx& c, bool hg, double mp[2], double fp[2]) {
   }
   if (build_tables(pl, hg, false) != DH_SUCCESS) return false;
   for (int w = 0; w < pl->nws; ++w) fill_kargs(pl, w);
+  // a beam centre that moved the window by whole pixels needs the spectrum anew
+  bool moved = false;
+  for (int q = 0; q < np; ++q) moved |= g.pol[q].x0 != c.ox[q] || g.pol[q].y0 != c.oy[q];
+  if (moved && !align_fft(c)) return false;
   dh::KArgs k = pl->ka[0];
   k.capt = c.capt;
+  k.fields = c.fields;
   k.nblk = field_blocks(g);      // trials run the field path
   const size_t per_frame = (size_t)np * c.bxe * c.bye;
   for (int b0 = 0; b0 < c.batch; b0 += pl->chunk) {
@@ -975,7 +1003,7 @@ extern "C" float dh_autoalign(dh_handle h, const void* frames, int batch, int mo
   if (!frames) return (set_err(pl, DH_ERR_NULLPOINTER), -FLT_MAX);
   if (batch < 1) batch = 1;
   if (batch > pl->max_batch) return (set_err(pl, DH_ERR_INVALIDDIMENSION), -FLT_MAX);
-  if (mode < DH_ALIGN_FULL || mode > DH_ALIGN_ESTIMATE || (what & DH_ALIGN_CENTRE) ||
+  if (mode < DH_ALIGN_FULL || mode > DH_ALIGN_ESTIMATE || (what & ~(DH_ALIGN_TILT | DH_ALIGN_DEFOCUS | DH_ALIGN_WAIST | DH_ALIGN_CENTRE)) ||
       (mode != DH_ALIGN_ESTIMATE && pl->g.G == 0) || !(tol >= 0.f))
     return (set_err(pl, DH_ERR_INVALIDARGUMENT), -FLT_MAX);
   hipStream_t s = (hipStream_t)stream;
@@ -988,7 +1016,7 @@ extern "C" float dh_autoalign(dh_handle h, const void* frames, int batch, int mo
   const dh_params start = P;
   // search margin around the starting tilt: 0.6 w_c, within the spectrum
   const double mdeg = 0.6 * P.window_radius_deg;
-  AlignCtx c{pl, s, batch};
+  AlignCtx c{pl, s, batch, frames, P.input_dtype == DH_INPUT_U16};
   c.bxe = c.bye = 0;
   double tlo[2][2], thi[2][2];
   for (int q = 0; q < np; ++q) {
@@ -1002,12 +1030,29 @@ extern "C" float dh_autoalign(dh_handle h, const void* frames, int batch, int mo
     tlo[q][1] = P.tilt_deg[q][1] - mdeg; thi[q][1] = P.tilt_deg[q][1] + mdeg;
   }
   if (c.bxe >= g.nx || c.bye >= g.ny) return (set_err(pl, DH_ERR_INVALIDARGUMENT), -FLT_MAX);
-  // scratch: extended row pass, stored spectrum, power map, captured power
+  // beam-centre search range: an eighth of the FFT window around the start,
+  // and centres whose window stays inside the frame (the window's centre pixel
+  // is the centre rounded to the nearest pixel, offset from the half-frame's)
+  const double cmx = (g.nx / 8) * pix, cmy = (g.ny / 8) * pix;
+  auto clamp_centre = [&](int q, int a, double v) {
+    const double c0 = start.beam_centre[q][a], m = a ? cmy : cmx;
+    const int half = P.frame_w / np;
+    const int base = a ? P.frame_h / 2 - g.ny / 2 : q * half + half / 2 - g.nx / 2;   // origin at pixel 0
+    const int n = a ? g.ny : g.nx, extent = a ? P.frame_h : P.frame_w;
+    const double lo = (-base - 0.5) * pix, hi = (extent - n - base + 0.499) * pix;
+    return std::min(std::min(c0 + m, hi), std::max(std::max(c0 - m, lo), v));
+  };
+  // the snap estimates centre and waist from the fields (with modes to fit)
+  const bool snap_field = mode != DH_ALIGN_TWEAK && (what & (DH_ALIGN_CENTRE | DH_ALIGN_WAIST)) && g.G > 0;
+  // scratch: extended row pass, stored spectrum, power map, captured power,
+  // and for the field snap the fields and their moments
   const size_t t1b = align256((size_t)batch * np * c.bxe * g.ny * 8);
   const size_t spb = align256((size_t)batch * np * c.bxe * c.bye * 8);
   const size_t pwb = align256((size_t)np * c.bxe * c.bye * 4);
   const size_t cpb = align256((size_t)batch * np * 2 * 8);
-  const size_t need = t1b + spb + pwb + cpb;
+  const size_t fdb = snap_field ? align256((size_t)batch * np * g.wx * g.wy * 8) : 0;
+  const size_t mob = snap_field ? align256((size_t)batch * np * 5 * 8) : 0;
+  const size_t need = t1b + spb + pwb + cpb + fdb + mob;
   if (need > pl->amem_bytes) {
     if (pl->amem) (void)hipFree(pl->amem);
     pl->amem = nullptr;
@@ -1018,22 +1063,13 @@ extern "C" float dh_autoalign(dh_handle h, const void* frames, int batch, int mo
     }
     pl->amem_bytes = need;
   }
-  float2* t1e = (float2*)pl->amem;
+  c.t1e = (float2*)pl->amem;
   c.spec = (float2*)(pl->amem + t1b);
   float* pw = (float*)(pl->amem + t1b + spb);
   c.capt = (double*)(pl->amem + t1b + spb + pwb);
-  {
-    dh::KArgs ke = pl->ka[0];
-    ke.bx = c.bxe;
-    ke.t1 = t1e;
-    for (int q = 0; q < np; ++q) {
-      ke.pol[q].k0 = c.k0e[q];
-      ke.pol[q].ky0 = c.ky0e[q];
-    }
-    if (dh::launch_row(ke, frames, P.input_dtype == DH_INPUT_U16, 0, batch, s) != hipSuccess ||
-        dh::launch_spec(ke, c.spec, c.bye, batch, s) != hipSuccess)
-      return (set_err(pl, DH_ERR_ERROR), -FLT_MAX);
-  }
+  float2* fdev = (float2*)(pl->amem + t1b + spb + pwb + cpb);
+  double* mdev = (double*)(pl->amem + t1b + spb + pwb + cpb + fdb);
+  if (!align_fft(c)) return (set_err(pl, DH_ERR_ERROR), -FLT_MAX);
   dh_align_report rep{};
   // snap: tilt at the centroid of the batch power spectrum above its mean
   if (mode != DH_ALIGN_TWEAK && (what & DH_ALIGN_TILT)) {
@@ -1062,7 +1098,49 @@ extern "C" float dh_autoalign(dh_handle h, const void* frames, int batch, int mo
       rep.snap_tilt_deg[q][1] = P.tilt_deg[q][1];
     }
   }
+  // locked parameters take the first polarisation's value
+  if (np > 1) {
+    if (pl->lock & DH_ALIGN_TILT) for (int a = 0; a < 2; ++a) P.tilt_deg[1][a] = P.tilt_deg[0][a];
+    if (pl->lock & DH_ALIGN_DEFOCUS) P.defocus[1] = P.defocus[0];
+  }
   double mp[2], fp[2];
+  if (snap_field) {
+    // snap of the beam centre (intensity centroid of the reconstructed fields)
+    // and of the waist (pooled central second moment, read as the power spread
+    // evenly over the modes of G groups: <x^2> = <y^2> = w^2 (2G + 1) / 12)
+    c.fields = fdev;
+    const bool ok = align_eval(c, true, mp, fp);
+    c.fields = nullptr;
+    std::vector<double> hm((size_t)batch * np * 5);
+    if (!ok || dh::launch_moments(fdev, batch * np, g.wx, g.wy, g.pxp, g.pyp, mdev, s) != hipSuccess ||
+        hipMemcpyAsync(hm.data(), mdev, hm.size() * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return (P = start, build_tables(pl), set_err(pl, DH_ERR_ERROR), -FLT_MAX);
+    double mom[2][5] = {};
+    for (int b = 0; b < batch; ++b)
+      for (int q = 0; q < np; ++q)
+        for (int t = 0; t < 5; ++t) mom[q][t] += hm[((size_t)b * np + q) * 5 + t];
+    double mxx = 0.0, myy = 0.0, tot = 0.0;
+    for (int q = 0; q < np; ++q) {
+      const double* m = mom[q];
+      if (!(m[0] > 0.0)) continue;
+      if (what & DH_ALIGN_CENTRE) {
+        P.beam_centre[q][0] = clamp_centre(q, 0, P.beam_centre[q][0] + m[1] / m[0]);
+        P.beam_centre[q][1] = clamp_centre(q, 1, P.beam_centre[q][1] + m[2] / m[0]);
+      }
+      mxx += m[3] - m[1] * m[1] / m[0];
+      myy += m[4] - m[2] * m[2] / m[0];
+      tot += m[0];
+    }
+    if ((what & DH_ALIGN_WAIST) && tot > 0.0 && mxx + myy > 0.0)
+      P.waist = std::min(4.0 * start.waist, std::max(0.25 * start.waist,
+                                                     std::sqrt(6.0 * (mxx + myy) / tot / (2 * g.G + 1))));
+    for (int q = 0; q < np; ++q) {
+      rep.snap_centre[q][0] = P.beam_centre[q][0];
+      rep.snap_centre[q][1] = P.beam_centre[q][1];
+    }
+    rep.snap_waist = P.waist;
+  }
   if (pl->g.G == 0) {  // estimate only, nothing to evaluate
     for (int q = 0; q < np; ++q) derive_pol(&P, &g, q);
     if (build_tables(pl, false) != DH_SUCCESS) return (set_err(pl, DH_ERR_ERROR), -FLT_MAX);
@@ -1091,49 +1169,69 @@ extern "C" float dh_autoalign(dh_handle h, const void* frames, int batch, int mo
   double best_pol[2] = {db(mp[0], fp[0]), np > 1 ? db(mp[1], fp[1]) : 0.0};
   rep.start_goal_db = goal;
   // tweak: coordinate search, a parabola through three trials per coordinate.
-  // Captured-power goal: the per-pol parameters of both pols move together,
-  // each pol on its own captured power (it depends only on its own tilt and
-  // defocus). Metric goal (couples the pols): one coordinate per pol, on the
-  // joint goal. The shared waist is always one coordinate on the joint goal.
+  // A coordinate is one parameter kind along one axis and takes one of three
+  // forms: every pol its own value, each on its own captured power (captured
+  // goal: a pol's power depends only on its own tilt, defocus and centre);
+  // one pol's value on the joint goal (metric goals couple the pols); or one
+  // value shared by all pols on the joint goal (the waist, locked parameters).
   if (mode != DH_ALIGN_ESTIMATE) {
-    struct Coord { int kind; int axis; int pol; double h; };   // kind 0 tilt, 1 defocus, 2 waist; pol -1: all
+    enum { TILT, DEFOCUS, WAIST, CENTRE };
+    enum { PER_POL = -2, SHARED = -1 };
+    struct Coord { int kind; int axis; int pol; double h; };
     std::vector<Coord> coords;
-    auto add = [&](int kind, int axis, double h) {
-      if (kind == 2 || !metric_goal) coords.push_back({kind, axis, -1, h});
+    auto add = [&](int kind, int axis, double h, bool locked) {
+      if (kind == WAIST || (locked && np > 1)) coords.push_back({kind, axis, SHARED, h});
+      else if (!metric_goal) coords.push_back({kind, axis, PER_POL, h});
       else for (int q = 0; q < np; ++q) coords.push_back({kind, axis, q, h});
     };
-    if (what & DH_ALIGN_TILT) { add(0, 0, 0.5 * binx); add(0, 1, 0.5 * biny); }
-    if (what & DH_ALIGN_DEFOCUS) add(1, 0, 0.02);
-    if (what & DH_ALIGN_WAIST) add(2, 0, 0.03 * P.waist);
+    const bool lt = pl->lock & DH_ALIGN_TILT, ld = pl->lock & DH_ALIGN_DEFOCUS;
+    if (what & DH_ALIGN_TILT) { add(TILT, 0, 0.5 * binx, lt); add(TILT, 1, 0.5 * biny, lt); }
+    if (what & DH_ALIGN_CENTRE) { add(CENTRE, 0, 0.5 * pix, false); add(CENTRE, 1, 0.5 * pix, false); }
+    if (what & DH_ALIGN_DEFOCUS) add(DEFOCUS, 0, 0.02, ld);
+    if (what & DH_ALIGN_WAIST) add(WAIST, 0, 0.03 * P.waist, false);
     auto get = [&](const Coord& k, int q) -> double& {
-      return k.kind == 0 ? P.tilt_deg[q][k.axis] : k.kind == 1 ? P.defocus[q] : P.waist;
+      switch (k.kind) {
+        case TILT: return P.tilt_deg[q][k.axis];
+        case DEFOCUS: return P.defocus[q];
+        case CENTRE: return P.beam_centre[q][k.axis];
+        default: return P.waist;
+      }
     };
     auto clampv = [&](const Coord& k, int q, double v) {
-      if (k.kind == 0) return std::min(thi[q][k.axis], std::max(tlo[q][k.axis], v));
-      if (k.kind == 2) return std::max(0.25 * start.waist, v);
+      if (k.kind == TILT) return std::min(thi[q][k.axis], std::max(tlo[q][k.axis], v));
+      if (k.kind == CENTRE) return clamp_centre(q, k.axis, v);
+      if (k.kind == WAIST) return std::max(0.25 * start.waist, v);
       return v;
     };
     for (int sweep = 0; sweep < 60 && !coords.empty(); ++sweep) {
       const double goal0 = goal;
       for (Coord& k : coords) {
-        const bool joint = k.kind == 2 || metric_goal;   // one value, on the joint goal
-        const int nq = joint ? 1 : np;
-        auto pq = [&](int i) { return joint ? (k.pol < 0 ? 0 : k.pol) : i; };   // pol of value i
+        const bool joint = k.pol != PER_POL;
+        const int nv = joint ? 1 : np;                       // values this coordinate moves
+        auto pol_of = [&](int i) { return joint ? std::max(k.pol, 0) : i; };
+        auto set = [&](int i, double v) {
+          if (k.pol == SHARED) for (int q = 0; q < np; ++q) get(k, q) = v;
+          else get(k, pol_of(i)) = v;
+        };
+        const bool hg = k.kind == WAIST;
         double x0[2], f0[2], fm[2], fpl[2], last[2];
-        for (int i = 0; i < nq; ++i) x0[i] = get(k, pq(i));
+        for (int i = 0; i < nv; ++i) x0[i] = get(k, pol_of(i));
         auto trial = [&](const double* v, double* out) -> bool {
-          for (int i = 0; i < nq; ++i) get(k, pq(i)) = last[i] = v[i];
-          if (joint) return eval_goal(k.kind == 2, out[0]);
+          for (int i = 0; i < nv; ++i) set(i, last[i] = v[i]);
+          if (joint) return eval_goal(hg, out[0]);
           if (!align_eval(c, false, mp, fp)) return false;
-          for (int q = 0; q < nq; ++q) out[q] = db(mp[q], fp[q]);
+          for (int q = 0; q < nv; ++q) out[q] = db(mp[q], fp[q]);
           return true;
         };
-        for (int i = 0; i < nq; ++i) f0[i] = joint ? goal : best_pol[i];
+        for (int i = 0; i < nv; ++i) f0[i] = joint ? goal : best_pol[i];
         double vp[2], vm[2];
-        for (int i = 0; i < nq; ++i) { vp[i] = clampv(k, pq(i), x0[i] + k.h); vm[i] = clampv(k, pq(i), x0[i] - k.h); }
+        for (int i = 0; i < nv; ++i) {
+          vp[i] = clampv(k, pol_of(i), x0[i] + k.h);
+          vm[i] = clampv(k, pol_of(i), x0[i] - k.h);
+        }
         bool okp = trial(vp, fpl), okm = trial(vm, fm);
         double vn[2], fn[2];
-        for (int i = 0; i < nq; ++i) {
+        for (int i = 0; i < nv; ++i) {
           if (!okp) fpl[i] = -1e300;
           if (!okm) fm[i] = -1e300;
           const double cv = fpl[i] + fm[i] - 2.0 * f0[i];
@@ -1141,32 +1239,35 @@ extern "C" float dh_autoalign(dh_handle h, const void* frames, int batch, int mo
           if (okp && okm && cv < 0) d = 0.5 * k.h * (fm[i] - fpl[i]) / cv;
           else d = (fpl[i] > fm[i]) ? 2.0 * k.h : -2.0 * k.h;
           d = std::max(-2.0 * k.h, std::min(2.0 * k.h, d));
-          vn[i] = clampv(k, pq(i), x0[i] + d);
+          vn[i] = clampv(k, pol_of(i), x0[i] + d);
         }
         const bool okn = trial(vn, fn);
         // keep the best of the four trials per value; the step grows when the
         // best trial is the far one and shrinks when no trial beat the centre
         bool moved = false, far = false, stale = false;
-        for (int i = 0; i < nq; ++i) {
+        for (int i = 0; i < nv; ++i) {
           double bv = x0[i], bf = f0[i];
           if (okp && fpl[i] > bf) { bv = vp[i]; bf = fpl[i]; }
           if (okm && fm[i] > bf) { bv = vm[i]; bf = fm[i]; }
           if (okn && fn[i] > bf) { bv = vn[i]; bf = fn[i]; }
-          get(k, pq(i)) = bv;
+          set(i, bv);
           if (joint) goal = bf; else best_pol[i] = bf;
           moved |= bv != x0[i];
           far |= std::fabs(bv - x0[i]) > 1.5 * k.h;
-          stale |= bv != last[i];
+          stale |= !(okn && bv == last[i]);
         }
         k.h *= far ? 2.0 : moved ? 1.0 : 0.5;
         if (!joint) {
           // the kept per-pol values come from different trials: the joint goal anew
           if (!align_eval(c, false, mp, fp)) return (P = start, build_tables(pl), set_err(pl, DH_ERR_ERROR), -FLT_MAX);
           goal = captured();
-        } else if (stale) {
-          // the tables (HG tables for the waist) still hold the last trial's value
-          double gv;
-          if (!eval_goal(k.kind == 2, gv)) return (P = start, build_tables(pl), set_err(pl, DH_ERR_ERROR), -FLT_MAX);
+        } else {
+          // the HG tables of a waist step must not be left at a rejected
+          // trial; per-pol powers follow every shared step
+          if (stale && (hg || !metric_goal)) {
+            double gv;
+            if (!eval_goal(hg, gv)) return (P = start, build_tables(pl), set_err(pl, DH_ERR_ERROR), -FLT_MAX);
+          }
           if (!metric_goal) for (int q = 0; q < np; ++q) best_pol[q] = db(mp[q], fp[q]);
         }
       }
@@ -1205,6 +1306,14 @@ extern "C" int dh_set_align_goal(dh_handle h, int goal, int pol_independent, int
   pl->goal = goal;
   pl->goal_indep = pol_independent != 0;
   pl->goal_aa = mul_conj_trans != 0;
+  return set_err(pl, DH_SUCCESS);
+}
+
+extern "C" int dh_set_pol_lock(dh_handle h, unsigned lock) {
+  Plan* pl = get(h);
+  if (!pl) return DH_ERR_INVALIDHANDLE;
+  if (lock & ~(DH_ALIGN_TILT | DH_ALIGN_DEFOCUS | DH_ALIGN_WAIST)) return set_err(pl, DH_ERR_INVALIDARGUMENT);
+  pl->lock = lock & (DH_ALIGN_TILT | DH_ALIGN_DEFOCUS);   // the waist is always one for both pols
   return set_err(pl, DH_SUCCESS);
 }
 

@@ -96,6 +96,10 @@ hipError_t launch_spec(const KArgs& a, float2* spec, int nrow, int nb, hipStream
 hipError_t launch_gather(const KArgs& a, const float2* spec, int bxe, int nrow, const int* offj, const int* offi,
                          int nb, hipStream_t s);
 hipError_t launch_psum(const float2* spec, int nb, int npol, size_t plane, float* pw, hipStream_t s);
+// FP64 intensity moments of n fields [wy][wx]: out[e][5] = sums of I, xI, yI,
+// x^2 I, y^2 I on the coarse grid x = (k - wx/2) px, y = (l - wy/2) py
+hipError_t launch_moments(const float2* fields, int n, int wx, int wy, double px, double py, double* out,
+                          hipStream_t s);
 // HG tables: out[k][n] in FP32 and, if the split pointers are non-null, the
 // packed hi/lo tables (bf16, and fp16 of the value times fp16_scale)
 hipError_t launch_hg(double pitch, int w, int wpad, double waist, int G, int gp, float* out,

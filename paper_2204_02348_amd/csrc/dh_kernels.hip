@@ -636,6 +636,38 @@ __global__ void k_psum(const float2* __restrict__ spec, int nb, int npol, size_t
   pw[e] = s;
 }
 
+// k_moments: grid (nb * npol); block e reduces field e ([wy][wx]) to the FP64
+// sums of I, x I, y I, x^2 I, y^2 I, I = |E|^2, on the coarse grid
+// x = (k - wx/2) px, y = (l - wy/2) py, in a fixed order.
+__global__ void __launch_bounds__(256) k_moments(const float2* __restrict__ f, int wx, int wy, double px, double py,
+                                                 double* __restrict__ out) {
+  __shared__ double red[5][256];
+  const int tid = threadIdx.x;
+  const float2* e = f + (size_t)blockIdx.x * wx * wy;
+  double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int t = tid; t < wx * wy; t += 256) {
+    const int l = t / wx, k = t - l * wx;
+    const float2 v = e[t];
+    const double i = (double)v.x * v.x + (double)v.y * v.y;
+    const double x = (k - 0.5 * wx) * px, y = (l - 0.5 * wy) * py;
+    s[0] += i;
+    s[1] += x * i;
+    s[2] += y * i;
+    s[3] += x * x * i;
+    s[4] += y * y * i;
+  }
+#pragma unroll
+  for (int q = 0; q < 5; ++q) red[q][tid] = s[q];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w)
+#pragma unroll
+      for (int q = 0; q < 5; ++q) red[q][tid] += red[q][tid + w];
+    __syncthreads();
+  }
+  if (tid < 5) out[(size_t)blockIdx.x * 5 + tid] = red[tid][0];
+}
+
 // ---------------------------------------------------------------------------
 // k_fld: grid (nblk, npol, nb); one block of 16 field rows per workgroup,
 // 4 waves: x-IFFT of the 16 rows, tilt/defocus removal, then the separable
@@ -1331,6 +1363,13 @@ hipError_t launch_gather(const KArgs& a, const float2* spec, int bxe, int nrow, 
 hipError_t launch_psum(const float2* spec, int nb, int npol, size_t plane, float* pw, hipStream_t s) {
   const size_t n = (size_t)npol * plane;
   hipLaunchKernelGGL(k_psum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, spec, nb, npol, plane, pw);
+  return hipGetLastError();
+}
+
+hipError_t launch_moments(const float2* fields, int n, int wx, int wy, double px, double py, double* out,
+                          hipStream_t s) {
+  if (n < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_moments, dim3(n), dim3(256), 0, s, fields, wx, wy, px, py, out);
   return hipGetLastError();
 }
 

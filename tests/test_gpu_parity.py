@@ -481,6 +481,118 @@ def test_alignment_il_goal_recovers_truth():
         assert abs(after[k] - rep.metrics[i]) <= 1e-3, (k, after[k], rep.metrics[i])
 
 
+def test_alignment_snap_centre_and_waist_match_oracle():
+    """ESTIMATE on the beam centre and waist only: the intensity centroid and
+    pooled second moment of the reconstructed fields, against the oracle's
+    estimate from the same starting parameters (1024x1024, 2 pols, G=30)."""
+    cfg = _half_height(dh_synth.config(4))
+    f, _ = dh_synth.make_frames(cfg, n_frames=3)
+    pix = 20e-6
+    start = dict(cfg["truth"], beam_centre=[[1.7 * pix, -2.3 * pix], [-0.6 * pix, 0.8 * pix]],
+                 waist=cfg["truth"]["waist"] * 1.1)
+    ref_c, ref_w = oracle.snap_centre_waist(f, start)
+    dh, plan, ft = _align_plan(start, f)
+    _say("snap of centre and waist from an offset start")
+    plan.autoalign(ft, f.shape[0], mode=dh.ALIGN_ESTIMATE, what=dh.ALIGN_CENTRE | dh.ALIGN_WAIST)
+    got = plan.params()
+    rep = plan.align_report()
+    plan.destroy()
+    for q in range(2):
+        for a in range(2):
+            _say("pol %d axis %d centre gpu %.5f px oracle %.5f px" % (q, a, got["beam_centre"][q][a] / pix,
+                                                                      ref_c[q][a] / pix))
+            assert abs(got["beam_centre"][q][a] - ref_c[q][a]) < 1e-3 * pix
+            assert rep.snap_centre[q][a] == got["beam_centre"][q][a]
+    _say("waist gpu %.6e oracle %.6e" % (got["waist"], ref_w))
+    assert abs(got["waist"] / ref_w - 1) < 1e-5 and rep.snap_waist == got["waist"]
+
+
+def _half_height(cfg):
+    """The 1024x1024 two-pol recipe with 512x512 FFT windows: room for the
+    window to follow the beam centre (pol 0 to +x, pol 1 to -x, both in y)."""
+    return dict(cfg, params=dict(cfg["params"], fft_h=512), truth=dict(cfg["truth"], fft_h=512))
+
+
+def _bins(p):
+    return [p["wavelength"] / (p["fft_w"] * p["pixel_size"]) / oracle.DEG,
+            p["wavelength"] / (p["fft_h"] * p["pixel_size"]) / oracle.DEG]
+
+
+def _shifted_centre_frames(n):
+    cfg = _half_height(dh_synth.config(4))
+    pix = 20e-6
+    truth = dict(cfg["truth"], beam_centre=[[2.6 * pix, -1.4 * pix], [-3.2 * pix, 0.7 * pix]])
+    f, _ = dh_synth.make_frames(dict(cfg, truth=truth), n_frames=n)
+    return cfg, truth, f
+
+
+def test_alignment_recovers_beam_centre():
+    """FULL alignment of tilt, defocus, waist and beam centre from nominal, on
+    frames whose beams sit off the nominal centres by whole and fractional
+    pixels; the aligned plan then matches the oracle at its parameters."""
+    cfg, truth, f = _shifted_centre_frames(20)
+    n = f.shape[0]
+    pix = 20e-6
+    dh, plan, ft = _align_plan(cfg["params"], f)
+    _say("alignment with beam centre from nominal, %d frames" % n)
+    what = dh.ALIGN_TILT | dh.ALIGN_DEFOCUS | dh.ALIGN_WAIST | dh.ALIGN_CENTRE
+    g = plan.autoalign(ft, n, mode=dh.ALIGN_FULL, what=what, tol=1e-5)
+    rep = plan.align_report()
+    got = plan.params()
+    bins = _bins(truth)
+    _say("goal %.5f dB (after snap %.5f), %d trials, %d sweeps; snap waist err %.2f %%" % (
+        g, rep.start_goal_db, rep.evaluations, rep.sweeps, 100 * (rep.snap_waist / truth["waist"] - 1)))
+    for q in range(2):
+        _say("pol %d centre err %.3f / %.3f px (snap %.3f / %.3f), tilt err %.3f / %.3f bins, defocus err %.4f D" % (
+            q, (got["beam_centre"][q][0] - truth["beam_centre"][q][0]) / pix,
+            (got["beam_centre"][q][1] - truth["beam_centre"][q][1]) / pix,
+            (rep.snap_centre[q][0] - truth["beam_centre"][q][0]) / pix,
+            (rep.snap_centre[q][1] - truth["beam_centre"][q][1]) / pix,
+            (got["tilt_deg"][q][0] - truth["tilt_deg"][q][0]) / bins[0],
+            (got["tilt_deg"][q][1] - truth["tilt_deg"][q][1]) / bins[1], got["defocus"][q] - truth["defocus"][q]))
+    _say("waist err %.4f %%" % (100 * (got["waist"] / truth["waist"] - 1)))
+    for q in range(2):
+        for a in range(2):
+            assert abs(got["beam_centre"][q][a] - truth["beam_centre"][q][a]) < 0.1 * pix
+            assert abs(rep.snap_centre[q][a] - truth["beam_centre"][q][a]) < 2.0 * pix
+            assert abs(got["tilt_deg"][q][a] - truth["tilt_deg"][q][a]) < 0.3 * bins[a]
+        assert abs(got["defocus"][q] - truth["defocus"][q]) < 0.01
+    assert abs(got["waist"] / truth["waist"] - 1) < 0.01
+    aligned = dict(truth, tilt_deg=got["tilt_deg"], defocus=got["defocus"], waist=got["waist"],
+                   beam_centre=got["beam_centre"])
+    plan.process(ft, n, None)
+    coefs = plan.coefs(False)
+    plan.destroy()
+    for i in (0, n - 1):
+        ref = oracle.process_frame(f[i].astype(np.float64), aligned)["coefs"]
+        for pol in range(2):
+            assert _rel(coefs[i][pol].astype(np.complex128), ref[pol]) <= TOL
+
+
+def test_alignment_pol_lock():
+    """Tilt and defocus locked across the polarisations: pol 1 carries pol 0's
+    values after the alignment, which finds the common truth."""
+    cfg = dh_synth.config(4)
+    t0 = cfg["truth"]
+    truth = dict(t0, tilt_deg=[t0["tilt_deg"][0], list(t0["tilt_deg"][0])], defocus=[t0["defocus"][0]] * 2)
+    f, _ = dh_synth.make_frames(dict(cfg, truth=truth), n_frames=10)
+    dh, plan, ft = _align_plan(cfg["params"], f)
+    plan.set_pol_lock(dh.ALIGN_TILT | dh.ALIGN_DEFOCUS)
+    with pytest.raises(dh.DhError):
+        plan.set_pol_lock(dh.ALIGN_CENTRE)
+    _say("alignment with locked tilt and defocus")
+    plan.autoalign(ft, f.shape[0], mode=dh.ALIGN_FULL, what=dh.ALIGN_TILT | dh.ALIGN_DEFOCUS | dh.ALIGN_WAIST,
+                   tol=1e-5)
+    got = plan.params()
+    plan.destroy()
+    bins = [1565e-9 / (512 * 20e-6) / oracle.DEG, 1565e-9 / (1024 * 20e-6) / oracle.DEG]
+    _say("tilt", got["tilt_deg"], "defocus", got["defocus"])
+    assert got["tilt_deg"][1] == got["tilt_deg"][0] and got["defocus"][1] == got["defocus"][0]
+    for a in range(2):
+        assert abs(got["tilt_deg"][0][a] - truth["tilt_deg"][0][a]) < 0.3 * bins[a]
+    assert abs(got["defocus"][0] - truth["defocus"][0]) < 0.01
+
+
 # ---------------------------------------------------------------- transfer-matrix metrics
 @pytest.mark.parametrize("n", [90, 1000])
 def test_transfer_metrics_match_oracle(n):
