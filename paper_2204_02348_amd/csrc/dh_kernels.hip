@@ -622,52 +622,6 @@ __global__ void __launch_bounds__(kTPB) k_gather(KArgs A, SpecRef S) {
   }
 }
 
-// k_psum: pw[p][j][i] = sum over frames of |spec[b][p][j][i]|^2
-__global__ void k_psum(const float2* __restrict__ spec, int nb, int npol, size_t plane, float* __restrict__ pw) {
-  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= npol * plane) return;
-  const int p = (int)(e / plane);
-  const size_t k = e - (size_t)p * plane;
-  float s = 0.f;
-  for (int b = 0; b < nb; ++b) {
-    const float2 v = spec[((size_t)b * npol + p) * plane + k];
-    s = fmaf(v.x, v.x, fmaf(v.y, v.y, s));
-  }
-  pw[e] = s;
-}
-
-// k_moments: grid (nb * npol); block e reduces field e ([wy][wx]) to the FP64
-// sums of I, x I, y I, x^2 I, y^2 I, I = |E|^2, on the coarse grid
-// x = (k - wx/2) px, y = (l - wy/2) py, in a fixed order.
-__global__ void __launch_bounds__(256) k_moments(const float2* __restrict__ f, int wx, int wy, double px, double py,
-                                                 double* __restrict__ out) {
-  __shared__ double red[5][256];
-  const int tid = threadIdx.x;
-  const float2* e = f + (size_t)blockIdx.x * wx * wy;
-  double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int t = tid; t < wx * wy; t += 256) {
-    const int l = t / wx, k = t - l * wx;
-    const float2 v = e[t];
-    const double i = (double)v.x * v.x + (double)v.y * v.y;
-    const double x = (k - 0.5 * wx) * px, y = (l - 0.5 * wy) * py;
-    s[0] += i;
-    s[1] += x * i;
-    s[2] += y * i;
-    s[3] += x * x * i;
-    s[4] += y * y * i;
-  }
-#pragma unroll
-  for (int q = 0; q < 5; ++q) red[q][tid] = s[q];
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (tid < w)
-#pragma unroll
-      for (int q = 0; q < 5; ++q) red[q][tid] += red[q][tid + w];
-    __syncthreads();
-  }
-  if (tid < 5) out[(size_t)blockIdx.x * 5 + tid] = red[tid][0];
-}
-
 // ---------------------------------------------------------------------------
 // k_fld: grid (nblk, npol, nb); one block of 16 field rows per workgroup,
 // 4 waves: x-IFFT of the 16 rows, tilt/defocus removal, then the separable
@@ -1091,86 +1045,6 @@ __global__ void k_zero(float2* p, size_t n) {
 }
 
 // ---------------------------------------------------------------------------
-// Transfer-matrix metrics, FP64. A is rows x cols with cols = P M:
-// combined, row b = frame b and A(b, p M + m) = c[b][p][m]; independent, row
-// p B + b holds c[b][p][m] in pol p's columns and zero in the others.
-__device__ __forceinline__ double2 tm_a(const TmArgs& t, int r, int col) {
-  int b = r;
-  if (t.indep) {
-    const int p = r / t.B;
-    b = r - p * t.B;
-    if (col / t.M != p) return make_double2(0.0, 0.0);
-  }
-  const float2 v = t.c[(size_t)b * t.P * t.M + col];
-  return make_double2((double)v.x, (double)v.y);
-}
-
-// G = X X^H, n x n, column-major: X = A (by rows, K = cols) or X = A^H
-// (K = rows). One thread per element.
-__global__ void k_tm_gram(TmArgs t, int by_rows, int n, double2* __restrict__ g) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y;
-  if (i >= n) return;
-  const int K = by_rows ? t.cols : t.rows;
-  double re = 0.0, im = 0.0;
-  for (int k = 0; k < K; ++k) {
-    // X(i,k) conj(X(j,k)); X = A^H: X(i,k) = conj(A(k,i))
-    const double2 x = by_rows ? tm_a(t, i, k) : tm_a(t, k, i);
-    const double2 y = by_rows ? tm_a(t, j, k) : tm_a(t, k, j);
-    const double xr = x.x, xi = by_rows ? x.y : -x.y;
-    const double yr = y.x, yi = by_rows ? y.y : -y.y;
-    re += xr * yr + xi * yi;
-    im += xi * yr - xr * yi;
-  }
-  g[(size_t)i + (size_t)j * n] = make_double2(re, im);
-}
-
-// mode key of transfer-matrix index k: (pol, HG group); past the modes, unique
-__device__ __forceinline__ long tm_key(const TmArgs& t, int k) {
-  if (k >= t.P * t.M) return -1 - (long)k;
-  const int p = k / t.M;
-  const short2 mn = t.modes[k - p * t.M];
-  return (long)p * 64 + mn.x + mn.y;
-}
-
-// Per row i of D (D = A, or the Gram A A^H in g, rows x rows): the row's
-// power sum_j |D_ij|^2, and for i < nd its diagonal |D_ii|^2 and the power in
-// the columns whose mode shares row i's mode key.
-__global__ void k_tm_rows(TmArgs t, const double2* __restrict__ g, int nrow, int ncol, int nd,
-                          double* __restrict__ rowpow, double* __restrict__ diag, double* __restrict__ same) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nrow) return;
-  const long ki = tm_key(t, i);
-  double tot = 0.0, sg = 0.0, dg = 0.0;
-  for (int j = 0; j < ncol; ++j) {
-    const double2 v = g ? g[(size_t)i + (size_t)j * nrow] : tm_a(t, i, j);
-    const double pw = v.x * v.x + v.y * v.y;
-    tot += pw;
-    if (i < nd) {
-      if (j == i) dg = pw;
-      if (tm_key(t, j) == ki) sg += pw;
-    }
-  }
-  rowpow[i] = tot;
-  if (i < nd) {
-    diag[i] = dg;
-    same[i] = sg;
-  }
-}
-
-hipError_t launch_tm_gram(const TmArgs& t, int by_rows, int n, double2* g, hipStream_t s) {
-  dim3 grid((n + 127) / 128, n);
-  hipLaunchKernelGGL(k_tm_gram, grid, dim3(128), 0, s, t, by_rows, n, g);
-  return hipGetLastError();
-}
-
-hipError_t launch_tm_rows(const TmArgs& t, const double2* g, int nrow, int ncol, int nd, double* rowpow, double* diag,
-                          double* same, hipStream_t s) {
-  hipLaunchKernelGGL(k_tm_rows, dim3((nrow + 127) / 128), dim3(128), 0, s, t, g, nrow, ncol, nd, rowpow, diag, same);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
 // dispatch over the supported sizes
 // transforms per row-pass block and columns per column-pass block (~32-80 KB of LDS)
 // row pass: TR transforms per block so that TR * N / R0 (the block size) is 256
@@ -1360,18 +1234,7 @@ hipError_t launch_gather(const KArgs& a, const float2* spec, int bxe, int nrow, 
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_psum(const float2* spec, int nb, int npol, size_t plane, float* pw, hipStream_t s) {
-  const size_t n = (size_t)npol * plane;
-  hipLaunchKernelGGL(k_psum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, spec, nb, npol, plane, pw);
-  return hipGetLastError();
-}
 
-hipError_t launch_moments(const float2* fields, int n, int wx, int wy, double px, double py, double* out,
-                          hipStream_t s) {
-  if (n < 1) return hipSuccess;
-  hipLaunchKernelGGL(k_moments, dim3(n), dim3(256), 0, s, fields, wx, wy, px, py, out);
-  return hipGetLastError();
-}
 
 hipError_t launch_norm(const KArgs& a, int b0, int nb, hipStream_t s) {
   hipLaunchKernelGGL(k_norm, dim3(nb), dim3(kTPB), 0, s, a, b0);
