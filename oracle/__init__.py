@@ -8,6 +8,7 @@ from .holo_oracle import (  # noqa: F401
     DEG, w_max_rad, tilt_bins, radius_bins, ifft_size, mode_list, mode_count,
     window_origin, mask_bins, geometry, hermite_gauss_1d, spectrum_window,
     field_from_window, overlap, power_normalise, process_frame, process_batch, captured_power, goal_db,
+    INT16_FULL, fields_to_int16,
 )
 from .transfer_metrics import METRICS, transfer_matrix, column_keys, transfer_metrics  # noqa: F401,E402
 from .align_snap import field_moments, batch_moments, snap_centre_waist  # noqa: F401,E402

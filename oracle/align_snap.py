@@ -30,11 +30,11 @@ from .holo_oracle import field_from_window, geometry, spectrum_window
 
 def field_moments(field: np.ndarray, g: dict) -> np.ndarray:
     """[sum I, sum x' I, sum y' I, sum x'^2 I, sum y'^2 I] of I = |E|^2 over
-    the coarse grid of one field [Wy][Wx] (coordinates relative to the beam
+    the field grid of one field [Fy][Fx] (coordinates relative to the beam
     centre, in metres)."""
-    wx, wy = g["wx"], g["wy"]
-    xk = (np.arange(wx) - wx / 2.0) * g["px2"]
-    yl = (np.arange(wy) - wy / 2.0) * g["py2"]
+    fx, fy = g["fx"], g["fy"]
+    xk = (np.arange(fx) - fx / 2.0) * g["px2"]
+    yl = (np.arange(fy) - fy / 2.0) * g["py2"]
     i = np.abs(np.asarray(field, dtype=np.complex128)) ** 2
     ix = i.sum(axis=0)          # over y: a function of x
     iy = i.sum(axis=1)          # over x: a function of y

@@ -154,8 +154,14 @@ def geometry(params: dict) -> dict:
         x0, y0, dx, dy = window_origin(params, pol)
         pols.append(dict(ax=ax, ay=ay, us=us, vs=vs, mask=m, x0=x0, y0=y0,
                          dx=dx, dy=dy, defocus=params["defocus"][pol]))
+    # the reconstructed field's grid: IFFT resolution mode 1 (the window
+    # size, pitch N p / W) or mode 0 (the FFT size, the camera pitch)
+    mode = params.get("ifft_mode", 1)
+    if mode not in (0, 1):
+        raise ValueError("ifft_mode is 0 or 1")
+    fx, fy = (wx, wy) if mode == 1 else (nx, ny)
     return dict(nx=nx, ny=ny, p=p, lam=lam, rx=rx, ry=ry, wx=wx, wy=wy,
-                px2=nx * p / wx, py2=ny * p / wy, pols=pols)
+                px2=nx * p / fx, py2=ny * p / fy, fx=fx, fy=fy, ifft_mode=mode, pols=pols)
 
 
 # --------------------------------------------------------------------------
@@ -215,17 +221,19 @@ def spectrum_window(frame: np.ndarray, g: dict, pol: int) -> np.ndarray:
 
 
 def field_from_window(window: np.ndarray, g: dict, pol: int) -> np.ndarray:
-    """Pipeline step 2 (IFFT at the Fourier-window size, mode 1) and the
-    tilt/defocus removal: E(x'_k, y'_l) on the coarse grid, [Wy][Wx]."""
+    """Pipeline step 2 (the IFFT) and the tilt/defocus removal: E(x'_k, y'_l)
+    on the field grid, [Fy][Fx]: in IFFT resolution mode 1 the Fourier-window
+    size (x'_k = (k - Wx/2) N p / Wx), in mode 0 the FFT size (x'_k =
+    (k - Nx/2) p, the camera pixels of the FFT window). The window is the
+    same in both modes: the bins, held on the Wy x Wx grid."""
     gp = g["pols"][pol]
     nx, ny, p, lam = g["nx"], g["ny"], g["p"], g["lam"]
     wx, wy = g["wx"], g["wy"]
-    xk = (np.arange(wx) - wx / 2.0) * g["px2"]
-    yl = (np.arange(wy) - wy / 2.0) * g["py2"]
+    xk = (np.arange(g["fx"]) - g["fx"] / 2.0) * g["px2"]
+    yl = (np.arange(g["fy"]) - g["fy"] / 2.0) * g["py2"]
     # every window bin (u, v) is represented by its grid cell (u mod W, v mod W);
     # recover the actual lattice bin to evaluate the inverse transform.
     us, vs, m = gp["us"], gp["vs"], gp["mask"]
-    e = np.zeros((wy, wx), dtype=np.complex128)
     ucol = {}
     for iu, u in enumerate(us):
         if m[:, iu].any():
@@ -248,11 +256,11 @@ def field_from_window(window: np.ndarray, g: dict, pol: int) -> np.ndarray:
 
 
 def overlap(field: np.ndarray, g: dict, waist: float, group_count: int) -> np.ndarray:
-    """Pipeline step 3: c_mn = sum_{k,l} E u_m(x'_k) u_n(y'_l) p'_x p'_y for
-    every HG(m,n) with m+n < groupCount, in mode_list order."""
-    wx, wy = g["wx"], g["wy"]
-    xk = (np.arange(wx) - wx / 2.0) * g["px2"]
-    yl = (np.arange(wy) - wy / 2.0) * g["py2"]
+    """Pipeline step 3: c_mn = sum_{k,l} E u_m(x'_k) u_n(y'_l) p'_x p'_y over
+    the field grid, for every HG(m,n) with m+n < groupCount, in mode_list
+    order."""
+    xk = (np.arange(g["fx"]) - g["fx"] / 2.0) * g["px2"]
+    yl = (np.arange(g["fy"]) - g["fy"] / 2.0) * g["py2"]
     ux = hermite_gauss_1d(group_count, xk, waist)   # [m][k]
     uy = hermite_gauss_1d(group_count, yl, waist)   # [n][l]
     cm = uy @ field @ ux.T * (g["px2"] * g["py2"])   # [n][m]
@@ -322,3 +330,27 @@ def process_batch(frames: np.ndarray, params: dict, indices=None) -> dict:
     idx = range(frames.shape[0]) if indices is None else indices
     res = [process_frame(frames[i], params, g) for i in idx]
     return {k: np.stack([r[k] for r in res]) for k in res[0]}
+
+
+# --------------------------------------------------------------------------
+# field export in the paper's 16-bit format ("Return reconstructed fields":
+# int16 real and imaginary parts and one float scale per field, the field
+# being (re + i im) / scale)
+# --------------------------------------------------------------------------
+INT16_FULL = 32767
+
+
+def fields_to_int16(field: np.ndarray):
+    """One field (complex64 values, any shape) -> (re, im, scale). Reading:
+    the scale maps the largest real or imaginary magnitude of the field to
+    32767, scale = 32767 / max(|Re|, |Im|) (1 for an all-zero field), and
+    each part is rounded to the nearest integer, ties to even. Done in FP32,
+    the precision the fields are kept in."""
+    f = np.asarray(field, dtype=np.complex64)
+    re = f.real.astype(np.float32)
+    im = f.imag.astype(np.float32)
+    peak = np.float32(max(float(np.abs(re).max(initial=0.0)), float(np.abs(im).max(initial=0.0))))
+    scale = np.float32(1.0) if peak == 0 else np.float32(INT16_FULL) / peak
+    qr = np.rint(re * scale).astype(np.int16)
+    qi = np.rint(im * scale).astype(np.int16)
+    return qr, qi, scale

@@ -17,7 +17,7 @@ MUTATIONS = {
     "drop_defocus": ('+ np.pi * gp["defocus"] * (xk[None, :] ** 2 + yl[:, None] ** 2) / lam', ''),
     "tilt_sign": ('phi = (2 * np.pi * (gp["ax"]', 'phi = (-2 * np.pi * (gp["ax"]'),
     "other_cross_term": ('((uu + ax) / rx) ** 2', '((uu - ax) / rx) ** 2'),
-    "field_pitch": ('px2=nx * p / wx', 'px2=p'),
+    "field_pitch": ('px2=nx * p / fx', 'px2=p'),
     "pixel_origin": ('xj = (np.arange(nx) - nx / 2.0) * p', 'xj = (np.arange(nx) - nx / 2.0 + 1) * p'),
     "subpixel_sign": ('* p - gp["dx"]', '* p + gp["dx"]'),
     "hermite_recurrence": ('- math.sqrt(n / (n + 1)) * psi_prev', '+ math.sqrt(n / (n + 1)) * psi_prev'),
@@ -163,7 +163,7 @@ SNAP_MUTATIONS = {
     "centre_axes_swapped": ("cx + sx / s, cy + sy / s", "cx + sy / s, cy + sx / s"),
     "not_central": ("mxx += sxx - sx * sx / s", "mxx += sxx"),
     "group_factor": ("(2 * g + 1)", "(2 * g - 1)"),
-    "grid_origin": ("(np.arange(wx) - wx / 2.0)", "np.arange(wx)"),
+    "grid_origin": ("(np.arange(fx) - fx / 2.0)", "np.arange(fx)"),
     "amplitude_not_intensity": ("i = np.abs(np.asarray(field, dtype=np.complex128)) ** 2",
                                 "i = np.abs(np.asarray(field, dtype=np.complex128))"),
     "pol_not_own": ("cx, cy = params[\"beam_centre\"][pol]", "cx, cy = params[\"beam_centre\"][0]"),
@@ -197,5 +197,43 @@ def test_snap_pins_catch_planted_mistake(name, monkeypatch):
         try:
             t()
         except AssertionError:
+            failed += 1
+    assert failed > 0, name
+
+
+# ---------------------------------------------------------------- IFFT mode 0 and the int16 format
+M0_MUTATIONS = {
+    "mode0_coarse_pitch": ("fx, fy = (wx, wy) if mode == 1 else (nx, ny)", "fx, fy = (wx, wy)"),
+    "mode0_pitch_of_window": ("px2=nx * p / fx, py2=ny * p / fy", "px2=nx * p / wx, py2=ny * p / wy"),
+    "mode0_grid_origin": ("xk = (np.arange(g[\"fx\"]) - g[\"fx\"] / 2.0) * g[\"px2\"]\n    yl = (np.arange(g[\"fy\"]) - g[\"fy\"] / 2.0) * g[\"py2\"]\n    # every",
+                          "xk = np.arange(g[\"fx\"]) * g[\"px2\"]\n    yl = np.arange(g[\"fy\"]) * g[\"py2\"]\n    # every"),
+    "int16_scale_from_real_only": ("float(np.abs(im).max(initial=0.0))", "0.0"),
+    "int16_truncates": ("np.rint(re * scale)", "np.trunc(re * scale)"),
+    "int16_full_scale": ("INT16_FULL = 32767", "INT16_FULL = 32768"),
+    "int16_rounds_half_away": ("qr = np.rint(re * scale)", "qr = np.sign(re * scale) * np.floor(np.abs(re * scale) + 0.5)"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(M0_MUTATIONS))
+def test_mode0_and_int16_pins_catch_planted_mistake(name, monkeypatch):
+    import oracle
+    import tests.test_oracle_pins as pins
+    old, new = M0_MUTATIONS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, name
+    mut = types.ModuleType("m0_mutant_" + name)
+    exec(compile(src.replace(old, new), SRC + ":" + name, "exec"), mut.__dict__)
+    for k in ("geometry", "field_from_window", "spectrum_window", "process_frame", "fields_to_int16", "overlap"):
+        monkeypatch.setattr(oracle, k, getattr(mut, k))
+    failed = 0
+    tests = [pins.test_mode0_field_is_the_full_size_inverse_fft,
+             lambda: pins.test_mode0_closed_form_recovery(0, 0),
+             pins.test_int16_peak_maps_to_full_scale_and_round_trips,
+             pins.test_int16_ties_to_even_and_zero_field]
+    for t in tests:
+        try:
+            with np.errstate(all="ignore"):
+                t()
+        except (AssertionError, ValueError, IndexError, OverflowError):
             failed += 1
     assert failed > 0, name

@@ -482,3 +482,75 @@ def test_snap_centre_per_polarisation():
     for q in range(2):
         for a in range(2):
             assert abs(centre[q][a] - truth["beam_centre"][q][a]) < 1e-6 * pix, (q, a)
+
+
+# ---------------------------------------------------------------- IFFT resolution mode 0
+def test_mode0_field_is_the_full_size_inverse_fft():
+    # mode 0: the window's bins zero-padded onto the N x N lattice and inverse
+    # transformed at full size (numpy's ifft2); the grid starts at -N/2 pixels,
+    # a (-1)^(u+v) factor on the bins. The tilt/defocus phase has unit modulus.
+    cfg = dh_synth.config(0)
+    p0 = dict(cfg["truth"], ifft_mode=0, defocus=[0.2, 0.0])
+    f, _ = dh_synth.make_frames(dict(cfg, truth=p0), n_frames=1, quantise=False)
+    g = oracle.geometry(p0)
+    assert (g["fx"], g["fy"]) == (p0["fft_w"], p0["fft_h"]) and g["px2"] == p0["pixel_size"]
+    win = oracle.spectrum_window(f[0], g, 0)
+    e = oracle.field_from_window(win, g, 0)
+    gp = g["pols"][0]
+    full = np.zeros((g["ny"], g["nx"]), dtype=complex)
+    for iv, v in enumerate(gp["vs"]):
+        for iu, u in enumerate(gp["us"]):
+            if gp["mask"][iv, iu]:
+                full[v % g["ny"], u % g["nx"]] = win[v % g["wy"], u % g["wx"]] * (-1.0) ** (u + v)
+    ref = np.fft.ifft2(full)
+    assert e.shape == (g["ny"], g["nx"])
+    assert np.abs(np.abs(e) - np.abs(ref)).max() < 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("idx,cam", [(0, 0), (1, 0), (3, 1)])
+def test_mode0_closed_form_recovery(idx, cam):
+    cfg = dh_synth.config(idx, cam)
+    truth = dict(cfg["truth"], ifft_mode=0)
+    frames, coefs = dh_synth.make_frames(dict(cfg, truth=truth), n_frames=1, quantise=False)
+    res = oracle.process_frame(frames[0], truth)
+    assert res["field"].shape[1:] == (truth["fft_h"], truth["fft_w"])
+    assert np.abs(res["coefs_norm"] - coefs[0]).max() < 1e-9
+    amp = _signal_amplitude(truth, coefs[0])
+    assert np.abs(res["coefs"] - amp * coefs[0]).max() < 1e-9 * amp
+
+
+def test_mode0_and_mode1_coefficients_agree():
+    # the same window, two quadratures of the same overlap
+    cfg = dh_synth.config(1)
+    f, _ = dh_synth.make_frames(cfg, n_frames=1)
+    a = oracle.process_frame(f[0].astype(np.float64), cfg["params"])["coefs"]
+    b = oracle.process_frame(f[0].astype(np.float64), dict(cfg["params"], ifft_mode=0))["coefs"]
+    assert np.linalg.norm(a - b) < 1e-6 * np.linalg.norm(a)
+
+
+# ---------------------------------------------------------------- int16 field format
+def test_int16_peak_maps_to_full_scale_and_round_trips():
+    rng = np.random.default_rng(5)
+    f = (rng.normal(size=(24, 40)) + 1j * rng.normal(size=(24, 40))).astype(np.complex64)
+    f[3, 7] = 9.0 - 2.0j                                 # the largest magnitude of any part
+    re, im, scale = oracle.fields_to_int16(f)
+    assert re.dtype == np.int16 and im.dtype == np.int16 and scale.dtype == np.float32
+    assert re[3, 7] == 32767 and scale == np.float32(32767) / np.float32(9.0)
+    back = (re.astype(np.float64) + 1j * im.astype(np.float64)) / float(scale)
+    assert np.abs(back.real - f.real).max() <= 0.5 / float(scale) * (1 + 1e-6)
+    assert np.abs(back.imag - f.imag).max() <= 0.5 / float(scale) * (1 + 1e-6)
+    # the imaginary part can set the scale, with either sign
+    g = f.copy()
+    g[0, 0] = 1.0 - 12.0j
+    re, im, scale = oracle.fields_to_int16(g)
+    assert im[0, 0] == -32767 and scale == np.float32(32767) / np.float32(12.0)
+
+
+def test_int16_ties_to_even_and_zero_field():
+    # peak 32767 makes the scale exactly 1: halves round to the even neighbour
+    f = np.array([32767.0, 2.5, 3.5, -2.5, -3.5, 0.5, 1.5], dtype=np.float32).astype(np.complex64)
+    re, im, scale = oracle.fields_to_int16(f)
+    assert scale == 1.0
+    assert re.tolist() == [32767, 2, 4, -2, -4, 0, 2] and not im.any()
+    re, im, scale = oracle.fields_to_int16(np.zeros((4, 4), dtype=np.complex64))
+    assert scale == 1.0 and not re.any() and not im.any()
