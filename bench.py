@@ -77,12 +77,16 @@ def counter_traffic(stage, info, frames_per_launch):
 def time_forms(dh, torch, cfg, ft, B, stream, steps=20, warmup=20):
     """frames/s and per-stage time of the coefficient forms on the same frames,
     at G=9 and G=20: plain FP32 on the field path and (where it applies) on
-    the spectral path, split BF16 and split FP16 (field path)."""
+    the spectral path, split BF16 and split FP16 (field path); and at G=9 IFFT
+    mode 0 (coefficients alone, and with the full-size fields exported)."""
     out = {}
     for groups in (9, 20):
-        forms = [("fp32", "field"), ("fp32", "spectral"), ("split_bf16", "field"), ("split_fp16", "field")]
-        for prec, path in forms:
-            d = dict(cfg["params"], max_mg=groups, precision=prec, path=path)
+        forms = [("fp32", "field", 1, 0), ("fp32", "spectral", 1, 0), ("split_bf16", "field", 1, 0),
+                 ("split_fp16", "field", 1, 0)]
+        if groups == 9:
+            forms += [("fp32", "spectral", 0, 0), ("fp32", "spectral", 0, 1)]
+        for prec, path, mode, fields in forms:
+            d = dict(cfg["params"], max_mg=groups, precision=prec, path=path, ifft_mode=mode, keep_fields=fields)
             if dh.plan_check(d, B)[0] != dh.SUCCESS:
                 continue
             plan = dh.Plan(d, max_batch=B)
@@ -99,7 +103,8 @@ def time_forms(dh, torch, cfg, ft, B, stream, steps=20, warmup=20):
             st = plan.stage_times()
             plan.destroy()
             ms = e0.elapsed_time(e1)
-            out[f"G{groups}_{prec}_{path}"] = {
+            name = f"G{groups}_{prec}_{path}" + ("" if mode else "_mode0") + ("_fields" if fields else "")
+            out[name] = {
                 "frames_per_s": round(steps * B / (ms / 1e3), 1),
                 "stages_ms": {k: round(v[0] / steps, 4) for k, v in st.items() if v[1]}}
     return out

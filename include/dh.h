@@ -93,27 +93,35 @@ typedef struct dh_params {
   int max_mg;                 /* G: modes HG(m,n) with m+n < G; 0 = no decomposition */
   int input_dtype;            /* DH_INPUT_F32 or DH_INPUT_U16 */
   int precision;              /* DH_PREC_* */
-  int ifft_mode;              /* 1: IFFT at the Fourier-window size (the only mode built) */
+  int ifft_mode;              /* IFFT resolution mode ("Window sizes", IFFTResolutionMode):
+                                 1: the field on the Fourier-window grid (W points, pitch N p / W);
+                                 0: the field on the FFT grid (N points, the camera pitch). Mode 0
+                                 runs the spectral path (needs FP32 and G >= 1): the coefficients
+                                 take the overlap over the FFT grid, and fields (keep_fields) are
+                                 made from the kept window by two complex GEMMs per pol */
   int keep_window;            /* nonzero: store each frame's Fourier window (dh_get_window) */
   int keep_fields;            /* nonzero: store each frame's field (dh_get_fields) */
-  int path;                   /* DH_PATH_*; SPECTRAL with keep_fields, a split precision or
-                                 G = 0 is DH_ERR_INVALIDARGUMENT */
+  int path;                   /* DH_PATH_*; SPECTRAL with keep_fields (mode 1), a split precision
+                                 or G = 0 is DH_ERR_INVALIDARGUMENT, as is FIELD in mode 0 */
 } dh_params;
 
 /* Geometry derived by the plan (all FP64 on the host). */
 typedef struct dh_plan_info {
   int fft_w, fft_h;           /* effective FFT window (after flooring) */
-  int ifft_w, ifft_h;         /* field size W: smallest multiple of 16 with prime factors
-                                 <= 13 that is >= floor(2 r) + 1 bins */
+  int ifft_w, ifft_h;         /* Fourier-window grid W: smallest multiple of 16 with prime
+                                 factors <= 13 that is >= floor(2 r) + 1 bins (the mode-1 IFFT
+                                 size; windows are stored on it in both modes) */
   int box_w, box_h;           /* spectrum bins spanned by the Fourier window (max over pols) */
   int modes;                  /* modes per polarisation, G (G+1) / 2 */
   int x0[2], y0[2];           /* window origins in the frame, pixels */
   double ax[2], ay[2];        /* cross-term position: SR* sits at bins (-ax, -ay) */
   double rx, ry;              /* window radius in bins along x, y */
-  double pitch_x, pitch_y;    /* field sample pitch p' = N p / W, m */
+  double pitch_x, pitch_y;    /* pitch of the W grid, N p / W, m */
   size_t device_bytes;        /* device memory the plan allocates */
   int chunk;                  /* frames per internal launch chunk */
   int path;                   /* DH_PATH_FIELD or DH_PATH_SPECTRAL: the path the plan runs */
+  int field_w, field_h;       /* field grid F: W in IFFT mode 1, N in mode 0 */
+  double field_pitch_x, field_pitch_y;  /* its pitch N p / F, m (the camera pitch in mode 0) */
 } dh_plan_info;
 
 /*
@@ -209,11 +217,38 @@ int dh_get_window(dh_handle h, dh_c64* host_out, const dh_c64** dev_out, int* ba
 
 /*
  * Reconstructed fields of the last batch (needs keep_fields):
- * [batch][pol][ifft_h][ifft_w] complex64 on the grid x'_k = (k - W/2) p'
- * around the beam centre (digHoloGetFields, here in FP32 rather than int16).
+ * [batch][pol][field_h][field_w] complex64 on the grid x'_k = (k - F/2) p'
+ * around the beam centre, F and p' the field grid of the IFFT mode
+ * (digHoloGetFields; kept in FP32, dh_get_fields16 gives the int16 form).
  */
 int dh_get_fields(dh_handle h, dh_c64* host_out, const dh_c64** dev_out, int* batch, int* pols,
                   int* width, int* height);
+
+/*
+ * The fields of the last batch in the paper's 16-bit form (digHoloGetFields16,
+ * "Return reconstructed fields"): int16 real and imaginary parts
+ * [batch][pol][field_h][field_w] and one float scale per field and pol, the
+ * field being (re + i im) / scale. The scale maps the largest real or
+ * imaginary magnitude of the field to 32767 (scale 1 for an all-zero field);
+ * each part is rounded to the nearest integer, ties to even, in FP32. The
+ * device copies live in a buffer the plan makes on the first call and
+ * overwrites on each; host pointers, if non-NULL, receive copies. Needs
+ * keep_fields (else DH_ERR_ERROR); DH_ERR_MEMORYALLOCATION if the buffer
+ * cannot be made. Synchronises the stream of the last dh_process_batch.
+ */
+int dh_get_fields16(dh_handle h, short* re_host, short* im_host, float* scale_host, const short** re_dev,
+                    const short** im_dev, const float** scale_dev, int* batch, int* pols, int* width,
+                    int* height);
+
+/*
+ * The same conversion for any n_fields complex64 fields of field_len values
+ * each, back to back in device memory: re, im (n_fields * field_len each)
+ * and scale (n_fields) are device buffers the caller owns. Asynchronous on
+ * `stream`. DH_ERR_INVALIDARGUMENT for n_fields < 0 or field_len < 1,
+ * DH_ERR_NULLPOINTER for a null buffer (n_fields > 0).
+ */
+int dh_fields_to_int16(const dh_c64* fields, int n_fields, long long field_len, short* re, short* im,
+                       float* scale, void* stream);
 
 /* Copy of the plan's parameters / derived geometry. */
 int dh_get_params(dh_handle h, dh_params* out);

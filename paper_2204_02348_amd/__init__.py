@@ -43,7 +43,7 @@ EXPORTS = ["dh_plan_check", "dh_plan", "dh_process_batch", "dh_mode_coefs", "dh_
            "dh_get_fields", "dh_get_params", "dh_get_plan_info", "dh_set_stage_timing", "dh_stage_times",
            "dh_autoalign", "dh_get_align_report", "dh_serve_create", "dh_serve_info", "dh_serve_submit",
            "dh_serve_progress", "dh_serve_replay", "dh_serve_stats", "dh_serve_destroy",
-           "dh_last_error", "dh_transfer_metrics", "dh_set_align_goal", "dh_set_pol_lock", "dh_destroy"]
+           "dh_last_error", "dh_transfer_metrics", "dh_set_align_goal", "dh_set_pol_lock", "dh_get_fields16", "dh_fields_to_int16", "dh_destroy"]
 ALIGN_FULL, ALIGN_TWEAK, ALIGN_ESTIMATE = 0, 1, 2
 ALIGN_TILT, ALIGN_DEFOCUS, ALIGN_WAIST, ALIGN_CENTRE = 1, 2, 4, 8
 # launch stages (DH_STAGE_*): row pass; column pass (FFT along y + window,
@@ -85,6 +85,7 @@ class PlanInfo(C.Structure):
         ("ax", C.c_double * 2), ("ay", C.c_double * 2), ("rx", C.c_double), ("ry", C.c_double),
         ("pitch_x", C.c_double), ("pitch_y", C.c_double),
         ("device_bytes", C.c_size_t), ("chunk", C.c_int), ("path", C.c_int),
+        ("field_w", C.c_int), ("field_h", C.c_int), ("field_pitch_x", C.c_double), ("field_pitch_y", C.c_double),
     ]
 
 
@@ -125,6 +126,11 @@ def lib():
         L.dh_transfer_metrics.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double)]
         L.dh_set_align_goal.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int]
         L.dh_set_pol_lock.argtypes = [C.c_int, C.c_uint]
+        L.dh_get_fields16.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                      C.POINTER(C.c_int)]
+        L.dh_fields_to_int16.argtypes = [C.c_void_p, C.c_int, C.c_longlong, C.c_void_p, C.c_void_p, C.c_void_p,
+                                         C.c_void_p]
         L.dh_last_error.argtypes = [C.c_int]
         L.dh_destroy.argtypes = [C.c_int]
         for name in EXPORTS:
@@ -195,6 +201,14 @@ def _stream(s) -> int:
     if isinstance(s, int):
         return s
     return s.cuda_stream
+
+
+def fields_to_int16(fields, n_fields: int, field_len: int, re, im, scale, stream=None):
+    """dh_fields_to_int16 on device buffers (torch tensors or raw pointers)."""
+    rc = lib().dh_fields_to_int16(C.c_void_p(_ptr(fields)), int(n_fields), int(field_len), C.c_void_p(_ptr(re)),
+                                  C.c_void_p(_ptr(im)), C.c_void_p(_ptr(scale)), C.c_void_p(_stream(stream)))
+    if rc != SUCCESS:
+        raise DhError(rc, "dh_fields_to_int16")
 
 
 class Plan:
@@ -278,6 +292,24 @@ class Plan:
 
     def fields(self) -> np.ndarray:
         return self._plane(lib().dh_get_fields, "dh_get_fields")
+
+    def fields16(self):
+        """(re, im, scale): int16 [batch][pol][h][w] parts and float32 [batch][pol]
+        scales of the last batch's fields, field = (re + i im) / scale."""
+        b, p, w, h = C.c_int(), C.c_int(), C.c_int(), C.c_int()
+        L = lib()
+        rc = L.dh_get_fields16(self.handle, None, None, None, None, None, None,
+                               C.byref(b), C.byref(p), C.byref(w), C.byref(h))
+        if rc != SUCCESS:
+            raise DhError(rc, "dh_get_fields16")
+        re = np.empty((b.value, p.value, h.value, w.value), dtype=np.int16)
+        im = np.empty_like(re)
+        sc = np.empty((b.value, p.value), dtype=np.float32)
+        rc = L.dh_get_fields16(self.handle, re.ctypes.data_as(C.c_void_p), im.ctypes.data_as(C.c_void_p),
+                               sc.ctypes.data_as(C.c_void_p), None, None, None, None, None, None, None)
+        if rc != SUCCESS:
+            raise DhError(rc, "dh_get_fields16")
+        return re, im, sc
 
     def set_stage_timing(self, on: bool):
         rc = lib().dh_set_stage_timing(self.handle, int(on))

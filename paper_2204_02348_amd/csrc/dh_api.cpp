@@ -51,6 +51,9 @@ struct PolGeom {
 struct Geom {
   int nx, ny, wx, wy, wyp, bx, by, G, gp, nmodes;
   double rx, ry, pxp, pyp;
+  int mode = 1;          // IFFT resolution mode
+  int fx = 0, fy = 0;    // field grid: W (mode 1) or N (mode 0)
+  double fpx = 0, fpy = 0;   // its pitch: N p / F
   bool spec = false;     // the plan runs the spectral path (DH_PATH_SPECTRAL)
   int byp = 16;          // by rounded up to 16
   PolGeom pol[2];
@@ -123,7 +126,7 @@ int derive(const dh_params* p, Geom* g) {
   if (p->input_dtype != DH_INPUT_F32 && p->input_dtype != DH_INPUT_U16) return DH_ERR_INVALIDARGUMENT;
   if (p->precision != DH_PREC_FP32 && p->precision != DH_PREC_SPLIT_BF16 && p->precision != DH_PREC_SPLIT_FP16)
     return DH_ERR_INVALIDARGUMENT;
-  if (p->ifft_mode != 1) return DH_ERR_INVALIDARGUMENT;
+  if (p->ifft_mode != 0 && p->ifft_mode != 1) return DH_ERR_INVALIDARGUMENT;
   if (p->path < DH_PATH_AUTO || p->path > DH_PATH_SPECTRAL) return DH_ERR_INVALIDARGUMENT;
   for (int q = 0; q < p->pol_count; ++q) {
     for (int a = 0; a < 2; ++a)
@@ -142,6 +145,11 @@ int derive(const dh_params* p, Geom* g) {
   g->wyp = (g->wy + 15) / 16 * 16;
   g->pxp = nx * pix / g->wx;
   g->pyp = ny * pix / g->wy;
+  g->mode = p->ifft_mode;
+  g->fx = g->mode ? g->wx : nx;
+  g->fy = g->mode ? g->wy : ny;
+  g->fpx = nx * pix / g->fx;
+  g->fpy = ny * pix / g->fy;
   g->G = p->max_mg;
   g->gp = g->G <= 16 ? 16 : 32;
   g->nmodes = g->G * (g->G + 1) / 2;
@@ -156,6 +164,14 @@ int derive(const dh_params* p, Geom* g) {
   }
   if (!dh::sizes_supported(nx, ny, g->wx, g->wy)) return DH_ERR_INVALIDDIMENSION;
   g->byp = (g->by + 15) / 16 * 16;
+  if (g->mode == 0) {
+    // IFFT mode 0: the coefficients come from spectral tables built on the FFT
+    // grid, the fields (on request) from the kept window by two complex GEMMs
+    if (p->path == DH_PATH_FIELD || p->precision != DH_PREC_FP32 || g->G == 0) return DH_ERR_INVALIDARGUMENT;
+    if (!dh::spectral_supported(ny, g->wy, g->gp)) return DH_ERR_INVALIDDIMENSION;
+    g->spec = true;
+    return DH_SUCCESS;
+  }
   const bool can_spec = p->precision == DH_PREC_FP32 && !p->keep_fields && g->G > 0 &&
                         dh::spectral_supported(ny, g->wy, g->gp);
   if (p->path == DH_PATH_SPECTRAL && !can_spec) return DH_ERR_INVALIDARGUMENT;
@@ -164,6 +180,15 @@ int derive(const dh_params* p, Geom* g) {
 }
 
 size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+
+// mode-0 fields are made from the kept window after the coefficients
+bool exports(const Geom& g, const dh_params* p) { return g.mode == 0 && p->keep_fields; }
+// frames per export GEMM group: the x-transformed windows within 256 MiB
+int export_chunk(const Geom& g, const dh_params* p, int max_batch) {
+  const size_t per = (size_t)p->pol_count * g.wy * g.fx * 8;
+  const long c = (long)((256ull << 20) / (per ? per : 1));
+  return (int)std::max(1L, std::min<long>(c, max_batch));
+}
 
 int env_int(const char* name, int dflt) {
   if (const char* env = std::getenv(name)) {
@@ -201,6 +226,8 @@ struct Layout {  // byte offsets inside one device allocation
   size_t pol_mrow[2], pol_rhox[2], pol_rhoy[2], pol_tx[2], pol_ty[2], pol_ux[2], pol_uy[2];
   size_t pol_uxs[2][4], pol_uys[2][4];   // split tables: bf16 hi, bf16 lo, fp16 hi, fp16 lo
   size_t pol_xs[2], pol_ys[2];           // spectral path tables
+  size_t pol_ex[2], pol_ey[2];           // mode-0 field export tables
+  size_t export_t;                       // mode-0 field export: the x-transformed windows
   size_t t1[4], f2[4], partial[4], capt, coefs, coefs_norm, window, fields, total;
 };
 
@@ -227,6 +254,8 @@ Layout layout(const Geom& g, const dh_params* p, int max_batch, int chunk, int n
     }
     L.pol_xs[q] = take(g.spec ? (size_t)g.bx * g.gp * 8 : 0);
     L.pol_ys[q] = take(g.spec ? (size_t)g.wyp * g.gp * 8 : 0);
+    L.pol_ex[q] = take(exports(g, p) ? (size_t)g.wx * g.fx * 8 : 0);
+    L.pol_ey[q] = take(exports(g, p) ? (size_t)g.fy * g.wy * 8 : 0);
   }
   const size_t P = p->pol_count;
   const size_t nm = g.nmodes > 0 ? g.nmodes : 1;
@@ -238,8 +267,9 @@ Layout layout(const Geom& g, const dh_params* p, int max_batch, int chunk, int n
   L.capt = take((size_t)max_batch * P * 2 * 8);
   L.coefs = take((size_t)max_batch * P * nm * 8);
   L.coefs_norm = take((size_t)max_batch * P * nm * 8);
-  L.window = p->keep_window ? take((size_t)max_batch * P * g.wy * g.wx * 8) : 0;
-  L.fields = p->keep_fields ? take((size_t)max_batch * P * g.wy * g.wx * 8) : 0;
+  L.window = p->keep_window || exports(g, p) ? take((size_t)max_batch * P * g.wy * g.wx * 8) : 0;
+  L.fields = p->keep_fields ? take((size_t)max_batch * P * g.fy * g.fx * 8) : 0;
+  L.export_t = exports(g, p) ? take((size_t)export_chunk(g, p, max_batch) * P * g.wy * g.fx * 8) : 0;
   L.total = o;
   return L;
 }
@@ -266,6 +296,7 @@ struct Plan {
   size_t tm_bytes = 0;
   rocblas_handle blas = nullptr;
   unsigned lock = 0;                 // DH_ALIGN_TILT / DH_ALIGN_DEFOCUS: pol 1 takes pol 0's value
+  char* q16_mem = nullptr;           // int16 fields and scales (dh_get_fields16), made on first use
   int goal = DH_GOAL_CAPTURED;       // alignment goal and its transfer-matrix options
   int goal_indep = 0, goal_aa = 0;
   size_t amem_bytes = 0;
@@ -384,24 +415,62 @@ std::vector<float2> spectral_axis(int nbox, int npad, int gp, int G, int uhi, in
   return t;
 }
 
+// Mode-0 field export table along one axis (FP64, stored FP32): for the
+// window grid cell q = u mod W of each bin u = u_hi - j of the box, and each
+// field sample x_k = (k - F/2) p' of the F-point grid,
+//   e[q][k] = norm e^{2 pi i u x_k / (N p)} e^{i phi(x_k)},
+// phi the tilt and defocus phase along the axis; zero for cells without a bin.
+// Stored [W][F], or transposed [F][W].
+std::vector<float2> export_axis(int uhi, int nbox, int w, int f, double tilt_bins, double defocus, double lam,
+                                double pitch, double norm, bool transposed) {
+  std::vector<float2> t((size_t)w * f, make_float2(0.f, 0.f));
+  for (int j = 0; j < nbox; ++j) {
+    const long long u = uhi - j;
+    long long qc = u % w;
+    if (qc < 0) qc += w;
+    for (int k = 0; k < f; ++k) {
+      const double x = (k - f / 2.0) * pitch;
+      // 2 pi (u + a) (k - f/2) / f, the bin phase reduced exactly first
+      long long e = (u * (2LL * k - f)) % (2LL * f);
+      if (e < 0) e += 2LL * f;
+      const double ph = kPi * (double)e / f + 2.0 * kPi * tilt_bins * (k - f / 2.0) / f + kPi * defocus * x * x / lam;
+      const cd v = std::exp(cd(0, ph)) * norm;
+      const size_t at = transposed ? (size_t)k * w + qc : (size_t)qc * f + k;
+      t[at] = make_float2((float)v.real(), (float)v.imag());
+    }
+  }
+  return t;
+}
+
 int build_spectral(Plan* pl) {
   const Geom& g = pl->g;
   if (!g.spec) return DH_SUCCESS;
   const dh_params* p = &pl->params;
   const Layout& L = pl->L;
   const double waist = p->waist > 0 ? p->waist : 1.0;
-  const std::vector<double> hx = hg_host(g.pxp, g.wx, waist, g.G), hy = hg_host(g.pyp, g.wy, waist, g.G);
+  // the overlap's quadrature runs over the field grid: the Fourier-window
+  // size in IFFT mode 1, the FFT size in mode 0
+  const std::vector<double> hx = hg_host(g.fpx, g.fx, waist, g.G), hy = hg_host(g.fpy, g.fy, waist, g.G);
   for (int q = 0; q < p->pol_count; ++q) {
     const PolGeom& P = g.pol[q];
     const std::vector<float2> xs =
-        spectral_axis(g.bx, g.bx, g.gp, g.G, P.uhi, g.wx, g.pxp, P.ax, p->defocus[q], p->wavelength, P.dx,
+        spectral_axis(g.bx, g.bx, g.gp, g.G, P.uhi, g.fx, g.fpx, P.ax, p->defocus[q], p->wavelength, P.dx,
                       p->pixel_size, g.nx, 1.0, hx);
     const std::vector<float2> ys =
-        spectral_axis(g.by, g.wyp, g.gp, g.G, P.vhi, g.wy, g.pyp, P.ay, p->defocus[q], p->wavelength, P.dy,
+        spectral_axis(g.by, g.wyp, g.gp, g.G, P.vhi, g.fy, g.fpy, P.ay, p->defocus[q], p->wavelength, P.dy,
                       p->pixel_size, g.ny, 1.0 / ((double)g.nx * g.ny), hy);
     if (hipMemcpy(pl->mem + L.pol_xs[q], xs.data(), xs.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(pl->mem + L.pol_ys[q], ys.data(), ys.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess)
       return DH_ERR_ERROR;
+    if (exports(g, p)) {
+      const std::vector<float2> ex = export_axis(P.uhi, P.uhi - P.ulo + 1, g.wx, g.fx, P.ax, p->defocus[q],
+                                                 p->wavelength, g.fpx, 1.0, false);
+      const std::vector<float2> ey = export_axis(P.vhi, P.vhi - P.vlo + 1, g.wy, g.fy, P.ay, p->defocus[q],
+                                                 p->wavelength, g.fpy, 1.0 / ((double)g.nx * g.ny), true);
+      if (hipMemcpy(pl->mem + L.pol_ex[q], ex.data(), ex.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(pl->mem + L.pol_ey[q], ey.data(), ey.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess)
+        return DH_ERR_ERROR;
+    }
   }
   return DH_SUCCESS;
 }
@@ -533,13 +602,52 @@ void fill_kargs(Plan* pl, int w) {
   a.nblk = g.spec ? dh::spectral_blocks(g.ny, g.bx) : field_blocks(g);
   a.coefs = (float2*)(m + L.coefs);
   a.coefs_norm = (float2*)(m + L.coefs_norm);
-  a.window = p->keep_window ? (float2*)(m + L.window) : nullptr;
-  a.fields = p->keep_fields ? (float2*)(m + L.fields) : nullptr;
+  a.window = p->keep_window || exports(g, p) ? (float2*)(m + L.window) : nullptr;
+  // the kernels write mode-1 fields; mode-0 fields come from the export
+  a.fields = p->keep_fields && g.mode == 1 ? (float2*)(m + L.fields) : nullptr;
 }
 
 int set_err(Plan* pl, int e) {
   if (pl) pl->last_error = e;
   return e;
+}
+
+// the plan's rocBLAS handle (made on first use), bound to stream s
+bool blas_on(Plan* pl, hipStream_t s) {
+  if (!pl->blas && rocblas_create_handle(&pl->blas) != rocblas_status_success) {
+    pl->blas = nullptr;
+    return false;
+  }
+  return rocblas_set_stream(pl->blas, s) == rocblas_status_success;
+}
+
+// IFFT mode 0: the fields of frames [0, batch) from their kept windows,
+// E = Ey W Ex per frame and pol (the export tables), as two complex GEMMs
+// per pol over groups of frames; row-major arrays are read as transposed
+// column-major ones: T^T = Ex^T W^T, then E^T = T^T Ey^T.
+int export_fields(Plan* pl, int batch, hipStream_t s) {
+  const Geom& g = pl->g;
+  const int P = pl->params.pol_count;
+  if (!blas_on(pl, s)) return DH_ERR_ERROR;
+  const rocblas_float_complex one = {1.f, 0.f}, zero = {0.f, 0.f};
+  auto cx = [&](size_t off) { return (rocblas_float_complex*)(pl->mem + off); };
+  const int grp = export_chunk(g, &pl->params, pl->max_batch);
+  for (int b0 = 0; b0 < batch; b0 += grp) {
+    const int nb = std::min(grp, batch - b0);
+    for (int q = 0; q < P; ++q) {
+      const rocblas_float_complex* win = cx(pl->L.window) + ((size_t)b0 * P + q) * g.wy * g.wx;
+      rocblas_float_complex* t = cx(pl->L.export_t) + (size_t)q * g.wy * g.fx;
+      rocblas_float_complex* f = cx(pl->L.fields) + ((size_t)b0 * P + q) * g.fy * g.fx;
+      if (rocblas_cgemm_strided_batched(pl->blas, rocblas_operation_none, rocblas_operation_none, g.fx, g.wy, g.wx,
+                                        &one, cx(pl->L.pol_ex[q]), g.fx, 0, win, g.wx, (rocblas_stride)P * g.wy * g.wx,
+                                        &zero, t, g.fx, (rocblas_stride)P * g.wy * g.fx, nb) != rocblas_status_success ||
+          rocblas_cgemm_strided_batched(pl->blas, rocblas_operation_none, rocblas_operation_none, g.fx, g.fy, g.wy,
+                                        &one, t, g.fx, (rocblas_stride)P * g.wy * g.fx, cx(pl->L.pol_ey[q]), g.wy, 0,
+                                        &zero, f, g.fx, (rocblas_stride)P * g.fy * g.fx, nb) != rocblas_status_success)
+        return DH_ERR_ERROR;
+    }
+  }
+  return DH_SUCCESS;
 }
 
 int copy_out(Plan* pl, void* host_out, size_t bytes, const void* dev) {
@@ -563,6 +671,7 @@ void release(Plan* pl) {
   if (pl->mem) (void)hipFree(pl->mem);
   if (pl->amem) (void)hipFree(pl->amem);
   if (pl->tm_mem) (void)hipFree(pl->tm_mem);
+  if (pl->q16_mem) (void)hipFree(pl->q16_mem);
   if (pl->blas) (void)rocblas_destroy_handle(pl->blas);
   (void)hipSetDevice(dev);
   delete pl;
@@ -594,6 +703,8 @@ int dh_plan_check(const dh_params* p, int max_batch, dh_plan_info* info) {
     info->device_bytes = L.total;
     info->chunk = chunk;
     info->path = g.spec ? DH_PATH_SPECTRAL : DH_PATH_FIELD;
+    info->field_w = g.fx; info->field_h = g.fy;
+    info->field_pitch_x = g.fpx; info->field_pitch_y = g.fpy;
   }
   return DH_SUCCESS;
 }
@@ -688,6 +799,7 @@ int dh_process_batch(dh_handle h, const void* frames, int batch, void* stream) {
       if (hipEventRecord(pl->join[w], pl->str[w]) != hipSuccess || hipStreamWaitEvent(s, pl->join[w], 0) != hipSuccess)
         return set_err(pl, DH_ERR_ERROR);
   }
+  if (exports(pl->g, &pl->params) && export_fields(pl, batch, s) != DH_SUCCESS) return set_err(pl, DH_ERR_ERROR);
   pl->last_batch = batch;
   pl->last_stream = s;
   return set_err(pl, DH_SUCCESS);
@@ -714,18 +826,24 @@ int dh_mode_coefs(dh_handle h, dh_c64* host_out, const dh_c64** dev_out, int* ba
   return set_err(pl, copy_out(pl, host_out, bytes, src));
 }
 
+// the plan's field buffer (mode 1: written by the kernels; mode 0: by the export)
+static const float2* field_buffer(Plan* pl) {
+  return pl->params.keep_fields ? (const float2*)(pl->mem + pl->L.fields) : nullptr;
+}
+
 static int get_plane(dh_handle h, bool win, dh_c64* host_out, const dh_c64** dev_out, int* batch, int* pols,
                      int* width, int* height) {
   Plan* pl = get(h);
   if (!pl) return DH_ERR_INVALIDHANDLE;
-  const float2* src = win ? pl->ka[0].window : pl->ka[0].fields;
+  const float2* src = win ? pl->ka[0].window : field_buffer(pl);
+  const int w = win ? pl->g.wx : pl->g.fx, hgt = win ? pl->g.wy : pl->g.fy;
   if (batch) *batch = pl->last_batch;
   if (pols) *pols = pl->params.pol_count;
-  if (width) *width = pl->g.wx;
-  if (height) *height = pl->g.wy;
+  if (width) *width = w;
+  if (height) *height = hgt;
   if (dev_out) *dev_out = (const dh_c64*)src;
   if (!src) return set_err(pl, DH_ERR_ERROR);
-  const size_t bytes = (size_t)pl->last_batch * pl->params.pol_count * pl->g.wx * pl->g.wy * sizeof(dh_c64);
+  const size_t bytes = (size_t)pl->last_batch * pl->params.pol_count * w * hgt * sizeof(dh_c64);
   return set_err(pl, copy_out(pl, host_out, bytes, src));
 }
 
@@ -860,11 +978,7 @@ int tm_compute(Plan* pl, int B, int pol_independent, int mul_conj_trans, hipStre
   char* m = pl->tm_mem;
   double2* g = (double2*)(m + og);
   double2* gd = extra ? (double2*)(m + od) : g;
-  if (!pl->blas && rocblas_create_handle(&pl->blas) != rocblas_status_success) {
-    pl->blas = nullptr;
-    return DH_ERR_ERROR;
-  }
-  if (rocblas_set_stream(pl->blas, s) != rocblas_status_success) return DH_ERR_ERROR;
+  if (!blas_on(pl, s)) return DH_ERR_ERROR;
   // the row statistics read the Gram matrix before the eigen-solver overwrites it
   if (dh::launch_tm_gram(t, byrows, n, g, s) != hipSuccess ||
       (extra && dh::launch_tm_gram(t, 1, t.rows, gd, s) != hipSuccess) ||
@@ -1306,6 +1420,55 @@ extern "C" int dh_set_align_goal(dh_handle h, int goal, int pol_independent, int
   pl->goal = goal;
   pl->goal_indep = pol_independent != 0;
   pl->goal_aa = mul_conj_trans != 0;
+  return set_err(pl, DH_SUCCESS);
+}
+
+extern "C" int dh_fields_to_int16(const dh_c64* fields, int n_fields, long long field_len, short* re, short* im,
+                                  float* scale, void* stream) {
+  if (n_fields < 0 || field_len < 1) return DH_ERR_INVALIDARGUMENT;
+  if (n_fields == 0) return DH_SUCCESS;
+  if (!fields || !re || !im || !scale) return DH_ERR_NULLPOINTER;
+  return dh::launch_q16((const float2*)fields, n_fields, field_len, re, im, scale, (hipStream_t)stream) == hipSuccess
+             ? DH_SUCCESS
+             : DH_ERR_ERROR;
+}
+
+extern "C" int dh_get_fields16(dh_handle h, short* re_host, short* im_host, float* scale_host, const short** re_dev,
+                               const short** im_dev, const float** scale_dev, int* batch, int* pols, int* width,
+                               int* height) {
+  Plan* pl = get(h);
+  if (!pl) return DH_ERR_INVALIDHANDLE;
+  const Geom& g = pl->g;
+  const int P = pl->params.pol_count;
+  if (batch) *batch = pl->last_batch;
+  if (pols) *pols = P;
+  if (width) *width = g.fx;
+  if (height) *height = g.fy;
+  const float2* src = field_buffer(pl);
+  if (!src || pl->last_batch < 1) return set_err(pl, DH_ERR_ERROR);
+  const size_t n = (size_t)pl->max_batch * P, len = (size_t)g.fx * g.fy;
+  const size_t o_im = align256(n * len * 2), o_sc = o_im + align256(n * len * 2);
+  if (!pl->q16_mem && hipMalloc(&pl->q16_mem, o_sc + align256(n * 4)) != hipSuccess) {
+    (void)hipGetLastError();
+    pl->q16_mem = nullptr;
+    return set_err(pl, DH_ERR_MEMORYALLOCATION);
+  }
+  short* re = (short*)pl->q16_mem;
+  short* im = (short*)(pl->q16_mem + o_im);
+  float* sc = (float*)(pl->q16_mem + o_sc);
+  if (re_dev) *re_dev = re;
+  if (im_dev) *im_dev = im;
+  if (scale_dev) *scale_dev = sc;
+  const int nf = pl->last_batch * P;
+  hipStream_t s = pl->last_stream;
+  if (dh::launch_q16(src, nf, (long long)len, re, im, sc, s) != hipSuccess) return set_err(pl, DH_ERR_ERROR);
+  if (re_host && hipMemcpyAsync(re_host, re, (size_t)nf * len * 2, hipMemcpyDeviceToHost, s) != hipSuccess)
+    return set_err(pl, DH_ERR_ERROR);
+  if (im_host && hipMemcpyAsync(im_host, im, (size_t)nf * len * 2, hipMemcpyDeviceToHost, s) != hipSuccess)
+    return set_err(pl, DH_ERR_ERROR);
+  if (scale_host && hipMemcpyAsync(scale_host, sc, (size_t)nf * 4, hipMemcpyDeviceToHost, s) != hipSuccess)
+    return set_err(pl, DH_ERR_ERROR);
+  if (hipStreamSynchronize(s) != hipSuccess) return set_err(pl, DH_ERR_ERROR);
   return set_err(pl, DH_SUCCESS);
 }
 

@@ -6,6 +6,7 @@
 //   k_tm_gram  Gram matrix of the batch transfer matrix (its eigenvalues are
 //              the squared singular values)
 //   k_tm_rows  row statistics of the matrix the diagonal metrics are taken on
+//   k_q16      fields to int16 real and imaginary parts with one scale each
 #include "dh_internal.hpp"
 
 namespace dh {
@@ -147,6 +148,41 @@ hipError_t launch_moments(const float2* fields, int n, int wx, int wy, double px
                           hipStream_t s) {
   if (n < 1) return hipSuccess;
   hipLaunchKernelGGL(k_moments, dim3(n), dim3(256), 0, s, fields, wx, wy, px, py, out);
+  return hipGetLastError();
+}
+
+// k_q16: grid (n fields); block e: scale = 32767 / max(|Re|, |Im|) over field
+// e (1 if it is all zero), correctly rounded, then each part times the scale
+// rounded to the nearest integer, ties to even (all in FP32).
+__global__ void __launch_bounds__(256) k_q16(const float2* __restrict__ f, long long len, short* __restrict__ re,
+                                             short* __restrict__ im, float* __restrict__ scale) {
+  __shared__ float red[256];
+  const int tid = threadIdx.x;
+  const size_t base = (size_t)blockIdx.x * (size_t)len;
+  float m = 0.f;
+  for (long long t = tid; t < len; t += 256) {
+    const float2 v = f[base + t];
+    m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
+  }
+  red[tid] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) red[tid] = fmaxf(red[tid], red[tid + w]);
+    __syncthreads();
+  }
+  const float peak = red[0];
+  const float s = peak > 0.f ? __fdiv_rn(32767.0f, peak) : 1.0f;
+  for (long long t = tid; t < len; t += 256) {
+    const float2 v = f[base + t];
+    re[base + t] = (short)rintf(v.x * s);
+    im[base + t] = (short)rintf(v.y * s);
+  }
+  if (tid == 0) scale[blockIdx.x] = s;
+}
+
+hipError_t launch_q16(const float2* fields, int n, long long len, short* re, short* im, float* scale, hipStream_t s) {
+  if (n < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_q16, dim3(n), dim3(256), 0, s, fields, len, re, im, scale);
   return hipGetLastError();
 }
 

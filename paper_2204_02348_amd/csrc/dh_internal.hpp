@@ -98,6 +98,8 @@ hipError_t launch_gather(const KArgs& a, const float2* spec, int bxe, int nrow, 
 hipError_t launch_psum(const float2* spec, int nb, int npol, size_t plane, float* pw, hipStream_t s);
 // FP64 intensity moments of n fields [wy][wx]: out[e][5] = sums of I, xI, yI,
 // x^2 I, y^2 I on the coarse grid x = (k - wx/2) px, y = (l - wy/2) py
+// fields to int16 (re, im) with one FP32 scale per field: n fields of len values
+hipError_t launch_q16(const float2* fields, int n, long long len, short* re, short* im, float* scale, hipStream_t s);
 hipError_t launch_moments(const float2* fields, int n, int wx, int wy, double px, double py, double* out,
                           hipStream_t s);
 // HG tables: out[k][n] in FP32 and, if the split pointers are non-null, the

@@ -52,7 +52,10 @@ def _p(idx=1, **kw):
     (dict(max_mg=33), dh.ERR_INVALIDARGUMENT),
     (dict(input_dtype=7), dh.ERR_INVALIDARGUMENT),
     (dict(precision=9), dh.ERR_INVALIDARGUMENT),
-    (dict(ifft_mode=0), dh.ERR_INVALIDARGUMENT),
+    (dict(ifft_mode=2), dh.ERR_INVALIDARGUMENT),
+    (dict(ifft_mode=0, path="field"), dh.ERR_INVALIDARGUMENT),        # mode 0 runs the spectral path
+    (dict(ifft_mode=0, precision="split_bf16"), dh.ERR_INVALIDARGUMENT),
+    (dict(ifft_mode=0, max_mg=0), dh.ERR_INVALIDARGUMENT),
     (dict(path=3), dh.ERR_INVALIDARGUMENT),
     (dict(path=-1), dh.ERR_INVALIDARGUMENT),
     (dict(path="spectral", keep_fields=1), dh.ERR_INVALIDARGUMENT),
@@ -143,9 +146,34 @@ def test_serving_rejects_bad_arguments_without_gpu():
     (3, 2, {}, dh.PATH_SPECTRAL),                                  # 1024x1024 camera G=15
     (3, 3, {}, dh.PATH_SPECTRAL),                                  # 2048x2048 camera G=20
     (3, 0, dict(max_mg=0), dh.PATH_FIELD),
+    (1, 0, dict(ifft_mode=0), dh.PATH_SPECTRAL),                   # IFFT mode 0
+    (1, 0, dict(ifft_mode=0, keep_fields=1), dh.PATH_SPECTRAL),    # mode-0 fields by the export
 ])
 def test_path_resolution(idx, cam, kw, path):
     d = dict(dh_synth.config(idx, cam)["params"])
     d.update(kw)
     rc, info = dh.plan_check(d)
     assert rc == dh.SUCCESS and info.path == path
+
+
+@pytest.mark.parametrize("idx,cam", [(0, 0), (1, 0), (3, 3)])
+def test_field_grid_of_both_ifft_modes(idx, cam):
+    import oracle
+    for mode in (1, 0):
+        d = dict(dh_synth.config(idx, cam)["params"], ifft_mode=mode)
+        rc, info = dh.plan_check(d)
+        g = oracle.geometry(d)
+        assert rc == dh.SUCCESS
+        assert (info.field_w, info.field_h) == (g["fx"], g["fy"])
+        assert info.field_pitch_x == pytest.approx(g["px2"], rel=1e-15)
+        assert info.field_pitch_y == pytest.approx(g["py2"], rel=1e-15)
+        assert (info.ifft_w, info.ifft_h) == (g["wx"], g["wy"])
+
+
+def test_int16_conversion_rejects_bad_arguments_without_gpu():
+    L = dh.lib()
+    assert L.dh_fields_to_int16(None, -1, 4, None, None, None, None) == dh.ERR_INVALIDARGUMENT
+    assert L.dh_fields_to_int16(None, 1, 0, None, None, None, None) == dh.ERR_INVALIDARGUMENT
+    assert L.dh_fields_to_int16(None, 0, 4, None, None, None, None) == dh.SUCCESS
+    assert L.dh_fields_to_int16(None, 2, 4, None, None, None, None) == dh.ERR_NULLPOINTER
+    assert L.dh_get_fields16(77, None, None, None, None, None, None, None, None, None, None) == dh.ERR_INVALIDHANDLE

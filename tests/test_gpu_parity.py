@@ -593,6 +593,103 @@ def test_alignment_pol_lock():
     assert abs(got["defocus"][0] - truth["defocus"][0]) < 0.01
 
 
+# ---------------------------------------------------------------- IFFT mode 0 and the int16 format
+@pytest.mark.parametrize("idx,cam,n,chunk", [
+    (0, 0, 1, None),      # 128x128 G=4
+    (1, 0, 7, 3),         # 640x512 2 pols G=9, ragged chunks
+    (3, 1, 2, None),      # 640x512 uint16 G=9
+    (4, 0, 2, None),      # 1024x1024 2 pols G=30
+])
+def test_mode0_coefficients_and_fields_vs_oracle(idx, cam, n, chunk):
+    """IFFT mode 0: coefficients from the FFT-grid tables and the full-size
+    fields made from the kept window, against the oracle in mode 0."""
+    import paper_2204_02348_amd as dh
+    cfg, f, _ = _frames(idx, cam=cam, n=n)
+    p = dict(cfg["params"], ifft_mode=0)
+    _say("IFFT mode 0, recipe", idx, "camera", cam, f.shape)
+    gpu = run_gpu(p, f, chunk=chunk)
+    assert gpu["info"].path == dh.PATH_SPECTRAL
+    assert gpu["field"].shape[2:] == (p["fft_h"], p["fft_w"])
+    check_frames(p, f, gpu, range(n))
+
+
+def test_mode0_fields_across_export_groups():
+    """1000 frames of 640x512 in IFFT mode 0 with fields: the export runs in
+    groups of frames; sampled frames on both sides of each group edge."""
+    torch = _torch()
+    import paper_2204_02348_amd as dh
+    cfg, pool, _ = _frames(1, n=50)
+    n = 1000
+    f = dh_synth.tile_pool(pool, n)
+    p = dict(cfg["params"], ifft_mode=0, keep_fields=1)
+    plan = dh.Plan(p, max_batch=n)
+    ft = torch.from_numpy(np.ascontiguousarray(f)).cuda()
+    _say("mode-0 fields, batch %d" % n)
+    plan.process(ft, n, None)
+    fields = plan.fields()
+    coefs = plan.coefs(False)
+    plan.destroy()
+    for i in (0, 296, 297, 593, 594, 999):
+        ref = oracle.process_frame(f[i].astype(np.float64), p)
+        for q in range(2):
+            assert _rel(fields[i][q].astype(np.complex128), ref["field"][q]) <= TOL, (i, q)
+            assert _rel(coefs[i][q].astype(np.complex128), ref["coefs"][q]) <= TOL, (i, q)
+
+
+def test_int16_conversion_is_bit_exact():
+    """dh_fields_to_int16 on seeded synthetic fields (ragged length, a zero
+    field, values planted on rounding ties) against the oracle's FP32
+    conversion: every code and scale identical."""
+    torch = _torch()
+    import paper_2204_02348_amd as dh
+    rng = np.random.default_rng(20240417)
+    n, length = 5, 4099
+    f = (rng.normal(size=(n, length)) + 1j * rng.normal(size=(n, length))).astype(np.complex64)
+    f[1] *= np.float32(1e-3)
+    f[2] = 0
+    f[3, :8] = np.array([32767.0, 2.5, 3.5, -2.5, -3.5, 0.5, 1.5, -0.5], dtype=np.float32)   # scale 1: ties
+    f[3, 8:] = (f[3, 8:] * np.float32(100)).astype(np.complex64)
+    dev = torch.from_numpy(f).cuda()
+    re = torch.empty((n, length), dtype=torch.int16, device="cuda")
+    im = torch.empty_like(re)
+    sc = torch.empty(n, dtype=torch.float32, device="cuda")
+    dh.fields_to_int16(dev, n, length, re, im, sc)
+    torch.cuda.synchronize()
+    gre, gim, gsc = re.cpu().numpy(), im.cpu().numpy(), sc.cpu().numpy()
+    for e in range(n):
+        ore, oim, osc = oracle.fields_to_int16(f[e])
+        _say("field %d scale gpu %r oracle %r" % (e, float(gsc[e]), float(osc)))
+        assert gsc[e] == osc
+        assert np.array_equal(gre[e], ore) and np.array_equal(gim[e], oim)
+
+
+def test_plan_fields16_match_oracle_fields():
+    """The plan's int16 export of its fields: codes within one step of the
+    oracle's conversion of the oracle's field (the two FP32 fields differ by
+    rounding), the decoded field within half a step plus that rounding."""
+    import paper_2204_02348_amd as dh
+    torch = _torch()
+    for mode in (1, 0):
+        cfg, f, _ = _frames(1, n=3)
+        p = dict(cfg["params"], ifft_mode=mode, keep_fields=1)
+        plan = dh.Plan(p, max_batch=3)
+        ft = torch.from_numpy(np.ascontiguousarray(f)).cuda()
+        plan.process(ft, 3, None)
+        re, im, sc = plan.fields16()
+        plan.destroy()
+        _say("fields16 mode %d shape %s" % (mode, re.shape))
+        for i in range(3):
+            ref = oracle.process_frame(f[i].astype(np.float64), p)["field"]
+            for q in range(2):
+                ore, oim, osc = oracle.fields_to_int16(ref[q])
+                assert abs(float(sc[i, q]) / float(osc) - 1) < 1e-5
+                assert np.abs(re[i, q].astype(np.int32) - ore).max() <= 1
+                assert np.abs(im[i, q].astype(np.int32) - oim).max() <= 1
+                dec = (re[i, q] + 1j * im[i, q].astype(np.float64)) / float(sc[i, q])
+                step = 1.0 / float(sc[i, q])
+                assert np.abs(dec - ref[q]).max() <= 0.5 * step + 1e-5 * np.abs(ref[q]).max()
+
+
 # ---------------------------------------------------------------- transfer-matrix metrics
 @pytest.mark.parametrize("n", [90, 1000])
 def test_transfer_metrics_match_oracle(n):
