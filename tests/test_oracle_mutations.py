@@ -237,3 +237,51 @@ def test_mode0_and_int16_pins_catch_planted_mistake(name, monkeypatch):
         except (AssertionError, ValueError, IndexError, OverflowError):
             failed += 1
     assert failed > 0, name
+
+
+# ---------------------------------------------------------------- basis transforms
+BASIS_SRC = os.path.join(os.path.dirname(SRC), "basis.py")
+
+BASIS_MUTATIONS = {
+    "l_order_reversed": ("for l in range(n, -n - 1, -2):", "for l in range(-n, n + 1, 2):"),
+    "no_conjugate": ("np.sum(ww * np.conj(a) * b)", "np.sum(ww * a * b)"),
+    "lg_norm": ("math.factorial(p + abs(l))", "math.factorial(p)"),
+    "phi_sign": ("np.exp(1j * l * phi)", "np.exp(-1j * l * phi)"),
+    "laguerre_argument": ("special.eval_genlaguerre(p, abs(l), 2.0 * r2)", "special.eval_genlaguerre(p, abs(l), r2)"),
+    "hg_axes_swapped": ("np.outer(u[n], u[m]) for m, n", "np.outer(u[m], u[n]) for m, n"),
+    "custom_extra_columns_used": ("k = min(modes, t.shape[1])", "k = t.shape[1]"),
+}
+
+
+def _basis_mutant(name):
+    import oracle
+    src = open(BASIS_SRC).read()
+    old, new = BASIS_MUTATIONS[name]
+    assert src.count(old) == 1, name
+    src = src.replace(old, new).replace("from .holo_oracle import hermite_gauss_1d, mode_list\n", "")
+    mod = types.ModuleType("basis_mutant_" + name)
+    mod.__dict__["hermite_gauss_1d"] = oracle.hermite_gauss_1d
+    mod.__dict__["mode_list"] = oracle.mode_list
+    exec(compile(src, BASIS_SRC + ":" + name, "exec"), mod.__dict__)
+    return mod
+
+
+@pytest.mark.parametrize("name", sorted(BASIS_MUTATIONS))
+def test_basis_pins_catch_planted_mistake(name, monkeypatch):
+    import oracle
+    import tests.test_oracle_pins as pins
+    mut = _basis_mutant(name)
+    for k in ("lg_modes", "lg_function", "hg_to_lg", "custom_transform", "apply_basis"):
+        monkeypatch.setattr(oracle, k, getattr(mut, k))
+    failed = 0
+    for t in [pins.test_lg_transform_is_unitary_and_keeps_groups,
+              pins.test_lg_low_orders_are_the_textbook_combinations,
+              pins.test_lg_transform_matches_the_closed_form,
+              pins.test_lg_transform_matches_fine_grid_overlaps,
+              pins.test_custom_transform_uses_only_the_plan_modes]:
+        try:
+            with np.errstate(all="ignore"):
+                t()
+        except (AssertionError, ValueError, IndexError):
+            failed += 1
+    assert failed > 0, name

@@ -554,3 +554,96 @@ def test_int16_ties_to_even_and_zero_field():
     assert re.tolist() == [32767, 2, 4, -2, -4, 0, 2] and not im.any()
     re, im, scale = oracle.fields_to_int16(np.zeros((4, 4), dtype=np.complex64))
     assert scale == 1.0 and not re.any() and not im.any()
+
+
+# ---------------------------------------------------------------- basis transforms (LG, custom)
+def _lg_closed_form(group_count):
+    """HG -> LG coefficient transform from the generating function of the
+    mode converter literature (the coefficient of t^k in (1-t)^n (1+t)^m,
+    n - m = l, n + m = N), with the phase convention of the basis reading:
+    T[(p,l)][HG(N-k, k)] = (-1)^p i^k b(n, m, k)."""
+    modes = oracle.mode_list(group_count)
+    col = {mn: i for i, mn in enumerate(modes)}
+    lg = oracle.lg_modes(group_count)
+    t = np.zeros((len(lg), len(modes)), dtype=complex)
+    for r, (p, l) in enumerate(lg):
+        big_n = 2 * p + abs(l)
+        n, m = p + max(l, 0), p + max(-l, 0)
+        for k in range(big_n + 1):
+            poly = sum(math.comb(n, a) * (-1) ** a * math.comb(m, k - a) for a in range(0, k + 1) if k - a <= m)
+            b = math.sqrt(math.factorial(big_n - k) * math.factorial(k)
+                          / (2 ** big_n * math.factorial(n) * math.factorial(m))) * poly
+            t[r, col[(big_n - k, k)]] = (-1) ** p * (1j) ** k * b
+    return t
+
+
+def test_lg_transform_is_unitary_and_keeps_groups():
+    t = oracle.hg_to_lg(12)
+    assert np.abs(t @ t.conj().T - np.eye(t.shape[0])).max() < 1e-12
+    hg_group = [m + n for m, n in oracle.mode_list(12)]
+    lg_group = [2 * p + abs(l) for p, l in oracle.lg_modes(12)]
+    assert hg_group == lg_group
+    for r in range(t.shape[0]):
+        for c in range(t.shape[1]):
+            if lg_group[r] != hg_group[c]:
+                assert abs(t[r, c]) < 1e-13
+
+
+def test_lg_low_orders_are_the_textbook_combinations():
+    # LG00 = HG00; LG0,+-1 = (HG10 +- i HG01)/sqrt2 (r e^{+-i phi} = x +- i y);
+    # LG10 = -(HG20 + HG02)/sqrt2 (L_1 = 1 - x against H_2 = 4 s^2 - 2)
+    t = oracle.hg_to_lg(3)
+    r2 = 1 / math.sqrt(2)
+    assert abs(t[0, 0] - 1) < 1e-13
+    assert np.abs(t[1, 1:3] - [r2, -1j * r2]).max() < 1e-13          # (0,+1) over HG(1,0), HG(0,1)
+    assert np.abs(t[2, 1:3] - [r2, 1j * r2]).max() < 1e-13           # (0,-1)
+    assert np.abs(t[4, 3:6] - [-r2, 0, -r2]).max() < 1e-13           # (1,0) over HG(2,0), (1,1), (0,2)
+
+
+def test_lg_transform_matches_the_closed_form():
+    assert np.abs(oracle.hg_to_lg(9) - _lg_closed_form(9)).max() < 1e-11
+
+
+def test_lg_transform_matches_fine_grid_overlaps():
+    # a plain Riemann sum of conj(LG) HG on a fine grid (independent of the
+    # Gauss-Hermite rule), for the modes of groups 0..4
+    w = 1.0
+    x = np.linspace(-7, 7, 701) * w
+    dx = x[1] - x[0]
+    xx, yy = np.meshgrid(x, x, indexing="xy")
+    g = 5
+    t = oracle.hg_to_lg(g)
+    for r, (p, l) in enumerate(oracle.lg_modes(g)):
+        a = oracle.lg_function(p, l, xx, yy, w)
+        for c, (m, n) in enumerate(oracle.mode_list(g)):
+            b = np.outer(dh_synth.hg_closed_form(n, x, w), dh_synth.hg_closed_form(m, x, w))
+            assert abs(np.sum(np.conj(a) * b) * dx * dx - t[r, c]) < 1e-9, (p, l, m, n)
+
+
+def test_lg_coefficients_of_a_pure_lg_hologram():
+    # a hologram whose signal is LG mode k alone (its HG expansion is row k of
+    # T conjugated) decomposes to the unit vector e_k in the LG basis
+    cfg = dh_synth.config(0)
+    truth = cfg["truth"]
+    t = oracle.hg_to_lg(truth["max_mg"])
+    for k in (0, 2, 4, 7):
+        c = np.conj(t[k])[None, :]
+        f = dh_synth.forward_hologram(truth, c)
+        got = oracle.apply_basis(oracle.process_frame(f, truth)["coefs_norm"], t)
+        e = np.zeros(t.shape[0])
+        e[k] = 1
+        assert np.abs(got[0] - e).max() < 1e-9, k
+
+
+def test_custom_transform_uses_only_the_plan_modes():
+    rng = np.random.default_rng(3)
+    m = rng.normal(size=(7, 15)) + 1j * rng.normal(size=(7, 15))
+    t = oracle.custom_transform(m, 10)
+    assert t.shape == (7, 10) and np.array_equal(t, m[:, :10])
+    t = oracle.custom_transform(m[:, :4], 10)
+    assert np.array_equal(t[:, :4], m[:, :4]) and not t[:, 4:].any()
+    c = rng.normal(size=(3, 2, 10)) + 1j * rng.normal(size=(3, 2, 10))
+    out = oracle.apply_basis(c, oracle.custom_transform(m, 10))
+    for b in range(3):
+        for q in range(2):
+            assert np.abs(out[b, q] - m[:, :10] @ c[b, q]).max() < 1e-12
