@@ -343,6 +343,34 @@ typedef struct dh_align_report {
 } dh_align_report;
 
 /*
+ * Modal basis of the coefficients ("Basis types", digHoloConfigSetBasisType*):
+ * fields are always decomposed in HG; another basis is one matrix product of
+ * the HG coefficients, c_out = T c_HG, per frame and polarisation, for the raw
+ * and the normalised coefficients alike (T applied after the HG power
+ * normalisation). After dh_set_basis, dh_mode_coefs returns the basis
+ * coefficients (modes = its output count) and dh_transfer_metrics and the
+ * metric goals of dh_autoalign take the matrix in that basis.
+ *   DH_BASIS_HG      the HG coefficients themselves (default);
+ *   DH_BASIS_LG      Laguerre-Gaussian, LG_{p,l} ~ (sqrt2 r/w)^|l| L_p^|l|(2r^2/w^2)
+ *                    e^{-r^2/w^2} e^{i l phi}, unit norm, same waist; group
+ *                    N = 2p + |l| < G, in group order, l = N, N-2, ..., -N inside
+ *                    a group; T[k][j] = <LG_k|HG_j> (unitary, within groups);
+ *   DH_BASIS_CUSTOM  the caller's host matrix `transform`, modes_out x modes_in
+ *                    row-major complex64; columns past the plan's HG modes are
+ *                    not used, missing ones count as zero. The matrix is copied.
+ * modes_out, modes_in and transform are read for DH_BASIS_CUSTOM only. A
+ * server (dh_serve_create) keeps the basis its plans had when it was made.
+ * Errors: DH_ERR_INVALIDHANDLE; DH_ERR_INVALIDARGUMENT (type);
+ * DH_ERR_INVALIDDIMENSION (G = 0, or custom sizes < 1 or modes_out > 65536);
+ * DH_ERR_NULLPOINTER (custom without a matrix); DH_ERR_MEMORYALLOCATION.
+ * Synchronises the device.
+ */
+#define DH_BASIS_HG 0
+#define DH_BASIS_LG 1
+#define DH_BASIS_CUSTOM 2
+int dh_set_basis(dh_handle h, int type, int modes_out, int modes_in, const dh_c64* transform);
+
+/*
  * Polarisation locks of later dh_autoalign calls ("Alignment": PolLockTilt,
  * PolLockDefocus, PolLockBasisWaist): a bitmask of DH_ALIGN_TILT and
  * DH_ALIGN_DEFOCUS; a locked parameter of pol 1 takes pol 0's value after the

@@ -63,15 +63,22 @@ def transfer_matrix(coefs: np.ndarray, pol_independent: bool) -> np.ndarray:
     return a
 
 
-def column_keys(npol: int, group_count: int) -> np.ndarray:
-    """(pol, HG group) of every column of the transfer matrix, as one integer."""
-    groups = np.array([m + n for m, n in mode_list(group_count)], dtype=np.int64)
-    return np.concatenate([p * (group_count + 1) + groups for p in range(npol)])
+def column_keys(npol: int, group_count: int, groups=None) -> np.ndarray:
+    """(pol, mode group) of every column of the transfer matrix, as one
+    integer. The groups are the HG groups m + n of `group_count` groups, or
+    the given group id of each mode (another basis)."""
+    if groups is None:
+        groups = [m + n for m, n in mode_list(group_count)]
+    groups = np.asarray(groups, dtype=np.int64)
+    span = int(groups.max()) + 1 if groups.size else 1
+    return np.concatenate([p * span + groups for p in range(npol)])
 
 
 def transfer_metrics(coefs: np.ndarray, group_count: int, pol_independent: bool = False,
-                     mul_conj_trans: bool = False) -> dict:
-    """The nine metrics of the batch transfer matrix, in dB."""
+                     mul_conj_trans: bool = False, groups=None) -> dict:
+    """The nine metrics of the batch transfer matrix, in dB. `groups`: the
+    mode group of each column mode when the coefficients are not HG (an LG
+    basis keeps the HG groups; a custom basis gives each mode its own)."""
     c = np.asarray(coefs, dtype=np.complex128)
     npol = c.shape[1]
     a = transfer_matrix(c, pol_independent)
@@ -95,7 +102,7 @@ def transfer_metrics(coefs: np.ndarray, group_count: int, pol_independent: bool 
 
     # SNRMG: index k (row or column of D) stands for the mode of column k of A
     # (a frame meant to excite that mode); indices past the modes match nothing
-    keys = column_keys(npol, group_count)
+    keys = column_keys(npol, group_count, groups)
 
     def key(n):
         k = np.arange(n)

@@ -35,15 +35,17 @@ PREC_SPLIT_BF16 = 1
 PREC_SPLIT_FP16 = 2
 METRICS = ["IL", "MDL", "DIAG", "SNRAVG", "DIAGBEST", "DIAGWORST", "SNRBEST", "SNRWORST", "SNRMG"]
 GOAL_CAPTURED = -1
+BASIS_HG, BASIS_LG, BASIS_CUSTOM = 0, 1, 2
 PATH_AUTO = 0
 PATH_FIELD = 1
 PATH_SPECTRAL = 2
 
 EXPORTS = ["dh_plan_check", "dh_plan", "dh_process_batch", "dh_mode_coefs", "dh_get_window",
-           "dh_get_fields", "dh_get_params", "dh_get_plan_info", "dh_set_stage_timing", "dh_stage_times",
-           "dh_autoalign", "dh_get_align_report", "dh_serve_create", "dh_serve_info", "dh_serve_submit",
-           "dh_serve_progress", "dh_serve_replay", "dh_serve_stats", "dh_serve_destroy",
-           "dh_last_error", "dh_transfer_metrics", "dh_set_align_goal", "dh_set_pol_lock", "dh_get_fields16", "dh_fields_to_int16", "dh_destroy"]
+           "dh_get_fields", "dh_get_fields16", "dh_fields_to_int16", "dh_get_params", "dh_get_plan_info",
+           "dh_set_stage_timing", "dh_stage_times", "dh_autoalign", "dh_get_align_report", "dh_set_align_goal",
+           "dh_set_pol_lock", "dh_transfer_metrics", "dh_set_basis", "dh_serve_create", "dh_serve_info",
+           "dh_serve_submit", "dh_serve_progress", "dh_serve_replay", "dh_serve_stats", "dh_serve_destroy",
+           "dh_last_error", "dh_destroy"]
 ALIGN_FULL, ALIGN_TWEAK, ALIGN_ESTIMATE = 0, 1, 2
 ALIGN_TILT, ALIGN_DEFOCUS, ALIGN_WAIST, ALIGN_CENTRE = 1, 2, 4, 8
 # launch stages (DH_STAGE_*): row pass; column pass (FFT along y + window,
@@ -126,6 +128,7 @@ def lib():
         L.dh_transfer_metrics.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double)]
         L.dh_set_align_goal.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int]
         L.dh_set_pol_lock.argtypes = [C.c_int, C.c_uint]
+        L.dh_set_basis.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p]
         L.dh_get_fields16.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
                                       C.POINTER(C.c_int)]
@@ -247,6 +250,16 @@ class Plan:
             if rc != SUCCESS:
                 raise DhError(rc, "dh_mode_coefs")
         return out
+
+    def set_basis(self, basis: int, matrix=None):
+        """BASIS_HG, BASIS_LG, or BASIS_CUSTOM with `matrix` (modes_out x modes_in complex)."""
+        if basis == BASIS_CUSTOM:
+            m = np.ascontiguousarray(np.asarray(matrix, dtype=np.complex64))
+            rc = lib().dh_set_basis(self.handle, basis, m.shape[0], m.shape[1], m.ctypes.data_as(C.c_void_p))
+        else:
+            rc = lib().dh_set_basis(self.handle, int(basis), 0, 0, None)
+        if rc != SUCCESS:
+            raise DhError(rc, "dh_set_basis")
 
     def set_align_goal(self, goal, pol_independent: bool = False, mul_conj_trans: bool = False):
         """Goal of later autoalign calls: GOAL_CAPTURED, a METRICS index or name."""

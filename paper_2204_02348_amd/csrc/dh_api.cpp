@@ -297,6 +297,14 @@ struct Plan {
   rocblas_handle blas = nullptr;
   unsigned lock = 0;                 // DH_ALIGN_TILT / DH_ALIGN_DEFOCUS: pol 1 takes pol 0's value
   char* q16_mem = nullptr;           // int16 fields and scales (dh_get_fields16), made on first use
+  // basis transform after the HG overlap (DH_BASIS_LG / CUSTOM): c_out = T c_HG
+  int basis = DH_BASIS_HG;
+  int bout = 0, bin = 0, bngrp = 0;  // output modes, HG modes used, group ids
+  char* bmem = nullptr;
+  float2* btt = nullptr;             // T transposed, [bin][bout]
+  int* bgrp = nullptr;               // [bout] group id of each output mode
+  float2* bc = nullptr;              // [max_batch][P][bout] raw, then normalised
+  float2* bcn = nullptr;
   int goal = DH_GOAL_CAPTURED;       // alignment goal and its transfer-matrix options
   int goal_indep = 0, goal_aa = 0;
   size_t amem_bytes = 0;
@@ -672,6 +680,7 @@ void release(Plan* pl) {
   if (pl->amem) (void)hipFree(pl->amem);
   if (pl->tm_mem) (void)hipFree(pl->tm_mem);
   if (pl->q16_mem) (void)hipFree(pl->q16_mem);
+  if (pl->bmem) (void)hipFree(pl->bmem);
   if (pl->blas) (void)rocblas_destroy_handle(pl->blas);
   (void)hipSetDevice(dev);
   delete pl;
@@ -799,6 +808,10 @@ int dh_process_batch(dh_handle h, const void* frames, int batch, void* stream) {
       if (hipEventRecord(pl->join[w], pl->str[w]) != hipSuccess || hipStreamWaitEvent(s, pl->join[w], 0) != hipSuccess)
         return set_err(pl, DH_ERR_ERROR);
   }
+  if (pl->basis != DH_BASIS_HG &&
+      dh::launch_basis(pl->ka[0].coefs, pl->ka[0].coefs_norm, pl->g.nmodes, pl->bin, pl->btt, pl->bout, pl->bc,
+                       pl->bcn, batch * pl->params.pol_count, s) != hipSuccess)
+    return set_err(pl, DH_ERR_ERROR);
   if (exports(pl->g, &pl->params) && export_fields(pl, batch, s) != DH_SUCCESS) return set_err(pl, DH_ERR_ERROR);
   pl->last_batch = batch;
   pl->last_stream = s;
@@ -815,11 +828,12 @@ int dh_mode_coefs(dh_handle h, dh_c64* host_out, const dh_c64** dev_out, int* ba
     if (dev_out) *dev_out = nullptr;
     return DH_ERR_INVALIDHANDLE;
   }
-  const int nm = pl->g.nmodes;
+  const bool tr = pl->basis != DH_BASIS_HG;
+  const int nm = tr ? pl->bout : pl->g.nmodes;
   if (batch) *batch = pl->last_batch;
   if (modes) *modes = nm;
   if (pols) *pols = pl->params.pol_count;
-  const float2* src = normalised ? pl->ka[0].coefs_norm : pl->ka[0].coefs;
+  const float2* src = tr ? (normalised ? pl->bcn : pl->bc) : (normalised ? pl->ka[0].coefs_norm : pl->ka[0].coefs);
   if (dev_out) *dev_out = nm > 0 ? (const dh_c64*)src : nullptr;
   if (nm == 0) return set_err(pl, DH_SUCCESS);
   const size_t bytes = (size_t)pl->last_batch * pl->params.pol_count * nm * sizeof(dh_c64);
@@ -945,13 +959,25 @@ double db10(double x) {
 int tm_compute(Plan* pl, int B, int pol_independent, int mul_conj_trans, hipStream_t s, double* out) {
   const int P = pl->params.pol_count, M = pl->g.nmodes;
   if (B < 1 || M < 1) return DH_ERR_ERROR;
+  const int MC = pl->basis != DH_BASIS_HG ? pl->bout : M;   // columns per pol of the matrix
   dh::TmArgs t{};
+  t.grp = nullptr;
   t.c = pl->ka[0].coefs;
   t.modes = pl->ka[0].modes;
   t.B = B; t.P = P; t.M = M;
+  if (pl->basis != DH_BASIS_HG) {
+    // the matrix of the current basis: its coefficients made from the HG ones
+    if (dh::launch_basis(pl->ka[0].coefs, pl->ka[0].coefs_norm, M, pl->bin, pl->btt, pl->bout, pl->bc, pl->bcn,
+                         B * P, s) != hipSuccess)
+      return DH_ERR_ERROR;
+    t.c = pl->bc;
+    t.M = pl->bout;
+    t.grp = pl->bgrp;
+    t.ngrp = pl->bngrp;
+  }
   t.indep = pol_independent ? 1 : 0;
   t.rows = t.indep ? P * B : B;
-  t.cols = P * M;
+  t.cols = P * MC;
   // singular values: eigenvalues of the smaller Gram matrix
   const int byrows = t.rows <= t.cols;
   const int n = byrows ? t.rows : t.cols;
@@ -1423,6 +1449,112 @@ extern "C" int dh_set_align_goal(dh_handle h, int goal, int pol_independent, int
   return set_err(pl, DH_SUCCESS);
 }
 
+namespace {
+// HG -> LG coefficient transform, row-major [M][M]: LG mode (p, l) of group
+// N = 2p + |l| (rows in group order, l = N, N-2, ..., -N) against HG(N-k, k)
+// (columns in the plan's mode order, m = N - k descending):
+//   T = (-1)^p i^k b(n, m, k),  n = p + max(l, 0), m = p + max(-l, 0),
+//   b = sqrt((N-k)! k! / (2^N n! m!)) [t^k] (1 - t)^n (1 + t)^m,
+// the mode-converter expansion of LG in HG, conjugated (T = <LG|HG>). The
+// polynomial coefficient is summed exactly in 64-bit integers.
+std::vector<cd> lg_transform(int G) {
+  const int M = G * (G + 1) / 2;
+  std::vector<cd> t((size_t)M * M, cd(0, 0));
+  auto binom = [](int n, int k) -> long long {
+    if (k < 0 || k > n) return 0;
+    long long r = 1;
+    for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+    return r;
+  };
+  int base = 0;
+  for (int N = 0; N < G; ++N) {
+    for (int r = 0; r <= N; ++r) {
+      const int l = N - 2 * r, p = (N - std::abs(l)) / 2;
+      const int n = p + std::max(l, 0), m = p + std::max(-l, 0);
+      for (int k = 0; k <= N; ++k) {
+        long long poly = 0;
+        for (int a = 0; a <= k; ++a) poly += (a & 1 ? -1 : 1) * binom(n, a) * binom(m, k - a);
+        const double b = std::exp(0.5 * (std::lgamma(N - k + 1.0) + std::lgamma(k + 1.0) - N * std::log(2.0) -
+                                         std::lgamma(n + 1.0) - std::lgamma(m + 1.0))) * (double)poly;
+        static const cd ik[4] = {cd(1, 0), cd(0, 1), cd(-1, 0), cd(0, -1)};
+        t[(size_t)(base + r) * M + base + k] = ((p & 1) ? -1.0 : 1.0) * ik[k & 3] * b;
+      }
+    }
+    base += N + 1;
+  }
+  return t;
+}
+}  // namespace
+
+extern "C" int dh_set_basis(dh_handle h, int type, int modes_out, int modes_in, const dh_c64* transform) {
+  Plan* pl = get(h);
+  if (!pl) return DH_ERR_INVALIDHANDLE;
+  if (type < DH_BASIS_HG || type > DH_BASIS_CUSTOM) return set_err(pl, DH_ERR_INVALIDARGUMENT);
+  const int M = pl->g.nmodes, G = pl->g.G, P = pl->params.pol_count;
+  int mout = 0, mused = 0, ngrp = 0;
+  std::vector<cd> t;                 // row-major [mout][mused]
+  std::vector<int> grp;
+  if (type == DH_BASIS_LG) {
+    if (M == 0) return set_err(pl, DH_ERR_INVALIDDIMENSION);
+    mout = mused = M;
+    ngrp = G;
+    t = lg_transform(G);
+    for (int N = 0; N < G; ++N)
+      for (int r = 0; r <= N; ++r) grp.push_back(N);
+  } else if (type == DH_BASIS_CUSTOM) {
+    if (M == 0 || modes_out < 1 || modes_in < 1 || modes_out > 65536) return set_err(pl, DH_ERR_INVALIDDIMENSION);
+    if (!transform) return set_err(pl, DH_ERR_NULLPOINTER);
+    mout = modes_out;
+    mused = std::min(modes_in, M);
+    ngrp = mout;                     // no group structure: every output mode its own
+    t.resize((size_t)mout * mused);
+    for (int k = 0; k < mout; ++k)
+      for (int j = 0; j < mused; ++j) {
+        const dh_c64& v = transform[(size_t)k * modes_in + j];
+        t[(size_t)k * mused + j] = cd(v.re, v.im);
+      }
+    for (int k = 0; k < mout; ++k) grp.push_back(k);
+  }
+  // work in flight may still read the old tables
+  if (hipDeviceSynchronize() != hipSuccess) return set_err(pl, DH_ERR_ERROR);
+  if (pl->bmem) (void)hipFree(pl->bmem);
+  pl->bmem = nullptr;
+  pl->btt = nullptr; pl->bgrp = nullptr; pl->bc = pl->bcn = nullptr;
+  pl->basis = DH_BASIS_HG;
+  pl->bout = pl->bin = pl->bngrp = 0;
+  ++pl->version;
+  if (type == DH_BASIS_HG) return set_err(pl, DH_SUCCESS);
+  const size_t ott = 0, ogr = align256((size_t)mused * mout * 8);
+  const size_t oc = ogr + align256((size_t)mout * 4), ocn = oc + align256((size_t)pl->max_batch * P * mout * 8);
+  const size_t total = ocn + align256((size_t)pl->max_batch * P * mout * 8);
+  if (hipMalloc(&pl->bmem, total) != hipSuccess) {
+    (void)hipGetLastError();
+    pl->bmem = nullptr;
+    return set_err(pl, DH_ERR_MEMORYALLOCATION);
+  }
+  std::vector<float2> tt((size_t)mused * mout);
+  for (int k = 0; k < mout; ++k)
+    for (int j = 0; j < mused; ++j) {
+      const cd v = t[(size_t)k * mused + j];
+      tt[(size_t)j * mout + k] = make_float2((float)v.real(), (float)v.imag());
+    }
+  if (hipMemcpy(pl->bmem + ott, tt.data(), tt.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(pl->bmem + ogr, grp.data(), grp.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(pl->bmem);
+    pl->bmem = nullptr;
+    return set_err(pl, DH_ERR_ERROR);
+  }
+  pl->btt = (float2*)(pl->bmem + ott);
+  pl->bgrp = (int*)(pl->bmem + ogr);
+  pl->bc = (float2*)(pl->bmem + oc);
+  pl->bcn = (float2*)(pl->bmem + ocn);
+  pl->basis = type;
+  pl->bout = mout;
+  pl->bin = mused;
+  pl->bngrp = ngrp;
+  return set_err(pl, DH_SUCCESS);
+}
+
 extern "C" int dh_fields_to_int16(const dh_c64* fields, int n_fields, long long field_len, short* re, short* im,
                                   float* scale, void* stream) {
   if (n_fields < 0 || field_len < 1) return DH_ERR_INVALIDARGUMENT;
@@ -1514,7 +1646,7 @@ struct Req {
 
 struct Lane {
   int version = -1;              // plan version the arguments and graphs were made for
-  size_t off[6] = {0, 0, 0, 0, 0, 0};
+  size_t off[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   hipStream_t s = nullptr;
   hipEvent_t done = nullptr;
   char* mem = nullptr;
@@ -1532,6 +1664,8 @@ struct Camera {
   std::vector<Lane> lanes;
   size_t lane_bytes = 0;
   int per_result = 0;            // complex values per request: pols x modes
+  int basis = DH_BASIS_HG;       // the plan's basis when the server was made
+  int bout = 0;
 };
 
 struct Server {
@@ -1553,7 +1687,7 @@ Server* sget(dh_server h) {
   return g_servers[h];
 }
 
-size_t lane_layout(const Plan* pl, int mb, size_t off[6]) {
+size_t lane_layout(const Plan* pl, int mb, size_t off[8]) {
   const Geom& g = pl->g;
   const size_t P = pl->params.pol_count, nm = g.nmodes > 0 ? g.nmodes : 1;
   size_t o = 0;
@@ -1565,6 +1699,9 @@ size_t lane_layout(const Plan* pl, int mb, size_t off[6]) {
   off[3] = take((size_t)mb * P * nm * 8);                            // coefs
   off[4] = take((size_t)mb * P * nm * 8);                            // coefs_norm
   off[5] = take((size_t)mb * 8);                                     // frame pointers
+  const size_t nb = pl->basis != DH_BASIS_HG ? pl->bout : 0;
+  off[6] = take((size_t)mb * P * nb * 8);                            // basis coefs
+  off[7] = take((size_t)mb * P * nb * 8);                            // basis coefs, normalised
   return o;
 }
 
@@ -1580,7 +1717,7 @@ void free_lane(Lane& L) {
 }
 
 int make_lane(Server* S, Camera& C, Lane& L) {
-  size_t off[6];
+  size_t off[8];
   lane_layout(C.pl, S->max_batch, off);
   if (hipStreamCreateWithFlags(&L.s, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&L.done, hipEventDisableTiming) != hipSuccess ||
@@ -1591,7 +1728,7 @@ int make_lane(Server* S, Camera& C, Lane& L) {
     free_lane(L);
     return DH_ERR_MEMORYALLOCATION;
   }
-  for (int i = 0; i < 6; ++i) L.off[i] = off[i];
+  for (int i = 0; i < 8; ++i) L.off[i] = off[i];
   return DH_SUCCESS;
 }
 
@@ -1615,16 +1752,22 @@ void lane_args(const Camera& C, Lane& L) {
 }
 
 hipError_t record_batch(const Camera& C, const Lane& L, int n) {
-  const int u16 = C.pl->params.input_dtype == DH_INPUT_U16;
-  const bool spec = C.pl->g.spec;
+  const Plan* pl = C.pl;
+  const int u16 = pl->params.input_dtype == DH_INPUT_U16;
+  const bool spec = pl->g.spec;
   hipError_t e = dh::launch_row(L.k, nullptr, u16, 0, n, L.s);
   if (e == hipSuccess) e = spec ? dh::launch_cspec(L.k, 0, n, L.s) : dh::launch_col(L.k, 0, n, L.s);
   if (e == hipSuccess && !spec && L.k.G > 0) e = dh::launch_fld(L.k, 0, n, L.s);
   if (e == hipSuccess && L.k.G > 0) e = dh::launch_norm(L.k, 0, n, L.s);
+  if (e == hipSuccess && C.basis != DH_BASIS_HG)
+    e = dh::launch_basis(L.k.coefs, L.k.coefs_norm, pl->g.nmodes, pl->bin, pl->btt, pl->bout,
+                         (float2*)(L.mem + L.off[6]), (float2*)(L.mem + L.off[7]), n * pl->params.pol_count, L.s);
   return e;
 }
 
 int launch_lane(Server* S, Camera& C, Lane& L) {
+  // the lanes were sized for the basis the plan had when the server was made
+  if (C.pl->basis != C.basis || (C.basis != DH_BASIS_HG && C.pl->bout != C.bout)) return DH_ERR_ERROR;
   lane_args(C, L);
   const int n = (int)std::min<size_t>(C.pending.size(), (size_t)S->max_batch);
   L.batch.assign(C.pending.begin(), C.pending.begin() + n);
@@ -1651,7 +1794,9 @@ int launch_lane(Server* S, Camera& C, Lane& L) {
   } else if (record_batch(C, L, n) != hipSuccess) {
     return DH_ERR_ERROR;
   }
-  const float2* res = S->normalised ? L.k.coefs_norm : L.k.coefs;
+  const float2* res = C.basis != DH_BASIS_HG
+                          ? (const float2*)(L.mem + L.off[S->normalised ? 7 : 6])
+                          : (S->normalised ? L.k.coefs_norm : L.k.coefs);
   if (C.per_result > 0 &&
       hipMemcpyAsync(L.hres, res, (size_t)n * C.per_result * 8, hipMemcpyDeviceToHost, L.s) != hipSuccess)
     return DH_ERR_ERROR;
@@ -1714,9 +1859,11 @@ int dh_serve_create(const dh_handle* plans, int ncam, int max_batch, size_t hbm_
       delete S;
       return DH_ERR_INVALIDHANDLE;
     }
-    size_t off[6];
+    size_t off[8];
     C.lane_bytes = lane_layout(C.pl, max_batch, off);
-    C.per_result = C.pl->params.pol_count * C.pl->g.nmodes;
+    C.basis = C.pl->basis;
+    C.bout = C.pl->bout;
+    C.per_result = C.pl->params.pol_count * (C.basis != DH_BASIS_HG ? C.bout : C.pl->g.nmodes);
     total += C.lane_bytes;
   }
   if (hbm_budget && total > hbm_budget) {  // not even one lane per camera fits

@@ -7,6 +7,7 @@
 //              the squared singular values)
 //   k_tm_rows  row statistics of the matrix the diagonal metrics are taken on
 //   k_q16      fields to int16 real and imaginary parts with one scale each
+//   k_basis    HG coefficients to another basis (LG, custom): one matrix product
 #include "dh_internal.hpp"
 
 namespace dh {
@@ -92,10 +93,11 @@ __global__ void k_tm_gram(TmArgs t, int by_rows, int n, double2* __restrict__ g)
   g[(size_t)i + (size_t)j * n] = make_double2(re, im);
 }
 
-// mode key of transfer-matrix index k: (pol, HG group); past the modes, unique
+// mode key of transfer-matrix index k: (pol, mode group); past the modes, unique
 __device__ __forceinline__ long tm_key(const TmArgs& t, int k) {
   if (k >= t.P * t.M) return -1 - (long)k;
   const int p = k / t.M;
+  if (t.grp) return (long)p * t.ngrp + t.grp[k - p * t.M];
   const short2 mn = t.modes[k - p * t.M];
   return (long)p * 64 + mn.x + mn.y;
 }
@@ -183,6 +185,39 @@ __global__ void __launch_bounds__(256) k_q16(const float2* __restrict__ f, long 
 hipError_t launch_q16(const float2* fields, int n, long long len, short* re, short* im, float* scale, hipStream_t s) {
   if (n < 1) return hipSuccess;
   hipLaunchKernelGGL(k_q16, dim3(n), dim3(256), 0, s, fields, len, re, im, scale);
+  return hipGetLastError();
+}
+
+// k_basis: grid (n, 2); block (e, y) maps coefficient vector e (a frame and
+// pol) of the raw (y = 0) or normalised (y = 1) HG coefficients to the basis:
+// out[e][k] = sum_{j < nused} tt[j][k] in[e][j], FP32, j in order. tt is T
+// transposed so that the threads of a block read consecutive k.
+__global__ void __launch_bounds__(256) k_basis(const float2* __restrict__ in, const float2* __restrict__ in_norm,
+                                               int nin, int nused, const float2* __restrict__ tt, int nout,
+                                               float2* __restrict__ out, float2* __restrict__ out_norm) {
+  __shared__ float2 c[528];
+  const int e = blockIdx.x;
+  const float2* src = (blockIdx.y ? in_norm : in) + (size_t)e * nin;
+  float2* dst = (blockIdx.y ? out_norm : out) + (size_t)e * nout;
+  for (int j = threadIdx.x; j < nused; j += 256) c[j] = src[j];
+  __syncthreads();
+  for (int k = threadIdx.x; k < nout; k += 256) {
+    float re = 0.f, im = 0.f;
+    for (int j = 0; j < nused; ++j) {
+      const float2 t = tt[(size_t)j * nout + k];
+      const float2 v = c[j];
+      re = fmaf(t.x, v.x, fmaf(-t.y, v.y, re));
+      im = fmaf(t.x, v.y, fmaf(t.y, v.x, im));
+    }
+    dst[k] = make_float2(re, im);
+  }
+}
+
+hipError_t launch_basis(const float2* in, const float2* in_norm, int nin, int nused, const float2* tt, int nout,
+                        float2* out, float2* out_norm, int n, hipStream_t s) {
+  if (n < 1) return hipSuccess;
+  if (nused > 528) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_basis, dim3(n, 2), dim3(256), 0, s, in, in_norm, nin, nused, tt, nout, out, out_norm);
   return hipGetLastError();
 }
 

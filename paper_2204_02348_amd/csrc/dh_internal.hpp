@@ -100,6 +100,11 @@ hipError_t launch_psum(const float2* spec, int nb, int npol, size_t plane, float
 // x^2 I, y^2 I on the coarse grid x = (k - wx/2) px, y = (l - wy/2) py
 // fields to int16 (re, im) with one FP32 scale per field: n fields of len values
 hipError_t launch_q16(const float2* fields, int n, long long len, short* re, short* im, float* scale, hipStream_t s);
+// basis transform of n coefficient vectors (frame x pol): out[e][k] = sum over
+// j < nused of tt[j][k] in[e][j] (in rows of nin values), for the raw and the
+// normalised coefficients
+hipError_t launch_basis(const float2* in, const float2* in_norm, int nin, int nused, const float2* tt, int nout,
+                        float2* out, float2* out_norm, int n, hipStream_t s);
 hipError_t launch_moments(const float2* fields, int n, int wx, int wy, double px, double py, double* out,
                           hipStream_t s);
 // HG tables: out[k][n] in FP32 and, if the split pointers are non-null, the
@@ -111,7 +116,9 @@ hipError_t launch_hg(double pitch, int w, int wpad, double waist, int G, int gp,
 // transfer-matrix metrics (FP64): A from the coefficients [B][P][M]
 struct TmArgs {
   const float2* c;          // raw coefficients of the batch
-  const short2* modes;      // [M] (m, n)
+  const short2* modes;      // [M] (m, n): HG mode keys (pol, m + n) when grp is null
+  const int* grp;           // [M] group id of each mode (key pol * ngrp + id), or null
+  int ngrp;
   int B, P, M;
   int indep;                // pol-independent rows (p B + b), cross-pol entries zero
   int rows, cols;           // B (or P B) x P M

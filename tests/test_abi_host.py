@@ -177,3 +177,7 @@ def test_int16_conversion_rejects_bad_arguments_without_gpu():
     assert L.dh_fields_to_int16(None, 0, 4, None, None, None, None) == dh.SUCCESS
     assert L.dh_fields_to_int16(None, 2, 4, None, None, None, None) == dh.ERR_NULLPOINTER
     assert L.dh_get_fields16(77, None, None, None, None, None, None, None, None, None, None) == dh.ERR_INVALIDHANDLE
+
+
+def test_basis_rejects_bad_handles_without_gpu():
+    assert dh.lib().dh_set_basis(91, dh.BASIS_LG, 0, 0, None) == dh.ERR_INVALIDHANDLE

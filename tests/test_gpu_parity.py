@@ -690,6 +690,102 @@ def test_plan_fields16_match_oracle_fields():
                 assert np.abs(dec - ref[q]).max() <= 0.5 * step + 1e-5 * np.abs(ref[q]).max()
 
 
+# ---------------------------------------------------------------- basis transforms (LG, custom)
+def _basis_run(p, f, basis, matrix=None, chunk=None):
+    torch = _torch()
+    import paper_2204_02348_amd as dh
+    if chunk:
+        os.environ["DH_CHUNK_FRAMES"] = str(chunk)
+    try:
+        plan = dh.Plan(p, max_batch=f.shape[0])
+    finally:
+        os.environ.pop("DH_CHUNK_FRAMES", None)
+    plan.set_basis(basis, matrix)
+    ft = torch.from_numpy(np.ascontiguousarray(f)).cuda()
+    plan.process(ft, f.shape[0], None)
+    out = plan.coefs(False), plan.coefs(True), plan.transfer_metrics()
+    plan.destroy()
+    return out
+
+
+@pytest.mark.parametrize("idx,n,chunk", [(1, 7, 3), (4, 2, None)])
+def test_lg_basis_vs_oracle(idx, n, chunk):
+    """LG coefficients (raw and normalised) against the oracle's HG
+    coefficients times its HG->LG transform (exact Gauss-Hermite overlaps)."""
+    import paper_2204_02348_amd as dh
+    cfg, f, _ = _frames(idx, n=n)
+    p = cfg["params"]
+    raw, nrm, met = _basis_run(p, f, dh.BASIS_LG, chunk=chunk)
+    t = oracle.hg_to_lg(p["max_mg"])
+    _say("LG basis, recipe %d, %d frames" % (idx, n))
+    oc = []
+    for i in range(n):
+        ref = oracle.process_frame(f[i].astype(np.float64), p)
+        oc.append(ref["coefs"])
+        lr, ln = oracle.apply_basis(ref["coefs"], t), oracle.apply_basis(ref["coefs_norm"], t)
+        for q in range(2):
+            assert _rel(raw[i][q].astype(np.complex128), lr[q]) <= TOL
+            assert _rel(nrm[i][q].astype(np.complex128), ln[q]) <= TOL
+    ref = oracle.transfer_metrics(oracle.apply_basis(np.stack(oc), t), p["max_mg"])
+    for k in oracle.METRICS:
+        assert abs(met[k] - ref[k]) <= 1e-3, (k, met[k], ref[k])
+
+
+def test_custom_basis_vs_oracle():
+    """A seeded 17 x 60 custom matrix on a G=9 plan (45 HG modes: columns 45..59
+    unused): coefficients and metrics (each output mode its own group)."""
+    import paper_2204_02348_amd as dh
+    cfg, f, _ = _frames(1, n=5)
+    p = cfg["params"]
+    rng = np.random.default_rng(99)
+    m = (rng.normal(size=(17, 60)) + 1j * rng.normal(size=(17, 60))).astype(np.complex64)
+    raw, nrm, met = _basis_run(p, f, dh.BASIS_CUSTOM, m)
+    t = oracle.custom_transform(m.astype(np.complex128), oracle.mode_count(p["max_mg"]))
+    _say("custom basis 17 x 60, shape", raw.shape)
+    assert raw.shape == (5, 2, 17)
+    oc = []
+    for i in range(5):
+        ref = oracle.process_frame(f[i].astype(np.float64), p)
+        oc.append(ref["coefs"])
+        lr, ln = oracle.apply_basis(ref["coefs"], t), oracle.apply_basis(ref["coefs_norm"], t)
+        for q in range(2):
+            assert _rel(raw[i][q].astype(np.complex128), lr[q]) <= TOL
+            assert _rel(nrm[i][q].astype(np.complex128), ln[q]) <= TOL
+    ref = oracle.transfer_metrics(oracle.apply_basis(np.stack(oc), t), p["max_mg"], groups=np.arange(17))
+    for k in oracle.METRICS:
+        assert abs(met[k] - ref[k]) <= 1e-3, (k, met[k], ref[k])
+
+
+def test_serving_returns_the_basis_coefficients():
+    """A camera whose plan has the LG basis: each served result equals the
+    plan's own LG coefficients of that frame, bit for bit."""
+    torch = _torch()
+    import paper_2204_02348_amd as dh
+    cfg = dh_synth.config(3, 1)
+    f, _ = dh_synth.make_frames(cfg, n_frames=8)
+    plan = dh.Plan(cfg["params"], max_batch=8)
+    plan.set_basis(dh.BASIS_LG)
+    pool = torch.from_numpy(f).cuda()
+    srv = dh.Server([plan], max_batch=8, hbm_budget=4 << 30)
+    per = srv.info(0)[2]
+    assert per == oracle.mode_count(cfg["params"]["max_mg"])
+    n = 40
+    t = np.linspace(0.0, 2e-3, n)
+    cam = np.zeros(n, dtype=np.int32)
+    idx = np.arange(n) % 8
+    res = [np.zeros(per, dtype=np.complex64) for _ in range(n)]
+    torch.cuda.synchronize()
+    srv.replay(t, cam, [pool[i].data_ptr() for i in idx], res)
+    srv.destroy()
+    _say("served %d LG results" % n)
+    for i in range(8):
+        plan.process(pool[i], 1, None)
+        alone = plan.coefs(True)[0].reshape(-1)
+        for k in np.nonzero(idx == i)[0]:
+            assert np.array_equal(res[k], alone), (i, k)
+    plan.destroy()
+
+
 # ---------------------------------------------------------------- transfer-matrix metrics
 @pytest.mark.parametrize("n", [90, 1000])
 def test_transfer_metrics_match_oracle(n):

@@ -118,7 +118,7 @@ TM_MUTATIONS = {
     "diag_amplitude": ("p = np.abs(d) ** 2", "p = np.abs(d)"),
     "aa_star_transposed": ("a @ a.conj().T if mul_conj_trans", "a.conj().T @ a if mul_conj_trans"),
     "snr_row_total": ("diag[i] / (rows[i] - diag[i])", "diag[i] / rows[i]"),
-    "snrmg_ignores_pol": ("p * (group_count + 1) + groups", "groups"),
+    "snrmg_ignores_pol": ("p * span + groups", "groups"),
 }
 
 
