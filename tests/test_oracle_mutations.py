@@ -285,3 +285,53 @@ def test_basis_pins_catch_planted_mistake(name, monkeypatch):
         except (AssertionError, ValueError, IndexError):
             failed += 1
     assert failed > 0, name
+
+
+# ---------------------------------------------------------------- wavelength sweeps and averaging
+SWEEP_SRC = os.path.join(os.path.dirname(SRC), "sweep_avg.py")
+
+SWEEP_MUTATIONS = {
+    "interlace_stride_inputs": ("frames[o, a] = a * n_out + j", "frames[o, a] = a * n_in + j"),
+    "sweep_ignores_repetition": ("frames[o, a] = (i * avg_count + a) * wl_count + w", "frames[o, a] = (i + a) * wl_count + w"),
+    "slow_output_is_fast": ("o = i * wl_count + w if out_order == FAST else w * n_in + i",
+                            "o = i * wl_count + w"),
+    "slow_input_is_fast": ("j = i * wl_count + w if in_order == FAST else w * n_in + i", "j = i * wl_count + w"),
+    "phase_not_removed": ("acc += w[a] * np.exp(-1j * ph[a])", "acc += w[a] * np.exp(1j * ph[a])"),
+    "sum_not_mean": ("return acc / w.shape[0], ph", "return acc, ph"),
+    "centre_wavelength_tilt": ("g = geometry(dict(params, wavelength=lam))", "g = geometry(dict(params))"),
+}
+
+
+def _sweep_mutant(name):
+    import oracle
+    src = open(SWEEP_SRC).read()
+    old, new = SWEEP_MUTATIONS[name]
+    assert src.count(old) == 1, name
+    src = src.replace(old, new).replace(
+        "from .holo_oracle import field_from_window, geometry, mask_bins, overlap, power_normalise, spectrum_window\n",
+        "")
+    mod = types.ModuleType("sweep_mutant_" + name)
+    for k in ("field_from_window", "geometry", "mask_bins", "overlap", "power_normalise", "spectrum_window"):
+        mod.__dict__[k] = getattr(oracle, k)
+    exec(compile(src, SWEEP_SRC + ":" + name, "exec"), mod.__dict__)
+    return mod
+
+
+@pytest.mark.parametrize("name", sorted(SWEEP_MUTATIONS))
+def test_sweep_pins_catch_planted_mistake(name, monkeypatch):
+    import oracle
+    import tests.test_oracle_pins as pins
+    mut = _sweep_mutant(name)
+    for k in ("frame_index_map", "at_wavelength", "average_windows", "process_sweep"):
+        monkeypatch.setattr(oracle, k, getattr(mut, k))
+    failed = 0
+    for t in [pins.test_frame_index_map_follows_the_paper_patterns,
+              pins.test_frame_index_map_output_orders,
+              pins.test_sweep_frame_is_processed_at_its_wavelength,
+              lambda: pins.test_averaging_aligns_the_phase_of_each_repetition(0),
+              lambda: pins.test_averaging_aligns_the_phase_of_each_repetition(1)]:
+        try:
+            t()
+        except (AssertionError, ValueError, IndexError):
+            failed += 1
+    assert failed > 0, name

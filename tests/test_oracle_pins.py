@@ -647,3 +647,111 @@ def test_custom_transform_uses_only_the_plan_modes():
     for b in range(3):
         for q in range(2):
             assert np.abs(out[b, q] - m[:, :10] @ c[b, q]).max() < 1e-12
+
+
+# ---------------------------------------------------------------- wavelength sweeps and averaging
+def _patterns():
+    modes = {"sequential": oracle.SEQUENTIAL, "interlaced": oracle.INTERLACED, "sweep": oracle.SEQUENTIAL_SWEEP}
+    orders = {"fast": oracle.FAST, "slow": oracle.SLOW}
+    out = []
+    for line in open(os.path.join(GOLD, "averaging_patterns.txt")):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        head, frames = line.split(":")
+        mode, n_out, avg, wl, i_o, o_o = head.split()
+        toks = frames.replace("{", " ").replace("}", " ").split()
+        out.append((modes[mode], int(n_out), int(avg), int(wl), orders[i_o], orders[o_o], toks))
+    return out
+
+
+def test_frame_index_map_follows_the_paper_patterns():
+    pats = _patterns()
+    assert len(pats) == 7
+    for mode, n_out, avg, wl, i_o, o_o, toks in pats:
+        lam, idx = oracle.frame_index_map(n_out, avg, mode, wl, i_o, o_o)
+        assert len(toks) == n_out * avg
+        for o in range(n_out):
+            i, w = (o // wl, o % wl) if o_o == oracle.FAST else (o % (n_out // wl), o // (n_out // wl))
+            want = chr(ord("A") + i) + (str(w) if wl > 1 else "")
+            got = [toks[j] for j in idx[o]]
+            assert got == [want] * avg, (mode, o, got, want)
+            assert lam[o] == w
+
+
+def test_frame_index_map_output_orders():
+    # the same inputs in the slow output order: wavelength blocks of inputs
+    lam, idx = oracle.frame_index_map(6, 1, oracle.SEQUENTIAL, 3, oracle.FAST, oracle.SLOW)
+    assert lam.tolist() == [0, 0, 1, 1, 2, 2]
+    assert idx[:, 0].tolist() == [0, 3, 1, 4, 2, 5]
+
+
+def _sweep_truth(lam):
+    cfg = dh_synth.config(1)
+    return dict(cfg["truth"], wavelength=lam, defocus=[0.05, -0.03])
+
+
+def test_sweep_frame_is_processed_at_its_wavelength():
+    # holograms taken at 1.6 % and -1.2 % off the centre wavelength (same tilt
+    # angles): each decomposes exactly at its own wavelength, not at the centre
+    cfg = dh_synth.config(1)
+    params = dict(_sweep_truth(1565e-9))
+    lams = [1565e-9 * 1.016, 1565e-9 * 0.988]
+    rng = np.random.default_rng(7)
+    nm = oracle.mode_count(params["max_mg"])
+    coefs, frames = [], []
+    for i in range(2):                       # two inputs, fast input order
+        c = rng.normal(size=(2, nm)) + 1j * rng.normal(size=(2, nm))
+        c /= np.linalg.norm(c)
+        coefs.append(c)
+        for lam in lams:
+            frames.append(dh_synth.forward_hologram(_sweep_truth(lam), c))
+    frames = np.stack(frames)
+    res = oracle.process_sweep(frames, params, lams, in_order=oracle.FAST, out_order=oracle.SLOW)
+    for o in range(4):                       # slow output: o = w I + i
+        w, i = o // 2, o % 2
+        assert np.abs(res["coefs_norm"][o] - coefs[i]).max() < 1e-9, o
+    # the geometry keeps the centre wavelength's window
+    g0, g1 = oracle.geometry(params), oracle.at_wavelength(params, lams[0])
+    assert (g1["rx"], g1["wx"], g1["px2"]) == (g0["rx"], g0["wx"], g0["px2"])
+    assert abs(g1["pols"][0]["ax"] / g0["pols"][0]["ax"] - 1565e-9 / lams[0]) < 1e-12
+    wrong = oracle.process_sweep(frames[:1], params, [1565e-9])
+    assert np.abs(wrong["coefs_norm"][0] - coefs[0]).max() > 1e-3
+    assert cfg["params"]["max_mg"] == params["max_mg"]
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_averaging_aligns_the_phase_of_each_repetition(mode):
+    # three captures of one field whose reference phase drifted by theta_a:
+    # the average is the first capture, raw and normalised, and the phases
+    # found are the drifts
+    cfg = dh_synth.config(0)
+    truth = cfg["truth"]
+    nm = oracle.mode_count(truth["max_mg"])
+    rng = np.random.default_rng(11)
+    thetas = [0.4, -1.9, 2.6]
+    cs = [rng.normal(size=(1, nm)) + 1j * rng.normal(size=(1, nm)) for _ in range(2)]   # two outputs
+    frames = [None] * 6
+    for o in range(2):
+        for a, th in enumerate(thetas):
+            j = o * 3 + a if mode == oracle.SEQUENTIAL else a * 2 + o
+            frames[j] = dh_synth.forward_hologram(truth, cs[o] * np.exp(1j * th))
+    frames = np.stack(frames)
+    res = oracle.process_sweep(frames, truth, [truth["wavelength"]], avg_count=3, avg_mode=mode)
+    for o in range(2):
+        first = oracle.process_frame(frames[o * 3 if mode == 0 else o], truth)
+        assert np.abs(res["coefs"][o] - first["coefs"]).max() < 1e-9 * np.abs(first["coefs"]).max()
+        assert np.abs(res["coefs_norm"][o] - first["coefs_norm"]).max() < 1e-9
+        d = np.angle(np.exp(1j * (res["phase"][o] - (np.array(thetas) - thetas[0]))))
+        assert np.abs(d).max() < 1e-9
+
+
+def test_average_of_one_frame_is_the_frame():
+    cfg = dh_synth.config(1)
+    f, _ = dh_synth.make_frames(cfg, n_frames=2)
+    p = cfg["params"]
+    res = oracle.process_sweep(f.astype(np.float64), p, [p["wavelength"]])
+    for o in range(2):
+        ref = oracle.process_frame(f[o].astype(np.float64), p)
+        for k in ("window", "field", "coefs", "coefs_norm"):
+            assert np.abs(res[k][o] - ref[k]).max() <= 1e-12 * max(1.0, np.abs(ref[k]).max())
