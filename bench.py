@@ -110,6 +110,36 @@ def time_forms(dh, torch, cfg, ft, B, stream, steps=20, warmup=20):
     return out
 
 
+def time_variants(dh, torch, cfg, ft, B, stream, steps=20, warmup=10):
+    """Input frames/s of the batch variants on the same 1000 frames (G=9,
+    spectral path): a sweep of 4 wavelengths (fast in, slow out), averaging of
+    4 frames per output (sequential), and LG coefficients."""
+    out = {}
+    lams = [cfg["params"]["wavelength"] * (1 + d) for d in (-0.006, -0.002, 0.002, 0.006)]
+    for name in ("sweep4", "avg4", "lg"):
+        plan = dh.Plan(cfg["params"], max_batch=B)
+        n_out = B
+        if name == "sweep4":
+            plan.set_wavelengths(lams, dh.WL_FAST, dh.WL_SLOW)
+        elif name == "avg4":
+            plan.set_averaging(4, dh.AVG_SEQUENTIAL)
+            n_out = B // 4
+        else:
+            plan.set_basis(dh.BASIS_LG)
+        for _ in range(warmup):
+            plan.process(ft, n_out, stream)
+        stream.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            plan.process(ft, n_out, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        plan.destroy()
+        out[name] = {"input_frames_per_s": round(steps * B / (e0.elapsed_time(e1) / 1e3), 1), "outputs": n_out}
+    return out
+
+
 def serving_bench(dh, torch, workers, seconds=10.0, warm=1.0, rate=5000.0, seed=220402348):
     """Serving form on the four uint16 cameras: Poisson arrivals at `rate` per
     camera from resident pools of 64 frames, continuous batching (lanes admitted
@@ -365,6 +395,8 @@ def main():
     plan.destroy()
     if not args.no_forms:
         out["forms"] = time_forms(dh, torch, cfg, ft, B, stream)
+        out["variants"] = time_variants(dh, torch, cfg, ft, B, stream)
+        print("[bench] forms done", file=sys.stderr, flush=True)
     del ft
     if not args.no_serving:
         out["serving"] = serving_bench(dh, torch, workers)

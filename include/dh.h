@@ -156,7 +156,11 @@ int dh_plan(const dh_params* p, int max_batch, size_t hbm_budget, dh_handle* out
  * plan's input_dtype) asynchronously on `stream` (a hipStream_t; NULL = the
  * default stream). The caller keeps ownership of `frames`; they must stay
  * valid and unchanged until the stream has passed this work. batch < 1 is
- * taken as 1; batch > max_batch returns DH_ERR_INVALIDDIMENSION.
+ * taken as 1; batch > max_batch returns DH_ERR_INVALIDDIMENSION. With
+ * averaging (dh_set_averaging) `batch` counts outputs and batch * count
+ * frames are read (DH_ERR_INVALIDDIMENSION above max_batch); with a
+ * wavelength sweep (dh_set_wavelengths) batch must be a multiple of the
+ * wavelength count (else DH_ERR_INVALIDDIMENSION).
  * Errors: DH_ERR_INVALIDHANDLE, DH_ERR_NULLPOINTER, DH_ERR_ERROR (launch).
  */
 int dh_process_batch(dh_handle h, const void* frames, int batch, void* stream);
@@ -369,6 +373,50 @@ typedef struct dh_align_report {
 #define DH_BASIS_LG 1
 #define DH_BASIS_CUSTOM 2
 int dh_set_basis(dh_handle h, int type, int modes_out, int modes_in, const dh_c64* transform);
+
+/*
+ * Wavelength sweeps ("Wavelength", "Input/output wavelength ordering"): the
+ * frames of a batch are taken at `count` wavelengths (m). Each frame is
+ * processed at its own wavelength: its tilt angle and defocus are converted
+ * with that wavelength, while the window radius in bins, the IFFT size and
+ * the field grid stay those of the plan's wavelength (the centre wavelength),
+ * so every output has one shape. A batch of N outputs holds I = N / count
+ * inputs at every wavelength (N must be a multiple of count); output o holds
+ * input i at wavelength w at o = i count + w (out_order DH_WL_FAST) or
+ * o = w I + i (DH_WL_SLOW); without averaging, frame j of the batch holds it
+ * at j = i count + w (in_order DH_WL_FAST) or w I + i (DH_WL_SLOW). count = 0
+ * goes back to every frame at the plan's wavelength.
+ * Errors: DH_ERR_INVALIDHANDLE; DH_ERR_INVALIDDIMENSION (count < 0 or > 4096);
+ * DH_ERR_NULLPOINTER; DH_ERR_INVALIDARGUMENT (a wavelength not > 0 or not
+ * finite, an unknown ordering); DH_ERR_MEMORYALLOCATION. Synchronises the
+ * device.
+ */
+#define DH_WL_FAST 0
+#define DH_WL_SLOW 1
+int dh_set_wavelengths(dh_handle h, const double* lambdas, int count, int in_order, int out_order);
+
+/*
+ * Frame averaging (digHoloSetBatchAvg, "Averaging modes"): each output of
+ * dh_process_batch is the average of `count` frames, so a batch of N outputs
+ * reads N * count frames (N * count <= max_batch). The repetitions of an
+ * output are adjacent (DH_AVG_SEQUENTIAL, AAABBB: frame j count + a), a batch
+ * apart (DH_AVG_INTERLACED, ABCABC: frame a N + j), or whole wavelength sweeps
+ * apart (DH_AVG_SEQUENTIAL_SWEEP, {A}{A}{B}{B}: frame (i count + a) L + w;
+ * the same as sequential for one wavelength), j being the output's frame
+ * index without averaging. Their Fourier windows are added in phase: each
+ * repetition is turned by exp(-i arg sum W_a conj(W_0)) (over both pols and
+ * every window bin; W_0 the first repetition) and the mean is the output's
+ * window; its field and coefficients follow (computed per frame and combined
+ * the same way, which is equal by linearity), the normalised coefficients
+ * from the averaged ones. count = 1 turns averaging off. Sweeps and averaging
+ * are not available to dh_autoalign or to servers (DH_ERR_INVALIDARGUMENT).
+ * Errors: DH_ERR_INVALIDHANDLE; DH_ERR_INVALIDDIMENSION (count < 1 or > 4096);
+ * DH_ERR_INVALIDARGUMENT (mode); DH_ERR_MEMORYALLOCATION.
+ */
+#define DH_AVG_SEQUENTIAL 0
+#define DH_AVG_INTERLACED 1
+#define DH_AVG_SEQUENTIAL_SWEEP 2
+int dh_set_averaging(dh_handle h, int count, int mode);
 
 /*
  * Polarisation locks of later dh_autoalign calls ("Alignment": PolLockTilt,

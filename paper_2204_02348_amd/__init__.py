@@ -36,6 +36,8 @@ PREC_SPLIT_FP16 = 2
 METRICS = ["IL", "MDL", "DIAG", "SNRAVG", "DIAGBEST", "DIAGWORST", "SNRBEST", "SNRWORST", "SNRMG"]
 GOAL_CAPTURED = -1
 BASIS_HG, BASIS_LG, BASIS_CUSTOM = 0, 1, 2
+WL_FAST, WL_SLOW = 0, 1
+AVG_SEQUENTIAL, AVG_INTERLACED, AVG_SEQUENTIAL_SWEEP = 0, 1, 2
 PATH_AUTO = 0
 PATH_FIELD = 1
 PATH_SPECTRAL = 2
@@ -43,7 +45,8 @@ PATH_SPECTRAL = 2
 EXPORTS = ["dh_plan_check", "dh_plan", "dh_process_batch", "dh_mode_coefs", "dh_get_window",
            "dh_get_fields", "dh_get_fields16", "dh_fields_to_int16", "dh_get_params", "dh_get_plan_info",
            "dh_set_stage_timing", "dh_stage_times", "dh_autoalign", "dh_get_align_report", "dh_set_align_goal",
-           "dh_set_pol_lock", "dh_transfer_metrics", "dh_set_basis", "dh_serve_create", "dh_serve_info",
+           "dh_set_pol_lock", "dh_transfer_metrics", "dh_set_basis", "dh_set_wavelengths", "dh_set_averaging",
+           "dh_serve_create", "dh_serve_info",
            "dh_serve_submit", "dh_serve_progress", "dh_serve_replay", "dh_serve_stats", "dh_serve_destroy",
            "dh_last_error", "dh_destroy"]
 ALIGN_FULL, ALIGN_TWEAK, ALIGN_ESTIMATE = 0, 1, 2
@@ -129,6 +132,8 @@ def lib():
         L.dh_set_align_goal.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int]
         L.dh_set_pol_lock.argtypes = [C.c_int, C.c_uint]
         L.dh_set_basis.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p]
+        L.dh_set_wavelengths.argtypes = [C.c_int, C.c_void_p, C.c_int, C.c_int, C.c_int]
+        L.dh_set_averaging.argtypes = [C.c_int, C.c_int, C.c_int]
         L.dh_get_fields16.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
                                       C.POINTER(C.c_int)]
@@ -250,6 +255,19 @@ class Plan:
             if rc != SUCCESS:
                 raise DhError(rc, "dh_mode_coefs")
         return out
+
+    def set_wavelengths(self, lambdas, in_order: int = WL_FAST, out_order: int = WL_FAST):
+        """Per-frame wavelengths of a sweep (empty: the plan's wavelength only)."""
+        lam = np.ascontiguousarray(np.asarray(lambdas, dtype=np.float64).reshape(-1))
+        rc = lib().dh_set_wavelengths(self.handle, lam.ctypes.data_as(C.c_void_p) if lam.size else None, lam.size,
+                                      int(in_order), int(out_order))
+        if rc != SUCCESS:
+            raise DhError(rc, "dh_set_wavelengths")
+
+    def set_averaging(self, count: int, mode: int = AVG_SEQUENTIAL):
+        rc = lib().dh_set_averaging(self.handle, int(count), int(mode))
+        if rc != SUCCESS:
+            raise DhError(rc, "dh_set_averaging")
 
     def set_basis(self, basis: int, matrix=None):
         """BASIS_HG, BASIS_LG, or BASIS_CUSTOM with `matrix` (modes_out x modes_in complex)."""

@@ -305,6 +305,20 @@ struct Plan {
   int* bgrp = nullptr;               // [bout] group id of each output mode
   float2* bc = nullptr;              // [max_batch][P][bout] raw, then normalised
   float2* bcn = nullptr;
+  // wavelength sweep (dh_set_wavelengths) and frame averaging (dh_set_averaging)
+  int nlam = 0;                      // 0: every frame at the plan's wavelength
+  int in_order = 0, out_order = 0;   // DH_WL_FAST / DH_WL_SLOW
+  int avg = 1, avg_mode = 0;
+  std::vector<double> lams;
+  std::vector<PolGeom> lam_geom;     // [nlam][P]
+  struct LamTab { size_t mrow, rhox, rhoy, tx, ty, xs, ys, ex, ey; };
+  std::vector<LamTab> lam_tab;       // [nlam][P] offsets in lmem
+  char* lmem = nullptr;
+  // staging of the input frames' results before the outputs are combined
+  char* smem = nullptr;
+  const void** sptr = nullptr;       // [max_batch] frame of each staged position
+  float2 *sc = nullptr, *scn = nullptr, *swin = nullptr, *sfld = nullptr;
+  double2* rot = nullptr;            // [max_batch] phase factor of each repetition
   int goal = DH_GOAL_CAPTURED;       // alignment goal and its transfer-matrix options
   int goal_indep = 0, goal_aa = 0;
   size_t amem_bytes = 0;
@@ -450,35 +464,79 @@ std::vector<float2> export_axis(int uhi, int nbox, int w, int f, double tilt_bin
   return t;
 }
 
+// Host tables of polarisation q with geometry P (its wavelength is p's):
+// the window rows, the centre ramps and the tilt/defocus phases of the field
+// path; with spec, the spectral path tables; with exp, the mode-0 export
+// tables.
+struct PolTables {
+  std::vector<int2> mrow;
+  std::vector<float2> rhox, rhoy, tx, ty, xs, ys, ex, ey;
+};
+
+PolTables pol_tables(const Geom& g, const PolGeom& P, const dh_params* p, int q, bool spec, bool exp) {
+  PolTables t;
+  const double pix = p->pixel_size, lam = p->wavelength;
+  const int byq = P.vhi - P.vlo + 1;
+  t.mrow.assign(g.by, make_int2(1, 0));
+  for (int i = 0; i < byq; ++i)
+    if (P.row_lo[i] <= P.row_hi[i]) t.mrow[i] = make_int2(P.uhi - P.row_hi[i], P.uhi - P.row_lo[i]);
+  t.rhox.resize(g.bx);
+  t.rhoy.resize(g.by);
+  t.tx.resize(g.wx);
+  t.ty.resize(g.wy);
+  for (int j = 0; j < g.bx; ++j) {
+    const int u = P.uhi - j;
+    const cd r = std::exp(cd(0, 2.0 * kPi * u * P.dx / (pix * g.nx)));
+    t.rhox[j] = make_float2((float)r.real(), (float)r.imag());
+  }
+  const double inv = 1.0 / ((double)g.nx * g.ny);
+  for (int i = 0; i < g.by; ++i) {
+    const int v = P.vhi - i;
+    const cd r = std::exp(cd(0, 2.0 * kPi * v * P.dy / (pix * g.ny))) * inv;
+    t.rhoy[i] = make_float2((float)r.real(), (float)r.imag());
+  }
+  for (int k = 0; k < g.wx; ++k) {
+    const double x = (k - g.wx / 2.0) * g.pxp;
+    const double ph = 2.0 * kPi * P.ax * (k - g.wx / 2.0) / g.wx + kPi * p->defocus[q] * x * x / lam;
+    t.tx[k] = make_float2((float)std::cos(ph), (float)std::sin(ph));
+  }
+  for (int l = 0; l < g.wy; ++l) {
+    const double y = (l - g.wy / 2.0) * g.pyp;
+    const double ph = 2.0 * kPi * P.ay * (l - g.wy / 2.0) / g.wy + kPi * p->defocus[q] * y * y / lam;
+    t.ty[l] = make_float2((float)std::cos(ph), (float)std::sin(ph));
+  }
+  if (spec) {
+    // the overlap's quadrature runs over the field grid: the Fourier-window
+    // size in IFFT mode 1, the FFT size in mode 0
+    const double waist = p->waist > 0 ? p->waist : 1.0;
+    const std::vector<double> hx = hg_host(g.fpx, g.fx, waist, g.G), hy = hg_host(g.fpy, g.fy, waist, g.G);
+    t.xs = spectral_axis(g.bx, g.bx, g.gp, g.G, P.uhi, g.fx, g.fpx, P.ax, p->defocus[q], lam, P.dx, pix, g.nx, 1.0,
+                         hx);
+    t.ys = spectral_axis(g.by, g.wyp, g.gp, g.G, P.vhi, g.fy, g.fpy, P.ay, p->defocus[q], lam, P.dy, pix, g.ny,
+                         inv, hy);
+  }
+  if (exp) {
+    t.ex = export_axis(P.uhi, P.uhi - P.ulo + 1, g.wx, g.fx, P.ax, p->defocus[q], lam, g.fpx, 1.0, false);
+    t.ey = export_axis(P.vhi, P.vhi - P.vlo + 1, g.wy, g.fy, P.ay, p->defocus[q], lam, g.fpy, inv, true);
+  }
+  return t;
+}
+
+template <typename T>
+bool upload(char* base, size_t off, const std::vector<T>& v) {
+  return v.empty() || hipMemcpy(base + off, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) == hipSuccess;
+}
+
 int build_spectral(Plan* pl) {
   const Geom& g = pl->g;
   if (!g.spec) return DH_SUCCESS;
   const dh_params* p = &pl->params;
   const Layout& L = pl->L;
-  const double waist = p->waist > 0 ? p->waist : 1.0;
-  // the overlap's quadrature runs over the field grid: the Fourier-window
-  // size in IFFT mode 1, the FFT size in mode 0
-  const std::vector<double> hx = hg_host(g.fpx, g.fx, waist, g.G), hy = hg_host(g.fpy, g.fy, waist, g.G);
   for (int q = 0; q < p->pol_count; ++q) {
-    const PolGeom& P = g.pol[q];
-    const std::vector<float2> xs =
-        spectral_axis(g.bx, g.bx, g.gp, g.G, P.uhi, g.fx, g.fpx, P.ax, p->defocus[q], p->wavelength, P.dx,
-                      p->pixel_size, g.nx, 1.0, hx);
-    const std::vector<float2> ys =
-        spectral_axis(g.by, g.wyp, g.gp, g.G, P.vhi, g.fy, g.fpy, P.ay, p->defocus[q], p->wavelength, P.dy,
-                      p->pixel_size, g.ny, 1.0 / ((double)g.nx * g.ny), hy);
-    if (hipMemcpy(pl->mem + L.pol_xs[q], xs.data(), xs.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(pl->mem + L.pol_ys[q], ys.data(), ys.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess)
+    const PolTables t = pol_tables(g, g.pol[q], p, q, true, exports(g, p));
+    if (!upload(pl->mem, L.pol_xs[q], t.xs) || !upload(pl->mem, L.pol_ys[q], t.ys) ||
+        (exports(g, p) && (!upload(pl->mem, L.pol_ex[q], t.ex) || !upload(pl->mem, L.pol_ey[q], t.ey))))
       return DH_ERR_ERROR;
-    if (exports(g, p)) {
-      const std::vector<float2> ex = export_axis(P.uhi, P.uhi - P.ulo + 1, g.wx, g.fx, P.ax, p->defocus[q],
-                                                 p->wavelength, g.fpx, 1.0, false);
-      const std::vector<float2> ey = export_axis(P.vhi, P.vhi - P.vlo + 1, g.wy, g.fy, P.ay, p->defocus[q],
-                                                 p->wavelength, g.fpy, 1.0 / ((double)g.nx * g.ny), true);
-      if (hipMemcpy(pl->mem + L.pol_ex[q], ex.data(), ex.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess ||
-          hipMemcpy(pl->mem + L.pol_ey[q], ey.data(), ey.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess)
-        return DH_ERR_ERROR;
-    }
   }
   return DH_SUCCESS;
 }
@@ -500,40 +558,13 @@ int build_tables(Plan* pl, bool hg = true, bool spec = true) {
   for (int gg = 0; gg < g.G; ++gg)
     for (int m = gg; m >= 0; --m) modes.push_back(make_short2((short)m, (short)(gg - m)));
   put(host, L.modes, modes);
-  const double pix = p->pixel_size, lam = p->wavelength;
   for (int q = 0; q < p->pol_count; ++q) {
-    const PolGeom& P = g.pol[q];
-    const int byq = P.vhi - P.vlo + 1;
-    std::vector<int2> mrow(g.by, make_int2(1, 0));
-    for (int i = 0; i < byq; ++i)
-      if (P.row_lo[i] <= P.row_hi[i]) mrow[i] = make_int2(P.uhi - P.row_hi[i], P.uhi - P.row_lo[i]);
-    std::vector<float2> rhox(g.bx), rhoy(g.by), tx(g.wx), ty(g.wy);
-    for (int j = 0; j < g.bx; ++j) {
-      const int u = P.uhi - j;
-      const cd r = std::exp(cd(0, 2.0 * kPi * u * P.dx / (pix * g.nx)));
-      rhox[j] = make_float2((float)r.real(), (float)r.imag());
-    }
-    const double inv = 1.0 / ((double)g.nx * g.ny);
-    for (int i = 0; i < g.by; ++i) {
-      const int v = P.vhi - i;
-      const cd r = std::exp(cd(0, 2.0 * kPi * v * P.dy / (pix * g.ny))) * inv;
-      rhoy[i] = make_float2((float)r.real(), (float)r.imag());
-    }
-    for (int k = 0; k < g.wx; ++k) {
-      const double x = (k - g.wx / 2.0) * g.pxp;
-      const double ph = 2.0 * kPi * P.ax * (k - g.wx / 2.0) / g.wx + kPi * p->defocus[q] * x * x / lam;
-      tx[k] = make_float2((float)std::cos(ph), (float)std::sin(ph));
-    }
-    for (int l = 0; l < g.wy; ++l) {
-      const double y = (l - g.wy / 2.0) * g.pyp;
-      const double ph = 2.0 * kPi * P.ay * (l - g.wy / 2.0) / g.wy + kPi * p->defocus[q] * y * y / lam;
-      ty[l] = make_float2((float)std::cos(ph), (float)std::sin(ph));
-    }
-    put(host, L.pol_mrow[q], mrow);
-    put(host, L.pol_rhox[q], rhox);
-    put(host, L.pol_rhoy[q], rhoy);
-    put(host, L.pol_tx[q], tx);
-    put(host, L.pol_ty[q], ty);
+    const PolTables t = pol_tables(g, g.pol[q], p, q, false, false);
+    put(host, L.pol_mrow[q], t.mrow);
+    put(host, L.pol_rhox[q], t.rhox);
+    put(host, L.pol_rhoy[q], t.rhoy);
+    put(host, L.pol_tx[q], t.tx);
+    put(host, L.pol_ty[q], t.ty);
   }
   if (hipMemcpy(pl->mem, host.data(), L.total_tables, hipMemcpyHostToDevice) != hipSuccess) return DH_ERR_ERROR;
   if (spec) {
@@ -633,25 +664,29 @@ bool blas_on(Plan* pl, hipStream_t s) {
 // E = Ey W Ex per frame and pol (the export tables), as two complex GEMMs
 // per pol over groups of frames; row-major arrays are read as transposed
 // column-major ones: T^T = Ex^T W^T, then E^T = T^T Ey^T.
-int export_fields(Plan* pl, int batch, hipStream_t s) {
+int export_fields(Plan* pl, int first, int count, int stride, const char* const ex[2], const char* const ey[2],
+                  hipStream_t s) {
   const Geom& g = pl->g;
   const int P = pl->params.pol_count;
   if (!blas_on(pl, s)) return DH_ERR_ERROR;
   const rocblas_float_complex one = {1.f, 0.f}, zero = {0.f, 0.f};
   auto cx = [&](size_t off) { return (rocblas_float_complex*)(pl->mem + off); };
   const int grp = export_chunk(g, &pl->params, pl->max_batch);
-  for (int b0 = 0; b0 < batch; b0 += grp) {
-    const int nb = std::min(grp, batch - b0);
+  for (int c0 = 0; c0 < count; c0 += grp) {
+    const int nb = std::min(grp, count - c0);
+    const size_t b0 = (size_t)first + (size_t)c0 * stride;   // output frame of the group's first field
     for (int q = 0; q < P; ++q) {
-      const rocblas_float_complex* win = cx(pl->L.window) + ((size_t)b0 * P + q) * g.wy * g.wx;
+      const rocblas_float_complex* win = cx(pl->L.window) + (b0 * P + q) * g.wy * g.wx;
       rocblas_float_complex* t = cx(pl->L.export_t) + (size_t)q * g.wy * g.fx;
-      rocblas_float_complex* f = cx(pl->L.fields) + ((size_t)b0 * P + q) * g.fy * g.fx;
+      rocblas_float_complex* f = cx(pl->L.fields) + (b0 * P + q) * g.fy * g.fx;
       if (rocblas_cgemm_strided_batched(pl->blas, rocblas_operation_none, rocblas_operation_none, g.fx, g.wy, g.wx,
-                                        &one, cx(pl->L.pol_ex[q]), g.fx, 0, win, g.wx, (rocblas_stride)P * g.wy * g.wx,
-                                        &zero, t, g.fx, (rocblas_stride)P * g.wy * g.fx, nb) != rocblas_status_success ||
+                                        &one, (const rocblas_float_complex*)ex[q], g.fx, 0, win, g.wx,
+                                        (rocblas_stride)stride * P * g.wy * g.wx, &zero, t, g.fx,
+                                        (rocblas_stride)P * g.wy * g.fx, nb) != rocblas_status_success ||
           rocblas_cgemm_strided_batched(pl->blas, rocblas_operation_none, rocblas_operation_none, g.fx, g.fy, g.wy,
-                                        &one, t, g.fx, (rocblas_stride)P * g.wy * g.fx, cx(pl->L.pol_ey[q]), g.wy, 0,
-                                        &zero, f, g.fx, (rocblas_stride)P * g.fy * g.fx, nb) != rocblas_status_success)
+                                        &one, t, g.fx, (rocblas_stride)P * g.wy * g.fx,
+                                        (const rocblas_float_complex*)ey[q], g.wy, 0, &zero, f, g.fx,
+                                        (rocblas_stride)stride * P * g.fy * g.fx, nb) != rocblas_status_success)
         return DH_ERR_ERROR;
     }
   }
@@ -681,6 +716,8 @@ void release(Plan* pl) {
   if (pl->tm_mem) (void)hipFree(pl->tm_mem);
   if (pl->q16_mem) (void)hipFree(pl->q16_mem);
   if (pl->bmem) (void)hipFree(pl->bmem);
+  if (pl->lmem) (void)hipFree(pl->lmem);
+  if (pl->smem) (void)hipFree(pl->smem);
   if (pl->blas) (void)rocblas_destroy_handle(pl->blas);
   (void)hipSetDevice(dev);
   delete pl;
@@ -765,6 +802,127 @@ int dh_plan(const dh_params* p, int max_batch, size_t hbm_budget, dh_handle* out
   return DH_SUCCESS;
 }
 
+namespace {
+
+// the path over frames [b0, b0 + nb) with arguments a on stream st
+bool launch_path(Plan* pl, const dh::KArgs& a, const void* frames, int u16, int b0, int nb, hipStream_t st) {
+  bool ok = timed_event(pl, st, DH_STAGE_FFT, true) == hipSuccess &&
+            dh::launch_row(a, frames, u16, b0, nb, st) == hipSuccess &&
+            timed_event(pl, st, DH_STAGE_FFT, false) == hipSuccess &&
+            timed_event(pl, st, DH_STAGE_CROP, true) == hipSuccess &&
+            (pl->g.spec ? dh::launch_cspec(a, b0, nb, st) : dh::launch_col(a, b0, nb, st)) == hipSuccess &&
+            timed_event(pl, st, DH_STAGE_CROP, false) == hipSuccess;
+  if (ok && !pl->g.spec && (a.G > 0 || a.fields))
+    ok = timed_event(pl, st, DH_STAGE_FIELD, true) == hipSuccess && dh::launch_fld(a, b0, nb, st) == hipSuccess &&
+         timed_event(pl, st, DH_STAGE_FIELD, false) == hipSuccess;
+  if (ok && a.G > 0)
+    ok = timed_event(pl, st, DH_STAGE_NORM, true) == hipSuccess && dh::launch_norm(a, b0, nb, st) == hipSuccess &&
+         timed_event(pl, st, DH_STAGE_NORM, false) == hipSuccess;
+  return ok;
+}
+
+// A run of frames [b0, b0 + n) processed with one wavelength's tables (lam
+// < 0: the plan's own) into the staging buffers (staged) or the outputs.
+struct Seg {
+  int b0, n, lam;
+  bool staged;
+};
+
+// the segments' chunks round robin over the workspaces and internal streams,
+// after the caller's prior work; the caller's stream continues after all
+int run_segments(Plan* pl, const void* frames, const std::vector<Seg>& segs, hipStream_t s) {
+  const int u16 = pl->params.input_dtype == DH_INPUT_U16;
+  int nchunks = 0;
+  for (const Seg& g : segs) nchunks += (g.n + pl->chunk - 1) / pl->chunk;
+  const int nws = std::max(1, std::min(pl->nws, nchunks));
+  if (nws > 1) {
+    if (hipEventRecord(pl->fork, s) != hipSuccess) return DH_ERR_ERROR;
+    for (int w = 0; w < nws; ++w)
+      if (hipStreamWaitEvent(pl->str[w], pl->fork, 0) != hipSuccess) return DH_ERR_ERROR;
+  }
+  int c = 0;
+  for (const Seg& sg : segs) {
+    for (int b0 = sg.b0; b0 < sg.b0 + sg.n; b0 += pl->chunk, ++c) {
+      const int nb = std::min(pl->chunk, sg.b0 + sg.n - b0);
+      const int w = c % nws;
+      dh::KArgs a = pl->ka[w];
+      if (sg.staged) {
+        a.fptr = pl->sptr;
+        a.coefs = pl->sc;
+        a.coefs_norm = pl->scn;
+        a.window = pl->swin;
+        a.fields = pl->sfld;
+      }
+      if (sg.lam >= 0) {
+        for (int q = 0; q < pl->params.pol_count; ++q) {
+          const PolGeom& P = pl->lam_geom[(size_t)sg.lam * 2 + q];
+          const Plan::LamTab& t = pl->lam_tab[(size_t)sg.lam * 2 + q];
+          dh::PolTab& pt = a.pol[q];
+          pt.x0 = P.x0; pt.y0 = P.y0;
+          pt.k0 = -P.uhi; pt.ky0 = -P.vhi;
+          pt.bxq = P.uhi - P.ulo + 1; pt.byq = P.vhi - P.vlo + 1;
+          pt.mrow = (const int2*)(pl->lmem + t.mrow);
+          pt.rhox = (const float2*)(pl->lmem + t.rhox);
+          pt.rhoy = (const float2*)(pl->lmem + t.rhoy);
+          pt.tx = (const float2*)(pl->lmem + t.tx);
+          pt.ty = (const float2*)(pl->lmem + t.ty);
+          if (pl->g.spec) {
+            pt.xs = (const float2*)(pl->lmem + t.xs);
+            pt.ys = (const float2*)(pl->lmem + t.ys);
+          }
+        }
+      }
+      if (!launch_path(pl, a, frames, u16, b0, nb, nws > 1 ? pl->str[w] : s)) return DH_ERR_ERROR;
+    }
+  }
+  if (nws > 1) {
+    for (int w = 0; w < nws; ++w)
+      if (hipEventRecord(pl->join[w], pl->str[w]) != hipSuccess || hipStreamWaitEvent(s, pl->join[w], 0) != hipSuccess)
+        return DH_ERR_ERROR;
+  }
+  return DH_SUCCESS;
+}
+
+bool sweeping(const Plan* pl) { return pl->nlam > 0 || pl->avg > 1; }
+
+// Wavelength sweep and/or averaging: the batch's batch * avg frames are
+// staged wavelength by wavelength (position (w I + i) A + a for input i at
+// wavelength w, repetition a), then combined into the outputs in the output
+// ordering (the repetitions phase-aligned and averaged).
+int process_sweep(Plan* pl, const void* frames, int batch, hipStream_t s) {
+  const Geom& g = pl->g;
+  const int P = pl->params.pol_count, L = std::max(pl->nlam, 1), A = pl->avg;
+  if (batch % L) return DH_ERR_INVALIDDIMENSION;
+  const int I = batch / L, n_in = batch * A;
+  if (n_in > pl->max_batch) return DH_ERR_INVALIDDIMENSION;
+  const size_t fbytes = (size_t)pl->params.frame_w * pl->params.frame_h *
+                        (pl->params.input_dtype == DH_INPUT_U16 ? 2 : 4);
+  const size_t plane = (size_t)g.wy * g.wx;
+  if (dh::launch_fptr((const char*)frames, fbytes, batch, L, I, A, pl->avg_mode, pl->in_order, pl->sptr, s) !=
+          hipSuccess ||
+      (pl->swin && dh::launch_zero(pl->swin, (size_t)n_in * P * plane, s) != hipSuccess))
+    return DH_ERR_ERROR;
+  std::vector<Seg> segs;
+  for (int w = 0; w < L; ++w) segs.push_back({w * I * A, I * A, pl->nlam > 0 ? w : -1, true});
+  int e = run_segments(pl, frames, segs, s);
+  if (e != DH_SUCCESS) return e;
+  const dh::KArgs& a0 = pl->ka[0];
+  const dh::Comb cb{L, I, A, pl->out_order};
+  if (A > 1 && dh::launch_avg_rot(pl->swin, P * plane, cb, batch, pl->rot, s) != hipSuccess) return DH_ERR_ERROR;
+  const double2* rot = A > 1 ? pl->rot : nullptr;
+  if (g.G > 0 && dh::launch_comb_coefs(pl->sc, pl->scn, rot, P * g.nmodes, cb, batch, a0.coefs, a0.coefs_norm, s) !=
+                     hipSuccess)
+    return DH_ERR_ERROR;
+  if (a0.window && dh::launch_comb_plane(pl->swin, rot, P * plane, cb, batch, a0.window, s) != hipSuccess)
+    return DH_ERR_ERROR;
+  if (pl->sfld && dh::launch_comb_plane(pl->sfld, rot, P * plane, cb, batch, (float2*)(pl->mem + pl->L.fields), s) !=
+                      hipSuccess)
+    return DH_ERR_ERROR;
+  return DH_SUCCESS;
+}
+
+}  // namespace
+
 int dh_process_batch(dh_handle h, const void* frames, int batch, void* stream) {
   Plan* pl = get(h);
   if (!pl) return DH_ERR_INVALIDHANDLE;
@@ -772,47 +930,36 @@ int dh_process_batch(dh_handle h, const void* frames, int batch, void* stream) {
   if (batch < 1) batch = 1;
   if (batch > pl->max_batch) return set_err(pl, DH_ERR_INVALIDDIMENSION);
   hipStream_t s = (hipStream_t)stream;
-  const int u16 = pl->params.input_dtype == DH_INPUT_U16;
-  const dh::KArgs& a0 = pl->ka[0];
-  if (a0.window && dh::launch_zero(a0.window, (size_t)batch * a0.npol * a0.wy * a0.wx, s) != hipSuccess)
-    return set_err(pl, DH_ERR_ERROR);
-  const int nchunks = (batch + pl->chunk - 1) / pl->chunk;
-  const int nws = std::min(pl->nws, nchunks);
-  if (nws > 1) {  // fork: every internal stream starts after the caller's prior work
-    if (hipEventRecord(pl->fork, s) != hipSuccess) return set_err(pl, DH_ERR_ERROR);
-    for (int w = 0; w < nws; ++w)
-      if (hipStreamWaitEvent(pl->str[w], pl->fork, 0) != hipSuccess) return set_err(pl, DH_ERR_ERROR);
-  }
-  for (int c = 0; c < nchunks; ++c) {
-    const int b0 = c * pl->chunk;
-    const int nb = std::min(pl->chunk, batch - b0);
-    const int w = c % nws;
-    const dh::KArgs& a = pl->ka[w];
-    hipStream_t st = nws > 1 ? pl->str[w] : s;
-    bool ok = timed_event(pl, st, DH_STAGE_FFT, true) == hipSuccess &&
-              dh::launch_row(a, frames, u16, b0, nb, st) == hipSuccess &&
-              timed_event(pl, st, DH_STAGE_FFT, false) == hipSuccess &&
-              timed_event(pl, st, DH_STAGE_CROP, true) == hipSuccess &&
-              (pl->g.spec ? dh::launch_cspec(a, b0, nb, st) : dh::launch_col(a, b0, nb, st)) == hipSuccess &&
-              timed_event(pl, st, DH_STAGE_CROP, false) == hipSuccess;
-    if (ok && !pl->g.spec && (a.G > 0 || a.fields))
-      ok = timed_event(pl, st, DH_STAGE_FIELD, true) == hipSuccess && dh::launch_fld(a, b0, nb, st) == hipSuccess &&
-           timed_event(pl, st, DH_STAGE_FIELD, false) == hipSuccess;
-    if (ok && a.G > 0)
-      ok = timed_event(pl, st, DH_STAGE_NORM, true) == hipSuccess && dh::launch_norm(a, b0, nb, st) == hipSuccess &&
-           timed_event(pl, st, DH_STAGE_NORM, false) == hipSuccess;
-    if (!ok) return set_err(pl, DH_ERR_ERROR);
-  }
-  if (nws > 1) {  // join: the caller's stream continues after every chunk
-    for (int w = 0; w < nws; ++w)
-      if (hipEventRecord(pl->join[w], pl->str[w]) != hipSuccess || hipStreamWaitEvent(s, pl->join[w], 0) != hipSuccess)
-        return set_err(pl, DH_ERR_ERROR);
+  const Geom& g = pl->g;
+  const int P = pl->params.pol_count;
+  if (sweeping(pl)) {
+    const int e = process_sweep(pl, frames, batch, s);
+    if (e != DH_SUCCESS) return set_err(pl, e);
+  } else {
+    const dh::KArgs& a0 = pl->ka[0];
+    if (a0.window && dh::launch_zero(a0.window, (size_t)batch * a0.npol * a0.wy * a0.wx, s) != hipSuccess)
+      return set_err(pl, DH_ERR_ERROR);
+    if (run_segments(pl, frames, {{0, batch, -1, false}}, s) != DH_SUCCESS) return set_err(pl, DH_ERR_ERROR);
   }
   if (pl->basis != DH_BASIS_HG &&
-      dh::launch_basis(pl->ka[0].coefs, pl->ka[0].coefs_norm, pl->g.nmodes, pl->bin, pl->btt, pl->bout, pl->bc,
-                       pl->bcn, batch * pl->params.pol_count, s) != hipSuccess)
+      dh::launch_basis(pl->ka[0].coefs, pl->ka[0].coefs_norm, g.nmodes, pl->bin, pl->btt, pl->bout, pl->bc, pl->bcn,
+                       batch * P, s) != hipSuccess)
     return set_err(pl, DH_ERR_ERROR);
-  if (exports(pl->g, &pl->params) && export_fields(pl, batch, s) != DH_SUCCESS) return set_err(pl, DH_ERR_ERROR);
+  if (exports(g, &pl->params)) {
+    // each output's fields from its window, with its wavelength's tables
+    const int L = std::max(pl->nlam, 1), I = batch / L;
+    for (int w = 0; w < L; ++w) {
+      const char* ex[2] = {nullptr, nullptr};
+      const char* ey[2] = {nullptr, nullptr};
+      for (int q = 0; q < P; ++q) {
+        ex[q] = pl->nlam > 0 ? pl->lmem + pl->lam_tab[(size_t)w * 2 + q].ex : pl->mem + pl->L.pol_ex[q];
+        ey[q] = pl->nlam > 0 ? pl->lmem + pl->lam_tab[(size_t)w * 2 + q].ey : pl->mem + pl->L.pol_ey[q];
+      }
+      const bool fast = pl->nlam > 0 && pl->out_order == DH_WL_FAST;
+      const int first = pl->nlam > 0 ? (fast ? w : w * I) : 0, count = pl->nlam > 0 ? I : batch;
+      if (export_fields(pl, first, count, fast ? L : 1, ex, ey, s) != DH_SUCCESS) return set_err(pl, DH_ERR_ERROR);
+    }
+  }
   pl->last_batch = batch;
   pl->last_stream = s;
   return set_err(pl, DH_SUCCESS);
@@ -1143,7 +1290,8 @@ extern "C" float dh_autoalign(dh_handle h, const void* frames, int batch, int mo
   if (!frames) return (set_err(pl, DH_ERR_NULLPOINTER), -FLT_MAX);
   if (batch < 1) batch = 1;
   if (batch > pl->max_batch) return (set_err(pl, DH_ERR_INVALIDDIMENSION), -FLT_MAX);
-  if (mode < DH_ALIGN_FULL || mode > DH_ALIGN_ESTIMATE || (what & ~(DH_ALIGN_TILT | DH_ALIGN_DEFOCUS | DH_ALIGN_WAIST | DH_ALIGN_CENTRE)) ||
+  if (sweeping(pl) || mode < DH_ALIGN_FULL || mode > DH_ALIGN_ESTIMATE ||
+      (what & ~(DH_ALIGN_TILT | DH_ALIGN_DEFOCUS | DH_ALIGN_WAIST | DH_ALIGN_CENTRE)) ||
       (mode != DH_ALIGN_ESTIMATE && pl->g.G == 0) || !(tol >= 0.f))
     return (set_err(pl, DH_ERR_INVALIDARGUMENT), -FLT_MAX);
   hipStream_t s = (hipStream_t)stream;
@@ -1555,6 +1703,126 @@ extern "C" int dh_set_basis(dh_handle h, int type, int modes_out, int modes_in, 
   return set_err(pl, DH_SUCCESS);
 }
 
+namespace {
+// staging buffers of a sweep or averaged batch (freed when neither is set)
+int ensure_staging(Plan* pl) {
+  if (pl->smem) (void)hipFree(pl->smem);
+  pl->smem = nullptr;
+  pl->sptr = nullptr;
+  pl->sc = pl->scn = pl->swin = pl->sfld = nullptr;
+  pl->rot = nullptr;
+  if (!sweeping(pl)) return DH_SUCCESS;
+  const Geom& g = pl->g;
+  const dh_params* p = &pl->params;
+  const size_t B = pl->max_batch, P = p->pol_count, nm = std::max(g.nmodes, 1);
+  const size_t plane = B * P * g.wy * g.wx * 8;
+  const bool win = pl->avg > 1 || p->keep_window || exports(g, p), fld = p->keep_fields && g.mode == 1;
+  size_t o = 0;
+  auto take = [&](size_t n) { size_t r = o; o += align256(n); return r; };
+  const size_t o_ptr = take(B * 8), o_c = take(B * P * nm * 8), o_cn = take(B * P * nm * 8);
+  const size_t o_w = win ? take(plane) : 0, o_f = fld ? take(plane) : 0, o_r = take(B * 16);
+  if (hipMalloc(&pl->smem, o) != hipSuccess) {
+    (void)hipGetLastError();
+    pl->smem = nullptr;
+    return DH_ERR_MEMORYALLOCATION;
+  }
+  pl->sptr = (const void**)(pl->smem + o_ptr);
+  pl->sc = (float2*)(pl->smem + o_c);
+  pl->scn = (float2*)(pl->smem + o_cn);
+  pl->swin = win ? (float2*)(pl->smem + o_w) : nullptr;
+  pl->sfld = fld ? (float2*)(pl->smem + o_f) : nullptr;
+  pl->rot = (double2*)(pl->smem + o_r);
+  return DH_SUCCESS;
+}
+}  // namespace
+
+extern "C" int dh_set_wavelengths(dh_handle h, const double* lambdas, int count, int in_order, int out_order) {
+  Plan* pl = get(h);
+  if (!pl) return DH_ERR_INVALIDHANDLE;
+  if (count < 0 || count > 4096) return set_err(pl, DH_ERR_INVALIDDIMENSION);
+  if (count > 0 && !lambdas) return set_err(pl, DH_ERR_NULLPOINTER);
+  if ((in_order != DH_WL_FAST && in_order != DH_WL_SLOW) || (out_order != DH_WL_FAST && out_order != DH_WL_SLOW))
+    return set_err(pl, DH_ERR_INVALIDARGUMENT);
+  const Geom& g = pl->g;
+  const dh_params* p = &pl->params;
+  const int P = p->pol_count;
+  // every wavelength's window must lie in the spectrum with the plan's box
+  std::vector<PolGeom> geo((size_t)count * 2);
+  for (int w = 0; w < count; ++w) {
+    if (!(lambdas[w] > 0.0) || !std::isfinite(lambdas[w])) return set_err(pl, DH_ERR_INVALIDARGUMENT);
+    dh_params pw = *p;
+    pw.wavelength = lambdas[w];
+    Geom gw = g;
+    for (int q = 0; q < P; ++q) {
+      const int e = derive_pol(&pw, &gw, q);
+      if (e != DH_SUCCESS) return set_err(pl, e);
+      geo[(size_t)w * 2 + q] = gw.pol[q];
+    }
+  }
+  if (hipDeviceSynchronize() != hipSuccess) return set_err(pl, DH_ERR_ERROR);
+  if (pl->lmem) (void)hipFree(pl->lmem);
+  pl->lmem = nullptr;
+  pl->nlam = 0;
+  pl->lams.clear();
+  pl->lam_geom.clear();
+  pl->lam_tab.clear();
+  if (count > 0) {
+    const bool exp = exports(g, p);
+    std::vector<Plan::LamTab> tab((size_t)count * 2);
+    size_t o = 0;
+    auto take = [&](size_t n) { size_t r = o; o += align256(n); return r; };
+    for (int w = 0; w < count; ++w)
+      for (int q = 0; q < P; ++q) {
+        Plan::LamTab& t = tab[(size_t)w * 2 + q];
+        t.mrow = take(g.by * 8); t.rhox = take(g.bx * 8); t.rhoy = take(g.by * 8);
+        t.tx = take(g.wx * 8); t.ty = take(g.wy * 8);
+        t.xs = g.spec ? take((size_t)g.bx * g.gp * 8) : 0;
+        t.ys = g.spec ? take((size_t)g.wyp * g.gp * 8) : 0;
+        t.ex = exp ? take((size_t)g.wx * g.fx * 8) : 0;
+        t.ey = exp ? take((size_t)g.fy * g.wy * 8) : 0;
+      }
+    if (hipMalloc(&pl->lmem, o) != hipSuccess) {
+      (void)hipGetLastError();
+      pl->lmem = nullptr;
+      return set_err(pl, DH_ERR_MEMORYALLOCATION);
+    }
+    for (int w = 0; w < count; ++w) {
+      dh_params pw = *p;
+      pw.wavelength = lambdas[w];
+      for (int q = 0; q < P; ++q) {
+        const Plan::LamTab& t = tab[(size_t)w * 2 + q];
+        const PolTables v = pol_tables(g, geo[(size_t)w * 2 + q], &pw, q, g.spec, exp);
+        if (!upload(pl->lmem, t.mrow, v.mrow) || !upload(pl->lmem, t.rhox, v.rhox) ||
+            !upload(pl->lmem, t.rhoy, v.rhoy) || !upload(pl->lmem, t.tx, v.tx) || !upload(pl->lmem, t.ty, v.ty) ||
+            (g.spec && (!upload(pl->lmem, t.xs, v.xs) || !upload(pl->lmem, t.ys, v.ys))) ||
+            (exp && (!upload(pl->lmem, t.ex, v.ex) || !upload(pl->lmem, t.ey, v.ey)))) {
+          (void)hipFree(pl->lmem);
+          pl->lmem = nullptr;
+          return set_err(pl, DH_ERR_ERROR);
+        }
+      }
+    }
+    pl->nlam = count;
+    pl->lams.assign(lambdas, lambdas + count);
+    pl->lam_geom = geo;
+    pl->lam_tab = tab;
+  }
+  pl->in_order = in_order;
+  pl->out_order = out_order;
+  return set_err(pl, ensure_staging(pl));
+}
+
+extern "C" int dh_set_averaging(dh_handle h, int count, int mode) {
+  Plan* pl = get(h);
+  if (!pl) return DH_ERR_INVALIDHANDLE;
+  if (count < 1 || count > 4096) return set_err(pl, DH_ERR_INVALIDDIMENSION);
+  if (mode < DH_AVG_SEQUENTIAL || mode > DH_AVG_SEQUENTIAL_SWEEP) return set_err(pl, DH_ERR_INVALIDARGUMENT);
+  if (hipDeviceSynchronize() != hipSuccess) return set_err(pl, DH_ERR_ERROR);
+  pl->avg = count;
+  pl->avg_mode = mode;
+  return set_err(pl, ensure_staging(pl));
+}
+
 extern "C" int dh_fields_to_int16(const dh_c64* fields, int n_fields, long long field_len, short* re, short* im,
                                   float* scale, void* stream) {
   if (n_fields < 0 || field_len < 1) return DH_ERR_INVALIDARGUMENT;
@@ -1766,8 +2034,10 @@ hipError_t record_batch(const Camera& C, const Lane& L, int n) {
 }
 
 int launch_lane(Server* S, Camera& C, Lane& L) {
-  // the lanes were sized for the basis the plan had when the server was made
-  if (C.pl->basis != C.basis || (C.basis != DH_BASIS_HG && C.pl->bout != C.bout)) return DH_ERR_ERROR;
+  // the lanes were sized for the basis the plan had when the server was made;
+  // sweeps and averaging are not served
+  if (C.pl->basis != C.basis || (C.basis != DH_BASIS_HG && C.pl->bout != C.bout) || sweeping(C.pl))
+    return DH_ERR_ERROR;
   lane_args(C, L);
   const int n = (int)std::min<size_t>(C.pending.size(), (size_t)S->max_batch);
   L.batch.assign(C.pending.begin(), C.pending.begin() + n);
@@ -1858,6 +2128,10 @@ int dh_serve_create(const dh_handle* plans, int ncam, int max_batch, size_t hbm_
     if (!C.pl) {
       delete S;
       return DH_ERR_INVALIDHANDLE;
+    }
+    if (sweeping(C.pl)) {   // each request is one frame at the plan's wavelength
+      delete S;
+      return DH_ERR_INVALIDARGUMENT;
     }
     size_t off[8];
     C.lane_bytes = lane_layout(C.pl, max_batch, off);

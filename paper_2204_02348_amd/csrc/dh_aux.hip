@@ -8,6 +8,9 @@
 //   k_tm_rows  row statistics of the matrix the diagonal metrics are taken on
 //   k_q16      fields to int16 real and imaginary parts with one scale each
 //   k_basis    HG coefficients to another basis (LG, custom): one matrix product
+//   k_fptr, k_avg_rot, k_comb_*   wavelength sweeps and frame averaging: the
+//              frame of each staged position, the phase of each repetition,
+//              and the outputs combined from the staged results
 #include "dh_internal.hpp"
 
 namespace dh {
@@ -218,6 +221,151 @@ hipError_t launch_basis(const float2* in, const float2* in_norm, int nin, int nu
   if (n < 1) return hipSuccess;
   if (nused > 528) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_basis, dim3(n, 2), dim3(256), 0, s, in, in_norm, nin, nused, tt, nout, out, out_norm);
+  return hipGetLastError();
+}
+
+// staged position of output o's repetition a
+__device__ __forceinline__ size_t stage_of(const Comb& c, int o, int a) {
+  int i, w;
+  if (c.out_order == 0) {
+    i = o / c.L;
+    w = o - i * c.L;
+  } else {
+    w = o / c.I;
+    i = o - w * c.I;
+  }
+  return ((size_t)w * c.I + i) * c.A + a;
+}
+
+__global__ void k_fptr(const char* base, unsigned long long fbytes, int n_out, int L, int I, int A, int avg_mode,
+                       int in_order, const void** __restrict__ sptr) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_out * A) return;
+  const int a = s % A, r = s / A, i = r % I, w = r / I;
+  const long long j0 = in_order == 0 ? (long long)i * L + w : (long long)w * I + i;
+  long long j;
+  if (avg_mode == 0)
+    j = j0 * A + a;                              // sequential: AAABBB
+  else if (avg_mode == 1)
+    j = (long long)a * n_out + j0;               // interlaced: ABCABC
+  else
+    j = ((long long)i * A + a) * L + w;          // sequential sweeps: {A}{A}{B}{B}
+  sptr[s] = base + (size_t)j * fbytes;
+}
+
+__global__ void __launch_bounds__(256) k_avg_rot(const float2* __restrict__ win, long long per, Comb c,
+                                                 double2* __restrict__ rot) {
+  __shared__ double rr[256], ri[256];
+  const int o = blockIdx.x, a = blockIdx.y, tid = threadIdx.x;
+  if (a == 0) {
+    if (tid == 0) rot[(size_t)o * c.A] = make_double2(1.0, 0.0);
+    return;
+  }
+  const float2* wa = win + stage_of(c, o, a) * per;
+  const float2* w0 = win + stage_of(c, o, 0) * per;
+  double re = 0.0, im = 0.0;
+  for (long long e = tid; e < per; e += 256) {
+    const float2 x = wa[e], y = w0[e];               // x conj(y)
+    re += (double)x.x * y.x + (double)x.y * y.y;
+    im += (double)x.y * y.x - (double)x.x * y.y;
+  }
+  rr[tid] = re;
+  ri[tid] = im;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) {
+      rr[tid] += rr[tid + w];
+      ri[tid] += ri[tid + w];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double m = sqrt(rr[0] * rr[0] + ri[0] * ri[0]);
+    rot[(size_t)o * c.A + a] = m > 0.0 ? make_double2(rr[0] / m, -ri[0] / m) : make_double2(1.0, 0.0);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_comb_coefs(const float2* __restrict__ sc, const float2* __restrict__ scn,
+                                                    const double2* __restrict__ rot, int per, Comb c,
+                                                    float2* __restrict__ out, float2* __restrict__ out_norm) {
+  __shared__ double red[256];
+  const int o = blockIdx.x, tid = threadIdx.x;
+  double pw = 0.0;
+  for (int e = tid; e < per; e += 256) {
+    double re = 0.0, im = 0.0;
+    for (int a = 0; a < c.A; ++a) {
+      const float2 v = sc[stage_of(c, o, a) * per + e];
+      const double2 r = rot ? rot[(size_t)o * c.A + a] : make_double2(1.0, 0.0);
+      re += r.x * v.x - r.y * v.y;
+      im += r.x * v.y + r.y * v.x;
+    }
+    const float2 f = make_float2((float)(re / c.A), (float)(im / c.A));
+    out[(size_t)o * per + e] = f;
+    pw += (double)f.x * f.x + (double)f.y * f.y;
+  }
+  if (c.A == 1) {   // a reordering: the staged normalised values as they are
+    for (int e = tid; e < per; e += 256) out_norm[(size_t)o * per + e] = scn[stage_of(c, o, 0) * per + e];
+    return;
+  }
+  red[tid] = pw;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  const double inv = red[0] > 0.0 ? 1.0 / sqrt(red[0]) : 0.0;
+  for (int e = tid; e < per; e += 256) {
+    const float2 f = out[(size_t)o * per + e];
+    out_norm[(size_t)o * per + e] = make_float2((float)(f.x * inv), (float)(f.y * inv));
+  }
+}
+
+__global__ void __launch_bounds__(256) k_comb_plane(const float2* __restrict__ in, const double2* __restrict__ rot,
+                                                    long long per, Comb c, int n_out, float2* __restrict__ out) {
+  for (int o = blockIdx.y; o < n_out; o += gridDim.y) {
+    const long long e0 = (long long)blockIdx.x * 1024;
+    const long long e1 = e0 + 1024 < per ? e0 + 1024 : per;
+    for (long long e = e0 + threadIdx.x; e < e1; e += 256) {
+      double re = 0.0, im = 0.0;
+      for (int a = 0; a < c.A; ++a) {
+        const float2 v = in[stage_of(c, o, a) * per + e];
+        const double2 r = rot ? rot[(size_t)o * c.A + a] : make_double2(1.0, 0.0);
+        re += r.x * v.x - r.y * v.y;
+        im += r.x * v.y + r.y * v.x;
+      }
+      out[(size_t)o * per + e] = make_float2((float)(re / c.A), (float)(im / c.A));
+    }
+  }
+}
+
+hipError_t launch_fptr(const char* base, size_t fbytes, int n_out, int L, int I, int A, int avg_mode, int in_order,
+                       const void** sptr, hipStream_t s) {
+  const int n = n_out * A;
+  if (n < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_fptr, dim3((n + 255) / 256), dim3(256), 0, s, base, (unsigned long long)fbytes, n_out, L, I, A,
+                     avg_mode, in_order, sptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_avg_rot(const float2* win, long long per, const Comb& c, int n_out, double2* rot, hipStream_t s) {
+  if (n_out < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_avg_rot, dim3(n_out, c.A), dim3(256), 0, s, win, per, c, rot);
+  return hipGetLastError();
+}
+
+hipError_t launch_comb_coefs(const float2* sc, const float2* scn, const double2* rot, int per, const Comb& c, int n_out,
+                             float2* out, float2* out_norm, hipStream_t s) {
+  if (n_out < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_comb_coefs, dim3(n_out), dim3(256), 0, s, sc, scn, rot, per, c, out, out_norm);
+  return hipGetLastError();
+}
+
+hipError_t launch_comb_plane(const float2* in, const double2* rot, long long per, const Comb& c, int n_out, float2* out,
+                             hipStream_t s) {
+  if (n_out < 1 || per < 1) return hipSuccess;
+  const long long bx = (per + 1023) / 1024;
+  hipLaunchKernelGGL(k_comb_plane, dim3((unsigned)bx, (unsigned)(n_out < 65535 ? n_out : 65535)), dim3(256), 0, s, in,
+                     rot, per, c, n_out, out);
   return hipGetLastError();
 }
 

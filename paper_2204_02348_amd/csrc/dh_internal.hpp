@@ -98,6 +98,26 @@ hipError_t launch_gather(const KArgs& a, const float2* spec, int bxe, int nrow, 
 hipError_t launch_psum(const float2* spec, int nb, int npol, size_t plane, float* pw, hipStream_t s);
 // FP64 intensity moments of n fields [wy][wx]: out[e][5] = sums of I, xI, yI,
 // x^2 I, y^2 I on the coarse grid x = (k - wx/2) px, y = (l - wy/2) py
+// wavelength sweep / averaging: N = I L outputs, A repetitions each; staged
+// position of output o's repetition a = (w I + i) A + a, (i, w) of o by the
+// output ordering (0: o = i L + w, 1: o = w I + i)
+struct Comb {
+  int L, I, A, out_order;
+};
+// sptr[s] = base + (input frame of staged position s) * fbytes for the n_out * A
+// positions (avg_mode 0 sequential, 1 interlaced, 2 sequential sweep; in_order
+// 0 fast, 1 slow)
+hipError_t launch_fptr(const char* base, size_t fbytes, int n_out, int L, int I, int A, int avg_mode, int in_order,
+                       const void** sptr, hipStream_t s);
+// rot[o A + a] = exp(-i arg sum win[s(o,a)] conj(win[s(o,0)])) over `per` values (1 for a = 0)
+hipError_t launch_avg_rot(const float2* win, long long per, const Comb& c, int n_out, double2* rot, hipStream_t s);
+// out[o] = mean over a of rot * staged[s(o, a)] (rot null: 1), `per` values per
+// position; coefficients also give out_norm (the staged normalised values for
+// A = 1, else out over the FP64 norm of out)
+hipError_t launch_comb_coefs(const float2* sc, const float2* scn, const double2* rot, int per, const Comb& c, int n_out,
+                             float2* out, float2* out_norm, hipStream_t s);
+hipError_t launch_comb_plane(const float2* in, const double2* rot, long long per, const Comb& c, int n_out, float2* out,
+                             hipStream_t s);
 // fields to int16 (re, im) with one FP32 scale per field: n fields of len values
 hipError_t launch_q16(const float2* fields, int n, long long len, short* re, short* im, float* scale, hipStream_t s);
 // basis transform of n coefficient vectors (frame x pol): out[e][k] = sum over

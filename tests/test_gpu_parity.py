@@ -786,6 +786,108 @@ def test_serving_returns_the_basis_coefficients():
     plan.destroy()
 
 
+# ---------------------------------------------------------------- wavelength sweeps and averaging
+def _sweep_run(p, f, n_out, lams=None, in_order=0, out_order=0, avg=1, mode=0, chunk=None):
+    torch = _torch()
+    import paper_2204_02348_amd as dh
+    if chunk:
+        os.environ["DH_CHUNK_FRAMES"] = str(chunk)
+    try:
+        plan = dh.Plan(p, max_batch=f.shape[0])
+    finally:
+        os.environ.pop("DH_CHUNK_FRAMES", None)
+    if lams is not None:
+        plan.set_wavelengths(lams, in_order, out_order)
+    if avg > 1:
+        plan.set_averaging(avg, mode)
+    ft = torch.from_numpy(np.ascontiguousarray(f)).cuda()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    plan.process(ft, n_out, s)
+    out = dict(coefs=plan.coefs(False), coefs_norm=plan.coefs(True))
+    if p.get("keep_window"):
+        out["window"] = plan.window()
+    if p.get("keep_fields"):
+        out["field"] = plan.fields()
+    torch.cuda.synchronize()
+    plan.destroy()
+    return out
+
+
+def _check_sweep(gpu, ref, keys, tol=TOL):
+    worst = {}
+    for k in keys:
+        for o in range(ref[k].shape[0]):
+            for q in range(ref[k].shape[1]):
+                worst[k] = max(worst.get(k, 0.0), _rel(gpu[k][o][q].astype(np.complex128), ref[k][o][q]))
+    _say("worst rel-L2", {k: f"{v:.2e}" for k, v in worst.items()})
+    for k, v in worst.items():
+        assert v <= tol, (k, v)
+
+
+@pytest.mark.parametrize("in_order,out_order", [(0, 0), (0, 1), (1, 0)])
+def test_wavelength_sweep_vs_oracle(in_order, out_order):
+    """Three wavelengths, two inputs, 640x512 two pols G=9 on the field path
+    with windows and fields, against the oracle's per-frame wavelengths."""
+    cfg, f, _ = _frames(1, n=6)
+    p = dict(cfg["params"], keep_window=1, keep_fields=1)
+    lams = [1565e-9 * 0.99, 1565e-9, 1565e-9 * 1.012]
+    _say("sweep in_order %d out_order %d" % (in_order, out_order))
+    gpu = _sweep_run(p, f, 6, lams, in_order, out_order, chunk=4)
+    ref = oracle.process_sweep(f.astype(np.float64), p, lams, in_order=in_order, out_order=out_order)
+    _check_sweep(gpu, ref, ("coefs", "coefs_norm", "window", "field"))
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_averaging_vs_oracle(mode):
+    """Three outputs, each the phase-aligned average of three frames
+    (sequential or interlaced), over chunks of four frames."""
+    cfg, f, _ = _frames(1, n=9)
+    p = dict(cfg["params"], keep_window=1, keep_fields=1)
+    _say("averaging mode %d" % mode)
+    gpu = _sweep_run(p, f, 3, avg=3, mode=mode, chunk=4)
+    ref = oracle.process_sweep(f.astype(np.float64), p, [p["wavelength"]], avg_count=3, avg_mode=mode)
+    _check_sweep(gpu, ref, ("coefs", "coefs_norm", "window", "field"))
+
+
+def test_averaged_sweep_spectral_and_mode0():
+    """Two wavelengths, averaging over sequential sweeps: on the spectral path
+    (coefficients only), and in IFFT mode 0 with the fields exported."""
+    cfg, f, _ = _frames(1, n=8)
+    lams = [1565e-9 * 1.008, 1565e-9 * 0.994]
+    for extra in (dict(), dict(ifft_mode=0, keep_fields=1)):
+        p = dict(cfg["params"], **extra)
+        _say("averaged sweep", extra)
+        gpu = _sweep_run(p, f, 4, lams, 0, 1, avg=2, mode=2)
+        ref = oracle.process_sweep(f.astype(np.float64), p, lams, avg_count=2, avg_mode=2, in_order=0, out_order=1)
+        _check_sweep(gpu, ref, ("coefs", "coefs_norm") + (("field",) if extra else ()))
+
+
+def test_sweep_rejections():
+    torch = _torch()
+    import paper_2204_02348_amd as dh
+    cfg, f, _ = _frames(1, n=4)
+    plan = dh.Plan(cfg["params"], max_batch=4)
+    plan.set_wavelengths([1565e-9, 1566e-9, 1567e-9])
+    ft = torch.from_numpy(f).cuda()
+    with pytest.raises(dh.DhError) as e:
+        plan.process(ft, 4, None)                       # not a whole number of sweeps
+    assert e.value.code == dh.ERR_INVALIDDIMENSION
+    plan.set_wavelengths([])
+    plan.set_averaging(3)
+    with pytest.raises(dh.DhError) as e:
+        plan.process(ft, 2, None)                       # 6 frames > max_batch 4
+    assert e.value.code == dh.ERR_INVALIDDIMENSION
+    with pytest.raises(dh.DhError):
+        plan.autoalign(ft, 1)
+    with pytest.raises(dh.DhError):
+        dh.Server([plan], max_batch=4)
+    with pytest.raises(dh.DhError) as e:
+        plan.set_wavelengths([1565e-9, -1.0])
+    assert e.value.code == dh.ERR_INVALIDARGUMENT
+    plan.destroy()
+
+
 # ---------------------------------------------------------------- transfer-matrix metrics
 @pytest.mark.parametrize("n", [90, 1000])
 def test_transfer_metrics_match_oracle(n):
