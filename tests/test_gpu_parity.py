@@ -169,6 +169,39 @@ def test_frame_alone_equals_frame_in_batch():
     assert np.array_equal(alone["coefs_norm"][0], batch["coefs_norm"][3])
 
 
+@pytest.mark.parametrize("path", ["field", "spectral"])
+@pytest.mark.parametrize("idx", [0, 1])
+def test_largest_group_count(idx, path):
+    """G = 32, the most the plan takes (528 modes per pol), on both paths."""
+    cfg, f, _ = _frames(idx, n=2 if idx else 1)
+    p = dict(cfg["params"], max_mg=32)
+    _say("G=32 recipe %d, %s path" % (idx, path))
+    gpu = run_gpu(p, f, keep=path == "field", path=path)
+    assert gpu["coefs"].shape[2] == 528
+    check_frames(p, f, gpu, range(f.shape[0]), keep=path == "field")
+
+
+def test_zero_frames_give_zero_not_nan():
+    """All-zero frames: every coefficient, raw and normalised (power 0), is
+    exactly zero on both paths, and the int16 export has scale 1."""
+    torch = _torch()
+    import paper_2204_02348_amd as dh
+    cfg = dh_synth.config(1)
+    f = np.zeros((3, 512, 640), dtype=np.float32)
+    ft = torch.from_numpy(f).cuda()
+    for path in ("field", "spectral"):
+        _say("zero frames, %s path" % path)
+        plan = dh.Plan(dict(cfg["params"], path=path, keep_fields=int(path == "field")), max_batch=3)
+        plan.process(ft, 3, None)
+        for normalised in (False, True):
+            c = plan.coefs(normalised)
+            assert np.all(c == 0) and not np.any(np.isnan(c))
+        if path == "field":
+            re, im, sc = plan.fields16()
+            assert not re.any() and not im.any() and np.all(sc == 1.0)
+        plan.destroy()
+
+
 # ---------------------------------------------------------------- spectral path
 @pytest.mark.parametrize("idx,cam,n,chunk", [
     (0, 0, 1, None),      # 128x128 G=4
