@@ -63,7 +63,7 @@ struct Geom {
 // (field path, also used by alignment) or column blocks (spectral path)
 int field_blocks(const Geom& g) { return g.wyp / 16; }
 int partial_blocks(const Geom& g) {
-  return g.spec ? std::max(field_blocks(g), dh::spectral_blocks(g.ny, g.bx)) : field_blocks(g);
+  return g.spec ? std::max(field_blocks(g), dh::spectral_blocks(g.ny, g.bx, g.gp)) : field_blocks(g);
 }
 
 bool inside(double u, double v, double ax, double ay, double rx, double ry) {
@@ -638,7 +638,7 @@ void fill_kargs(Plan* pl, int w) {
   a.t1 = (float2*)(m + L.t1[w]);
   a.f2 = (float2*)(m + L.f2[w]);
   a.partial = (float2*)(m + L.partial[w]);
-  a.nblk = g.spec ? dh::spectral_blocks(g.ny, g.bx) : field_blocks(g);
+  a.nblk = g.spec ? dh::spectral_blocks(g.ny, g.bx, g.gp) : field_blocks(g);
   a.coefs = (float2*)(m + L.coefs);
   a.coefs_norm = (float2*)(m + L.coefs_norm);
   a.window = p->keep_window || exports(g, p) ? (float2*)(m + L.window) : nullptr;
@@ -892,6 +892,7 @@ bool sweeping(const Plan* pl) { return pl->nlam > 0 || pl->avg > 1; }
 int process_sweep(Plan* pl, const void* frames, int batch, hipStream_t s) {
   const Geom& g = pl->g;
   const int P = pl->params.pol_count, L = std::max(pl->nlam, 1), A = pl->avg;
+  if (!pl->smem) return DH_ERR_ERROR;
   if (batch % L) return DH_ERR_INVALIDDIMENSION;
   const int I = batch / L, n_in = batch * A;
   if (n_in > pl->max_batch) return DH_ERR_INVALIDDIMENSION;
@@ -1809,7 +1810,17 @@ extern "C" int dh_set_wavelengths(dh_handle h, const double* lambdas, int count,
   }
   pl->in_order = in_order;
   pl->out_order = out_order;
-  return set_err(pl, ensure_staging(pl));
+  const int e = ensure_staging(pl);
+  if (e != DH_SUCCESS) {   // no staging: back to single-wavelength processing
+    if (pl->lmem) (void)hipFree(pl->lmem);
+    pl->lmem = nullptr;
+    pl->nlam = 0;
+    pl->lams.clear();
+    pl->lam_geom.clear();
+    pl->lam_tab.clear();
+    (void)ensure_staging(pl);
+  }
+  return set_err(pl, e);
 }
 
 extern "C" int dh_set_averaging(dh_handle h, int count, int mode) {
@@ -1818,9 +1829,15 @@ extern "C" int dh_set_averaging(dh_handle h, int count, int mode) {
   if (count < 1 || count > 4096) return set_err(pl, DH_ERR_INVALIDDIMENSION);
   if (mode < DH_AVG_SEQUENTIAL || mode > DH_AVG_SEQUENTIAL_SWEEP) return set_err(pl, DH_ERR_INVALIDARGUMENT);
   if (hipDeviceSynchronize() != hipSuccess) return set_err(pl, DH_ERR_ERROR);
+  const int old = pl->avg;
   pl->avg = count;
   pl->avg_mode = mode;
-  return set_err(pl, ensure_staging(pl));
+  const int e = ensure_staging(pl);
+  if (e != DH_SUCCESS) {   // no staging: averaging stays as it was
+    pl->avg = old;
+    (void)ensure_staging(pl);
+  }
+  return set_err(pl, e);
 }
 
 extern "C" int dh_fields_to_int16(const dh_c64* fields, int n_fields, long long field_len, short* re, short* im,
@@ -1962,7 +1979,7 @@ size_t lane_layout(const Plan* pl, int mb, size_t off[8]) {
   auto take = [&](size_t bytes) { size_t r = o; o += align256(bytes); return r; };
   off[0] = take((size_t)mb * P * g.ny * g.bx * 8);                  // t1
   off[1] = take(g.spec ? 0 : (size_t)mb * P * g.wy * ((g.bx + 15) / 16 * 16) * 8);  // f2
-  const int nblk = g.spec ? dh::spectral_blocks(g.ny, g.bx) : field_blocks(g);
+  const int nblk = g.spec ? dh::spectral_blocks(g.ny, g.bx, g.gp) : field_blocks(g);
   off[2] = take((size_t)mb * P * nblk * (nm + 1) * 8);               // partial
   off[3] = take((size_t)mb * P * nm * 8);                            // coefs
   off[4] = take((size_t)mb * P * nm * 8);                            // coefs_norm

@@ -87,7 +87,7 @@ hipError_t launch_norm(const KArgs& a, int b0, int nb, hipStream_t s);
 // spectral path: column FFT + masked window contracted with the xs / ys
 // tables into per-column-block partials (replaces launch_col + launch_fld)
 bool spectral_supported(int ny, int wy, int gp);
-int spectral_blocks(int ny, int bx);     // column blocks per frame and pol
+int spectral_blocks(int ny, int bx, int gp);   // column blocks per frame and pol
 hipError_t launch_cspec(const KArgs& a, int b0, int nb, hipStream_t s);
 hipError_t launch_zero(float2* p, size_t n, hipStream_t s);
 // alignment: column FFT of an extended box stored as spec[b][p][j][i] (nrow rows
