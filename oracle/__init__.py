@@ -17,3 +17,4 @@ from .sweep_avg import (  # noqa: F401,E402
     SEQUENTIAL, INTERLACED, SEQUENTIAL_SWEEP, FAST, SLOW, frame_index_map, at_wavelength, average_windows,
     process_sweep,
 )
+from .window_fit import max_window_radius  # noqa: F401,E402

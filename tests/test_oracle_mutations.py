@@ -335,3 +335,39 @@ def test_sweep_pins_catch_planted_mistake(name, monkeypatch):
         except (AssertionError, ValueError, IndexError):
             failed += 1
     assert failed > 0, name
+
+
+# ---------------------------------------------------------------- largest window for a tilt
+WIN_SRC = os.path.join(os.path.dirname(SRC), "window_fit.py")
+
+WIN_MUTATIONS = {
+    "origin_terms_radius_w": ("w = min(math.hypot(tx, ty) / 3.0,", "w = min(math.hypot(tx, ty) / 2.0,"),
+    "no_spectrum_edge": ("w_max_deg - abs(tx), w_max_deg - abs(ty))", "math.inf)"),
+    "no_periodic_images": ("for kx in range(-2, 3):\n                for ky in range(-2, 3):",
+                           "for kx in range(0, 1):\n                for ky in range(0, 1):"),
+    "conjugate_gap_w": ("math.hypot(2 * tx - kx * period, 2 * ty - ky * period) / 2.0",
+                        "math.hypot(2 * tx - kx * period, 2 * ty - ky * period) / 1.0"),
+    "wrap_origin_image_period": ("math.hypot(tx - kx * period, ty - ky * period) / 3.0",
+                                 "math.hypot(tx - kx * w_max_deg, ty - ky * w_max_deg) / 3.0"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(WIN_MUTATIONS))
+def test_window_pins_catch_planted_mistake(name, monkeypatch):
+    import oracle
+    import tests.test_oracle_pins as pins
+    src = open(WIN_SRC).read()
+    old, new = WIN_MUTATIONS[name]
+    assert src.count(old) == 1, name
+    mod = types.ModuleType("win_mutant_" + name)
+    exec(compile(src.replace(old, new), WIN_SRC + ":" + name, "exec"), mod.__dict__)
+    monkeypatch.setattr(oracle, "max_window_radius", mod.max_window_radius)
+    failed = 0
+    for t in [pins.test_largest_window_at_the_papers_tilt, pins.test_largest_wrapped_window,
+              lambda: pins.test_largest_window_by_brute_force(False),
+              lambda: pins.test_largest_window_by_brute_force(True)]:
+        try:
+            t()
+        except AssertionError:
+            failed += 1
+    assert failed > 0, name

@@ -43,7 +43,7 @@ def test_worked_geometry_numbers():
     assert abs(wc - float(g["window_radius_deg"])) <= 1e-3
     tilt = 3 * wc / math.sqrt(2)
     assert abs(tilt - float(g["tilt_deg"])) <= 2e-3
-    # wrap variant: positive root of 8w^2 + 4w - 2 = 0 (the printed form is garbled)
+    # wrap variant: positive root of 8w^2 + 2w - 2 = 0 (the printed form is garbled)
     assert round((-2 + math.sqrt(68)) / 16, 4) == float(g["wrap_ratio"])
 
 
@@ -755,3 +755,68 @@ def test_average_of_one_frame_is_the_frame():
         ref = oracle.process_frame(f[o].astype(np.float64), p)
         for k in ("window", "field", "coefs", "coefs_norm"):
             assert np.abs(res[k][o] - ref[k]).max() <= 1e-12 * max(1.0, np.abs(ref[k]).max())
+
+
+# ---------------------------------------------------------------- largest window for a tilt
+def _wmax():
+    g = {k: v for k, v, _ in _read_table("worked_geometry.txt")}
+    return oracle.w_max_rad(float(g["pixel_m"]), float(g["wavelength_m"])) / oracle.DEG, g
+
+
+def test_largest_window_at_the_papers_tilt():
+    # the worked example: at t = (3w/sqrt2, 3w/sqrt2) both the origin terms and
+    # the spectrum edge touch the window, w = w_max / (1 + 3/sqrt2) (the printed
+    # ratio 0.3205 and radius 0.719 deg within their printed digits)
+    wmax, g = _wmax()
+    w = wmax / (1 + 3 / math.sqrt(2))
+    t = 3 * w / math.sqrt(2)
+    got = oracle.max_window_radius([(t, t)], wmax)
+    assert abs(got - w) < 1e-12
+    assert abs(got / wmax - float(g["window_ratio"])) < 2e-4
+    assert abs(got - float(g["window_radius_deg"])) < 1e-3
+    assert abs(t - float(g["tilt_deg"])) < 2e-3
+    # two pols: the smaller window; a tilt too close to the origin gives |t|/3
+    assert oracle.max_window_radius([(t, t), (0.3, 0.4)], wmax) == pytest.approx(0.5 / 3, abs=1e-12)
+
+
+def test_largest_wrapped_window():
+    # with wrapping, at t = (w_max - w, w_max) the window touches the origin's
+    # terms and the conjugate term's image: w = 0.3904 w_max (the printed root);
+    # without wrapping that tilt leaves no window at all (it sits on the edge)
+    wmax, g = _wmax()
+    w = (-2 + math.sqrt(68)) / 16 * wmax
+    got = oracle.max_window_radius([(wmax - w, wmax)], wmax, wrap=True)
+    assert abs(got - w) < 1e-12
+    assert round(got / wmax, 4) == float(g["wrap_ratio"])
+    assert oracle.max_window_radius([(wmax - w, wmax)], wmax) == 0.0
+
+
+@pytest.mark.parametrize("wrap", [False, True])
+def test_largest_window_by_brute_force(wrap):
+    # sample the window's rim: at the returned radius no rim point lies inside
+    # an origin term (radius 2w) or a conjugate term (radius w), or (without
+    # wrapping) outside the spectrum, and 0.2 % larger some point does
+    rng = np.random.default_rng(3 + wrap)
+    wmax = 2.0
+    th = np.linspace(0, 2 * math.pi, 4000, endpoint=False)
+    imgs = [(0, 0)] if not wrap else [(kx * 2 * wmax, ky * 2 * wmax) for kx in range(-2, 3) for ky in range(-2, 3)]
+
+    def violates(t, w):
+        x = t[0] + w * np.cos(th)
+        y = t[1] + w * np.sin(th)
+        for ix, iy in imgs:
+            if np.any(np.hypot(x - ix, y - iy) < 2 * w - 1e-12):
+                return True
+            if np.any(np.hypot(x - (-t[0] + ix), y - (-t[1] + iy)) < w - 1e-12):
+                return True
+        if not wrap and (np.any(np.abs(x) > wmax + 1e-12) or np.any(np.abs(y) > wmax + 1e-12)):
+            return True
+        return False
+
+    for _ in range(40):
+        t = rng.uniform(-wmax, wmax, size=2)
+        w = oracle.max_window_radius([tuple(t)], wmax, wrap=wrap)
+        if w <= 1e-3:
+            continue
+        assert not violates(t, w), (t, w)
+        assert violates(t, w * 1.002), (t, w)
