@@ -152,6 +152,21 @@ int dh_plan_check(const dh_params* p, int max_batch, dh_plan_info* info);
 int dh_plan(const dh_params* p, int max_batch, size_t hbm_budget, dh_handle* out);
 
 /*
+ * The largest Fourier window radius (degrees) for the tilts of `p` (the
+ * paper's AutoAlignFourierWindowRadius, "as large as possible for the tilt";
+ * background section "How do you choose the angle of the Reference Field?"):
+ * the window around each pol's cross term stays clear of the autocorrelation
+ * terms at the origin (radius twice the window's) and of the conjugate cross
+ * term, and, without wrap, inside the resolvable spectrum +-w_max; with wrap
+ * the spectrum is periodic (period 2 w_max) and the same gaps hold from every
+ * image. The smaller radius of the two pols. Host only: a plan's box is fixed,
+ * so a caller plans again with the radius returned. Uses pixel_size,
+ * wavelength, pol_count and tilt_deg only. Errors: DH_ERR_NULLPOINTER,
+ * DH_ERR_INVALIDPOLARISATION, DH_ERR_INVALIDARGUMENT.
+ */
+int dh_max_window_radius(const dh_params* p, int wrap, double* radius_deg);
+
+/*
  * Process `batch` frames (device pointer, [batch][frame_h][frame_w] of the
  * plan's input_dtype) asynchronously on `stream` (a hipStream_t; NULL = the
  * default stream). The caller keeps ownership of `frames`; they must stay

@@ -42,7 +42,7 @@ PATH_AUTO = 0
 PATH_FIELD = 1
 PATH_SPECTRAL = 2
 
-EXPORTS = ["dh_plan_check", "dh_plan", "dh_process_batch", "dh_mode_coefs", "dh_get_window",
+EXPORTS = ["dh_plan_check", "dh_max_window_radius", "dh_plan", "dh_process_batch", "dh_mode_coefs", "dh_get_window",
            "dh_get_fields", "dh_get_fields16", "dh_fields_to_int16", "dh_get_params", "dh_get_plan_info",
            "dh_set_stage_timing", "dh_stage_times", "dh_autoalign", "dh_get_align_report", "dh_set_align_goal",
            "dh_set_pol_lock", "dh_transfer_metrics", "dh_set_basis", "dh_set_wavelengths", "dh_set_averaging",
@@ -107,6 +107,7 @@ def lib():
         c64p = C.c_void_p
         L.dh_plan_check.argtypes = [C.POINTER(Params), C.c_int, C.POINTER(PlanInfo)]
         L.dh_plan.argtypes = [C.POINTER(Params), C.c_int, C.c_size_t, C.POINTER(C.c_int)]
+        L.dh_max_window_radius.argtypes = [C.POINTER(Params), C.c_int, C.POINTER(C.c_double)]
         L.dh_process_batch.argtypes = [C.c_int, C.c_void_p, C.c_int, C.c_void_p]
         L.dh_mode_coefs.argtypes = [C.c_int, c64p, C.POINTER(C.c_void_p), C.POINTER(C.c_int),
                                     C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_int]
@@ -189,6 +190,16 @@ def plan_check(d: dict, max_batch: int = 1):
     p = make_params(d)
     rc = lib().dh_plan_check(C.byref(p), max_batch, C.byref(info))
     return rc, info
+
+
+def max_window_radius(d: dict, wrap: bool = False) -> float:
+    """dh_max_window_radius: the largest window radius (degrees) for the tilts in d."""
+    p = make_params(d)
+    r = C.c_double()
+    rc = lib().dh_max_window_radius(C.byref(p), int(wrap), C.byref(r))
+    if rc != SUCCESS:
+        raise DhError(rc, "dh_max_window_radius")
+    return r.value
 
 
 def _ptr(x) -> int:

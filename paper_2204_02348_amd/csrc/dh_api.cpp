@@ -755,6 +755,38 @@ int dh_plan_check(const dh_params* p, int max_batch, dh_plan_info* info) {
   return DH_SUCCESS;
 }
 
+int dh_max_window_radius(const dh_params* p, int wrap, double* radius_deg) {
+  if (!p || !radius_deg) return DH_ERR_NULLPOINTER;
+  if (p->pol_count != 1 && p->pol_count != 2) return DH_ERR_INVALIDPOLARISATION;
+  if (!(p->pixel_size > 0) || !(p->wavelength > 0)) return DH_ERR_INVALIDARGUMENT;
+  // angles in degrees (paraxial, as the tilt-to-bin mapping), where the
+  // window is a circle; the spectrum spans +-w_max = lambda / (2 p) along each
+  // axis and repeats with period 2 w_max when it wraps
+  const double wmax = p->wavelength / (2.0 * p->pixel_size) / kDeg;
+  double best = HUGE_VAL;
+  for (int q = 0; q < p->pol_count; ++q) {
+    const double tx = p->tilt_deg[q][0], ty = p->tilt_deg[q][1];
+    if (!std::isfinite(tx) || !std::isfinite(ty)) return DH_ERR_INVALIDARGUMENT;
+    double w;
+    if (!wrap) {
+      // clear of the autocorrelation terms at the origin (radius 2w) and inside the spectrum
+      w = std::min(std::hypot(tx, ty) / 3.0, std::min(wmax - std::fabs(tx), wmax - std::fabs(ty)));
+    } else {
+      // the same gaps from every periodic image of the origin terms and of the conjugate term
+      w = HUGE_VAL;
+      const double per = 2.0 * wmax;
+      for (int kx = -2; kx <= 2; ++kx)
+        for (int ky = -2; ky <= 2; ++ky) {
+          w = std::min(w, std::hypot(tx - kx * per, ty - ky * per) / 3.0);
+          w = std::min(w, std::hypot(2.0 * tx - kx * per, 2.0 * ty - ky * per) / 2.0);
+        }
+    }
+    best = std::min(best, w);
+  }
+  *radius_deg = std::max(best, 0.0);
+  return DH_SUCCESS;
+}
+
 int dh_plan(const dh_params* p, int max_batch, size_t hbm_budget, dh_handle* out) {
   if (!p || !out) return DH_ERR_NULLPOINTER;
   Geom g;

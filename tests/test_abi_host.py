@@ -181,3 +181,20 @@ def test_int16_conversion_rejects_bad_arguments_without_gpu():
 
 def test_basis_rejects_bad_handles_without_gpu():
     assert dh.lib().dh_set_basis(91, dh.BASIS_LG, 0, 0, None) == dh.ERR_INVALIDHANDLE
+
+
+@pytest.mark.parametrize("wrap", [False, True])
+def test_max_window_radius_matches_oracle(wrap):
+    import oracle
+    rng = np.random.default_rng(8 + wrap)
+    base = dh_synth.config(1)["params"]
+    wmax = oracle.w_max_rad(base["pixel_size"], base["wavelength"]) / oracle.DEG
+    for _ in range(50):
+        t = rng.uniform(-wmax, wmax, size=(2, 2))
+        d = dict(base, tilt_deg=t.tolist())
+        got = dh.max_window_radius(d, wrap)
+        ref = oracle.max_window_radius([tuple(t[0]), tuple(t[1])], wmax, wrap)
+        assert got == pytest.approx(ref, abs=1e-12)
+    # the paper's worked example: window ~0.719 deg at tilt 1.525 deg on both axes
+    assert abs(dh.max_window_radius(dict(base, tilt_deg=[[1.525, 1.525], [1.525, 1.525]])) - 0.719) < 3e-3
+    assert dh.lib().dh_max_window_radius(None, 0, None) == dh.ERR_NULLPOINTER
