@@ -896,6 +896,41 @@ def test_averaged_sweep_spectral_and_mode0():
         _check_sweep(gpu, ref, ("coefs", "coefs_norm") + (("field",) if extra else ()))
 
 
+def test_sweep_with_lg_basis_metrics_and_int16_fields():
+    """A 2-wavelength sweep (slow out) averaged over 2 interlaced repetitions,
+    in the LG basis, with fields: LG coefficients, the transfer-matrix metrics
+    of the LG matrix, and the int16 fields, against the oracle."""
+    torch = _torch()
+    import paper_2204_02348_amd as dh
+    cfg, f, _ = _frames(1, n=8)
+    p = dict(cfg["params"], keep_fields=1)
+    lams = [1565e-9 * 0.995, 1565e-9 * 1.004]
+    plan = dh.Plan(p, max_batch=8)
+    plan.set_wavelengths(lams, dh.WL_FAST, dh.WL_SLOW)
+    plan.set_averaging(2, dh.AVG_INTERLACED)
+    plan.set_basis(dh.BASIS_LG)
+    ft = torch.from_numpy(np.ascontiguousarray(f)).cuda()
+    plan.process(ft, 4, None)
+    raw, nrm = plan.coefs(False), plan.coefs(True)
+    met = plan.transfer_metrics()
+    re, im, sc = plan.fields16()
+    plan.destroy()
+    ref = oracle.process_sweep(f.astype(np.float64), p, lams, avg_count=2, avg_mode=1, in_order=0, out_order=1)
+    t = oracle.hg_to_lg(p["max_mg"])
+    _say("sweep + averaging + LG + int16")
+    for o in range(4):
+        for q in range(2):
+            assert _rel(raw[o][q].astype(np.complex128), oracle.apply_basis(ref["coefs"][o], t)[q]) <= TOL
+            assert _rel(nrm[o][q].astype(np.complex128), oracle.apply_basis(ref["coefs_norm"][o], t)[q]) <= TOL
+            ore, oim, osc = oracle.fields_to_int16(ref["field"][o][q])
+            assert abs(float(sc[o, q]) / float(osc) - 1) < 1e-5
+            assert np.abs(re[o, q].astype(np.int32) - ore).max() <= 1
+            assert np.abs(im[o, q].astype(np.int32) - oim).max() <= 1
+    mref = oracle.transfer_metrics(oracle.apply_basis(ref["coefs"], t), p["max_mg"])
+    for k in oracle.METRICS:
+        assert abs(met[k] - mref[k]) <= 1e-3, (k, met[k], mref[k])
+
+
 def test_sweep_rejections():
     torch = _torch()
     import paper_2204_02348_amd as dh
