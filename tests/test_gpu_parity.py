@@ -646,6 +646,24 @@ def test_mode0_coefficients_and_fields_vs_oracle(idx, cam, n, chunk):
     check_frames(p, f, gpu, range(n))
 
 
+def test_mode0_and_mode1_give_the_same_coefficients():
+    """The two IFFT resolution modes are two quadratures of one overlap: on
+    the GPU their coefficients agree as closely as the oracle's own modes."""
+    torch = _torch()
+    import paper_2204_02348_amd as dh
+    cfg, f, _ = _frames(1, n=20)
+    ft = torch.from_numpy(np.ascontiguousarray(f)).cuda()
+    out = {}
+    for mode in (1, 0):
+        plan = dh.Plan(dict(cfg["params"], ifft_mode=mode), max_batch=20)
+        plan.process(ft, 20, None)
+        out[mode] = plan.coefs(True).astype(np.complex128)
+        plan.destroy()
+    worst = max(_rel(out[0][i][q], out[1][i][q]) for i in range(20) for q in range(2))
+    _say("mode 0 vs mode 1 worst rel-L2 %.2e" % worst)
+    assert worst <= 2e-6
+
+
 def test_mode0_fields_across_export_groups():
     """1000 frames of 640x512 in IFFT mode 0 with fields: the export runs in
     groups of frames; sampled frames on both sides of each group edge."""
