@@ -12,6 +12,7 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -137,6 +138,48 @@ def time_variants(dh, torch, cfg, ft, B, stream, steps=20, warmup=10):
         torch.cuda.synchronize()
         plan.destroy()
         out[name] = {"input_frames_per_s": round(steps * B / (e0.elapsed_time(e1) / 1e3), 1), "outputs": n_out}
+    return out
+
+
+def time_aux(dh, torch, cfg, ft, B, stream, reps=20):
+    """The kernels around the path on the benchmark batch: the int16 field
+    conversion (HBM bound: 8 B read + 4 B written per field value) and the
+    nine transfer-matrix metrics of the 1000 x 90 matrix (FP64 Gram,
+    rocSOLVER eigenvalues, one host sync)."""
+    out = {}
+    plan = dh.Plan(dict(cfg["params"], keep_fields=1), max_batch=B)
+    plan.process(ft, B, stream)
+    stream.synchronize()
+    nf = B * cfg["params"]["pol_count"]
+    info = plan.info
+    flen = info.field_w * info.field_h
+    dev = ctypes.c_void_p()                # the plan's own device field buffer
+    if dh.lib().dh_get_fields(plan.handle, None, ctypes.byref(dev), None, None, None, None) != dh.SUCCESS:
+        raise RuntimeError("dh_get_fields")
+    fields = dev.value
+    re = torch.empty((nf, flen), dtype=torch.int16, device="cuda:0")
+    im = torch.empty_like(re)
+    sc = torch.empty(nf, dtype=torch.float32, device="cuda:0")
+    for _ in range(3):
+        dh.fields_to_int16(fields, nf, flen, re, im, sc, stream)
+    stream.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        dh.fields_to_int16(fields, nf, flen, re, im, sc, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    gbs = nf * flen * 12 / (ms * 1e-3) / 1e9
+    out["int16_fields"] = {"fields": nf, "values_per_field": flen, "ms": round(ms, 4), "achieved_GBs": round(gbs, 1),
+                           "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    plan.transfer_metrics()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.transfer_metrics()
+    out["transfer_metrics"] = {"matrix": f"{B} x {2 * info.modes}",
+                               "ms": round((time.perf_counter() - t0) / reps * 1e3, 3)}
+    plan.destroy()
     return out
 
 
@@ -396,6 +439,7 @@ def main():
     if not args.no_forms:
         out["forms"] = time_forms(dh, torch, cfg, ft, B, stream)
         out["variants"] = time_variants(dh, torch, cfg, ft, B, stream)
+        out["aux"] = time_aux(dh, torch, cfg, ft, B, stream)
         print("[bench] forms done", file=sys.stderr, flush=True)
     del ft
     if not args.no_serving:

@@ -156,38 +156,67 @@ hipError_t launch_moments(const float2* fields, int n, int wx, int wy, double px
   return hipGetLastError();
 }
 
-// k_q16: grid (n fields); block e: scale = 32767 / max(|Re|, |Im|) over field
-// e (1 if it is all zero), correctly rounded, then each part times the scale
-// rounded to the nearest integer, ties to even (all in FP32).
-__global__ void __launch_bounds__(256) k_q16(const float2* __restrict__ f, long long len, short* __restrict__ re,
+// k_q16: grid (n fields), TPB threads; block e: scale = 32767 / max(|Re|,
+// |Im|) over field e (1 if it is all zero), correctly rounded, then each part
+// times the scale rounded to the nearest integer, ties to even (all in FP32).
+// NV > 0: the field (len <= NV TPB) is read once into registers; NV = 0: read
+// twice (the second time mostly from L2).
+template <int TPB, int NV>
+__global__ void __launch_bounds__(TPB) k_q16(const float2* __restrict__ f, long long len, short* __restrict__ re,
                                              short* __restrict__ im, float* __restrict__ scale) {
-  __shared__ float red[256];
+  __shared__ float red[TPB];
   const int tid = threadIdx.x;
   const size_t base = (size_t)blockIdx.x * (size_t)len;
+  float2 v[NV > 0 ? NV : 1];
   float m = 0.f;
-  for (long long t = tid; t < len; t += 256) {
-    const float2 v = f[base + t];
-    m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
+  if constexpr (NV > 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const long long t = tid + (long long)k * TPB;
+      v[k] = t < len ? f[base + t] : make_float2(0.f, 0.f);
+      m = fmaxf(m, fmaxf(fabsf(v[k].x), fabsf(v[k].y)));
+    }
+  } else {
+    for (long long t = tid; t < len; t += TPB) {
+      const float2 x = f[base + t];
+      m = fmaxf(m, fmaxf(fabsf(x.x), fabsf(x.y)));
+    }
   }
   red[tid] = m;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
+  for (int w = TPB / 2; w > 0; w >>= 1) {
     if (tid < w) red[tid] = fmaxf(red[tid], red[tid + w]);
     __syncthreads();
   }
   const float peak = red[0];
   const float s = peak > 0.f ? __fdiv_rn(32767.0f, peak) : 1.0f;
-  for (long long t = tid; t < len; t += 256) {
-    const float2 v = f[base + t];
-    re[base + t] = (short)rintf(v.x * s);
-    im[base + t] = (short)rintf(v.y * s);
+  if constexpr (NV > 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const long long t = tid + (long long)k * TPB;
+      if (t < len) {
+        re[base + t] = (short)rintf(v[k].x * s);
+        im[base + t] = (short)rintf(v[k].y * s);
+      }
+    }
+  } else {
+    for (long long t = tid; t < len; t += TPB) {
+      const float2 x = f[base + t];
+      re[base + t] = (short)rintf(x.x * s);
+      im[base + t] = (short)rintf(x.y * s);
+    }
   }
   if (tid == 0) scale[blockIdx.x] = s;
 }
 
 hipError_t launch_q16(const float2* fields, int n, long long len, short* re, short* im, float* scale, hipStream_t s) {
   if (n < 1) return hipSuccess;
-  hipLaunchKernelGGL(k_q16, dim3(n), dim3(256), 0, s, fields, len, re, im, scale);
+  if (len <= 8 * 1024)
+    hipLaunchKernelGGL((k_q16<1024, 8>), dim3(n), dim3(1024), 0, s, fields, len, re, im, scale);
+  else if (len <= 24 * 1024)
+    hipLaunchKernelGGL((k_q16<1024, 24>), dim3(n), dim3(1024), 0, s, fields, len, re, im, scale);
+  else
+    hipLaunchKernelGGL((k_q16<1024, 0>), dim3(n), dim3(1024), 0, s, fields, len, re, im, scale);
   return hipGetLastError();
 }
 
