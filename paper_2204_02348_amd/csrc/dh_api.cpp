@@ -183,9 +183,9 @@ size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
 
 // mode-0 fields are made from the kept window after the coefficients
 bool exports(const Geom& g, const dh_params* p) { return g.mode == 0 && p->keep_fields; }
-// frames per export GEMM group: the x-transformed windows within 256 MiB
+// frames per export group: the y-transformed columns within 256 MiB
 int export_chunk(const Geom& g, const dh_params* p, int max_batch) {
-  const size_t per = (size_t)p->pol_count * g.wy * g.fx * 8;
+  const size_t per = (size_t)p->pol_count * g.fy * ((g.bx + 15) / 16 * 16) * 8;
   const long c = (long)((256ull << 20) / (per ? per : 1));
   return (int)std::max(1L, std::min<long>(c, max_batch));
 }
@@ -226,8 +226,8 @@ struct Layout {  // byte offsets inside one device allocation
   size_t pol_mrow[2], pol_rhox[2], pol_rhoy[2], pol_tx[2], pol_ty[2], pol_ux[2], pol_uy[2];
   size_t pol_uxs[2][4], pol_uys[2][4];   // split tables: bf16 hi, bf16 lo, fp16 hi, fp16 lo
   size_t pol_xs[2], pol_ys[2];           // spectral path tables
-  size_t pol_ex[2], pol_ey[2];           // mode-0 field export tables
-  size_t export_t;                       // mode-0 field export: the x-transformed windows
+  size_t pol_ex[2], pol_ey[2];           // mode-0 field export: phase tables along x and y
+  size_t export_t;                       // mode-0 field export: the y-transformed box columns
   size_t t1[4], f2[4], partial[4], capt, coefs, coefs_norm, window, fields, total;
 };
 
@@ -254,8 +254,8 @@ Layout layout(const Geom& g, const dh_params* p, int max_batch, int chunk, int n
     }
     L.pol_xs[q] = take(g.spec ? (size_t)g.bx * g.gp * 8 : 0);
     L.pol_ys[q] = take(g.spec ? (size_t)g.wyp * g.gp * 8 : 0);
-    L.pol_ex[q] = take(exports(g, p) ? (size_t)g.wx * g.fx * 8 : 0);
-    L.pol_ey[q] = take(exports(g, p) ? (size_t)g.fy * g.wy * 8 : 0);
+    L.pol_ex[q] = take(exports(g, p) ? (size_t)g.fx * 8 : 0);
+    L.pol_ey[q] = take(exports(g, p) ? (size_t)g.fy * 8 : 0);
   }
   const size_t P = p->pol_count;
   const size_t nm = g.nmodes > 0 ? g.nmodes : 1;
@@ -269,7 +269,8 @@ Layout layout(const Geom& g, const dh_params* p, int max_batch, int chunk, int n
   L.coefs_norm = take((size_t)max_batch * P * nm * 8);
   L.window = p->keep_window || exports(g, p) ? take((size_t)max_batch * P * g.wy * g.wx * 8) : 0;
   L.fields = p->keep_fields ? take((size_t)max_batch * P * g.fy * g.fx * 8) : 0;
-  L.export_t = exports(g, p) ? take((size_t)export_chunk(g, p, max_batch) * P * g.wy * g.fx * 8) : 0;
+  L.export_t = exports(g, p) ? take((size_t)export_chunk(g, p, max_batch) * P * g.fy * ((g.bx + 15) / 16 * 16) * 8)
+                              : 0;
   L.total = o;
   return L;
 }
@@ -437,29 +438,15 @@ std::vector<float2> spectral_axis(int nbox, int npad, int gp, int G, int uhi, in
   return t;
 }
 
-// Mode-0 field export table along one axis (FP64, stored FP32): for the
-// window grid cell q = u mod W of each bin u = u_hi - j of the box, and each
-// field sample x_k = (k - F/2) p' of the F-point grid,
-//   e[q][k] = norm e^{2 pi i u x_k / (N p)} e^{i phi(x_k)},
-// phi the tilt and defocus phase along the axis; zero for cells without a bin.
-// Stored [W][F], or transposed [F][W].
-std::vector<float2> export_axis(int uhi, int nbox, int w, int f, double tilt_bins, double defocus, double lam,
-                                double pitch, double norm, bool transposed) {
-  std::vector<float2> t((size_t)w * f, make_float2(0.f, 0.f));
-  for (int j = 0; j < nbox; ++j) {
-    const long long u = uhi - j;
-    long long qc = u % w;
-    if (qc < 0) qc += w;
-    for (int k = 0; k < f; ++k) {
-      const double x = (k - f / 2.0) * pitch;
-      // 2 pi (u + a) (k - f/2) / f, the bin phase reduced exactly first
-      long long e = (u * (2LL * k - f)) % (2LL * f);
-      if (e < 0) e += 2LL * f;
-      const double ph = kPi * (double)e / f + 2.0 * kPi * tilt_bins * (k - f / 2.0) / f + kPi * defocus * x * x / lam;
-      const cd v = std::exp(cd(0, ph)) * norm;
-      const size_t at = transposed ? (size_t)k * w + qc : (size_t)qc * f + k;
-      t[at] = make_float2((float)v.real(), (float)v.imag());
-    }
+// Mode-0 field export: the tilt and defocus phase along one axis of the
+// F-point field grid x_k = (k - F/2) p', times norm (FP64, stored FP32):
+//   e[k] = norm e^{i (2 pi a (k - F/2) / F + pi D x_k^2 / lambda)},  a the tilt in bins.
+std::vector<float2> export_phase(int f, double pitch, double tilt_bins, double defocus, double lam, double norm) {
+  std::vector<float2> t(f);
+  for (int k = 0; k < f; ++k) {
+    const double x = (k - f / 2.0) * pitch;
+    const cd v = std::exp(cd(0, 2.0 * kPi * tilt_bins * (k - f / 2.0) / f + kPi * defocus * x * x / lam)) * norm;
+    t[k] = make_float2((float)v.real(), (float)v.imag());
   }
   return t;
 }
@@ -516,8 +503,8 @@ PolTables pol_tables(const Geom& g, const PolGeom& P, const dh_params* p, int q,
                          inv, hy);
   }
   if (exp) {
-    t.ex = export_axis(P.uhi, P.uhi - P.ulo + 1, g.wx, g.fx, P.ax, p->defocus[q], lam, g.fpx, 1.0, false);
-    t.ey = export_axis(P.vhi, P.vhi - P.vlo + 1, g.wy, g.fy, P.ay, p->defocus[q], lam, g.fpy, inv, true);
+    t.ex = export_phase(g.fx, g.fpx, P.ax, p->defocus[q], lam, 1.0);
+    t.ey = export_phase(g.fy, g.fpy, P.ay, p->defocus[q], lam, inv);
   }
   return t;
 }
@@ -660,35 +647,35 @@ bool blas_on(Plan* pl, hipStream_t s) {
   return rocblas_set_stream(pl->blas, s) == rocblas_status_success;
 }
 
-// IFFT mode 0: the fields of frames [0, batch) from their kept windows,
-// E = Ey W Ex per frame and pol (the export tables), as two complex GEMMs
-// per pol over groups of frames; row-major arrays are read as transposed
-// column-major ones: T^T = Ex^T W^T, then E^T = T^T Ey^T.
-int export_fields(Plan* pl, int first, int count, int stride, const char* const ex[2], const char* const ey[2],
-                  hipStream_t s) {
+// IFFT mode 0: the fields of `count` output frames (first, first + stride,
+// ...) from their kept windows, with wavelength lam's tables and geometry (lam
+// < 0: the plan's): the window's bins zero-padded to the N_y x N_x grid and
+// inverse transformed, y first (k_m0y, into the scratch, per group of frames)
+// then x (k_m0x), with the tilt/defocus phase and 1/(Nx Ny) applied.
+int export_fields(Plan* pl, int first, int count, int stride, int lam, hipStream_t s) {
   const Geom& g = pl->g;
   const int P = pl->params.pol_count;
-  if (!blas_on(pl, s)) return DH_ERR_ERROR;
-  const rocblas_float_complex one = {1.f, 0.f}, zero = {0.f, 0.f};
-  auto cx = [&](size_t off) { return (rocblas_float_complex*)(pl->mem + off); };
+  dh::M0Args m{};
+  m.win = (const float2*)(pl->mem + pl->L.window);
+  m.t2 = (float2*)(pl->mem + pl->L.export_t);
+  m.fields = (float2*)(pl->mem + pl->L.fields);
+  m.tw_nx = pl->ka[0].tw_nx;
+  m.tw_ny = pl->ka[0].tw_ny;
+  m.nx = g.nx; m.ny = g.ny; m.wx = g.wx; m.wy = g.wy; m.bxp = (g.bx + 15) / 16 * 16; m.npol = P;
+  m.stride = stride;
+  for (int q = 0; q < P; ++q) {
+    const PolGeom& G = lam >= 0 ? pl->lam_geom[(size_t)lam * 2 + q] : g.pol[q];
+    m.pol[q].uhi = G.uhi; m.pol[q].vhi = G.vhi;
+    m.pol[q].bxq = G.uhi - G.ulo + 1; m.pol[q].byq = G.vhi - G.vlo + 1;
+    const char* base = lam >= 0 ? pl->lmem : pl->mem;
+    m.pol[q].phx = (const float2*)(base + (lam >= 0 ? pl->lam_tab[(size_t)lam * 2 + q].ex : pl->L.pol_ex[q]));
+    m.pol[q].phy = (const float2*)(base + (lam >= 0 ? pl->lam_tab[(size_t)lam * 2 + q].ey : pl->L.pol_ey[q]));
+  }
   const int grp = export_chunk(g, &pl->params, pl->max_batch);
   for (int c0 = 0; c0 < count; c0 += grp) {
+    m.first = first + c0 * stride;
     const int nb = std::min(grp, count - c0);
-    const size_t b0 = (size_t)first + (size_t)c0 * stride;   // output frame of the group's first field
-    for (int q = 0; q < P; ++q) {
-      const rocblas_float_complex* win = cx(pl->L.window) + (b0 * P + q) * g.wy * g.wx;
-      rocblas_float_complex* t = cx(pl->L.export_t) + (size_t)q * g.wy * g.fx;
-      rocblas_float_complex* f = cx(pl->L.fields) + (b0 * P + q) * g.fy * g.fx;
-      if (rocblas_cgemm_strided_batched(pl->blas, rocblas_operation_none, rocblas_operation_none, g.fx, g.wy, g.wx,
-                                        &one, (const rocblas_float_complex*)ex[q], g.fx, 0, win, g.wx,
-                                        (rocblas_stride)stride * P * g.wy * g.wx, &zero, t, g.fx,
-                                        (rocblas_stride)P * g.wy * g.fx, nb) != rocblas_status_success ||
-          rocblas_cgemm_strided_batched(pl->blas, rocblas_operation_none, rocblas_operation_none, g.fx, g.fy, g.wy,
-                                        &one, t, g.fx, (rocblas_stride)P * g.wy * g.fx,
-                                        (const rocblas_float_complex*)ey[q], g.wy, 0, &zero, f, g.fx,
-                                        (rocblas_stride)stride * P * g.fy * g.fx, nb) != rocblas_status_success)
-        return DH_ERR_ERROR;
-    }
+    if (dh::launch_m0y(m, nb, s) != hipSuccess || dh::launch_m0x(m, nb, s) != hipSuccess) return DH_ERR_ERROR;
   }
   return DH_SUCCESS;
 }
@@ -982,15 +969,10 @@ int dh_process_batch(dh_handle h, const void* frames, int batch, void* stream) {
     // each output's fields from its window, with its wavelength's tables
     const int L = std::max(pl->nlam, 1), I = batch / L;
     for (int w = 0; w < L; ++w) {
-      const char* ex[2] = {nullptr, nullptr};
-      const char* ey[2] = {nullptr, nullptr};
-      for (int q = 0; q < P; ++q) {
-        ex[q] = pl->nlam > 0 ? pl->lmem + pl->lam_tab[(size_t)w * 2 + q].ex : pl->mem + pl->L.pol_ex[q];
-        ey[q] = pl->nlam > 0 ? pl->lmem + pl->lam_tab[(size_t)w * 2 + q].ey : pl->mem + pl->L.pol_ey[q];
-      }
       const bool fast = pl->nlam > 0 && pl->out_order == DH_WL_FAST;
       const int first = pl->nlam > 0 ? (fast ? w : w * I) : 0, count = pl->nlam > 0 ? I : batch;
-      if (export_fields(pl, first, count, fast ? L : 1, ex, ey, s) != DH_SUCCESS) return set_err(pl, DH_ERR_ERROR);
+      if (export_fields(pl, first, count, fast ? L : 1, pl->nlam > 0 ? w : -1, s) != DH_SUCCESS)
+        return set_err(pl, DH_ERR_ERROR);
     }
   }
   pl->last_batch = batch;
@@ -1811,8 +1793,8 @@ extern "C" int dh_set_wavelengths(dh_handle h, const double* lambdas, int count,
         t.tx = take(g.wx * 8); t.ty = take(g.wy * 8);
         t.xs = g.spec ? take((size_t)g.bx * g.gp * 8) : 0;
         t.ys = g.spec ? take((size_t)g.wyp * g.gp * 8) : 0;
-        t.ex = exp ? take((size_t)g.wx * g.fx * 8) : 0;
-        t.ey = exp ? take((size_t)g.fy * g.wy * 8) : 0;
+        t.ex = exp ? take((size_t)g.fx * 8) : 0;
+        t.ey = exp ? take((size_t)g.fy * 8) : 0;
       }
     if (hipMalloc(&pl->lmem, o) != hipSuccess) {
       (void)hipGetLastError();

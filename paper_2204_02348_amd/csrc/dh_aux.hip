@@ -8,9 +8,12 @@
 //   k_tm_rows  row statistics of the matrix the diagonal metrics are taken on
 //   k_q16      fields to int16 real and imaginary parts with one scale each
 //   k_basis    HG coefficients to another basis (LG, custom): one matrix product
+//   k_m0y, k_m0x  IFFT mode 0 field export: the window zero-padded to the FFT
+//              grid and inverse transformed along y, then x (LDS FFTs)
 //   k_fptr, k_avg_rot, k_comb_*   wavelength sweeps and frame averaging: the
 //              frame of each staged position, the phase of each repetition,
 //              and the outputs combined from the staged results
+#include "dh_fft.hpp"
 #include "dh_internal.hpp"
 
 namespace dh {
@@ -396,6 +399,116 @@ hipError_t launch_comb_plane(const float2* in, const double2* rot, long long per
   hipLaunchKernelGGL(k_comb_plane, dim3((unsigned)bx, (unsigned)(n_out < 65535 ? n_out : 65535)), dim3(256), 0, s, in,
                      rot, per, c, n_out, out);
   return hipGetLastError();
+}
+
+// k_m0y: grid (ceil(bx / CG), npol, frames). Column j of the box (bin
+// u = uhi - j) of output frame first + z stride: its window bins v = vhi - i
+// (cell (v mod wy, u mod wx)) placed at v mod Ny with the factor (-1)^v of
+// the grid origin, inverse transformed (forward FFT of the conjugate,
+// conjugated back), times the y phase: t2[z][p][l][j].
+template <int NY, int CG>
+__global__ void __launch_bounds__(256) k_m0y(M0Args m) {
+  using LN = Lds<NY>;
+  constexpr int ST = LN::STRIDE;
+  __shared__ float2 buf[CG * ST];
+  const int tid = threadIdx.x, p = blockIdx.y, z = blockIdx.z;
+  const int jc0 = blockIdx.x * CG;
+  const auto& P = m.pol[p];
+  const size_t fr = (size_t)m.first + (size_t)z * m.stride;
+  const float2* win = m.win + (fr * m.npol + p) * m.wy * m.wx;
+  for (int e = tid; e < CG * ST; e += 256) buf[e] = make_float2(0.f, 0.f);
+  __syncthreads();
+  for (int e = tid; e < CG * P.byq; e += 256) {
+    const int c = e % CG, i = e / CG, j = jc0 + c;
+    if (j >= P.bxq) continue;
+    const int u = P.uhi - j, v = P.vhi - i;
+    int qu = u % m.wx, qv = v % m.wy, rv = v % NY;
+    if (qu < 0) qu += m.wx;
+    if (qv < 0) qv += m.wy;
+    if (rv < 0) rv += NY;
+    const float2 w = win[(size_t)qv * m.wx + qu];
+    const float sg = (v & 1) ? -1.f : 1.f;
+    buf[c * ST + LN::at(rv)] = make_float2(sg * w.x, -sg * w.y);
+  }
+  __syncthreads();
+  fft_lds<NY, CG, ST, 256>(buf, m.tw_ny, tid);
+  __syncthreads();
+  float2* out = m.t2 + ((size_t)z * m.npol + p) * NY * m.bxp;
+  for (int e = tid; e < CG * NY; e += 256) {
+    const int c = e % CG, l = e / CG, j = jc0 + c;
+    if (j >= P.bxq) continue;
+    const float2 y = buf[c * ST + LN::at(l)];
+    const float2 ph = P.phy[l];
+    // conj(y) * ph
+    out[(size_t)l * m.bxp + j] = make_float2(y.x * ph.x + y.y * ph.y, y.x * ph.y - y.y * ph.x);
+  }
+}
+
+// k_m0x: grid (ceil(Ny / TR), npol, frames). Rows l of t2: the box columns
+// placed at u mod Nx with the factor (-1)^u, inverse transformed as above,
+// times the x phase: the field row fields[fr][p][l][0..Nx).
+template <int NX, int TR>
+__global__ void __launch_bounds__(256) k_m0x(M0Args m) {
+  using LN = Lds<NX>;
+  constexpr int ST = LN::STRIDE;
+  __shared__ float2 buf[TR * ST];
+  const int tid = threadIdx.x, p = blockIdx.y, z = blockIdx.z;
+  const int l0 = blockIdx.x * TR;
+  const auto& P = m.pol[p];
+  const size_t fr = (size_t)m.first + (size_t)z * m.stride;
+  const float2* in = m.t2 + ((size_t)z * m.npol + p) * m.ny * m.bxp;
+  for (int e = tid; e < TR * ST; e += 256) buf[e] = make_float2(0.f, 0.f);
+  __syncthreads();
+  for (int e = tid; e < TR * P.bxq; e += 256) {
+    const int r = e / P.bxq, j = e % P.bxq, l = l0 + r;
+    if (l >= m.ny) continue;
+    const int u = P.uhi - j;
+    int ru = u % NX;
+    if (ru < 0) ru += NX;
+    const float2 t = in[(size_t)l * m.bxp + j];
+    const float sg = (u & 1) ? -1.f : 1.f;
+    buf[r * ST + LN::at(ru)] = make_float2(sg * t.x, -sg * t.y);
+  }
+  __syncthreads();
+  fft_lds<NX, TR, ST, 256>(buf, m.tw_nx, tid);
+  __syncthreads();
+  float2* out = m.fields + (fr * m.npol + p) * (size_t)m.ny * NX;
+  for (int e = tid; e < TR * NX; e += 256) {
+    const int r = e / NX, k = e % NX, l = l0 + r;
+    if (l >= m.ny) continue;
+    const float2 y = buf[r * ST + LN::at(k)];
+    const float2 ph = P.phx[k];
+    out[(size_t)l * NX + k] = make_float2(y.x * ph.x + y.y * ph.y, y.x * ph.y - y.y * ph.x);
+  }
+}
+
+#define DH_M0_SIZES(X) X(64) X(128) X(256) X(320) X(512) X(640) X(1024) X(2048)
+
+hipError_t launch_m0y(const M0Args& m, int nb, hipStream_t s) {
+  if (nb < 1) return hipSuccess;
+  const int bx = std::max(m.pol[0].bxq, m.npol > 1 ? m.pol[1].bxq : 0);
+#define X(N)                                                                                           \
+  if (m.ny == N) {                                                                                    \
+    constexpr int CG = N >= 1024 ? 4 : 8;                                                             \
+    hipLaunchKernelGGL((k_m0y<N, CG>), dim3((bx + CG - 1) / CG, m.npol, nb), dim3(256), 0, s, m);     \
+    return hipGetLastError();                                                                         \
+  }
+  DH_M0_SIZES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_m0x(const M0Args& m, int nb, hipStream_t s) {
+  if (nb < 1) return hipSuccess;
+#define X(N)                                                                                           \
+  if (m.nx == N) {                                                                                    \
+    constexpr int TR = N >= 2048 ? 2 : N >= 1024 ? 4 : 8;                                             \
+    hipLaunchKernelGGL((k_m0x<N, TR>), dim3((m.ny + TR - 1) / TR, m.npol, nb), dim3(256), 0, s, m);   \
+    return hipGetLastError();                                                                         \
+  }
+  DH_M0_SIZES(X)
+#undef X
+  return hipErrorInvalidValue;
 }
 
 }  // namespace dh

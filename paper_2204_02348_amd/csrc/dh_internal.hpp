@@ -118,6 +118,25 @@ hipError_t launch_comb_coefs(const float2* sc, const float2* scn, const double2*
                              float2* out, float2* out_norm, hipStream_t s);
 hipError_t launch_comb_plane(const float2* in, const double2* rot, long long per, const Comb& c, int n_out, float2* out,
                              hipStream_t s);
+// IFFT mode 0 field export: output frames first + z stride (z < the launch's
+// frames) of the window [frame][pol][wy][wx] to fields [frame][pol][ny][nx];
+// t2 [z][pol][ny][bxp] holds the y-transformed box columns of the group
+struct M0Args {
+  const float2* win;
+  float2* t2;
+  float2* fields;
+  const float2* tw_nx;     // per-pass twiddles of the N_x and N_y transforms
+  const float2* tw_ny;
+  int nx, ny, wx, wy, bxp, npol;
+  int first, stride;
+  struct {
+    int uhi, vhi, bxq, byq;  // box: column j is bin uhi - j, row i is bin vhi - i
+    const float2* phx;       // [nx] tilt/defocus phase along x
+    const float2* phy;       // [ny] the same along y, times 1/(Nx Ny)
+  } pol[2];
+};
+hipError_t launch_m0y(const M0Args& m, int nb, hipStream_t s);
+hipError_t launch_m0x(const M0Args& m, int nb, hipStream_t s);
 // fields to int16 (re, im) with one FP32 scale per field: n fields of len values
 hipError_t launch_q16(const float2* fields, int n, long long len, short* re, short* im, float* scale, hipStream_t s);
 // basis transform of n coefficient vectors (frame x pol): out[e][k] = sum over
