@@ -98,7 +98,8 @@ typedef struct dh_params {
                                  0: the field on the FFT grid (N points, the camera pitch). Mode 0
                                  runs the spectral path (needs FP32 and G >= 1): the coefficients
                                  take the overlap over the FFT grid, and fields (keep_fields) are
-                                 made from the kept window by two complex GEMMs per pol */
+                                 the kept window zero-padded to the FFT grid and inverse
+                                 transformed at full size */
   int keep_window;            /* nonzero: store each frame's Fourier window (dh_get_window) */
   int keep_fields;            /* nonzero: store each frame's field (dh_get_fields) */
   int path;                   /* DH_PATH_*; SPECTRAL with keep_fields (mode 1), a split precision

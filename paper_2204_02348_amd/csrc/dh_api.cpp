@@ -166,7 +166,7 @@ int derive(const dh_params* p, Geom* g) {
   g->byp = (g->by + 15) / 16 * 16;
   if (g->mode == 0) {
     // IFFT mode 0: the coefficients come from spectral tables built on the FFT
-    // grid, the fields (on request) from the kept window by two complex GEMMs
+    // grid, the fields (on request) from the kept window by full-size inverse FFTs
     if (p->path == DH_PATH_FIELD || p->precision != DH_PREC_FP32 || g->G == 0) return DH_ERR_INVALIDARGUMENT;
     if (!dh::spectral_supported(ny, g->wy, g->gp)) return DH_ERR_INVALIDDIMENSION;
     g->spec = true;
