@@ -228,9 +228,20 @@ __device__ __forceinline__ void dft(float2* v) {
 template <int PAD>
 __device__ __forceinline__ int padi(int i) { return i + i / PAD; }
 
-// buf: LDS; tw: this pass's twiddle table (see fft_lds).
-template <int N, int R, int NS, int NTR, int STRIDE, int TPB, int PAD>
-__device__ __forceinline__ void stockham_pass(float2* buf, const float2* __restrict__ tw, int tid) {
+// a twiddle-table entry from LDS / generic memory, or from the global address
+// space (read as a plain vector: the float2 class cannot be copied from there)
+typedef float tw_floatx2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2 ld_tw(const float2* __restrict__ t, int i) { return t[i]; }
+__device__ __forceinline__ float2 ld_tw(const __attribute__((address_space(1))) float2* t, int i) {
+  const tw_floatx2 v = reinterpret_cast<const __attribute__((address_space(1))) tw_floatx2*>(t)[i];
+  return make_float2(v.x, v.y);
+}
+
+// buf: LDS; tw: this pass's twiddle table (see fft_lds), in LDS or, where a
+// workgroup's LDS is better spent on occupancy, in global memory (TW is then a
+// global-address-space pointer, read through the caches).
+template <int N, int R, int NS, int NTR, int STRIDE, int TPB, int PAD, typename TW>
+__device__ __forceinline__ void stockham_pass(float2* buf, TW tw, int tid) {
   constexpr int NB = N / R;
   constexpr int TOTAL = NTR * NB;
   constexpr int IT = (TOTAL + TPB - 1) / TPB;
@@ -255,7 +266,7 @@ __device__ __forceinline__ void stockham_pass(float2* buf, const float2* __restr
       if constexpr (NS > 1) {
         // this pass's twiddles e^{-2 pi i k r/(NS R)}, stored [r-1][k]
 #pragma unroll
-        for (int r = 1; r < R; ++r) v[it][r] = cmul(v[it][r], tw[(r - 1) * NS + k]);
+        for (int r = 1; r < R; ++r) v[it][r] = cmul(v[it][r], ld_tw(tw, (r - 1) * NS + k));
       }
       dft<R>(v[it]);
       float2* dst = buf + tr * STRIDE;
@@ -326,8 +337,8 @@ __device__ __forceinline__ void fft_pass1_regs(float2 (*v)[FftPlan<N>::R0], floa
 }
 
 // Passes 2.. of the transform (starts and ends with a barrier).
-template <int N, int NTR, int STRIDE, int TPB>
-__device__ __forceinline__ void fft_rest(float2* buf, const float2* __restrict__ tw, int tid) {
+template <int N, int NTR, int STRIDE, int TPB, typename TW>
+__device__ __forceinline__ void fft_rest(float2* buf, TW tw, int tid) {
   using P = FftPlan<N>;
   constexpr int PAD = P::R0;
   __syncthreads();

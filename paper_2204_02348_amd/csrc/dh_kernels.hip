@@ -345,8 +345,14 @@ __global__ void __launch_bounds__(kTPB) k_cspec(KArgs A, int b0) {
   constexpr int NQ = CG * GP;                      // float2: Q
   constexpr bool IN_BUF = NRED * 4 + NQ * 8 <= CG * ST * 8;
   static_assert(KSW * NT <= 96, "B operands are held in registers");
+  // From 1024 rows on, the twiddles are read through the caches instead of LDS
+  // wherever that lets one more workgroup onto a CU (160 KB of LDS each); at
+  // 512 rows the extra workgroup measured slower than the LDS reads it saves.
+  constexpr int LDS_REST = CG * ST * 8 + WYP * 8 + CG * GP * 8 + 16 + (IN_BUF ? 8 : (NRED / 2 + NQ) * 8);
+  constexpr int LDS_CU = 160 * 1024;
+  constexpr bool TWG = NY >= 1024 && LDS_CU / LDS_REST > LDS_CU / (LDS_REST + twn<NY>() * 8);
   __shared__ float2 buf[CG * ST];
-  __shared__ float2 twy[twn<NY>()];
+  __shared__ float2 twy[TWG ? 1 : twn<NY>()];
   __shared__ int2 s_mrow[WYP];
   __shared__ float2 s_x[CG * GP];                  // xs rows of the block's columns
   __shared__ float s_pw[4];
@@ -358,10 +364,10 @@ __global__ void __launch_bounds__(kTPB) k_cspec(KArgs A, int b0) {
   const PolTab& P = A.pol[p];
   const int jc0 = blockIdx.x * CG;
   // tables first: their loads are in flight with the column loads
-  Staged<float2, twn<NY>(), kTPB> stwy;
+  Staged<float2, TWG ? 1 : twn<NY>(), kTPB> stwy;
   Staged<int2, WYP, kTPB> smr;
   Staged<float2, CG * GP, kTPB> sx;
-  stwy.load(A.tw_ny, twn<NY>(), tid);
+  if constexpr (!TWG) stwy.load(A.tw_ny, twn<NY>(), tid);
   smr.load(P.mrow, A.by, tid);
   const int ncx = A.bx - jc0 < CG ? A.bx - jc0 : CG;
   sx.load(P.xs + (size_t)jc0 * GP, ncx * GP, tid);
@@ -402,12 +408,15 @@ __global__ void __launch_bounds__(kTPB) k_cspec(KArgs A, int b0) {
         for (int r = 0; r < Q::R0; ++r) v[it][r] = buf_ld_nt(rt, (int)t1_at(j, b + r * Q::NB, A.bx) * 8, 0);
       }
     }
-    stwy.store(twy, twn<NY>(), make_float2(0.f, 0.f), tid);
+    if constexpr (!TWG) stwy.store(twy, twn<NY>(), make_float2(0.f, 0.f), tid);
     smr.store(s_mrow, A.by, make_int2(1, 0), tid);
     sx.store(s_x, ncx * GP, make_float2(0.f, 0.f), tid);
     fft_pass1_regs<NY, CG, ST, kTPB>(v, buf, tid);
   }
-  fft_rest<NY, CG, ST, kTPB>(buf, twy, tid);
+  if constexpr (TWG)
+    fft_rest<NY, CG, ST, kTPB>(buf, as_global(A.tw_ny), tid);
+  else
+    fft_rest<NY, CG, ST, kTPB>(buf, static_cast<const float2*>(twy), tid);
   if (A.window) {
     // window = M * I~ = conj(val) (-1)^(u+v) Nx Ny at (v mod wy, u mod wx), as in k_col
     float2* win = A.window + ((size_t)(b0 + bl) * A.npol + p) * A.wy * A.wx;
