@@ -132,14 +132,17 @@ __global__ void __launch_bounds__(TR * NX / FftPlan<NX>::R0) k_row(KArgs A, cons
   using Q = Pass1<NX, TR, TR * NX / FftPlan<NX>::R0>;
   constexpr int TPB = TR * NX / FftPlan<NX>::R0;
   static_assert(Q::IT == 1, "one first-pass butterfly per thread");
+  // 2048-point rows: the twiddles (16 KB) are read through the caches, so
+  // that two 512-thread workgroups fit on a CU
+  constexpr bool TWG = NX >= 2048;
   __shared__ float2 buf[TR * L::STRIDE];
-  __shared__ float2 tws[twn<NX>()];
+  __shared__ float2 tws[TWG ? 1 : twn<NX>()];
   const int tid = threadIdx.x;
   const int p = blockIdx.y;
   const int bl = blockIdx.z;                 // frame within the chunk
   const PolTab& P = A.pol[p];
-  Staged<float2, twn<NX>(), TPB> stw;
-  stw.load(A.tw_nx, twn<NX>(), tid);
+  Staged<float2, TWG ? 1 : twn<NX>(), TPB> stw;
+  if constexpr (!TWG) stw.load(A.tw_nx, twn<NX>(), tid);
   const TIn* fr = A.fptr ? static_cast<const TIn*>(A.fptr[b0 + bl]) : frames + (size_t)(b0 + bl) * A.frame_h * A.frame_w;
   const gptr<TIn> win = as_global(fr) + ((size_t)P.y0 * A.frame_w + P.x0);
   // the operands of every tile are requested up front: later tiles' loads are
@@ -159,7 +162,7 @@ __global__ void __launch_bounds__(TR * NX / FftPlan<NX>::R0) k_row(KArgs A, cons
         v[tt][r].x = load_px(r0 + r * Q::NB);
         v[tt][r].y = load_px(r1 + r * Q::NB);
       }
-      if (tt == 0) stw.store(tws, twn<NX>(), make_float2(0.f, 0.f), tid);
+      if constexpr (!TWG) if (tt == 0) stw.store(tws, twn<NX>(), make_float2(0.f, 0.f), tid);
     }
   }
   float2* out = A.t1 + (size_t)(bl * A.npol + p) * A.bx * A.ny;
@@ -168,7 +171,10 @@ __global__ void __launch_bounds__(TR * NX / FftPlan<NX>::R0) k_row(KArgs A, cons
     const int ybase = (blockIdx.x * TT + tt) * (2 * TR);
     if (tt > 0) __syncthreads();           // the previous tile's split has read buf
     fft_pass1_regs<NX, TR, L::STRIDE, TPB>(v + tt, buf, tid);
-    fft_rest<NX, TR, L::STRIDE, TPB>(buf, tws, tid);
+    if constexpr (TWG)
+      fft_rest<NX, TR, L::STRIDE, TPB>(buf, as_global(A.tw_nx), tid);
+    else
+      fft_rest<NX, TR, L::STRIDE, TPB>(buf, static_cast<const float2*>(tws), tid);
     // two-for-one split at the kept bins: both rows of a pair from Z[k], Z[NX-k]
     for (int e = tid; e < TR * A.bx; e += TPB) {
       const int t = e % TR, j = e / TR;
@@ -1058,8 +1064,10 @@ __global__ void k_zero(float2* p, size_t n) {
 // transforms per row-pass block and columns per column-pass block (~32-80 KB of LDS)
 // row pass: TR transforms per block so that TR * N / R0 (the block size) is 256
 // or 320; at N = 320, 8 transforms (160 threads, 22 KB of LDS: 7 blocks per CU)
-// measured faster than 16 (320 threads, 3 blocks per CU)
-template <int N> constexpr int row_tr() { return 256 / (N / FftPlan<N>::R0) > 0 ? (N == 320 ? 8 : N == 640 ? 4 : 256 / (N / FftPlan<N>::R0)) : 1; }
+// measured faster than 16 (320 threads, 3 blocks per CU). At N = 2048, 4
+// transforms (512 threads): each block then writes 64 B of every t1 tile line
+// (2 transforms, 32 B pieces: 0.51 -> 0.30 ms per 64 frames with one tile)
+template <int N> constexpr int row_tr() { return 256 / (N / FftPlan<N>::R0) > 0 ? (N == 320 ? 8 : N == 640 ? 4 : N == 2048 ? 4 : 256 / (N / FftPlan<N>::R0)) : 1; }
 template <int N> constexpr int col_cg() { return N >= 2048 ? 4 : N >= 1024 ? 4 : N >= 512 ? 8 : 16; }
 // the spectral column pass: at 1024 rows with one mode tile 8 columns fit
 // (1024-row camera: 0.253 -> 0.230 ms per 256 frames; with two mode tiles
@@ -1075,7 +1083,8 @@ static hipError_t row_n(const KArgs& a, const void* frames, int u16, int b0, int
   // tile's transform) when that still leaves the chip well filled; one tile
   // for small batches, where latency matters more
   const int nyb = (a.ny + 2 * TR - 1) / (2 * TR);
-  const bool two = (long)((nyb + 1) / 2) * a.npol * nb >= 4096;
+  // one tile at 2048: the second tile's registers would cost a workgroup per CU
+  const bool two = NX < 2048 && (long)((nyb + 1) / 2) * a.npol * nb >= 4096;
   dim3 grid(two ? (nyb + 1) / 2 : nyb, a.npol, nb);
   if (u16) {
     if (two)
