@@ -401,6 +401,18 @@ hipError_t launch_comb_plane(const float2* in, const double2* rot, long long per
   return hipGetLastError();
 }
 
+// The t2 intermediate and the fields are streamed (each element written and
+// read once): non-temporal stores and loads.
+typedef float m0_floatx2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void m0_st_nt(float2* p, float2 v) {
+  const m0_floatx2 t = {v.x, v.y};
+  __builtin_nontemporal_store(t, reinterpret_cast<m0_floatx2*>(p));
+}
+__device__ __forceinline__ float2 m0_ld_nt(const float2* p) {
+  const m0_floatx2 t = __builtin_nontemporal_load(reinterpret_cast<const m0_floatx2*>(p));
+  return make_float2(t.x, t.y);
+}
+
 // k_m0y: grid (ceil(bx / CG), npol, frames). Column j of the box (bin
 // u = uhi - j) of output frame first + z stride: its window bins v = vhi - i
 // (cell (v mod wy, u mod wx)) placed at v mod Ny with the factor (-1)^v of
@@ -440,7 +452,7 @@ __global__ void __launch_bounds__(256) k_m0y(M0Args m) {
     const float2 y = buf[c * ST + LN::at(l)];
     const float2 ph = P.phy[l];
     // conj(y) * ph
-    out[(size_t)l * m.bxp + j] = make_float2(y.x * ph.x + y.y * ph.y, y.x * ph.y - y.y * ph.x);
+    m0_st_nt(out + (size_t)l * m.bxp + j, make_float2(y.x * ph.x + y.y * ph.y, y.x * ph.y - y.y * ph.x));
   }
 }
 
@@ -465,7 +477,7 @@ __global__ void __launch_bounds__(256) k_m0x(M0Args m) {
     const int u = P.uhi - j;
     int ru = u % NX;
     if (ru < 0) ru += NX;
-    const float2 t = in[(size_t)l * m.bxp + j];
+    const float2 t = m0_ld_nt(in + (size_t)l * m.bxp + j);
     const float sg = (u & 1) ? -1.f : 1.f;
     buf[r * ST + LN::at(ru)] = make_float2(sg * t.x, -sg * t.y);
   }
@@ -478,7 +490,7 @@ __global__ void __launch_bounds__(256) k_m0x(M0Args m) {
     if (l >= m.ny) continue;
     const float2 y = buf[r * ST + LN::at(k)];
     const float2 ph = P.phx[k];
-    out[(size_t)l * NX + k] = make_float2(y.x * ph.x + y.y * ph.y, y.x * ph.y - y.y * ph.x);
+    m0_st_nt(out + (size_t)l * NX + k, make_float2(y.x * ph.x + y.y * ph.y, y.x * ph.y - y.y * ph.x));
   }
 }
 
