@@ -1066,10 +1066,14 @@ __global__ void k_zero(float2* p, size_t n) {
 // transforms per row-pass block and columns per column-pass block (~32-80 KB of LDS)
 // row pass: TR transforms per block so that TR * N / R0 (the block size) is 256
 // or 320; at N = 320, 8 transforms (160 threads, 22 KB of LDS: 7 blocks per CU)
-// measured faster than 16 (320 threads, 3 blocks per CU). At N = 2048, 4
-// transforms (512 threads): each block then writes 64 B of every t1 tile line
-// (2 transforms, 32 B pieces: 0.51 -> 0.30 ms per 64 frames with one tile)
-template <int N> constexpr int row_tr() { return 256 / (N / FftPlan<N>::R0) > 0 ? (N == 320 ? 8 : N == 640 ? 4 : N == 2048 ? 4 : 256 / (N / FftPlan<N>::R0)) : 1; }
+// measured faster than 16 (320 threads, 3 blocks per CU). At N = 512 and
+// 1024, 8 transforms (512 threads), so that a block writes whole 128 B t1
+// tile lines (with 4 transforms: 0.726 -> 0.626 ms per 500 two-pol 1024x1024
+// frames, 0.257 -> 0.243 ms per 256 one-pol 1024x1024 u16 frames). At
+// N = 2048, 4 transforms (512 threads): each block then writes 64 B of every
+// t1 tile line (2 transforms, 32 B pieces: 0.51 -> 0.30 ms per 64 frames with
+// one tile)
+template <int N> constexpr int row_tr() { return 256 / (N / FftPlan<N>::R0) > 0 ? (N == 320 ? 8 : N == 640 ? 4 : N == 2048 ? 4 : N == 512 ? 8 : N == 1024 ? 8 : 256 / (N / FftPlan<N>::R0)) : 1; }
 template <int N> constexpr int col_cg() { return N >= 2048 ? 4 : N >= 1024 ? 4 : N >= 512 ? 8 : 16; }
 // the spectral column pass: at 1024 rows with one mode tile 8 columns fit
 // (1024-row camera: 0.253 -> 0.230 ms per 256 frames; with two mode tiles
