@@ -1117,8 +1117,12 @@ double db10(double x) {
 }
 
 // The nine metrics of the transfer matrix of the B frames whose raw
-// coefficients are in ka[0].coefs, on stream s (synchronises it).
-int tm_compute(Plan* pl, int B, int pol_independent, int mul_conj_trans, hipStream_t s, double* out) {
+// coefficients are in ka[0].coefs, on stream s (synchronises it). IL is the
+// Gram matrix's trace over n (the sum of the s_k^2); only MDL needs the
+// eigenvalues, and with eig = false (a goal other than MDL) the eigen-solver
+// is skipped and out[MDL] is NaN.
+int tm_compute(Plan* pl, int B, int pol_independent, int mul_conj_trans, hipStream_t s, double* out,
+               bool eig = true) {
   const int P = pl->params.pol_count, M = pl->g.nmodes;
   if (B < 1 || M < 1) return DH_ERR_ERROR;
   const int MC = pl->basis != DH_BASIS_HG ? pl->bout : M;   // columns per pol of the matrix
@@ -1173,28 +1177,38 @@ int tm_compute(Plan* pl, int B, int pol_independent, int mul_conj_trans, hipStre
       dh::launch_tm_rows(t, aa ? gd : nullptr, t.rows, ncol, nd, (double*)(m + orow), (double*)(m + odg),
                          (double*)(m + osm), s) != hipSuccess)
     return DH_ERR_ERROR;
-  if (rocsolver_zheevd(pl->blas, rocblas_evect_none, rocblas_fill_upper, n, (rocblas_double_complex*)g, n,
-                       (double*)(m + oe), (double*)(m + ow), (rocblas_int*)(m + oi)) != rocblas_status_success)
+  // the Gram's diagonal (real), read before the eigen-solver overwrites it
+  std::vector<double> gdiag(n), eigv(eig ? n : 0), rowp(t.rows), dg(nd), sm(nd);
+  if (hipMemcpy2DAsync(gdiag.data(), 8, g, (size_t)(n + 1) * 16, 8, n, hipMemcpyDeviceToHost, s) != hipSuccess)
     return DH_ERR_ERROR;
-  std::vector<double> eig(n), rowp(t.rows), dg(nd), sm(nd);
+  if (eig && rocsolver_zheevd(pl->blas, rocblas_evect_none, rocblas_fill_upper, n, (rocblas_double_complex*)g, n,
+                              (double*)(m + oe), (double*)(m + ow), (rocblas_int*)(m + oi)) != rocblas_status_success)
+    return DH_ERR_ERROR;
   int info = 0;
-  if (hipMemcpyAsync(eig.data(), m + oe, (size_t)n * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+  if ((eig && (hipMemcpyAsync(eigv.data(), m + oe, (size_t)n * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+               hipMemcpyAsync(&info, m + oi, 4, hipMemcpyDeviceToHost, s) != hipSuccess)) ||
       hipMemcpyAsync(rowp.data(), m + orow, (size_t)t.rows * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipMemcpyAsync(dg.data(), m + odg, (size_t)nd * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipMemcpyAsync(sm.data(), m + osm, (size_t)nd * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipMemcpyAsync(&info, m + oi, 4, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+      hipStreamSynchronize(s) != hipSuccess)
     return DH_ERR_ERROR;
   if (info != 0) return DH_ERR_ERROR;
-  // IL, MDL from s^2 = the Gram's eigenvalues (rounding can leave tiny negatives)
-  double smin = HUGE_VAL, smax = 0.0, ssum = 0.0;
-  for (double e : eig) {
-    const double v = std::max(e, 0.0);
-    smin = std::min(smin, v);
-    smax = std::max(smax, v);
-    ssum += v;
+  // IL = sum s_k^2 / n = trace / n; MDL from s^2 = the Gram's eigenvalues
+  // (rounding can leave tiny negatives)
+  double trace = 0.0;
+  for (double d : gdiag) trace += d;
+  out[DH_METRIC_IL] = db10(trace / n);
+  if (eig) {
+    double smin = HUGE_VAL, smax = 0.0;
+    for (double e : eigv) {
+      const double v = std::max(e, 0.0);
+      smin = std::min(smin, v);
+      smax = std::max(smax, v);
+    }
+    out[DH_METRIC_MDL] = smax > 0.0 ? db10(smin / smax) : -HUGE_VAL;
+  } else {
+    out[DH_METRIC_MDL] = std::nan("");
   }
-  out[DH_METRIC_IL] = db10(ssum / n);
-  out[DH_METRIC_MDL] = smax > 0.0 ? db10(smin / smax) : -HUGE_VAL;
   double total = 0.0, dsum = 0.0, ssame = 0.0, dmax = 0.0, dmin = HUGE_VAL, rmax = -1.0, rmin = HUGE_VAL;
   for (int i = 0; i < t.rows; ++i) total += rowp[i];
   for (int i = 0; i < nd; ++i) {
@@ -1463,7 +1477,8 @@ extern "C" float dh_autoalign(dh_handle h, const void* frames, int batch, int mo
       return true;
     }
     double m[DH_METRIC_COUNT];
-    if (tm_compute(pl, c.batch, pl->goal_indep, pl->goal_aa, s, m) != DH_SUCCESS) return false;
+    if (tm_compute(pl, c.batch, pl->goal_indep, pl->goal_aa, s, m, pl->goal == DH_METRIC_MDL) != DH_SUCCESS)
+      return false;
     gv = std::max(-1000.0, std::min(1000.0, m[pl->goal]));   // finite for the parabola
     return true;
   };

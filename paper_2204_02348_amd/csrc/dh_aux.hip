@@ -80,14 +80,17 @@ __device__ __forceinline__ double2 tm_a(const TmArgs& t, int r, int col) {
 }
 
 // G = X X^H, n x n, column-major: X = A (by rows, K = cols) or X = A^H
-// (K = rows). One thread per element.
-__global__ void k_tm_gram(TmArgs t, int by_rows, int n, double2* __restrict__ g) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y;
-  if (i >= n) return;
+// (K = rows). One wave per element, four per block: lane l takes
+// k = l, l + 64, ..., and the partial sums meet in a fixed butterfly, so an
+// element does not depend on the launch.
+__global__ void __launch_bounds__(256) k_tm_gram(TmArgs t, int by_rows, int n, double2* __restrict__ g) {
+  const int lane = threadIdx.x & 63;
+  const long e = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (e >= (long)n * n) return;                 // the whole wave
+  const int i = (int)(e % n), j = (int)(e / n);
   const int K = by_rows ? t.cols : t.rows;
   double re = 0.0, im = 0.0;
-  for (int k = 0; k < K; ++k) {
+  for (int k = lane; k < K; k += 64) {
     // X(i,k) conj(X(j,k)); X = A^H: X(i,k) = conj(A(k,i))
     const double2 x = by_rows ? tm_a(t, i, k) : tm_a(t, k, i);
     const double2 y = by_rows ? tm_a(t, j, k) : tm_a(t, k, j);
@@ -96,7 +99,12 @@ __global__ void k_tm_gram(TmArgs t, int by_rows, int n, double2* __restrict__ g)
     re += xr * yr + xi * yi;
     im += xi * yr - xr * yi;
   }
-  g[(size_t)i + (size_t)j * n] = make_double2(re, im);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    re += __shfl_xor(re, off, 64);
+    im += __shfl_xor(im, off, 64);
+  }
+  if (lane == 0) g[(size_t)i + (size_t)j * n] = make_double2(re, im);
 }
 
 // mode key of transfer-matrix index k: (pol, mode group); past the modes, unique
@@ -134,8 +142,10 @@ __global__ void k_tm_rows(TmArgs t, const double2* __restrict__ g, int nrow, int
 }
 
 hipError_t launch_tm_gram(const TmArgs& t, int by_rows, int n, double2* g, hipStream_t s) {
-  dim3 grid((n + 127) / 128, n);
-  hipLaunchKernelGGL(k_tm_gram, grid, dim3(128), 0, s, t, by_rows, n, g);
+  if (n < 1) return hipSuccess;
+  const long blocks = ((long)n * n + 3) / 4;
+  if (blocks > 0x7fffffffL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_tm_gram, dim3((unsigned)blocks), dim3(256), 0, s, t, by_rows, n, g);
   return hipGetLastError();
 }
 
