@@ -1155,8 +1155,14 @@ int tm_compute(Plan* pl, int B, int pol_independent, int mul_conj_trans, hipStre
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o += align256(bytes); return r; };
   const size_t og = take((size_t)n * n * 16), od = extra ? take((size_t)t.rows * t.rows * 16) : 0;
-  const size_t oe = take((size_t)n * 8), ow = take((size_t)n * 8), oi = take(8);
-  const size_t orow = take((size_t)t.rows * 8), odg = take((size_t)nd * 8), osm = take((size_t)nd * 8);
+  const size_t ow = take((size_t)n * 8);
+  // the results, one block for one copy to the host: eigenvalues [n], the
+  // Gram's diagonal [n], row powers [rows], diagonal powers [nd], same-group
+  // powers [nd], the solver's info
+  const size_t nres = 2 * (size_t)n + t.rows + 2 * (size_t)nd + 1;
+  const size_t ores = take(nres * 8);
+  const size_t oe = ores, ogd = oe + (size_t)n * 8, orow = ogd + (size_t)n * 8;
+  const size_t odg = orow + (size_t)t.rows * 8, osm = odg + (size_t)nd * 8, oi = osm + (size_t)nd * 8;
   if (o > pl->tm_bytes) {
     if (pl->tm_mem) (void)hipFree(pl->tm_mem);
     pl->tm_mem = nullptr;
@@ -1177,31 +1183,32 @@ int tm_compute(Plan* pl, int B, int pol_independent, int mul_conj_trans, hipStre
       dh::launch_tm_rows(t, aa ? gd : nullptr, t.rows, ncol, nd, (double*)(m + orow), (double*)(m + odg),
                          (double*)(m + osm), s) != hipSuccess)
     return DH_ERR_ERROR;
-  // the Gram's diagonal (real), read before the eigen-solver overwrites it
-  std::vector<double> gdiag(n), eigv(eig ? n : 0), rowp(t.rows), dg(nd), sm(nd);
-  if (hipMemcpy2DAsync(gdiag.data(), 8, g, (size_t)(n + 1) * 16, 8, n, hipMemcpyDeviceToHost, s) != hipSuccess)
-    return DH_ERR_ERROR;
+  // the Gram's diagonal, read before the eigen-solver overwrites the matrix
+  if (dh::launch_tm_diag(g, n, (double*)(m + ogd), s) != hipSuccess) return DH_ERR_ERROR;
   if (eig && rocsolver_zheevd(pl->blas, rocblas_evect_none, rocblas_fill_upper, n, (rocblas_double_complex*)g, n,
                               (double*)(m + oe), (double*)(m + ow), (rocblas_int*)(m + oi)) != rocblas_status_success)
     return DH_ERR_ERROR;
-  int info = 0;
-  if ((eig && (hipMemcpyAsync(eigv.data(), m + oe, (size_t)n * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
-               hipMemcpyAsync(&info, m + oi, 4, hipMemcpyDeviceToHost, s) != hipSuccess)) ||
-      hipMemcpyAsync(rowp.data(), m + orow, (size_t)t.rows * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipMemcpyAsync(dg.data(), m + odg, (size_t)nd * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipMemcpyAsync(sm.data(), m + osm, (size_t)nd * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+  std::vector<double> res(nres);
+  if (hipMemcpyAsync(res.data(), m + ores, nres * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return DH_ERR_ERROR;
+  rocblas_int info = 0;
+  if (eig) std::memcpy(&info, &res[nres - 1], sizeof(info));
   if (info != 0) return DH_ERR_ERROR;
+  const double* eigv = res.data();
+  const double* gdiag = eigv + n;
+  const double* rowp = gdiag + n;
+  const double* dg = rowp + t.rows;
+  const double* sm = dg + nd;
   // IL = sum s_k^2 / n = trace / n; MDL from s^2 = the Gram's eigenvalues
   // (rounding can leave tiny negatives)
   double trace = 0.0;
-  for (double d : gdiag) trace += d;
+  for (int i = 0; i < n; ++i) trace += gdiag[i];
   out[DH_METRIC_IL] = db10(trace / n);
   if (eig) {
     double smin = HUGE_VAL, smax = 0.0;
-    for (double e : eigv) {
-      const double v = std::max(e, 0.0);
+    for (int i = 0; i < n; ++i) {
+      const double v = std::max(eigv[i], 0.0);
       smin = std::min(smin, v);
       smax = std::max(smax, v);
     }

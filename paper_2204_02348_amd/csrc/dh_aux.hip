@@ -6,6 +6,7 @@
 //   k_tm_gram  Gram matrix of the batch transfer matrix (its eigenvalues are
 //              the squared singular values)
 //   k_tm_rows  row statistics of the matrix the diagonal metrics are taken on
+//   k_tm_diag  the Gram matrix's diagonal (IL is its trace over n)
 //   k_q16      fields to int16 real and imaginary parts with one scale each
 //   k_basis    HG coefficients to another basis (LG, custom): one matrix product
 //   k_m0y, k_m0x  IFFT mode 0 field export: the window zero-padded to the FFT
@@ -152,6 +153,18 @@ hipError_t launch_tm_gram(const TmArgs& t, int by_rows, int n, double2* g, hipSt
 hipError_t launch_tm_rows(const TmArgs& t, const double2* g, int nrow, int ncol, int nd, double* rowpow, double* diag,
                           double* same, hipStream_t s) {
   hipLaunchKernelGGL(k_tm_rows, dim3((nrow + 127) / 128), dim3(128), 0, s, t, g, nrow, ncol, nd, rowpow, diag, same);
+  return hipGetLastError();
+}
+
+// the real diagonal of an n x n complex matrix (its trace's terms)
+__global__ void k_tm_diag(const double2* __restrict__ g, int n, double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = g[(size_t)i * (n + 1)].x;
+}
+
+hipError_t launch_tm_diag(const double2* g, int n, double* out, hipStream_t s) {
+  if (n < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_tm_diag, dim3((n + 255) / 256), dim3(256), 0, s, g, n, out);
   return hipGetLastError();
 }
 

@@ -168,5 +168,7 @@ hipError_t launch_tm_gram(const TmArgs& t, int by_rows, int n, double2* g, hipSt
 // and for rows < nd the diagonal power and the power sharing the row's mode key
 hipError_t launch_tm_rows(const TmArgs& t, const double2* g, int nrow, int ncol, int nd, double* rowpow, double* diag,
                           double* same, hipStream_t s);
+// out[i] = Re g[i][i] of an n x n complex matrix
+hipError_t launch_tm_diag(const double2* g, int n, double* out, hipStream_t s);
 
 }  // namespace dh
