@@ -183,6 +183,37 @@ def time_aux(dh, torch, cfg, ft, B, stream, reps=20):
     return out
 
 
+def single_frame_bench(dh, torch, reps=2000, warm=200):
+    """One 128x128 f32 frame at a time (1 pol, G=4, the smallest workload):
+    the latency a caller sees for dh_process_batch of one frame followed by
+    a stream synchronisation (binding call included), p50/p99 over `reps`
+    calls after `warm`, and the device time of one frame's kernels."""
+    cfg = dh_synth.config(0)
+    f, _ = dh_synth.make_frames(cfg, n_frames=1)
+    ft = torch.from_numpy(f).cuda()
+    plan = dh.Plan(cfg["params"], max_batch=1)
+    stream = torch.cuda.Stream()
+    lat = []
+    for i in range(warm + reps):
+        t0 = time.perf_counter()
+        plan.process(ft, 1, stream)
+        stream.synchronize()
+        if i >= warm:
+            lat.append((time.perf_counter() - t0) * 1e3)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        plan.process(ft, 1, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    plan.destroy()
+    lat = np.array(lat)
+    return {"workload": "1 frame 128x128 f32, 1 pol, G=4 (10 modes), process + stream sync per frame",
+            "p50_ms": round(float(np.percentile(lat, 50)), 4), "p99_ms": round(float(np.percentile(lat, 99)), 4),
+            "frames_per_s_one_at_a_time": round(1e3 / float(np.mean(lat)), 1),
+            "device_ms_per_frame_back_to_back": round(e0.elapsed_time(e1) / reps, 4)}
+
+
 def serving_bench(dh, torch, workers, seconds=10.0, warm=1.0, rate=5000.0, seed=220402348):
     """Serving form on the four uint16 cameras: Poisson arrivals at `rate` per
     camera from resident pools of 64 frames, continuous batching (lanes admitted
@@ -443,6 +474,7 @@ def main():
         print("[bench] forms done", file=sys.stderr, flush=True)
     del ft
     if not args.no_serving:
+        out["single_frame"] = single_frame_bench(dh, torch)
         out["serving"] = serving_bench(dh, torch, workers)
         print("[bench] serving done", file=sys.stderr, flush=True)
     if not args.no_align:
