@@ -325,6 +325,7 @@ struct Plan {
   size_t amem_bytes = 0;
   dh_align_report rep{};
   int version = 0;                   // bumped whenever the tables are rebuilt
+  std::vector<char> trial_host;      // host image of the per-pol tables of an alignment trial
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
   std::vector<int> ev_stage;         // stage of launch i (events 2i, 2i+1)
@@ -573,6 +574,46 @@ int build_tables(Plan* pl, bool hg = true, bool spec = true) {
       return DH_ERR_ERROR;
   }
   if (hipDeviceSynchronize() != hipSuccess) return DH_ERR_ERROR;
+  return DH_SUCCESS;
+}
+
+// The tables an alignment trial changes, on stream s with no host sync: the
+// per-pol window tables (mask rows, centre ramps, tilt/defocus phases) in one
+// upload of their contiguous range and, for a new waist (hg), the HG tables.
+// The twiddles and the mode list do not depend on the trial's parameters. The
+// host image lives in the plan until the next trial, which starts after this
+// one's results were read back (stream synchronised).
+int trial_tables(Plan* pl, bool hg, hipStream_t s) {
+  ++pl->version;
+  const Geom& g = pl->g;
+  const dh_params* p = &pl->params;
+  const Layout& L = pl->L;
+  const size_t lo = L.pol_mrow[0], len = L.total_tables - lo;
+  pl->trial_host.assign(L.total_tables, 0);
+  for (int q = 0; q < p->pol_count; ++q) {
+    const PolTables t = pol_tables(g, g.pol[q], p, q, false, false);
+    put(pl->trial_host, L.pol_mrow[q], t.mrow);
+    put(pl->trial_host, L.pol_rhox[q], t.rhox);
+    put(pl->trial_host, L.pol_rhoy[q], t.rhoy);
+    put(pl->trial_host, L.pol_tx[q], t.tx);
+    put(pl->trial_host, L.pol_ty[q], t.ty);
+  }
+  if (hipMemcpyAsync(pl->mem + lo, pl->trial_host.data() + lo, len, hipMemcpyHostToDevice, s) != hipSuccess)
+    return DH_ERR_ERROR;
+  if (!hg) return DH_SUCCESS;
+  const double waist = p->waist > 0 ? p->waist : 1.0;
+  pl->s_uh = (float)hg_fp16_scale(waist, std::max(g.pxp, g.pyp));
+  for (int q = 0; q < p->pol_count; ++q) {
+    char* m = pl->mem;
+    if (dh::launch_hg(g.pxp, g.wx, g.wx, waist, g.G, g.gp, (float*)(m + L.pol_ux[q]),
+                      (unsigned short*)(m + L.pol_uxs[q][0]), (unsigned short*)(m + L.pol_uxs[q][1]),
+                      (_Float16*)(m + L.pol_uxs[q][2]), (_Float16*)(m + L.pol_uxs[q][3]), pl->s_uh, s) != hipSuccess)
+      return DH_ERR_ERROR;
+    if (dh::launch_hg(g.pyp, g.wy, g.wyp, waist, g.G, g.gp, (float*)(m + L.pol_uy[q]),
+                      (unsigned short*)(m + L.pol_uys[q][0]), (unsigned short*)(m + L.pol_uys[q][1]),
+                      (_Float16*)(m + L.pol_uys[q][2]), (_Float16*)(m + L.pol_uys[q][3]), pl->s_uh, s) != hipSuccess)
+      return DH_ERR_ERROR;
+  }
   return DH_SUCCESS;
 }
 
@@ -1284,12 +1325,18 @@ bool align_eval(AlignCtx& c, bool hg, double mp[2], double fp[2]) {
     offi[q] = -g.pol[q].vhi - c.ky0e[q];
     if (offj[q] < 0 || offj[q] + g.bx > c.bxe || offi[q] < 0 || offi[q] + g.by > c.bye) return false;
   }
-  if (build_tables(pl, hg, false) != DH_SUCCESS) return false;
+  // on a failure past this point the stream is drained first, so that no
+  // pending upload of this trial lands after the caller's restoring rebuild
+  auto fail = [&]() {
+    (void)hipStreamSynchronize(c.s);
+    return false;
+  };
+  if (trial_tables(pl, hg, c.s) != DH_SUCCESS) return fail();
   for (int w = 0; w < pl->nws; ++w) fill_kargs(pl, w);
   // a beam centre that moved the window by whole pixels needs the spectrum anew
   bool moved = false;
   for (int q = 0; q < np; ++q) moved |= g.pol[q].x0 != c.ox[q] || g.pol[q].y0 != c.oy[q];
-  if (moved && !align_fft(c)) return false;
+  if (moved && !align_fft(c)) return fail();
   dh::KArgs k = pl->ka[0];
   k.capt = c.capt;
   k.fields = c.fields;
@@ -1299,7 +1346,7 @@ bool align_eval(AlignCtx& c, bool hg, double mp[2], double fp[2]) {
     const int nb = std::min(pl->chunk, c.batch - b0);
     if (dh::launch_gather(k, c.spec + b0 * per_frame, c.bxe, c.bye, offj, offi, nb, c.s) != hipSuccess ||
         dh::launch_fld(k, b0, nb, c.s) != hipSuccess || dh::launch_norm(k, b0, nb, c.s) != hipSuccess)
-      return false;
+      return fail();
   }
   std::vector<double> h((size_t)c.batch * np * 2);
   if (hipMemcpyAsync(h.data(), c.capt, h.size() * 8, hipMemcpyDeviceToHost, c.s) != hipSuccess ||
