@@ -88,28 +88,34 @@ int derive_pol(const dh_params* p, Geom* g, int q) {
   P.dx = p->beam_centre[q][0] - ix * pix;
   P.dy = p->beam_centre[q][1] - iy * pix;
   if (P.x0 < 0 || P.x0 + nx > p->frame_w || P.y0 < 0 || P.y0 + ny > p->frame_h) return DH_ERR_INVALIDDIMENSION;
-  // bounding box of the bins inside the window
+  // the first and last bin inside the window on each row of a bounding range,
+  // found by scanning in from both ends (the row's minimum and maximum, as a
+  // full scan would give, at the cost of the bins outside only: alignment
+  // trials re-derive this every time), and the box they span
   const int u_a = (int)std::floor(-P.ax - g->rx) - 1, u_b = (int)std::ceil(-P.ax + g->rx) + 1;
   const int v_a = (int)std::floor(-P.ay - g->ry) - 1, v_b = (int)std::ceil(-P.ay + g->ry) + 1;
+  std::vector<int> rlo((size_t)(v_b - v_a + 1), 1), rhi((size_t)(v_b - v_a + 1), 0);
   P.ulo = u_b; P.uhi = u_a; P.vlo = v_b; P.vhi = v_a;
-  for (int v = v_a; v <= v_b; ++v)
-    for (int u = u_a; u <= u_b; ++u)
-      if (inside(u, v, P.ax, P.ay, g->rx, g->ry)) {
-        P.ulo = std::min(P.ulo, u); P.uhi = std::max(P.uhi, u);
-        P.vlo = std::min(P.vlo, v); P.vhi = std::max(P.vhi, v);
-      }
+  for (int v = v_a; v <= v_b; ++v) {
+    int lo = u_a;
+    while (lo <= u_b && !inside(lo, v, P.ax, P.ay, g->rx, g->ry)) ++lo;
+    if (lo > u_b) continue;
+    int hi = u_b;
+    while (!inside(hi, v, P.ax, P.ay, g->rx, g->ry)) --hi;   // stops at lo at the latest
+    rlo[(size_t)(v - v_a)] = lo;
+    rhi[(size_t)(v - v_a)] = hi;
+    P.ulo = std::min(P.ulo, lo); P.uhi = std::max(P.uhi, hi);
+    P.vlo = std::min(P.vlo, v); P.vhi = std::max(P.vhi, v);
+  }
   if (P.uhi < P.ulo || P.vhi < P.vlo) return DH_ERR_INVALIDARGUMENT;  // empty window
   const int bxq = P.uhi - P.ulo + 1, byq = P.vhi - P.vlo + 1;
   if (bxq > g->bx || byq > g->by) return DH_ERR_INVALIDARGUMENT;
   P.row_lo.assign(byq, 1);
   P.row_hi.assign(byq, 0);
   for (int i = 0; i < byq; ++i) {
-    const int v = P.vhi - i;
-    int lo = INT32_MAX, hi = INT32_MIN;
-    for (int u = P.ulo; u <= P.uhi; ++u)
-      if (inside(u, v, P.ax, P.ay, g->rx, g->ry)) { lo = std::min(lo, u); hi = std::max(hi, u); }
-    if (lo <= hi) { P.row_lo[i] = lo; P.row_hi[i] = hi; }
-    else { P.row_lo[i] = 1; P.row_hi[i] = 0; }
+    const size_t r = (size_t)(P.vhi - i - v_a);
+    P.row_lo[i] = rlo[r];
+    P.row_hi[i] = rhi[r];
   }
   return DH_SUCCESS;
 }
