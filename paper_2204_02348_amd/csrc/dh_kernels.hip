@@ -427,7 +427,7 @@ __global__ void __launch_bounds__(kTPB) k_cspec(KArgs A, int b0) {
     // window = M * I~ = conj(val) (-1)^(u+v) Nx Ny at (v mod wy, u mod wx), as in k_col
     float2* win = A.window + ((size_t)(b0 + bl) * A.npol + p) * A.wy * A.wx;
     // the block's columns fastest across the threads: neighbouring box columns
-    // are neighbouring window cells of one row (64 B per 8 lanes)
+    // are neighbouring cells of one window row (CG cells per row and lane group)
     for (int e = tid; e < CG * WY; e += kTPB) {
       const int c = e % CG, q = e / CG;
       const int j = jc0 + c;
