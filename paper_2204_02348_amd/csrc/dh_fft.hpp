@@ -351,8 +351,8 @@ __device__ __forceinline__ void fft_rest(float2* buf, TW tw, int tid) {
 // Lds<N>, transform t at buf + t * STRIDE). tw holds the twiddles of pass 2
 // then pass 3: entry (r-1)*NS + k = e^{-2 pi i k r / (NS R)}, so the lanes of
 // a wave (consecutive k) read consecutive entries.
-template <int N, int NTR, int STRIDE, int TPB>
-__device__ __forceinline__ void fft_lds(float2* buf, const float2* __restrict__ tw, int tid) {
+template <int N, int NTR, int STRIDE, int TPB, typename TW>
+__device__ __forceinline__ void fft_lds(float2* buf, TW tw, int tid) {
   using P = FftPlan<N>;
   constexpr int PAD = Lds<N>::PAD;
   static_assert(P::R0 * P::R1 * P::R2 == N, "bad factorisation");

@@ -213,26 +213,32 @@ __global__ void __launch_bounds__(kTPB) k_col(KArgs A, int b0) {
   using LW = Lds<WY>;
   using Q = Pass1<NY, CG, kTPB>;
   constexpr int ST = (LN::STRIDE > LW::STRIDE) ? LN::STRIDE : LW::STRIDE;
+  // at 2048 rows the twiddles of both transforms and the box-row ramp are read
+  // through the caches: the workgroup's LDS drops from 102 to 75 KB and two
+  // workgroups fit on a CU
+  constexpr bool TWG = NY >= 2048;
   __shared__ float2 buf[CG * ST];
-  __shared__ float2 twy[twn<NY>()];
-  __shared__ float2 tww[twn<WY>()];
+  __shared__ float2 twy[TWG ? 1 : twn<NY>()];
+  __shared__ float2 tww[TWG ? 1 : twn<WY>()];
   __shared__ int2 s_mrow[WY];
   __shared__ float2 s_crx[CG];              // conj(rho_x) of this block's columns
-  __shared__ float2 s_cry[WY];              // conj(rho_y) by box row
+  __shared__ float2 s_cry[TWG ? 1 : WY];    // conj(rho_y) by box row
   const int tid = threadIdx.x;
   const int p = blockIdx.y;
   const int bl = blockIdx.z;
   const PolTab& P = A.pol[p];
   const int jc0 = blockIdx.x * CG;
-  Staged<float2, twn<NY>(), kTPB> stwy;
-  Staged<float2, twn<WY>(), kTPB> stww;
+  Staged<float2, TWG ? 1 : twn<NY>(), kTPB> stwy;
+  Staged<float2, TWG ? 1 : twn<WY>(), kTPB> stww;
   Staged<int2, WY, kTPB> smr;
-  Staged<float2, WY, kTPB> scy;
+  Staged<float2, TWG ? 1 : WY, kTPB> scy;
   Staged<float2, CG, kTPB> scx;
-  stwy.load(A.tw_ny, twn<NY>(), tid);
-  stww.load(A.tw_wy, twn<WY>(), tid);
+  if constexpr (!TWG) {
+    stwy.load(A.tw_ny, twn<NY>(), tid);
+    stww.load(A.tw_wy, twn<WY>(), tid);
+    scy.load(P.rhoy, A.by, tid);
+  }
   smr.load(P.mrow, A.by, tid);
-  scy.load(P.rhoy, A.by, tid);
   const int ncx = A.bx - jc0 < CG ? A.bx - jc0 : CG;
   scx.load(P.rhox + jc0, ncx, tid);
   const float2* in = A.t1 + ((size_t)(bl * A.npol + p) * A.bx) * NY;
@@ -258,17 +264,22 @@ __global__ void __launch_bounds__(kTPB) k_col(KArgs A, int b0) {
       }
     }
 #pragma unroll
-    for (int i = 0; i < scy.IT; ++i) scy.v[i] = conjf2(scy.v[i]);
-#pragma unroll
     for (int i = 0; i < scx.IT; ++i) scx.v[i] = conjf2(scx.v[i]);
-    stwy.store(twy, twn<NY>(), make_float2(0.f, 0.f), tid);
-    stww.store(tww, twn<WY>(), make_float2(0.f, 0.f), tid);
+    if constexpr (!TWG) {
+#pragma unroll
+      for (int i = 0; i < scy.IT; ++i) scy.v[i] = conjf2(scy.v[i]);
+      stwy.store(twy, twn<NY>(), make_float2(0.f, 0.f), tid);
+      stww.store(tww, twn<WY>(), make_float2(0.f, 0.f), tid);
+      scy.store(s_cry, A.by, make_float2(0.f, 0.f), tid);
+    }
     smr.store(s_mrow, A.by, make_int2(1, 0), tid);
-    scy.store(s_cry, A.by, make_float2(0.f, 0.f), tid);
     scx.store(s_crx, ncx, make_float2(0.f, 0.f), tid);
     fft_pass1_regs<NY, CG, ST, kTPB>(v, buf, tid);
   }
-  fft_rest<NY, CG, ST, kTPB>(buf, twy, tid);
+  if constexpr (TWG)
+    fft_rest<NY, CG, ST, kTPB>(buf, as_global(A.tw_ny), tid);
+  else
+    fft_rest<NY, CG, ST, kTPB>(buf, static_cast<const float2*>(twy), tid);
   constexpr int NE = (CG * WY + kTPB - 1) / kTPB;
   float2 z[NE];
   const bool keep_win = A.window != nullptr;
@@ -287,7 +298,12 @@ __global__ void __launch_bounds__(kTPB) k_col(KArgs A, int b0) {
           int vv = (P.ky0 + i) % NY;
           if (vv < 0) vv += NY;
           const float2 f = buf[c * ST + LN::at(vv)];
-          val = cmul(cmul(f, s_crx[c]), s_cry[i]);
+          float2 cry;
+          if constexpr (TWG)
+            cry = conjf2(ld_tw(as_global(P.rhoy), i));
+          else
+            cry = s_cry[i];
+          val = cmul(cmul(f, s_crx[c]), cry);
           if (keep_win) {
             // window = M * I~ = conj(val) (-1)^(u+v) Nx Ny at (v mod wy, u mod wx)
             const int u = -(P.k0 + j), v = -(P.ky0 + i);
@@ -308,7 +324,10 @@ __global__ void __launch_bounds__(kTPB) k_col(KArgs A, int b0) {
     if (e < CG * WY) buf[(e / WY) * ST + LW::at(e % WY)] = z[it];
   }
   __syncthreads();
-  fft_lds<WY, CG, ST, kTPB>(buf, tww, tid);
+  if constexpr (TWG)
+    fft_lds<WY, CG, ST, kTPB>(buf, as_global(A.tw_wy), tid);
+  else
+    fft_lds<WY, CG, ST, kTPB>(buf, static_cast<const float2*>(tww), tid);
   float2* out = A.f2 + ((size_t)(bl * A.npol + p) * WY) * A.bxp;
   constexpr int NO = (CG * WY + kTPB - 1) / kTPB;
   float2 ov[NO];
