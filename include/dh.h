@@ -458,7 +458,8 @@ int dh_get_align_report(dh_handle h, dh_align_report* out);
  * over the cameras while their device bytes fit hbm_budget (0: no limit;
  * at least one lane per camera, else DH_ERR_MEMORYALLOCATION; at most four).
  * use_graphs: capture each lane's launch sequence once per batch size as a
- * hipGraph and replay it. normalised: results are the power-normalised
+ * hipGraph and replay it, for batches of up to 16 requests (larger batches
+ * are launched directly). normalised: results are the power-normalised
  * coefficients (else raw). Writes the server handle to *out.
  *
  * Admission: a request waits in its camera's queue until a lane of that

@@ -2007,7 +2007,7 @@ extern "C" int dh_get_align_report(dh_handle h, dh_align_report* out) {
 // the load and requests that arrive while others are on the GPU join the next
 // free lane. Lanes of all cameras run concurrently on the device. The launch
 // sequence of a batch is captured once per (lane, batch size) as a hipGraph
-// and replayed.
+// and replayed (batches of up to 16 requests; larger ones launch directly).
 namespace {
 
 using Clock = std::chrono::steady_clock;
@@ -2125,6 +2125,8 @@ void lane_args(const Camera& C, Lane& L) {
   L.version = C.pl->version;
 }
 
+constexpr int kGraphBatches = 16;   // largest batch launched as a captured graph
+
 hipError_t record_batch(const Camera& C, const Lane& L, int n) {
   const Plan* pl = C.pl;
   const int u16 = pl->params.input_dtype == DH_INPUT_U16;
@@ -2151,7 +2153,11 @@ int launch_lane(Server* S, Camera& C, Lane& L) {
   for (int i = 0; i < n; ++i) L.hptr[i] = L.batch[i].frame;
   if (hipMemcpyAsync((void*)L.k.fptr, L.hptr, (size_t)n * sizeof(void*), hipMemcpyHostToDevice, L.s) != hipSuccess)
     return DH_ERR_ERROR;
-  if (S->graphs) {
+  // graphs replay the small batches, where launch latency is a large part of
+  // a request's time; a larger batch is launched directly (its kernels run far
+  // longer than the few launches take), so a lane holds at most kGraphBatches
+  // graphs and a burst of large batches never waits for a capture
+  if (S->graphs && n <= kGraphBatches) {
     auto it = L.graphs.find(n);
     if (it == L.graphs.end()) {
       hipGraph_t gr = nullptr;
