@@ -201,6 +201,48 @@ def test_snap_pins_catch_planted_mistake(name, monkeypatch):
     assert failed > 0, name
 
 
+# ---------------------------------------------------------------- alignment snap: tilt from the whole plane
+PLANE_SRC = os.path.join(os.path.dirname(SRC), "plane_snap.py")
+
+PLANE_MUTATIONS = {
+    "tilt_sign": ("tilts.append([-uc * binx, -vc * biny])", "tilts.append([uc * binx, vc * biny])"),
+    "mirror_rule": ("first = d1 < d2 if d1 != d2 else", "first = d1 > d2 if d1 != d2 else"),
+    "centroid_not_periodic": ("sv += w * dv", "sv += w * (_signed((cv + dv) % ny, ny) - cv)"),
+    "bins_per_degree_axes": ("binx = params[\"wavelength\"] / (nx *", "binx = params[\"wavelength\"] / (ny *"),
+    "centroid_axes_swapped": ("uc = cu + (su / sw", "uc = cu + (sv / sw"),
+}
+
+
+def _plane_mutant(name):
+    import oracle
+    src = open(PLANE_SRC).read()
+    old, new = PLANE_MUTATIONS[name]
+    assert src.count(old) == 1, name
+    src = src.replace(old, new).replace("from .holo_oracle import geometry\n", "")
+    mod = types.ModuleType("plane_mutant_" + name)
+    mod.__dict__["geometry"] = oracle.geometry
+    exec(compile(src, PLANE_SRC + ":" + name, "exec"), mod.__dict__)
+    return mod
+
+
+@pytest.mark.parametrize("name", sorted(PLANE_MUTATIONS))
+def test_plane_snap_pins_catch_planted_mistake(name, monkeypatch):
+    import oracle
+    import tests.test_oracle_pins as pins
+    mut = _plane_mutant(name)
+    monkeypatch.setattr(oracle, "snap_tilt_plane", mut.snap_tilt_plane)
+    failed = 0
+    for t in [pins.test_plane_snap_finds_the_tilt_of_a_gaussian_beam,
+              pins.test_plane_snap_takes_the_term_nearer_the_start,
+              pins.test_plane_snap_per_polarisation_on_a_rectangular_window,
+              pins.test_plane_snap_term_across_the_plane_edge]:
+        try:
+            t()
+        except AssertionError:
+            failed += 1
+    assert failed > 0, name
+
+
 # ---------------------------------------------------------------- IFFT mode 0 and the int16 format
 M0_MUTATIONS = {
     "mode0_coarse_pitch": ("fx, fy = (wx, wy) if mode == 1 else (nx, ny)", "fx, fy = (wx, wy)"),

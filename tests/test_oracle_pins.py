@@ -484,6 +484,59 @@ def test_snap_centre_per_polarisation():
             assert abs(centre[q][a] - truth["beam_centre"][q][a]) < 1e-6 * pix, (q, a)
 
 
+# ---------------------------------------------------------------- alignment snap (tilt, whole plane)
+def _deg_per_bin(t, axis):
+    n = t["fft_w"] if axis == 0 else t["fft_h"]
+    return t["wavelength"] / (n * t["pixel_size"]) / oracle.DEG
+
+
+def test_plane_snap_finds_the_tilt_of_a_gaussian_beam():
+    # HG00 at the tilt (1.5, 1.5) deg: its cross term is a Gaussian centred on
+    # minus the tilt, so the centroid is the tilt; from a zero start the term
+    # with positive x tilt is the one taken
+    truth = dict(dh_synth.config(0)["truth"])
+    f = _one_mode_frames(truth, [[(0, 0)]])
+    got = oracle.snap_tilt_plane(f, dict(truth, tilt_deg=[[0.0, 0.0]]))
+    for a in range(2):
+        assert abs(got[0][a] - truth["tilt_deg"][0][a]) < 0.02 * _deg_per_bin(truth, a), (a, got)
+
+
+def test_plane_snap_takes_the_term_nearer_the_start():
+    # a tilt of (-1.3, 1.1) deg: from a start near it the snap returns it; from
+    # a zero start the mirror term (positive x tilt) is taken, at minus it
+    truth = dict(dh_synth.config(0)["truth"], tilt_deg=[[-1.3, 1.1]])
+    f = _one_mode_frames(truth, [[(0, 0)]])
+    near = oracle.snap_tilt_plane(f, dict(truth, tilt_deg=[[-1.0, 1.0]]))
+    zero = oracle.snap_tilt_plane(f, dict(truth, tilt_deg=[[0.0, 0.0]]))
+    for a in range(2):
+        tol = 0.02 * _deg_per_bin(truth, a)
+        assert abs(near[0][a] - truth["tilt_deg"][0][a]) < tol, (a, near)
+        assert abs(zero[0][a] + truth["tilt_deg"][0][a]) < tol, (a, zero)
+
+
+def test_plane_snap_per_polarisation_on_a_rectangular_window():
+    # two pols, 256 x 128 windows (different bins per degree along x and y),
+    # each with its own tilt
+    truth = dict(dh_synth.config(1)["truth"], defocus=[0.0, 0.0], max_mg=1, fft_w=256, fft_h=128,
+                 tilt_deg=[[1.3, 1.7], [-1.6, 1.2]])
+    f = _one_mode_frames(truth, [[(0, 0), (1, 0)]])
+    got = oracle.snap_tilt_plane(f, dict(truth, tilt_deg=[[1.0, 1.0], [-1.0, 1.0]]))
+    for q in range(2):
+        for a in range(2):
+            assert abs(got[q][a] - truth["tilt_deg"][q][a]) < 0.02 * _deg_per_bin(truth, a), (q, a, got)
+
+
+def test_plane_snap_term_across_the_plane_edge():
+    # a y tilt of 2.15 deg on a 128-row window puts the term 61.5 bins from the
+    # origin, 2.5 bins from the edge of the plane: its bins wrap, and the
+    # centroid taken with periodic offsets is still the tilt
+    truth = dict(dh_synth.config(0)["truth"], tilt_deg=[[1.0, 2.15]], window_radius_deg=0.3)
+    f = _one_mode_frames(truth, [[(0, 0)]])
+    got = oracle.snap_tilt_plane(f, dict(truth, tilt_deg=[[1.0, 2.0]]))
+    for a in range(2):
+        assert abs(got[0][a] - truth["tilt_deg"][0][a]) < 0.05 * _deg_per_bin(truth, a), (a, got)
+
+
 # ---------------------------------------------------------------- IFFT resolution mode 0
 def test_mode0_field_is_the_full_size_inverse_fft():
     # mode 0: the window's bins zero-padded onto the N x N lattice and inverse
