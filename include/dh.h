@@ -315,14 +315,20 @@ int dh_stage_times(dh_handle h, double* ms, int* launches);
  * batch's raw coefficients. With a metric goal every trial evaluates that
  * metric, and each polarisation's tilt, defocus and centre is a coordinate of
  * its own (pol locks: dh_set_pol_lock).
- * Snap: the tilt at the centroid of the batch power spectrum (above its mean)
- * near the current tilt; then, from the fields reconstructed there (G > 0),
+ * Snap: the tilt from scratch, from the whole Fourier plane of the first 32
+ * frames: the zero-order region (twice the window radius about the origin)
+ * left out, the brightest other bin and its mirror are the cross terms, the
+ * one whose tilt is nearer the current tilt is taken (from a zero tilt:
+ * positive x, then positive y), at the centroid of its power above the mean
+ * (report: plane_tilt_deg); then the tilt at the centroid of the batch power
+ * spectrum (above its mean) near that tilt; then, from the fields
+ * reconstructed there (G > 0),
  * the beam centre at the centroid of the batch intensity |E|^2 and the waist
  * from its pooled central second moment, w = sqrt(6 (<x^2> + <y^2>) / (2G + 1))
  * (exact when the power is spread evenly over the modes of G groups).
  * Defocus is not snapped. Tweak: a coordinate search. Tilts stay within 0.6
- * window radii and beam centres within an eighth of the FFT window of their
- * start; a centre that moves the FFT window out of the frame is a failed
+ * window radii of the snap's (of the start with TWEAK) and beam centres
+ * within an eighth of the FFT window of their start; a centre that moves the FFT window out of the frame is a failed
  * trial. Each trial re-runs the window gather, the IFFTs and the overlap from
  * a spectrum kept on the device, computed again only when a centre moves the
  * window by whole pixels.
@@ -360,6 +366,7 @@ typedef struct dh_align_report {
   double metrics[DH_METRIC_COUNT];  /* every metric at the final parameters (dh_transfer_metrics) */
   double snap_centre[2][2];    /* beam centre found by the snap ([pol][x,y], metres) */
   double snap_waist;           /* waist found by the snap (metres) */
+  double plane_tilt_deg[2][2]; /* the snap's first guess from the whole Fourier plane ([pol][x,y]) */
 } dh_align_report;
 
 /*

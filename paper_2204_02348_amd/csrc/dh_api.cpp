@@ -1370,6 +1370,97 @@ bool align_eval(AlignCtx& c, bool hg, double mp[2], double fp[2]) {
 
 double db(double m, double f) { return (m > 0 && f > 0) ? 10.0 * std::log10(m / f) : -300.0; }
 
+// The snap's first guess of the tilt from scratch (the paper's snap discards
+// the current alignment and looks for the off-axis term in Fourier space):
+// the power spectrum of each pol's whole FFT window summed over the first nb
+// frames; bins inside the zero-order region (the ellipse of twice the window
+// radius around the origin) are left out; the brightest other bin and its
+// mirror are the two cross terms, and the one whose tilt (minus its bin) lies
+// nearer the starting tilt is taken (from a zero start: positive x tilt, then
+// positive y); its position is refined to the centroid of the power above the
+// mean of the bins left in, over the window-radius ellipse around the
+// brightest bin, with bin offsets taken periodically. tilt[q] in degrees.
+// back to the parameters an alignment started from (its error paths): the
+// geometry derived again, the tables rebuilt and the kernel arguments refilled
+void restore(Plan* pl, const dh_params& start) {
+  pl->params = start;
+  for (int q = 0; q < start.pol_count; ++q) (void)derive_pol(&pl->params, &pl->g, q);
+  (void)build_tables(pl);
+  for (int w = 0; w < pl->nws; ++w) fill_kargs(pl, w);
+}
+
+constexpr int kSnapFrames = 32;   // frames the whole-plane snap sums
+
+int snap_plane(Plan* pl, const void* frames, int nb, hipStream_t s, double tilt[2][2]) {
+  const Geom& g = pl->g;
+  const dh_params& p = pl->params;
+  const int np = p.pol_count, nx = g.nx, ny = g.ny;
+  const size_t plane = (size_t)nx * ny;
+  const size_t tb = align256((size_t)nb * np * plane * 8), pb = align256((size_t)np * plane * 4);
+  char* mem = nullptr;
+  if (hipMalloc(&mem, 2 * tb + pb) != hipSuccess) {
+    (void)hipGetLastError();
+    return DH_ERR_MEMORYALLOCATION;
+  }
+  dh::KArgs ke = pl->ka[0];
+  ke.bx = nx;
+  ke.t1 = (float2*)mem;
+  for (int q = 0; q < np; ++q) {
+    ke.pol[q].k0 = 0;
+    ke.pol[q].ky0 = 0;
+  }
+  float2* spec = (float2*)(mem + tb);
+  float* pw = (float*)(mem + 2 * tb);
+  std::vector<float> hp((size_t)np * plane);
+  const bool ok = dh::launch_row(ke, frames, p.input_dtype == DH_INPUT_U16, 0, nb, s) == hipSuccess &&
+                  dh::launch_spec(ke, spec, ny, nb, s) == hipSuccess &&
+                  dh::launch_psum(spec, nb, np, plane, pw, s) == hipSuccess &&
+                  hipMemcpyAsync(hp.data(), pw, hp.size() * 4, hipMemcpyDeviceToHost, s) == hipSuccess &&
+                  hipStreamSynchronize(s) == hipSuccess;
+  (void)hipFree(mem);
+  if (!ok) return DH_ERR_ERROR;
+  const double binx = p.wavelength / (nx * p.pixel_size) / kDeg, biny = p.wavelength / (ny * p.pixel_size) / kDeg;
+  auto sgn = [](int k, int n) { return k < n / 2 ? k : k - n; };        // signed bin of index k
+  auto idx = [](int k, int n) { return ((k % n) + n) % n; };            // index of signed bin k
+  for (int q = 0; q < np; ++q) {
+    const float* m = hp.data() + (size_t)q * plane;                      // m[j * ny + i]: bin (j, i)
+    double mean = 0.0;
+    long cnt = 0;
+    int pj = -1, pi = -1;
+    float best = -1.f;
+    for (int j = 0; j < nx; ++j)
+      for (int i = 0; i < ny; ++i) {
+        if (inside(sgn(j, nx), sgn(i, ny), 0.0, 0.0, 2.0 * g.rx, 2.0 * g.ry)) continue;
+        const float v = m[(size_t)j * ny + i];
+        mean += v;
+        ++cnt;
+        if (v > best) { best = v; pj = j; pi = i; }
+      }
+    if (pj < 0) return DH_ERR_INVALIDARGUMENT;
+    mean /= (double)cnt;
+    // the two cross terms: at bin b (tilt -b) and at -b (tilt b)
+    const int bu = sgn(pj, nx), bv = sgn(pi, ny);
+    const double t0x = p.tilt_deg[q][0], t0y = p.tilt_deg[q][1];
+    const double d1 = std::hypot(-bu * binx - t0x, -bv * biny - t0y), d2 = std::hypot(bu * binx - t0x, bv * biny - t0y);
+    bool first;
+    if (d1 != d2) first = d1 < d2;
+    else first = (-bu > 0) || (-bu == 0 && -bv > 0);
+    const int cu = first ? bu : -bu, cv = first ? bv : -bv;            // the chosen term's bin
+    const int hx = (int)std::ceil(g.rx), hy = (int)std::ceil(g.ry);
+    double sw = 0.0, su = 0.0, sv = 0.0;
+    for (int du = -hx; du <= hx; ++du)
+      for (int dv = -hy; dv <= hy; ++dv) {
+        if (!inside(du, dv, 0.0, 0.0, g.rx, g.ry)) continue;
+        const double w = std::max(0.0, (double)m[(size_t)idx(cu + du, nx) * ny + idx(cv + dv, ny)] - mean);
+        sw += w; su += w * du; sv += w * dv;
+      }
+    const double uc = cu + (sw > 0 ? su / sw : 0.0), vc = cv + (sw > 0 ? sv / sw : 0.0);
+    tilt[q][0] = -uc * binx;
+    tilt[q][1] = -vc * biny;
+  }
+  return DH_SUCCESS;
+}
+
 }  // namespace
 
 extern "C" float dh_autoalign(dh_handle h, const void* frames, int batch, int mode, unsigned what, float tol,
@@ -1391,6 +1482,19 @@ extern "C" float dh_autoalign(dh_handle h, const void* frames, int batch, int mo
   const double pix = P.pixel_size, lam = P.wavelength;
   const double binx = lam / (g.nx * pix) / kDeg, biny = lam / (g.ny * pix) / kDeg;   // one bin in degrees
   const dh_params start = P;
+  dh_align_report rep{};
+  // snap from scratch: the tilt of the off-axis term in the whole Fourier
+  // plane, around which the stored spectrum is then made
+  if (mode != DH_ALIGN_TWEAK && (what & DH_ALIGN_TILT)) {
+    double t[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+    const int e = snap_plane(pl, frames, std::min(batch, kSnapFrames), s, t);
+    if (e != DH_SUCCESS) return (set_err(pl, e), -FLT_MAX);
+    for (int q = 0; q < np; ++q)
+      for (int a = 0; a < 2; ++a) P.tilt_deg[q][a] = rep.plane_tilt_deg[q][a] = t[q][a];
+    for (int q = 0; q < np; ++q)
+      if (derive_pol(&P, &g, q) != DH_SUCCESS)
+        return (restore(pl, start), set_err(pl, DH_ERR_INVALIDARGUMENT), -FLT_MAX);
+  }
   // search margin around the starting tilt: 0.6 w_c, within the spectrum
   const double mdeg = 0.6 * P.window_radius_deg;
   AlignCtx c{pl, s, batch, frames, P.input_dtype == DH_INPUT_U16};
@@ -1406,7 +1510,7 @@ extern "C" float dh_autoalign(dh_handle h, const void* frames, int batch, int mo
     tlo[q][0] = P.tilt_deg[q][0] - mdeg; thi[q][0] = P.tilt_deg[q][0] + mdeg;
     tlo[q][1] = P.tilt_deg[q][1] - mdeg; thi[q][1] = P.tilt_deg[q][1] + mdeg;
   }
-  if (c.bxe >= g.nx || c.bye >= g.ny) return (set_err(pl, DH_ERR_INVALIDARGUMENT), -FLT_MAX);
+  if (c.bxe >= g.nx || c.bye >= g.ny) return (restore(pl, start), set_err(pl, DH_ERR_INVALIDARGUMENT), -FLT_MAX);
   // beam-centre search range: an eighth of the FFT window around the start,
   // and centres whose window stays inside the frame (the window's centre pixel
   // is the centre rounded to the nearest pixel, offset from the half-frame's)
@@ -1436,7 +1540,7 @@ extern "C" float dh_autoalign(dh_handle h, const void* frames, int batch, int mo
     pl->amem_bytes = 0;
     if (hipMalloc(&pl->amem, need) != hipSuccess) {
       (void)hipGetLastError();
-      return (set_err(pl, DH_ERR_MEMORYALLOCATION), -FLT_MAX);
+      return (restore(pl, start), set_err(pl, DH_ERR_MEMORYALLOCATION), -FLT_MAX);
     }
     pl->amem_bytes = need;
   }
@@ -1446,8 +1550,7 @@ extern "C" float dh_autoalign(dh_handle h, const void* frames, int batch, int mo
   c.capt = (double*)(pl->amem + t1b + spb + pwb);
   float2* fdev = (float2*)(pl->amem + t1b + spb + pwb + cpb);
   double* mdev = (double*)(pl->amem + t1b + spb + pwb + cpb + fdb);
-  if (!align_fft(c)) return (set_err(pl, DH_ERR_ERROR), -FLT_MAX);
-  dh_align_report rep{};
+  if (!align_fft(c)) return (restore(pl, start), set_err(pl, DH_ERR_ERROR), -FLT_MAX);
   // snap: tilt at the centroid of the batch power spectrum above its mean
   if (mode != DH_ALIGN_TWEAK && (what & DH_ALIGN_TILT)) {
     const size_t plane = (size_t)c.bxe * c.bye;
@@ -1492,7 +1595,7 @@ extern "C" float dh_autoalign(dh_handle h, const void* frames, int batch, int mo
     if (!ok || dh::launch_moments(fdev, batch * np, g.wx, g.wy, g.pxp, g.pyp, mdev, s) != hipSuccess ||
         hipMemcpyAsync(hm.data(), mdev, hm.size() * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
-      return (P = start, build_tables(pl), set_err(pl, DH_ERR_ERROR), -FLT_MAX);
+      return (restore(pl, start), set_err(pl, DH_ERR_ERROR), -FLT_MAX);
     double mom[2][5] = {};
     for (int b = 0; b < batch; ++b)
       for (int q = 0; q < np; ++q)
@@ -1543,7 +1646,7 @@ extern "C" float dh_autoalign(dh_handle h, const void* frames, int batch, int mo
     return true;
   };
   double goal;
-  if (!eval_goal(true, goal)) return (P = start, build_tables(pl), set_err(pl, DH_ERR_ERROR), -FLT_MAX);
+  if (!eval_goal(true, goal)) return (restore(pl, start), set_err(pl, DH_ERR_ERROR), -FLT_MAX);
   double best_pol[2] = {db(mp[0], fp[0]), np > 1 ? db(mp[1], fp[1]) : 0.0};
   rep.start_goal_db = goal;
   // tweak: coordinate search, a parabola through three trials per coordinate.
@@ -1637,14 +1740,14 @@ extern "C" float dh_autoalign(dh_handle h, const void* frames, int batch, int mo
         k.h *= far ? 2.0 : moved ? 1.0 : 0.5;
         if (!joint) {
           // the kept per-pol values come from different trials: the joint goal anew
-          if (!align_eval(c, false, mp, fp)) return (P = start, build_tables(pl), set_err(pl, DH_ERR_ERROR), -FLT_MAX);
+          if (!align_eval(c, false, mp, fp)) return (restore(pl, start), set_err(pl, DH_ERR_ERROR), -FLT_MAX);
           goal = captured();
         } else {
           // the HG tables of a waist step must not be left at a rejected
           // trial; per-pol powers follow every shared step
           if (stale && (hg || !metric_goal)) {
             double gv;
-            if (!eval_goal(hg, gv)) return (P = start, build_tables(pl), set_err(pl, DH_ERR_ERROR), -FLT_MAX);
+            if (!eval_goal(hg, gv)) return (restore(pl, start), set_err(pl, DH_ERR_ERROR), -FLT_MAX);
           }
           if (!metric_goal) for (int q = 0; q < np; ++q) best_pol[q] = db(mp[q], fp[q]);
         }
@@ -1657,7 +1760,7 @@ extern "C" float dh_autoalign(dh_handle h, const void* frames, int batch, int mo
   // metrics of the final coefficients go in the report
   if (!eval_goal(true, goal) || build_spectral(pl) != DH_SUCCESS ||
       tm_compute(pl, c.batch, pl->goal_indep, pl->goal_aa, s, rep.metrics) != DH_SUCCESS)
-    return (P = start, build_tables(pl), set_err(pl, DH_ERR_ERROR), -FLT_MAX);
+    return (restore(pl, start), set_err(pl, DH_ERR_ERROR), -FLT_MAX);
   for (int w = 0; w < pl->nws; ++w) fill_kargs(pl, w);
   rep.goal = pl->goal;
   rep.goal_db = goal;

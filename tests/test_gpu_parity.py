@@ -340,6 +340,56 @@ def test_alignment_snap_finds_the_tilt():
             assert err < 3.0
 
 
+@pytest.mark.parametrize("idx,cam", [(1, 0), (3, 1)])
+def test_alignment_plane_snap_matches_oracle(idx, cam):
+    """The snap's first guess from the whole Fourier plane (ESTIMATE, tilt),
+    from a zero starting tilt, against the oracle's on the same frames:
+    640x512 f32 with 2 pols, and the 640x512 uint16 camera."""
+    cfg, f, _ = _frames(idx, cam=cam, n=6)
+    start = dict(cfg["params"], tilt_deg=[[0.0, 0.0]] * cfg["params"]["pol_count"])
+    ref = oracle.snap_tilt_plane(f, start)
+    dh, plan, ft = _align_plan(start, f)
+    _say("plane snap, recipe", idx, "camera", cam, f.shape)
+    plan.autoalign(ft, f.shape[0], mode=dh.ALIGN_ESTIMATE, what=dh.ALIGN_TILT)
+    rep = plan.align_report()
+    plan.destroy()
+    p = cfg["params"]
+    bins = [p["wavelength"] / (p["fft_w"] * p["pixel_size"]) / oracle.DEG,
+            p["wavelength"] / (p["fft_h"] * p["pixel_size"]) / oracle.DEG]
+    for q in range(p["pol_count"]):
+        for a in range(2):
+            err = abs(rep.plane_tilt_deg[q][a] - ref[q][a]) / bins[a]
+            _say("pol %d axis %d: gpu %.5f oracle %.5f deg (%.4f bins apart), truth %.5f" % (
+                q, a, rep.plane_tilt_deg[q][a], ref[q][a], err, cfg["truth"]["tilt_deg"][q][a]))
+            assert err < 0.01
+
+
+def test_alignment_full_from_a_zero_tilt():
+    """FULL alignment starting from a zero tilt (the snap finds the off-axis
+    term in the whole Fourier plane) recovers the truth (1024x1024, 2 pols,
+    G=30)."""
+    cfg = dh_synth.config(4)
+    n = 20
+    f, _ = dh_synth.make_frames(cfg, n_frames=n)
+    truth = cfg["truth"]
+    dh, plan, ft = _align_plan(dict(cfg["params"], tilt_deg=[[0.0, 0.0], [0.0, 0.0]]), f)
+    _say("alignment full from a zero tilt, %d frames" % n)
+    plan.autoalign(ft, n, mode=dh.ALIGN_FULL, what=dh.ALIGN_TILT | dh.ALIGN_DEFOCUS | dh.ALIGN_WAIST, tol=1e-5)
+    rep = plan.align_report()
+    got = plan.params()
+    plan.destroy()
+    bins = [1565e-9 / (512 * 20e-6) / oracle.DEG, 1565e-9 / (1024 * 20e-6) / oracle.DEG]
+    for q in range(2):
+        _say("pol %d plane snap %.4f %.4f, final tilt err %.3f / %.3f bins" % (
+            q, rep.plane_tilt_deg[q][0], rep.plane_tilt_deg[q][1],
+            (got["tilt_deg"][q][0] - truth["tilt_deg"][q][0]) / bins[0],
+            (got["tilt_deg"][q][1] - truth["tilt_deg"][q][1]) / bins[1]))
+        assert abs(got["tilt_deg"][q][0] - truth["tilt_deg"][q][0]) < 0.3 * bins[0]
+        assert abs(got["tilt_deg"][q][1] - truth["tilt_deg"][q][1]) < 0.3 * bins[1]
+        assert abs(got["defocus"][q] - truth["defocus"][q]) < 0.01
+    assert abs(got["waist"] / truth["waist"] - 1) < 0.01
+
+
 def test_alignment_recovers_truth_and_then_processes():
     cfg = dh_synth.config(4)
     n = 20
