@@ -319,6 +319,23 @@ def alignment_bench(dh, torch, workers, align_frames=50, decomp_frames=5000):
                                          for a in range(2)] for q in range(2)],
                       "defocus_err_D": [round(got["defocus"][q] - truth["defocus"][q], 5) for q in range(2)],
                       "waist_err_pct": round(100 * (got["waist"] / truth["waist"] - 1), 3)}
+    # the same alignment from a zero tilt: the snap finds the off-axis term in
+    # the whole Fourier plane
+    plan_z = dh.Plan(dict(cfg["params"], tilt_deg=[[0.0, 0.0], [0.0, 0.0]]), max_batch=align_frames)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gz = plan_z.autoalign(frames, align_frames, dh.ALIGN_FULL, what, 1e-5)
+    wall = time.perf_counter() - t0
+    rep = plan_z.align_report()
+    got = plan_z.params()
+    plan_z.destroy()
+    out["zero_tilt_start"] = {"align_wall_s": round(wall, 4), "goal_db": round(gz, 6), "trials": rep.evaluations,
+                              "plane_snap_err_bins": [[round((rep.plane_tilt_deg[q][a] - truth["tilt_deg"][q][a])
+                                                             / bins[a], 3) for a in range(2)] for q in range(2)],
+                              "tilt_err_bins": [[round((got["tilt_deg"][q][a] - truth["tilt_deg"][q][a]) / bins[a], 4)
+                                                 for a in range(2)] for q in range(2)],
+                              "defocus_err_D": [round(got["defocus"][q] - truth["defocus"][q], 5) for q in range(2)],
+                              "waist_err_pct": round(100 * (got["waist"] / truth["waist"] - 1), 3)}
     stream = torch.cuda.Stream()
     for _ in range(2):
         plan.process(frames, decomp_frames, stream)
