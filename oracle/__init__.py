@@ -6,12 +6,12 @@ The GPU library never calls it and shares no code with it.
 """
 from .holo_oracle import (  # noqa: F401
     DEG, w_max_rad, tilt_bins, radius_bins, ifft_size, mode_list, mode_count,
-    window_origin, mask_bins, geometry, hermite_gauss_1d, spectrum_window,
+    window_origin, mask_bins, geometry, hermite_gauss_1d, spectrum_window, window_pixels,
     field_from_window, overlap, power_normalise, process_frame, process_batch, captured_power, goal_db,
     INT16_FULL, fields_to_int16,
 )
 from .transfer_metrics import METRICS, transfer_matrix, column_keys, transfer_metrics  # noqa: F401,E402
-from .align_snap import field_moments, batch_moments, snap_centre_waist  # noqa: F401,E402
+from .align_snap import field_moments, batch_moments, snap_centre_waist, snap_defocus_magnitude  # noqa: F401,E402
 from .plane_snap import SNAP_FRAMES, plane_power, snap_tilt_plane  # noqa: F401,E402
 from .basis import lg_modes, lg_function, hg_to_lg, custom_transform, apply_basis  # noqa: F401,E402
 from .sweep_avg import (  # noqa: F401,E402

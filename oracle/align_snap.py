@@ -18,6 +18,17 @@ so for the waist. It gives no formula. The readings taken here:
                the modes m + n < G the mean of m is (G - 1) / 3, so
                <x^2> = <y^2> = w^2 (2G + 1) / 12 and
                w = sqrt(6 (<x^2> + <y^2>) / (2G + 1)).
+  defocus      the paper says the snap finds its magnitude only. A defocus D
+               is the phase pi D r^2 / lambda on the field, whose gradient
+               2 pi D r / lambda widens the angular spectrum:
+               <kx^2> + <ky^2> = K_S + a^2 (<x^2> + <y^2>), a = 2 pi D / lambda,
+               with K_S the angular spread of the modes themselves; for HG_mn
+               <kx^2> = (2m + 1) / w^2, so with the power spread evenly over G
+               groups K_S = 2 (2G + 1) / (3 w^2). Per pol, <k^2> is the central
+               second moment of the batch's window power |M I~|^2 over the
+               window bins (k = 2 pi u / (N p)) and <x^2> + <y^2> the central
+               second moment of |E|^2; |D| = lambda a / (2 pi) with
+               a^2 = max(0, (<k^2> - K_S) / (<x^2> + <y^2>)).
 """
 from __future__ import annotations
 
@@ -25,7 +36,7 @@ import math
 
 import numpy as np
 
-from .holo_oracle import field_from_window, geometry, spectrum_window
+from .holo_oracle import field_from_window, geometry, spectrum_window, window_pixels
 
 
 def field_moments(field: np.ndarray, g: dict) -> np.ndarray:
@@ -69,3 +80,35 @@ def snap_centre_waist(frames: np.ndarray, params: dict, indices=None):
     g = params["max_mg"]
     waist = math.sqrt(6.0 * (mxx + myy) / total / (2 * g + 1))
     return centre, waist
+
+
+def snap_defocus_magnitude(frames: np.ndarray, params: dict, waist: float, indices=None):
+    """The snap's defocus magnitude per pol (dioptre) from the batch at params
+    (its tilt the snapped one), with `waist` in K_S."""
+    g = geometry(params)
+    mom = batch_moments(frames, params, indices)
+    idx = range(frames.shape[0]) if indices is None else indices
+    nx, ny, p, lam = g["nx"], g["ny"], g["p"], g["lam"]
+    kx, ky = 2.0 * math.pi / (nx * p), 2.0 * math.pi / (ny * p)
+    ks = 2.0 * (2 * params["max_mg"] + 1) / (3.0 * waist * waist)
+    out = []
+    for pol in range(params["pol_count"]):
+        gp = g["pols"][pol]
+        us, vs, m = gp["us"], gp["vs"], gp["mask"]
+        xj = np.arange(nx) * p
+        yj = np.arange(ny) * p
+        dx_mat = np.exp(-2j * np.pi * np.outer(us, xj) / (nx * p))
+        dy_mat = np.exp(-2j * np.pi * np.outer(vs, yj) / (ny * p))
+        pw = np.zeros((len(vs), len(us)))
+        for b in idx:
+            win = window_pixels(np.asarray(frames[b], dtype=np.float64), g, pol)
+            pw += np.abs(dy_mat @ win @ dx_mat.T) ** 2
+        pw = np.where(m, pw, 0.0)
+        w0 = pw.sum()
+        uu, vv = np.asarray(us, dtype=np.float64)[None, :], np.asarray(vs, dtype=np.float64)[:, None]
+        mu, mv = (pw * uu).sum() / w0, (pw * vv).sum() / w0
+        k2 = kx * kx * (pw * (uu - mu) ** 2).sum() / w0 + ky * ky * (pw * (vv - mv) ** 2).sum() / w0
+        s, sx, sy, sxx, syy = mom[pol]
+        spread = (sxx - sx * sx / s) / s + (syy - sy * sy / s) / s
+        out.append(math.sqrt(max(0.0, (k2 - ks) / spread)) * lam / (2.0 * math.pi))
+    return out

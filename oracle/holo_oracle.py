@@ -192,7 +192,8 @@ def hermite_gauss_1d(n_max: int, x: np.ndarray, waist: float) -> np.ndarray:
 # --------------------------------------------------------------------------
 # the pipeline, as definitions
 # --------------------------------------------------------------------------
-def _window_pixels(frame: np.ndarray, g: dict, pol: int) -> np.ndarray:
+def window_pixels(frame: np.ndarray, g: dict, pol: int) -> np.ndarray:
+    """The FFT window of `pol` cut from the frame, [Ny][Nx], FP64."""
     gp = g["pols"][pol]
     return np.asarray(frame, dtype=np.float64)[gp["y0"]:gp["y0"] + g["ny"],
                                                gp["x0"]:gp["x0"] + g["nx"]]
@@ -204,7 +205,7 @@ def spectrum_window(frame: np.ndarray, g: dict, pol: int) -> np.ndarray:
     the pixel coordinates taken relative to the (sub-pixel) beam centre."""
     gp = g["pols"][pol]
     nx, ny, p = g["nx"], g["ny"], g["p"]
-    win = _window_pixels(frame, g, pol)
+    win = window_pixels(frame, g, pol)
     xj = (np.arange(nx) - nx / 2.0) * p - gp["dx"]
     yj = (np.arange(ny) - ny / 2.0) * p - gp["dy"]
     us, vs, m = gp["us"], gp["vs"], gp["mask"]

@@ -159,6 +159,11 @@ def test_metric_pins_catch_planted_mistake(name, monkeypatch):
 SNAP_SRC = os.path.join(os.path.dirname(SRC), "align_snap.py")
 
 SNAP_MUTATIONS = {
+    "defocus_factor": ("* lam / (2.0 * math.pi))", "* lam / math.pi)"),
+    "modes_spread": ("ks = 2.0 * (2 * params[\"max_mg\"] + 1)", "ks = (2 * params[\"max_mg\"] + 1)"),
+    "k_axes": ("ky * ky * (pw * (vv - mv) ** 2)", "kx * kx * (pw * (vv - mv) ** 2)"),
+    "k_not_central": ("(pw * (uu - mu) ** 2)", "(pw * uu ** 2)"),
+    "spread_not_central": ("spread = (sxx - sx * sx / s) / s", "spread = sxx / s"),
     "centre_sign": ("cx + sx / s, cy + sy / s", "cx - sx / s, cy - sy / s"),
     "centre_axes_swapped": ("cx + sx / s, cy + sy / s", "cx + sy / s, cy + sx / s"),
     "not_central": ("mxx += sxx - sx * sx / s", "mxx += sxx"),
@@ -175,9 +180,10 @@ def _snap_mutant(name):
     src = open(SNAP_SRC).read()
     old, new = SNAP_MUTATIONS[name]
     assert src.count(old) == 1, name
-    src = src.replace(old, new).replace("from .holo_oracle import field_from_window, geometry, spectrum_window\n", "")
+    src = src.replace(old, new).replace(
+        "from .holo_oracle import field_from_window, geometry, spectrum_window, window_pixels\n", "")
     mod = types.ModuleType("snap_mutant_" + name)
-    for k in ("field_from_window", "geometry", "spectrum_window"):
+    for k in ("field_from_window", "geometry", "spectrum_window", "window_pixels"):
         mod.__dict__[k] = getattr(oracle, k)
     exec(compile(src, SNAP_SRC + ":" + name, "exec"), mod.__dict__)
     return mod
@@ -190,10 +196,13 @@ def test_snap_pins_catch_planted_mistake(name, monkeypatch):
     mut = _snap_mutant(name)
     monkeypatch.setattr(oracle, "snap_centre_waist", mut.snap_centre_waist)
     monkeypatch.setattr(oracle, "batch_moments", mut.batch_moments)
+    monkeypatch.setattr(oracle, "snap_defocus_magnitude", mut.snap_defocus_magnitude)
     failed = 0
     for t in [pins.test_snap_centre_is_the_offset_of_a_shifted_gaussian,
               pins.test_snap_waist_from_every_mode_of_g_groups,
-              pins.test_snap_centre_per_polarisation]:
+              pins.test_snap_centre_per_polarisation,
+              pins.test_snap_defocus_magnitude_of_a_gaussian_beam,
+              pins.test_snap_defocus_magnitude_with_every_mode_of_g_groups]:
         try:
             t()
         except AssertionError:

@@ -484,6 +484,32 @@ def test_snap_centre_per_polarisation():
             assert abs(centre[q][a] - truth["beam_centre"][q][a]) < 1e-6 * pix, (q, a)
 
 
+def test_snap_defocus_magnitude_of_a_gaussian_beam():
+    # HG00 (G = 1) under a defocus D, also displaced from the window centre:
+    # <k^2> = 2 / w^2 + a^2 (<x^2> + <y^2>) exactly, so the snap returns |D|
+    base = dict(dh_synth.config(0)["truth"], max_mg=1)
+    pix = base["pixel_size"]
+    for d, off in ((0.3, [0.0, 0.0]), (-0.2, [0.7 * pix, -1.3 * pix]), (0.0, [0.0, 0.0])):
+        t = dict(base, defocus=[d], beam_centre=[off])
+        f = _one_mode_frames(t, [[(0, 0)]])
+        got = oracle.snap_defocus_magnitude(f, dict(t, defocus=[0.0], beam_centre=[[0.0, 0.0]]), t["waist"])
+        assert abs(got[0] - abs(d)) < 1e-6, (d, got)
+
+
+def test_snap_defocus_magnitude_with_every_mode_of_g_groups():
+    # one frame per HG mode of G = 3 groups at unit power on a 256 x 128
+    # window per pol (different bins per radian along x and y): the pooled
+    # spread of the modes is K_S = 2 (2G + 1) / (3 w^2), and the snap returns
+    # each pol's own |D|
+    t = dict(dh_synth.config(1)["truth"], max_mg=3, fft_w=256, fft_h=128, tilt_deg=[[1.3, 1.7], [-1.6, 1.2]],
+             defocus=[0.25, -0.15], waist=300e-6)
+    nm = oracle.mode_count(3)
+    f = _one_mode_frames(t, [[(0, k), (1, k)] for k in range(nm)])
+    got = oracle.snap_defocus_magnitude(f, dict(t, defocus=[0.0, 0.0]), t["waist"])
+    for q, d in enumerate(t["defocus"]):
+        assert abs(got[q] / abs(d) - 1.0) < 2e-3, (q, got)
+
+
 # ---------------------------------------------------------------- alignment snap (tilt, whole plane)
 def _deg_per_bin(t, axis):
     n = t["fft_w"] if axis == 0 else t["fft_h"]
