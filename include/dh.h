@@ -326,7 +326,11 @@ int dh_stage_times(dh_handle h, double* ms, int* launches);
  * the beam centre at the centroid of the batch intensity |E|^2 and the waist
  * from its pooled central second moment, w = sqrt(6 (<x^2> + <y^2>) / (2G + 1))
  * (exact when the power is spread evenly over the modes of G groups).
- * Defocus is not snapped. Tweak: a coordinate search. Tilts stay within 0.6
+ * Defocus (with DH_ALIGN_DEFOCUS): its magnitude per pol from the window's
+ * angular spread beyond the modes' own, 2 (2G + 1) / (3 w^2), over the field's
+ * spatial spread (report: snap_defocus); of the start value, +|D| and -|D|
+ * each pol keeps the one with its highest captured power (three trials).
+ * Tweak: a coordinate search. Tilts stay within 0.6
  * window radii of the snap's (of the start with TWEAK) and beam centres
  * within an eighth of the FFT window of their start; a centre that moves the FFT window out of the frame is a failed
  * trial. Each trial re-runs the window gather, the IFFTs and the overlap from
@@ -367,6 +371,7 @@ typedef struct dh_align_report {
   double snap_centre[2][2];    /* beam centre found by the snap ([pol][x,y], metres) */
   double snap_waist;           /* waist found by the snap (metres) */
   double plane_tilt_deg[2][2]; /* the snap's first guess from the whole Fourier plane ([pol][x,y]) */
+  double snap_defocus[2];      /* defocus magnitude found by the snap ([pol], dioptre) */
 } dh_align_report;
 
 /*

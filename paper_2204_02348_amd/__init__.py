@@ -79,7 +79,8 @@ class AlignReport(C.Structure):
     _fields_ = [("evaluations", C.c_int), ("sweeps", C.c_int), ("start_goal_db", C.c_double),
                 ("goal_db", C.c_double), ("captured", C.c_double), ("snap_tilt_deg", (C.c_double * 2) * 2),
                 ("goal", C.c_int), ("metrics", C.c_double * 9), ("snap_centre", (C.c_double * 2) * 2),
-                ("snap_waist", C.c_double), ("plane_tilt_deg", (C.c_double * 2) * 2)]
+                ("snap_waist", C.c_double), ("plane_tilt_deg", (C.c_double * 2) * 2),
+                ("snap_defocus", C.c_double * 2)]
 
 
 class PlanInfo(C.Structure):

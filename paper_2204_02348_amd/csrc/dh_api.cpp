@@ -1524,7 +1524,8 @@ extern "C" float dh_autoalign(dh_handle h, const void* frames, int batch, int mo
     return std::min(std::min(c0 + m, hi), std::max(std::max(c0 - m, lo), v));
   };
   // the snap estimates centre and waist from the fields (with modes to fit)
-  const bool snap_field = mode != DH_ALIGN_TWEAK && (what & (DH_ALIGN_CENTRE | DH_ALIGN_WAIST)) && g.G > 0;
+  const bool snap_field =
+      mode != DH_ALIGN_TWEAK && (what & (DH_ALIGN_CENTRE | DH_ALIGN_WAIST | DH_ALIGN_DEFOCUS)) && g.G > 0;
   // scratch: extended row pass, stored spectrum, power map, captured power,
   // and for the field snap the fields and their moments
   const size_t t1b = align256((size_t)batch * np * c.bxe * g.ny * 8);
@@ -1551,14 +1552,18 @@ extern "C" float dh_autoalign(dh_handle h, const void* frames, int batch, int mo
   float2* fdev = (float2*)(pl->amem + t1b + spb + pwb + cpb);
   double* mdev = (double*)(pl->amem + t1b + spb + pwb + cpb + fdb);
   if (!align_fft(c)) return (restore(pl, start), set_err(pl, DH_ERR_ERROR), -FLT_MAX);
-  // snap: tilt at the centroid of the batch power spectrum above its mean
-  if (mode != DH_ALIGN_TWEAK && (what & DH_ALIGN_TILT)) {
-    const size_t plane = (size_t)c.bxe * c.bye;
-    std::vector<float> hp(np * plane);
+  // the batch power spectrum over the stored box (tilt and defocus snaps)
+  const size_t plane = (size_t)c.bxe * c.bye;
+  std::vector<float> hp;
+  if (mode != DH_ALIGN_TWEAK && (what & (DH_ALIGN_TILT | DH_ALIGN_DEFOCUS))) {
+    hp.resize(np * plane);
     if (dh::launch_psum(c.spec, batch, np, plane, pw, s) != hipSuccess ||
         hipMemcpyAsync(hp.data(), pw, hp.size() * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
-      return (set_err(pl, DH_ERR_ERROR), -FLT_MAX);
+      return (restore(pl, start), set_err(pl, DH_ERR_ERROR), -FLT_MAX);
+  }
+  // snap: tilt at the centroid of the batch power spectrum above its mean
+  if (mode != DH_ALIGN_TWEAK && (what & DH_ALIGN_TILT)) {
     for (int q = 0; q < np; ++q) {
       const float* m = hp.data() + q * plane;
       double mean = 0.0;
@@ -1620,6 +1625,49 @@ extern "C" float dh_autoalign(dh_handle h, const void* frames, int batch, int mo
       rep.snap_centre[q][1] = P.beam_centre[q][1];
     }
     rep.snap_waist = P.waist;
+    if (what & DH_ALIGN_DEFOCUS) {
+      // defocus magnitude per pol (reading 30): the spread of the window's
+      // power in angle beyond what the modes of G groups hold at the waist,
+      // over the spread of the field's intensity in space; the sign (and
+      // the start value) by one trial each, kept per pol by its captured power
+      double dmag[2] = {0.0, 0.0};
+      for (int q = 0; q < np; ++q) {
+        const double* m = mom[q];
+        const double sx = m[0] > 0.0 ? (m[3] - m[1] * m[1] / m[0]) / m[0] : 0.0;
+        const double sy = m[0] > 0.0 ? (m[4] - m[2] * m[2] / m[0]) / m[0] : 0.0;
+        const double ax = P.tilt_deg[q][0] / binx, ay = P.tilt_deg[q][1] / biny;
+        const float* hq = hp.data() + (size_t)q * plane;
+        double w0 = 0.0, wt = 0.0, ws = 0.0, wtt = 0.0, wss = 0.0;
+        for (int j = 0; j < c.bxe; ++j)
+          for (int i = 0; i < c.bye; ++i) {
+            const double t = c.k0e[q] + j, u = c.ky0e[q] + i;     // tilt bins of the stored (mirror) term
+            if (!inside(-t, -u, ax, ay, g.rx, g.ry)) continue;
+            const double w = hq[(size_t)j * c.bye + i];
+            w0 += w; wt += w * t; ws += w * u; wtt += w * t * t; wss += w * u * u;
+          }
+        if (!(w0 > 0.0) || !(sx + sy > 0.0)) continue;
+        const double kx = 2.0 * kPi / (g.nx * pix), ky = 2.0 * kPi / (g.ny * pix);
+        const double k2 = kx * kx * (wtt / w0 - (wt / w0) * (wt / w0)) + ky * ky * (wss / w0 - (ws / w0) * (ws / w0));
+        const double k2s = 2.0 * (2 * g.G + 1) / (3.0 * P.waist * P.waist);
+        const double a2 = std::max(0.0, (k2 - k2s) / (sx + sy));
+        dmag[q] = std::sqrt(a2) * lam / (2.0 * kPi);
+      }
+      double best[2] = {-HUGE_VAL, -HUGE_VAL}, keep[2] = {P.defocus[0], np > 1 ? P.defocus[1] : 0.0};
+      const double d0[2] = {P.defocus[0], np > 1 ? P.defocus[1] : 0.0};
+      for (int k = 0; k < 3; ++k) {
+        for (int q = 0; q < np; ++q) P.defocus[q] = k == 0 ? d0[q] : (k == 1 ? dmag[q] : -dmag[q]);
+        if (!align_eval(c, false, mp, fp)) return (restore(pl, start), set_err(pl, DH_ERR_ERROR), -FLT_MAX);
+        for (int q = 0; q < np; ++q) {
+          const double v = db(mp[q], fp[q]);
+          if (v > best[q]) { best[q] = v; keep[q] = P.defocus[q]; }
+        }
+      }
+      for (int q = 0; q < np; ++q) {
+        P.defocus[q] = keep[q];
+        rep.snap_defocus[q] = dmag[q];
+      }
+      if (np > 1 && (pl->lock & DH_ALIGN_DEFOCUS)) P.defocus[1] = P.defocus[0];
+    }
   }
   if (pl->g.G == 0) {  // estimate only, nothing to evaluate
     for (int q = 0; q < np; ++q) derive_pol(&P, &g, q);

@@ -390,6 +390,27 @@ def test_alignment_full_from_a_zero_tilt():
     assert abs(got["waist"] / truth["waist"] - 1) < 0.01
 
 
+def test_alignment_defocus_snap_matches_oracle():
+    """ESTIMATE on the defocus alone, at the true tilt, centre and waist and a
+    zero defocus: the snap's magnitude per pol against the oracle's (1024x1024,
+    2 pols, G=30); the kept defocus is one of 0, +|D|, -|D|."""
+    cfg = dh_synth.config(4)
+    f, _ = dh_synth.make_frames(cfg, n_frames=3)
+    truth = cfg["truth"]
+    start = dict(truth, defocus=[0.0, 0.0])
+    ref = oracle.snap_defocus_magnitude(f, start, truth["waist"])
+    dh, plan, ft = _align_plan(start, f)
+    plan.autoalign(ft, f.shape[0], mode=dh.ALIGN_ESTIMATE, what=dh.ALIGN_DEFOCUS)
+    rep = plan.align_report()
+    got = plan.params()["defocus"]
+    plan.destroy()
+    for q in range(2):
+        _say("pol %d |D| gpu %.6f oracle %.6f, kept %.5f, truth %.5f" % (
+            q, rep.snap_defocus[q], ref[q], got[q], truth["defocus"][q]))
+        assert abs(rep.snap_defocus[q] - ref[q]) <= 1e-4 * max(1.0, ref[q])
+        assert min(abs(got[q]), abs(got[q] - rep.snap_defocus[q]), abs(got[q] + rep.snap_defocus[q])) < 1e-12
+
+
 def test_alignment_recovers_truth_and_then_processes():
     cfg = dh_synth.config(4)
     n = 20
