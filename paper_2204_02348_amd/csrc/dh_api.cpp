@@ -1656,7 +1656,8 @@ extern "C" float dh_autoalign(dh_handle h, const void* frames, int batch, int mo
       const double d0[2] = {P.defocus[0], np > 1 ? P.defocus[1] : 0.0};
       for (int k = 0; k < 3; ++k) {
         for (int q = 0; q < np; ++q) P.defocus[q] = k == 0 ? d0[q] : (k == 1 ? dmag[q] : -dmag[q]);
-        if (!align_eval(c, false, mp, fp)) return (restore(pl, start), set_err(pl, DH_ERR_ERROR), -FLT_MAX);
+        // the first trial also builds the HG tables of the snapped waist
+        if (!align_eval(c, k == 0, mp, fp)) return (restore(pl, start), set_err(pl, DH_ERR_ERROR), -FLT_MAX);
         for (int q = 0; q < np; ++q) {
           const double v = db(mp[q], fp[q]);
           if (v > best[q]) { best[q] = v; keep[q] = P.defocus[q]; }
