@@ -36,10 +36,10 @@ factorisation, blocking or reordering:
   coefs      c_mn = sum_{k,l} E(x'_k,y'_l) u_m(x'_k) u_n(y'_l) p'_x p'_y
   norm       c_hat = c / sqrt(sum over both pols and all modes of |c|^2)
 
-Readings taken where the paper is silent or garbled are listed in the design doc
-(window ratio and IFFT size rule, paraxial angle -> bin mapping, which cross
-term, defocus sign, coordinate origins, mask boundary, normalisations, mode
-ordering, beam-centre origin).
+Where the paper is silent or garbled, the readings taken are the ones written
+out above and in the functions below (window ratio and IFFT size rule,
+paraxial angle -> bin mapping, which cross term, defocus sign, coordinate
+origins, mask boundary, normalisations, mode ordering, beam-centre origin).
 """
 from __future__ import annotations
 

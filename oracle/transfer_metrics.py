@@ -14,8 +14,8 @@ batch x (pol x mode) matrix; independent polarisations give a
 (batch x pol) x (pol x mode) matrix whose cross-polarisation entries are zero,
 so that a missing polarisation drives the mode dependent loss to -inf. It
 can also analyse A A* instead of A. The readings taken here (dB scales, which
-entries are "diagonal") are listed in the design doc; in short, with s_k the
-singular values of A and D = A (or A A*):
+entries are "diagonal"), with s_k the singular values of A and D = A (or
+A A*):
 
   IL        10 log10(mean_k s_k^2)
   MDL       10 log10(min_k s_k^2 / max_k s_k^2)            (<= 0 dB)
