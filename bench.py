@@ -400,8 +400,8 @@ def main():
         print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4}), flush=True)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(frames shard with no exchange; see the design notes).", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path "
+              "(frames would shard by frame with no exchange).", file=sys.stderr)
         sys.exit(2)
 
     cfg = dh_synth.config(1)

@@ -131,7 +131,7 @@ typedef struct dh_plan_info {
  *   DH_ERR_NULLPOINTER        p is NULL;
  *   DH_ERR_INVALIDDIMENSION   frame or window size not a positive multiple of 16,
  *                             window outside the frame, or an FFT/IFFT length
- *                             this build does not provide;
+ *                             the library has no kernel for;
  *   DH_ERR_INVALIDPOLARISATION pol_count not 1 or 2;
  *   DH_ERR_INVALIDARGUMENT    pixel/wavelength/radius/waist not > 0, max_mg outside
  *                             0..32, unknown dtype/precision/ifft_mode/path, a Fourier
