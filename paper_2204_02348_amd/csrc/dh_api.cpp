@@ -1320,7 +1320,7 @@ bool align_fft(AlignCtx& c) {
 
 // one trial with the plan's current parameters: per-pol mode and field power
 // summed over the batch (FP64), or false if the window left the stored region
-bool align_eval(AlignCtx& c, bool hg, double mp[2], double fp[2]) {
+bool align_eval(AlignCtx& c, bool hg, double mp[2], double fp[2], bool readback = true) {
   Plan* pl = c.pl;
   Geom& g = pl->g;
   const int np = pl->params.pol_count;
@@ -1353,6 +1353,10 @@ bool align_eval(AlignCtx& c, bool hg, double mp[2], double fp[2]) {
     if (dh::launch_gather(k, c.spec + b0 * per_frame, c.bxe, c.bye, offj, offi, nb, c.s) != hipSuccess ||
         dh::launch_fld(k, b0, nb, c.s) != hipSuccess || dh::launch_norm(k, b0, nb, c.s) != hipSuccess)
       return fail();
+  }
+  if (!readback) {   // the caller reads the trial's coefficients on the same stream
+    ++c.evals;
+    return true;
   }
   std::vector<double> h((size_t)c.batch * np * 2);
   if (hipMemcpyAsync(h.data(), c.capt, h.size() * 8, hipMemcpyDeviceToHost, c.s) != hipSuccess ||
@@ -1588,7 +1592,7 @@ extern "C" float dh_autoalign(dh_handle h, const void* frames, int batch, int mo
     if (pl->lock & DH_ALIGN_TILT) for (int a = 0; a < 2; ++a) P.tilt_deg[1][a] = P.tilt_deg[0][a];
     if (pl->lock & DH_ALIGN_DEFOCUS) P.defocus[1] = P.defocus[0];
   }
-  double mp[2], fp[2];
+  double mp[2] = {0.0, 0.0}, fp[2] = {0.0, 0.0};
   if (snap_field) {
     // snap of the beam centre (intensity centroid of the reconstructed fields)
     // and of the waist (pooled central second moment, read as the power spread
@@ -1682,8 +1686,10 @@ extern "C" float dh_autoalign(dh_handle h, const void* frames, int batch, int mo
   // of the batch's coefficients (joint only)
   const bool metric_goal = pl->goal >= 0;
   auto captured = [&]() { return db(mp[0] + (np > 1 ? mp[1] : 0.0), fp[0] + (np > 1 ? fp[1] : 0.0)); };
-  auto eval_goal = [&](bool hg, double& gv) -> bool {
-    if (!align_eval(c, hg, mp, fp)) return false;
+  // a metric goal reads the trial's coefficients in tm_compute; the captured
+  // powers are read back only where they are used (capt)
+  auto eval_goal = [&](bool hg, double& gv, bool capt = false) -> bool {
+    if (!align_eval(c, hg, mp, fp, !metric_goal || capt)) return false;
     if (!metric_goal) {
       gv = captured();
       return true;
@@ -1807,7 +1813,7 @@ extern "C" float dh_autoalign(dh_handle h, const void* frames, int batch, int mo
   }
   // leave the plan at the final parameters with complete tables; all the
   // metrics of the final coefficients go in the report
-  if (!eval_goal(true, goal) || build_spectral(pl) != DH_SUCCESS ||
+  if (!eval_goal(true, goal, true) || build_spectral(pl) != DH_SUCCESS ||
       tm_compute(pl, c.batch, pl->goal_indep, pl->goal_aa, s, rep.metrics) != DH_SUCCESS)
     return (restore(pl, start), set_err(pl, DH_ERR_ERROR), -FLT_MAX);
   for (int w = 0; w < pl->nws; ++w) fill_kargs(pl, w);
