@@ -120,13 +120,17 @@ __device__ __forceinline__ long tm_key(const TmArgs& t, int k) {
 // Per row i of D (D = A, or the Gram A A^H in g, rows x rows): the row's
 // power sum_j |D_ij|^2, and for i < nd its diagonal |D_ii|^2 and the power in
 // the columns whose mode shares row i's mode key.
-__global__ void k_tm_rows(TmArgs t, const double2* __restrict__ g, int nrow, int ncol, int nd,
-                          double* __restrict__ rowpow, double* __restrict__ diag, double* __restrict__ same) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nrow) return;
+__global__ void __launch_bounds__(256) k_tm_rows(TmArgs t, const double2* __restrict__ g, int nrow, int ncol,
+                                                 int nd, double* __restrict__ rowpow, double* __restrict__ diag,
+                                                 double* __restrict__ same) {
+  // one wave per row, four per block: lane l takes the columns l, l + 64, ...,
+  // and the partial sums meet in a fixed butterfly
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= nrow) return;                        // the whole wave
   const long ki = tm_key(t, i);
   double tot = 0.0, sg = 0.0, dg = 0.0;
-  for (int j = 0; j < ncol; ++j) {
+  for (int j = lane; j < ncol; j += 64) {
     const double2 v = g ? g[(size_t)i + (size_t)j * nrow] : tm_a(t, i, j);
     const double pw = v.x * v.x + v.y * v.y;
     tot += pw;
@@ -135,10 +139,18 @@ __global__ void k_tm_rows(TmArgs t, const double2* __restrict__ g, int nrow, int
       if (tm_key(t, j) == ki) sg += pw;
     }
   }
-  rowpow[i] = tot;
-  if (i < nd) {
-    diag[i] = dg;
-    same[i] = sg;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    tot += __shfl_xor(tot, off, 64);
+    sg += __shfl_xor(sg, off, 64);
+    dg += __shfl_xor(dg, off, 64);
+  }
+  if (lane == 0) {
+    rowpow[i] = tot;
+    if (i < nd) {
+      diag[i] = dg;
+      same[i] = sg;
+    }
   }
 }
 
@@ -152,7 +164,8 @@ hipError_t launch_tm_gram(const TmArgs& t, int by_rows, int n, double2* g, hipSt
 
 hipError_t launch_tm_rows(const TmArgs& t, const double2* g, int nrow, int ncol, int nd, double* rowpow, double* diag,
                           double* same, hipStream_t s) {
-  hipLaunchKernelGGL(k_tm_rows, dim3((nrow + 127) / 128), dim3(128), 0, s, t, g, nrow, ncol, nd, rowpow, diag, same);
+  if (nrow < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_tm_rows, dim3((nrow + 3) / 4), dim3(256), 0, s, t, g, nrow, ncol, nd, rowpow, diag, same);
   return hipGetLastError();
 }
 
