@@ -1695,8 +1695,10 @@ extern "C" float dh_autoalign(dh_handle h, const void* frames, int batch, int mo
       return true;
     }
     double m[DH_METRIC_COUNT];
-    if (tm_compute(pl, c.batch, pl->goal_indep, pl->goal_aa, s, m, pl->goal == DH_METRIC_MDL) != DH_SUCCESS)
+    if (tm_compute(pl, c.batch, pl->goal_indep, pl->goal_aa, s, m, pl->goal == DH_METRIC_MDL) != DH_SUCCESS) {
+      (void)hipStreamSynchronize(s);   // the trial's uploads land before any restoring rebuild
       return false;
+    }
     gv = std::max(-1000.0, std::min(1000.0, m[pl->goal]));   // finite for the parabola
     return true;
   };
