@@ -198,3 +198,35 @@ def test_max_window_radius_matches_oracle(wrap):
     # the paper's worked example: window ~0.719 deg at tilt 1.525 deg on both axes
     assert abs(dh.max_window_radius(dict(base, tilt_deg=[[1.525, 1.525], [1.525, 1.525]])) - 0.719) < 3e-3
     assert dh.lib().dh_max_window_radius(None, 0, None) == dh.ERR_NULLPOINTER
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The binding's ctypes mirrors of dh_params, dh_plan_info and
+    dh_align_report have the header's size and every field at the header's
+    offset (a small C program built with gcc against include/dh.h)."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    structs = {"dh_params": dh.Params, "dh_plan_info": dh.PlanInfo, "dh_align_report": dh.AlignReport}
+    lines = ['#include "dh.h"', "#include <stdio.h>", "#include <stddef.h>", "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for name, _ in py._fields_:
+            lines.append(f'  printf("{cname} {name} %zu\\n", offsetof({cname}, {name}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(root, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            cname, name, val = line.split()
+            got[(cname, name)] = int(val)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for name, _ in py._fields_:
+            assert got[(cname, name)] == getattr(py, name).offset, (cname, name)
