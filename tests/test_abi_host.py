@@ -230,3 +230,16 @@ def test_struct_layouts_match_the_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for name, _ in py._fields_:
             assert got[(cname, name)] == getattr(py, name).offset, (cname, name)
+
+
+def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
+    """With libdh.so absent the binding raises on first use: there is no
+    host-side substitute for any step of the path."""
+    monkeypatch.setattr(dh, "_lib", None)
+    monkeypatch.setattr(dh, "LIB_PATH", str(tmp_path / "libdh.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        dh.lib()
+    with pytest.raises(RuntimeError, match="missing"):
+        dh.plan_check(_p(0))
+    with pytest.raises(RuntimeError, match="missing"):
+        dh.max_window_radius(_p(0))
