@@ -53,6 +53,50 @@ def stage_bytes(info, params, frames):
     }
 
 
+def frame_bytes_of(params):
+    px = 2 if params.get("input_dtype", "f32") == "u16" else 4
+    return params["frame_w"] * params["frame_h"] * px
+
+
+def algorithmic_bytes_per_frame(params, info):
+    """The path's algorithmic HBM bytes per frame: the input frame read once
+    plus the raw coefficients written once (complex64 per mode and pol)."""
+    return frame_bytes_of(params) + params["pol_count"] * info.modes * 8
+
+
+def nominal_mflop_per_frame(params, info):
+    """Nominal arithmetic of the paper's pipeline per frame (MFLOP): the 2D
+    real FFT of each pol window (2.5 N log2 N), the complex IFFT of the Fourier
+    window (5 M log2 M), the tilt/defocus phase (6 flop per field value) and
+    the separable overlap (4 Wy Wx G + 4 G^2 Wy)."""
+    import math
+    n = info.fft_w * info.fft_h
+    m = info.ifft_w * info.ifft_h
+    g = params["max_mg"]
+    per_pol = (2.5 * n * math.log2(n) + 5 * m * math.log2(m) + 6 * m
+               + 4 * info.ifft_h * info.ifft_w * g + 4 * g * g * info.ifft_h)
+    return params["pol_count"] * per_pol / 1e6
+
+
+FP32_VECTOR_PEAK_TFLOPS = 157.3      # packed (dual) FP32; plain FP32 FMA issue gives half
+
+
+def config_fraction(name, params, info, frames_per_s, workload):
+    """frames/s of one workload against the HBM ceiling (algorithmic bytes) and
+    the FP32 vector ceiling (nominal flops); the lower ceiling binds."""
+    ab = algorithmic_bytes_per_frame(params, info)
+    mf = nominal_mflop_per_frame(params, info)
+    hbm_ceiling = HBM_PEAK_GBS * 1e9 / ab
+    alu_ceiling = FP32_VECTOR_PEAK_TFLOPS * 1e12 / (mf * 1e6)
+    bound = "hbm" if hbm_ceiling <= alu_ceiling else "alu"
+    return {"workload": workload, "frames_per_s": round(frames_per_s, 1),
+            "algorithmic_bytes_per_frame": int(ab), "nominal_mflop_per_frame": round(mf, 2),
+            "hbm_frac": round(frames_per_s * ab / (HBM_PEAK_GBS * 1e9), 4),
+            "alu_frac": round(frames_per_s * mf * 1e6 / (FP32_VECTOR_PEAK_TFLOPS * 1e12), 4),
+            "bound": bound, "ceiling_frames_per_s": round(min(hbm_ceiling, alu_ceiling), 1),
+            "frac_of_ceiling": round(frames_per_s / min(hbm_ceiling, alu_ceiling), 4)}
+
+
 def stage_kernel(stage, info):
     return {"row_fft": "dh::k_row", "column_fft_window": "dh::k_cspec" if info.path == 2 else "dh::k_col",
             "field_overlap": "dh::k_fld", "power_norm": "dh::k_norm"}[stage]
@@ -108,6 +152,10 @@ def time_forms(dh, torch, cfg, ft, B, stream, steps=20, warmup=20):
             out[name] = {
                 "frames_per_s": round(steps * B / (ms / 1e3), 1),
                 "stages_ms": {k: round(v[0] / steps, 4) for k, v in st.items() if v[1]}}
+            if groups == 20 and prec == "fp32" and path == "spectral" and mode == 1:
+                info = dh.plan_check(d, B)[1]
+                out["_c3"] = config_fraction("c3", d, info, steps * B / (ms / 1e3),
+                                             "1000 frames 640x512 f32, 2 pols, G=20 (210 modes/pol), FP32")
     return out
 
 
@@ -183,7 +231,7 @@ def time_aux(dh, torch, cfg, ft, B, stream, reps=20):
     return out
 
 
-def single_frame_bench(dh, torch, reps=2000, warm=200):
+def single_frame_bench(dh, torch, reps=10000, warm=500):
     """One 128x128 f32 frame at a time (1 pol, G=4, the smallest workload):
     the latency a caller sees for dh_process_batch of one frame followed by
     a stream synchronisation (binding call included), p50/p99 over `reps`
@@ -264,13 +312,98 @@ def serving_bench(dh, torch, workers, seconds=10.0, warm=1.0, rate=5000.0, seed=
     srv.destroy()
     # the same 20000 requests one at a time through dh_process_batch (batch 1, waiting for each)
     t0 = time.perf_counter()
-    for k in range(2000):
+    for k in range(n):
         c = int(cam[k])
         plans[c].process(int(ptr[k]), 1, None)
         plans[c].coefs(True)
-    out["one_at_a_time_frames_per_s"] = round(2000 / (time.perf_counter() - t0), 1)
+    out["one_at_a_time_frames_per_s"] = round(n / (time.perf_counter() - t0), 1)
+    # the plain batch path on the same trace (static batching), and saturated
+    m = t >= warm
+    done_b, nb_rounds = static_batching(dh, torch, plans, pools, t, cam, max_batch=256)
+    lat_b = (done_b - t) * 1e3
+    out["static_batching"] = {
+        "what": "the same Poisson trace through per-camera dh_process_batch: whenever the device is idle, every "
+                "request that has arrived (<= 256 per camera) forms one batch per camera, the batches run on one "
+                "stream and the loop waits for their coefficients; later arrivals wait for the next round. Frames "
+                "are read as contiguous runs of each camera's resident pool (no gather), the plain path's best case",
+        "frames_per_s": round(float(m.sum() / (done_b[m].max() - warm)), 1),
+        "p50_ms": round(float(np.percentile(lat_b[m], 50)), 4), "p99_ms": round(float(np.percentile(lat_b[m], 99)), 4),
+        "rounds": nb_rounds}
+    done_b, nb_rounds = static_batching(dh, torch, plans, pools, np.zeros(n), cam[:n], max_batch=256)
+    out["static_batching"]["saturated_frames_per_s"] = round(n / float(done_b.max()), 1)
     for p in plans:
         p.destroy()
+    return out
+
+
+def static_batching(dh, torch, plans, pools, t, cam, max_batch=256):
+    """Replay a request trace through the plain batch path in real time: a loop
+    that, whenever its previous round has finished, takes every request that
+    has arrived (up to max_batch per camera), runs one dh_process_batch per
+    camera on one stream and reads the coefficients back, then stamps the
+    round's completion time on its requests. Returns (completion times, rounds)."""
+    from collections import deque
+    stream = torch.cuda.Stream()
+    tiled = []
+    for pool in pools:                      # contiguous runs of up to max_batch frames
+        reps = -(-max_batch // pool.shape[0])
+        tiled.append(pool.repeat(reps, *([1] * (pool.dim() - 1)))[:max_batch].contiguous())
+    torch.cuda.synchronize()
+    n = t.size
+    done = np.zeros(n)
+    pending = [deque() for _ in plans]
+    nxt, finished, rounds = 0, 0, 0
+    start = time.perf_counter()
+    while finished < n:
+        now = time.perf_counter() - start
+        while nxt < n and t[nxt] <= now:
+            pending[int(cam[nxt])].append(nxt)
+            nxt += 1
+        if not any(pending):
+            continue
+        took = []
+        for c, q in enumerate(pending):
+            k = min(len(q), max_batch)
+            if k:
+                ids = [q.popleft() for _ in range(k)]
+                plans[c].process(tiled[c], k, stream)
+                took.append((c, ids))
+        for c, ids in took:
+            plans[c].coefs(True)             # waits for the stream
+        end = time.perf_counter() - start
+        for c, ids in took:
+            done[ids] = end
+            finished += len(ids)
+        rounds += 1
+    return done, rounds
+
+
+def camera_batches(dh, torch, workers, batch=256, steps=10, warmup=10):
+    """Batch throughput of each serving camera's plan on its own (uint16
+    frames, 1 pol), with the fraction of the binding ceiling."""
+    out = {}
+    for c in range(4):
+        cfg = dh_synth.config(3, c)
+        b = batch if c < 3 else 64
+        pool, _ = dh_synth.make_frames(cfg, n_frames=64, workers=workers)
+        ft = torch.from_numpy(dh_synth.tile_pool(pool, b)).to("cuda:0")
+        plan = dh.Plan(cfg["params"], max_batch=b)
+        stream = torch.cuda.Stream()
+        for _ in range(warmup):
+            plan.process(ft, b, stream)
+        stream.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            plan.process(ft, b, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        fps = steps * b / (e0.elapsed_time(e1) / 1e3)
+        p = cfg["params"]
+        out[f"{p['frame_w']}x{p['frame_h']}"] = config_fraction(
+            "c4", p, plan.info, fps, f"{b} frames {p['frame_w']}x{p['frame_h']} uint16, 1 pol, G={p['max_mg']}")
+        plan.destroy()
+        del ft
     return out
 
 
@@ -347,29 +480,58 @@ def alignment_bench(dh, torch, workers, align_frames=50, decomp_frames=5000):
     e1.record(stream)
     torch.cuda.synchronize()
     out["decompose_frames_per_s"] = round(5 * decomp_frames / (e0.elapsed_time(e1) / 1e3), 1)
+    out["_c5"] = config_fraction("c5", cfg["params"], plan.info, out["decompose_frames_per_s"],
+                                 "5000 frames 1024x1024 f32, 2 pols, G=30 (465 modes/pol), FP32")
     plan.destroy()
     return out
 
 
-def cpu_baseline(cfg, frames, seconds):
-    """The FP64 oracle, as it stands, on a bounded sample of the same frames."""
-    import oracle
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def _blas():
     try:
         from threadpoolctl import threadpool_info
-        threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
+        libs = [f"{t.get('internal_api')} {t.get('version')}" for t in threadpool_info() if t.get("user_api") == "blas"]
+        return ", ".join(libs) or "unknown"
     except Exception:
-        threads = len(os.sched_getaffinity(0))
+        return "unknown"
+
+
+def cpu_baseline(cfg, frames, seconds):
+    """The FP64 oracle, as it stands, on a bounded sample of the same frames:
+    one leg with one BLAS thread and one with every core the process may use.
+    The headline object is the all-cores leg."""
+    import oracle
+    from threadpoolctl import threadpool_limits
     p = cfg["params"]
     g = oracle.geometry(p)
-    oracle.process_frame(frames[0].astype(np.float64), p, g)   # warm caches
-    n = 0
-    t0 = time.perf_counter()
-    while n < frames.shape[0] and (n < 4 or time.perf_counter() - t0 < seconds):
-        oracle.process_frame(frames[n].astype(np.float64), p, g)
-        n += 1
-    dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "frames/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{n} frames of the same batch, one at a time, {dt:.1f} s"}
+    ncores = len(os.sched_getaffinity(0))
+    legs = []
+    for threads in (1, ncores):
+        with threadpool_limits(limits=threads):
+            oracle.process_frame(frames[0].astype(np.float64), p, g)   # warm caches
+            n = 0
+            t0 = time.perf_counter()
+            while n < frames.shape[0] and (n < 2 or time.perf_counter() - t0 < seconds):
+                oracle.process_frame(frames[n].astype(np.float64), p, g)
+                n += 1
+            dt = time.perf_counter() - t0
+        legs.append({"value": n / dt, "unit": "frames/s", "cores": threads, "frames": n, "seconds": round(dt, 2)})
+    cpu, blas = _cpu_model(), _blas()
+    all_cores = legs[1]
+    return {"value": all_cores["value"], "unit": "frames/s", "cores": all_cores["cores"], "kind": "oracle",
+            "sample": f"{all_cores['frames']} frames of the same batch, one at a time, {all_cores['seconds']} s "
+                      f"({ncores} BLAS threads); single-thread leg {legs[0]['frames']} frames in {legs[0]['seconds']} s",
+            "cpu_model": cpu, "blas": blas, "legs": legs}
 
 
 def main():
@@ -381,7 +543,9 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--frames", type=int, default=1000)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--settle-ms", type=float, default=150.0,
+                    help="untimed steps for this long before the warm-up steps (engine clock ramp)")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the FP32 / split BF16 / split FP16 comparison")
     ap.add_argument("--no-serving", action="store_true", help="skip the four-camera serving run")
@@ -420,10 +584,19 @@ def main():
     info = plan.info
     stream = torch.cuda.Stream(device=dev)
     torch.cuda.synchronize()
+    # the engine clock ramps up over the first ~20 ms of sustained work (the
+    # VALU-bound column pass runs ~25 % slower before): untimed steps until
+    # --settle-ms of device work have passed, then the W warm-up steps
+    settle = 0
+    t_settle = time.perf_counter()
+    while (time.perf_counter() - t_settle) * 1e3 < args.settle_ms:
+        plan.process(ft, B, stream)
+        stream.synchronize()
+        settle += 1
     for _ in range(args.warmup):
         plan.process(ft, B, stream)
     stream.synchronize()
-    print(f"[bench] warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
+    print(f"[bench] clock settle {settle} steps, warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
 
     # timed window 1: the throughput (one event pair per step, for the latency)
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
@@ -452,20 +625,38 @@ def main():
     plan.set_stage_timing(False)
     stage_window_ms = w0.elapsed_time(w1) / args.steps
 
-    # roofline of the dominant kernel: algorithmic bytes per launch / mean launch time
+    # roofline of the dominant kernel: the path's algorithmic bytes (each frame
+    # read once, its coefficients written once) for the frames one launch
+    # processes, over the kernel's mean launch time
     sb = stage_bytes(info, cfg["params"], B)
     dom = max(stages, key=lambda k: stages[k][0])
     ms_dom, n_dom = stages[dom]
-    per_launch_bytes = sb[dom] / (n_dom / args.steps)
-    achieved = per_launch_bytes / (ms_dom / n_dom / 1e3) / 1e9
     frames_per_launch = B / (n_dom / args.steps)
+    alg_frame = algorithmic_bytes_per_frame(cfg["params"], info)
+    per_launch_bytes = alg_frame * frames_per_launch
+    launch_s = ms_dom / n_dom / 1e3
+    achieved = per_launch_bytes / launch_s / 1e9
+    traffic = counter_traffic(dom, info, frames_per_launch) if B == 1000 else None
+    kernel_bytes = sb[dom] / (n_dom / args.steps)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": counter_traffic(dom, info, frames_per_launch) if B == 1000 else None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                "algorithmic_bytes": round(per_launch_bytes), "kernel": dom,
-                "launch_ms": round(ms_dom / n_dom, 4), "launches_per_step": n_dom // args.steps}
-    frame_bytes = frames[0].nbytes
+                "algorithmic_bytes": round(per_launch_bytes),
+                "algorithmic_bytes_per_frame": int(alg_frame),
+                "algorithmic_what": "frame read once + raw coefficients written once, per frame of the launch",
+                "kernel": dom, "launch_ms": round(ms_dom / n_dom, 4), "launches_per_step": n_dom // args.steps,
+                "kernel_bytes": round(kernel_bytes),
+                "kernel_bytes_what": "what the kernel reads and writes by design (frame in, row-pass spectrum out)",
+                "kernel_bytes_frac": round(kernel_bytes / launch_s / 1e9 / HBM_PEAK_GBS, 4),
+                "traffic_over_algorithmic": round(traffic / per_launch_bytes, 3) if traffic else None}
+    step_s = total_ms / args.steps / 1e3
+    fft_ms = (stages["row_fft"][0] + stages["column_fft_window"][0]) / args.steps
+    path = {"what": "whole path: frames x algorithmic bytes per frame over the timed step",
+            "achieved_GBs": round(B * alg_frame / step_s / 1e9, 1),
+            "frac": round(B * alg_frame / step_s / 1e9 / HBM_PEAK_GBS, 4),
+            "ceiling_frames_per_s": round(HBM_PEAK_GBS * 1e9 / alg_frame, 1),
+            "fft_stages_frac": round(B * frame_bytes_of(cfg["params"]) / (fft_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "fft_stages_what": "frame bytes over the row + column pass time (stage window)"}
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "frames/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(total_ms / args.steps, 4),
@@ -475,27 +666,33 @@ def main():
                                "defocus, shot+read noise; plain FP32",
                    "frames": B, "frame": "640x512", "pols": 2, "max_mg": 9, "precision": "fp32",
                    "path": {1: "field", 2: "spectral"}[info.path]},
+        "clock_settle_steps": settle,
         "p50_ms": round(float(np.percentile(lat, 50)), 4), "p99_ms": round(float(np.percentile(lat, 99)), 4),
         "stages_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in stages.items()},
         "stage_window": {"what": "a second timed window of the same K steps right after the first, with HIP "
                                  "events around every launch; stages_ms_per_step and roofline come from it",
                          "ms_per_step": round(stage_window_ms, 4)},
-        "path_hbm_frac": round(frame_bytes * value / 1e9 / HBM_PEAK_GBS, 4),
+        "path_roofline": path,
         "roofline": roofline,
+        "configs_roofline": {"c2": config_fraction("c2", cfg["params"], info, value, "1000 frames 640x512 f32, "
+                                                   "2 pols, G=9 (45 modes/pol), FP32 (this line's value)")},
     }
     plan.destroy()
     if not args.no_forms:
         out["forms"] = time_forms(dh, torch, cfg, ft, B, stream)
         out["variants"] = time_variants(dh, torch, cfg, ft, B, stream)
         out["aux"] = time_aux(dh, torch, cfg, ft, B, stream)
+        out["configs_roofline"]["c3"] = out["forms"].pop("_c3", None)
         print("[bench] forms done", file=sys.stderr, flush=True)
     del ft
     if not args.no_serving:
         out["single_frame"] = single_frame_bench(dh, torch)
         out["serving"] = serving_bench(dh, torch, workers)
+        out["configs_roofline"]["c4"] = camera_batches(dh, torch, workers)
         print("[bench] serving done", file=sys.stderr, flush=True)
     if not args.no_align:
         out["alignment"] = alignment_bench(dh, torch, workers)
+        out["configs_roofline"]["c5"] = out["alignment"].pop("_c5", None)
         print("[bench] alignment done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, frames, args.cpu_seconds)

@@ -215,6 +215,45 @@ def _ptr(x) -> int:
     raise TypeError(type(x))
 
 
+def _frames_ptr(x, n_frames: int, frame_elems: int, input_dtype: int, device, what: str) -> int:
+    """Device address of `n_frames` frames of `frame_elems` pixels for a call
+    into the library. A tensor-like object (``data_ptr``, ``is_cuda``) must be
+    on the plan's GPU, contiguous, of the plan's pixel type (4-byte floats for
+    f32 plans, 2-byte integers for u16 plans) and hold at least the frames the
+    call reads; anything else raises ValueError before the library is called.
+    A raw integer address is the caller's responsibility."""
+    if x is None:
+        raise ValueError(f"{what}: frames is None")
+    if isinstance(x, int):
+        return x
+    if not hasattr(x, "data_ptr"):
+        raise ValueError(f"{what}: frames must be a device tensor or an integer device address, not {type(x)}")
+    if hasattr(x, "is_cuda"):
+        if not x.is_cuda:
+            raise ValueError(f"{what}: frames must be in GPU memory (got a host tensor)")
+        if device is not None and getattr(x.device, "index", device) != device:
+            raise ValueError(f"{what}: frames are on cuda:{x.device.index}, the plan on cuda:{device}")
+        if not x.is_contiguous():
+            raise ValueError(f"{what}: frames must be contiguous")
+        want = 2 if input_dtype == INPUT_U16 else 4
+        if x.element_size() != want or (input_dtype == INPUT_F32) != bool(x.is_floating_point()):
+            kind = "uint16" if input_dtype == INPUT_U16 else "float32"
+            raise ValueError(f"{what}: the plan reads {kind} pixels, frames have dtype {x.dtype}")
+        if x.numel() < n_frames * frame_elems:
+            raise ValueError(f"{what}: {n_frames} frames of {frame_elems} pixels needed, frames hold {x.numel()}")
+    return x.data_ptr()
+
+
+def _current_device():
+    """The current torch device ordinal if torch is loaded and has a GPU, else None."""
+    import sys
+    torch = sys.modules.get("torch")
+    try:
+        return torch.cuda.current_device() if torch is not None and torch.cuda.is_available() else None
+    except Exception:
+        return None
+
+
 def _stream(s) -> int:
     if s is None:
         return 0
@@ -242,14 +281,23 @@ class Plan:
             raise DhError(rc, "dh_plan")
         self.handle = h.value
         self.max_batch = max_batch
+        self.device = _current_device()
+        self._avg = 1
+        self._frame_elems = self._p.frame_w * self._p.frame_h
         info = PlanInfo()
         rc = lib().dh_get_plan_info(self.handle, C.byref(info))
         if rc != SUCCESS:
             raise DhError(rc, "dh_get_plan_info")
         self.info = info
 
+    def _frames(self, frames, batch: int, what: str) -> int:
+        n = max(int(batch), 1) * self._avg
+        return _frames_ptr(frames, n, self._frame_elems, self._p.input_dtype, self.device, what)
+
     def process(self, frames, batch: int, stream=None):
-        rc = lib().dh_process_batch(self.handle, C.c_void_p(_ptr(frames)), batch, C.c_void_p(_stream(stream)))
+        """dh_process_batch: `batch` outputs from batch x (averaging count) frames."""
+        ptr = self._frames(frames, batch, "dh_process_batch")
+        rc = lib().dh_process_batch(self.handle, C.c_void_p(ptr), batch, C.c_void_p(_stream(stream)))
         if rc != SUCCESS:
             raise DhError(rc, "dh_process_batch")
 
@@ -280,6 +328,7 @@ class Plan:
         rc = lib().dh_set_averaging(self.handle, int(count), int(mode))
         if rc != SUCCESS:
             raise DhError(rc, "dh_set_averaging")
+        self._avg = max(int(count), 1)
 
     def set_basis(self, basis: int, matrix=None):
         """BASIS_HG, BASIS_LG, or BASIS_CUSTOM with `matrix` (modes_out x modes_in complex)."""
@@ -371,7 +420,9 @@ class Plan:
     def autoalign(self, frames, batch: int, mode: int = ALIGN_FULL,
                   what: int = ALIGN_TILT | ALIGN_DEFOCUS | ALIGN_WAIST, tol: float = 1e-4, stream=None) -> float:
         """Goal in dB after alignment; the plan keeps the aligned parameters."""
-        g = lib().dh_autoalign(self.handle, C.c_void_p(_ptr(frames)), batch, mode, what, tol,
+        ptr = _frames_ptr(frames, max(int(batch), 1), self._frame_elems, self._p.input_dtype, self.device,
+                          "dh_autoalign")
+        g = lib().dh_autoalign(self.handle, C.c_void_p(ptr), batch, mode, what, tol,
                                C.c_void_p(_stream(stream)))
         if g == -3.4028234663852886e38:
             raise DhError(self.last_error(), "dh_autoalign")
@@ -447,7 +498,11 @@ class Server:
         return done
 
     def submit(self, camera: int, frame, result=None):
-        rc = lib().dh_serve_submit(self.handle, camera, C.c_void_p(_ptr(frame)),
+        if not 0 <= camera < len(self.plans):
+            raise ValueError(f"dh_serve_submit: camera {camera} of {len(self.plans)}")
+        pl = self.plans[camera]
+        ptr = _frames_ptr(frame, 1, pl._frame_elems, pl._p.input_dtype, pl.device, "dh_serve_submit")
+        rc = lib().dh_serve_submit(self.handle, camera, C.c_void_p(ptr),
                                    None if result is None else result.ctypes.data)
         if rc != SUCCESS:
             raise DhError(rc, "dh_serve_submit")

@@ -72,6 +72,15 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, unsig
 __device__ __forceinline__ float2 buf_ld_nt(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
   return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 2));
 }
+// t1 travels non-temporally unless the build asks for cached t1 traffic
+// (-DDH_T1_CACHED=1), the form for launches whose t1 fits the caches
+#ifndef DH_T1_CACHED
+#define DH_T1_CACHED 0
+#endif
+constexpr bool kT1Nt = !DH_T1_CACHED;
+__device__ __forceinline__ float2 buf_ld_t1(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, kT1Nt ? 2 : 0));
+}
 
 // t1 element (box column j, row y) of one frame and pol: tiles of 16 rows,
 // [y / 16][j][y % 16], so that a row-pass block's writes are contiguous
@@ -180,8 +189,8 @@ __global__ void __launch_bounds__(TR * NX / FftPlan<NX>::R0) k_row(KArgs A, cons
       const int t = e % TR, j = e / TR;
       const int y = ybase + 2 * t;
       if (y >= A.ny) continue;
-      int k = P.k0 + j;
-      k = (k >= NX) ? k - NX : (k < 0 ? k + NX : k);
+      // bins are periodic: a tilt of any size reaches its window through k mod NX
+      const int k = ((P.k0 + j) % NX + NX) % NX;
       const int km = (k == 0) ? 0 : NX - k;
       const float2* tb = buf + t * L::STRIDE;
       const float2 z1 = tb[L::at(k)];
@@ -192,7 +201,7 @@ __global__ void __launch_bounds__(TR * NX / FftPlan<NX>::R0) k_row(KArgs A, cons
       // rows y, y+1 (ny is even). A workgroup writes 2 TR rows of each
       // 16-row tile per phase: from 64 B on, non-temporal stores are faster;
       // the 32 B pieces of TR = 2 need the cache to merge them into lines
-      if constexpr (2 * TR >= 8) {
+      if constexpr (2 * TR >= 8 && kT1Nt) {
         const floatx4 t4 = {x.x, x.y, x.z, x.w};
         __builtin_nontemporal_store(t4, reinterpret_cast<floatx4*>(o));
       } else {
@@ -257,10 +266,10 @@ __global__ void __launch_bounds__(kTPB) k_col(KArgs A, int b0) {
         const int voff = ((b >> 4) * A.bx + j) * 128 + (b & 15) * 8;
         const int rstride = (Q::NB / 16) * A.bx * 128;
 #pragma unroll
-        for (int r = 0; r < Q::R0; ++r) v[it][r] = buf_ld_nt(rt, voff, r * rstride);
+        for (int r = 0; r < Q::R0; ++r) v[it][r] = buf_ld_t1(rt, voff, r * rstride);
       } else {
 #pragma unroll
-        for (int r = 0; r < Q::R0; ++r) v[it][r] = buf_ld_nt(rt, (int)t1_at(j, b + r * Q::NB, A.bx) * 8, 0);
+        for (int r = 0; r < Q::R0; ++r) v[it][r] = buf_ld_t1(rt, (int)t1_at(j, b + r * Q::NB, A.bx) * 8, 0);
       }
     }
 #pragma unroll
@@ -427,10 +436,10 @@ __global__ void __launch_bounds__(kTPB) k_cspec(KArgs A, int b0) {
         const int voff = ((b >> 4) * A.bx + j) * 128 + (b & 15) * 8;
         const int rstride = (Q::NB / 16) * A.bx * 128;
 #pragma unroll
-        for (int r = 0; r < Q::R0; ++r) v[it][r] = buf_ld_nt(rt, voff, r * rstride);
+        for (int r = 0; r < Q::R0; ++r) v[it][r] = buf_ld_t1(rt, voff, r * rstride);
       } else {
 #pragma unroll
-        for (int r = 0; r < Q::R0; ++r) v[it][r] = buf_ld_nt(rt, (int)t1_at(j, b + r * Q::NB, A.bx) * 8, 0);
+        for (int r = 0; r < Q::R0; ++r) v[it][r] = buf_ld_t1(rt, (int)t1_at(j, b + r * Q::NB, A.bx) * 8, 0);
       }
     }
     if constexpr (!TWG) stwy.store(twy, twn<NY>(), make_float2(0.f, 0.f), tid);

@@ -243,3 +243,60 @@ def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
         dh.plan_check(_p(0))
     with pytest.raises(RuntimeError, match="missing"):
         dh.max_window_radius(_p(0))
+
+
+class _FakeDevice:
+    def __init__(self, index):
+        self.index = index
+
+
+class _FakeTensor:
+    """Duck-typed stand-in for a device tensor (no GPU needed)."""
+
+    def __init__(self, numel, elem=4, floating=True, cuda=True, contiguous=True, device=0):
+        self._n, self._e, self._f, self.is_cuda, self._c = numel, elem, floating, cuda, contiguous
+        self.device = _FakeDevice(device)
+        self.dtype = f"fake{elem * 8}{'f' if floating else 'i'}"
+
+    def data_ptr(self):
+        return 0x1000
+
+    def numel(self):
+        return self._n
+
+    def element_size(self):
+        return self._e
+
+    def is_floating_point(self):
+        return self._f
+
+    def is_contiguous(self):
+        return self._c
+
+
+@pytest.mark.parametrize("kw,dtype,msg", [
+    (dict(cuda=False), dh.INPUT_F32, "GPU memory"),
+    (dict(contiguous=False), dh.INPUT_F32, "contiguous"),
+    (dict(elem=8), dh.INPUT_F32, "float32"),                       # float64 frames for an f32 plan
+    (dict(elem=4, floating=False), dh.INPUT_F32, "float32"),       # int32 frames
+    (dict(elem=4), dh.INPUT_U16, "uint16"),                        # float32 frames for a u16 plan
+    (dict(numel=3 * 640 * 512 - 1), dh.INPUT_F32, "frames hold"),  # one pixel short of 3 frames
+    (dict(device=1), dh.INPUT_F32, "cuda:1"),
+])
+def test_binding_rejects_bad_frame_buffers(kw, dtype, msg):
+    args = dict(numel=3 * 640 * 512, elem=2 if dtype == dh.INPUT_U16 else 4, floating=dtype == dh.INPUT_F32)
+    args.update(kw)
+    with pytest.raises(ValueError, match=msg):
+        dh._frames_ptr(_FakeTensor(**args), 3, 640 * 512, dtype, 0, "dh_process_batch")
+    with pytest.raises(ValueError):
+        dh._frames_ptr(None, 3, 640 * 512, dtype, 0, "dh_process_batch")
+    with pytest.raises(ValueError):
+        dh._frames_ptr(np.zeros(4, np.float32), 1, 4, dtype, 0, "dh_process_batch")
+
+
+def test_binding_accepts_good_frame_buffers():
+    t = _FakeTensor(3 * 640 * 512)
+    assert dh._frames_ptr(t, 3, 640 * 512, dh.INPUT_F32, 0, "x") == 0x1000
+    t = _FakeTensor(2 * 64, elem=2, floating=False)
+    assert dh._frames_ptr(t, 2, 64, dh.INPUT_U16, None, "x") == 0x1000
+    assert dh._frames_ptr(0x2000, 10 ** 6, 10 ** 6, dh.INPUT_F32, 0, "x") == 0x2000   # raw address: trusted

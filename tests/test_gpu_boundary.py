@@ -1,0 +1,57 @@
+"""Boundary semantics on the GPU, through the C ABI: tilts beyond the
+spectrum (periodic bins), batches larger than the plan's max_batch, the
+field axes."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import dh_synth
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _rel(a, b):
+    n = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (n if n > 0 else 1.0)
+
+
+@pytest.mark.parametrize("path", ["spectral", "field"])
+@pytest.mark.parametrize("shift", [4, -4])
+def test_tilt_beyond_the_spectrum_aliases(path, shift):
+    """A reference tilt several spectrum widths away reaches its window through
+    the periodic bins (k mod N), as the oracle's direct DFT does: the 128x128
+    frame with its x tilt moved by `shift` times w_max (2 N bins) matches the
+    oracle at that tilt."""
+    torch = _torch()
+    import paper_2204_02348_amd as dh
+    cfg = dh_synth.config(0)
+    f, _ = dh_synth.make_frames(cfg)
+    p = dict(cfg["params"])
+    wmax = math.degrees(p["wavelength"] / (2 * p["pixel_size"]))
+    p["tilt_deg"] = [[p["tilt_deg"][0][0] + shift * wmax, p["tilt_deg"][0][1]], [0.0, 0.0]]
+    _say(f"128x128 tilt x {p['tilt_deg'][0][0]:.3f} deg, {path} path")
+    plan = dh.Plan(dict(p, path=path, keep_window=1), max_batch=1)
+    plan.process(torch.from_numpy(f).cuda(), 1, None)
+    got, win = plan.coefs(False)[0, 0], plan.window()[0, 0]
+    plan.destroy()
+    ref = oracle.process_frame(f[0].astype(np.float64), p)
+    e, ew = _rel(got, ref["coefs"][0]), _rel(win, ref["window"][0])
+    _say(f"coefficient rel-L2 {e:.2e}, window {ew:.2e}")
+    assert e <= TOL and ew <= TOL
