@@ -19,3 +19,7 @@ from .sweep_avg import (  # noqa: F401,E402
     process_sweep,
 )
 from .window_fit import max_window_radius  # noqa: F401,E402
+from .batch_summary import (  # noqa: F401,E402
+    PARAMETERS, plane_parameters, fourier_axes, fourier_plane, field_axes, summarise, batch_summary_fourier,
+    batch_summary_field,
+)

@@ -422,3 +422,47 @@ def test_window_pins_catch_planted_mistake(name, monkeypatch):
         except AssertionError:
             failed += 1
     assert failed > 0, name
+
+
+# ---------------------------------------------------------------- batch summary
+SUM_SRC = os.path.join(os.path.dirname(SRC), "batch_summary.py")
+
+SUM_MUTATIONS = {
+    "aeff_not_squared": ("out[5] = (s * da) ** 2", "out[5] = (s * da)"),
+    "com_over_power": ("out[1] = float(i.sum(axis=0) @ x) / s", "out[1] = float(i.sum(axis=0) @ x) / (s * da)"),
+    "total_without_cell": ("out[0] = s * da", "out[0] = s"),
+    "maxabs_is_intensity": ("out[3] = math.sqrt(flat[k])", "out[3] = flat[k]"),
+    "index_column_major": ("flat = i.ravel()", "flat = i.T.ravel()"),
+    "wrap_period_off_by_one": ("period = h * dy", "period = (h - 1) * dy"),
+    "fourier_rows_unshifted": ("ky = np.arange(ny) - ny // 2", "ky = np.arange(ny)"),
+    "fourier_x_axis_pitch": ("x = np.arange(nx // 2 + 1) * lam / (nx * p) / DEG",
+                             "x = np.arange(nx // 2 + 1) * lam / (ny * p) / DEG"),
+    "batch_entry_mean": ("total = intensities.sum(axis=0)", "total = intensities.mean(axis=0)"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(SUM_MUTATIONS))
+def test_summary_pins_catch_planted_mistake(name, monkeypatch):
+    import oracle
+    import tests.test_oracle_pins as pins
+    src = open(SUM_SRC).read()
+    old, new = SUM_MUTATIONS[name]
+    assert src.count(old) == 1, name
+    src = src.replace(old, new).replace("from .holo_oracle import DEG, geometry, window_pixels\n", "")
+    mod = types.ModuleType("sum_mutant_" + name)
+    for k in ("DEG", "geometry", "window_pixels"):
+        mod.__dict__[k] = getattr(oracle.holo_oracle, k)
+    exec(compile(src, SUM_SRC + ":" + name, "exec"), mod.__dict__)
+    for f in ("plane_parameters", "fourier_axes", "fourier_plane", "field_axes", "summarise",
+              "batch_summary_fourier", "batch_summary_field"):
+        monkeypatch.setattr(oracle, f, getattr(mod, f))
+    failed = 0
+    for t in [pins.test_summary_gaussian_beam_closed_forms, pins.test_summary_wrapped_centre_of_mass,
+              pins.test_summary_uniform_patch_and_zero_plane, pins.test_summary_fourier_plane_of_a_tone,
+              pins.test_summary_field_plane_of_a_fundamental_mode,
+              pins.test_summary_batch_entry_is_the_summed_intensity]:
+        try:
+            t()
+        except (AssertionError, ValueError, IndexError):
+            failed += 1
+    assert failed > 0, name

@@ -899,3 +899,113 @@ def test_largest_window_by_brute_force(wrap):
             continue
         assert not violates(t, w), (t, w)
         assert violates(t, w * 1.002), (t, w)
+
+
+# ---------------------------------------------------------------- batch summary
+def _gauss_plane(w, h, dx, dy, x0, y0, waist):
+    x = (np.arange(w) - w / 2.0) * dx
+    y = (np.arange(h) - h / 2.0) * dy
+    r2 = (x[None, :] - x0) ** 2 + (y[:, None] - y0) ** 2
+    return np.exp(-2.0 * r2 / waist ** 2), x, y
+
+
+def test_summary_gaussian_beam_closed_forms():
+    """I = exp(-2 r^2 / w^2): total power pi w^2 / 2, effective area pi w^2,
+    centre of mass at the beam centre, peak 1 at its grid point."""
+    waist = 1.0
+    dx, dy = waist / 16, waist / 12
+    k0, l0 = 140, 101
+    x0, y0 = (k0 - 128) * dx, (l0 - 96) * dy
+    i, x, y = _gauss_plane(256, 192, dx, dy, x0, y0, waist)
+    par = oracle.plane_parameters(i, x, y)
+    assert abs(par[0] - math.pi * waist ** 2 / 2) < 1e-10
+    assert abs(par[5] - math.pi * waist ** 2) < 1e-10
+    assert abs(par[1] - x0) < 1e-12 and abs(par[2] - y0) < 1e-12
+    assert abs(par[3] - 1.0) < 1e-15 and par[4] == l0 * 256 + k0
+    assert abs(par[6] - y0) < 1e-12
+
+
+def test_summary_wrapped_centre_of_mass():
+    """A beam straddling the y edge of a periodic axis: the plain centre of
+    mass lands mid-axis, the wrap-aware one on the beam."""
+    waist, h, w = 1.0, 128, 64
+    dx = dy = waist / 8
+    x = (np.arange(w) - w / 2.0) * dx
+    y = (np.arange(h) - h / 2.0) * dy
+    period = h * dy
+    yc = y[0] + 1.5 * dy              # 1.5 rows above the first row: wraps onto the last rows
+    i = np.zeros((h, w))
+    for k in (-1, 0, 1):
+        i += np.exp(-2.0 * (x[None, :] ** 2 + (y[:, None] - yc + k * period) ** 2) / waist ** 2)
+    par = oracle.plane_parameters(i, x, y)
+    assert abs(par[6] - yc) < 1e-12
+    assert abs(par[2] - yc) > period / 4
+
+
+def test_summary_uniform_patch_and_zero_plane():
+    x, y = np.arange(10) * 0.5, np.arange(7) * 2.0
+    i = np.zeros((7, 10))
+    i[2:5, 3:7] = 4.0                 # 12 pixels of intensity 4, |z| = 2
+    par = oracle.plane_parameters(i, x, y)
+    assert par[0] == 12 * 4.0 * 1.0 and par[5] == 12 * 1.0
+    assert par[1] == 2.25 and par[2] == 6.0 and par[3] == 2.0 and par[4] == 2 * 10 + 3
+    assert np.all(oracle.plane_parameters(np.zeros((7, 10)), x, y) == 0.0)
+
+
+def test_summary_fourier_plane_of_a_tone():
+    """A window 1 + cos(2 pi (u0 x / Nx + v0 y / Ny)) on the non-square 320x512
+    windows: the half plane holds the DC bin (Nx Ny)^2 and the tone bin
+    (Nx Ny / 2)^2 only, so COM = (u0, v0) bins / 5, AEFF = 25/17 cells and the
+    peak is the DC bin at row Ny/2, column 0."""
+    cfg = dh_synth.config(1)
+    p = cfg["params"]
+    g = oracle.geometry(p)
+    nx, ny = g["nx"], g["ny"]
+    u0, v0 = 37, -51
+    frame = np.zeros((p["frame_h"], p["frame_w"]))
+    for pol in range(2):
+        gp = g["pols"][pol]
+        jx, jy = np.arange(nx), np.arange(ny)
+        frame[gp["y0"]:gp["y0"] + ny, gp["x0"]:gp["x0"] + nx] = 1.0 + np.cos(
+            2 * math.pi * (u0 * jx[None, :] / nx + v0 * jy[:, None] / ny))
+    par, total, x, y = oracle.batch_summary_fourier(frame[None], p)
+    bx = p["wavelength"] / (nx * p["pixel_size"]) / oracle.DEG
+    by = p["wavelength"] / (ny * p["pixel_size"]) / oracle.DEG
+    assert abs(x[1] - x[0] - bx) < 1e-15 and abs(y[1] - y[0] - by) < 1e-15 and y[ny // 2] == 0.0
+    n2 = float(nx * ny) ** 2
+    for pol in range(2):
+        e = par[:, pol, 0]
+        assert abs(e[1] - u0 * bx / 5) < 1e-9 * bx and abs(e[2] - v0 * by / 5) < 1e-9 * by
+        assert abs(e[3] - nx * ny) < 1e-6 and e[4] == (ny // 2) * (nx // 2 + 1)
+        assert abs(e[5] - 25 / 17 * bx * by) < 1e-9 * bx * by
+        assert abs(e[0] - 1.25 * n2 * bx * by) < 1e-9 * n2 * bx * by
+        assert np.allclose(par[:, pol, 1], e)              # one frame: the batch entry is the frame
+
+
+def test_summary_field_plane_of_a_fundamental_mode():
+    """A hologram of HG00 alone (unquantised) reconstructs exp(-r^2/w^2):
+    effective area pi w^2 and centre of mass at the beam centre."""
+    cfg = dh_synth.config(0)
+    truth = cfg["truth"]
+    c = np.zeros((1, oracle.mode_count(truth["max_mg"])), np.complex128)
+    c[0, 0] = 1.0
+    frame = dh_synth.forward_hologram(truth, c)
+    r = oracle.process_frame(frame, truth)
+    par, total, x, y = oracle.batch_summary_field(r["field"][None], truth)
+    w = truth["waist"]
+    assert abs(par[5, 0, 0] - math.pi * w * w) < 1e-6 * math.pi * w * w
+    assert abs(par[1, 0, 0]) < 1e-9 * w and abs(par[2, 0, 0]) < 1e-9 * w
+    assert x[len(x) // 2] == 0.0 and abs(x[1] - x[0] - oracle.geometry(truth)["px2"]) < 1e-18
+
+
+def test_summary_batch_entry_is_the_summed_intensity():
+    """Two displaced beams: the batch entry is the analysis of the summed
+    intensity, whose centre of mass is the power-weighted mean of theirs."""
+    i1, x, y = _gauss_plane(128, 128, 0.1, 0.1, 0.7, -0.3, 1.0)
+    i2, _, _ = _gauss_plane(128, 128, 0.1, 0.1, -0.4, 0.5, 1.0)
+    inten = np.stack([np.stack([i1]), np.stack([3.0 * i2])])
+    par, total = oracle.summarise(inten, x, y)
+    assert np.allclose(total[0], i1 + 3.0 * i2, rtol=0, atol=0)
+    assert abs(par[1, 0, 2] - (0.7 * 1 - 0.4 * 3) / 4) < 1e-12
+    assert abs(par[2, 0, 2] - (-0.3 * 1 + 0.5 * 3) / 4) < 1e-12
+    assert abs(par[0, 0, 2] - (par[0, 0, 0] + par[0, 0, 1])) < 1e-12
