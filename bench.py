@@ -193,7 +193,7 @@ def time_aux(dh, torch, cfg, ft, B, stream, reps=20):
     """The kernels around the path on the benchmark batch: the int16 field
     conversion (HBM bound: 8 B read + 4 B written per field value) and the
     nine transfer-matrix metrics of the 1000 x 90 matrix (FP64 Gram,
-    rocSOLVER eigenvalues, one host sync)."""
+    Jacobi eigenvalues, one host sync)."""
     out = {}
     plan = dh.Plan(dict(cfg["params"], keep_fields=1), max_batch=B)
     plan.process(ft, B, stream)

@@ -201,7 +201,8 @@ int dh_process_batch(dh_handle h, const void* frames, int batch, void* stream);
  * x (pol x mode), row p*batch + b holds frame b's pol-p coefficients in pol
  * p's columns and zeros in the other pol's (a missing pol gives MDL = -inf).
  * IL and MDL come from the singular values of A (eigenvalues of the smaller
- * Gram matrix, FP64, rocSOLVER); the diagonal and SNR metrics from D = A
+ * Gram matrix, FP64, by the library's cyclic Jacobi kernel; a smaller side
+ * above 2048 is refused with DH_ERR_ERROR); the diagonal and SNR metrics from D = A
  * (mul_conj_trans 0) or D = A A^H (1), with entry (i, i) as the diagonal for
  * i < min(rows, cols of D); row i of A stands for the mode of column i, which
  * is what SNRMG compares. Values are +inf / -inf where a ratio's denominator
@@ -211,6 +212,19 @@ int dh_process_batch(dh_handle h, const void* frames, int batch, void* stream);
  * processed, G = 0, or the eigen-solver failed), DH_ERR_MEMORYALLOCATION.
  */
 int dh_transfer_metrics(dh_handle h, int pol_independent, int mul_conj_trans, double* out);
+
+/*
+ * The eigen step of the MDL metric on its own ("Transfer matrix analysis
+ * parameters": MDL from the singular values of the transfer matrix, which are
+ * the square roots of the eigenvalues of its Gram matrix). a_host: n x n
+ * Hermitian matrix in host memory, complex FP64 interleaved (re, im),
+ * column-major (only its Hermitian part is meaningful); w_host: n eigenvalues
+ * out, ascending. Runs the library's FP64 cyclic Jacobi kernel on the current
+ * device (one workgroup) on `stream` and waits for it; allocates and frees a
+ * device copy of the matrix. Errors: DH_ERR_NULLPOINTER, DH_ERR_INVALIDDIMENSION
+ * (n < 1 or n > 2048), DH_ERR_MEMORYALLOCATION, DH_ERR_ERROR (no convergence).
+ */
+int dh_hermitian_eigenvalues(const double* a_host, int n, double* w_host, void* stream);
 
 /*
  * Coefficients of the last processed batch, [batch][pol][mode] complex64.

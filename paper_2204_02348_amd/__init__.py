@@ -45,7 +45,7 @@ PATH_SPECTRAL = 2
 EXPORTS = ["dh_plan_check", "dh_max_window_radius", "dh_plan", "dh_process_batch", "dh_mode_coefs", "dh_get_window",
            "dh_get_fields", "dh_get_fields16", "dh_fields_to_int16", "dh_get_params", "dh_get_plan_info",
            "dh_set_stage_timing", "dh_stage_times", "dh_autoalign", "dh_get_align_report", "dh_set_align_goal",
-           "dh_set_pol_lock", "dh_transfer_metrics", "dh_set_basis", "dh_set_wavelengths", "dh_set_averaging",
+           "dh_set_pol_lock", "dh_transfer_metrics", "dh_hermitian_eigenvalues", "dh_set_basis", "dh_set_wavelengths", "dh_set_averaging",
            "dh_serve_create", "dh_serve_info",
            "dh_serve_submit", "dh_serve_progress", "dh_serve_replay", "dh_serve_stats", "dh_serve_destroy",
            "dh_last_error", "dh_destroy"]
@@ -132,6 +132,7 @@ def lib():
         L.dh_serve_destroy.argtypes = [C.c_int]
         L.dh_transfer_metrics.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double)]
         L.dh_set_align_goal.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int]
+        L.dh_hermitian_eigenvalues.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
         L.dh_set_pol_lock.argtypes = [C.c_int, C.c_uint]
         L.dh_set_basis.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p]
         L.dh_set_wavelengths.argtypes = [C.c_int, C.c_void_p, C.c_int, C.c_int, C.c_int]
@@ -260,6 +261,21 @@ def _stream(s) -> int:
     if isinstance(s, int):
         return s
     return s.cuda_stream
+
+
+def hermitian_eigenvalues(a, stream=None) -> np.ndarray:
+    """Eigenvalues (ascending) of a Hermitian matrix by the library's Jacobi
+    kernel (dh_hermitian_eigenvalues): the eigen step of the MDL metric."""
+    m = np.asfortranarray(np.asarray(a, dtype=np.complex128))
+    n = m.shape[0]
+    if m.shape != (n, n):
+        raise ValueError("a square matrix is needed")
+    w = np.empty(n, dtype=np.float64)
+    rc = lib().dh_hermitian_eigenvalues(m.ctypes.data_as(C.c_void_p), n, w.ctypes.data_as(C.c_void_p),
+                                        C.c_void_p(_stream(stream)))
+    if rc != SUCCESS:
+        raise DhError(rc, "dh_hermitian_eigenvalues")
+    return w
 
 
 def fields_to_int16(fields, n_fields: int, field_len: int, re, im, scale, stream=None):

@@ -3,8 +3,8 @@
 #include "dh.h"
 
 #include <hip/hip_runtime.h>
-#include <rocsolver/rocsolver.h>
 
+#include <algorithm>
 #include <cfloat>
 #include <chrono>
 #include <deque>
@@ -297,11 +297,9 @@ struct Plan {
   // stream the kernel runs on
   // alignment: device scratch reused across calls, and the last report
   char* amem = nullptr;
-  // transfer-matrix metrics: workspace (grown on demand) and the rocBLAS
-  // handle rocSOLVER runs on
+  // transfer-matrix metrics: workspace (grown on demand)
   char* tm_mem = nullptr;
   size_t tm_bytes = 0;
-  rocblas_handle blas = nullptr;
   unsigned lock = 0;                 // DH_ALIGN_TILT / DH_ALIGN_DEFOCUS: pol 1 takes pol 0's value
   char* q16_mem = nullptr;           // int16 fields and scales (dh_get_fields16), made on first use
   // basis transform after the HG overlap (DH_BASIS_LG / CUSTOM): c_out = T c_HG
@@ -685,15 +683,6 @@ int set_err(Plan* pl, int e) {
   return e;
 }
 
-// the plan's rocBLAS handle (made on first use), bound to stream s
-bool blas_on(Plan* pl, hipStream_t s) {
-  if (!pl->blas && rocblas_create_handle(&pl->blas) != rocblas_status_success) {
-    pl->blas = nullptr;
-    return false;
-  }
-  return rocblas_set_stream(pl->blas, s) == rocblas_status_success;
-}
-
 // IFFT mode 0: the fields of `count` output frames (first, first + stride,
 // ...) from their kept windows, with wavelength lam's tables and geometry (lam
 // < 0: the plan's): the window's bins zero-padded to the N_y x N_x grid and
@@ -752,7 +741,6 @@ void release(Plan* pl) {
   if (pl->bmem) (void)hipFree(pl->bmem);
   if (pl->lmem) (void)hipFree(pl->lmem);
   if (pl->smem) (void)hipFree(pl->smem);
-  if (pl->blas) (void)rocblas_destroy_handle(pl->blas);
   (void)hipSetDevice(dev);
   delete pl;
 }
@@ -1202,7 +1190,6 @@ int tm_compute(Plan* pl, int B, int pol_independent, int mul_conj_trans, hipStre
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o += align256(bytes); return r; };
   const size_t og = take((size_t)n * n * 16), od = extra ? take((size_t)t.rows * t.rows * 16) : 0;
-  const size_t ow = take((size_t)n * 8);
   // the results, one block for one copy to the host: eigenvalues [n], the
   // Gram's diagonal [n], row powers [rows], diagonal powers [nd], same-group
   // powers [nd], the solver's info
@@ -1223,7 +1210,6 @@ int tm_compute(Plan* pl, int B, int pol_independent, int mul_conj_trans, hipStre
   char* m = pl->tm_mem;
   double2* g = (double2*)(m + og);
   double2* gd = extra ? (double2*)(m + od) : g;
-  if (!blas_on(pl, s)) return DH_ERR_ERROR;
   // the row statistics read the Gram matrix before the eigen-solver overwrites it
   if (dh::launch_tm_gram(t, byrows, n, g, s) != hipSuccess ||
       (extra && dh::launch_tm_gram(t, 1, t.rows, gd, s) != hipSuccess) ||
@@ -1232,16 +1218,14 @@ int tm_compute(Plan* pl, int B, int pol_independent, int mul_conj_trans, hipStre
     return DH_ERR_ERROR;
   // the Gram's diagonal, read before the eigen-solver overwrites the matrix
   if (dh::launch_tm_diag(g, n, (double*)(m + ogd), s) != hipSuccess) return DH_ERR_ERROR;
-  if (eig && rocsolver_zheevd(pl->blas, rocblas_evect_none, rocblas_fill_upper, n, (rocblas_double_complex*)g, n,
-                              (double*)(m + oe), (double*)(m + ow), (rocblas_int*)(m + oi)) != rocblas_status_success)
-    return DH_ERR_ERROR;
+  if (eig && dh::launch_heig(g, n, (double*)(m + oe), (int*)(m + oi), s) != hipSuccess) return DH_ERR_ERROR;
   std::vector<double> res(nres);
   if (hipMemcpyAsync(res.data(), m + ores, nres * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return DH_ERR_ERROR;
-  rocblas_int info = 0;
+  int info = 1;                          // the eigen-solver's sweeps, -1 if it did not converge
   if (eig) std::memcpy(&info, &res[nres - 1], sizeof(info));
-  if (info != 0) return DH_ERR_ERROR;
+  if (info < 0) return DH_ERR_ERROR;
   const double* eigv = res.data();
   const double* gdiag = eigv + n;
   const double* rowp = gdiag + n;
@@ -1835,6 +1819,31 @@ extern "C" int dh_transfer_metrics(dh_handle h, int pol_independent, int mul_con
   if (!pl) return DH_ERR_INVALIDHANDLE;
   if (!out) return set_err(pl, DH_ERR_NULLPOINTER);
   return set_err(pl, tm_compute(pl, pl->last_batch, pol_independent, mul_conj_trans, pl->last_stream, out));
+}
+
+extern "C" int dh_hermitian_eigenvalues(const double* a_host, int n, double* w_host, void* stream) {
+  if (!a_host || !w_host) return DH_ERR_NULLPOINTER;
+  if (n < 1 || n > 2048) return DH_ERR_INVALIDDIMENSION;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t mb = align256((size_t)n * n * 16), wb = align256((size_t)n * 8);
+  char* mem = nullptr;
+  if (hipMalloc(&mem, mb + wb + 256) != hipSuccess) {
+    (void)hipGetLastError();
+    return DH_ERR_MEMORYALLOCATION;
+  }
+  std::vector<double> w(n);
+  int info = -1;
+  const bool ok = hipMemcpyAsync(mem, a_host, (size_t)n * n * 16, hipMemcpyHostToDevice, s) == hipSuccess &&
+                  dh::launch_heig((double2*)mem, n, (double*)(mem + mb), (int*)(mem + mb + wb), s) == hipSuccess &&
+                  hipMemcpyAsync(w.data(), mem + mb, (size_t)n * 8, hipMemcpyDeviceToHost, s) == hipSuccess &&
+                  hipMemcpyAsync(&info, mem + mb + wb, sizeof(int), hipMemcpyDeviceToHost, s) == hipSuccess &&
+                  hipStreamSynchronize(s) == hipSuccess;
+  (void)hipFree(mem);
+  if (!ok) return DH_ERR_ERROR;
+  if (info < 0) return DH_ERR_ERROR;
+  std::sort(w.begin(), w.end());
+  std::memcpy(w_host, w.data(), (size_t)n * 8);
+  return DH_SUCCESS;
 }
 
 extern "C" int dh_set_align_goal(dh_handle h, int goal, int pol_independent, int mul_conj_trans) {

@@ -7,6 +7,8 @@
 //              the squared singular values)
 //   k_tm_rows  row statistics of the matrix the diagonal metrics are taken on
 //   k_tm_diag  the Gram matrix's diagonal (IL is its trace over n)
+//   k_heig     eigenvalues of the Gram matrix (FP64 cyclic Jacobi, one
+//              workgroup): the squared singular values for MDL
 //   k_q16      fields to int16 real and imaginary parts with one scale each
 //   k_basis    HG coefficients to another basis (LG, custom): one matrix product
 //   k_m0y, k_m0x  IFFT mode 0 field export: the window zero-padded to the FFT
@@ -181,6 +183,143 @@ hipError_t launch_tm_diag(const double2* g, int n, double* out, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// k_heig: every eigenvalue of an n x n Hermitian matrix (FP64 complex,
+// column-major, overwritten) by cyclic two-sided Jacobi, in one workgroup.
+// The sweep is a round-robin tournament over the indices (padded to even m):
+// in each of its m - 1 rounds the m/2 index pairs are disjoint, so their plane
+// rotations are applied together, first to the columns (A U), then to the
+// rows (U^H A U). For a pair (p, q) with a_pq = |a_pq| e^{i phi}, U is the
+// real rotation by theta (tan 2 theta = 2|a_pq| / (a_qq - a_pp), |theta| <=
+// pi/4) after the phase e^{-i phi} on index q; it zeroes a_pq and a_qp and
+// moves the diagonal to a_pp - t|a_pq| and a_qq + t|a_pq|, t = tan theta.
+// A pair is left alone when |a_pq| <= 1e-15 sqrt(|a_pp a_qq|) (the relative
+// test that keeps small eigenvalues of a semi-definite matrix accurate) or
+// below an absolute floor tied to the trace; the matrix is converged when a
+// whole sweep rotates nothing. info = sweeps used, or -1 if kMaxSweeps did not
+// converge. Matrices up to kHeigLds rows are worked on in LDS, larger ones (up
+// to kHeigMaxN) in place in global memory.
+constexpr int kHeigLds = 96;
+constexpr int kHeigMaxN = 2048;
+constexpr int kHeigThreads = 1024;
+constexpr int kMaxSweeps = 60;
+
+__device__ __forceinline__ double2 zmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+template <bool IN_LDS>
+__global__ void __launch_bounds__(kHeigThreads) k_heig(double2* __restrict__ g, int n, double* __restrict__ w,
+                                                       int* __restrict__ info) {
+  constexpr int NP = IN_LDS ? kHeigLds / 2 : kHeigMaxN / 2;   // index pairs per round, at most
+  __shared__ double2 lds[IN_LDS ? kHeigLds * kHeigLds : 1];
+  __shared__ double s_c[NP], s_s[NP], s_app[NP], s_aqq[NP];
+  __shared__ double2 s_ph[NP];
+  __shared__ int s_p[NP], s_q[NP], s_rot[NP];
+  __shared__ int s_count;
+  __shared__ double s_red[kHeigThreads / 64];
+  const int tid = threadIdx.x;
+  double2* a = IN_LDS ? lds : g;
+  if constexpr (IN_LDS)
+    for (int e = tid; e < n * n; e += kHeigThreads) lds[e] = g[e];
+  const int m = n + (n & 1);
+  const int half = m / 2;
+  // absolute floor: entries this small next to the trace are rounding dust
+  double tr = 0.0;
+  for (int i = tid; i < n; i += kHeigThreads) tr += fabs(g[(size_t)i * (n + 1)].x);
+  for (int off = 32; off > 0; off >>= 1) tr += __shfl_xor(tr, off, 64);
+  if ((tid & 63) == 0) s_red[tid >> 6] = tr;
+  __syncthreads();
+  tr = 0.0;
+  for (int k = 0; k < kHeigThreads / 64; ++k) tr += s_red[k];
+  const double floor_abs = 1e-300 + 1e-30 * tr;
+  int sweep = 0;
+  bool done = n < 2;
+  while (!done && sweep < kMaxSweeps) {
+    if (tid == 0) s_count = 0;
+    __syncthreads();
+    for (int r = 0; r < m - 1; ++r) {
+      // rotation of each pair from the matrix before this round
+      for (int k = tid; k < half; k += kHeigThreads) {
+        int p, q;
+        if (k == 0) {
+          p = m - 1;
+          q = r;
+        } else {
+          p = (r + k) % (m - 1);
+          q = (r - k + (m - 1)) % (m - 1);
+        }
+        if (p > q) { const int t = p; p = q; q = t; }
+        s_p[k] = p;
+        s_q[k] = q;
+        int rot = 0;
+        if (q < n) {
+          const double app = a[(size_t)p * n + p].x, aqq = a[(size_t)q * n + q].x;
+          const double2 apq = a[(size_t)q * n + p];                    // row p, column q
+          const double mag = hypot(apq.x, apq.y);
+          if (mag > floor_abs && mag > 1e-15 * sqrt(fabs(app * aqq))) {
+            const double tau = (aqq - app) / (2.0 * mag);
+            const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            const double c = 1.0 / sqrt(1.0 + t * t);
+            s_c[k] = c;
+            s_s[k] = t * c;
+            s_ph[k] = make_double2(apq.x / mag, apq.y / mag);
+            s_app[k] = app - t * mag;
+            s_aqq[k] = aqq + t * mag;
+            rot = 1;
+            atomicAdd(&s_count, 1);
+          }
+        }
+        s_rot[k] = rot;
+      }
+      __syncthreads();
+      // columns: col_p <- c col_p - s e^{-i phi} col_q, col_q <- s col_p + c e^{-i phi} col_q
+      for (int e = tid; e < half * n; e += kHeigThreads) {
+        const int k = e / n, i = e - k * n;
+        if (!s_rot[k]) continue;
+        const int p = s_p[k], q = s_q[k];
+        const double c = s_c[k], sn = s_s[k];
+        const double2 ph = make_double2(s_ph[k].x, -s_ph[k].y);
+        const double2 x = a[(size_t)p * n + i], y = zmul(ph, a[(size_t)q * n + i]);
+        a[(size_t)p * n + i] = make_double2(c * x.x - sn * y.x, c * x.y - sn * y.y);
+        a[(size_t)q * n + i] = make_double2(sn * x.x + c * y.x, sn * x.y + c * y.y);
+      }
+      __syncthreads();
+      // rows: row_p <- c row_p - s e^{i phi} row_q, row_q <- s row_p + c e^{i phi} row_q;
+      // the pair's own 2 x 2 block takes its exact values
+      for (int e = tid; e < half * n; e += kHeigThreads) {
+        const int k = e / n, j = e - k * n;
+        if (!s_rot[k]) continue;
+        const int p = s_p[k], q = s_q[k];
+        if (j == p || j == q) {
+          a[(size_t)j * n + p] = j == p ? make_double2(s_app[k], 0.0) : make_double2(0.0, 0.0);
+          a[(size_t)j * n + q] = j == q ? make_double2(s_aqq[k], 0.0) : make_double2(0.0, 0.0);
+          continue;
+        }
+        const double c = s_c[k], sn = s_s[k];
+        const double2 x = a[(size_t)j * n + p], y = zmul(s_ph[k], a[(size_t)j * n + q]);
+        a[(size_t)j * n + p] = make_double2(c * x.x - sn * y.x, c * x.y - sn * y.y);
+        a[(size_t)j * n + q] = make_double2(sn * x.x + c * y.x, sn * x.y + c * y.y);
+      }
+      __syncthreads();
+    }
+    ++sweep;
+    done = s_count == 0;
+    __syncthreads();                 // every thread has read s_count
+  }
+  for (int i = tid; i < n; i += kHeigThreads) w[i] = a[(size_t)i * n + i].x;
+  if (tid == 0) *info = done ? sweep : -1;
+}
+
+hipError_t launch_heig(double2* g, int n, double* w, int* info, hipStream_t s) {
+  if (n < 1) return hipSuccess;
+  if (n > kHeigMaxN) return hipErrorInvalidValue;
+  if (n <= kHeigLds)
+    hipLaunchKernelGGL(k_heig<true>, dim3(1), dim3(kHeigThreads), 0, s, g, n, w, info);
+  else
+    hipLaunchKernelGGL(k_heig<false>, dim3(1), dim3(kHeigThreads), 0, s, g, n, w, info);
+  return hipGetLastError();
+}
 
 hipError_t launch_psum(const float2* spec, int nb, int npol, size_t plane, float* pw, hipStream_t s) {
   const size_t n = (size_t)npol * plane;

@@ -170,5 +170,8 @@ hipError_t launch_tm_rows(const TmArgs& t, const double2* g, int nrow, int ncol,
                           double* same, hipStream_t s);
 // out[i] = Re g[i][i] of an n x n complex matrix
 hipError_t launch_tm_diag(const double2* g, int n, double* out, hipStream_t s);
+// every eigenvalue of the n x n Hermitian g (column-major, overwritten) into
+// w[n] by cyclic Jacobi; info = sweeps used, -1 if it did not converge
+hipError_t launch_heig(double2* g, int n, double* w, int* info, hipStream_t s);
 
 }  // namespace dh
