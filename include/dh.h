@@ -168,16 +168,25 @@ int dh_plan(const dh_params* p, int max_batch, size_t hbm_budget, dh_handle* out
 int dh_max_window_radius(const dh_params* p, int wrap, double* radius_deg);
 
 /*
- * Process `batch` frames (device pointer, [batch][frame_h][frame_w] of the
- * plan's input_dtype) asynchronously on `stream` (a hipStream_t; NULL = the
- * default stream). The caller keeps ownership of `frames`; they must stay
- * valid and unchanged until the stream has passed this work. batch < 1 is
- * taken as 1; batch > max_batch returns DH_ERR_INVALIDDIMENSION. With
- * averaging (dh_set_averaging) `batch` counts outputs and batch * count
- * frames are read (DH_ERR_INVALIDDIMENSION above max_batch); with a
- * wavelength sweep (dh_set_wavelengths) batch must be a multiple of the
- * wavelength count (else DH_ERR_INVALIDDIMENSION).
- * Errors: DH_ERR_INVALIDHANDLE, DH_ERR_NULLPOINTER, DH_ERR_ERROR (launch).
+ * Batch processing ("Execute batch processing": digHoloProcessBatch, with the
+ * batch count of digHoloConfigSetBatchCount; the pipeline of "digHolo
+ * processing pipeline", steps 1-3). Process `batch` frames (device pointer,
+ * [batch][frame_h][frame_w] of the plan's input_dtype) asynchronously on
+ * `stream` (a hipStream_t; NULL = the default stream). The caller keeps
+ * ownership of `frames`; they must stay valid and unchanged until the stream
+ * has passed this work. batch < 1 is taken as 1. A batch larger than
+ * max_batch is processed in launch chunks like any other; its coefficient
+ * outputs (raw, normalised, basis) move to an allocation for `batch` frames,
+ * made on the first such call and grown only when a larger batch comes (the
+ * call then waits for the device); this is refused with
+ * DH_ERR_INVALIDDIMENSION while `stream` is being captured and for plans that
+ * keep windows or fields, sweep wavelengths or average (their buffers hold
+ * max_batch outputs). With averaging (dh_set_averaging) `batch` counts
+ * outputs and batch * count frames are read (DH_ERR_INVALIDDIMENSION above
+ * max_batch); with a wavelength sweep (dh_set_wavelengths) batch must be a
+ * multiple of the wavelength count (else DH_ERR_INVALIDDIMENSION).
+ * Errors: DH_ERR_INVALIDHANDLE, DH_ERR_NULLPOINTER, DH_ERR_INVALIDDIMENSION,
+ * DH_ERR_MEMORYALLOCATION (growing the outputs), DH_ERR_ERROR (launch).
  */
 int dh_process_batch(dh_handle h, const void* frames, int batch, void* stream);
 
@@ -257,6 +266,58 @@ int dh_get_window(dh_handle h, dh_c64* host_out, const dh_c64** dev_out, int* ba
  */
 int dh_get_fields(dh_handle h, dh_c64* host_out, const dh_c64** dev_out, int* batch, int* pols,
                   int* width, int* height);
+
+/*
+ * Axes of the reconstructed field grid (the x and y axis arrays that
+ * digHoloGetFields returns with the fields): x[k] = (k - F_x/2) p'_x and
+ * y[l] = (l - F_y/2) p'_y in metres from each polarisation's beam centre, F and
+ * p' the field grid of the IFFT mode (the same for both polarisations). x, y:
+ * host arrays of width / height doubles (each may be NULL); width, height
+ * receive the sizes. Host only. Errors: DH_ERR_INVALIDHANDLE.
+ */
+int dh_get_field_axes(dh_handle h, double* x, double* y, int* width, int* height);
+
+/*
+ * Batch summary ("Advanced functions", digHoloBatchGetSummary; "Analysis
+ * parameter types"): for every batch element and polarisation, and for the
+ * intensity summed over the batch (the last, "+1", entry), the DH_ANALYSIS_*
+ * parameters of one plane:
+ *   plane 0, the Fourier plane: |FFT|^2 of each polarisation's FFT window on
+ *     the real-to-complex half plane, width fft_w/2 + 1 (k_x = 0 .. N_x/2) by
+ *     height fft_h (k_y = -N_y/2 .. N_y/2 - 1, ascending); axes in degrees of
+ *     paraxial angle (bin k at k lambda/(N p) rad), the units of the tilt.
+ *     Computed from `frames` (device pointer, `batch` frames of the plan's
+ *     frame size and input type, contiguous) on `stream`.
+ *   plane 1, the reconstructed field plane: |E|^2 of the last batch's fields
+ *     (needs keep_fields; `frames` and `batch` are ignored), axes as
+ *     dh_get_field_axes; runs on the stream of the last dh_process_batch.
+ * With I the intensity and dA = |dx dy| the cell of the plane's axes:
+ * TOTALPOWER = sum I dA; COMX, COMY = centres of mass on the axes; MAXABS =
+ * sqrt(max I); MAXABSIDX = row-major index y W + x of the first maximum,
+ * stored as int32 bits in its float slot (as the paper warns); AEFF = (sum I
+ * dA)^2 / (sum I^2 dA) (a Gaussian beam I ~ exp(-2 r^2/w^2) gives pi w^2);
+ * COMYWRAP = the circular mean of y over the period H dy of the y axis, in
+ * the axis' range. Sums in FP64; an all-zero plane gives zeros.
+ * Outputs (host memory, each may be NULL): params [DH_ANALYSIS_COUNT][pols]
+ * [total_count] float, total_count = batch + 1; x_axis [width], y_axis
+ * [height] double; total_intensity [pols][height][width] float, the summed
+ * intensity. With params and total_intensity both NULL only the sizes and
+ * axes are returned. Allocates and frees device scratch per call and waits
+ * for the stream. Errors: DH_ERR_INVALIDHANDLE, DH_ERR_INVALIDARGUMENT (plane),
+ * DH_ERR_NULLPOINTER (plane 0 without frames), DH_ERR_ERROR (plane 1 without
+ * kept fields or a processed batch), DH_ERR_MEMORYALLOCATION.
+ */
+#define DH_ANALYSIS_TOTALPOWER 0
+#define DH_ANALYSIS_COMX 1
+#define DH_ANALYSIS_COMY 2
+#define DH_ANALYSIS_MAXABS 3
+#define DH_ANALYSIS_MAXABSIDX 4
+#define DH_ANALYSIS_AEFF 5
+#define DH_ANALYSIS_COMYWRAP 6
+#define DH_ANALYSIS_COUNT 7
+int dh_batch_summary(dh_handle h, int plane, const void* frames, int batch, void* stream, float* params,
+                     double* x_axis, double* y_axis, float* total_intensity, int* total_count, int* pols,
+                     int* width, int* height);
 
 /*
  * The fields of the last batch in the paper's 16-bit form (digHoloGetFields16,

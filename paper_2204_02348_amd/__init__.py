@@ -45,7 +45,8 @@ PATH_SPECTRAL = 2
 EXPORTS = ["dh_plan_check", "dh_max_window_radius", "dh_plan", "dh_process_batch", "dh_mode_coefs", "dh_get_window",
            "dh_get_fields", "dh_get_fields16", "dh_fields_to_int16", "dh_get_params", "dh_get_plan_info",
            "dh_set_stage_timing", "dh_stage_times", "dh_autoalign", "dh_get_align_report", "dh_set_align_goal",
-           "dh_set_pol_lock", "dh_transfer_metrics", "dh_hermitian_eigenvalues", "dh_set_basis", "dh_set_wavelengths", "dh_set_averaging",
+           "dh_set_pol_lock", "dh_transfer_metrics", "dh_hermitian_eigenvalues", "dh_batch_summary",
+           "dh_get_field_axes", "dh_set_basis", "dh_set_wavelengths", "dh_set_averaging",
            "dh_serve_create", "dh_serve_info",
            "dh_serve_submit", "dh_serve_progress", "dh_serve_replay", "dh_serve_stats", "dh_serve_destroy",
            "dh_last_error", "dh_destroy"]
@@ -133,6 +134,10 @@ def lib():
         L.dh_transfer_metrics.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double)]
         L.dh_set_align_goal.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int]
         L.dh_hermitian_eigenvalues.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
+        L.dh_batch_summary.argtypes = [C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
+                                       C.c_void_p, C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                       C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.dh_get_field_axes.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.dh_set_pol_lock.argtypes = [C.c_int, C.c_uint]
         L.dh_set_basis.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p]
         L.dh_set_wavelengths.argtypes = [C.c_int, C.c_void_p, C.c_int, C.c_int, C.c_int]
@@ -418,6 +423,45 @@ class Plan:
         if rc != SUCCESS:
             raise DhError(rc, "dh_get_fields16")
         return re, im, sc
+
+    def field_axes(self):
+        """(x, y): the field grid's axes in metres from the beam centre (dh_get_field_axes)."""
+        w, h = C.c_int(), C.c_int()
+        rc = lib().dh_get_field_axes(self.handle, None, None, C.byref(w), C.byref(h))
+        if rc != SUCCESS:
+            raise DhError(rc, "dh_get_field_axes")
+        x, y = np.empty(w.value), np.empty(h.value)
+        rc = lib().dh_get_field_axes(self.handle, x.ctypes.data_as(C.c_void_p), y.ctypes.data_as(C.c_void_p),
+                                     None, None)
+        if rc != SUCCESS:
+            raise DhError(rc, "dh_get_field_axes")
+        return x, y
+
+    def batch_summary(self, plane: int, frames=None, batch: int = 0, stream=None):
+        """dh_batch_summary: (params [7][pol][batch+1] float64 with MAXABSIDX as
+        integers, summed intensity [pol][h][w], x axis, y axis). plane 0: the
+        Fourier plane of `batch` frames; plane 1: the last batch's fields."""
+        tc, npol, w, h = C.c_int(), C.c_int(), C.c_int(), C.c_int()
+        ptr = 0
+        if plane == 0:
+            ptr = _frames_ptr(frames, max(int(batch), 1), self._frame_elems, self._p.input_dtype, self.device,
+                              "dh_batch_summary")
+        L = lib()
+        rc = L.dh_batch_summary(self.handle, int(plane), C.c_void_p(ptr), int(batch), C.c_void_p(_stream(stream)),
+                                None, None, None, None, C.byref(tc), C.byref(npol), C.byref(w), C.byref(h))
+        if rc != SUCCESS:
+            raise DhError(rc, "dh_batch_summary")
+        par = np.empty((7, npol.value, tc.value), dtype=np.float32)
+        tot = np.empty((npol.value, h.value, w.value), dtype=np.float32)
+        x, y = np.empty(w.value), np.empty(h.value)
+        rc = L.dh_batch_summary(self.handle, int(plane), C.c_void_p(ptr), int(batch), C.c_void_p(_stream(stream)),
+                                par.ctypes.data_as(C.c_void_p), x.ctypes.data_as(C.c_void_p),
+                                y.ctypes.data_as(C.c_void_p), tot.ctypes.data_as(C.c_void_p), None, None, None, None)
+        if rc != SUCCESS:
+            raise DhError(rc, "dh_batch_summary")
+        out = par.astype(np.float64)
+        out[4] = par[4].view(np.int32)
+        return out, tot, x, y
 
     def set_stage_timing(self, on: bool):
         rc = lib().dh_set_stage_timing(self.handle, int(on))

@@ -308,8 +308,13 @@ struct Plan {
   char* bmem = nullptr;
   float2* btt = nullptr;             // T transposed, [bin][bout]
   int* bgrp = nullptr;               // [bout] group id of each output mode
-  float2* bc = nullptr;              // [max_batch][P][bout] raw, then normalised
+  float2* bc = nullptr;              // [max(max_batch, ocap)][P][bout] raw, then normalised
   float2* bcn = nullptr;
+  // outputs of batches larger than max_batch: the raw and normalised
+  // coefficients (and the basis coefficients) for ocap frames, made on the
+  // first such batch and grown when a larger one comes
+  char* omem = nullptr;
+  int ocap = 0;
   // wavelength sweep (dh_set_wavelengths) and frame averaging (dh_set_averaging)
   int nlam = 0;                      // 0: every frame at the plan's wavelength
   int in_order = 0, out_order = 0;   // DH_WL_FAST / DH_WL_SLOW
@@ -671,8 +676,9 @@ void fill_kargs(Plan* pl, int w) {
   a.f2 = (float2*)(m + L.f2[w]);
   a.partial = (float2*)(m + L.partial[w]);
   a.nblk = g.spec ? dh::spectral_blocks(g.ny, g.bx, g.gp) : field_blocks(g);
-  a.coefs = (float2*)(m + L.coefs);
-  a.coefs_norm = (float2*)(m + L.coefs_norm);
+  a.coefs = pl->omem ? (float2*)pl->omem : (float2*)(m + L.coefs);
+  a.coefs_norm = pl->omem ? (float2*)(pl->omem + align256((size_t)pl->ocap * p->pol_count * g.nmodes * 8))
+                          : (float2*)(m + L.coefs_norm);
   a.window = p->keep_window || exports(g, p) ? (float2*)(m + L.window) : nullptr;
   // the kernels write mode-1 fields; mode-0 fields come from the export
   a.fields = p->keep_fields && g.mode == 1 ? (float2*)(m + L.fields) : nullptr;
@@ -739,6 +745,7 @@ void release(Plan* pl) {
   if (pl->tm_mem) (void)hipFree(pl->tm_mem);
   if (pl->q16_mem) (void)hipFree(pl->q16_mem);
   if (pl->bmem) (void)hipFree(pl->bmem);
+  if (pl->omem) (void)hipFree(pl->omem);
   if (pl->lmem) (void)hipFree(pl->lmem);
   if (pl->smem) (void)hipFree(pl->smem);
   (void)hipSetDevice(dev);
@@ -978,13 +985,51 @@ int process_sweep(Plan* pl, const void* frames, int batch, hipStream_t s) {
 
 }  // namespace
 
+namespace {
+// Coefficient outputs for a batch larger than the plan's max_batch (the
+// paper sizes its buffers by the batch count it is given): the raw and
+// normalised coefficients, and the basis coefficients when a basis is set,
+// move to an allocation for `batch` frames, made once and grown only when a
+// larger batch comes. Not while the stream is being captured (no allocation
+// there), nor for plans that keep windows or fields, sweep or average (their
+// buffers stay at max_batch).
+int grow_outputs(Plan* pl, int batch, hipStream_t s) {
+  if (batch <= pl->max_batch || batch <= pl->ocap) return DH_SUCCESS;
+  const dh_params& p = pl->params;
+  if (p.keep_window || p.keep_fields || sweeping(pl)) return DH_ERR_INVALIDDIMENSION;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return DH_ERR_INVALIDDIMENSION;
+  const size_t P = p.pol_count, nm = pl->g.nmodes;
+  const size_t cb = align256((size_t)batch * P * nm * 8), bb = align256((size_t)batch * P * pl->bout * 8);
+  // work in flight may still write the old outputs
+  if (hipDeviceSynchronize() != hipSuccess) return DH_ERR_ERROR;
+  char* mem = nullptr;
+  if (hipMalloc(&mem, 2 * cb + 2 * bb + 256) != hipSuccess) {
+    (void)hipGetLastError();
+    return DH_ERR_MEMORYALLOCATION;
+  }
+  if (pl->omem) (void)hipFree(pl->omem);
+  pl->omem = mem;
+  pl->ocap = batch;
+  for (int w = 0; w < pl->nws; ++w) fill_kargs(pl, w);
+  if (pl->basis != DH_BASIS_HG) {
+    pl->bc = (float2*)(mem + 2 * cb);
+    pl->bcn = (float2*)(mem + 2 * cb + bb);
+  }
+  return DH_SUCCESS;
+}
+}  // namespace
+
 int dh_process_batch(dh_handle h, const void* frames, int batch, void* stream) {
   Plan* pl = get(h);
   if (!pl) return DH_ERR_INVALIDHANDLE;
   if (!frames) return set_err(pl, DH_ERR_NULLPOINTER);
   if (batch < 1) batch = 1;
-  if (batch > pl->max_batch) return set_err(pl, DH_ERR_INVALIDDIMENSION);
   hipStream_t s = (hipStream_t)stream;
+  if (batch > pl->max_batch) {
+    const int e = grow_outputs(pl, batch, s);
+    if (e != DH_SUCCESS) return set_err(pl, e);
+  }
   const Geom& g = pl->g;
   const int P = pl->params.pol_count;
   if (sweeping(pl)) {
@@ -1066,6 +1111,137 @@ int dh_get_window(dh_handle h, dh_c64* host_out, const dh_c64** dev_out, int* ba
 int dh_get_fields(dh_handle h, dh_c64* host_out, const dh_c64** dev_out, int* batch, int* pols, int* width,
                   int* height) {
   return get_plane(h, false, host_out, dev_out, batch, pols, width, height);
+}
+
+int dh_get_field_axes(dh_handle h, double* x, double* y, int* width, int* height) {
+  Plan* pl = get(h);
+  if (!pl) return DH_ERR_INVALIDHANDLE;
+  const Geom& g = pl->g;
+  if (width) *width = g.fx;
+  if (height) *height = g.fy;
+  for (int k = 0; x && k < g.fx; ++k) x[k] = (k - 0.5 * g.fx) * g.fpx;
+  for (int l = 0; y && l < g.fy; ++l) y[l] = (l - 0.5 * g.fy) * g.fpy;
+  return set_err(pl, DH_SUCCESS);
+}
+
+// Batch summary ("Analysis parameter types", digHoloBatchGetSummary). The
+// eight sums of every plane (k_summ) are turned into the seven parameters on
+// the host in FP64: with dA = |dx dy| the axis cell, total power S dA, the
+// centres of mass x0 + dx sum(k I)/S and y0 + dy sum(l I)/S, sqrt(max I) and
+// its index l W + k, the effective area (S dA)^2 / (sum I^2 dA), and the
+// wrap-aware y centre y0 + H dy arg(sum I e^{2 pi i l/H}) / (2 pi), the angle
+// in [0, 2 pi). An all-zero plane gives zeros.
+extern "C" int dh_batch_summary(dh_handle h, int plane, const void* frames, int batch, void* stream, float* params,
+                                double* x_axis, double* y_axis, float* total_intensity, int* total_count, int* pols,
+                                int* width, int* height) {
+  Plan* pl = get(h);
+  if (!pl) return DH_ERR_INVALIDHANDLE;
+  if (plane != 0 && plane != 1) return set_err(pl, DH_ERR_INVALIDARGUMENT);
+  const Geom& g = pl->g;
+  const dh_params& p = pl->params;
+  const int P = p.pol_count;
+  const int W = plane == 0 ? g.nx / 2 + 1 : g.fx, H = plane == 0 ? g.ny : g.fy;
+  if (plane == 1) batch = pl->last_batch;
+  else if (batch < 1) batch = 1;
+  const int total = batch + 1;
+  if (total_count) *total_count = total;
+  if (pols) *pols = P;
+  if (width) *width = W;
+  if (height) *height = H;
+  // axes: degrees of paraxial angle (Fourier plane) or metres from the beam centre (field plane)
+  double dx, dy, x0, y0;
+  if (plane == 0) {
+    dx = p.wavelength / (g.nx * p.pixel_size) / kDeg;
+    dy = p.wavelength / (g.ny * p.pixel_size) / kDeg;
+    x0 = 0.0;
+    y0 = -(g.ny / 2) * dy;
+  } else {
+    dx = g.fpx;
+    dy = g.fpy;
+    x0 = -0.5 * g.fx * dx;
+    y0 = -0.5 * g.fy * dy;
+  }
+  for (int k = 0; x_axis && k < W; ++k) x_axis[k] = x0 + k * dx;
+  for (int l = 0; y_axis && l < H; ++l) y_axis[l] = y0 + l * dy;
+  if (!params && !total_intensity) return set_err(pl, DH_SUCCESS);
+  const float2* fld = field_buffer(pl);
+  if (plane == 1 && (!fld || pl->last_batch < 1)) return set_err(pl, DH_ERR_ERROR);
+  if (plane == 0 && !frames) return set_err(pl, DH_ERR_NULLPOINTER);
+  hipStream_t s = plane == 1 ? pl->last_stream : (hipStream_t)stream;
+  // scratch: the sums, the summed intensity, and (Fourier plane) the half
+  // plane of a group of frames: row pass over columns 0..Nx/2, column FFT
+  const int bxe = g.nx / 2 + 1;
+  const size_t per = (size_t)P * g.ny * bxe * 8;
+  int grp = plane == 0 ? (int)std::max<size_t>(1, std::min<size_t>(batch, (256ull << 20) / per)) : 0;
+  const size_t sb = align256((size_t)(batch + 1) * P * 8 * 8), mb = align256((size_t)P * W * H * 8);
+  const size_t tb = align256((size_t)grp * per);
+  char* mem = nullptr;
+  if (hipMalloc(&mem, sb + mb + 2 * tb) != hipSuccess) {
+    (void)hipGetLastError();
+    return set_err(pl, DH_ERR_MEMORYALLOCATION);
+  }
+  double* sums = (double*)mem;
+  double* map = (double*)(mem + sb);
+  bool ok = true;
+  if (plane == 1) {
+    ok = dh::launch_summ(fld, nullptr, (long long)W * H, W, H, 1, W, batch * P, sums, s) == hipSuccess &&
+         dh::launch_isum(fld, (long long)W * H, W, H, 1, W, batch, P, 0, map, s) == hipSuccess;
+  } else {
+    dh::KArgs ke = pl->ka[0];
+    ke.bx = bxe;
+    ke.t1 = (float2*)(mem + sb + mb);
+    ke.fptr = nullptr;
+    for (int q = 0; q < P; ++q) {
+      ke.pol[q].k0 = 0;
+      ke.pol[q].ky0 = -(g.ny / 2);
+    }
+    float2* spec = (float2*)(mem + sb + mb + tb);
+    const int u16 = p.input_dtype == DH_INPUT_U16;
+    for (int b0 = 0; ok && b0 < batch; b0 += grp) {
+      const int nb = std::min(grp, batch - b0);
+      ok = dh::launch_row(ke, frames, u16, b0, nb, s) == hipSuccess &&
+           dh::launch_spec(ke, spec, g.ny, nb, s) == hipSuccess &&
+           dh::launch_summ(spec, nullptr, (long long)bxe * g.ny, W, H, g.ny, 1, nb * P, sums + (size_t)b0 * P * 8,
+                           s) == hipSuccess &&
+           dh::launch_isum(spec, (long long)bxe * g.ny, W, H, g.ny, 1, nb, P, b0 > 0, map, s) == hipSuccess;
+    }
+  }
+  ok = ok && dh::launch_summ(nullptr, map, (long long)W * H, W, H, 1, W, P, sums + (size_t)batch * P * 8, s) ==
+                 hipSuccess;
+  std::vector<double> hs((size_t)(batch + 1) * P * 8), hm(total_intensity ? (size_t)P * W * H : 0);
+  ok = ok && hipMemcpyAsync(hs.data(), sums, hs.size() * 8, hipMemcpyDeviceToHost, s) == hipSuccess &&
+       (!total_intensity || hipMemcpyAsync(hm.data(), map, hm.size() * 8, hipMemcpyDeviceToHost, s) == hipSuccess);
+  const bool synced = hipStreamSynchronize(s) == hipSuccess;
+  (void)hipFree(mem);
+  if (!ok || !synced) return set_err(pl, DH_ERR_ERROR);
+  const double da = std::fabs(dx * dy);
+  for (int e = 0; e <= batch && params; ++e)
+    for (int q = 0; q < P; ++q) {
+      const double* t = &hs[((size_t)e * P + q) * 8];
+      double v[DH_ANALYSIS_COUNT] = {0, 0, 0, 0, 0, 0, 0};
+      int idx = 0;
+      if (t[0] > 0.0) {
+        v[DH_ANALYSIS_TOTALPOWER] = t[0] * da;
+        v[DH_ANALYSIS_COMX] = x0 + dx * t[1] / t[0];
+        v[DH_ANALYSIS_COMY] = y0 + dy * t[2] / t[0];
+        v[DH_ANALYSIS_MAXABS] = std::sqrt(t[6]);
+        idx = (int)t[7];
+        v[DH_ANALYSIS_AEFF] = (t[0] * da) * (t[0] * da) / (t[3] * da);
+        double ang = std::atan2(t[5], t[4]);
+        if (ang < 0.0) ang += 2.0 * M_PI;
+        if (ang >= 2.0 * M_PI) ang = 0.0;
+        v[DH_ANALYSIS_COMYWRAP] = y0 + H * dy * ang / (2.0 * M_PI);
+      }
+      for (int k = 0; k < DH_ANALYSIS_COUNT; ++k) {
+        float* o = params + ((size_t)k * P + q) * total + e;
+        if (k == DH_ANALYSIS_MAXABSIDX)
+          std::memcpy(o, &idx, sizeof(int));
+        else
+          *o = (float)v[k];
+      }
+    }
+  for (size_t i = 0; i < hm.size(); ++i) total_intensity[i] = (float)hm[i];
+  return set_err(pl, DH_SUCCESS);
 }
 
 int dh_get_params(dh_handle h, dh_params* out) {
@@ -1932,8 +2108,9 @@ extern "C" int dh_set_basis(dh_handle h, int type, int modes_out, int modes_in, 
   ++pl->version;
   if (type == DH_BASIS_HG) return set_err(pl, DH_SUCCESS);
   const size_t ott = 0, ogr = align256((size_t)mused * mout * 8);
-  const size_t oc = ogr + align256((size_t)mout * 4), ocn = oc + align256((size_t)pl->max_batch * P * mout * 8);
-  const size_t total = ocn + align256((size_t)pl->max_batch * P * mout * 8);
+  const size_t cap = (size_t)std::max(pl->max_batch, pl->ocap);
+  const size_t oc = ogr + align256((size_t)mout * 4), ocn = oc + align256(cap * P * mout * 8);
+  const size_t total = ocn + align256(cap * P * mout * 8);
   if (hipMalloc(&pl->bmem, total) != hipSuccess) {
     (void)hipGetLastError();
     pl->bmem = nullptr;

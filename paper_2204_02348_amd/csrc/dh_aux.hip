@@ -7,6 +7,8 @@
 //              the squared singular values)
 //   k_tm_rows  row statistics of the matrix the diagonal metrics are taken on
 //   k_tm_diag  the Gram matrix's diagonal (IL is its trace over n)
+//   k_summ, k_isum  batch summary: the sums of each plane's parameters, and
+//              the intensity summed over the batch
 //   k_heig     eigenvalues of the Gram matrix (FP64 cyclic Jacobi, one
 //              workgroup): the squared singular values for MDL
 //   k_q16      fields to int16 real and imaginary parts with one scale each
@@ -318,6 +320,128 @@ hipError_t launch_heig(double2* g, int n, double* w, int* info, hipStream_t s) {
     hipLaunchKernelGGL(k_heig<true>, dim3(1), dim3(kHeigThreads), 0, s, g, n, w, info);
   else
     hipLaunchKernelGGL(k_heig<false>, dim3(1), dim3(kHeigThreads), 0, s, g, n, w, info);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batch summary ("Analysis parameter types"). A plane is H x W values, value
+// (l, k) (row l of the y axis, column k of the x axis) at base + l sy + k sx;
+// the intensity is |z|^2 of a complex64 value, taken in FP64 from its FP32
+// parts, or an FP64 intensity map. Sums run over the plane in memory order.
+struct SumPlane {
+  const float2* z;         // complex planes (or null)
+  const double* map;       // FP64 intensity planes (or null)
+  long long pstride;       // elements between consecutive planes
+  int w, h, sx, sy;        // sx == 1: rows contiguous; else columns contiguous (sy == 1)
+};
+
+__device__ __forceinline__ double plane_at(const SumPlane& P, long long base, int l, int k) {
+  const long long a = base + (long long)l * P.sy + (long long)k * P.sx;
+  if (P.map) return P.map[a];
+  const float2 v = P.z[a];
+  return (double)v.x * v.x + (double)v.y * v.y;
+}
+
+// k_summ: grid (n planes), 256 threads. out[e][8] = sum I, sum k I, sum l I,
+// sum I^2, sum cos(2 pi l / H) I, sum sin(2 pi l / H) I, max I, its index
+// l W + k (the lowest index on ties). Fixed order: per thread a fixed stride,
+// then a fixed tree.
+__global__ void __launch_bounds__(256) k_summ(SumPlane P, double* __restrict__ out) {
+  __shared__ double red[6][256];
+  __shared__ double rmax[256];
+  __shared__ int ridx[256];
+  const int tid = threadIdx.x;
+  const long long base = (long long)blockIdx.x * P.pstride;
+  const int n = P.w * P.h;
+  double s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double best = -1.0;
+  int bidx = 0x7fffffff;
+  for (int e = tid; e < n; e += 256) {
+    int l, k;
+    if (P.sx == 1) {
+      l = e / P.w;
+      k = e - l * P.w;
+    } else {
+      k = e / P.h;
+      l = e - k * P.h;
+    }
+    const double v = plane_at(P, base, l, k);
+    double sn, cs;
+    sincospi(2.0 * l / P.h, &sn, &cs);
+    s[0] += v;
+    s[1] += k * v;
+    s[2] += l * v;
+    s[3] += v * v;
+    s[4] += cs * v;
+    s[5] += sn * v;
+    const int idx = l * P.w + k;
+    if (v > best || (v == best && idx < bidx)) {
+      best = v;
+      bidx = idx;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 6; ++q) red[q][tid] = s[q];
+  rmax[tid] = best;
+  ridx[tid] = bidx;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) {
+#pragma unroll
+      for (int q = 0; q < 6; ++q) red[q][tid] += red[q][tid + w];
+      const double o = rmax[tid + w];
+      const int oi = ridx[tid + w];
+      if (o > rmax[tid] || (o == rmax[tid] && oi < ridx[tid])) {
+        rmax[tid] = o;
+        ridx[tid] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    double* o = out + (size_t)blockIdx.x * 8;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) o[q] = red[q][0];
+    o[6] = rmax[0] > 0.0 ? rmax[0] : 0.0;
+    o[7] = rmax[0] > 0.0 ? (double)ridx[0] : 0.0;
+  }
+}
+
+// k_isum: map[p][l][k] (+)= sum over the nb planes of pol p (plane b npol + p)
+// of their intensity, frames in order (row-major map, one thread per pixel)
+__global__ void k_isum(SumPlane P, int nb, int npol, int accumulate, double* __restrict__ map) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long n = (long long)P.w * P.h;
+  if (e >= n * npol) return;
+  const int p = (int)(e / n);
+  const int r = (int)(e - (long long)p * n);
+  int l, k;
+  if (P.sx == 1) {
+    l = r / P.w;
+    k = r - l * P.w;
+  } else {
+    k = r / P.h;
+    l = r - k * P.h;
+  }
+  double acc = accumulate ? map[(size_t)p * n + (size_t)l * P.w + k] : 0.0;
+  for (int b = 0; b < nb; ++b) acc += plane_at(P, (long long)(b * npol + p) * P.pstride, l, k);
+  map[(size_t)p * n + (size_t)l * P.w + k] = acc;
+}
+
+hipError_t launch_summ(const float2* z, const double* map, long long pstride, int w, int h, int sx, int sy, int n,
+                       double* out, hipStream_t s) {
+  if (n < 1) return hipSuccess;
+  SumPlane P{z, map, pstride, w, h, sx, sy};
+  hipLaunchKernelGGL(k_summ, dim3(n), dim3(256), 0, s, P, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_isum(const float2* z, long long pstride, int w, int h, int sx, int sy, int nb, int npol,
+                       int accumulate, double* map, hipStream_t s) {
+  const long long n = (long long)w * h * npol;
+  if (n < 1 || nb < 1) return hipSuccess;
+  SumPlane P{z, nullptr, pstride, w, h, sx, sy};
+  hipLaunchKernelGGL(k_isum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, P, nb, npol, accumulate, map);
   return hipGetLastError();
 }
 

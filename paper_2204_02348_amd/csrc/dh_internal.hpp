@@ -170,6 +170,14 @@ hipError_t launch_tm_rows(const TmArgs& t, const double2* g, int nrow, int ncol,
                           double* same, hipStream_t s);
 // out[i] = Re g[i][i] of an n x n complex matrix
 hipError_t launch_tm_diag(const double2* g, int n, double* out, hipStream_t s);
+// batch summary: the eight sums of each of n planes (see k_summ) from complex
+// planes z or FP64 intensity maps, value (l, k) of plane e at e pstride + l sy
+// + k sx; and map[p][l][k] (+)= the intensity summed over nb frames (plane
+// b npol + p of z)
+hipError_t launch_summ(const float2* z, const double* map, long long pstride, int w, int h, int sx, int sy, int n,
+                       double* out, hipStream_t s);
+hipError_t launch_isum(const float2* z, long long pstride, int w, int h, int sx, int sy, int nb, int npol,
+                       int accumulate, double* map, hipStream_t s);
 // every eigenvalue of the n x n Hermitian g (column-major, overwritten) into
 // w[n] by cyclic Jacobi; info = sweeps used, -1 if it did not converge
 hipError_t launch_heig(double2* g, int n, double* w, int* info, hipStream_t s);

@@ -55,3 +55,43 @@ def test_tilt_beyond_the_spectrum_aliases(path, shift):
     e, ew = _rel(got, ref["coefs"][0]), _rel(win, ref["window"][0])
     _say(f"coefficient rel-L2 {e:.2e}, window {ew:.2e}")
     assert e <= TOL and ew <= TOL
+
+
+def test_batch_larger_than_max_batch():
+    """batch = 2.5 x max_batch: processed in chunks into grown coefficient
+    outputs, every sampled frame matching the oracle; a later smaller batch
+    reuses them; the LG basis follows; plans keeping windows refuse."""
+    torch = _torch()
+    import os
+    import paper_2204_02348_amd as dh
+    cfg = dh_synth.config(1)
+    f, _ = dh_synth.make_frames(cfg, n_frames=10)
+    ft = torch.from_numpy(f).cuda()
+    _say("640x512, max_batch 4, batch 10, chunks of 3")
+    os.environ["DH_CHUNK_FRAMES"] = "3"
+    try:
+        plan = dh.Plan(cfg["params"], max_batch=4)
+    finally:
+        os.environ.pop("DH_CHUNK_FRAMES", None)
+    plan.process(ft, 10, None)
+    got, gotn = plan.coefs(False), plan.coefs(True)
+    assert got.shape == (10, 2, 45)
+    for i in (0, 3, 4, 7, 9):
+        ref = oracle.process_frame(f[i].astype(np.float64), cfg["params"])
+        for p in range(2):
+            assert _rel(got[i, p], ref["coefs"][p]) <= TOL
+            assert _rel(gotn[i, p], ref["coefs_norm"][p]) <= TOL
+    plan.process(ft[4:], 6, None)
+    again = plan.coefs(False)
+    assert again.shape == (6, 2, 45) and np.array_equal(again, got[4:])
+    plan.set_basis(dh.BASIS_LG)
+    plan.process(ft, 10, None)
+    lg10 = plan.coefs(False)
+    plan.process(ft[7:], 1, None)
+    assert np.array_equal(plan.coefs(False)[0], lg10[7])
+    plan.destroy()
+    keep = dh.Plan(dict(cfg["params"], keep_window=1), max_batch=4)
+    with pytest.raises(dh.DhError) as e:
+        keep.process(ft, 10, None)
+    assert e.value.code == dh.ERR_INVALIDDIMENSION
+    keep.destroy()
