@@ -1126,11 +1126,12 @@ int dh_get_field_axes(dh_handle h, double* x, double* y, int* width, int* height
 
 // Batch summary ("Analysis parameter types", digHoloBatchGetSummary). The
 // eight sums of every plane (k_summ) are turned into the seven parameters on
-// the host in FP64: with dA = |dx dy| the axis cell, total power S dA, the
-// centres of mass x0 + dx sum(k I)/S and y0 + dy sum(l I)/S, sqrt(max I) and
-// its index l W + k, the effective area (S dA)^2 / (sum I^2 dA), and the
-// wrap-aware y centre y0 + H dy arg(sum I e^{2 pi i l/H}) / (2 pi), the angle
-// in [0, 2 pi). An all-zero plane gives zeros.
+// the host in FP64: with axis values (k + cx) dx and (l + cy) dy, dA = |dx dy|
+// the axis cell, total power S dA, the centres of mass (cx + sum(k I)/S) dx
+// and (cy + sum(l I)/S) dy, sqrt(max I) and its index l W + k, the effective
+// area (S dA)^2 / (sum I^2 dA), and the wrap-aware y centre
+// (cy + H arg(sum I e^{2 pi i l/H}) / (2 pi)) dy, the angle in [0, 2 pi). An
+// all-zero plane gives zeros.
 extern "C" int dh_batch_summary(dh_handle h, int plane, const void* frames, int batch, void* stream, float* params,
                                 double* x_axis, double* y_axis, float* total_intensity, int* total_count, int* pols,
                                 int* width, int* height) {
@@ -1148,21 +1149,22 @@ extern "C" int dh_batch_summary(dh_handle h, int plane, const void* frames, int 
   if (pols) *pols = P;
   if (width) *width = W;
   if (height) *height = H;
-  // axes: degrees of paraxial angle (Fourier plane) or metres from the beam centre (field plane)
-  double dx, dy, x0, y0;
+  // axes: degrees of paraxial angle (Fourier plane) or metres from the beam
+  // centre (field plane, the values dh_get_field_axes gives): value (k + cx) dx
+  double dx, dy, cx, cy;
   if (plane == 0) {
     dx = p.wavelength / (g.nx * p.pixel_size) / kDeg;
     dy = p.wavelength / (g.ny * p.pixel_size) / kDeg;
-    x0 = 0.0;
-    y0 = -(g.ny / 2) * dy;
+    cx = 0.0;
+    cy = -(double)(g.ny / 2);
   } else {
     dx = g.fpx;
     dy = g.fpy;
-    x0 = -0.5 * g.fx * dx;
-    y0 = -0.5 * g.fy * dy;
+    cx = -0.5 * g.fx;
+    cy = -0.5 * g.fy;
   }
-  for (int k = 0; x_axis && k < W; ++k) x_axis[k] = x0 + k * dx;
-  for (int l = 0; y_axis && l < H; ++l) y_axis[l] = y0 + l * dy;
+  for (int k = 0; x_axis && k < W; ++k) x_axis[k] = (k + cx) * dx;
+  for (int l = 0; y_axis && l < H; ++l) y_axis[l] = (l + cy) * dy;
   if (!params && !total_intensity) return set_err(pl, DH_SUCCESS);
   const float2* fld = field_buffer(pl);
   if (plane == 1 && (!fld || pl->last_batch < 1)) return set_err(pl, DH_ERR_ERROR);
@@ -1222,15 +1224,15 @@ extern "C" int dh_batch_summary(dh_handle h, int plane, const void* frames, int 
       int idx = 0;
       if (t[0] > 0.0) {
         v[DH_ANALYSIS_TOTALPOWER] = t[0] * da;
-        v[DH_ANALYSIS_COMX] = x0 + dx * t[1] / t[0];
-        v[DH_ANALYSIS_COMY] = y0 + dy * t[2] / t[0];
+        v[DH_ANALYSIS_COMX] = (cx + t[1] / t[0]) * dx;
+        v[DH_ANALYSIS_COMY] = (cy + t[2] / t[0]) * dy;
         v[DH_ANALYSIS_MAXABS] = std::sqrt(t[6]);
         idx = (int)t[7];
         v[DH_ANALYSIS_AEFF] = (t[0] * da) * (t[0] * da) / (t[3] * da);
         double ang = std::atan2(t[5], t[4]);
         if (ang < 0.0) ang += 2.0 * M_PI;
         if (ang >= 2.0 * M_PI) ang = 0.0;
-        v[DH_ANALYSIS_COMYWRAP] = y0 + H * dy * ang / (2.0 * M_PI);
+        v[DH_ANALYSIS_COMYWRAP] = (cy + H * ang / (2.0 * M_PI)) * dy;
       }
       for (int k = 0; k < DH_ANALYSIS_COUNT; ++k) {
         float* o = params + ((size_t)k * P + q) * total + e;

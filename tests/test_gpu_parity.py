@@ -1032,8 +1032,9 @@ def test_sweep_rejections():
     assert e.value.code == dh.ERR_INVALIDDIMENSION
     plan.set_wavelengths([])
     plan.set_averaging(3)
+    ft6 = torch.cat([ft, ft[:2]])                       # the frames the call reads
     with pytest.raises(dh.DhError) as e:
-        plan.process(ft, 2, None)                       # 6 frames > max_batch 4
+        plan.process(ft6, 2, None)                      # 6 staged frames > max_batch 4
     assert e.value.code == dh.ERR_INVALIDDIMENSION
     with pytest.raises(dh.DhError):
         plan.autoalign(ft, 1)
