@@ -236,6 +236,23 @@ int dh_transfer_metrics(dh_handle h, int pol_independent, int mul_conj_trans, do
 int dh_hermitian_eigenvalues(const double* a_host, int n, double* w_host, void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the eigen step of
+ * dh_hermitian_eigenvalues with no allocation of any kind. a_dev: n x n
+ * Hermitian matrix in device memory (layout as above), read only; w_dev: n
+ * eigenvalues out in device memory, ascending. The working copy of the matrix
+ * lives in a fixed device array of the library (DH_NOALLOC_EIG_MAX_N^2 complex
+ * FP64 values, 1 MiB, held on every GPU the library runs on until the process
+ * ends). Runs on `stream` on the current device and waits for it. Calls that
+ * overlap on one GPU share that array and race: issue them from one thread
+ * and stream per GPU. Errors: DH_ERR_NULLPOINTER, DH_ERR_INVALIDDIMENSION
+ * (n < 1 or n > DH_NOALLOC_EIG_MAX_N), DH_ERR_ERROR (no convergence, or a HIP
+ * call failed).
+ */
+#define DH_NOALLOC_EIG_MAX_N 256
+int dh_hermitian_eigenvalues_noalloc(const double* a_dev, int n, double* w_dev, void* stream);
+
+/*
  * Coefficients of the last processed batch, [batch][pol][mode] complex64.
  * host_out non-NULL: waits for the stream of the last dh_process_batch and
  * copies batch*pols*modes values. dev_out non-NULL: receives the library's

@@ -45,7 +45,8 @@ PATH_SPECTRAL = 2
 EXPORTS = ["dh_plan_check", "dh_max_window_radius", "dh_plan", "dh_process_batch", "dh_mode_coefs", "dh_get_window",
            "dh_get_fields", "dh_get_fields16", "dh_fields_to_int16", "dh_get_params", "dh_get_plan_info",
            "dh_set_stage_timing", "dh_stage_times", "dh_autoalign", "dh_get_align_report", "dh_set_align_goal",
-           "dh_set_pol_lock", "dh_transfer_metrics", "dh_hermitian_eigenvalues", "dh_batch_summary",
+           "dh_set_pol_lock", "dh_transfer_metrics", "dh_hermitian_eigenvalues",
+           "dh_hermitian_eigenvalues_noalloc", "dh_batch_summary",
            "dh_get_field_axes", "dh_set_basis", "dh_set_wavelengths", "dh_set_averaging",
            "dh_serve_create", "dh_serve_info",
            "dh_serve_submit", "dh_serve_progress", "dh_serve_replay", "dh_serve_stats", "dh_serve_destroy",
@@ -134,6 +135,7 @@ def lib():
         L.dh_transfer_metrics.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double)]
         L.dh_set_align_goal.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int]
         L.dh_hermitian_eigenvalues.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
+        L.dh_hermitian_eigenvalues_noalloc.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
         L.dh_batch_summary.argtypes = [C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
                                        C.c_void_p, C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                        C.POINTER(C.c_int), C.POINTER(C.c_int)]
@@ -281,6 +283,19 @@ def hermitian_eigenvalues(a, stream=None) -> np.ndarray:
     if rc != SUCCESS:
         raise DhError(rc, "dh_hermitian_eigenvalues")
     return w
+
+
+NOALLOC_EIG_MAX_N = 256          # DH_NOALLOC_EIG_MAX_N
+
+
+def hermitian_eigenvalues_noalloc(a_dev, n: int, w_dev, stream=None) -> None:
+    """dh_hermitian_eigenvalues_noalloc on device buffers (torch tensors or raw
+    addresses): a_dev holds the n x n matrix (complex FP64, column-major), w_dev
+    receives the n eigenvalues, ascending. No device memory is allocated."""
+    rc = lib().dh_hermitian_eigenvalues_noalloc(C.c_void_p(_ptr(a_dev)), int(n), C.c_void_p(_ptr(w_dev)),
+                                                C.c_void_p(_stream(stream)))
+    if rc != SUCCESS:
+        raise DhError(rc, "dh_hermitian_eigenvalues_noalloc")
 
 
 def fields_to_int16(fields, n_fields: int, field_len: int, re, im, scale, stream=None):

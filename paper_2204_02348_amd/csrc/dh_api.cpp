@@ -2019,9 +2019,61 @@ extern "C" int dh_hermitian_eigenvalues(const double* a_host, int n, double* w_h
   (void)hipFree(mem);
   if (!ok) return DH_ERR_ERROR;
   if (info < 0) return DH_ERR_ERROR;
-  std::sort(w.begin(), w.end());
-  std::memcpy(w_host, w.data(), (size_t)n * 8);
+  std::memcpy(w_host, w.data(), (size_t)n * 8);     // ascending, as the kernel writes them
   return DH_SUCCESS;
+}
+
+// ---------------------------------------------------------------------------
+// dh_hermitian_eigenvalues_noalloc: the same eigen step with the working copy
+// of the matrix in a fixed device array instead of an allocation. Every GPU
+// the library runs on holds its own copy of `scratch` (the matrix, up to
+// DH_NOALLOC_EIG_MAX_N rows, then the solver's info word) until the process
+// ends; host code reaches it only through the device address that
+// hipGetSymbolAddress returns on that device, looked up once per device on
+// the first call there. Calls on one GPU share the array: calls that overlap
+// on one GPU race. The matrix copy and the info word are rewritten by every
+// call, so nothing has to start at zero.
+namespace {
+constexpr size_t kNoAllocMat = (size_t)DH_NOALLOC_EIG_MAX_N * DH_NOALLOC_EIG_MAX_N;
+__device__ __align__(256) double2 scratch[kNoAllocMat + 16];
+
+std::mutex g_scratch_mu;
+std::map<int, double2*> g_scratch_ptr;     // device ordinal -> device address of scratch
+
+// scratch's device address on the current device (looked up on first use)
+double2* scratch_on_device() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) return it->second;
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  g_scratch_ptr[dev] = (double2*)ptr;
+  return (double2*)ptr;
+}
+}  // namespace
+
+extern "C" int dh_hermitian_eigenvalues_noalloc(const double* a_dev, int n, double* w_dev, void* stream) {
+  if (!a_dev || !w_dev) return DH_ERR_NULLPOINTER;
+  if (n < 1 || n > DH_NOALLOC_EIG_MAX_N) return DH_ERR_INVALIDDIMENSION;
+  double2* sp = scratch_on_device();
+  if (!sp) return DH_ERR_ERROR;
+  hipStream_t s = (hipStream_t)stream;
+  int* info_dev = (int*)(sp + kNoAllocMat);
+  int info = -1;
+  const bool ok = hipMemcpyAsync(sp, a_dev, (size_t)n * n * 16, hipMemcpyDeviceToDevice, s) == hipSuccess &&
+                  dh::launch_heig(sp, n, w_dev, info_dev, s) == hipSuccess &&
+                  hipMemcpyAsync(&info, info_dev, sizeof(int), hipMemcpyDeviceToHost, s) == hipSuccess &&
+                  hipStreamSynchronize(s) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    return DH_ERR_ERROR;
+  }
+  return info < 0 ? DH_ERR_ERROR : DH_SUCCESS;
 }
 
 extern "C" int dh_set_align_goal(dh_handle h, int goal, int pol_independent, int mul_conj_trans) {

@@ -199,8 +199,9 @@ hipError_t launch_tm_diag(const double2* g, int n, double* out, hipStream_t s) {
 // test that keeps small eigenvalues of a semi-definite matrix accurate) or
 // below an absolute floor tied to the trace; the matrix is converged when a
 // whole sweep rotates nothing. info = sweeps used, or -1 if kMaxSweeps did not
-// converge. Matrices up to kHeigLds rows are worked on in LDS, larger ones (up
-// to kHeigMaxN) in place in global memory.
+// converge. The eigenvalues go to w in ascending order. Matrices up to
+// kHeigLds rows are worked on in LDS, larger ones (up to kHeigMaxN) in place
+// in global memory.
 constexpr int kHeigLds = 96;
 constexpr int kHeigMaxN = 2048;
 constexpr int kHeigThreads = 1024;
@@ -309,7 +310,20 @@ __global__ void __launch_bounds__(kHeigThreads) k_heig(double2* __restrict__ g, 
     done = s_count == 0;
     __syncthreads();                 // every thread has read s_count
   }
-  for (int i = tid; i < n; i += kHeigThreads) w[i] = a[(size_t)i * n + i].x;
+  // the eigenvalues in ascending order: each goes to its rank in a strict
+  // total order (value, then index; NaN after every number), so the ranks
+  // are a permutation of 0..n-1
+  for (int i = tid; i < n; i += kHeigThreads) {
+    const double v = a[(size_t)i * n + i].x;
+    const bool vn = v != v;
+    int r = 0;
+    for (int j = 0; j < n; ++j) {
+      const double u = a[(size_t)j * n + j].x;
+      const bool un = u != u;
+      r += (un || vn) ? (un && vn ? j < i : !un) : (u < v || (u == v && j < i));
+    }
+    w[r] = v;
+  }
   if (tid == 0) *info = done ? sweep : -1;
 }
 

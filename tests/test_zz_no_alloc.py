@@ -1,0 +1,68 @@
+"""The allocation-free eigen step (dh_hermitian_eigenvalues_noalloc) through
+the C ABI, against dh_hermitian_eigenvalues on the same matrices: two calls
+in a row on one GPU, the second smaller, each bit-identical to the allocating
+entry point and within 1e-12 of the planted spectrum."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _planted(n, seed):
+    rng = np.random.default_rng(seed)
+    z = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    q, r = np.linalg.qr(z)
+    q = q * (np.diag(r) / np.abs(np.diag(r)))
+    lam = np.logspace(0, -6, n)
+    rng.shuffle(lam)
+    a = (q * lam) @ q.conj().T
+    return 0.5 * (a + a.conj().T), np.sort(lam)
+
+
+def test_noalloc_eigenvalues_match_allocating_entry_point():
+    torch = _torch()
+    import paper_2204_02348_amd as dh
+    stream = torch.cuda.Stream()
+    # global-memory form (n > 96), then the LDS form with a smaller matrix:
+    # the second call reuses the same device array
+    for n, seed in [(200, 7), (40, 8)]:
+        a, lam = _planted(n, seed)
+        _say(f"no-alloc Jacobi eigenvalues n={n}")
+        ref = dh.hermitian_eigenvalues(a)
+        a_dev = torch.from_numpy(np.asfortranarray(a).ravel(order="F").view(np.float64).copy()).cuda()
+        keep = a_dev.clone()
+        w_dev = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+        dh.hermitian_eigenvalues_noalloc(a_dev, n, w_dev, stream)
+        got = w_dev.cpu().numpy()
+        assert torch.equal(a_dev, keep)                  # the input is not modified
+        assert np.array_equal(got, ref), np.abs(got - ref).max()
+        assert np.abs(got - lam).max() <= 1e-12 * lam.max()
+        assert np.all(np.diff(got) >= 0)
+
+
+def test_noalloc_eigenvalues_rejects():
+    torch = _torch()
+    import paper_2204_02348_amd as dh
+    n = dh.NOALLOC_EIG_MAX_N + 1
+    a_dev = torch.zeros(2 * n * n, dtype=torch.float64, device="cuda")
+    w_dev = torch.zeros(n, dtype=torch.float64, device="cuda")
+    with pytest.raises(dh.DhError) as e:
+        dh.hermitian_eigenvalues_noalloc(a_dev, n, w_dev)
+    assert e.value.code == dh.ERR_INVALIDDIMENSION
+    with pytest.raises(dh.DhError) as e:
+        dh.hermitian_eigenvalues_noalloc(None, 4, w_dev)
+    assert e.value.code == dh.ERR_NULLPOINTER
