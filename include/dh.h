@@ -90,19 +90,21 @@ typedef struct dh_params {
   double tilt_deg[2][2];      /* [pol][x,y] reference tilt, degrees ("Alignment") */
   double defocus[2];          /* [pol] reference defocus, dioptre ("Alignment") */
   double waist;               /* HG waist (1/e^2 intensity radius), m, shared by both pols */
-  int max_mg;                 /* G: modes HG(m,n) with m+n < G; 0 = no decomposition */
+  int max_mg;                 /* G: modes HG(m,n) with m+n < G; 0 = no decomposition; at most
+                                 100 (the paper's largest LG basis, "Basis types"). Above 32 the
+                                 spectral path only (FP32, no mode-1 fields, no AutoAlign) */
   int input_dtype;            /* DH_INPUT_F32 or DH_INPUT_U16 */
   int precision;              /* DH_PREC_* */
   int ifft_mode;              /* IFFT resolution mode ("Window sizes", IFFTResolutionMode):
                                  1: the field on the Fourier-window grid (W points, pitch N p / W);
                                  0: the field on the FFT grid (N points, the camera pitch). Mode 0
-                                 runs the spectral path (needs FP32 and G >= 1): the coefficients
-                                 take the overlap over the FFT grid, and fields (keep_fields) are
-                                 the kept window zero-padded to the FFT grid and inverse
-                                 transformed at full size */
+                                 runs the spectral path (needs FP32): the coefficients take the
+                                 overlap over the FFT grid, and fields (keep_fields) are the kept
+                                 window zero-padded to the FFT grid and inverse transformed at
+                                 full size; with G = 0 only the fields are made */
   int keep_window;            /* nonzero: store each frame's Fourier window (dh_get_window) */
   int keep_fields;            /* nonzero: store each frame's field (dh_get_fields) */
-  int path;                   /* DH_PATH_*; SPECTRAL with keep_fields (mode 1), a split precision
+  int path;                   /* DH_PATH_*; SPECTRAL in mode 1 with keep_fields, a split precision
                                  or G = 0 is DH_ERR_INVALIDARGUMENT, as is FIELD in mode 0 */
 } dh_params;
 
@@ -134,7 +136,8 @@ typedef struct dh_plan_info {
  *                             the library has no kernel for;
  *   DH_ERR_INVALIDPOLARISATION pol_count not 1 or 2;
  *   DH_ERR_INVALIDARGUMENT    pixel/wavelength/radius/waist not > 0, max_mg outside
- *                             0..32, unknown dtype/precision/ifft_mode/path, a Fourier
+ *                             0..100 (or above 32 where the plan would take the field
+ *                             path), unknown dtype/precision/ifft_mode/path, a Fourier
  *                             window wider than the spectrum, or DH_PATH_SPECTRAL
  *                             where it does not apply (see DH_PATH_*).
  * max_batch < 1 is taken as 1 (the paper clamps batchCount the same way).
@@ -428,6 +431,8 @@ int dh_stage_times(dh_handle h, double* ms, int* launches);
  * trial. Each trial re-runs the window gather, the IFFTs and the overlap from
  * a spectrum kept on the device, computed again only when a centre moves the
  * window by whole pixels.
+ * The trials run the field path's overlap, so plans with G > 32 return
+ * DH_ERR_INVALIDARGUMENT.
  * The returned value is the goal in dB; -FLT_MAX on failure, with the reason
  * in dh_last_error (DH_ERR_INVALIDHANDLE, NULLPOINTER, INVALIDDIMENSION,
  * INVALIDARGUMENT, MEMORYALLOCATION, ERROR). Synchronises the device.

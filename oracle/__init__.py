@@ -13,7 +13,9 @@ from .holo_oracle import (  # noqa: F401
 from .transfer_metrics import METRICS, transfer_matrix, column_keys, transfer_metrics  # noqa: F401,E402
 from .align_snap import field_moments, batch_moments, snap_centre_waist, snap_defocus_magnitude  # noqa: F401,E402
 from .plane_snap import SNAP_FRAMES, plane_power, snap_tilt_plane  # noqa: F401,E402
-from .basis import lg_modes, lg_function, hg_to_lg, custom_transform, apply_basis  # noqa: F401,E402
+from .basis import (  # noqa: F401,E402
+    lg_modes, lg_function, hg_to_lg, lg_blocks, apply_lg_blocks, custom_transform, apply_basis,
+)
 from .sweep_avg import (  # noqa: F401,E402
     SEQUENTIAL, INTERLACED, SEQUENTIAL_SWEEP, FAST, SLOW, frame_index_map, at_wavelength, average_windows,
     process_sweep,

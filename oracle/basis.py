@@ -21,7 +21,9 @@ The overlap is evaluated by Gauss-Hermite quadrature: both functions are a
 polynomial times exp(-(x^2 + y^2) / w^2), so with x = w s / sqrt2 the
 integrand is a polynomial times exp(-s^2 - t^2), which a rule of G + 4
 nodes per axis integrates exactly (up to rounding). The Laguerre polynomials
-come from scipy, the Gauss-Hermite rule from numpy.
+come from scipy, the Gauss-Hermite rule from numpy. For large G (up to the
+100 groups the paper names for LG) the transform is taken one mode group at
+a time (lg_blocks): the full matrix is pinned block diagonal at small G.
 """
 from __future__ import annotations
 
@@ -51,20 +53,56 @@ def lg_function(p: int, l: int, x: np.ndarray, y: np.ndarray, waist: float) -> n
     return c * rad * np.exp(1j * l * phi)
 
 
-def hg_to_lg(group_count: int) -> np.ndarray:
-    """T (M x M, complex): c_LG = T c_HG, T[k][j] = <LG_k | HG_j>. It does not
-    depend on the waist (both bases scale with it); w = 1 is used."""
+def _overlaps(lg_pl, hg_mn, nodes: int) -> np.ndarray:
+    """<LG_k | HG_j> for the LG modes lg_pl [(p, l)] (rows) and the HG modes
+    hg_mn [(m, n)] (columns), by Gauss-Hermite quadrature with `nodes` nodes
+    per axis, at w = 1 (the transform does not depend on the waist: both
+    bases scale with it)."""
     w = 1.0
-    s, wt = np.polynomial.hermite.hermgauss(group_count + 4)
+    s, wt = np.polynomial.hermite.hermgauss(nodes)
     x = w * s / math.sqrt(2.0)                    # nodes along each axis
-    u = hermite_gauss_1d(group_count, x, w)       # [n][node]
+    u = hermite_gauss_1d(max(max(m, n) for m, n in hg_mn) + 1, x, w)     # [n][node]
     xx, yy = np.meshgrid(x, x, indexing="xy")     # [y node][x node]
     # integral f exp(-s^2 - t^2) ds dt ~ sum wt_a wt_b f; f = product * exp(s^2 + t^2)
     ww = np.outer(wt, wt) * np.exp(np.add.outer(s * s, s * s)) * (w * w / 2.0)
-    hg = [np.outer(u[n], u[m]) for m, n in mode_list(group_count)]          # [y][x]: u_n(y) u_m(x)
-    lg = [lg_function(p, l, xx, yy, w) for p, l in lg_modes(group_count)]
-    t = np.array([[np.sum(ww * np.conj(a) * b) for b in hg] for a in lg])
-    return t
+    hg = np.array([np.outer(u[n], u[m]).ravel() for m, n in hg_mn])      # [y][x]: u_n(y) u_m(x)
+    lg = np.array([lg_function(p, l, xx, yy, w).ravel() for p, l in lg_pl])
+    return np.conj(lg) @ (ww.ravel() * hg).T
+
+
+def hg_to_lg(group_count: int) -> np.ndarray:
+    """T (M x M, complex): c_LG = T c_HG, T[k][j] = <LG_k | HG_j>, every LG
+    mode against every HG mode (the definition; practical for G up to ~20).
+    A rule of G + 4 nodes integrates every product of two modes of groups
+    below G exactly (a polynomial of degree < 2G times the Gaussian)."""
+    return _overlaps(lg_modes(group_count), mode_list(group_count), group_count + 4)
+
+
+def lg_blocks(group_count: int) -> list:
+    """The transform for large G, one block per mode group: block N is the
+    (N+1) x (N+1) matrix <LG_k | HG_j> over the LG and HG modes of group N,
+    in basis order, with the same quadrature rule as hg_to_lg. An LG mode of
+    group N = 2p + |l| has no overlap with HG modes of other groups (both are
+    a polynomial of total degree N times the same Gaussian, and the HG modes
+    of a group span exactly the degree-N part), so T is block diagonal."""
+    lg, hg = lg_modes(group_count), mode_list(group_count)
+    out, start = [], 0
+    for n in range(group_count):
+        out.append(_overlaps(lg[start:start + n + 1], hg[start:start + n + 1], group_count + 4))
+        start += n + 1
+    return out
+
+
+def apply_lg_blocks(coefs: np.ndarray, blocks: list) -> np.ndarray:
+    """coefs [..., pol, M] HG -> LG [..., pol, M], each group by its block."""
+    c = np.asarray(coefs, dtype=np.complex128)
+    out = np.zeros_like(c)
+    start = 0
+    for b in blocks:
+        k = b.shape[0]
+        out[..., start:start + k] = np.einsum("km,...m->...k", b, c[..., start:start + k])
+        start += k
+    return out
 
 
 def custom_transform(matrix: np.ndarray, modes: int) -> np.ndarray:

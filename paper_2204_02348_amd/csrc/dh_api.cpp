@@ -127,7 +127,7 @@ int derive(const dh_params* p, Geom* g) {
   const int nx = (p->fft_w / 16) * 16, ny = (p->fft_h / 16) * 16;
   if (nx <= 0 || ny <= 0) return DH_ERR_INVALIDDIMENSION;
   if (!(p->pixel_size > 0) || !(p->wavelength > 0) || !(p->window_radius_deg > 0)) return DH_ERR_INVALIDARGUMENT;
-  if (p->max_mg < 0 || p->max_mg > 32) return DH_ERR_INVALIDARGUMENT;
+  if (p->max_mg < 0 || p->max_mg > dh::kMaxGroups) return DH_ERR_INVALIDARGUMENT;
   if (p->max_mg > 0 && !(p->waist > 0)) return DH_ERR_INVALIDARGUMENT;
   if (p->input_dtype != DH_INPUT_F32 && p->input_dtype != DH_INPUT_U16) return DH_ERR_INVALIDARGUMENT;
   if (p->precision != DH_PREC_FP32 && p->precision != DH_PREC_SPLIT_BF16 && p->precision != DH_PREC_SPLIT_FP16)
@@ -157,7 +157,9 @@ int derive(const dh_params* p, Geom* g) {
   g->fpx = nx * pix / g->fx;
   g->fpy = ny * pix / g->fy;
   g->G = p->max_mg;
-  g->gp = g->G <= 16 ? 16 : 32;
+  // mode columns of the tables: one or two 16-column tiles, beyond that a
+  // multiple of 32 (the spectral contraction's chunks of two tiles)
+  g->gp = g->G <= 16 ? 16 : (g->G + 31) / 32 * 32;
   g->nmodes = g->G * (g->G + 1) / 2;
   // every window position fits a box of floor(2r)+1 bins per axis, so the
   // workspaces do not change when the tilt does (alignment)
@@ -172,8 +174,9 @@ int derive(const dh_params* p, Geom* g) {
   g->byp = (g->by + 15) / 16 * 16;
   if (g->mode == 0) {
     // IFFT mode 0: the coefficients come from spectral tables built on the FFT
-    // grid, the fields (on request) from the kept window by full-size inverse FFTs
-    if (p->path == DH_PATH_FIELD || p->precision != DH_PREC_FP32 || g->G == 0) return DH_ERR_INVALIDARGUMENT;
+    // grid, the fields (on request) from the kept window by full-size inverse
+    // FFTs; with G = 0 only the window and the fields are made
+    if (p->path == DH_PATH_FIELD || p->precision != DH_PREC_FP32) return DH_ERR_INVALIDARGUMENT;
     if (!dh::spectral_supported(ny, g->wy, g->gp)) return DH_ERR_INVALIDDIMENSION;
     g->spec = true;
     return DH_SUCCESS;
@@ -182,6 +185,8 @@ int derive(const dh_params* p, Geom* g) {
                         dh::spectral_supported(ny, g->wy, g->gp);
   if (p->path == DH_PATH_SPECTRAL && !can_spec) return DH_ERR_INVALIDARGUMENT;
   g->spec = p->path == DH_PATH_SPECTRAL || (p->path == DH_PATH_AUTO && can_spec);
+  // the field path's overlap takes up to two mode tiles (G <= 32)
+  if (g->gp > dh::kMaxGpField && !g->spec) return DH_ERR_INVALIDARGUMENT;
   return DH_SUCCESS;
 }
 
@@ -306,7 +311,8 @@ struct Plan {
   int basis = DH_BASIS_HG;
   int bout = 0, bin = 0, bngrp = 0;  // output modes, HG modes used, group ids
   char* bmem = nullptr;
-  float2* btt = nullptr;             // T transposed, [bin][bout]
+  float2* btt = nullptr;             // T entries (see bt_entry)
+  int4* brng = nullptr;              // [bout] per output mode: first HG mode, count, entry offset, entry stride
   int* bgrp = nullptr;               // [bout] group id of each output mode
   float2* bc = nullptr;              // [max(max_batch, ocap)][P][bout] raw, then normalised
   float2* bcn = nullptr;
@@ -1042,7 +1048,7 @@ int dh_process_batch(dh_handle h, const void* frames, int batch, void* stream) {
     if (run_segments(pl, frames, {{0, batch, -1, false}}, s) != DH_SUCCESS) return set_err(pl, DH_ERR_ERROR);
   }
   if (pl->basis != DH_BASIS_HG &&
-      dh::launch_basis(pl->ka[0].coefs, pl->ka[0].coefs_norm, g.nmodes, pl->bin, pl->btt, pl->bout, pl->bc, pl->bcn,
+      dh::launch_basis(pl->ka[0].coefs, pl->ka[0].coefs_norm, g.nmodes, pl->bin, pl->brng, pl->btt, pl->bout, pl->bc, pl->bcn,
                        batch * P, s) != hipSuccess)
     return set_err(pl, DH_ERR_ERROR);
   if (exports(g, &pl->params)) {
@@ -1346,7 +1352,7 @@ int tm_compute(Plan* pl, int B, int pol_independent, int mul_conj_trans, hipStre
   t.B = B; t.P = P; t.M = M;
   if (pl->basis != DH_BASIS_HG) {
     // the matrix of the current basis: its coefficients made from the HG ones
-    if (dh::launch_basis(pl->ka[0].coefs, pl->ka[0].coefs_norm, M, pl->bin, pl->btt, pl->bout, pl->bc, pl->bcn,
+    if (dh::launch_basis(pl->ka[0].coefs, pl->ka[0].coefs_norm, M, pl->bin, pl->brng, pl->btt, pl->bout, pl->bc, pl->bcn,
                          B * P, s) != hipSuccess)
       return DH_ERR_ERROR;
     t.c = pl->bc;
@@ -1638,7 +1644,8 @@ extern "C" float dh_autoalign(dh_handle h, const void* frames, int batch, int mo
   if (batch > pl->max_batch) return (set_err(pl, DH_ERR_INVALIDDIMENSION), -FLT_MAX);
   if (sweeping(pl) || mode < DH_ALIGN_FULL || mode > DH_ALIGN_ESTIMATE ||
       (what & ~(DH_ALIGN_TILT | DH_ALIGN_DEFOCUS | DH_ALIGN_WAIST | DH_ALIGN_CENTRE)) ||
-      (mode != DH_ALIGN_ESTIMATE && pl->g.G == 0) || !(tol >= 0.f))
+      (mode != DH_ALIGN_ESTIMATE && pl->g.G == 0) || !(tol >= 0.f) ||
+      pl->g.gp > dh::kMaxGpField)      // the trials run the field path's overlap (G <= 32)
     return (set_err(pl, DH_ERR_INVALIDARGUMENT), -FLT_MAX);
   hipStream_t s = (hipStream_t)stream;
   if (hipDeviceSynchronize() != hipSuccess) return (set_err(pl, DH_ERR_ERROR), -FLT_MAX);
@@ -2087,37 +2094,38 @@ extern "C" int dh_set_align_goal(dh_handle h, int goal, int pol_independent, int
 }
 
 namespace {
-// HG -> LG coefficient transform, row-major [M][M]: LG mode (p, l) of group
-// N = 2p + |l| (rows in group order, l = N, N-2, ..., -N) against HG(N-k, k)
-// (columns in the plan's mode order, m = N - k descending):
+// HG -> LG coefficient transform. LG mode (p, l) of group N = 2p + |l| is a
+// combination of the HG modes of the same group only ("Basis types": both
+// bases hold the same modes per group), so T is block diagonal: block N is
+// (N+1) x (N+1), rows in LG order (l = N, N-2, ..., -N), columns HG(N-k, k)
+// in the plan's mode order (m = N - k descending):
 //   T = (-1)^p i^k b(n, m, k),  n = p + max(l, 0), m = p + max(-l, 0),
 //   b = sqrt((N-k)! k! / (2^N n! m!)) [t^k] (1 - t)^n (1 + t)^m,
 // the mode-converter expansion of LG in HG, conjugated (T = <LG|HG>). The
-// polynomial coefficient is summed exactly in 64-bit integers.
-std::vector<cd> lg_transform(int G) {
-  const int M = G * (G + 1) / 2;
-  std::vector<cd> t((size_t)M * M, cd(0, 0));
-  auto binom = [](int n, int k) -> long long {
+// polynomial coefficient is an alternating sum of binomial products up to
+// C(N, k) (< 2^97 for N < 100), summed exactly in 128-bit integers.
+// Returns the blocks one after another, block N row-major.
+std::vector<cd> lg_blocks(int G) {
+  std::vector<cd> t;
+  auto binom = [](int n, int k) -> __int128 {
     if (k < 0 || k > n) return 0;
-    long long r = 1;
+    __int128 r = 1;
     for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
     return r;
   };
-  int base = 0;
+  static const cd ik[4] = {cd(1, 0), cd(0, 1), cd(-1, 0), cd(0, -1)};
   for (int N = 0; N < G; ++N) {
     for (int r = 0; r <= N; ++r) {
       const int l = N - 2 * r, p = (N - std::abs(l)) / 2;
       const int n = p + std::max(l, 0), m = p + std::max(-l, 0);
       for (int k = 0; k <= N; ++k) {
-        long long poly = 0;
+        __int128 poly = 0;
         for (int a = 0; a <= k; ++a) poly += (a & 1 ? -1 : 1) * binom(n, a) * binom(m, k - a);
         const double b = std::exp(0.5 * (std::lgamma(N - k + 1.0) + std::lgamma(k + 1.0) - N * std::log(2.0) -
                                          std::lgamma(n + 1.0) - std::lgamma(m + 1.0))) * (double)poly;
-        static const cd ik[4] = {cd(1, 0), cd(0, 1), cd(-1, 0), cd(0, -1)};
-        t[(size_t)(base + r) * M + base + k] = ((p & 1) ? -1.0 : 1.0) * ik[k & 3] * b;
+        t.push_back(((p & 1) ? -1.0 : 1.0) * ik[k & 3] * b);
       }
     }
-    base += N + 1;
   }
   return t;
 }
@@ -2129,39 +2137,60 @@ extern "C" int dh_set_basis(dh_handle h, int type, int modes_out, int modes_in, 
   if (type < DH_BASIS_HG || type > DH_BASIS_CUSTOM) return set_err(pl, DH_ERR_INVALIDARGUMENT);
   const int M = pl->g.nmodes, G = pl->g.G, P = pl->params.pol_count;
   int mout = 0, mused = 0, ngrp = 0;
-  std::vector<cd> t;                 // row-major [mout][mused]
+  // the transform as entries and, per output mode k, the range of HG modes it
+  // takes: out[k] = sum_{i < cnt} e[off + i stride] c[first + i]
+  std::vector<float2> tt;
+  std::vector<int4> rng;
   std::vector<int> grp;
   if (type == DH_BASIS_LG) {
     if (M == 0) return set_err(pl, DH_ERR_INVALIDDIMENSION);
     mout = mused = M;
     ngrp = G;
-    t = lg_transform(G);
-    for (int N = 0; N < G; ++N)
-      for (int r = 0; r <= N; ++r) grp.push_back(N);
+    const std::vector<cd> t = lg_blocks(G);
+    tt.resize(t.size());
+    size_t off = 0;
+    int base = 0;
+    for (int N = 0; N < G; ++N) {
+      // block N stored transposed, [HG k][LG r], so the threads of one group read consecutive entries
+      for (int r = 0; r <= N; ++r) {
+        for (int k = 0; k <= N; ++k) {
+          const cd v = t[off + (size_t)r * (N + 1) + k];
+          tt[off + (size_t)k * (N + 1) + r] = make_float2((float)v.real(), (float)v.imag());
+        }
+        rng.push_back(make_int4(base, N + 1, (int)(off + r), N + 1));
+        grp.push_back(N);
+      }
+      off += (size_t)(N + 1) * (N + 1);
+      base += N + 1;
+    }
   } else if (type == DH_BASIS_CUSTOM) {
     if (M == 0 || modes_out < 1 || modes_in < 1 || modes_out > 65536) return set_err(pl, DH_ERR_INVALIDDIMENSION);
     if (!transform) return set_err(pl, DH_ERR_NULLPOINTER);
     mout = modes_out;
     mused = std::min(modes_in, M);
+    if ((size_t)mout * mused > (size_t)INT32_MAX) return set_err(pl, DH_ERR_INVALIDDIMENSION);
     ngrp = mout;                     // no group structure: every output mode its own
-    t.resize((size_t)mout * mused);
-    for (int k = 0; k < mout; ++k)
+    // dense, stored transposed [j][k] (consecutive output modes side by side)
+    tt.resize((size_t)mout * mused);
+    for (int k = 0; k < mout; ++k) {
       for (int j = 0; j < mused; ++j) {
         const dh_c64& v = transform[(size_t)k * modes_in + j];
-        t[(size_t)k * mused + j] = cd(v.re, v.im);
+        tt[(size_t)j * mout + k] = make_float2((float)v.re, (float)v.im);
       }
-    for (int k = 0; k < mout; ++k) grp.push_back(k);
+      rng.push_back(make_int4(0, mused, k, mout));
+      grp.push_back(k);
+    }
   }
   // work in flight may still read the old tables
   if (hipDeviceSynchronize() != hipSuccess) return set_err(pl, DH_ERR_ERROR);
   if (pl->bmem) (void)hipFree(pl->bmem);
   pl->bmem = nullptr;
-  pl->btt = nullptr; pl->bgrp = nullptr; pl->bc = pl->bcn = nullptr;
+  pl->btt = nullptr; pl->brng = nullptr; pl->bgrp = nullptr; pl->bc = pl->bcn = nullptr;
   pl->basis = DH_BASIS_HG;
   pl->bout = pl->bin = pl->bngrp = 0;
   ++pl->version;
   if (type == DH_BASIS_HG) return set_err(pl, DH_SUCCESS);
-  const size_t ott = 0, ogr = align256((size_t)mused * mout * 8);
+  const size_t ott = 0, orn = align256(tt.size() * 8), ogr = orn + align256((size_t)mout * 16);
   const size_t cap = (size_t)std::max(pl->max_batch, pl->ocap);
   const size_t oc = ogr + align256((size_t)mout * 4), ocn = oc + align256(cap * P * mout * 8);
   const size_t total = ocn + align256(cap * P * mout * 8);
@@ -2170,19 +2199,15 @@ extern "C" int dh_set_basis(dh_handle h, int type, int modes_out, int modes_in, 
     pl->bmem = nullptr;
     return set_err(pl, DH_ERR_MEMORYALLOCATION);
   }
-  std::vector<float2> tt((size_t)mused * mout);
-  for (int k = 0; k < mout; ++k)
-    for (int j = 0; j < mused; ++j) {
-      const cd v = t[(size_t)k * mused + j];
-      tt[(size_t)j * mout + k] = make_float2((float)v.real(), (float)v.imag());
-    }
   if (hipMemcpy(pl->bmem + ott, tt.data(), tt.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(pl->bmem + orn, rng.data(), rng.size() * 16, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(pl->bmem + ogr, grp.data(), grp.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
     (void)hipFree(pl->bmem);
     pl->bmem = nullptr;
     return set_err(pl, DH_ERR_ERROR);
   }
   pl->btt = (float2*)(pl->bmem + ott);
+  pl->brng = (int4*)(pl->bmem + orn);
   pl->bgrp = (int*)(pl->bmem + ogr);
   pl->bc = (float2*)(pl->bmem + oc);
   pl->bcn = (float2*)(pl->bmem + ocn);
@@ -2536,7 +2561,7 @@ hipError_t record_batch(const Camera& C, const Lane& L, int n) {
   if (e == hipSuccess && !spec && L.k.G > 0) e = dh::launch_fld(L.k, 0, n, L.s);
   if (e == hipSuccess && L.k.G > 0) e = dh::launch_norm(L.k, 0, n, L.s);
   if (e == hipSuccess && C.basis != DH_BASIS_HG)
-    e = dh::launch_basis(L.k.coefs, L.k.coefs_norm, pl->g.nmodes, pl->bin, pl->btt, pl->bout,
+    e = dh::launch_basis(L.k.coefs, L.k.coefs_norm, pl->g.nmodes, pl->bin, pl->brng, pl->btt, pl->bout,
                          (float2*)(L.mem + L.off[6]), (float2*)(L.mem + L.off[7]), n * pl->params.pol_count, L.s);
   return e;
 }

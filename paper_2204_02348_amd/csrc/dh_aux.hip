@@ -118,7 +118,7 @@ __device__ __forceinline__ long tm_key(const TmArgs& t, int k) {
   const int p = k / t.M;
   if (t.grp) return (long)p * t.ngrp + t.grp[k - p * t.M];
   const short2 mn = t.modes[k - p * t.M];
-  return (long)p * 64 + mn.x + mn.y;
+  return (long)p * 256 + mn.x + mn.y;      // groups m + n < 100
 }
 
 // Per row i of D (D = A, or the Gram A A^H in g, rows x rows): the row's
@@ -538,22 +538,27 @@ hipError_t launch_q16(const float2* fields, int n, long long len, short* re, sho
 
 // k_basis: grid (n, 2); block (e, y) maps coefficient vector e (a frame and
 // pol) of the raw (y = 0) or normalised (y = 1) HG coefficients to the basis:
-// out[e][k] = sum_{j < nused} tt[j][k] in[e][j], FP32, j in order. tt is T
-// transposed so that the threads of a block read consecutive k.
+// out[e][k] = sum_{i < cnt_k} tt[off_k + i stride_k] in[e][first_k + i],
+// FP32, i in order, with (first, cnt, off, stride) = rng[k]: the HG modes an
+// output mode takes (all of them for a dense transform, its own group for
+// LG), entries laid out so that the threads of a block read consecutive ones.
+constexpr int kBasisMaxIn = kMaxGroups * (kMaxGroups + 1) / 2;
 __global__ void __launch_bounds__(256) k_basis(const float2* __restrict__ in, const float2* __restrict__ in_norm,
-                                               int nin, int nused, const float2* __restrict__ tt, int nout,
-                                               float2* __restrict__ out, float2* __restrict__ out_norm) {
-  __shared__ float2 c[528];
+                                               int nin, int nused, const int4* __restrict__ rng,
+                                               const float2* __restrict__ tt, int nout, float2* __restrict__ out,
+                                               float2* __restrict__ out_norm) {
+  __shared__ float2 c[kBasisMaxIn];
   const int e = blockIdx.x;
   const float2* src = (blockIdx.y ? in_norm : in) + (size_t)e * nin;
   float2* dst = (blockIdx.y ? out_norm : out) + (size_t)e * nout;
   for (int j = threadIdx.x; j < nused; j += 256) c[j] = src[j];
   __syncthreads();
   for (int k = threadIdx.x; k < nout; k += 256) {
+    const int4 r = rng[k];
     float re = 0.f, im = 0.f;
-    for (int j = 0; j < nused; ++j) {
-      const float2 t = tt[(size_t)j * nout + k];
-      const float2 v = c[j];
+    for (int i = 0; i < r.y; ++i) {
+      const float2 t = tt[(size_t)r.z + (size_t)i * r.w];
+      const float2 v = c[r.x + i];
       re = fmaf(t.x, v.x, fmaf(-t.y, v.y, re));
       im = fmaf(t.x, v.y, fmaf(t.y, v.x, im));
     }
@@ -561,11 +566,11 @@ __global__ void __launch_bounds__(256) k_basis(const float2* __restrict__ in, co
   }
 }
 
-hipError_t launch_basis(const float2* in, const float2* in_norm, int nin, int nused, const float2* tt, int nout,
-                        float2* out, float2* out_norm, int n, hipStream_t s) {
+hipError_t launch_basis(const float2* in, const float2* in_norm, int nin, int nused, const int4* rng,
+                        const float2* tt, int nout, float2* out, float2* out_norm, int n, hipStream_t s) {
   if (n < 1) return hipSuccess;
-  if (nused > 528) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_basis, dim3(n, 2), dim3(256), 0, s, in, in_norm, nin, nused, tt, nout, out, out_norm);
+  if (nused > kBasisMaxIn) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_basis, dim3(n, 2), dim3(256), 0, s, in, in_norm, nin, nused, rng, tt, nout, out, out_norm);
   return hipGetLastError();
 }
 

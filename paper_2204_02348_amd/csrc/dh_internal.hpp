@@ -6,6 +6,14 @@
 
 namespace dh {
 
+// Largest mode-group count G a plan takes, and its padded column count: the
+// mode tables hold gp columns, 16 for G <= 16, else 32 ceil(G / 32) (the
+// paper names LG bases of up to 100 groups; its HG basis sets no bound)
+constexpr int kMaxGroups = 100;
+constexpr int kMaxGp = 128;
+// the field path's overlap tiles modes in at most two 16-column tiles
+constexpr int kMaxGpField = 32;
+
 // Per-polarisation plan tables (device pointers) and window geometry.
 //
 // "Box": the rectangle of spectrum bins that holds every bin of the Fourier
@@ -50,7 +58,7 @@ struct KArgs {
   int nx, ny, wx, wy, wyp;  // FFT window, IFFT window, IFFT rows rounded up to 16
   int bx, by;               // box size (max over pols)
   int bxp;                  // f2 row pitch: bx rounded up to 16
-  int G, gp, nmodes;        // groups, padded group count (16 or 32), modes per pol
+  int G, gp, nmodes;        // groups, padded group count (16 ceil(G / 16)), modes per pol
   float nxny;               // Nx * Ny
   int prec;                 // DH_PREC_FP32 / SPLIT_BF16 / SPLIT_FP16
   float s_uh;               // power-of-two prescale of the fp16 split HG tables
@@ -139,11 +147,12 @@ hipError_t launch_m0y(const M0Args& m, int nb, hipStream_t s);
 hipError_t launch_m0x(const M0Args& m, int nb, hipStream_t s);
 // fields to int16 (re, im) with one FP32 scale per field: n fields of len values
 hipError_t launch_q16(const float2* fields, int n, long long len, short* re, short* im, float* scale, hipStream_t s);
-// basis transform of n coefficient vectors (frame x pol): out[e][k] = sum over
-// j < nused of tt[j][k] in[e][j] (in rows of nin values), for the raw and the
-// normalised coefficients
-hipError_t launch_basis(const float2* in, const float2* in_norm, int nin, int nused, const float2* tt, int nout,
-                        float2* out, float2* out_norm, int n, hipStream_t s);
+// basis transform of n coefficient vectors (frame x pol, rows of nin values,
+// the first nused of them taken): out[e][k] = sum_{i < cnt} tt[off + i stride]
+// in[e][first + i] with (first, cnt, off, stride) = rng[k], for the raw and
+// the normalised coefficients
+hipError_t launch_basis(const float2* in, const float2* in_norm, int nin, int nused, const int4* rng,
+                        const float2* tt, int nout, float2* out, float2* out_norm, int n, hipStream_t s);
 hipError_t launch_moments(const float2* fields, int n, int wx, int wy, double px, double py, double* out,
                           hipStream_t s);
 // HG tables: out[k][n] in FP32 and, if the split pointers are non-null, the

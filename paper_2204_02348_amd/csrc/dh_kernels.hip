@@ -366,7 +366,11 @@ __global__ void __launch_bounds__(kTPB) k_col(KArgs A, int b0) {
 // the four waves round robin. B = Re ys and Im ys of the same rows. With
 // S = a + ib and ys = c + id, conj(S) ys = (ac + bd) + i(ad - bc).
 // The block's field power follows from Parseval: sum |E|^2 = wx wy sum |S|^2 / (Nx Ny)^2.
-template <int NY, int WY, int CG, int NT>
+// NT mode tiles of 16 are contracted at a time. MC: the plan has more mode
+// tiles (gp > 16 NT, up to kMaxGp); the contraction then runs once per chunk
+// of NT tiles over the same window in LDS, each chunk's Q columns collected in
+// LDS before the final product (tables of gp columns; MC = false: gp = 16 NT).
+template <int NY, int WY, int CG, int NT, bool MC>
 __global__ void __launch_bounds__(kTPB) k_cspec(KArgs A, int b0) {
   using LN = Lds<NY>;
   using Q = Pass1<NY, CG, kTPB>;
@@ -374,49 +378,53 @@ __global__ void __launch_bounds__(kTPB) k_cspec(KArgs A, int b0) {
   constexpr int MT = (2 * CG + 15) / 16;          // A-row tiles
   constexpr int WYP = (WY + 15) / 16 * 16;
   constexpr int KSW = WYP / 16;                    // K steps per wave, at most
-  constexpr int GP = 16 * NT;
+  constexpr int GP = 16 * NT;                      // mode columns per chunk
+  constexpr int GPM = MC ? kMaxGp : GP;            // mode columns held in LDS, at most
   constexpr int NRED = 4 * MT * NT * 2 * 256;      // floats: the waves' MFMA results
-  constexpr int NQ = CG * GP;                      // float2: Q
-  constexpr bool IN_BUF = NRED * 4 + NQ * 8 <= CG * ST * 8;
+  constexpr int NQ = CG * GP;                      // float2: one chunk of Q
+  // with several chunks the window stays in buf until the last one
+  constexpr bool IN_BUF = !MC && NRED * 4 + NQ * 8 <= CG * ST * 8;
   static_assert(KSW * NT <= 96, "B operands are held in registers");
   // From 1024 rows on, the twiddles are read through the caches instead of LDS
   // wherever that lets one more workgroup onto a CU (160 KB of LDS each); at
   // 512 rows the extra workgroup measured slower than the LDS reads it saves.
-  constexpr int LDS_REST = CG * ST * 8 + WYP * 8 + CG * GP * 8 + 16 + (IN_BUF ? 8 : (NRED / 2 + NQ) * 8);
+  constexpr int LDS_REST = CG * ST * 8 + WYP * 8 + CG * GPM * 8 + 16 + (IN_BUF ? 8 : (NRED / 2 + CG * GPM) * 8);
   constexpr int LDS_CU = 160 * 1024;
   constexpr bool TWG = NY >= 1024 && LDS_CU / LDS_REST > LDS_CU / (LDS_REST + twn<NY>() * 8);
   __shared__ float2 buf[CG * ST];
   __shared__ float2 twy[TWG ? 1 : twn<NY>()];
   __shared__ int2 s_mrow[WYP];
-  __shared__ float2 s_x[CG * GP];                  // xs rows of the block's columns
+  __shared__ float2 s_x[CG * GPM];                 // xs rows of the block's columns
   __shared__ float s_pw[4];
-  __shared__ float2 s_spill[IN_BUF ? 1 : (NRED / 2 + NQ)];
+  __shared__ float2 s_spill[IN_BUF ? 1 : (NRED / 2 + CG * GPM)];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const int p = blockIdx.y;
   const int bl = blockIdx.z;
   const PolTab& P = A.pol[p];
   const int jc0 = blockIdx.x * CG;
+  const int gpt = MC ? A.gp : GP;                  // table row stride (mode columns)
+  const int nch = MC ? gpt / GP : 1;               // chunks of NT mode tiles
   // tables first: their loads are in flight with the column loads
   Staged<float2, TWG ? 1 : twn<NY>(), kTPB> stwy;
   Staged<int2, WYP, kTPB> smr;
-  Staged<float2, CG * GP, kTPB> sx;
+  Staged<float2, CG * GPM, kTPB> sx;
   if constexpr (!TWG) stwy.load(A.tw_ny, twn<NY>(), tid);
   smr.load(P.mrow, A.by, tid);
   const int ncx = A.bx - jc0 < CG ? A.bx - jc0 : CG;
-  sx.load(P.xs + (size_t)jc0 * GP, ncx * GP, tid);
+  sx.load(P.xs + (size_t)jc0 * gpt, ncx * gpt, tid);
   // this wave's B operands: steps s = wv + 4 t, box rows i = 4 s + lane / 16;
   // the ys table has 16 KSW rows (wy rounded up to 16), zero from row by on.
   // The first DB steps' operands are loaded before the column FFT, the rest
   // DB steps ahead of their use (DB = KSW where they all fit in registers)
   constexpr int DB = KSW * NT <= 24 ? KSW : 12 / NT;
   float bre[KSW][NT], bim[KSW][NT];
-  const float2* yrow = P.ys + (4 * wv + (lane >> 4)) * GP + (lane & 15);
+  const float2* yrow = P.ys + (4 * wv + (lane >> 4)) * gpt + (lane & 15);
 #pragma unroll
   for (int t = 0; t < DB; ++t)
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
-      const float2 y = yrow[t * 16 * GP + nt * 16];
+      const float2 y = yrow[t * 16 * gpt + nt * 16];
       bre[t][nt] = y.x;
       bim[t][nt] = y.y;
     }
@@ -444,7 +452,7 @@ __global__ void __launch_bounds__(kTPB) k_cspec(KArgs A, int b0) {
     }
     if constexpr (!TWG) stwy.store(twy, twn<NY>(), make_float2(0.f, 0.f), tid);
     smr.store(s_mrow, A.by, make_int2(1, 0), tid);
-    sx.store(s_x, ncx * GP, make_float2(0.f, 0.f), tid);
+    sx.store(s_x, ncx * gpt, make_float2(0.f, 0.f), tid);
     fft_pass1_regs<NY, CG, ST, kTPB>(v, buf, tid);
   }
   if constexpr (TWG)
@@ -473,97 +481,112 @@ __global__ void __launch_bounds__(kTPB) k_cspec(KArgs A, int b0) {
       win[(size_t)q * A.wx + qu] = make_float2(sg * val.x, -sg * val.y);
     }
   }
-  floatx4 d1[MT][NT], d2[MT][NT];
-#pragma unroll
-  for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-      d1[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
-      d2[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
-    }
   float pw = 0.f;
-  {
-    // the A operands (mask interval and spectrum value of each step) are read
-    // DA steps ahead of their MFMAs (all of them first where they fit in
-    // registers); every address is valid: rows past the box have empty mask
-    // intervals and zero B operands. The mask is applied as a select.
-    constexpr int DA = KSW <= 16 ? KSW : 12;
-    int2 mv[KSW];
-    float2 fv[KSW][MT];
-    int i = 4 * wv + (lane >> 4);                 // box row of the next step to read
-    int vv = (P.ky0 + i) % NY;                    // its column-FFT bin
-    if (vv < 0) vv += NY;
-#pragma unroll
-    for (int t = 0; t < KSW + DA; ++t) {
-      if (t < KSW) {                              // read step t (compile-time after unrolling)
-        mv[t] = s_mrow[i];                        // i < 16 KSW = WYP
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) fv[t][mt] = buf[((mt * 16 + (lane & 15)) % CG) * ST + LN::at(vv)];
-        i += 16;
-        vv += 16;
-        if (vv >= NY) vv -= NY;
-      }
-      const int u = t - DA;                       // step whose MFMAs run now
-      if (u >= 0) {
-        if (u + DB < KSW) {
-#pragma unroll
-          for (int nt = 0; nt < NT; ++nt) {
-            const float2 y = yrow[(u + DB) * 16 * GP + nt * 16];
-            bre[u + DB][nt] = y.x;
-            bim[u + DB][nt] = y.y;
-          }
-        }
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-          const int r = mt * 16 + (lane & 15);
-          const int part = r / CG;
-          const int ja = jc0 + r % CG;
-          const bool ok = part < 2 && ja >= mv[u].x && ja <= mv[u].y;
-          const float a = ok ? (part ? fv[u][mt].y : fv[u][mt].x) : 0.f;
-          pw = fmaf(a, a, pw);
-#pragma unroll
-          for (int nt = 0; nt < NT; ++nt) {
-            d1[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bre[u][nt], d1[mt][nt], 0, 0, 0);
-            d2[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bim[u][nt], d2[mt][nt], 0, 0, 0);
-          }
-        }
-      }
-    }
-  }
-  __syncthreads();                                // every wave is done with buf
   float* red = IN_BUF ? reinterpret_cast<float*>(buf) : reinterpret_cast<float*>(s_spill);
   float2* s_q = reinterpret_cast<float2*>(red + NRED);
-  // red[(((w MT + mt) NT + nt) 2 + h) 256 + row 16 + n], h = 0: d1, 1: d2
+  for (int ch = 0; ch < nch; ++ch) {
+    if (ch > 0) {
+      // the next chunk's first B operands (chunk 0's were loaded before the FFT)
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt)
+      for (int t = 0; t < DB; ++t)
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int el = (4 * (lane >> 4) + r) * 16 + (lane & 15);
-        red[(((wv * MT + mt) * NT + nt) * 2 + 0) * 256 + el] = d1[mt][nt][r];
-        red[(((wv * MT + mt) * NT + nt) * 2 + 1) * 256 + el] = d2[mt][nt][r];
-      }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) pw += __shfl_xor(pw, off, 64);
-  if (lane == 0) s_pw[wv] = pw;
-  __syncthreads();
-  // Q[j][n], the four waves summed in order
-  for (int e = tid; e < NQ; e += kTPB) {
-    const int j = e / GP, n = e % GP;
-    const int nt = n >> 4, nn = n & 15;
-    const int r0 = j, r1 = CG + j;                // rows of Re S and Im S
-    float qr = 0.f, qi = 0.f;
-#pragma unroll
-    for (int w = 0; w < 4; ++w) {
-      const float* b0r = red + (((w * MT + (r0 >> 4)) * NT + nt) * 2) * 256 + (r0 & 15) * 16 + nn;
-      const float* b1r = red + (((w * MT + (r1 >> 4)) * NT + nt) * 2) * 256 + (r1 & 15) * 16 + nn;
-      qr += b0r[0] + b1r[256];                    // a c + b d
-      qi += b0r[256] - b1r[0];                    // a d - b c
+        for (int nt = 0; nt < NT; ++nt) {
+          const float2 y = yrow[t * 16 * gpt + ch * GP + nt * 16];
+          bre[t][nt] = y.x;
+          bim[t][nt] = y.y;
+        }
     }
-    s_q[e] = make_float2(qr, qi);
+    floatx4 d1[MT][NT], d2[MT][NT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        d1[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+        d2[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+      }
+    {
+      // the A operands (mask interval and spectrum value of each step) are read
+      // DA steps ahead of their MFMAs (all of them first where they fit in
+      // registers); every address is valid: rows past the box have empty mask
+      // intervals and zero B operands. The mask is applied as a select.
+      constexpr int DA = KSW <= 16 ? KSW : 12;
+      int2 mv[KSW];
+      float2 fv[KSW][MT];
+      int i = 4 * wv + (lane >> 4);                 // box row of the next step to read
+      int vv = (P.ky0 + i) % NY;                    // its column-FFT bin
+      if (vv < 0) vv += NY;
+#pragma unroll
+      for (int t = 0; t < KSW + DA; ++t) {
+        if (t < KSW) {                              // read step t (compile-time after unrolling)
+          mv[t] = s_mrow[i];                        // i < 16 KSW = WYP
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) fv[t][mt] = buf[((mt * 16 + (lane & 15)) % CG) * ST + LN::at(vv)];
+          i += 16;
+          vv += 16;
+          if (vv >= NY) vv -= NY;
+        }
+        const int u = t - DA;                       // step whose MFMAs run now
+        if (u >= 0) {
+          if (u + DB < KSW) {
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+              const float2 y = yrow[(u + DB) * 16 * gpt + ch * GP + nt * 16];
+              bre[u + DB][nt] = y.x;
+              bim[u + DB][nt] = y.y;
+            }
+          }
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) {
+            const int r = mt * 16 + (lane & 15);
+            const int part = r / CG;
+            const int ja = jc0 + r % CG;
+            const bool ok = part < 2 && ja >= mv[u].x && ja <= mv[u].y;
+            const float a = ok ? (part ? fv[u][mt].y : fv[u][mt].x) : 0.f;
+            if (ch == 0) pw = fmaf(a, a, pw);
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+              d1[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bre[u][nt], d1[mt][nt], 0, 0, 0);
+              d2[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bim[u][nt], d2[mt][nt], 0, 0, 0);
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();                              // every wave is done with buf (and the last chunk's red)
+    // red[(((w MT + mt) NT + nt) 2 + h) 256 + row 16 + n], h = 0: d1, 1: d2
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int el = (4 * (lane >> 4) + r) * 16 + (lane & 15);
+          red[(((wv * MT + mt) * NT + nt) * 2 + 0) * 256 + el] = d1[mt][nt][r];
+          red[(((wv * MT + mt) * NT + nt) * 2 + 1) * 256 + el] = d2[mt][nt][r];
+        }
+    if (ch == 0) {
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) pw += __shfl_xor(pw, off, 64);
+      if (lane == 0) s_pw[wv] = pw;
+    }
+    __syncthreads();
+    // Q[j][ch GP + n], the four waves summed in order
+    for (int e = tid; e < NQ; e += kTPB) {
+      const int j = e / GP, n = e % GP;
+      const int nt = n >> 4, nn = n & 15;
+      const int r0 = j, r1 = CG + j;              // rows of Re S and Im S
+      float qr = 0.f, qi = 0.f;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const float* b0r = red + (((w * MT + (r0 >> 4)) * NT + nt) * 2) * 256 + (r0 & 15) * 16 + nn;
+        const float* b1r = red + (((w * MT + (r1 >> 4)) * NT + nt) * 2) * 256 + (r1 & 15) * 16 + nn;
+        qr += b0r[0] + b1r[256];                  // a c + b d
+        qi += b0r[256] - b1r[0];                  // a d - b c
+      }
+      s_q[j * gpt + ch * GP + n] = make_float2(qr, qi);
+    }
+    __syncthreads();
   }
-  __syncthreads();
   const int pstride = A.nmodes + 1;
   float2* part = A.partial + ((size_t)(bl * A.nblk + blockIdx.x) * A.npol + p) * pstride;
   if (tid == 0)
@@ -572,7 +595,7 @@ __global__ void __launch_bounds__(kTPB) k_cspec(KArgs A, int b0) {
     const short2 mn = A.modes[e];
     float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
-    for (int j = 0; j < CG; ++j) acc = cadd(acc, cmul(s_x[j * GP + mn.x], s_q[j * GP + mn.y]));
+    for (int j = 0; j < CG; ++j) acc = cadd(acc, cmul(s_x[j * gpt + mn.x], s_q[j * gpt + mn.y]));
     part[e] = acc;
   }
 }
@@ -1155,6 +1178,7 @@ static void fld_wm(const KArgs& a, dim3 grid, int b0, hipStream_t s) {
 template <int WX>
 static hipError_t fld_w(const KArgs& a, int b0, int nb, hipStream_t s) {
   dim3 grid(a.nblk, a.npol, nb);
+  if (a.gp > kMaxGpField) return hipErrorInvalidValue;
   if (a.gp <= 16)
     fld_wm<WX, 1>(a, grid, b0, s);
   else
@@ -1215,9 +1239,10 @@ hipError_t launch_col(const KArgs& a, int b0, int nb, hipStream_t s) {
 template <int NY, int WY, int NT>
 constexpr bool cspec_fits() { return ((WY + 15) / 16) * NT <= 96; }
 
+// gp 16: one mode tile; 32: two; above: chunks of two tiles (gp a multiple of 32)
 bool spectral_supported(int ny, int wy, int gp) {
-  const int nt = gp / 16;
-#define X(N, W) if (ny == N && wy == W) return nt == 1 ? cspec_fits<N, W, 1>() : cspec_fits<N, W, 2>();
+  if (gp < 16 || gp > kMaxGp || (gp > 32 && gp % 32)) return false;
+#define X(N, W) if (ny == N && wy == W) return gp == 16 ? cspec_fits<N, W, 1>() : cspec_fits<N, W, 2>();
   DH_COL_PAIRS(X)
 #undef X
   return false;
@@ -1231,12 +1256,12 @@ int spectral_blocks(int ny, int bx, int gp) {
   return (bx + cg - 1) / cg;
 }
 
-template <int NY, int WY, int NT>
+template <int NY, int WY, int NT, bool MC>
 static hipError_t cspec_nwt(const KArgs& a, int b0, int nb, hipStream_t s) {
   if constexpr (cspec_fits<NY, WY, NT>()) {
     constexpr int CG = cspec_cg<NY, NT>();
     dim3 grid((a.bx + CG - 1) / CG, a.npol, nb);
-    hipLaunchKernelGGL((k_cspec<NY, WY, CG, NT>), grid, dim3(kTPB), 0, s, a, b0);
+    hipLaunchKernelGGL((k_cspec<NY, WY, CG, NT, MC>), grid, dim3(kTPB), 0, s, a, b0);
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;
@@ -1244,8 +1269,11 @@ static hipError_t cspec_nwt(const KArgs& a, int b0, int nb, hipStream_t s) {
 }
 
 hipError_t launch_cspec(const KArgs& a, int b0, int nb, hipStream_t s) {
-#define X(N, W) \
-  if (a.ny == N && a.wy == W) return a.gp == 16 ? cspec_nwt<N, W, 1>(a, b0, nb, s) : cspec_nwt<N, W, 2>(a, b0, nb, s);
+  if (!spectral_supported(a.ny, a.wy, a.gp)) return hipErrorInvalidValue;
+#define X(N, W)                                                                              \
+  if (a.ny == N && a.wy == W)                                                                \
+    return a.gp == 16 ? cspec_nwt<N, W, 1, false>(a, b0, nb, s)                              \
+                      : a.gp == 32 ? cspec_nwt<N, W, 2, false>(a, b0, nb, s) : cspec_nwt<N, W, 2, true>(a, b0, nb, s);
   DH_COL_PAIRS(X)
 #undef X
   return hipErrorInvalidValue;

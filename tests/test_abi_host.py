@@ -49,13 +49,16 @@ def _p(idx=1, **kw):
     (dict(window_radius_deg=5.0), dh.ERR_INVALIDARGUMENT),  # wider than the spectrum
     (dict(waist=0.0), dh.ERR_INVALIDARGUMENT),
     (dict(max_mg=-1), dh.ERR_INVALIDARGUMENT),
-    (dict(max_mg=33), dh.ERR_INVALIDARGUMENT),
+    (dict(max_mg=101), dh.ERR_INVALIDARGUMENT),          # past the paper's 100 LG groups
+    (dict(max_mg=33, path="field"), dh.ERR_INVALIDARGUMENT),    # the field path's overlap: G <= 32
+    (dict(max_mg=40, keep_fields=1), dh.ERR_INVALIDARGUMENT),   # mode-1 fields need the field path
+    (dict(max_mg=64, precision="split_fp16"), dh.ERR_INVALIDARGUMENT),
     (dict(input_dtype=7), dh.ERR_INVALIDARGUMENT),
     (dict(precision=9), dh.ERR_INVALIDARGUMENT),
     (dict(ifft_mode=2), dh.ERR_INVALIDARGUMENT),
     (dict(ifft_mode=0, path="field"), dh.ERR_INVALIDARGUMENT),        # mode 0 runs the spectral path
     (dict(ifft_mode=0, precision="split_bf16"), dh.ERR_INVALIDARGUMENT),
-    (dict(ifft_mode=0, max_mg=0), dh.ERR_INVALIDARGUMENT),
+    (dict(ifft_mode=0, max_mg=0, path="field"), dh.ERR_INVALIDARGUMENT),
     (dict(path=3), dh.ERR_INVALIDARGUMENT),
     (dict(path=-1), dh.ERR_INVALIDARGUMENT),
     (dict(path="spectral", keep_fields=1), dh.ERR_INVALIDARGUMENT),
@@ -66,6 +69,26 @@ def _p(idx=1, **kw):
 def test_validation_error_codes(kw, code):
     rc, _ = dh.plan_check(_p(**kw))
     assert rc == code
+
+
+@pytest.mark.parametrize("kw", [dict(max_mg=33), dict(max_mg=64), dict(max_mg=100),
+                                dict(max_mg=100, ifft_mode=0, keep_fields=1)])
+def test_large_group_counts_take_the_spectral_path(kw):
+    # G above 32 runs the spectral contraction in chunks of 32 mode columns;
+    # IFFT mode 0 exports its fields from the kept window
+    d = _p(3, **kw)
+    d.update(dh_synth.config(3, 3)["params"], **kw)
+    rc, info = dh.plan_check(d)
+    assert rc == 0 and info.path == dh.PATH_SPECTRAL
+    assert info.modes == kw["max_mg"] * (kw["max_mg"] + 1) // 2
+
+
+def test_mode0_without_decomposition():
+    # IFFT mode 0 with G = 0: the field reconstruction alone (the paper's
+    # field-reconstruction benchmarks run without a decomposition)
+    rc, info = dh.plan_check(_p(1, ifft_mode=0, max_mg=0, keep_fields=1))
+    assert rc == 0 and info.path == dh.PATH_SPECTRAL and info.modes == 0
+    assert (info.field_w, info.field_h) == (320, 512)
 
 
 def test_null_pointer():

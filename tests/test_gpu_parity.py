@@ -181,6 +181,53 @@ def test_largest_group_count(idx, path):
     check_frames(p, f, gpu, range(f.shape[0]), keep=path == "field")
 
 
+@pytest.mark.parametrize("idx,cam,g,n", [
+    (1, 0, 33, 2),       # 640x512, 2 pols: 64 mode columns, the second chunk mostly padding
+    (1, 0, 64, 2),       # two full chunks
+    (0, 0, 48, 1),       # 128x128: 16 box columns per workgroup, two A-row tiles
+    (3, 3, 64, 1),       # 2048x2048 u16 camera, W = 672
+    (3, 3, 100, 1),      # the largest group count: 5050 modes per pol, four chunks
+])
+def test_large_group_counts(idx, cam, g, n):
+    """G above 32 on the spectral path (mode columns contracted in chunks of
+    32 over the window held in LDS): coefficients and window against the
+    oracle."""
+    cfg, f, _ = _frames(idx, cam, n=n)
+    p = dict(cfg["params"], max_mg=g)
+    _say(f"G={g} recipe {idx} camera {cam}, {n} frames, spectral path")
+    gpu = run_gpu(p, f, keep=True, path="spectral")
+    assert gpu["coefs"].shape[2] == g * (g + 1) // 2
+    check_frames(p, f, gpu, range(n))
+
+
+def test_lg_basis_at_100_groups():
+    """The LG basis at the paper's largest group count on the 2048x2048
+    camera: coefficients (raw and normalised) against the oracle's HG
+    coefficients times its per-group HG->LG blocks."""
+    import paper_2204_02348_amd as dh
+    cfg, f, _ = _frames(3, 3, n=1)
+    p = dict(cfg["params"], max_mg=100)
+    _say("LG basis, G=100, 2048x2048 camera")
+    raw, nrm, _ = _basis_run(p, f, dh.BASIS_LG)
+    assert raw.shape == (1, 1, 5050)
+    blocks = oracle.lg_blocks(100)
+    ref = oracle.process_frame(f[0].astype(np.float64), p)
+    lr, ln = oracle.apply_lg_blocks(ref["coefs"], blocks), oracle.apply_lg_blocks(ref["coefs_norm"], blocks)
+    e, en = _rel(raw[0][0].astype(np.complex128), lr[0]), _rel(nrm[0][0].astype(np.complex128), ln[0])
+    _say(f"LG rel-L2 raw {e:.2e}, normalised {en:.2e}")
+    assert e <= TOL and en <= TOL
+
+
+def test_mode0_large_group_count():
+    """IFFT mode 0 with G = 64 (coefficients from the spectral tables on the
+    FFT grid, fields exported) against the oracle."""
+    cfg, f, _ = _frames(1, n=2)
+    p = dict(cfg["params"], max_mg=64, ifft_mode=0)
+    _say("mode 0, G=64, 640x512")
+    gpu = run_gpu(p, f, keep=False, path="spectral")
+    check_frames(p, f, gpu, range(2), keep=False)
+
+
 def test_zero_frames_give_zero_not_nan():
     """All-zero frames: every coefficient, raw and normalised (power 0), is
     exactly zero on both paths, and the int16 export has scale 1."""
@@ -713,6 +760,20 @@ def test_mode0_coefficients_and_fields_vs_oracle(idx, cam, n, chunk):
     _say("IFFT mode 0, recipe", idx, "camera", cam, f.shape)
     gpu = run_gpu(p, f, chunk=chunk)
     assert gpu["info"].path == dh.PATH_SPECTRAL
+    assert gpu["field"].shape[2:] == (p["fft_h"], p["fft_w"])
+    check_frames(p, f, gpu, range(n))
+
+
+@pytest.mark.parametrize("idx,cam,n", [(1, 0, 3), (3, 2, 2)])
+def test_mode0_without_decomposition(idx, cam, n):
+    """IFFT mode 0 with G = 0: the field reconstruction alone (window and
+    full-size fields, no coefficients) against the oracle."""
+    import paper_2204_02348_amd as dh
+    cfg, f, _ = _frames(idx, cam=cam, n=n)
+    p = dict(cfg["params"], ifft_mode=0, max_mg=0)
+    _say("IFFT mode 0, G=0, recipe", idx, "camera", cam, f.shape)
+    gpu = run_gpu(p, f)
+    assert gpu["info"].path == dh.PATH_SPECTRAL and gpu["info"].modes == 0
     assert gpu["field"].shape[2:] == (p["fft_h"], p["fft_w"])
     check_frames(p, f, gpu, range(n))
 

@@ -295,11 +295,13 @@ BASIS_SRC = os.path.join(os.path.dirname(SRC), "basis.py")
 
 BASIS_MUTATIONS = {
     "l_order_reversed": ("for l in range(n, -n - 1, -2):", "for l in range(-n, n + 1, 2):"),
-    "no_conjugate": ("np.sum(ww * np.conj(a) * b)", "np.sum(ww * a * b)"),
+    "no_conjugate": ("return np.conj(lg) @ (ww.ravel() * hg).T", "return lg @ (ww.ravel() * hg).T"),
     "lg_norm": ("math.factorial(p + abs(l))", "math.factorial(p)"),
     "phi_sign": ("np.exp(1j * l * phi)", "np.exp(-1j * l * phi)"),
     "laguerre_argument": ("special.eval_genlaguerre(p, abs(l), 2.0 * r2)", "special.eval_genlaguerre(p, abs(l), r2)"),
-    "hg_axes_swapped": ("np.outer(u[n], u[m]) for m, n", "np.outer(u[m], u[n]) for m, n"),
+    "hg_axes_swapped": ("np.outer(u[n], u[m]).ravel() for m, n", "np.outer(u[m], u[n]).ravel() for m, n"),
+    "block_wrong_group": ("hg[start:start + n + 1], group_count + 4", "hg[start + 1:start + n + 2], group_count + 4"),
+    "block_no_conjugate_order": ("b, c[..., start:start + k]", "b.T, c[..., start:start + k]"),
     "custom_extra_columns_used": ("k = min(modes, t.shape[1])", "k = t.shape[1]"),
 }
 
@@ -322,19 +324,23 @@ def test_basis_pins_catch_planted_mistake(name, monkeypatch):
     import oracle
     import tests.test_oracle_pins as pins
     mut = _basis_mutant(name)
-    for k in ("lg_modes", "lg_function", "hg_to_lg", "custom_transform", "apply_basis"):
+    for k in ("lg_modes", "lg_function", "hg_to_lg", "lg_blocks", "apply_lg_blocks", "custom_transform",
+              "apply_basis"):
         monkeypatch.setattr(oracle, k, getattr(mut, k))
     failed = 0
     for t in [pins.test_lg_transform_is_unitary_and_keeps_groups,
               pins.test_lg_low_orders_are_the_textbook_combinations,
               pins.test_lg_transform_matches_the_closed_form,
               pins.test_lg_transform_matches_fine_grid_overlaps,
-              pins.test_custom_transform_uses_only_the_plan_modes]:
+              pins.test_custom_transform_uses_only_the_plan_modes,
+              pins.test_lg_blocks_are_the_full_transform,
+              pins.test_lg_blocks_at_100_groups]:           # the costly pin last
         try:
             with np.errstate(all="ignore"):
                 t()
         except (AssertionError, ValueError, IndexError):
             failed += 1
+            break
     assert failed > 0, name
 
 

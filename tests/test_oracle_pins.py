@@ -699,6 +699,49 @@ def test_lg_transform_matches_fine_grid_overlaps():
             assert abs(np.sum(np.conj(a) * b) * dx * dx - t[r, c]) < 1e-9, (p, l, m, n)
 
 
+def _lg_closed_form_block(big_n):
+    """Block of group N of the closed form above (exact integer sums)."""
+    t = np.zeros((big_n + 1, big_n + 1), dtype=complex)
+    for r in range(big_n + 1):
+        l = big_n - 2 * r
+        p = (big_n - abs(l)) // 2
+        n, m = p + max(l, 0), p + max(-l, 0)
+        for k in range(big_n + 1):
+            poly = sum(math.comb(n, a) * (-1) ** a * math.comb(m, k - a) for a in range(0, k + 1) if k - a <= m)
+            # sqrt of a ratio of big integers, then the exact integer poly
+            b = math.sqrt(math.factorial(big_n - k) * math.factorial(k)
+                          / (2 ** big_n * math.factorial(n) * math.factorial(m))) * poly
+            t[r, k] = (-1) ** p * (1j) ** k * b
+    return t
+
+
+def test_lg_blocks_are_the_full_transform():
+    # the per-group blocks are the diagonal blocks of the full overlap matrix
+    # (whose other entries vanish, pinned above), and applying them is the
+    # dense product
+    full = oracle.hg_to_lg(12)
+    blocks = oracle.lg_blocks(12)
+    start = 0
+    for n, b in enumerate(blocks):
+        assert b.shape == (n + 1, n + 1)
+        assert np.abs(b - full[start:start + n + 1, start:start + n + 1]).max() < 1e-13
+        start += n + 1
+    rng = np.random.default_rng(5)
+    c = rng.normal(size=(3, 2, 78)) + 1j * rng.normal(size=(3, 2, 78))
+    assert np.abs(oracle.apply_lg_blocks(c, blocks) - oracle.apply_basis(c, full)).max() < 1e-12
+
+
+def test_lg_blocks_at_100_groups():
+    # the paper's largest LG basis: every block unitary, and the highest,
+    # a middle and a low group equal to the exact closed form
+    blocks = oracle.lg_blocks(100)
+    assert len(blocks) == 100
+    for n, b in enumerate(blocks):
+        assert np.abs(b @ b.conj().T - np.eye(n + 1)).max() < 1e-10, n
+    for n in (7, 64, 99):
+        assert np.abs(blocks[n] - _lg_closed_form_block(n)).max() < 1e-10, n
+
+
 def test_lg_coefficients_of_a_pure_lg_hologram():
     # a hologram whose signal is LG mode k alone (its HG expansion is row k of
     # T conjugated) decomposes to the unit vector e_k in the LG basis
