@@ -240,7 +240,30 @@ struct Layout {  // byte offsets inside one device allocation
   size_t pol_ex[2], pol_ey[2];           // mode-0 field export: phase tables along x and y
   size_t export_t;                       // mode-0 field export: the y-transformed box columns
   size_t t1[4], f2[4], partial[4], capt, coefs, coefs_norm, window, fields, total;
+  size_t fctr[4], fslot[4];              // fused launch: counters and row-pass spectrum slots
 };
+
+// Fused row + column launches (spectral path, shapes with a fused kernel),
+// taken when the environment sets DH_FUSED=1: queues of the layout (the XCD
+// count of the part; fewer found at run time leave some unused) and slots per
+// queue: as many pol-frame spectra as fit in three quarters of an XCD's 4 MB
+// L2, at least 3 and at most 8 (DH_FUSED_SLOTS overrides).
+constexpr int kFusedQueues = 8;
+bool fused_enabled(const Geom& g, const dh_params* p) {
+  const char* env = std::getenv("DH_FUSED");
+  if (!env || std::strtol(env, nullptr, 10) != 1) return false;
+  return g.spec && dh::fused_supported(g.nx, g.ny, g.wy, g.gp, p->input_dtype == DH_INPUT_U16);
+}
+int fused_slots(const Geom& g) {
+  const size_t slot = (size_t)g.bx * g.ny * 8;
+  const long s = (long)((3ull << 20) / (slot ? slot : 1));
+  int n = (int)std::max(3L, std::min(8L, s));
+  if (const char* env = std::getenv("DH_FUSED_SLOTS")) {
+    const long v = std::strtol(env, nullptr, 10);
+    if (v >= 2 && v <= 64) n = (int)v;       // a row task waits on the columns of the pol-frame S back
+  }
+  return n;
+}
 
 Layout layout(const Geom& g, const dh_params* p, int max_batch, int chunk, int nws) {
   Layout L{};
@@ -282,6 +305,11 @@ Layout layout(const Geom& g, const dh_params* p, int max_batch, int chunk, int n
   L.fields = p->keep_fields ? take((size_t)max_batch * P * g.fy * g.fx * 8) : 0;
   L.export_t = exports(g, p) ? take((size_t)export_chunk(g, p, max_batch) * P * g.fy * ((g.bx + 15) / 16 * 16) * 8)
                               : 0;
+  const bool fused = fused_enabled(g, p);
+  for (int w = 0; w < nws; ++w) {
+    L.fctr[w] = fused ? take(dh::fused_counter_ints(kFusedQueues, chunk * (int)P) * 4) : 0;
+    L.fslot[w] = fused ? take((size_t)kFusedQueues * fused_slots(g) * g.bx * g.ny * 8) : 0;
+  }
   L.total = o;
   return L;
 }
@@ -296,6 +324,8 @@ struct Plan {
   char* mem = nullptr;
   hipStream_t last_stream = nullptr;
   dh::KArgs ka[4]{};                 // one per workspace
+  bool fused = false;                // row and column passes in one fused launch
+  dh::FusedQ fq[4]{};                // its queues, per workspace
   hipStream_t str[4]{};              // internal streams (nws > 1)
   hipEvent_t fork = nullptr, join[4]{};
   // per-stage timing: a start and an end event around every launch, on the
@@ -728,6 +758,17 @@ int export_fields(Plan* pl, int first, int count, int stride, int lam, hipStream
   return DH_SUCCESS;
 }
 
+// whether the last fused launch of any workspace gave up a wait (read after
+// the plan's stream has been synchronised)
+bool fused_failed(Plan* pl) {
+  if (!pl->fused) return false;
+  for (int w = 0; w < pl->nws; ++w) {
+    int err = 0;
+    if (hipMemcpy(&err, pl->fq[w].ctr, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess || err != 0) return true;
+  }
+  return false;
+}
+
 int copy_out(Plan* pl, void* host_out, size_t bytes, const void* dev) {
   if (!host_out) return DH_SUCCESS;
   if (hipStreamSynchronize(pl->last_stream) != hipSuccess) return DH_ERR_ERROR;
@@ -786,6 +827,7 @@ int dh_plan_check(const dh_params* p, int max_batch, dh_plan_info* info) {
     info->path = g.spec ? DH_PATH_SPECTRAL : DH_PATH_FIELD;
     info->field_w = g.fx; info->field_h = g.fy;
     info->field_pitch_x = g.fpx; info->field_pitch_y = g.fpy;
+    info->fused = fused_enabled(g, p) ? 1 : 0;
   }
   return DH_SUCCESS;
 }
@@ -853,6 +895,19 @@ int dh_plan(const dh_params* p, int max_batch, size_t hbm_budget, dh_handle* out
     return e;
   }
   for (int w = 0; w < pl->nws; ++w) fill_kargs(pl, w);
+  pl->fused = fused_enabled(pl->g, &pl->params);
+  if (pl->fused) {
+    const int nq = dh::fused_queues();
+    if (nq < 1) {
+      release(pl);
+      return DH_ERR_ERROR;
+    }
+    unsigned spin = 1u << 22;          // polls (a few seconds) before a launch gives up
+    if (const char* env = std::getenv("DH_FUSED_SPIN")) spin = (unsigned)std::strtoul(env, nullptr, 10);
+    for (int w = 0; w < pl->nws; ++w)
+      pl->fq[w] = dh::FusedQ{(int*)(pl->mem + pl->L.fctr[w]), (float2*)(pl->mem + pl->L.fslot[w]),
+                             std::min(nq, kFusedQueues), fused_slots(pl->g), spin};
+  }
   if (pl->nws > 1) {
     bool ok = hipEventCreateWithFlags(&pl->fork, hipEventDisableTiming) == hipSuccess;
     for (int w = 0; w < pl->nws && ok; ++w)
@@ -871,14 +926,21 @@ int dh_plan(const dh_params* p, int max_batch, size_t hbm_budget, dh_handle* out
 
 namespace {
 
-// the path over frames [b0, b0 + nb) with arguments a on stream st
-bool launch_path(Plan* pl, const dh::KArgs& a, const void* frames, int u16, int b0, int nb, hipStream_t st) {
-  bool ok = timed_event(pl, st, DH_STAGE_FFT, true) == hipSuccess &&
-            dh::launch_row(a, frames, u16, b0, nb, st) == hipSuccess &&
-            timed_event(pl, st, DH_STAGE_FFT, false) == hipSuccess &&
-            timed_event(pl, st, DH_STAGE_CROP, true) == hipSuccess &&
-            (pl->g.spec ? dh::launch_cspec(a, b0, nb, st) : dh::launch_col(a, b0, nb, st)) == hipSuccess &&
-            timed_event(pl, st, DH_STAGE_CROP, false) == hipSuccess;
+// the path over frames [b0, b0 + nb) with arguments a on stream st, in
+// workspace w (fused: row and column passes in one launch, timed as the FFT stage)
+bool launch_path(Plan* pl, const dh::KArgs& a, const void* frames, int u16, int b0, int nb, hipStream_t st, int w) {
+  bool ok;
+  if (pl->fused)
+    ok = timed_event(pl, st, DH_STAGE_FFT, true) == hipSuccess &&
+         dh::launch_fused(a, frames, u16, b0, nb, pl->fq[w], st) == hipSuccess &&
+         timed_event(pl, st, DH_STAGE_FFT, false) == hipSuccess;
+  else
+    ok = timed_event(pl, st, DH_STAGE_FFT, true) == hipSuccess &&
+         dh::launch_row(a, frames, u16, b0, nb, st) == hipSuccess &&
+         timed_event(pl, st, DH_STAGE_FFT, false) == hipSuccess &&
+         timed_event(pl, st, DH_STAGE_CROP, true) == hipSuccess &&
+         (pl->g.spec ? dh::launch_cspec(a, b0, nb, st) : dh::launch_col(a, b0, nb, st)) == hipSuccess &&
+         timed_event(pl, st, DH_STAGE_CROP, false) == hipSuccess;
   if (ok && !pl->g.spec && (a.G > 0 || a.fields))
     ok = timed_event(pl, st, DH_STAGE_FIELD, true) == hipSuccess && dh::launch_fld(a, b0, nb, st) == hipSuccess &&
          timed_event(pl, st, DH_STAGE_FIELD, false) == hipSuccess;
@@ -939,7 +1001,7 @@ int run_segments(Plan* pl, const void* frames, const std::vector<Seg>& segs, hip
           }
         }
       }
-      if (!launch_path(pl, a, frames, u16, b0, nb, nws > 1 ? pl->str[w] : s)) return DH_ERR_ERROR;
+      if (!launch_path(pl, a, frames, u16, b0, nb, nws > 1 ? pl->str[w] : s, w)) return DH_ERR_ERROR;
     }
   }
   if (nws > 1) {
@@ -1085,7 +1147,9 @@ int dh_mode_coefs(dh_handle h, dh_c64* host_out, const dh_c64** dev_out, int* ba
   if (dev_out) *dev_out = nm > 0 ? (const dh_c64*)src : nullptr;
   if (nm == 0) return set_err(pl, DH_SUCCESS);
   const size_t bytes = (size_t)pl->last_batch * pl->params.pol_count * nm * sizeof(dh_c64);
-  return set_err(pl, copy_out(pl, host_out, bytes, src));
+  const int e = copy_out(pl, host_out, bytes, src);
+  if (e != DH_SUCCESS || !host_out) return set_err(pl, e);
+  return set_err(pl, fused_failed(pl) ? DH_ERR_ERROR : DH_SUCCESS);
 }
 
 // the plan's field buffer (mode 1: written by the kernels; mode 0: by the export)
@@ -1264,7 +1328,13 @@ int dh_get_plan_info(dh_handle h, dh_plan_info* out) {
   Plan* pl = get(h);
   if (!pl) return DH_ERR_INVALIDHANDLE;
   if (!out) return set_err(pl, DH_ERR_NULLPOINTER);
-  return dh_plan_check(&pl->params, pl->max_batch, out);
+  const int e = dh_plan_check(&pl->params, pl->max_batch, out);
+  if (e != DH_SUCCESS) return set_err(pl, e);
+  // what the plan was built with (the environment may have changed since)
+  out->chunk = pl->chunk;
+  out->device_bytes = pl->L.total;
+  out->fused = pl->fused ? 1 : 0;
+  return set_err(pl, DH_SUCCESS);
 }
 
 int dh_set_stage_timing(dh_handle h, int enabled) {

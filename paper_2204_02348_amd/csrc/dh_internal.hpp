@@ -147,6 +147,26 @@ hipError_t launch_m0y(const M0Args& m, int nb, hipStream_t s);
 hipError_t launch_m0x(const M0Args& m, int nb, hipStream_t s);
 // fields to int16 (re, im) with one FP32 scale per field: n fields of len values
 hipError_t launch_q16(const float2* fields, int n, long long len, short* re, short* im, float* scale, hipStream_t s);
+// Fused row + column launch (spectral path): one persistent kernel whose
+// workgroups take tasks from per-XCD queues. Pol-frame q of the launch belongs
+// to queue q mod nqueue; its row-pass spectrum goes to slot (q / nqueue) mod S
+// of that queue, so that the row tasks that write it and the column tasks that
+// read it run on one XCD and the spectrum stays in that XCD's L2.
+struct FusedQ {
+  int* ctr;          // [1] error flag, [nqueue] task counters, [nq] rows done, [nq] columns done
+  float2* t1;        // [nqueue][S] slots of one pol-frame's row-pass spectrum (bx * ny)
+  int nqueue, S;     // queues, slots per queue
+  unsigned spin;     // polls of a dependency before the launch gives up
+};
+// queues to use on the current device: the XCD count read from the hardware
+// (1 where it cannot be read consistently); -1 on error
+int fused_queues();
+bool fused_supported(int nx, int ny, int wy, int gp, int u16);
+// counters zeroed, then the fused kernel over frames [b0, b0 + nb)
+hipError_t launch_fused(const KArgs& a, const void* frames, int u16, int b0, int nb, const FusedQ& f,
+                        hipStream_t s);
+size_t fused_counter_ints(int nqueue, int nq);
+
 // basis transform of n coefficient vectors (frame x pol, rows of nin values,
 // the first nused of them taken): out[e][k] = sum_{i < cnt} tt[off + i stride]
 // in[e][first + i] with (first, cnt, off, stride) = rng[k], for the raw and

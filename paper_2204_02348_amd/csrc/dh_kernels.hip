@@ -18,6 +18,11 @@
 // Layouts: frames [b][frame_h][frame_w] row-major (x fastest); spectra and
 // fields complex64 interleaved; every intermediate row-major with the
 // contiguous axis the one the next kernel reads along.
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <vector>
+
 #include "dh_fft.hpp"
 #include "dh_internal.hpp"
 
@@ -81,6 +86,10 @@ constexpr bool kT1Nt = !DH_T1_CACHED;
 __device__ __forceinline__ float2 buf_ld_t1(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
   return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, kT1Nt ? 2 : 0));
 }
+template <int AUX>
+__device__ __forceinline__ float2 buf_ld_aux(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, AUX));
+}
 
 // t1 element (box column j, row y) of one frame and pol: tiles of 16 rows,
 // [y / 16][j][y % 16], so that a row-pass block's writes are contiguous
@@ -108,11 +117,12 @@ __device__ __forceinline__ void stage_twiddles(float2* dst, const float2* __rest
 // LDS stores: the loads are issued ahead of a kernel's main operand loads and
 // the stores wait only for them, so the table costs one memory latency that
 // overlaps the main loads. Entries [n, N) get `fill`; n >= 1.
-template <typename T, int N, int TPB>
+template <typename T, int N, int TPB, int NTH = TPB>
 struct Staged {
   static constexpr int IT = (N + TPB - 1) / TPB;
   T v[IT];
   __device__ __forceinline__ void load(const T* __restrict__ src, int n, int tid) {
+    if (NTH != TPB && tid >= TPB) return;
 #pragma unroll
     for (int i = 0; i < IT; ++i) {
       const int e = tid + i * TPB;
@@ -120,6 +130,7 @@ struct Staged {
     }
   }
   __device__ __forceinline__ void store(T* dst, int n, T fill, int tid) const {
+    if (NTH != TPB && tid >= TPB) return;
 #pragma unroll
     for (int i = 0; i < IT; ++i) {
       const int e = tid + i * TPB;
@@ -135,22 +146,32 @@ struct Staged {
 // operands straight from the frame; all tiles' loads are issued up front.
 // t1 at (box column j, row y) = sum_x I[y][x] e^{-2 pi i k x / NX},
 // k = k0 + j (mod NX), stored at t1_at(j, y)
-template <int NX, int TR, typename TIn, int TT>
-__global__ void __launch_bounds__(TR * NX / FftPlan<NX>::R0) k_row(KArgs A, const TIn* __restrict__ frames, int b0) {
+template <int NX, int TR> struct RowShape {
   using L = Lds<NX>;
-  using Q = Pass1<NX, TR, TR * NX / FftPlan<NX>::R0>;
-  constexpr int TPB = TR * NX / FftPlan<NX>::R0;
-  static_assert(Q::IT == 1, "one first-pass butterfly per thread");
+  static constexpr int TPB = TR * NX / FftPlan<NX>::R0;
   // 2048-point rows: the twiddles (16 KB) are read through the caches, so
   // that two 512-thread workgroups fit on a CU
-  constexpr bool TWG = NX >= 2048;
-  __shared__ float2 buf[TR * L::STRIDE];
-  __shared__ float2 tws[TWG ? 1 : twn<NX>()];
-  const int tid = threadIdx.x;
-  const int p = blockIdx.y;
-  const int bl = blockIdx.z;                 // frame within the chunk
+  static constexpr bool TWG = NX >= 2048;
+  static constexpr int BUF = TR * L::STRIDE;            // float2 of LDS: the transforms
+  static constexpr int TWS = TWG ? 1 : twn<NX>();       // float2 of LDS: the twiddles
+};
+
+// The row pass of row-tile group `tg` of frame `bl` (within the launch, frames
+// from b0), pol p, into `out` (that frame and pol's t1); buf and tws: LDS of
+// RowShape's sizes. A workgroup of NTH >= TPB threads runs it with the
+// threads from TPB on idle.
+template <int NX, int TR, typename TIn, int TT, int NTH>
+__device__ __forceinline__ void row_tiles(const KArgs& A, const TIn* __restrict__ frames, int b0, int tg, int p,
+                                          int bl, float2* __restrict__ out, float2* buf, float2* tws, int tid) {
+  using RS = RowShape<NX, TR>;
+  using L = typename RS::L;
+  constexpr int TPB = RS::TPB;
+  using Q = Pass1<NX, TR, TPB>;
+  static_assert(Q::IT == 1, "one first-pass butterfly per thread");
+  constexpr bool TWG = RS::TWG;
+  const bool act = NTH == TPB || tid < TPB;
   const PolTab& P = A.pol[p];
-  Staged<float2, TWG ? 1 : twn<NX>(), TPB> stw;
+  Staged<float2, TWG ? 1 : twn<NX>(), TPB, NTH> stw;
   if constexpr (!TWG) stw.load(A.tw_nx, twn<NX>(), tid);
   const TIn* fr = A.fptr ? static_cast<const TIn*>(A.fptr[b0 + bl]) : frames + (size_t)(b0 + bl) * A.frame_h * A.frame_w;
   const gptr<TIn> win = as_global(fr) + ((size_t)P.y0 * A.frame_w + P.x0);
@@ -158,11 +179,11 @@ __global__ void __launch_bounds__(TR * NX / FftPlan<NX>::R0) k_row(KArgs A, cons
   // in flight while the earlier tiles' transforms run. A tile past the last
   // row (odd tile count) loads row pair 0 instead and stores nothing.
   float2 v[TT][Q::R0];
-  {
+  if (act) {
     const int t = tid / Q::NB, b = tid % Q::NB;
 #pragma unroll
     for (int tt = 0; tt < TT; ++tt) {
-      const int y0 = (blockIdx.x * TT + tt) * (2 * TR);
+      const int y0 = (tg * TT + tt) * (2 * TR);
       const int y = (y0 < A.ny ? y0 : 0) + 2 * t;      // ny is a multiple of 2 TR
       const gptr<TIn> r0 = win + ((size_t)y * A.frame_w + b);
       const gptr<TIn> r1 = r0 + A.frame_w;
@@ -174,41 +195,52 @@ __global__ void __launch_bounds__(TR * NX / FftPlan<NX>::R0) k_row(KArgs A, cons
       if constexpr (!TWG) if (tt == 0) stw.store(tws, twn<NX>(), make_float2(0.f, 0.f), tid);
     }
   }
-  float2* out = A.t1 + (size_t)(bl * A.npol + p) * A.bx * A.ny;
 #pragma unroll
   for (int tt = 0; tt < TT; ++tt) {
-    const int ybase = (blockIdx.x * TT + tt) * (2 * TR);
+    const int ybase = (tg * TT + tt) * (2 * TR);
     if (tt > 0) __syncthreads();           // the previous tile's split has read buf
-    fft_pass1_regs<NX, TR, L::STRIDE, TPB>(v + tt, buf, tid);
+    fft_pass1_regs<NX, TR, L::STRIDE, TPB, NTH>(v + tt, buf, tid);
     if constexpr (TWG)
-      fft_rest<NX, TR, L::STRIDE, TPB>(buf, as_global(A.tw_nx), tid);
+      fft_rest<NX, TR, L::STRIDE, TPB, NTH>(buf, as_global(A.tw_nx), tid);
     else
-      fft_rest<NX, TR, L::STRIDE, TPB>(buf, static_cast<const float2*>(tws), tid);
+      fft_rest<NX, TR, L::STRIDE, TPB, NTH>(buf, static_cast<const float2*>(tws), tid);
     // two-for-one split at the kept bins: both rows of a pair from Z[k], Z[NX-k]
-    for (int e = tid; e < TR * A.bx; e += TPB) {
-      const int t = e % TR, j = e / TR;
-      const int y = ybase + 2 * t;
-      if (y >= A.ny) continue;
-      // bins are periodic: a tilt of any size reaches its window through k mod NX
-      const int k = ((P.k0 + j) % NX + NX) % NX;
-      const int km = (k == 0) ? 0 : NX - k;
-      const float2* tb = buf + t * L::STRIDE;
-      const float2 z1 = tb[L::at(k)];
-      const float2 z2 = conjf2(tb[L::at(km)]);
-      const float2 d = csub(z1, z2);
-      const float4 x = make_float4(0.5f * (z1.x + z2.x), 0.5f * (z1.y + z2.y), 0.5f * d.y, -0.5f * d.x);
-      float2* o = out + t1_at(j, y, A.bx);
-      // rows y, y+1 (ny is even). A workgroup writes 2 TR rows of each
-      // 16-row tile per phase: from 64 B on, non-temporal stores are faster;
-      // the 32 B pieces of TR = 2 need the cache to merge them into lines
-      if constexpr (2 * TR >= 8 && kT1Nt) {
-        const floatx4 t4 = {x.x, x.y, x.z, x.w};
-        __builtin_nontemporal_store(t4, reinterpret_cast<floatx4*>(o));
-      } else {
-        *reinterpret_cast<float4*>(o) = x;
+    if (act) {
+      for (int e = tid; e < TR * A.bx; e += TPB) {
+        const int t = e % TR, j = e / TR;
+        const int y = ybase + 2 * t;
+        if (y >= A.ny) continue;
+        // bins are periodic: a tilt of any size reaches its window through k mod NX
+        const int k = ((P.k0 + j) % NX + NX) % NX;
+        const int km = (k == 0) ? 0 : NX - k;
+        const float2* tb = buf + t * L::STRIDE;
+        const float2 z1 = tb[L::at(k)];
+        const float2 z2 = conjf2(tb[L::at(km)]);
+        const float2 d = csub(z1, z2);
+        const float4 x = make_float4(0.5f * (z1.x + z2.x), 0.5f * (z1.y + z2.y), 0.5f * d.y, -0.5f * d.x);
+        float2* o = out + t1_at(j, y, A.bx);
+        // rows y, y+1 (ny is even). A workgroup writes 2 TR rows of each
+        // 16-row tile per phase: from 64 B on, non-temporal stores are faster;
+        // the 32 B pieces of TR = 2 need the cache to merge them into lines
+        if constexpr (2 * TR >= 8 && kT1Nt && NTH == TPB) {
+          const floatx4 t4 = {x.x, x.y, x.z, x.w};
+          __builtin_nontemporal_store(t4, reinterpret_cast<floatx4*>(o));
+        } else {
+          *reinterpret_cast<float4*>(o) = x;
+        }
       }
     }
   }
+}
+
+template <int NX, int TR, typename TIn, int TT>
+__global__ void __launch_bounds__(TR * NX / FftPlan<NX>::R0) k_row(KArgs A, const TIn* __restrict__ frames, int b0) {
+  using RS = RowShape<NX, TR>;
+  __shared__ float2 buf[RS::BUF];
+  __shared__ float2 tws[RS::TWS];
+  const int p = blockIdx.y, bl = blockIdx.z;
+  float2* out = A.t1 + (size_t)(bl * A.npol + p) * A.bx * A.ny;
+  row_tiles<NX, TR, TIn, TT, RS::TPB>(A, frames, b0, blockIdx.x, p, bl, out, buf, tws, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -371,38 +403,46 @@ __global__ void __launch_bounds__(kTPB) k_col(KArgs A, int b0) {
 // of NT tiles over the same window in LDS, each chunk's Q columns collected in
 // LDS before the final product (tables of gp columns; MC = false: gp = 16 NT).
 template <int NY, int WY, int CG, int NT, bool MC>
-__global__ void __launch_bounds__(kTPB) k_cspec(KArgs A, int b0) {
-  using LN = Lds<NY>;
-  using Q = Pass1<NY, CG, kTPB>;
-  constexpr int ST = LN::STRIDE;
-  constexpr int MT = (2 * CG + 15) / 16;          // A-row tiles
-  constexpr int WYP = (WY + 15) / 16 * 16;
-  constexpr int KSW = WYP / 16;                    // K steps per wave, at most
-  constexpr int GP = 16 * NT;                      // mode columns per chunk
-  constexpr int GPM = MC ? kMaxGp : GP;            // mode columns held in LDS, at most
-  constexpr int NRED = 4 * MT * NT * 2 * 256;      // floats: the waves' MFMA results
-  constexpr int NQ = CG * GP;                      // float2: one chunk of Q
+struct CspecShape {
+  static constexpr int ST = Lds<NY>::STRIDE;
+  static constexpr int MT = (2 * CG + 15) / 16;          // A-row tiles
+  static constexpr int WYP = (WY + 15) / 16 * 16;
+  static constexpr int KSW = WYP / 16;                    // K steps per wave, at most
+  static constexpr int GP = 16 * NT;                      // mode columns per chunk
+  static constexpr int GPM = MC ? kMaxGp : GP;            // mode columns held in LDS, at most
+  static constexpr int NRED = 4 * MT * NT * 2 * 256;      // floats: the waves' MFMA results
+  static constexpr int NQ = CG * GP;                      // float2: one chunk of Q
   // with several chunks the window stays in buf until the last one
-  constexpr bool IN_BUF = !MC && NRED * 4 + NQ * 8 <= CG * ST * 8;
-  static_assert(KSW * NT <= 96, "B operands are held in registers");
+  static constexpr bool IN_BUF = !MC && NRED * 4 + NQ * 8 <= CG * ST * 8;
   // From 1024 rows on, the twiddles are read through the caches instead of LDS
   // wherever that lets one more workgroup onto a CU (160 KB of LDS each); at
   // 512 rows the extra workgroup measured slower than the LDS reads it saves.
-  constexpr int LDS_REST = CG * ST * 8 + WYP * 8 + CG * GPM * 8 + 16 + (IN_BUF ? 8 : (NRED / 2 + CG * GPM) * 8);
-  constexpr int LDS_CU = 160 * 1024;
-  constexpr bool TWG = NY >= 1024 && LDS_CU / LDS_REST > LDS_CU / (LDS_REST + twn<NY>() * 8);
-  __shared__ float2 buf[CG * ST];
-  __shared__ float2 twy[TWG ? 1 : twn<NY>()];
-  __shared__ int2 s_mrow[WYP];
-  __shared__ float2 s_x[CG * GPM];                 // xs rows of the block's columns
-  __shared__ float s_pw[4];
-  __shared__ float2 s_spill[IN_BUF ? 1 : (NRED / 2 + CG * GPM)];
-  const int tid = threadIdx.x;
+  static constexpr int LDS_REST =
+      CG * ST * 8 + WYP * 8 + CG * GPM * 8 + 16 + (IN_BUF ? 8 : (NRED / 2 + CG * GPM) * 8);
+  static constexpr int LDS_CU = 160 * 1024;
+  static constexpr bool TWG = NY >= 1024 && LDS_CU / LDS_REST > LDS_CU / (LDS_REST + twn<NY>() * 8);
+  // LDS of the pass, float2 (int2 for the mask rows, float for the powers)
+  static constexpr int BUF = CG * ST, TWY = TWG ? 1 : twn<NY>(), MROW = WYP, SX = CG * GPM;
+  static constexpr int SPILL = IN_BUF ? 1 : (NRED / 2 + CG * GPM);
+};
+
+// The spectral column pass of box-column block cb of frame bl (within the
+// launch, frames from b0), pol p, from `in` (that frame and pol's t1; loads
+// with cache policy T1AUX); LDS arrays of CspecShape's sizes.
+template <int NY, int WY, int CG, int NT, bool MC, int T1AUX>
+__device__ __forceinline__ void cspec_block(const KArgs& A, int b0, int cb, int p, int bl, const float2* in,
+                                            float2* buf, float2* twy, int2* s_mrow, float2* s_x, float* s_pw,
+                                            float2* s_spill, int tid) {
+  using SH = CspecShape<NY, WY, CG, NT, MC>;
+  using LN = Lds<NY>;
+  using Q = Pass1<NY, CG, kTPB>;
+  constexpr int ST = SH::ST, MT = SH::MT, WYP = SH::WYP, KSW = SH::KSW, GP = SH::GP, GPM = SH::GPM;
+  constexpr int NRED = SH::NRED, NQ = SH::NQ;
+  constexpr bool IN_BUF = SH::IN_BUF, TWG = SH::TWG;
+  static_assert(KSW * NT <= 96, "B operands are held in registers");
   const int lane = tid & 63, wv = tid >> 6;
-  const int p = blockIdx.y;
-  const int bl = blockIdx.z;
   const PolTab& P = A.pol[p];
-  const int jc0 = blockIdx.x * CG;
+  const int jc0 = cb * CG;
   const int gpt = MC ? A.gp : GP;                  // table row stride (mode columns)
   const int nch = MC ? gpt / GP : 1;               // chunks of NT mode tiles
   // tables first: their loads are in flight with the column loads
@@ -428,7 +468,6 @@ __global__ void __launch_bounds__(kTPB) k_cspec(KArgs A, int b0) {
       bre[t][nt] = y.x;
       bim[t][nt] = y.y;
     }
-  const float2* in = A.t1 + ((size_t)(bl * A.npol + p) * A.bx) * NY;
   {
     float2 v[Q::IT][Q::R0];
     // element (j, b + r NB) of the tiled t1 at byte t1_at * 8; where NB is a
@@ -444,10 +483,10 @@ __global__ void __launch_bounds__(kTPB) k_cspec(KArgs A, int b0) {
         const int voff = ((b >> 4) * A.bx + j) * 128 + (b & 15) * 8;
         const int rstride = (Q::NB / 16) * A.bx * 128;
 #pragma unroll
-        for (int r = 0; r < Q::R0; ++r) v[it][r] = buf_ld_t1(rt, voff, r * rstride);
+        for (int r = 0; r < Q::R0; ++r) v[it][r] = buf_ld_aux<T1AUX>(rt, voff, r * rstride);
       } else {
 #pragma unroll
-        for (int r = 0; r < Q::R0; ++r) v[it][r] = buf_ld_t1(rt, (int)t1_at(j, b + r * Q::NB, A.bx) * 8, 0);
+        for (int r = 0; r < Q::R0; ++r) v[it][r] = buf_ld_aux<T1AUX>(rt, (int)t1_at(j, b + r * Q::NB, A.bx) * 8, 0);
       }
     }
     if constexpr (!TWG) stwy.store(twy, twn<NY>(), make_float2(0.f, 0.f), tid);
@@ -588,7 +627,7 @@ __global__ void __launch_bounds__(kTPB) k_cspec(KArgs A, int b0) {
     __syncthreads();
   }
   const int pstride = A.nmodes + 1;
-  float2* part = A.partial + ((size_t)(bl * A.nblk + blockIdx.x) * A.npol + p) * pstride;
+  float2* part = A.partial + ((size_t)(bl * A.nblk + cb) * A.npol + p) * pstride;
   if (tid == 0)
     part[A.nmodes] = make_float2(A.capt ? (((s_pw[0] + s_pw[1]) + s_pw[2]) + s_pw[3]) * A.spow : 0.f, 0.f);
   for (int e = tid; e < A.nmodes; e += kTPB) {
@@ -598,6 +637,171 @@ __global__ void __launch_bounds__(kTPB) k_cspec(KArgs A, int b0) {
     for (int j = 0; j < CG; ++j) acc = cadd(acc, cmul(s_x[j * gpt + mn.x], s_q[j * gpt + mn.y]));
     part[e] = acc;
   }
+}
+
+template <int NY, int WY, int CG, int NT, bool MC>
+__global__ void __launch_bounds__(kTPB) k_cspec(KArgs A, int b0) {
+  using SH = CspecShape<NY, WY, CG, NT, MC>;
+  __shared__ float2 buf[SH::BUF];
+  __shared__ float2 twy[SH::TWY];
+  __shared__ int2 s_mrow[SH::MROW];
+  __shared__ float2 s_x[SH::SX];                 // xs rows of the block's columns
+  __shared__ float s_pw[4];
+  __shared__ float2 s_spill[SH::SPILL];
+  const int p = blockIdx.y, bl = blockIdx.z;
+  const float2* in = A.t1 + ((size_t)(bl * A.npol + p) * A.bx) * NY;
+  cspec_block<NY, WY, CG, NT, MC, kT1Nt ? 2 : 0>(A, b0, blockIdx.x, p, bl, in, buf, twy, s_mrow, s_x, s_pw, s_spill,
+                                                 threadIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// k_fused (spectral path): the row pass and the column pass of a launch in one
+// persistent kernel, so that a pol-frame's row-pass spectrum (bx x ny complex,
+// 0.4 MB at 640x512) goes from the row tasks that write it to the column tasks
+// that read it through the L2 of one XCD instead of through HBM.
+//
+// Tasks: per pol-frame, R row tasks (TT tiles of 2 TR rows each, as k_row)
+// and C column tasks (CG box columns each, as k_cspec). Pol-frame q belongs to
+// queue q mod nqueue (the XCD count), its spectrum to slot (q / nqueue) mod S
+// of that queue. Each queue hands out its tasks in the order
+//   R(0) | R(1) C(0) | R(2) C(1) | ... | C(last)
+// (R(i), C(i): the row and column tasks of the queue's i-th pol-frame), so
+// the column tasks of a pol-frame follow its row tasks by one pol-frame. A
+// workgroup takes tasks from the queue of its own XCD first, then from the
+// others (a queue whose XCD has no workgroups is still drained).
+//
+// Waits: a column task waits until its pol-frame's R row tasks are done; a
+// row task of the i-th pol-frame (i >= S) waits until the C column tasks of
+// the slot's previous pol-frame (i - S) are done. Both wait only on tasks
+// handed out earlier from the same queue, i.e. held by running workgroups,
+// so every wait ends. Each wait gives up after F.spin polls and then sets the
+// error flag, which makes every later wait give up at once (the host reports
+// the launch as failed; spin = 0 gives up at the first wait). Hand-over: each thread's stores, an agent-scope
+// release fence, a barrier, then the counter increment; the reader polls,
+// meets a barrier, then an agent-scope acquire fence before its loads.
+constexpr unsigned kXccIdReg = 20u | (0u << 6) | (3u << 11);    // hwreg(HW_REG_XCC_ID, 0, 4)
+#ifndef DH_FUSED_PROTO
+#define DH_FUSED_PROTO 0
+#endif
+#ifndef DH_FUSED_T1AUX
+#define DH_FUSED_T1AUX 0
+#endif
+
+__device__ __forceinline__ bool dep_wait(int* c, int target, int* err, unsigned spin) {
+  if (spin == 0) {                   // a launch told to give up at its first wait
+    __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return false;
+  }
+  unsigned n = 0;
+  for (;;) {
+    if (__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) return true;
+    if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || ++n > spin) {
+      __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(4);
+  }
+}
+
+template <int NX, int TR, typename TIn, int TT, int NY, int WY, int CG, int NT, bool MC>
+__global__ void __launch_bounds__(kTPB) k_fused(KArgs A, const TIn* __restrict__ frames, int b0, int nq, FusedQ F) {
+  using RS = RowShape<NX, TR>;
+  using SH = CspecShape<NY, WY, CG, NT, MC>;
+  static_assert(RS::TPB <= kTPB, "the row pass fits the workgroup");
+  // LDS: the row pass's arrays and the column pass's, overlaid (float2 units)
+  constexpr int O_TWY = SH::BUF, O_MROW = O_TWY + SH::TWY, O_SX = O_MROW + SH::MROW;
+  constexpr int O_SPILL = O_SX + SH::SX, O_PW = O_SPILL + SH::SPILL;
+  constexpr int COLN = O_PW + 2, ROWN = RS::BUF + RS::TWS;
+  __shared__ float2 lds[COLN > ROWN ? COLN : ROWN];
+  __shared__ int s_task, s_ok;
+  const int tid = threadIdx.x;
+  constexpr int RT = 2 * TR * TT;                        // rows per row task
+  const int R = (A.ny + RT - 1) / RT, C = (A.bx + CG - 1) / CG, per = R + C;
+  int* err = F.ctr;
+  int* next = F.ctr + 1;
+  int* rows = next + F.nqueue;
+  int* cols = rows + nq;
+  const size_t slot_elems = (size_t)A.bx * A.ny;
+  const int home = F.nqueue > 1 ? (int)(__builtin_amdgcn_s_getreg(kXccIdReg) % (unsigned)F.nqueue) : 0;
+  // Control values shared through LDS (the task, a wait's outcome) are read
+  // back as scalars, so that the compiler sees every branch on them as
+  // uniform; thread 0's own work (claims, counters, waits) sits in plain
+  // if-regions that end at a barrier inside the loop body. (With the claim at
+  // the top of the loop, the lanes that skip it reach the loop's barrier by an
+  // edge of their own, and the compiler made that barrier the header of an
+  // inner loop that repeats the task without the next claim.)
+  for (int k = 0; k < (DH_FUSED_PROTO == 2 ? 1 : F.nqueue); ++k) {
+    const int qid = (home + k) % F.nqueue;               // own queue first, then the others
+    const int nqx = qid < nq ? (nq - qid + F.nqueue - 1) / F.nqueue : 0;
+    const int ntask = nqx * per;
+    if (tid == 0) s_task = __hip_atomic_fetch_add(next + qid, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    int t = __builtin_amdgcn_readfirstlane(s_task);
+    while (t < ntask) {
+      bool row;
+      int i, sub;
+      if (t < R) {
+        row = true; i = 0; sub = t;
+      } else {
+        const int u = t - R, kk = u / per + 1, r = u - (kk - 1) * per;
+        if (kk < nqx) {
+          row = r < R;
+          i = row ? kk : kk - 1;
+          sub = row ? r : r - R;
+        } else {
+          row = false; i = nqx - 1; sub = r;
+        }
+      }
+      const int q = i * F.nqueue + qid;                  // pol-frame of the launch
+      const int bl = q / A.npol, p = q - bl * A.npol;
+      float2* slot = F.t1 + ((size_t)qid * F.S + i % F.S) * slot_elems;
+      if (tid == 0)
+        s_ok = row ? (i < F.S || dep_wait(cols + (i - F.S) * F.nqueue + qid, C, err, F.spin))
+                   : dep_wait(rows + q, R, err, F.spin);
+      __syncthreads();
+      const int ok = __builtin_amdgcn_readfirstlane(s_ok);
+      if (ok && row) {
+        row_tiles<NX, TR, TIn, TT, kTPB>(A, frames, b0, sub, p, bl, slot, lds, lds + RS::BUF, tid);
+#if DH_FUSED_PROTO == 0
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+#else
+        __builtin_amdgcn_s_waitcnt(0);                   // this wave's stores are done
+#endif
+      } else if (ok) {
+#if DH_FUSED_PROTO == 0
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+#elif DH_FUSED_PROTO == 1
+        if (tid < 64) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __syncthreads();
+#endif
+        cspec_block<NY, WY, CG, NT, MC, DH_FUSED_T1AUX>(A, b0, sub, p, bl, slot, lds, lds + O_TWY,
+                                           reinterpret_cast<int2*>(lds + O_MROW), lds + O_SX,
+                                           reinterpret_cast<float*>(lds + O_PW), lds + O_SPILL, tid);
+      }
+      // every wave's stores are fenced and its loads of the slot consumed:
+      // thread 0 marks the task done and takes the next one
+      __syncthreads();
+      if (tid == 0) {
+#if DH_FUSED_PROTO == 1
+        if (ok && row) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+#endif
+        if (ok) __hip_atomic_fetch_add(row ? rows + q : cols + q, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_task = __hip_atomic_fetch_add(next + qid, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      __syncthreads();
+      t = __builtin_amdgcn_readfirstlane(s_task);
+    }
+    __syncthreads();                                     // s_task is read before the next queue's claim
+  }
+}
+
+__global__ void k_zero_int(int* p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
+}
+
+// the XCD each of a grid of workgroups runs on
+__global__ void k_xcc_probe(int* out) {
+  if (threadIdx.x == 0) out[blockIdx.x] = (int)__builtin_amdgcn_s_getreg(kXccIdReg);
 }
 
 // ---------------------------------------------------------------------------
@@ -1319,6 +1523,102 @@ hipError_t launch_gather(const KArgs& a, const float2* spec, int bxe, int nrow, 
 }
 
 
+
+size_t fused_counter_ints(int nqueue, int nq) { return (size_t)nqueue + 2 * (size_t)nq + 1; }
+
+#ifndef DH_FUSED_TT
+#define DH_FUSED_TT 1
+#endif
+// fused instantiations: (row length, column length, IFFT rows, mode tiles), f32 frames
+#define DH_FUSED_SHAPES(X) X(320, 512, 176, 1)
+
+bool fused_supported(int nx, int ny, int wy, int gp, int u16) {
+  if (u16) return false;
+#define X(N, M, W, T) if (nx == N && ny == M && wy == W && gp == 16 * T) return true;
+  DH_FUSED_SHAPES(X)
+#undef X
+  return false;
+}
+
+int fused_queues() {
+  // workgroups are dealt to the XCDs in turn: a probe grid of many workgroups
+  // reads the XCD id of each; the queues are those ids if they are exactly
+  // 0 .. n-1 (n <= 16), else one queue
+  static std::mutex mu;
+  static std::map<int, int> cache;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return -1;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(dev);
+  if (it != cache.end()) return it->second;
+  constexpr int n = 4096;
+  int* d = nullptr;
+  std::vector<int> h(n, -1);
+  if (hipMalloc(&d, n * sizeof(int)) != hipSuccess) return -1;
+  hipLaunchKernelGGL(k_xcc_probe, dim3(n), dim3(64), 0, 0, d);
+  const bool ok = hipGetLastError() == hipSuccess && hipMemcpy(h.data(), d, n * sizeof(int), hipMemcpyDeviceToHost) ==
+                                                        hipSuccess;
+  (void)hipFree(d);
+  if (!ok) return -1;
+  int mx = -1;
+  bool seen[16] = {};
+  for (int v : h) {
+    if (v < 0 || v >= 16) {
+      mx = -2;
+      break;
+    }
+    seen[v] = true;
+    mx = std::max(mx, v);
+  }
+  int q = 1;
+  if (mx >= 0) {
+    q = mx + 1;
+    for (int v = 0; v <= mx; ++v)
+      if (!seen[v]) q = 1;
+  }
+  cache[dev] = q;
+  return q;
+}
+
+template <int NX, int NY, int WY, int NT>
+static hipError_t fused_nw(const KArgs& a, const float* frames, int b0, int nb, const FusedQ& f, hipStream_t s) {
+  constexpr int TR = row_tr<NX>();
+  constexpr int CG = cspec_cg<NY, NT>();
+  constexpr int TT = DH_FUSED_TT;
+  constexpr int RT = 2 * TR * TT;
+  const auto kern = k_fused<NX, TR, float, TT, NY, WY, CG, NT, false>;
+  // workgroups resident on the whole device (cached per device)
+  static int cap[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return hipErrorInvalidValue;
+  if (cap[dev] == 0) {
+    int per_cu = 0;
+    hipDeviceProp_t prop;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kTPB, 0) != hipSuccess ||
+        hipGetDeviceProperties(&prop, dev) != hipSuccess || per_cu < 1)
+      return hipErrorInvalidValue;
+    cap[dev] = per_cu * prop.multiProcessorCount;
+  }
+  const int nq = nb * a.npol;
+  const size_t nctr = fused_counter_ints(f.nqueue, nq);
+  hipLaunchKernelGGL(k_zero_int, dim3((unsigned)std::min<size_t>((nctr + 255) / 256, 1024)), dim3(256), 0, s, f.ctr,
+                     nctr);
+  const long tasks = (long)nq * ((a.ny + RT - 1) / RT + (a.bx + CG - 1) / CG);
+  const int grid = (int)std::min<long>(cap[dev], tasks);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kTPB), 0, s, a, frames, b0, nq, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_fused(const KArgs& a, const void* frames, int u16, int b0, int nb, const FusedQ& f,
+                        hipStream_t s) {
+  if (u16 || f.nqueue < 1 || f.S < 1) return hipErrorInvalidValue;
+#define X(N, M, W, T)                                                  \
+  if (a.nx == N && a.ny == M && a.wy == W && a.gp == 16 * T)           \
+    return fused_nw<N, M, W, T>(a, static_cast<const float*>(frames), b0, nb, f, s);
+  DH_FUSED_SHAPES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
 
 hipError_t launch_norm(const KArgs& a, int b0, int nb, hipStream_t s) {
   hipLaunchKernelGGL(k_norm, dim3(nb), dim3(kTPB), 0, s, a, b0);
