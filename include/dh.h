@@ -125,9 +125,9 @@ typedef struct dh_plan_info {
   int path;                   /* DH_PATH_FIELD or DH_PATH_SPECTRAL: the path the plan runs */
   int field_w, field_h;       /* field grid F: W in IFFT mode 1, N in mode 0 */
   double field_pitch_x, field_pitch_y;  /* its pitch N p / F, m (the camera pitch in mode 0) */
-  int fused;                  /* nonzero: the row and column passes run as one fused launch
-                                 (spectral path, shapes with a fused kernel, when the
-                                 environment sets DH_FUSED=1) */
+  int generic;                /* lengths run by the runtime-length kernels: bit 0 the row
+                                 pass (N_x), bit 1 the column pass and mode-0 export (N_y,
+                                 or an (N_y, W_y) pair without a compiled column kernel) */
 } dh_plan_info;
 
 /*

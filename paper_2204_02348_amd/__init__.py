@@ -94,7 +94,7 @@ class PlanInfo(C.Structure):
         ("pitch_x", C.c_double), ("pitch_y", C.c_double),
         ("device_bytes", C.c_size_t), ("chunk", C.c_int), ("path", C.c_int),
         ("field_w", C.c_int), ("field_h", C.c_int), ("field_pitch_x", C.c_double), ("field_pitch_y", C.c_double),
-        ("fused", C.c_int),
+        ("generic", C.c_int),
     ]
 
 

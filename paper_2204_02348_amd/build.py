@@ -22,7 +22,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
           # no packed FP32 instructions anywhere
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wno-unused-command-line-argument"]
-SOURCES = ["dh_kernels.hip", "dh_aux.hip", "dh_api.cpp"]
+SOURCES = ["dh_kernels.hip", "dh_aux.hip", "dh_generic.hip", "dh_api.cpp"]
 
 
 def _compile(src: str) -> str:

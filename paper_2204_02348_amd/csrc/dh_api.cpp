@@ -57,13 +57,14 @@ struct Geom {
   bool spec = false;     // the plan runs the spectral path (DH_PATH_SPECTRAL)
   int byp = 16;          // by rounded up to 16
   PolGeom pol[2];
+  dh::GenFft gx{}, gy{}; // row / column lengths the generic kernels run (np > 0)
 };
 
 // blocks with a coefficient partial per frame and pol: 16-row field blocks
 // (field path, also used by alignment) or column blocks (spectral path)
 int field_blocks(const Geom& g) { return g.wyp / 16; }
 int partial_blocks(const Geom& g) {
-  return g.spec ? std::max(field_blocks(g), dh::spectral_blocks(g.ny, g.bx, g.gp)) : field_blocks(g);
+  return g.spec ? std::max(field_blocks(g), dh::spectral_blocks(g.ny, g.wy, g.bx, g.gp)) : field_blocks(g);
 }
 
 bool inside(double u, double v, double ax, double ay, double rx, double ry) {
@@ -170,23 +171,30 @@ int derive(const dh_params* p, Geom* g) {
     const int e = derive_pol(p, g, q);
     if (e != DH_SUCCESS) return e;
   }
-  if (!dh::sizes_supported(nx, ny, g->wx, g->wy)) return DH_ERR_INVALIDDIMENSION;
   g->byp = (g->by + 15) / 16 * 16;
+  // Lengths without a compiled kernel run on the generic kernels: the row
+  // pass for N_x, the spectral column pass (and the mode-0 export) for N_y or
+  // an (N_y, W_y) pair without a compiled column kernel. The field path needs
+  // compiled kernels for every length.
+  g->gx = dh::GenFft{};
+  g->gy = dh::GenFft{};
+  if (!dh::fft_compiled(nx) && !dh::gen_plan(nx, &g->gx)) return DH_ERR_INVALIDDIMENSION;
   if (g->mode == 0) {
     // IFFT mode 0: the coefficients come from spectral tables built on the FFT
     // grid, the fields (on request) from the kept window by full-size inverse
     // FFTs; with G = 0 only the window and the fields are made
     if (p->path == DH_PATH_FIELD || p->precision != DH_PREC_FP32) return DH_ERR_INVALIDARGUMENT;
-    if (!dh::spectral_supported(ny, g->wy, g->gp)) return DH_ERR_INVALIDDIMENSION;
     g->spec = true;
-    return DH_SUCCESS;
+  } else {
+    const bool can_spec = p->precision == DH_PREC_FP32 && !p->keep_fields && g->G > 0;
+    if (p->path == DH_PATH_SPECTRAL && !can_spec) return DH_ERR_INVALIDARGUMENT;
+    g->spec = p->path == DH_PATH_SPECTRAL || (p->path == DH_PATH_AUTO && can_spec);
+    // the field path's overlap takes up to two mode tiles (G <= 32)
+    if (g->gp > dh::kMaxGpField && !g->spec) return DH_ERR_INVALIDARGUMENT;
+    if (!g->spec && !dh::sizes_supported(nx, ny, g->wx, g->wy)) return DH_ERR_INVALIDDIMENSION;
   }
-  const bool can_spec = p->precision == DH_PREC_FP32 && !p->keep_fields && g->G > 0 &&
-                        dh::spectral_supported(ny, g->wy, g->gp);
-  if (p->path == DH_PATH_SPECTRAL && !can_spec) return DH_ERR_INVALIDARGUMENT;
-  g->spec = p->path == DH_PATH_SPECTRAL || (p->path == DH_PATH_AUTO && can_spec);
-  // the field path's overlap takes up to two mode tiles (G <= 32)
-  if (g->gp > dh::kMaxGpField && !g->spec) return DH_ERR_INVALIDARGUMENT;
+  if (g->spec && !dh::spectral_supported(ny, g->wy, g->gp) && !dh::gen_plan(ny, &g->gy))
+    return DH_ERR_INVALIDDIMENSION;
   return DH_SUCCESS;
 }
 
@@ -240,36 +248,16 @@ struct Layout {  // byte offsets inside one device allocation
   size_t pol_ex[2], pol_ey[2];           // mode-0 field export: phase tables along x and y
   size_t export_t;                       // mode-0 field export: the y-transformed box columns
   size_t t1[4], f2[4], partial[4], capt, coefs, coefs_norm, window, fields, total;
-  size_t fctr[4], fslot[4];              // fused launch: counters and row-pass spectrum slots
 };
 
-// Fused row + column launches (spectral path, shapes with a fused kernel),
-// taken when the environment sets DH_FUSED=1: queues of the layout (the XCD
-// count of the part; fewer found at run time leave some unused) and slots per
-// queue: as many pol-frame spectra as fit in three quarters of an XCD's 4 MB
-// L2, at least 3 and at most 8 (DH_FUSED_SLOTS overrides).
-constexpr int kFusedQueues = 8;
-bool fused_enabled(const Geom& g, const dh_params* p) {
-  const char* env = std::getenv("DH_FUSED");
-  if (!env || std::strtol(env, nullptr, 10) != 1) return false;
-  return g.spec && dh::fused_supported(g.nx, g.ny, g.wy, g.gp, p->input_dtype == DH_INPUT_U16);
-}
-int fused_slots(const Geom& g) {
-  const size_t slot = (size_t)g.bx * g.ny * 8;
-  const long s = (long)((3ull << 20) / (slot ? slot : 1));
-  int n = (int)std::max(3L, std::min(8L, s));
-  if (const char* env = std::getenv("DH_FUSED_SLOTS")) {
-    const long v = std::strtol(env, nullptr, 10);
-    if (v >= 2 && v <= 64) n = (int)v;       // a row task waits on the columns of the pol-frame S back
-  }
-  return n;
-}
+
 
 Layout layout(const Geom& g, const dh_params* p, int max_batch, int chunk, int nws) {
   Layout L{};
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o += align256(bytes); return r; };
-  L.tw_nx = take(g.nx * 8); L.tw_ny = take(g.ny * 8); L.tw_wx = take(g.wx * 8); L.tw_wy = take(g.wy * 8);
+  L.tw_nx = take(dh::gen_twiddle_count(g.nx) * 8); L.tw_ny = take(dh::gen_twiddle_count(g.ny) * 8);
+  L.tw_wx = take(g.wx * 8); L.tw_wy = take(g.wy * 8);
   L.modes = take((g.nmodes > 0 ? g.nmodes : 1) * 4);
   for (int q = 0; q < p->pol_count; ++q) {
     L.pol_mrow[q] = take(g.by * 8);
@@ -305,11 +293,6 @@ Layout layout(const Geom& g, const dh_params* p, int max_batch, int chunk, int n
   L.fields = p->keep_fields ? take((size_t)max_batch * P * g.fy * g.fx * 8) : 0;
   L.export_t = exports(g, p) ? take((size_t)export_chunk(g, p, max_batch) * P * g.fy * ((g.bx + 15) / 16 * 16) * 8)
                               : 0;
-  const bool fused = fused_enabled(g, p);
-  for (int w = 0; w < nws; ++w) {
-    L.fctr[w] = fused ? take(dh::fused_counter_ints(kFusedQueues, chunk * (int)P) * 4) : 0;
-    L.fslot[w] = fused ? take((size_t)kFusedQueues * fused_slots(g) * g.bx * g.ny * 8) : 0;
-  }
   L.total = o;
   return L;
 }
@@ -324,8 +307,6 @@ struct Plan {
   char* mem = nullptr;
   hipStream_t last_stream = nullptr;
   dh::KArgs ka[4]{};                 // one per workspace
-  bool fused = false;                // row and column passes in one fused launch
-  dh::FusedQ fq[4]{};                // its queues, per workspace
   hipStream_t str[4]{};              // internal streams (nws > 1)
   hipEvent_t fork = nullptr, join[4]{};
   // per-stage timing: a start and an end event around every launch, on the
@@ -405,7 +386,8 @@ void put(std::vector<char>& host, size_t off, const std::vector<T>& v) {
 // Twiddles of the FFT passes after the first, in FP64 rounded to FP32:
 // for a pass of radix R after earlier radices with product NS, entry
 // (r-1)*NS + k = e^{-2 pi i k r / (NS R)}; the passes follow each other.
-std::vector<float2> twiddles(int n) {
+std::vector<float2> twiddles(int n, const dh::GenFft& gen) {
+  if (gen.np > 0) return dh::gen_twiddles(gen);
   int r[3];
   dh::fft_radices(n, r);
   std::vector<float2> t;
@@ -583,10 +565,10 @@ int build_tables(Plan* pl, bool hg = true, bool spec = true) {
   const dh_params* p = &pl->params;
   const Layout& L = pl->L;
   std::vector<char> host(L.total_tables, 0);
-  put(host, L.tw_nx, twiddles(g.nx));
-  put(host, L.tw_ny, twiddles(g.ny));
-  put(host, L.tw_wx, twiddles(g.wx));
-  put(host, L.tw_wy, twiddles(g.wy));
+  put(host, L.tw_nx, twiddles(g.nx, g.gx));
+  put(host, L.tw_ny, twiddles(g.ny, g.gy));
+  put(host, L.tw_wx, twiddles(g.wx, dh::GenFft{}));
+  put(host, L.tw_wy, twiddles(g.wy, dh::GenFft{}));
   std::vector<short2> modes;
   for (int gg = 0; gg < g.G; ++gg)
     for (int m = gg; m >= 0; --m) modes.push_back(make_short2((short)m, (short)(gg - m)));
@@ -671,6 +653,7 @@ void fill_kargs(Plan* pl, int w) {
   a.frame_w = p->frame_w; a.frame_h = p->frame_h; a.npol = p->pol_count;
   a.nx = g.nx; a.ny = g.ny; a.wx = g.wx; a.wy = g.wy; a.wyp = g.wyp;
   a.bx = g.bx; a.by = g.by; a.bxp = (g.bx + 15) / 16 * 16; a.G = g.G; a.gp = g.gp; a.nmodes = g.nmodes;
+  a.gx = g.gx; a.gy = g.gy;
   a.nxny = (float)((double)g.nx * g.ny);
   a.prec = p->precision;
   a.s_uh = pl->s_uh;
@@ -711,7 +694,7 @@ void fill_kargs(Plan* pl, int w) {
   a.t1 = (float2*)(m + L.t1[w]);
   a.f2 = (float2*)(m + L.f2[w]);
   a.partial = (float2*)(m + L.partial[w]);
-  a.nblk = g.spec ? dh::spectral_blocks(g.ny, g.bx, g.gp) : field_blocks(g);
+  a.nblk = g.spec ? dh::spectral_blocks(g.ny, g.wy, g.bx, g.gp) : field_blocks(g);
   a.coefs = pl->omem ? (float2*)pl->omem : (float2*)(m + L.coefs);
   a.coefs_norm = pl->omem ? (float2*)(pl->omem + align256((size_t)pl->ocap * p->pol_count * g.nmodes * 8))
                           : (float2*)(m + L.coefs_norm);
@@ -740,6 +723,7 @@ int export_fields(Plan* pl, int first, int count, int stride, int lam, hipStream
   m.tw_nx = pl->ka[0].tw_nx;
   m.tw_ny = pl->ka[0].tw_ny;
   m.nx = g.nx; m.ny = g.ny; m.wx = g.wx; m.wy = g.wy; m.bxp = (g.bx + 15) / 16 * 16; m.npol = P;
+  m.gx = g.gx; m.gy = g.gy;
   m.stride = stride;
   for (int q = 0; q < P; ++q) {
     const PolGeom& G = lam >= 0 ? pl->lam_geom[(size_t)lam * 2 + q] : g.pol[q];
@@ -756,17 +740,6 @@ int export_fields(Plan* pl, int first, int count, int stride, int lam, hipStream
     if (dh::launch_m0y(m, nb, s) != hipSuccess || dh::launch_m0x(m, nb, s) != hipSuccess) return DH_ERR_ERROR;
   }
   return DH_SUCCESS;
-}
-
-// whether the last fused launch of any workspace gave up a wait (read after
-// the plan's stream has been synchronised)
-bool fused_failed(Plan* pl) {
-  if (!pl->fused) return false;
-  for (int w = 0; w < pl->nws; ++w) {
-    int err = 0;
-    if (hipMemcpy(&err, pl->fq[w].ctr, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess || err != 0) return true;
-  }
-  return false;
 }
 
 int copy_out(Plan* pl, void* host_out, size_t bytes, const void* dev) {
@@ -827,7 +800,7 @@ int dh_plan_check(const dh_params* p, int max_batch, dh_plan_info* info) {
     info->path = g.spec ? DH_PATH_SPECTRAL : DH_PATH_FIELD;
     info->field_w = g.fx; info->field_h = g.fy;
     info->field_pitch_x = g.fpx; info->field_pitch_y = g.fpy;
-    info->fused = fused_enabled(g, p) ? 1 : 0;
+    info->generic = (g.gx.np > 0 ? 1 : 0) | (g.gy.np > 0 ? 2 : 0);
   }
   return DH_SUCCESS;
 }
@@ -895,19 +868,6 @@ int dh_plan(const dh_params* p, int max_batch, size_t hbm_budget, dh_handle* out
     return e;
   }
   for (int w = 0; w < pl->nws; ++w) fill_kargs(pl, w);
-  pl->fused = fused_enabled(pl->g, &pl->params);
-  if (pl->fused) {
-    const int nq = dh::fused_queues();
-    if (nq < 1) {
-      release(pl);
-      return DH_ERR_ERROR;
-    }
-    unsigned spin = 1u << 22;          // polls (a few seconds) before a launch gives up
-    if (const char* env = std::getenv("DH_FUSED_SPIN")) spin = (unsigned)std::strtoul(env, nullptr, 10);
-    for (int w = 0; w < pl->nws; ++w)
-      pl->fq[w] = dh::FusedQ{(int*)(pl->mem + pl->L.fctr[w]), (float2*)(pl->mem + pl->L.fslot[w]),
-                             std::min(nq, kFusedQueues), fused_slots(pl->g), spin};
-  }
   if (pl->nws > 1) {
     bool ok = hipEventCreateWithFlags(&pl->fork, hipEventDisableTiming) == hipSuccess;
     for (int w = 0; w < pl->nws && ok; ++w)
@@ -926,21 +886,14 @@ int dh_plan(const dh_params* p, int max_batch, size_t hbm_budget, dh_handle* out
 
 namespace {
 
-// the path over frames [b0, b0 + nb) with arguments a on stream st, in
-// workspace w (fused: row and column passes in one launch, timed as the FFT stage)
-bool launch_path(Plan* pl, const dh::KArgs& a, const void* frames, int u16, int b0, int nb, hipStream_t st, int w) {
-  bool ok;
-  if (pl->fused)
-    ok = timed_event(pl, st, DH_STAGE_FFT, true) == hipSuccess &&
-         dh::launch_fused(a, frames, u16, b0, nb, pl->fq[w], st) == hipSuccess &&
-         timed_event(pl, st, DH_STAGE_FFT, false) == hipSuccess;
-  else
-    ok = timed_event(pl, st, DH_STAGE_FFT, true) == hipSuccess &&
-         dh::launch_row(a, frames, u16, b0, nb, st) == hipSuccess &&
-         timed_event(pl, st, DH_STAGE_FFT, false) == hipSuccess &&
-         timed_event(pl, st, DH_STAGE_CROP, true) == hipSuccess &&
-         (pl->g.spec ? dh::launch_cspec(a, b0, nb, st) : dh::launch_col(a, b0, nb, st)) == hipSuccess &&
-         timed_event(pl, st, DH_STAGE_CROP, false) == hipSuccess;
+// the path over frames [b0, b0 + nb) with arguments a on stream st
+bool launch_path(Plan* pl, const dh::KArgs& a, const void* frames, int u16, int b0, int nb, hipStream_t st) {
+  bool ok = timed_event(pl, st, DH_STAGE_FFT, true) == hipSuccess &&
+            dh::launch_row(a, frames, u16, b0, nb, st) == hipSuccess &&
+            timed_event(pl, st, DH_STAGE_FFT, false) == hipSuccess &&
+            timed_event(pl, st, DH_STAGE_CROP, true) == hipSuccess &&
+            (pl->g.spec ? dh::launch_cspec(a, b0, nb, st) : dh::launch_col(a, b0, nb, st)) == hipSuccess &&
+            timed_event(pl, st, DH_STAGE_CROP, false) == hipSuccess;
   if (ok && !pl->g.spec && (a.G > 0 || a.fields))
     ok = timed_event(pl, st, DH_STAGE_FIELD, true) == hipSuccess && dh::launch_fld(a, b0, nb, st) == hipSuccess &&
          timed_event(pl, st, DH_STAGE_FIELD, false) == hipSuccess;
@@ -1001,7 +954,7 @@ int run_segments(Plan* pl, const void* frames, const std::vector<Seg>& segs, hip
           }
         }
       }
-      if (!launch_path(pl, a, frames, u16, b0, nb, nws > 1 ? pl->str[w] : s, w)) return DH_ERR_ERROR;
+      if (!launch_path(pl, a, frames, u16, b0, nb, nws > 1 ? pl->str[w] : s)) return DH_ERR_ERROR;
     }
   }
   if (nws > 1) {
@@ -1147,9 +1100,7 @@ int dh_mode_coefs(dh_handle h, dh_c64* host_out, const dh_c64** dev_out, int* ba
   if (dev_out) *dev_out = nm > 0 ? (const dh_c64*)src : nullptr;
   if (nm == 0) return set_err(pl, DH_SUCCESS);
   const size_t bytes = (size_t)pl->last_batch * pl->params.pol_count * nm * sizeof(dh_c64);
-  const int e = copy_out(pl, host_out, bytes, src);
-  if (e != DH_SUCCESS || !host_out) return set_err(pl, e);
-  return set_err(pl, fused_failed(pl) ? DH_ERR_ERROR : DH_SUCCESS);
+  return set_err(pl, copy_out(pl, host_out, bytes, src));
 }
 
 // the plan's field buffer (mode 1: written by the kernels; mode 0: by the export)
@@ -1239,6 +1190,8 @@ extern "C" int dh_batch_summary(dh_handle h, int plane, const void* frames, int 
   const float2* fld = field_buffer(pl);
   if (plane == 1 && (!fld || pl->last_batch < 1)) return set_err(pl, DH_ERR_ERROR);
   if (plane == 0 && !frames) return set_err(pl, DH_ERR_NULLPOINTER);
+  // the Fourier plane takes the compiled column transform of N_y
+  if (plane == 0 && pl->g.gy.np > 0) return set_err(pl, DH_ERR_INVALIDDIMENSION);
   hipStream_t s = plane == 1 ? pl->last_stream : (hipStream_t)stream;
   // scratch: the sums, the summed intensity, and (Fourier plane) the half
   // plane of a group of frames: row pass over columns 0..Nx/2, column FFT
@@ -1333,7 +1286,6 @@ int dh_get_plan_info(dh_handle h, dh_plan_info* out) {
   // what the plan was built with (the environment may have changed since)
   out->chunk = pl->chunk;
   out->device_bytes = pl->L.total;
-  out->fused = pl->fused ? 1 : 0;
   return set_err(pl, DH_SUCCESS);
 }
 
@@ -1717,6 +1669,9 @@ extern "C" float dh_autoalign(dh_handle h, const void* frames, int batch, int mo
       (mode != DH_ALIGN_ESTIMATE && pl->g.G == 0) || !(tol >= 0.f) ||
       pl->g.gp > dh::kMaxGpField)      // the trials run the field path's overlap (G <= 32)
     return (set_err(pl, DH_ERR_INVALIDARGUMENT), -FLT_MAX);
+  // the snaps and trials run compiled kernels for every length
+  if (pl->g.gx.np > 0 || pl->g.gy.np > 0 || !dh::sizes_supported(pl->g.nx, pl->g.ny, pl->g.wx, pl->g.wy))
+    return (set_err(pl, DH_ERR_INVALIDDIMENSION), -FLT_MAX);
   hipStream_t s = (hipStream_t)stream;
   if (hipDeviceSynchronize() != hipSuccess) return (set_err(pl, DH_ERR_ERROR), -FLT_MAX);
   dh_params& P = pl->params;
@@ -2563,7 +2518,7 @@ size_t lane_layout(const Plan* pl, int mb, size_t off[8]) {
   auto take = [&](size_t bytes) { size_t r = o; o += align256(bytes); return r; };
   off[0] = take((size_t)mb * P * g.ny * g.bx * 8);                  // t1
   off[1] = take(g.spec ? 0 : (size_t)mb * P * g.wy * ((g.bx + 15) / 16 * 16) * 8);  // f2
-  const int nblk = g.spec ? dh::spectral_blocks(g.ny, g.bx, g.gp) : field_blocks(g);
+  const int nblk = g.spec ? dh::spectral_blocks(g.ny, g.wy, g.bx, g.gp) : field_blocks(g);
   off[2] = take((size_t)mb * P * nblk * (nm + 1) * 8);               // partial
   off[3] = take((size_t)mb * P * nm * 8);                            // coefs
   off[4] = take((size_t)mb * P * nm * 8);                            // coefs_norm

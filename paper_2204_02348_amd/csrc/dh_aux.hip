@@ -817,6 +817,7 @@ __global__ void __launch_bounds__(256) k_m0x(M0Args m) {
 hipError_t launch_m0y(const M0Args& m, int nb, hipStream_t s) {
   if (nb < 1) return hipSuccess;
   const int bx = std::max(m.pol[0].bxq, m.npol > 1 ? m.pol[1].bxq : 0);
+  if (m.gy.np > 0) return launch_m0y_gen(m, bx, nb, s);
 #define X(N)                                                                                           \
   if (m.ny == N) {                                                                                    \
     constexpr int CG = N >= 1024 ? 4 : 8;                                                             \
@@ -830,6 +831,7 @@ hipError_t launch_m0y(const M0Args& m, int nb, hipStream_t s) {
 
 hipError_t launch_m0x(const M0Args& m, int nb, hipStream_t s) {
   if (nb < 1) return hipSuccess;
+  if (m.gx.np > 0) return launch_m0x_gen(m, nb, s);
 #define X(N)                                                                                           \
   if (m.nx == N) {                                                                                    \
     constexpr int TR = N >= 2048 ? 2 : N >= 1024 ? 4 : 8;                                             \

@@ -239,20 +239,17 @@ __device__ __forceinline__ float2 ld_tw(const __attribute__((address_space(1))) 
 
 // buf: LDS; tw: this pass's twiddle table (see fft_lds), in LDS or, where a
 // workgroup's LDS is better spent on occupancy, in global memory (TW is then a
-// global-address-space pointer, read through the caches). TPB threads do the
-// work; a workgroup of NTH > TPB threads runs the pass with its threads from
-// TPB on idle (they still meet every barrier).
-template <int N, int R, int NS, int NTR, int STRIDE, int TPB, int PAD, int NTH = TPB, typename TW>
+// global-address-space pointer, read through the caches).
+template <int N, int R, int NS, int NTR, int STRIDE, int TPB, int PAD, typename TW>
 __device__ __forceinline__ void stockham_pass(float2* buf, TW tw, int tid) {
   constexpr int NB = N / R;
   constexpr int TOTAL = NTR * NB;
   constexpr int IT = (TOTAL + TPB - 1) / TPB;
-  const bool act = NTH == TPB || tid < TPB;
   float2 v[IT][R];
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
     const int g = tid + it * TPB;
-    if (act && (TOTAL % TPB == 0 || g < TOTAL)) {
+    if (TOTAL % TPB == 0 || g < TOTAL) {
       const int tr = g / NB, b = g % NB;
       const float2* src = buf + tr * STRIDE;
 #pragma unroll
@@ -263,7 +260,7 @@ __device__ __forceinline__ void stockham_pass(float2* buf, TW tw, int tid) {
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
     const int g = tid + it * TPB;
-    if (act && (TOTAL % TPB == 0 || g < TOTAL)) {
+    if (TOTAL % TPB == 0 || g < TOTAL) {
       const int tr = g / NB, b = g % NB;
       const int k = b % NS;
       if constexpr (NS > 1) {
@@ -322,15 +319,14 @@ struct Pass1 {
   static constexpr int IT = (TOTAL + TPB - 1) / TPB;
 };
 
-template <int N, int NTR, int STRIDE, int TPB, int NTH = TPB>
+template <int N, int NTR, int STRIDE, int TPB>
 __device__ __forceinline__ void fft_pass1_regs(float2 (*v)[FftPlan<N>::R0], float2* buf, int tid) {
   using Q = Pass1<N, NTR, TPB>;
   constexpr int R0 = Q::R0, NB = Q::NB;
-  const bool act = NTH == TPB || tid < TPB;
 #pragma unroll
   for (int it = 0; it < Q::IT; ++it) {
     const int g = tid + it * TPB;
-    if (act && (Q::TOTAL % TPB == 0 || g < Q::TOTAL)) {
+    if (Q::TOTAL % TPB == 0 || g < Q::TOTAL) {
       const int tr = g / NB, b = g % NB;
       dft<R0>(v[it]);
       float2* dst = buf + tr * STRIDE + padi<R0>(b * R0);
@@ -341,14 +337,14 @@ __device__ __forceinline__ void fft_pass1_regs(float2 (*v)[FftPlan<N>::R0], floa
 }
 
 // Passes 2.. of the transform (starts and ends with a barrier).
-template <int N, int NTR, int STRIDE, int TPB, int NTH = TPB, typename TW>
+template <int N, int NTR, int STRIDE, int TPB, typename TW>
 __device__ __forceinline__ void fft_rest(float2* buf, TW tw, int tid) {
   using P = FftPlan<N>;
   constexpr int PAD = P::R0;
   __syncthreads();
-  if constexpr (P::R1 > 1) stockham_pass<N, P::R1, P::R0, NTR, STRIDE, TPB, PAD, NTH>(buf, tw, tid);
+  if constexpr (P::R1 > 1) stockham_pass<N, P::R1, P::R0, NTR, STRIDE, TPB, PAD>(buf, tw, tid);
   constexpr int OFF2 = (P::R1 - 1) * P::R0;
-  if constexpr (P::R2 > 1) stockham_pass<N, P::R2, P::R0 * P::R1, NTR, STRIDE, TPB, PAD, NTH>(buf, tw + OFF2, tid);
+  if constexpr (P::R2 > 1) stockham_pass<N, P::R2, P::R0 * P::R1, NTR, STRIDE, TPB, PAD>(buf, tw + OFF2, tid);
 }
 
 // forward FFT of NTR transforms of length N held in LDS (padded layout of

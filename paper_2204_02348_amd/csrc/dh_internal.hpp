@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstddef>
+#include <vector>
 
 namespace dh {
 
@@ -13,6 +14,20 @@ constexpr int kMaxGroups = 100;
 constexpr int kMaxGp = 128;
 // the field path's overlap tiles modes in at most two 16-column tiles
 constexpr int kMaxGpField = 32;
+
+// A transform length without a compiled kernel: n = r[0] r[1] ... r[np-1]
+// (radices 2, 3, 4, 5, 7, 8, 11, 13, 16 and at most one prime above 13). The
+// twiddles of pass s sit at table + off[s] as [r - 1][NS] (NS = r[0] ...
+// r[s-1]); the roots e^{-2 pi i m / p} of a prime radix p > 16 at table +
+// roots. np = 0: the length has a compiled kernel (or no plan).
+constexpr int kGenMaxN = 2048;          // the compiled lengths go to 2048 too; keeps every LDS buffer <= 64 KB
+constexpr int kGenMaxPasses = 12;
+struct GenFft {
+  int n, np;
+  int r[kGenMaxPasses];
+  int off[kGenMaxPasses];
+  int roots;
+};
 
 // Per-polarisation plan tables (device pointers) and window geometry.
 //
@@ -84,9 +99,12 @@ struct KArgs {
   float2* coefs_norm;       // [max_batch][P][nmodes] power-normalised
   float2* window;           // [max_batch][P][wy][wx] or null
   float2* fields;           // [max_batch][P][wy][wx] or null
+  GenFft gx, gy;            // row / column lengths without a compiled kernel (np > 0): the
+                            // generic kernels run them, with tw_nx / tw_ny the generic tables
 };
 
-bool sizes_supported(int nx, int ny, int wx, int wy);
+bool sizes_supported(int nx, int ny, int wx, int wy);    // every kernel of the field path compiled
+bool fft_compiled(int n);                                // a compiled row / column / export transform
 void fft_radices(int n, int r[3]);   // radices of the passes of a supported length
 hipError_t launch_row(const KArgs& a, const void* frames, int u16, int b0, int nb, hipStream_t s);
 hipError_t launch_col(const KArgs& a, int b0, int nb, hipStream_t s);
@@ -95,7 +113,7 @@ hipError_t launch_norm(const KArgs& a, int b0, int nb, hipStream_t s);
 // spectral path: column FFT + masked window contracted with the xs / ys
 // tables into per-column-block partials (replaces launch_col + launch_fld)
 bool spectral_supported(int ny, int wy, int gp);
-int spectral_blocks(int ny, int bx, int gp);   // column blocks per frame and pol
+int spectral_blocks(int ny, int wy, int bx, int gp);   // column blocks per frame and pol
 hipError_t launch_cspec(const KArgs& a, int b0, int nb, hipStream_t s);
 hipError_t launch_zero(float2* p, size_t n, hipStream_t s);
 // alignment: column FFT of an extended box stored as spec[b][p][j][i] (nrow rows
@@ -142,30 +160,24 @@ struct M0Args {
     const float2* phx;       // [nx] tilt/defocus phase along x
     const float2* phy;       // [ny] the same along y, times 1/(Nx Ny)
   } pol[2];
+  GenFft gx, gy;             // as in KArgs
 };
 hipError_t launch_m0y(const M0Args& m, int nb, hipStream_t s);
 hipError_t launch_m0x(const M0Args& m, int nb, hipStream_t s);
 // fields to int16 (re, im) with one FP32 scale per field: n fields of len values
 hipError_t launch_q16(const float2* fields, int n, long long len, short* re, short* im, float* scale, hipStream_t s);
-// Fused row + column launch (spectral path): one persistent kernel whose
-// workgroups take tasks from per-XCD queues. Pol-frame q of the launch belongs
-// to queue q mod nqueue; its row-pass spectrum goes to slot (q / nqueue) mod S
-// of that queue, so that the row tasks that write it and the column tasks that
-// read it run on one XCD and the spectrum stays in that XCD's L2.
-struct FusedQ {
-  int* ctr;          // [1] error flag, [nqueue] task counters, [nq] rows done, [nq] columns done
-  float2* t1;        // [nqueue][S] slots of one pol-frame's row-pass spectrum (bx * ny)
-  int nqueue, S;     // queues, slots per queue
-  unsigned spin;     // polls of a dependency before the launch gives up
-};
-// queues to use on the current device: the XCD count read from the hardware
-// (1 where it cannot be read consistently); -1 on error
-int fused_queues();
-bool fused_supported(int nx, int ny, int wy, int gp, int u16);
-// counters zeroed, then the fused kernel over frames [b0, b0 + nb)
-hipError_t launch_fused(const KArgs& a, const void* frames, int u16, int b0, int nb, const FusedQ& f,
-                        hipStream_t s);
-size_t fused_counter_ints(int nqueue, int nq);
+// generic-length kernels (dh_generic.hip): plan and twiddle table of a
+// length (false: more than one prime factor above 13, or n > kGenMaxN);
+// entries the table needs at most; launches as launch_row / launch_cspec /
+// launch_m0y / launch_m0x, which call them for lengths with np > 0
+bool gen_plan(int n, GenFft* g);
+std::vector<float2> gen_twiddles(const GenFft& g);
+size_t gen_twiddle_count(int n);
+int gen_cols_per_block(int ny, int gp);
+hipError_t launch_row_gen(const KArgs& a, const void* frames, int u16, int b0, int nb, hipStream_t s);
+hipError_t launch_cspec_gen(const KArgs& a, int b0, int nb, hipStream_t s);
+hipError_t launch_m0y_gen(const M0Args& m, int bx, int nb, hipStream_t s);
+hipError_t launch_m0x_gen(const M0Args& m, int nb, hipStream_t s);
 
 // basis transform of n coefficient vectors (frame x pol, rows of nin values,
 // the first nused of them taken): out[e][k] = sum_{i < cnt} tt[off + i stride]

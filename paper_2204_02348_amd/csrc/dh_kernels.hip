@@ -19,9 +19,6 @@
 // fields complex64 interleaved; every intermediate row-major with the
 // contiguous axis the one the next kernel reads along.
 #include <algorithm>
-#include <map>
-#include <mutex>
-#include <vector>
 
 #include "dh_fft.hpp"
 #include "dh_internal.hpp"
@@ -117,12 +114,11 @@ __device__ __forceinline__ void stage_twiddles(float2* dst, const float2* __rest
 // LDS stores: the loads are issued ahead of a kernel's main operand loads and
 // the stores wait only for them, so the table costs one memory latency that
 // overlaps the main loads. Entries [n, N) get `fill`; n >= 1.
-template <typename T, int N, int TPB, int NTH = TPB>
+template <typename T, int N, int TPB>
 struct Staged {
   static constexpr int IT = (N + TPB - 1) / TPB;
   T v[IT];
   __device__ __forceinline__ void load(const T* __restrict__ src, int n, int tid) {
-    if (NTH != TPB && tid >= TPB) return;
 #pragma unroll
     for (int i = 0; i < IT; ++i) {
       const int e = tid + i * TPB;
@@ -130,7 +126,6 @@ struct Staged {
     }
   }
   __device__ __forceinline__ void store(T* dst, int n, T fill, int tid) const {
-    if (NTH != TPB && tid >= TPB) return;
 #pragma unroll
     for (int i = 0; i < IT; ++i) {
       const int e = tid + i * TPB;
@@ -158,9 +153,8 @@ template <int NX, int TR> struct RowShape {
 
 // The row pass of row-tile group `tg` of frame `bl` (within the launch, frames
 // from b0), pol p, into `out` (that frame and pol's t1); buf and tws: LDS of
-// RowShape's sizes. A workgroup of NTH >= TPB threads runs it with the
-// threads from TPB on idle.
-template <int NX, int TR, typename TIn, int TT, int NTH>
+// RowShape's sizes.
+template <int NX, int TR, typename TIn, int TT>
 __device__ __forceinline__ void row_tiles(const KArgs& A, const TIn* __restrict__ frames, int b0, int tg, int p,
                                           int bl, float2* __restrict__ out, float2* buf, float2* tws, int tid) {
   using RS = RowShape<NX, TR>;
@@ -169,9 +163,8 @@ __device__ __forceinline__ void row_tiles(const KArgs& A, const TIn* __restrict_
   using Q = Pass1<NX, TR, TPB>;
   static_assert(Q::IT == 1, "one first-pass butterfly per thread");
   constexpr bool TWG = RS::TWG;
-  const bool act = NTH == TPB || tid < TPB;
   const PolTab& P = A.pol[p];
-  Staged<float2, TWG ? 1 : twn<NX>(), TPB, NTH> stw;
+  Staged<float2, TWG ? 1 : twn<NX>(), TPB> stw;
   if constexpr (!TWG) stw.load(A.tw_nx, twn<NX>(), tid);
   const TIn* fr = A.fptr ? static_cast<const TIn*>(A.fptr[b0 + bl]) : frames + (size_t)(b0 + bl) * A.frame_h * A.frame_w;
   const gptr<TIn> win = as_global(fr) + ((size_t)P.y0 * A.frame_w + P.x0);
@@ -179,7 +172,7 @@ __device__ __forceinline__ void row_tiles(const KArgs& A, const TIn* __restrict_
   // in flight while the earlier tiles' transforms run. A tile past the last
   // row (odd tile count) loads row pair 0 instead and stores nothing.
   float2 v[TT][Q::R0];
-  if (act) {
+  {
     const int t = tid / Q::NB, b = tid % Q::NB;
 #pragma unroll
     for (int tt = 0; tt < TT; ++tt) {
@@ -199,13 +192,13 @@ __device__ __forceinline__ void row_tiles(const KArgs& A, const TIn* __restrict_
   for (int tt = 0; tt < TT; ++tt) {
     const int ybase = (tg * TT + tt) * (2 * TR);
     if (tt > 0) __syncthreads();           // the previous tile's split has read buf
-    fft_pass1_regs<NX, TR, L::STRIDE, TPB, NTH>(v + tt, buf, tid);
+    fft_pass1_regs<NX, TR, L::STRIDE, TPB>(v + tt, buf, tid);
     if constexpr (TWG)
-      fft_rest<NX, TR, L::STRIDE, TPB, NTH>(buf, as_global(A.tw_nx), tid);
+      fft_rest<NX, TR, L::STRIDE, TPB>(buf, as_global(A.tw_nx), tid);
     else
-      fft_rest<NX, TR, L::STRIDE, TPB, NTH>(buf, static_cast<const float2*>(tws), tid);
+      fft_rest<NX, TR, L::STRIDE, TPB>(buf, static_cast<const float2*>(tws), tid);
     // two-for-one split at the kept bins: both rows of a pair from Z[k], Z[NX-k]
-    if (act) {
+    {
       for (int e = tid; e < TR * A.bx; e += TPB) {
         const int t = e % TR, j = e / TR;
         const int y = ybase + 2 * t;
@@ -222,7 +215,7 @@ __device__ __forceinline__ void row_tiles(const KArgs& A, const TIn* __restrict_
         // rows y, y+1 (ny is even). A workgroup writes 2 TR rows of each
         // 16-row tile per phase: from 64 B on, non-temporal stores are faster;
         // the 32 B pieces of TR = 2 need the cache to merge them into lines
-        if constexpr (2 * TR >= 8 && kT1Nt && NTH == TPB) {
+        if constexpr (2 * TR >= 8 && kT1Nt) {
           const floatx4 t4 = {x.x, x.y, x.z, x.w};
           __builtin_nontemporal_store(t4, reinterpret_cast<floatx4*>(o));
         } else {
@@ -240,7 +233,7 @@ __global__ void __launch_bounds__(TR * NX / FftPlan<NX>::R0) k_row(KArgs A, cons
   __shared__ float2 tws[RS::TWS];
   const int p = blockIdx.y, bl = blockIdx.z;
   float2* out = A.t1 + (size_t)(bl * A.npol + p) * A.bx * A.ny;
-  row_tiles<NX, TR, TIn, TT, RS::TPB>(A, frames, b0, blockIdx.x, p, bl, out, buf, tws, threadIdx.x);
+  row_tiles<NX, TR, TIn, TT>(A, frames, b0, blockIdx.x, p, bl, out, buf, tws, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -652,156 +645,6 @@ __global__ void __launch_bounds__(kTPB) k_cspec(KArgs A, int b0) {
   const float2* in = A.t1 + ((size_t)(bl * A.npol + p) * A.bx) * NY;
   cspec_block<NY, WY, CG, NT, MC, kT1Nt ? 2 : 0>(A, b0, blockIdx.x, p, bl, in, buf, twy, s_mrow, s_x, s_pw, s_spill,
                                                  threadIdx.x);
-}
-
-// ---------------------------------------------------------------------------
-// k_fused (spectral path): the row pass and the column pass of a launch in one
-// persistent kernel, so that a pol-frame's row-pass spectrum (bx x ny complex,
-// 0.4 MB at 640x512) goes from the row tasks that write it to the column tasks
-// that read it through the L2 of one XCD instead of through HBM.
-//
-// Tasks: per pol-frame, R row tasks (TT tiles of 2 TR rows each, as k_row)
-// and C column tasks (CG box columns each, as k_cspec). Pol-frame q belongs to
-// queue q mod nqueue (the XCD count), its spectrum to slot (q / nqueue) mod S
-// of that queue. Each queue hands out its tasks in the order
-//   R(0) | R(1) C(0) | R(2) C(1) | ... | C(last)
-// (R(i), C(i): the row and column tasks of the queue's i-th pol-frame), so
-// the column tasks of a pol-frame follow its row tasks by one pol-frame. A
-// workgroup takes tasks from the queue of its own XCD first, then from the
-// others (a queue whose XCD has no workgroups is still drained).
-//
-// Waits: a column task waits until its pol-frame's R row tasks are done; a
-// row task of the i-th pol-frame (i >= S) waits until the C column tasks of
-// the slot's previous pol-frame (i - S) are done. Both wait only on tasks
-// handed out earlier from the same queue, i.e. held by running workgroups,
-// so every wait ends. Each wait gives up after F.spin polls and then sets the
-// error flag, which makes every later wait give up at once (the host reports
-// the launch as failed; spin = 0 gives up at the first wait). Hand-over: each thread's stores, an agent-scope
-// release fence, a barrier, then the counter increment; the reader polls,
-// meets a barrier, then an agent-scope acquire fence before its loads.
-constexpr unsigned kXccIdReg = 20u | (0u << 6) | (3u << 11);    // hwreg(HW_REG_XCC_ID, 0, 4)
-#ifndef DH_FUSED_PROTO
-#define DH_FUSED_PROTO 0
-#endif
-#ifndef DH_FUSED_T1AUX
-#define DH_FUSED_T1AUX 0
-#endif
-
-__device__ __forceinline__ bool dep_wait(int* c, int target, int* err, unsigned spin) {
-  if (spin == 0) {                   // a launch told to give up at its first wait
-    __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return false;
-  }
-  unsigned n = 0;
-  for (;;) {
-    if (__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) return true;
-    if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || ++n > spin) {
-      __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      return false;
-    }
-    __builtin_amdgcn_s_sleep(4);
-  }
-}
-
-template <int NX, int TR, typename TIn, int TT, int NY, int WY, int CG, int NT, bool MC>
-__global__ void __launch_bounds__(kTPB) k_fused(KArgs A, const TIn* __restrict__ frames, int b0, int nq, FusedQ F) {
-  using RS = RowShape<NX, TR>;
-  using SH = CspecShape<NY, WY, CG, NT, MC>;
-  static_assert(RS::TPB <= kTPB, "the row pass fits the workgroup");
-  // LDS: the row pass's arrays and the column pass's, overlaid (float2 units)
-  constexpr int O_TWY = SH::BUF, O_MROW = O_TWY + SH::TWY, O_SX = O_MROW + SH::MROW;
-  constexpr int O_SPILL = O_SX + SH::SX, O_PW = O_SPILL + SH::SPILL;
-  constexpr int COLN = O_PW + 2, ROWN = RS::BUF + RS::TWS;
-  __shared__ float2 lds[COLN > ROWN ? COLN : ROWN];
-  __shared__ int s_task, s_ok;
-  const int tid = threadIdx.x;
-  constexpr int RT = 2 * TR * TT;                        // rows per row task
-  const int R = (A.ny + RT - 1) / RT, C = (A.bx + CG - 1) / CG, per = R + C;
-  int* err = F.ctr;
-  int* next = F.ctr + 1;
-  int* rows = next + F.nqueue;
-  int* cols = rows + nq;
-  const size_t slot_elems = (size_t)A.bx * A.ny;
-  const int home = F.nqueue > 1 ? (int)(__builtin_amdgcn_s_getreg(kXccIdReg) % (unsigned)F.nqueue) : 0;
-  // Control values shared through LDS (the task, a wait's outcome) are read
-  // back as scalars, so that the compiler sees every branch on them as
-  // uniform; thread 0's own work (claims, counters, waits) sits in plain
-  // if-regions that end at a barrier inside the loop body. (With the claim at
-  // the top of the loop, the lanes that skip it reach the loop's barrier by an
-  // edge of their own, and the compiler made that barrier the header of an
-  // inner loop that repeats the task without the next claim.)
-  for (int k = 0; k < (DH_FUSED_PROTO == 2 ? 1 : F.nqueue); ++k) {
-    const int qid = (home + k) % F.nqueue;               // own queue first, then the others
-    const int nqx = qid < nq ? (nq - qid + F.nqueue - 1) / F.nqueue : 0;
-    const int ntask = nqx * per;
-    if (tid == 0) s_task = __hip_atomic_fetch_add(next + qid, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    int t = __builtin_amdgcn_readfirstlane(s_task);
-    while (t < ntask) {
-      bool row;
-      int i, sub;
-      if (t < R) {
-        row = true; i = 0; sub = t;
-      } else {
-        const int u = t - R, kk = u / per + 1, r = u - (kk - 1) * per;
-        if (kk < nqx) {
-          row = r < R;
-          i = row ? kk : kk - 1;
-          sub = row ? r : r - R;
-        } else {
-          row = false; i = nqx - 1; sub = r;
-        }
-      }
-      const int q = i * F.nqueue + qid;                  // pol-frame of the launch
-      const int bl = q / A.npol, p = q - bl * A.npol;
-      float2* slot = F.t1 + ((size_t)qid * F.S + i % F.S) * slot_elems;
-      if (tid == 0)
-        s_ok = row ? (i < F.S || dep_wait(cols + (i - F.S) * F.nqueue + qid, C, err, F.spin))
-                   : dep_wait(rows + q, R, err, F.spin);
-      __syncthreads();
-      const int ok = __builtin_amdgcn_readfirstlane(s_ok);
-      if (ok && row) {
-        row_tiles<NX, TR, TIn, TT, kTPB>(A, frames, b0, sub, p, bl, slot, lds, lds + RS::BUF, tid);
-#if DH_FUSED_PROTO == 0
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-#else
-        __builtin_amdgcn_s_waitcnt(0);                   // this wave's stores are done
-#endif
-      } else if (ok) {
-#if DH_FUSED_PROTO == 0
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-#elif DH_FUSED_PROTO == 1
-        if (tid < 64) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        __syncthreads();
-#endif
-        cspec_block<NY, WY, CG, NT, MC, DH_FUSED_T1AUX>(A, b0, sub, p, bl, slot, lds, lds + O_TWY,
-                                           reinterpret_cast<int2*>(lds + O_MROW), lds + O_SX,
-                                           reinterpret_cast<float*>(lds + O_PW), lds + O_SPILL, tid);
-      }
-      // every wave's stores are fenced and its loads of the slot consumed:
-      // thread 0 marks the task done and takes the next one
-      __syncthreads();
-      if (tid == 0) {
-#if DH_FUSED_PROTO == 1
-        if (ok && row) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-#endif
-        if (ok) __hip_atomic_fetch_add(row ? rows + q : cols + q, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s_task = __hip_atomic_fetch_add(next + qid, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-      __syncthreads();
-      t = __builtin_amdgcn_readfirstlane(s_task);
-    }
-    __syncthreads();                                     // s_task is read before the next queue's claim
-  }
-}
-
-__global__ void k_zero_int(int* p, size_t n) {
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
-}
-
-// the XCD each of a grid of workgroups runs on
-__global__ void k_xcc_probe(int* out) {
-  if (threadIdx.x == 0) out[blockIdx.x] = (int)__builtin_amdgcn_s_getreg(kXccIdReg);
 }
 
 // ---------------------------------------------------------------------------
@@ -1428,13 +1271,17 @@ bool sizes_supported(int nx, int ny, int wx, int wy) {
   return fft_ok(nx) && fft_ok(ny) && ifft_ok(wx) && ifft_ok(wy) && pair_ok(ny, wy);
 }
 
+bool fft_compiled(int n) { return fft_ok(n); }
+
 hipError_t launch_row(const KArgs& a, const void* frames, int u16, int b0, int nb, hipStream_t s) {
+  if (a.gx.np > 0) return launch_row_gen(a, frames, u16, b0, nb, s);
 #define X(N) if (a.nx == N) return row_n<N>(a, frames, u16, b0, nb, s);
   DH_FFT_SIZES(X)
 #undef X
   return hipErrorInvalidValue;
 }
 hipError_t launch_col(const KArgs& a, int b0, int nb, hipStream_t s) {
+  if (a.gy.np > 0) return hipErrorInvalidValue;
 #define X(N, W) if (a.ny == N && a.wy == W) return col_nw<N, W>(a, b0, nb, s);
   DH_COL_PAIRS(X)
 #undef X
@@ -1452,7 +1299,11 @@ bool spectral_supported(int ny, int wy, int gp) {
   return false;
 }
 
-int spectral_blocks(int ny, int bx, int gp) {
+int spectral_blocks(int ny, int wy, int bx, int gp) {
+  if (!spectral_supported(ny, wy, gp)) {            // the generic column kernel's blocks
+    const int cgg = gen_cols_per_block(ny, gp);
+    return (bx + cgg - 1) / cgg;
+  }
   int cg = 16;
 #define X(N) if (ny == N) cg = gp == 16 ? cspec_cg<N, 1>() : cspec_cg<N, 2>();
   DH_FFT_SIZES(X)
@@ -1473,6 +1324,7 @@ static hipError_t cspec_nwt(const KArgs& a, int b0, int nb, hipStream_t s) {
 }
 
 hipError_t launch_cspec(const KArgs& a, int b0, int nb, hipStream_t s) {
+  if (a.gy.np > 0) return launch_cspec_gen(a, b0, nb, s);
   if (!spectral_supported(a.ny, a.wy, a.gp)) return hipErrorInvalidValue;
 #define X(N, W)                                                                              \
   if (a.ny == N && a.wy == W)                                                                \
@@ -1498,6 +1350,7 @@ static hipError_t spec_n(const KArgs& a, float2* spec, int nrow, int nb, hipStre
 }
 
 hipError_t launch_spec(const KArgs& a, float2* spec, int nrow, int nb, hipStream_t s) {
+  if (a.gy.np > 0) return hipErrorInvalidValue;
 #define X(N) if (a.ny == N) return spec_n<N>(a, spec, nrow, nb, s);
   DH_FFT_SIZES(X)
 #undef X
@@ -1523,102 +1376,6 @@ hipError_t launch_gather(const KArgs& a, const float2* spec, int bxe, int nrow, 
 }
 
 
-
-size_t fused_counter_ints(int nqueue, int nq) { return (size_t)nqueue + 2 * (size_t)nq + 1; }
-
-#ifndef DH_FUSED_TT
-#define DH_FUSED_TT 1
-#endif
-// fused instantiations: (row length, column length, IFFT rows, mode tiles), f32 frames
-#define DH_FUSED_SHAPES(X) X(320, 512, 176, 1)
-
-bool fused_supported(int nx, int ny, int wy, int gp, int u16) {
-  if (u16) return false;
-#define X(N, M, W, T) if (nx == N && ny == M && wy == W && gp == 16 * T) return true;
-  DH_FUSED_SHAPES(X)
-#undef X
-  return false;
-}
-
-int fused_queues() {
-  // workgroups are dealt to the XCDs in turn: a probe grid of many workgroups
-  // reads the XCD id of each; the queues are those ids if they are exactly
-  // 0 .. n-1 (n <= 16), else one queue
-  static std::mutex mu;
-  static std::map<int, int> cache;
-  int dev = -1;
-  if (hipGetDevice(&dev) != hipSuccess) return -1;
-  std::lock_guard<std::mutex> lk(mu);
-  auto it = cache.find(dev);
-  if (it != cache.end()) return it->second;
-  constexpr int n = 4096;
-  int* d = nullptr;
-  std::vector<int> h(n, -1);
-  if (hipMalloc(&d, n * sizeof(int)) != hipSuccess) return -1;
-  hipLaunchKernelGGL(k_xcc_probe, dim3(n), dim3(64), 0, 0, d);
-  const bool ok = hipGetLastError() == hipSuccess && hipMemcpy(h.data(), d, n * sizeof(int), hipMemcpyDeviceToHost) ==
-                                                        hipSuccess;
-  (void)hipFree(d);
-  if (!ok) return -1;
-  int mx = -1;
-  bool seen[16] = {};
-  for (int v : h) {
-    if (v < 0 || v >= 16) {
-      mx = -2;
-      break;
-    }
-    seen[v] = true;
-    mx = std::max(mx, v);
-  }
-  int q = 1;
-  if (mx >= 0) {
-    q = mx + 1;
-    for (int v = 0; v <= mx; ++v)
-      if (!seen[v]) q = 1;
-  }
-  cache[dev] = q;
-  return q;
-}
-
-template <int NX, int NY, int WY, int NT>
-static hipError_t fused_nw(const KArgs& a, const float* frames, int b0, int nb, const FusedQ& f, hipStream_t s) {
-  constexpr int TR = row_tr<NX>();
-  constexpr int CG = cspec_cg<NY, NT>();
-  constexpr int TT = DH_FUSED_TT;
-  constexpr int RT = 2 * TR * TT;
-  const auto kern = k_fused<NX, TR, float, TT, NY, WY, CG, NT, false>;
-  // workgroups resident on the whole device (cached per device)
-  static int cap[64] = {};
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return hipErrorInvalidValue;
-  if (cap[dev] == 0) {
-    int per_cu = 0;
-    hipDeviceProp_t prop;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kTPB, 0) != hipSuccess ||
-        hipGetDeviceProperties(&prop, dev) != hipSuccess || per_cu < 1)
-      return hipErrorInvalidValue;
-    cap[dev] = per_cu * prop.multiProcessorCount;
-  }
-  const int nq = nb * a.npol;
-  const size_t nctr = fused_counter_ints(f.nqueue, nq);
-  hipLaunchKernelGGL(k_zero_int, dim3((unsigned)std::min<size_t>((nctr + 255) / 256, 1024)), dim3(256), 0, s, f.ctr,
-                     nctr);
-  const long tasks = (long)nq * ((a.ny + RT - 1) / RT + (a.bx + CG - 1) / CG);
-  const int grid = (int)std::min<long>(cap[dev], tasks);
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(kTPB), 0, s, a, frames, b0, nq, f);
-  return hipGetLastError();
-}
-
-hipError_t launch_fused(const KArgs& a, const void* frames, int u16, int b0, int nb, const FusedQ& f,
-                        hipStream_t s) {
-  if (u16 || f.nqueue < 1 || f.S < 1) return hipErrorInvalidValue;
-#define X(N, M, W, T)                                                  \
-  if (a.nx == N && a.ny == M && a.wy == W && a.gp == 16 * T)           \
-    return fused_nw<N, M, W, T>(a, static_cast<const float*>(frames), b0, nb, f, s);
-  DH_FUSED_SHAPES(X)
-#undef X
-  return hipErrorInvalidValue;
-}
 
 hipError_t launch_norm(const KArgs& a, int b0, int nb, hipStream_t s) {
   hipLaunchKernelGGL(k_norm, dim3(nb), dim3(kTPB), 0, s, a, b0);

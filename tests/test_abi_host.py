@@ -91,6 +91,33 @@ def test_mode0_without_decomposition():
     assert (info.field_w, info.field_h) == (320, 512)
 
 
+COMPILED = (64, 128, 256, 320, 512, 640, 1024, 2048)      # transform lengths with compiled kernels
+
+
+def test_every_window_size_multiple_of_16():
+    # "Window sizes": any multiple of 16 from 64 to 2048 along either axis
+    # (compiled transforms or the runtime-length kernels), on the spectral path
+    base = dict(dh_synth.config(3, 1)["params"], input_dtype="f32")
+    for n in range(64, 2049, 16):
+        for fw, fh in ((n, n), (n, 256), (384, n)):
+            rc, info = dh.plan_check(dict(base, frame_w=fw, frame_h=fh, fft_w=fw, fft_h=fh))
+            assert rc == 0 and info.path == dh.PATH_SPECTRAL, (fw, fh, rc)
+            # bit 0: the row pass runs the runtime-length kernel exactly when N_x has no compiled one
+            assert bool(info.generic & 1) == (fw not in COMPILED), (fw, fh, info.generic)
+            if fh not in COMPILED:
+                assert info.generic & 2, (fw, fh)
+
+
+def test_generic_sizes_keep_the_field_path_out():
+    # the field path (mode-1 fields, split precision, AutoAlign trials) needs
+    # compiled transforms for every length
+    d = dict(dh_synth.config(3, 1)["params"], input_dtype="f32", frame_w=384, frame_h=256, fft_w=384, fft_h=256)
+    assert dh.plan_check(d)[0] == 0
+    assert dh.plan_check(dict(d, keep_fields=1))[0] == dh.ERR_INVALIDDIMENSION
+    assert dh.plan_check(dict(d, precision="split_bf16"))[0] == dh.ERR_INVALIDDIMENSION
+    assert dh.plan_check(dict(d, ifft_mode=0, keep_fields=1))[0] == 0
+
+
 def test_null_pointer():
     assert dh.lib().dh_plan_check(None, 1, None) == dh.ERR_NULLPOINTER
     h = ctypes.c_int()

@@ -228,59 +228,6 @@ def test_mode0_large_group_count():
     check_frames(p, f, gpu, range(2), keep=False)
 
 
-@pytest.mark.parametrize("n", [1000, 7, 1])
-def test_fused_launch_bit_identical_to_separate_passes(n):
-    """640x512, 2 pols, G=9: the fused row + column launch (the benchmark's
-    launch at n = 1000; a ragged and a single-frame batch) gives coefficients
-    bit-identical to the separate row and column launches, and matches the
-    oracle on sampled frames."""
-    torch = _torch()
-    import paper_2204_02348_amd as dh
-    cfg, pool, _ = _frames(1, n=min(n, 50))
-    f = dh_synth.tile_pool(pool, n) if n > 50 else pool
-    ft = torch.from_numpy(np.ascontiguousarray(f)).cuda()
-    out = {}
-    for fused in (1, 0):
-        os.environ["DH_FUSED"] = str(fused)
-        try:
-            plan = dh.Plan(cfg["params"], max_batch=n)
-        finally:
-            os.environ.pop("DH_FUSED", None)
-        assert plan.info.fused == fused
-        _say(f"640x512 batch {n}, fused {fused}")
-        plan.process(ft, n, None)
-        out[fused] = (plan.coefs(False), plan.coefs(True))
-        plan.destroy()
-    assert np.array_equal(out[1][0], out[0][0]) and np.array_equal(out[1][1], out[0][1])
-    check_frames(cfg["params"], f, dict(coefs=out[1][0], coefs_norm=out[1][1]), sorted({0, n // 2, n - 1}),
-                 keep=False)
-
-
-def test_fused_launch_gives_up_and_reports():
-    """A fused launch told to give up at its first wait (spin limit 0) ends,
-    and the plan reports it as DH_ERR_ERROR; the next plan works."""
-    torch = _torch()
-    import paper_2204_02348_amd as dh
-    cfg, f, _ = _frames(1, n=4)
-    ft = torch.from_numpy(np.ascontiguousarray(f)).cuda()
-    os.environ["DH_FUSED_SPIN"] = "0"
-    os.environ["DH_FUSED"] = "1"
-    try:
-        plan = dh.Plan(cfg["params"], max_batch=4)
-    finally:
-        os.environ.pop("DH_FUSED_SPIN", None)
-        os.environ.pop("DH_FUSED", None)
-    assert plan.info.fused == 1
-    _say("fused launch with spin limit 0")
-    plan.process(ft, 4, None)
-    with pytest.raises(dh.DhError) as e:
-        plan.coefs(False)
-    assert e.value.code == dh.ERR_ERROR
-    plan.destroy()
-    gpu = run_gpu(cfg["params"], f, keep=False)
-    check_frames(cfg["params"], f, gpu, range(4), keep=False)
-
-
 def test_zero_frames_give_zero_not_nan():
     """All-zero frames: every coefficient, raw and normalised (power 0), is
     exactly zero on both paths, and the int16 export has scale 1."""
