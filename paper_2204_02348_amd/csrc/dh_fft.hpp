@@ -221,12 +221,22 @@ __device__ __forceinline__ void dft(float2* v) {
 }
 
 // ------------------------------------------------------------------ Stockham pass over NTR transforms
-// LDS layout of one transform: element i lives at i + i / PAD (one spare slot
-// after every PAD elements, PAD = the first radix), which makes the strided
-// writes of the first pass and the reads of every pass bank-conflict free;
-// transform t starts at t * STRIDE (an odd stride >= the padded length).
+// LDS layout of one transform (Lds<N> below). Measured bank behaviour of the
+// gfx950 LDS: 64-bit reads serve 32 lanes per cycle over 32 banks of 8 bytes,
+// 64-bit writes 16 lanes per cycle over 32 banks of 4 bytes (so a float2 slot
+// is bank (index mod 32) for reads, (index mod 16) for writes). Two layouts:
+//  - padded: element i at i + i / PAD (one spare slot after every PAD = R0
+//    elements), transform t at t * STRIDE (odd STRIDE >= the padded length);
+//  - swizzled (the 8 x 8 x 8 plan of 512 points): element i at i XOR s(i),
+//    s moving bits 4..6 onto bits 0..2 and bit 6 onto bit 3, no spare slots,
+//    STRIDE = N + 4. Every pass's reads (32 consecutive elements) and writes
+//    (runs of 16 lanes: 8-element blocks in the first pass, two groups of 8
+//    lanes 64 apart in the second, 16 consecutive in the third) then fall in
+//    distinct banks, and the stride of 4 mod 32 spreads the 8 transforms of a
+//    workgroup over the banks for reads across transforms.
 template <int PAD>
 __device__ __forceinline__ int padi(int i) { return i + i / PAD; }
+__device__ __forceinline__ int swz512(int i) { return i ^ ((i >> 4) & 7) ^ (((i >> 6) & 1) << 3); }
 
 // a twiddle-table entry from LDS / generic memory, or from the global address
 // space (read as a plain vector: the float2 class cannot be copied from there)
@@ -240,8 +250,13 @@ __device__ __forceinline__ float2 ld_tw(const __attribute__((address_space(1))) 
 // buf: LDS; tw: this pass's twiddle table (see fft_lds), in LDS or, where a
 // workgroup's LDS is better spent on occupancy, in global memory (TW is then a
 // global-address-space pointer, read through the caches).
-template <int N, int R, int NS, int NTR, int STRIDE, int TPB, int PAD, typename TW>
-__device__ __forceinline__ void stockham_pass(float2* buf, TW tw, int tid) {
+template <int N> struct Lds;
+
+// ROT (last pass only, NS R = N): the outputs go out in plain order, rotated
+// down by `rot` blocks of NS: bin b + NS r to slot b + NS ((r - rot) mod R).
+template <int N, int R, int NS, int NTR, int STRIDE, int TPB, typename TW, bool ROT = false>
+__device__ __forceinline__ void stockham_pass(float2* buf, TW tw, int tid, int rot = 0) {
+  static_assert(!ROT || NS * R == N, "rotated output from the last pass only");
   constexpr int NB = N / R;
   constexpr int TOTAL = NTR * NB;
   constexpr int IT = (TOTAL + TPB - 1) / TPB;
@@ -252,8 +267,14 @@ __device__ __forceinline__ void stockham_pass(float2* buf, TW tw, int tid) {
     if (TOTAL % TPB == 0 || g < TOTAL) {
       const int tr = g / NB, b = g % NB;
       const float2* src = buf + tr * STRIDE;
+      if constexpr (Lds<N>::SWZ) {
+        const int fa = Lds<N>::at(b);
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[it][r] = src[padi<PAD>(b + r * NB)];
+        for (int r = 0; r < R; ++r) v[it][r] = src[Lds<N>::join(fa, r * NB)];
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[it][r] = src[Lds<N>::at(b + r * NB)];
+      }
     }
   }
   __syncthreads();
@@ -271,8 +292,20 @@ __device__ __forceinline__ void stockham_pass(float2* buf, TW tw, int tid) {
       dft<R>(v[it]);
       float2* dst = buf + tr * STRIDE;
       const int base = (b / NS) * NS * R + k;
+      if constexpr (ROT) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) dst[padi<PAD>(base + r * NS)] = v[it][r];
+        for (int r = 0; r < R; ++r) {
+          const int rr = r - rot < 0 ? r - rot + R : r - rot;    // uniform across the workgroup
+          dst[k + rr * NS] = v[it][r];
+        }
+      } else if constexpr (Lds<N>::SWZ) {
+        const int fa = Lds<N>::at(base);
+#pragma unroll
+        for (int r = 0; r < R; ++r) dst[Lds<N>::join(fa, r * NS)] = v[it][r];
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) dst[Lds<N>::at(base + r * NS)] = v[it][r];
+      }
     }
   }
   __syncthreads();
@@ -298,12 +331,29 @@ template <> struct FftPlan<672>  { static constexpr int R0 = 32, R1 = 21, R2 = 1
 template <> struct FftPlan<1024> { static constexpr int R0 = 16, R1 = 8,  R2 = 8; };
 template <> struct FftPlan<2048> { static constexpr int R0 = 16, R1 = 16, R2 = 8; };
 
-// padded layout of a length-N transform in LDS
+// layout of a length-N transform in LDS (see stockham_pass)
 template <int N> struct Lds {
+  static constexpr bool SWZ = N == 512;
   static constexpr int PAD = FftPlan<N>::R0;
-  static constexpr int SPAN = N + (N - 1) / PAD + 1;            // padded length
-  static constexpr int STRIDE = SPAN | 1;                        // odd transform stride
-  __device__ static __forceinline__ int at(int i) { return padi<PAD>(i); }
+  static constexpr int SPAN = SWZ ? N : N + (N - 1) / PAD + 1;  // slots one transform covers
+  static constexpr int STRIDE = SWZ ? N + 4 : SPAN | 1;         // transform stride
+  __device__ static __forceinline__ int at(int i) {
+    if constexpr (SWZ)
+      return swz512(i);
+    else
+      return padi<PAD>(i);
+  }
+  // swizzled layout: at(a + c) for a lane part a and a compile-time part c
+  // with no common bits, given fa = at(a). The swizzle is linear over XOR and
+  // changes bits 0..3 only, so at(a + c) = fa ^ at(c); where fa has no bits
+  // in at(c)'s bits 4 and up (true for every split the passes make: the
+  // constant part sits above the lane part's bits, or between its groups of
+  // bits with at(a) clear there), that XOR is a small XOR plus an add, which
+  // folds into the LDS instruction's immediate offset.
+  __device__ static __forceinline__ int join(int fa, int c) {
+    const int ac = swz512(c);
+    return (fa ^ (ac & 15)) + (ac & ~15);
+  }
 };
 
 // ---------------------------------------------------------------------------
@@ -329,9 +379,18 @@ __device__ __forceinline__ void fft_pass1_regs(float2 (*v)[FftPlan<N>::R0], floa
     if (Q::TOTAL % TPB == 0 || g < Q::TOTAL) {
       const int tr = g / NB, b = g % NB;
       dft<R0>(v[it]);
-      float2* dst = buf + tr * STRIDE + padi<R0>(b * R0);
+      if constexpr (Lds<N>::SWZ) {
+        // at(b R0 + r) = at(b R0) ^ r: the swizzle reads bits above the first radix
+        // (in bytes, so that the XOR and the transform offset fold into one add)
+        char* dst = reinterpret_cast<char*>(buf + tr * STRIDE);
+        const int a8 = Lds<N>::at(b * R0) * 8;
 #pragma unroll
-      for (int r = 0; r < R0; ++r) dst[r] = v[it][r];   // padi(b R0 + r) = padi(b R0) + r
+        for (int r = 0; r < R0; ++r) *reinterpret_cast<float2*>(dst + (a8 ^ (r * 8))) = v[it][r];
+      } else {
+        float2* dst = buf + tr * STRIDE + padi<R0>(b * R0);
+#pragma unroll
+        for (int r = 0; r < R0; ++r) dst[r] = v[it][r];   // padi(b R0 + r) = padi(b R0) + r
+      }
     }
   }
 }
@@ -340,11 +399,31 @@ __device__ __forceinline__ void fft_pass1_regs(float2 (*v)[FftPlan<N>::R0], floa
 template <int N, int NTR, int STRIDE, int TPB, typename TW>
 __device__ __forceinline__ void fft_rest(float2* buf, TW tw, int tid) {
   using P = FftPlan<N>;
-  constexpr int PAD = P::R0;
   __syncthreads();
-  if constexpr (P::R1 > 1) stockham_pass<N, P::R1, P::R0, NTR, STRIDE, TPB, PAD>(buf, tw, tid);
+  if constexpr (P::R1 > 1) stockham_pass<N, P::R1, P::R0, NTR, STRIDE, TPB>(buf, tw, tid);
   constexpr int OFF2 = (P::R1 - 1) * P::R0;
-  if constexpr (P::R2 > 1) stockham_pass<N, P::R2, P::R0 * P::R1, NTR, STRIDE, TPB, PAD>(buf, tw + OFF2, tid);
+  if constexpr (P::R2 > 1) stockham_pass<N, P::R2, P::R0 * P::R1, NTR, STRIDE, TPB>(buf, tw + OFF2, tid);
+}
+
+// Passes 2.. as fft_rest, the last one writing its outputs in plain order,
+// rotated so that bin (rot NSL + i) mod N lands at slot i of the transform
+// (NSL = the last pass's NS = N / its radix; 0 <= rot < that radix). Needs a
+// plan of two or more passes.
+template <int N> constexpr int last_ns() {
+  return FftPlan<N>::R2 > 1 ? FftPlan<N>::R0 * FftPlan<N>::R1 : FftPlan<N>::R0;
+}
+template <int N, int NTR, int STRIDE, int TPB, typename TW>
+__device__ __forceinline__ void fft_rest_rot(float2* buf, TW tw, int tid, int rot) {
+  using P = FftPlan<N>;
+  static_assert(P::R1 > 1, "a single-pass plan has no later pass to rotate");
+  __syncthreads();
+  if constexpr (P::R2 > 1) {
+    stockham_pass<N, P::R1, P::R0, NTR, STRIDE, TPB>(buf, tw, tid);
+    constexpr int OFF2 = (P::R1 - 1) * P::R0;
+    stockham_pass<N, P::R2, P::R0 * P::R1, NTR, STRIDE, TPB, TW, true>(buf, tw + OFF2, tid, rot);
+  } else {
+    stockham_pass<N, P::R1, P::R0, NTR, STRIDE, TPB, TW, true>(buf, tw, tid, rot);
+  }
 }
 
 // forward FFT of NTR transforms of length N held in LDS (padded layout of
@@ -354,13 +433,12 @@ __device__ __forceinline__ void fft_rest(float2* buf, TW tw, int tid) {
 template <int N, int NTR, int STRIDE, int TPB, typename TW>
 __device__ __forceinline__ void fft_lds(float2* buf, TW tw, int tid) {
   using P = FftPlan<N>;
-  constexpr int PAD = Lds<N>::PAD;
   static_assert(P::R0 * P::R1 * P::R2 == N, "bad factorisation");
   static_assert(STRIDE >= Lds<N>::SPAN, "stride too small");
-  stockham_pass<N, P::R0, 1, NTR, STRIDE, TPB, PAD>(buf, tw, tid);
-  if constexpr (P::R1 > 1) stockham_pass<N, P::R1, P::R0, NTR, STRIDE, TPB, PAD>(buf, tw, tid);
+  stockham_pass<N, P::R0, 1, NTR, STRIDE, TPB>(buf, tw, tid);
+  if constexpr (P::R1 > 1) stockham_pass<N, P::R1, P::R0, NTR, STRIDE, TPB>(buf, tw, tid);
   constexpr int OFF2 = (P::R1 - 1) * P::R0;
-  if constexpr (P::R2 > 1) stockham_pass<N, P::R2, P::R0 * P::R1, NTR, STRIDE, TPB, PAD>(buf, tw + OFF2, tid);
+  if constexpr (P::R2 > 1) stockham_pass<N, P::R2, P::R0 * P::R1, NTR, STRIDE, TPB>(buf, tw + OFF2, tid);
 }
 
 }  // namespace dh

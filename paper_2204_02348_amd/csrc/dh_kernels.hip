@@ -395,11 +395,17 @@ __global__ void __launch_bounds__(kTPB) k_col(KArgs A, int b0) {
 // tiles (gp > 16 NT, up to kMaxGp); the contraction then runs once per chunk
 // of NT tiles over the same window in LDS, each chunk's Q columns collected in
 // LDS before the final product (tables of gp columns; MC = false: gp = 16 NT).
+// ROT (swizzled layouts): the column FFT's last pass writes the bins in plain
+// order rotated so that window row i (bin ky0 + i) sits at slot B + i, B < the
+// last pass's block; the A operands are then read at fixed offsets per step,
+// each lane reading its own real or imaginary part, and a transform stride of
+// 2 mod 16 puts the 32 lanes of a read in distinct banks.
 template <int NY, int WY, int CG, int NT, bool MC>
 struct CspecShape {
-  static constexpr int ST = Lds<NY>::STRIDE;
-  static constexpr int MT = (2 * CG + 15) / 16;          // A-row tiles
   static constexpr int WYP = (WY + 15) / 16 * 16;
+  static constexpr bool ROT = Lds<NY>::SWZ && last_ns<NY>() + WYP <= NY;
+  static constexpr int ST = ROT ? NY + 2 : Lds<NY>::STRIDE;
+  static constexpr int MT = (2 * CG + 15) / 16;          // A-row tiles
   static constexpr int KSW = WYP / 16;                    // K steps per wave, at most
   static constexpr int GP = 16 * NT;                      // mode columns per chunk
   static constexpr int GPM = MC ? kMaxGp : GP;            // mode columns held in LDS, at most
@@ -431,7 +437,8 @@ __device__ __forceinline__ void cspec_block(const KArgs& A, int b0, int cb, int 
   using Q = Pass1<NY, CG, kTPB>;
   constexpr int ST = SH::ST, MT = SH::MT, WYP = SH::WYP, KSW = SH::KSW, GP = SH::GP, GPM = SH::GPM;
   constexpr int NRED = SH::NRED, NQ = SH::NQ;
-  constexpr bool IN_BUF = SH::IN_BUF, TWG = SH::TWG;
+  constexpr bool IN_BUF = SH::IN_BUF, TWG = SH::TWG, ROT = SH::ROT;
+  static_assert(!ROT || MT == 1, "rotated reads take one A-row tile");
   static_assert(KSW * NT <= 96, "B operands are held in registers");
   const int lane = tid & 63, wv = tid >> 6;
   const PolTab& P = A.pol[p];
@@ -487,10 +494,21 @@ __device__ __forceinline__ void cspec_block(const KArgs& A, int b0, int cb, int 
     sx.store(s_x, ncx * gpt, make_float2(0.f, 0.f), tid);
     fft_pass1_regs<NY, CG, ST, kTPB>(v, buf, tid);
   }
-  if constexpr (TWG)
-    fft_rest<NY, CG, ST, kTPB>(buf, as_global(A.tw_ny), tid);
-  else
-    fft_rest<NY, CG, ST, kTPB>(buf, static_cast<const float2*>(twy), tid);
+  // window row i is bin (ky0 + i) mod NY; with ROT at slot rb + i
+  int kyn = P.ky0 % NY;
+  if (kyn < 0) kyn += NY;
+  const int rrot = kyn / last_ns<NY>(), rb = kyn - rrot * last_ns<NY>();
+  if constexpr (ROT) {
+    if constexpr (TWG)
+      fft_rest_rot<NY, CG, ST, kTPB>(buf, as_global(A.tw_ny), tid, rrot);
+    else
+      fft_rest_rot<NY, CG, ST, kTPB>(buf, static_cast<const float2*>(twy), tid, rrot);
+  } else {
+    if constexpr (TWG)
+      fft_rest<NY, CG, ST, kTPB>(buf, as_global(A.tw_ny), tid);
+    else
+      fft_rest<NY, CG, ST, kTPB>(buf, static_cast<const float2*>(twy), tid);
+  }
   if (A.window) {
     // window = M * I~ = conj(val) (-1)^(u+v) Nx Ny at (v mod wy, u mod wx), as in k_col
     float2* win = A.window + ((size_t)(b0 + bl) * A.npol + p) * A.wy * A.wx;
@@ -505,7 +523,7 @@ __device__ __forceinline__ void cspec_block(const KArgs& A, int b0, int cb, int 
       if (j < mr.x || j > mr.y) continue;
       int vv = (P.ky0 + i) % NY;
       if (vv < 0) vv += NY;
-      const float2 val = cmul(cmul(buf[c * ST + LN::at(vv)], conjf2(P.rhox[j])), conjf2(P.rhoy[i]));
+      const float2 val = cmul(cmul(buf[c * ST + (ROT ? rb + i : LN::at(vv))], conjf2(P.rhox[j])), conjf2(P.rhoy[i]));
       const int u = -(P.k0 + j), v = -(P.ky0 + i);
       int qu = u % A.wx;
       if (qu < 0) qu += A.wx;
@@ -544,15 +562,23 @@ __device__ __forceinline__ void cspec_block(const KArgs& A, int b0, int cb, int 
       constexpr int DA = KSW <= 16 ? KSW : 12;
       int2 mv[KSW];
       float2 fv[KSW][MT];
+      float fr[KSW];                                // ROT: this lane's part of the step's value
       int i = 4 * wv + (lane >> 4);                 // box row of the next step to read
       int vv = (P.ky0 + i) % NY;                    // its column-FFT bin
       if (vv < 0) vv += NY;
+      // ROT: float index of (column, part) at window row i; a step moves 16 rows
+      const float* bfl = reinterpret_cast<const float*>(buf) +
+                         2 * (((lane & 15) % CG) * ST + rb + i) + (((lane & 15) / CG) & 1);
 #pragma unroll
       for (int t = 0; t < KSW + DA; ++t) {
         if (t < KSW) {                              // read step t (compile-time after unrolling)
           mv[t] = s_mrow[i];                        // i < 16 KSW = WYP
+          if constexpr (ROT) {
+            fr[t] = bfl[32 * t];
+          } else {
 #pragma unroll
-          for (int mt = 0; mt < MT; ++mt) fv[t][mt] = buf[((mt * 16 + (lane & 15)) % CG) * ST + LN::at(vv)];
+            for (int mt = 0; mt < MT; ++mt) fv[t][mt] = buf[((mt * 16 + (lane & 15)) % CG) * ST + LN::at(vv)];
+          }
           i += 16;
           vv += 16;
           if (vv >= NY) vv -= NY;
@@ -573,7 +599,11 @@ __device__ __forceinline__ void cspec_block(const KArgs& A, int b0, int cb, int 
             const int part = r / CG;
             const int ja = jc0 + r % CG;
             const bool ok = part < 2 && ja >= mv[u].x && ja <= mv[u].y;
-            const float a = ok ? (part ? fv[u][mt].y : fv[u][mt].x) : 0.f;
+            float a;
+            if constexpr (ROT)
+              a = ok ? fr[u] : 0.f;
+            else
+              a = ok ? (part ? fv[u][mt].y : fv[u][mt].x) : 0.f;
             if (ch == 0) pw = fmaf(a, a, pw);
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
