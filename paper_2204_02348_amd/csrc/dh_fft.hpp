@@ -227,16 +227,20 @@ __device__ __forceinline__ void dft(float2* v) {
 // is bank (index mod 32) for reads, (index mod 16) for writes). Two layouts:
 //  - padded: element i at i + i / PAD (one spare slot after every PAD = R0
 //    elements), transform t at t * STRIDE (odd STRIDE >= the padded length);
-//  - swizzled (the 8 x 8 x 8 plan of 512 points): element i at i XOR s(i),
-//    s moving bits 4..6 onto bits 0..2 and bit 6 onto bit 3, no spare slots,
-//    STRIDE = N + 4. Every pass's reads (32 consecutive elements) and writes
-//    (runs of 16 lanes: 8-element blocks in the first pass, two groups of 8
-//    lanes 64 apart in the second, 16 consecutive in the third) then fall in
-//    distinct banks, and the stride of 4 mod 32 spreads the 8 transforms of a
+//  - swizzled (512 = 8 x 8 x 8, 1024 = 16 x 8 x 8, 2048 = 16 x 16 x 8):
+//    element i at i XOR s(i), no spare slots, STRIDE = N + 4. For 512, s moves
+//    bits 4..6 onto bits 0..2 and bit 6 onto bit 3; for the plans that start
+//    with radix 16, s moves bits 4..7 onto bits 0..3. Every pass's reads (32
+//    consecutive elements) and writes (runs of 16 lanes: R0-element blocks in
+//    the first pass, groups of NS lanes in the later ones) then fall in
+//    distinct banks, and the stride of 4 mod 32 spreads the transforms of a
 //    workgroup over the banks for reads across transforms.
 template <int PAD>
 __device__ __forceinline__ int padi(int i) { return i + i / PAD; }
-__device__ __forceinline__ int swz512(int i) { return i ^ ((i >> 4) & 7) ^ (((i >> 6) & 1) << 3); }
+template <int N>
+__host__ __device__ constexpr int swz(int i) {
+  return N == 512 ? i ^ ((i >> 4) & 7) ^ (((i >> 6) & 1) << 3) : i ^ ((i >> 4) & 15);
+}
 
 // a twiddle-table entry from LDS / generic memory, or from the global address
 // space (read as a plain vector: the float2 class cannot be copied from there)
@@ -333,13 +337,13 @@ template <> struct FftPlan<2048> { static constexpr int R0 = 16, R1 = 16, R2 = 8
 
 // layout of a length-N transform in LDS (see stockham_pass)
 template <int N> struct Lds {
-  static constexpr bool SWZ = N == 512;
+  static constexpr bool SWZ = N == 512 || N == 1024 || N == 2048;
   static constexpr int PAD = FftPlan<N>::R0;
   static constexpr int SPAN = SWZ ? N : N + (N - 1) / PAD + 1;  // slots one transform covers
   static constexpr int STRIDE = SWZ ? N + 4 : SPAN | 1;         // transform stride
   __device__ static __forceinline__ int at(int i) {
     if constexpr (SWZ)
-      return swz512(i);
+      return swz<N>(i);
     else
       return padi<PAD>(i);
   }
@@ -351,7 +355,7 @@ template <int N> struct Lds {
   // bits with at(a) clear there), that XOR is a small XOR plus an add, which
   // folds into the LDS instruction's immediate offset.
   __device__ static __forceinline__ int join(int fa, int c) {
-    const int ac = swz512(c);
+    const int ac = swz<N>(c);
     return (fa ^ (ac & 15)) + (ac & ~15);
   }
 };

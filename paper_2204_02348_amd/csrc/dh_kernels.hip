@@ -1217,8 +1217,9 @@ static hipError_t row_n(const KArgs& a, const void* frames, int u16, int b0, int
   // tile's transform) when that still leaves the chip well filled; one tile
   // for small batches, where latency matters more
   const int nyb = (a.ny + 2 * TR - 1) / (2 * TR);
-  // one tile at 2048: the second tile's registers would cost a workgroup per CU
-  const bool two = NX < 2048 && (long)((nyb + 1) / 2) * a.npol * nb >= 4096;
+  // one tile from 1024 points: the second tile's registers would cost a
+  // workgroup per CU
+  const bool two = NX < 1024 && (long)((nyb + 1) / 2) * a.npol * nb >= 4096;
   dim3 grid(two ? (nyb + 1) / 2 : nyb, a.npol, nb);
   if (u16) {
     if (two)
