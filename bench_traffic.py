@@ -57,8 +57,8 @@ def main():
     ap.add_argument("--copy-write", required=True)
     ap.add_argument("--fetch", required=True)
     ap.add_argument("--write", required=True)
-    ap.add_argument("--frames-per-step", type=int, required=True)
-    ap.add_argument("--steps", type=int, required=True, help="batches processed in the profiled run")
+    ap.add_argument("--frames-per-launch", type=int, required=True,
+                    help="frames each launch of the bench's kernels processes")
     ap.add_argument("--name", required=True)
     ap.add_argument("--command", required=True, help="the profiled command, recorded in the output")
     a = ap.parse_args()
@@ -68,17 +68,20 @@ def main():
     w_scale = COPY_BYTES / (cw * 1024)
     fetch = per_kernel(a.fetch, "FETCH_SIZE")
     write = per_kernel(a.write, "WRITE_SIZE")
-    frames = a.frames_per_step * a.steps
+    # each counter run is averaged over its own dispatches (the two runs can
+    # process different batch counts: the bench's clock settling is timed)
+    fpl = a.frames_per_launch
     kernels = {}
     for k in fetch:
+        w = write.get(k, [0.0, 1])
         kernels[k] = {
-            "read_bytes_per_frame": fetch[k][0] * 1024 * f_scale / frames,
-            "write_bytes_per_frame": write.get(k, [0.0, 0])[0] * 1024 * w_scale / frames,
-            "dispatches": fetch[k][1],
+            "read_bytes_per_frame": fetch[k][0] / fetch[k][1] * 1024 * f_scale / fpl,
+            "write_bytes_per_frame": w[0] / max(w[1], 1) * 1024 * w_scale / fpl,
+            "dispatches": [fetch[k][1], w[1]],
         }
     out = {"name": a.name, "fingerprint": source_fingerprint(), "fetch_scale": f_scale, "write_scale": w_scale,
            "copy_counter_kb": {"FETCH_SIZE": cf, "WRITE_SIZE": cw, "copy_bytes": COPY_BYTES},
-           "frames_profiled": frames, "command": a.command, "kernels": kernels}
+           "frames_per_launch": fpl, "command": a.command, "kernels": kernels}
     path = os.path.join(HERE, "profiles", f"traffic_{a.name}.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
