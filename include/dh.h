@@ -216,7 +216,7 @@ int dh_process_batch(dh_handle h, const void* frames, int batch, void* stream);
  * x (pol x mode), row p*batch + b holds frame b's pol-p coefficients in pol
  * p's columns and zeros in the other pol's (a missing pol gives MDL = -inf).
  * IL and MDL come from the singular values of A (eigenvalues of the smaller
- * Gram matrix, FP64, by the library's cyclic Jacobi kernel; a smaller side
+ * Gram matrix, FP64, by the library's eigenvalue kernel; a smaller side
  * above 2048 is refused with DH_ERR_ERROR); the diagonal and SNR metrics from D = A
  * (mul_conj_trans 0) or D = A A^H (1), with entry (i, i) as the diagonal for
  * i < min(rows, cols of D); row i of A stands for the mode of column i, which
@@ -234,10 +234,13 @@ int dh_transfer_metrics(dh_handle h, int pol_independent, int mul_conj_trans, do
  * the square roots of the eigenvalues of its Gram matrix). a_host: n x n
  * Hermitian matrix in host memory, complex FP64 interleaved (re, im),
  * column-major (only its Hermitian part is meaningful); w_host: n eigenvalues
- * out, ascending. Runs the library's FP64 cyclic Jacobi kernel on the current
- * device (one workgroup) on `stream` and waits for it; allocates and frees a
- * device copy of the matrix. Errors: DH_ERR_NULLPOINTER, DH_ERR_INVALIDDIMENSION
- * (n < 1 or n > 2048), DH_ERR_MEMORYALLOCATION, DH_ERR_ERROR (no convergence).
+ * out, ascending. Runs the library's FP64 kernel (Householder reduction to a
+ * real tridiagonal matrix, then bisection with Sturm counts; every eigenvalue
+ * within a small multiple of n eps |A| of the exact one) on the current device
+ * (one workgroup) on `stream` and waits for it; allocates and frees a device
+ * copy of the matrix. Errors: DH_ERR_NULLPOINTER, DH_ERR_INVALIDDIMENSION
+ * (n < 1 or n > 2048), DH_ERR_MEMORYALLOCATION, DH_ERR_ERROR (entries that are
+ * not finite, or a HIP call failed).
  */
 int dh_hermitian_eigenvalues(const double* a_host, int n, double* w_host, void* stream);
 
@@ -252,8 +255,8 @@ int dh_hermitian_eigenvalues(const double* a_host, int n, double* w_host, void* 
  * ends). Runs on `stream` on the current device and waits for it. Calls that
  * overlap on one GPU share that array and race: issue them from one thread
  * and stream per GPU. Errors: DH_ERR_NULLPOINTER, DH_ERR_INVALIDDIMENSION
- * (n < 1 or n > DH_NOALLOC_EIG_MAX_N), DH_ERR_ERROR (no convergence, or a HIP
- * call failed).
+ * (n < 1 or n > DH_NOALLOC_EIG_MAX_N), DH_ERR_ERROR (entries that are not
+ * finite, or a HIP call failed).
  */
 #define DH_NOALLOC_EIG_MAX_N 256
 int dh_hermitian_eigenvalues_noalloc(const double* a_dev, int n, double* w_dev, void* stream);

@@ -272,8 +272,9 @@ def _stream(s) -> int:
 
 
 def hermitian_eigenvalues(a, stream=None) -> np.ndarray:
-    """Eigenvalues (ascending) of a Hermitian matrix by the library's Jacobi
-    kernel (dh_hermitian_eigenvalues): the eigen step of the MDL metric."""
+    """Eigenvalues (ascending) of a Hermitian matrix by the library's FP64
+    eigenvalue kernel (dh_hermitian_eigenvalues): the eigen step of the MDL
+    metric."""
     m = np.asfortranarray(np.asarray(a, dtype=np.complex128))
     n = m.shape[0]
     if m.shape != (n, n):

@@ -1429,7 +1429,7 @@ int tm_compute(Plan* pl, int B, int pol_independent, int mul_conj_trans, hipStre
   if (hipMemcpyAsync(res.data(), m + ores, nres * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return DH_ERR_ERROR;
-  int info = 1;                          // the eigen-solver's sweeps, -1 if it did not converge
+  int info = 0;                          // the eigen-solver's status: -1 if the matrix was not finite
   if (eig) std::memcpy(&info, &res[nres - 1], sizeof(info));
   if (info < 0) return DH_ERR_ERROR;
   const double* eigv = res.data();

@@ -9,8 +9,9 @@
 //   k_tm_diag  the Gram matrix's diagonal (IL is its trace over n)
 //   k_summ, k_isum  batch summary: the sums of each plane's parameters, and
 //              the intensity summed over the batch
-//   k_heig     eigenvalues of the Gram matrix (FP64 cyclic Jacobi, one
-//              workgroup): the squared singular values for MDL
+//   k_heig     eigenvalues of the Gram matrix (FP64 Householder reduction to
+//              a tridiagonal, then bisection; one workgroup): the squared
+//              singular values for MDL
 //   k_q16      fields to int16 real and imaginary parts with one scale each
 //   k_basis    HG coefficients to another basis (LG, custom): one matrix product
 //   k_m0y, k_m0x  IFFT mode 0 field export: the window zero-padded to the FFT
@@ -187,144 +188,195 @@ hipError_t launch_tm_diag(const double2* g, int n, double* out, hipStream_t s) {
 
 // ---------------------------------------------------------------------------
 // k_heig: every eigenvalue of an n x n Hermitian matrix (FP64 complex,
-// column-major, overwritten) by cyclic two-sided Jacobi, in one workgroup.
-// The sweep is a round-robin tournament over the indices (padded to even m):
-// in each of its m - 1 rounds the m/2 index pairs are disjoint, so their plane
-// rotations are applied together, first to the columns (A U), then to the
-// rows (U^H A U). For a pair (p, q) with a_pq = |a_pq| e^{i phi}, U is the
-// real rotation by theta (tan 2 theta = 2|a_pq| / (a_qq - a_pp), |theta| <=
-// pi/4) after the phase e^{-i phi} on index q; it zeroes a_pq and a_qp and
-// moves the diagonal to a_pp - t|a_pq| and a_qq + t|a_pq|, t = tan theta.
-// A pair is left alone when |a_pq| <= 1e-15 sqrt(|a_pp a_qq|) (the relative
-// test that keeps small eigenvalues of a semi-definite matrix accurate) or
-// below an absolute floor tied to the trace; the matrix is converged when a
-// whole sweep rotates nothing. info = sweeps used, or -1 if kMaxSweeps did not
-// converge. The eigenvalues go to w in ascending order. Matrices up to
-// kHeigLds rows are worked on in LDS, larger ones (up to kHeigMaxN) in place
-// in global memory.
+// column-major, overwritten), in one workgroup, in two textbook steps:
+//  1. Householder reduction to a real symmetric tridiagonal matrix. The input
+//     is first replaced by its Hermitian part (A + A^H) / 2, both triangles
+//     stored. For column k, x = A(k+1.., k): a reflector H = I - tau u u^H
+//     (u(0) = 1) with H^H x = beta e1, beta = -sign(Re x0) |x| real, then
+//     A22 <- H^H A22 H on the trailing block as the rank-2 update
+//     A22 - u w^H - w u^H, p = tau A22 u, w = p - (tau / 2)(p^H u) u.
+//     The tridiagonal keeps d_k = A(k, k) and the off-diagonal beta_k (real:
+//     a Hermitian tridiagonal with off-diagonal e_k has the same eigenvalues
+//     as the real one with |e_k|).
+//  2. Bisection with Sturm counts: the number of eigenvalues below x is the
+//     number of negative q_i in q_0 = d_0 - x, q_i = d_i - x - e_{i-1}^2 /
+//     q_{i-1}; thread t narrows the Gershgorin interval to eigenvalue t until
+//     it is a few ulps wide, so w comes out in ascending order.
+// The reduction is backward stable in FP64, so every eigenvalue is within a
+// small multiple of n eps |A| of the exact one. info = 0, or -1 when the
+// tridiagonal is not finite (w is then NaN). Matrices up to kHeigLds rows
+// are worked on in LDS, larger ones (up to kHeigMaxN) in place in global
+// memory.
 constexpr int kHeigLds = 96;
 constexpr int kHeigMaxN = 2048;
-constexpr int kHeigThreads = 1024;
-constexpr int kMaxSweeps = 60;
+constexpr int kHeigThreads = 256;
 
 __device__ __forceinline__ double2 zmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 zcmul(double2 a, double2 b) {     // conj(a) b
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+
+// sum over the workgroup of (x, y); every thread gets it. buf: 2 NW doubles,
+// alternated between calls by the caller so that one barrier suffices
+template <int NW>
+__device__ __forceinline__ double2 heig_sum(double2 v, double* buf, int tid) {
+  for (int off = 32; off > 0; off >>= 1) {
+    v.x += __shfl_xor(v.x, off, 64);
+    v.y += __shfl_xor(v.y, off, 64);
+  }
+  if ((tid & 63) == 0) {
+    buf[2 * (tid >> 6)] = v.x;
+    buf[2 * (tid >> 6) + 1] = v.y;
+  }
+  __syncthreads();
+  double2 r = make_double2(0.0, 0.0);
+  for (int k = 0; k < NW; ++k) {
+    r.x += buf[2 * k];
+    r.y += buf[2 * k + 1];
+  }
+  return r;
 }
 
 template <bool IN_LDS>
 __global__ void __launch_bounds__(kHeigThreads) k_heig(double2* __restrict__ g, int n, double* __restrict__ w,
                                                        int* __restrict__ info) {
-  constexpr int NP = IN_LDS ? kHeigLds / 2 : kHeigMaxN / 2;   // index pairs per round, at most
+  constexpr int NV = IN_LDS ? kHeigLds : kHeigMaxN;
+  constexpr int NW = kHeigThreads / 64;
   __shared__ double2 lds[IN_LDS ? kHeigLds * kHeigLds : 1];
-  __shared__ double s_c[NP], s_s[NP], s_app[NP], s_aqq[NP];
-  __shared__ double2 s_ph[NP];
-  __shared__ int s_p[NP], s_q[NP], s_rot[NP];
-  __shared__ int s_count;
-  __shared__ double s_red[kHeigThreads / 64];
-  const int tid = threadIdx.x;
+  __shared__ double2 s_u[NV], s_w[NV];
+  __shared__ double s_d[NV], s_e2[NV];
+  __shared__ double s_red[2][2 * NW];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   double2* a = IN_LDS ? lds : g;
-  if constexpr (IN_LDS)
-    for (int e = tid; e < n * n; e += kHeigThreads) lds[e] = g[e];
-  const int m = n + (n & 1);
-  const int half = m / 2;
-  // absolute floor: entries this small next to the trace are rounding dust
-  double tr = 0.0;
-  for (int i = tid; i < n; i += kHeigThreads) tr += fabs(g[(size_t)i * (n + 1)].x);
-  for (int off = 32; off > 0; off >>= 1) tr += __shfl_xor(tr, off, 64);
-  if ((tid & 63) == 0) s_red[tid >> 6] = tr;
+  // the Hermitian part, both triangles (each pair read and written by one thread)
+  for (int e = tid; e < n * n; e += kHeigThreads) {
+    const int i = e % n, j = e / n;
+    if (i < j) continue;
+    const double2 x = g[i + (size_t)j * n], y = g[j + (size_t)i * n];
+    const double2 h = make_double2(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
+    if (i == j) {
+      a[i + (size_t)j * n] = make_double2(h.x, 0.0);
+    } else {
+      a[i + (size_t)j * n] = h;
+      a[j + (size_t)i * n] = make_double2(h.x, -h.y);
+    }
+  }
   __syncthreads();
-  tr = 0.0;
-  for (int k = 0; k < kHeigThreads / 64; ++k) tr += s_red[k];
-  const double floor_abs = 1e-300 + 1e-30 * tr;
-  int sweep = 0;
-  bool done = n < 2;
-  while (!done && sweep < kMaxSweeps) {
-    if (tid == 0) s_count = 0;
+  int rb = 0;                                    // s_red half for the next sum
+  for (int k = 0; k + 2 < n; ++k) {
+    const int k1 = k + 1, m = n - k1;
+    const double2* col = a + k1 + (size_t)k * n;   // x = A(k1 .., k), m entries
+    double2 part = make_double2(0.0, 0.0);
+    for (int i = 1 + tid; i < m; i += kHeigThreads) part.x += col[i].x * col[i].x + col[i].y * col[i].y;
+    const double ss = heig_sum<NW>(part, s_red[rb], tid).x;
+    rb ^= 1;
+    const double2 x0 = col[0];
+    // every thread forms the same reflector from the same values
+    const bool ident = ss == 0.0 && x0.y == 0.0;
+    const double nrm = sqrt(x0.x * x0.x + x0.y * x0.y + ss);
+    const double beta = ident ? x0.x : (x0.x >= 0.0 ? -nrm : nrm);
+    if (tid == 0) {
+      s_d[k] = a[k + (size_t)k * n].x;
+      s_e2[k] = beta * beta;
+    }
+    if (ident) continue;                          // H = I (uniform across the workgroup)
+    const double2 tau = make_double2((beta - x0.x) / beta, -x0.y / beta);
+    // u = x / (x0 - beta), u(0) = 1
+    const double2 den = make_double2(x0.x - beta, x0.y);
+    const double dd = den.x * den.x + den.y * den.y;
+    const double2 sc = make_double2(den.x / dd, -den.y / dd);
+    for (int i = tid; i < m; i += kHeigThreads) s_u[i] = i == 0 ? make_double2(1.0, 0.0) : zmul(col[i], sc);
     __syncthreads();
-    for (int r = 0; r < m - 1; ++r) {
-      // rotation of each pair from the matrix before this round
-      for (int k = tid; k < half; k += kHeigThreads) {
-        int p, q;
-        if (k == 0) {
-          p = m - 1;
-          q = r;
-        } else {
-          p = (r + k) % (m - 1);
-          q = (r - k + (m - 1)) % (m - 1);
-        }
-        if (p > q) { const int t = p; p = q; q = t; }
-        s_p[k] = p;
-        s_q[k] = q;
-        int rot = 0;
-        if (q < n) {
-          const double app = a[(size_t)p * n + p].x, aqq = a[(size_t)q * n + q].x;
-          const double2 apq = a[(size_t)q * n + p];                    // row p, column q
-          const double mag = hypot(apq.x, apq.y);
-          if (mag > floor_abs && mag > 1e-15 * sqrt(fabs(app * aqq))) {
-            const double tau = (aqq - app) / (2.0 * mag);
-            const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            const double c = 1.0 / sqrt(1.0 + t * t);
-            s_c[k] = c;
-            s_s[k] = t * c;
-            s_ph[k] = make_double2(apq.x / mag, apq.y / mag);
-            s_app[k] = app - t * mag;
-            s_aqq[k] = aqq + t * mag;
-            rot = 1;
-            atomicAdd(&s_count, 1);
-          }
-        }
-        s_rot[k] = rot;
+    // p = tau A22 u: p_i = sum_j A22(i, j) u_j = sum_j conj(A22(j, i)) u_j,
+    // column k1 + i read contiguously, one wave per i
+    for (int i = wv; i < m; i += NW) {
+      const double2* ci = a + k1 + (size_t)(k1 + i) * n;
+      double2 acc = make_double2(0.0, 0.0);
+      for (int j = lane; j < m; j += 64) {
+        const double2 t = zcmul(ci[j], s_u[j]);
+        acc.x += t.x;
+        acc.y += t.y;
       }
-      __syncthreads();
-      // columns: col_p <- c col_p - s e^{-i phi} col_q, col_q <- s col_p + c e^{-i phi} col_q
-      for (int e = tid; e < half * n; e += kHeigThreads) {
-        const int k = e / n, i = e - k * n;
-        if (!s_rot[k]) continue;
-        const int p = s_p[k], q = s_q[k];
-        const double c = s_c[k], sn = s_s[k];
-        const double2 ph = make_double2(s_ph[k].x, -s_ph[k].y);
-        const double2 x = a[(size_t)p * n + i], y = zmul(ph, a[(size_t)q * n + i]);
-        a[(size_t)p * n + i] = make_double2(c * x.x - sn * y.x, c * x.y - sn * y.y);
-        a[(size_t)q * n + i] = make_double2(sn * x.x + c * y.x, sn * x.y + c * y.y);
+      for (int off = 32; off > 0; off >>= 1) {
+        acc.x += __shfl_xor(acc.x, off, 64);
+        acc.y += __shfl_xor(acc.y, off, 64);
       }
-      __syncthreads();
-      // rows: row_p <- c row_p - s e^{i phi} row_q, row_q <- s row_p + c e^{i phi} row_q;
-      // the pair's own 2 x 2 block takes its exact values
-      for (int e = tid; e < half * n; e += kHeigThreads) {
-        const int k = e / n, j = e - k * n;
-        if (!s_rot[k]) continue;
-        const int p = s_p[k], q = s_q[k];
-        if (j == p || j == q) {
-          a[(size_t)j * n + p] = j == p ? make_double2(s_app[k], 0.0) : make_double2(0.0, 0.0);
-          a[(size_t)j * n + q] = j == q ? make_double2(s_aqq[k], 0.0) : make_double2(0.0, 0.0);
-          continue;
-        }
-        const double c = s_c[k], sn = s_s[k];
-        const double2 x = a[(size_t)j * n + p], y = zmul(s_ph[k], a[(size_t)j * n + q]);
-        a[(size_t)j * n + p] = make_double2(c * x.x - sn * y.x, c * x.y - sn * y.y);
-        a[(size_t)j * n + q] = make_double2(sn * x.x + c * y.x, sn * x.y + c * y.y);
-      }
-      __syncthreads();
+      if (lane == 0) s_w[i] = zmul(tau, acc);
     }
-    ++sweep;
-    done = s_count == 0;
-    __syncthreads();                 // every thread has read s_count
-  }
-  // the eigenvalues in ascending order: each goes to its rank in a strict
-  // total order (value, then index; NaN after every number), so the ranks
-  // are a permutation of 0..n-1
-  for (int i = tid; i < n; i += kHeigThreads) {
-    const double v = a[(size_t)i * n + i].x;
-    const bool vn = v != v;
-    int r = 0;
-    for (int j = 0; j < n; ++j) {
-      const double u = a[(size_t)j * n + j].x;
-      const bool un = u != u;
-      r += (un || vn) ? (un && vn ? j < i : !un) : (u < v || (u == v && j < i));
+    __syncthreads();
+    // w = p - (tau / 2) (p^H u) u
+    double2 kp = make_double2(0.0, 0.0);
+    for (int i = tid; i < m; i += kHeigThreads) {
+      const double2 t = zcmul(s_w[i], s_u[i]);
+      kp.x += t.x;
+      kp.y += t.y;
     }
-    w[r] = v;
+    const double2 K = heig_sum<NW>(kp, s_red[rb], tid);
+    rb ^= 1;
+    const double2 al = zmul(make_double2(-0.5 * tau.x, -0.5 * tau.y), K);
+    for (int i = tid; i < m; i += kHeigThreads) {
+      const double2 t = zmul(al, s_u[i]);
+      s_w[i] = make_double2(s_w[i].x + t.x, s_w[i].y + t.y);
+    }
+    __syncthreads();
+    // A22 <- A22 - u w^H - w u^H, column by column, rows across the lanes
+    for (int j = wv; j < m; j += NW) {
+      const double2 cw = make_double2(s_w[j].x, -s_w[j].y), cu = make_double2(s_u[j].x, -s_u[j].y);
+      double2* cj = a + k1 + (size_t)(k1 + j) * n;
+      for (int i = lane; i < m; i += 64) {
+        const double2 t1 = zmul(s_u[i], cw), t2 = zmul(s_w[i], cu);
+        cj[i] = make_double2(cj[i].x - t1.x - t2.x, cj[i].y - t1.y - t2.y);
+      }
+    }
+    __syncthreads();
   }
-  if (tid == 0) *info = done ? sweep : -1;
+  if (tid == 0) {
+    if (n >= 2) {
+      const double2 l = a[(n - 1) + (size_t)(n - 2) * n];
+      s_d[n - 2] = a[(n - 2) + (size_t)(n - 2) * n].x;
+      s_e2[n - 2] = l.x * l.x + l.y * l.y;
+    }
+    s_d[n - 1] = a[(n - 1) + (size_t)(n - 1) * n].x;
+  }
+  __syncthreads();
+  // Gershgorin interval of the tridiagonal (every thread the same)
+  double lo = HUGE_VAL, hi = -HUGE_VAL, emax = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double el = i > 0 ? sqrt(s_e2[i - 1]) : 0.0, er = i + 1 < n ? sqrt(s_e2[i]) : 0.0;
+    lo = fmin(lo, s_d[i] - el - er);
+    hi = fmax(hi, s_d[i] + el + er);
+    if (i + 1 < n) emax = fmax(emax, s_e2[i]);
+  }
+  const bool finite = lo - lo == 0.0 && hi - hi == 0.0;
+  // a pivot never smaller than this (keeps the Sturm recurrence finite)
+  const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax);
+  const double span = fmax(fabs(lo), fabs(hi));
+  lo -= 2.2e-16 * span + pivmin;
+  hi += 2.2e-16 * span + pivmin;
+  for (int t = tid; t < n; t += kHeigThreads) {
+    double x0 = lo, x1 = hi;
+    for (int it = 0; it < 128 && finite; ++it) {
+      const double mid = 0.5 * (x0 + x1);
+      if (x1 - x0 <= 4.5e-16 * fmax(fabs(x0), fabs(x1)) + 2.0 * pivmin || mid <= x0 || mid >= x1) break;
+      int cnt = 0;
+      double q = s_d[0] - mid;
+      if (fabs(q) < pivmin) q = -pivmin;
+      cnt += q < 0.0;
+      for (int i = 1; i < n; ++i) {
+        q = (s_d[i] - mid) - s_e2[i - 1] / q;
+        if (fabs(q) < pivmin) q = -pivmin;
+        cnt += q < 0.0;
+      }
+      if (cnt > t)
+        x1 = mid;
+      else
+        x0 = mid;
+    }
+    w[t] = finite ? 0.5 * (x0 + x1) : NAN;
+  }
+  if (tid == 0) *info = finite ? 0 : -1;
 }
 
 hipError_t launch_heig(double2* g, int n, double* w, int* info, hipStream_t s) {

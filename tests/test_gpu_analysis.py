@@ -43,7 +43,7 @@ def test_hermitian_eigenvalues_planted_spectrum(n, rank):
     _torch()
     import paper_2204_02348_amd as dh
     a, lam = _planted(n, rank, 100 + n + rank)
-    _say(f"Jacobi eigenvalues n={n} rank={rank}")
+    _say(f"eigenvalues n={n} rank={rank}")
     w = dh.hermitian_eigenvalues(a)
     err = np.abs(w - lam)
     assert err.max() <= 1e-12 * lam.max(), err.max()

@@ -41,7 +41,7 @@ def test_noalloc_eigenvalues_match_allocating_entry_point():
     # the second call reuses the same device array
     for n, seed in [(200, 7), (40, 8)]:
         a, lam = _planted(n, seed)
-        _say(f"no-alloc Jacobi eigenvalues n={n}")
+        _say(f"no-alloc eigenvalues n={n}")
         ref = dh.hermitian_eigenvalues(a)
         a_dev = torch.from_numpy(np.asfortranarray(a).ravel(order="F").view(np.float64).copy()).cuda()
         keep = a_dev.clone()
