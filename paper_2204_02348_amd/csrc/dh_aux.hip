@@ -209,7 +209,7 @@ hipError_t launch_tm_diag(const double2* g, int n, double* out, hipStream_t s) {
 // memory.
 constexpr int kHeigLds = 96;
 constexpr int kHeigMaxN = 2048;
-constexpr int kHeigThreads = 256;
+constexpr int kHeigThreads = 1024;
 
 __device__ __forceinline__ double2 zmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -248,6 +248,7 @@ __global__ void __launch_bounds__(kHeigThreads) k_heig(double2* __restrict__ g, 
   __shared__ double2 s_u[NV], s_w[NV];
   __shared__ double s_d[NV], s_e2[NV];
   __shared__ double s_red[2][2 * NW];
+  __shared__ double s_mm[3][NW];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   double2* a = IN_LDS ? lds : g;
   // the Hermitian part, both triangles (each pair read and written by one thread)
@@ -289,21 +290,30 @@ __global__ void __launch_bounds__(kHeigThreads) k_heig(double2* __restrict__ g, 
     const double2 sc = make_double2(den.x / dd, -den.y / dd);
     for (int i = tid; i < m; i += kHeigThreads) s_u[i] = i == 0 ? make_double2(1.0, 0.0) : zmul(col[i], sc);
     __syncthreads();
-    // p = tau A22 u: p_i = sum_j A22(i, j) u_j = sum_j conj(A22(j, i)) u_j,
-    // column k1 + i read contiguously, one wave per i
-    for (int i = wv; i < m; i += NW) {
-      const double2* ci = a + k1 + (size_t)(k1 + i) * n;
-      double2 acc = make_double2(0.0, 0.0);
-      for (int j = lane; j < m; j += 64) {
-        const double2 t = zcmul(ci[j], s_u[j]);
+    // p = tau A22 u: thread i sums row i, the lanes of a wave reading
+    // consecutive rows of each column (both triangles are stored)
+    for (int i = tid; i < m; i += kHeigThreads) {
+      const double2* ri = a + k1 + i + (size_t)k1 * n;
+      // (unrolled so that several loads are in flight; two partial sums)
+      double2 acc = make_double2(0.0, 0.0), acc2 = make_double2(0.0, 0.0);
+      int j = 0;
+      for (; j + 8 <= m; j += 8) {
+#pragma unroll
+        for (int q = 0; q < 8; q += 2) {
+          const double2 t = zmul(ri[(size_t)(j + q) * n], s_u[j + q]);
+          const double2 t2 = zmul(ri[(size_t)(j + q + 1) * n], s_u[j + q + 1]);
+          acc.x += t.x;
+          acc.y += t.y;
+          acc2.x += t2.x;
+          acc2.y += t2.y;
+        }
+      }
+      for (; j < m; ++j) {
+        const double2 t = zmul(ri[(size_t)j * n], s_u[j]);
         acc.x += t.x;
         acc.y += t.y;
       }
-      for (int off = 32; off > 0; off >>= 1) {
-        acc.x += __shfl_xor(acc.x, off, 64);
-        acc.y += __shfl_xor(acc.y, off, 64);
-      }
-      if (lane == 0) s_w[i] = zmul(tau, acc);
+      s_w[i] = zmul(tau, make_double2(acc.x + acc2.x, acc.y + acc2.y));
     }
     __syncthreads();
     // w = p - (tau / 2) (p^H u) u
@@ -322,12 +332,37 @@ __global__ void __launch_bounds__(kHeigThreads) k_heig(double2* __restrict__ g, 
     }
     __syncthreads();
     // A22 <- A22 - u w^H - w u^H, column by column, rows across the lanes
-    for (int j = wv; j < m; j += NW) {
-      const double2 cw = make_double2(s_w[j].x, -s_w[j].y), cu = make_double2(s_u[j].x, -s_u[j].y);
-      double2* cj = a + k1 + (size_t)(k1 + j) * n;
-      for (int i = lane; i < m; i += 64) {
-        const double2 t1 = zmul(s_u[i], cw), t2 = zmul(s_w[i], cu);
-        cj[i] = make_double2(cj[i].x - t1.x - t2.x, cj[i].y - t1.y - t2.y);
+    if constexpr (IN_LDS) {
+      // each lane's u_i and w_i (at most two rows) held in registers across the columns
+      constexpr int RI = (kHeigLds + 63) / 64;
+      double2 ur[RI], wr[RI];
+#pragma unroll
+      for (int r = 0; r < RI; ++r) {
+        const int i = lane + 64 * r;
+        ur[r] = i < m ? s_u[i] : make_double2(0.0, 0.0);
+        wr[r] = i < m ? s_w[i] : make_double2(0.0, 0.0);
+      }
+#pragma unroll 2
+      for (int j = wv; j < m; j += NW) {
+        const double2 cw = make_double2(s_w[j].x, -s_w[j].y), cu = make_double2(s_u[j].x, -s_u[j].y);
+        double2* cj = a + k1 + (size_t)(k1 + j) * n;
+#pragma unroll
+        for (int r = 0; r < RI; ++r) {
+          const int i = lane + 64 * r;
+          if (i < m) {
+            const double2 t1 = zmul(ur[r], cw), t2 = zmul(wr[r], cu);
+            cj[i] = make_double2(cj[i].x - t1.x - t2.x, cj[i].y - t1.y - t2.y);
+          }
+        }
+      }
+    } else {
+      for (int j = wv; j < m; j += NW) {
+        const double2 cw = make_double2(s_w[j].x, -s_w[j].y), cu = make_double2(s_u[j].x, -s_u[j].y);
+        double2* cj = a + k1 + (size_t)(k1 + j) * n;
+        for (int i = lane; i < m; i += 64) {
+          const double2 t1 = zmul(s_u[i], cw), t2 = zmul(s_w[i], cu);
+          cj[i] = make_double2(cj[i].x - t1.x - t2.x, cj[i].y - t1.y - t2.y);
+        }
       }
     }
     __syncthreads();
@@ -341,13 +376,30 @@ __global__ void __launch_bounds__(kHeigThreads) k_heig(double2* __restrict__ g, 
     s_d[n - 1] = a[(n - 1) + (size_t)(n - 1) * n].x;
   }
   __syncthreads();
-  // Gershgorin interval of the tridiagonal (every thread the same)
+  // Gershgorin interval of the tridiagonal: each thread its rows, then the
+  // workgroup's extremes (every thread gets them)
   double lo = HUGE_VAL, hi = -HUGE_VAL, emax = 0.0;
-  for (int i = 0; i < n; ++i) {
+  for (int i = tid; i < n; i += kHeigThreads) {
     const double el = i > 0 ? sqrt(s_e2[i - 1]) : 0.0, er = i + 1 < n ? sqrt(s_e2[i]) : 0.0;
     lo = fmin(lo, s_d[i] - el - er);
     hi = fmax(hi, s_d[i] + el + er);
     if (i + 1 < n) emax = fmax(emax, s_e2[i]);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, off, 64));
+    hi = fmax(hi, __shfl_xor(hi, off, 64));
+    emax = fmax(emax, __shfl_xor(emax, off, 64));
+  }
+  if (lane == 0) {
+    s_mm[0][wv] = lo;
+    s_mm[1][wv] = hi;
+    s_mm[2][wv] = emax;
+  }
+  __syncthreads();
+  for (int k = 0; k < NW; ++k) {
+    lo = fmin(lo, s_mm[0][k]);
+    hi = fmax(hi, s_mm[1][k]);
+    emax = fmax(emax, s_mm[2][k]);
   }
   const bool finite = lo - lo == 0.0 && hi - hi == 0.0;
   // a pivot never smaller than this (keeps the Sturm recurrence finite)
@@ -355,26 +407,44 @@ __global__ void __launch_bounds__(kHeigThreads) k_heig(double2* __restrict__ g, 
   const double span = fmax(fabs(lo), fabs(hi));
   lo -= 2.2e-16 * span + pivmin;
   hi += 2.2e-16 * span + pivmin;
-  for (int t = tid; t < n; t += kHeigThreads) {
+  // K adjacent lanes per eigenvalue (a power of two up to 8, as the
+  // workgroup allows): each step they count at the K interior points that
+  // cut the interval into K + 1 equal parts, and the interval becomes the
+  // part where the count first exceeds the eigenvalue's index
+  const int K = n * 8 <= kHeigThreads ? 8 : n * 4 <= kHeigThreads ? 4 : n * 2 <= kHeigThreads ? 2 : 1;
+  const int per = kHeigThreads / K, sub = tid % K, g0 = lane & ~(K - 1);
+  for (int b0 = 0; b0 < n; b0 += per) {
+    const int t = b0 + tid / K;                   // this group's eigenvalue
     double x0 = lo, x1 = hi;
-    for (int it = 0; it < 128 && finite; ++it) {
-      const double mid = 0.5 * (x0 + x1);
-      if (x1 - x0 <= 4.5e-16 * fmax(fabs(x0), fabs(x1)) + 2.0 * pivmin || mid <= x0 || mid >= x1) break;
+    for (int it = 0; it < 128; ++it) {
+      const bool live = t < n && finite && x1 - x0 > 4.5e-16 * fmax(fabs(x0), fabs(x1)) + 2.0 * pivmin;
+      if (__ballot(live) == 0) break;             // the wave's groups are all done
+      const double h = (x1 - x0) / (K + 1);
+      const double xs = x0 + h * (sub + 1);
       int cnt = 0;
-      double q = s_d[0] - mid;
+      double q = s_d[0] - xs;
       if (fabs(q) < pivmin) q = -pivmin;
       cnt += q < 0.0;
+#pragma unroll 4
       for (int i = 1; i < n; ++i) {
-        q = (s_d[i] - mid) - s_e2[i - 1] / q;
+        // 1 / q: the hardware estimate refined by two Newton steps
+        double r = __builtin_amdgcn_rcp(q);
+        r = fma(r, fma(-q, r, 1.0), r);
+        r = fma(r, fma(-q, r, 1.0), r);
+        q = (s_d[i] - xs) - s_e2[i - 1] * r;
         if (fabs(q) < pivmin) q = -pivmin;
         cnt += q < 0.0;
       }
-      if (cnt > t)
-        x1 = mid;
-      else
-        x0 = mid;
+      const unsigned long long gb = (__ballot(cnt > t) >> g0) & ((1ull << K) - 1);
+      const int s1 = gb ? __builtin_ctzll(gb) : K;  // first point past the eigenvalue
+      if (live) {                                   // every lane of the group alike
+        const double nx0 = s1 > 0 ? x0 + h * s1 : x0;
+        const double nx1 = s1 < K ? x0 + h * (s1 + 1) : x1;
+        x0 = nx0;
+        x1 = nx1;
+      }
     }
-    w[t] = finite ? 0.5 * (x0 + x1) : NAN;
+    if (t < n && sub == 0) w[t] = finite ? 0.5 * (x0 + x1) : NAN;
   }
   if (tid == 0) *info = finite ? 0 : -1;
 }
