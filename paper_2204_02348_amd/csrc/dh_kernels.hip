@@ -423,6 +423,8 @@ struct CspecShape {
   // LDS of the pass, float2 (int2 for the mask rows, float for the powers)
   static constexpr int BUF = CG * ST, TWY = TWG ? 1 : twn<NY>(), MROW = WYP, SX = CG * GPM;
   static constexpr int SPILL = IN_BUF ? 1 : (NRED / 2 + CG * GPM);
+  // workgroups per CU that the LDS allows
+  static constexpr int WG_PER_CU = LDS_CU / ((BUF + TWY + MROW + SX + SPILL) * 8 + 16);
 };
 
 // The spectral column pass of box-column block cb of frame bl (within the
@@ -457,7 +459,9 @@ __device__ __forceinline__ void cspec_block(const KArgs& A, int b0, int cb, int 
   // the ys table has 16 KSW rows (wy rounded up to 16), zero from row by on.
   // The first DB steps' operands are loaded before the column FFT, the rest
   // DB steps ahead of their use (DB = KSW where they all fit in registers)
-  constexpr int DB = KSW * NT <= 24 ? KSW : 12 / NT;
+  // (up to 48 steps x tiles held where the LDS already limits the CU to two
+  // workgroups, so the registers are there)
+  constexpr int DB = KSW * NT <= (SH::WG_PER_CU <= 2 ? 48 : 24) ? KSW : 12 / NT;
   float bre[KSW][NT], bim[KSW][NT];
   const float2* yrow = P.ys + (4 * wv + (lane >> 4)) * gpt + (lane & 15);
 #pragma unroll
@@ -1206,7 +1210,11 @@ template <int N> constexpr int col_cg() { return N >= 2048 ? 4 : N >= 1024 ? 4 :
 // the spectral column pass: at 1024 rows with one mode tile 8 columns fit
 // (1024-row camera: 0.253 -> 0.230 ms per 256 frames; with two mode tiles
 // the larger workgroup costs occupancy and 4 stays faster)
-template <int N, int NT> constexpr int cspec_cg() { return N == 1024 && NT == 1 ? 8 : col_cg<N>(); }
+// 8 columns per spectral workgroup at 1024 points (except with mode chunks,
+// whose LDS would then allow one workgroup per CU): each workgroup reads the
+// whole ys table (WY x gp) from L2, so fewer, wider workgroups read it less
+// often (C5-shaped batch: 2.40 -> 2.31 ms per 1000 frames)
+template <int N, int NT, bool MC = false> constexpr int cspec_cg() { return N == 1024 && !MC ? 8 : col_cg<N>(); }
 
 template <int NX>
 static hipError_t row_n(const KArgs& a, const void* frames, int u16, int b0, int nb, hipStream_t s) {
@@ -1336,7 +1344,7 @@ int spectral_blocks(int ny, int wy, int bx, int gp) {
     return (bx + cgg - 1) / cgg;
   }
   int cg = 16;
-#define X(N) if (ny == N) cg = gp == 16 ? cspec_cg<N, 1>() : cspec_cg<N, 2>();
+#define X(N) if (ny == N) cg = gp == 16 ? cspec_cg<N, 1>() : gp == 32 ? cspec_cg<N, 2>() : cspec_cg<N, 2, true>();
   DH_FFT_SIZES(X)
 #undef X
   return (bx + cg - 1) / cg;
@@ -1345,7 +1353,7 @@ int spectral_blocks(int ny, int wy, int bx, int gp) {
 template <int NY, int WY, int NT, bool MC>
 static hipError_t cspec_nwt(const KArgs& a, int b0, int nb, hipStream_t s) {
   if constexpr (cspec_fits<NY, WY, NT>()) {
-    constexpr int CG = cspec_cg<NY, NT>();
+    constexpr int CG = cspec_cg<NY, NT, MC>();
     dim3 grid((a.bx + CG - 1) / CG, a.npol, nb);
     hipLaunchKernelGGL((k_cspec<NY, WY, CG, NT, MC>), grid, dim3(kTPB), 0, s, a, b0);
     return hipGetLastError();

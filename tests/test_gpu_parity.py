@@ -185,6 +185,8 @@ def test_largest_group_count(idx, path):
     (1, 0, 33, 2),       # 640x512, 2 pols: 64 mode columns, the second chunk mostly padding
     (1, 0, 64, 2),       # two full chunks
     (0, 0, 48, 1),       # 128x128: 16 box columns per workgroup, two A-row tiles
+    (3, 2, 40, 1),       # 1024x1024 u16 camera: 1024-point columns with mode chunks (4 per workgroup)
+    (4, 0, 30, 1),       # 1024x1024, 2 pols, G=30: 1024-point columns, 8 per workgroup, two mode tiles
     (3, 3, 64, 1),       # 2048x2048 u16 camera, W = 672
     (3, 3, 100, 1),      # the largest group count: 5050 modes per pol, four chunks
 ])
