@@ -49,7 +49,7 @@ struct PolGeom {
 };
 
 struct Geom {
-  int nx, ny, wx, wy, wyp, bx, by, G, gp, nmodes;
+  int nx, ny, wx, wy, wyp, wys, bx, by, G, gp, nmodes;
   double rx, ry, pxp, pyp;
   int mode = 1;          // IFFT resolution mode
   int fx = 0, fy = 0;    // field grid: W (mode 1) or N (mode 0)
@@ -150,6 +150,9 @@ int derive(const dh_params* p, Geom* g) {
   g->wx = field_len(g->rx);
   g->wy = field_len(g->ry);
   g->wyp = (g->wy + 15) / 16 * 16;
+  // rows of the spectral ys table: a multiple of 32 (zero past the box), the
+  // K extent of the widest column workgroup's MFMA steps
+  g->wys = (g->wy + 31) / 32 * 32;
   g->pxp = nx * pix / g->wx;
   g->pyp = ny * pix / g->wy;
   g->mode = p->ifft_mode;
@@ -275,7 +278,7 @@ Layout layout(const Geom& g, const dh_params* p, int max_batch, int chunk, int n
       L.pol_uys[q][t] = take((size_t)g.wyp * g.gp * 2);
     }
     L.pol_xs[q] = take(g.spec ? (size_t)g.bx * g.gp * 8 : 0);
-    L.pol_ys[q] = take(g.spec ? (size_t)g.wyp * g.gp * 8 : 0);
+    L.pol_ys[q] = take(g.spec ? (size_t)g.wys * g.gp * 8 : 0);
     L.pol_ex[q] = take(exports(g, p) ? (size_t)g.fx * 8 : 0);
     L.pol_ey[q] = take(exports(g, p) ? (size_t)g.fy * 8 : 0);
   }
@@ -527,7 +530,7 @@ PolTables pol_tables(const Geom& g, const PolGeom& P, const dh_params* p, int q,
     const std::vector<double> hx = hg_host(g.fpx, g.fx, waist, g.G), hy = hg_host(g.fpy, g.fy, waist, g.G);
     t.xs = spectral_axis(g.bx, g.bx, g.gp, g.G, P.uhi, g.fx, g.fpx, P.ax, p->defocus[q], lam, P.dx, pix, g.nx, 1.0,
                          hx);
-    t.ys = spectral_axis(g.by, g.wyp, g.gp, g.G, P.vhi, g.fy, g.fpy, P.ay, p->defocus[q], lam, P.dy, pix, g.ny,
+    t.ys = spectral_axis(g.by, g.wys, g.gp, g.G, P.vhi, g.fy, g.fpy, P.ay, p->defocus[q], lam, P.dy, pix, g.ny,
                          inv, hy);
   }
   if (exp) {
@@ -2317,7 +2320,7 @@ extern "C" int dh_set_wavelengths(dh_handle h, const double* lambdas, int count,
         t.mrow = take(g.by * 8); t.rhox = take(g.bx * 8); t.rhoy = take(g.by * 8);
         t.tx = take(g.wx * 8); t.ty = take(g.wy * 8);
         t.xs = g.spec ? take((size_t)g.bx * g.gp * 8) : 0;
-        t.ys = g.spec ? take((size_t)g.wyp * g.gp * 8) : 0;
+        t.ys = g.spec ? take((size_t)g.wys * g.gp * 8) : 0;
         t.ex = exp ? take((size_t)g.fx * 8) : 0;
         t.ey = exp ? take((size_t)g.fy * 8) : 0;
       }

@@ -400,16 +400,22 @@ __global__ void __launch_bounds__(kTPB) k_col(KArgs A, int b0) {
 // last pass's block; the A operands are then read at fixed offsets per step,
 // each lane reading its own real or imaginary part, and a transform stride of
 // 2 mod 16 puts the 32 lanes of a read in distinct banks.
-template <int NY, int WY, int CG, int NT, bool MC>
+// NWV waves per workgroup; each MFMA step takes 4 box rows per wave, so the
+// window rows are padded to a multiple of 4 NWV (the ys table has a multiple
+// of 32 rows, zero past the box, so either width reads inside it).
+template <int NY, int WY, int CG, int NT, bool MC, int NWV = 4>
 struct CspecShape {
-  static constexpr int WYP = (WY + 15) / 16 * 16;
+  static_assert(NWV == 4 || NWV == 8, "four or eight waves");
+  static constexpr int TPB = 64 * NWV;
+  static constexpr int RS = 4 * NWV;                      // box rows per round of steps
+  static constexpr int WYP = (WY + RS - 1) / RS * RS;
   static constexpr bool ROT = Lds<NY>::SWZ && last_ns<NY>() + WYP <= NY;
   static constexpr int ST = ROT ? NY + 2 : Lds<NY>::STRIDE;
   static constexpr int MT = (2 * CG + 15) / 16;          // A-row tiles
-  static constexpr int KSW = WYP / 16;                    // K steps per wave, at most
+  static constexpr int KSW = WYP / RS;                    // K steps per wave
   static constexpr int GP = 16 * NT;                      // mode columns per chunk
   static constexpr int GPM = MC ? kMaxGp : GP;            // mode columns held in LDS, at most
-  static constexpr int NRED = 4 * MT * NT * 2 * 256;      // floats: the waves' MFMA results
+  static constexpr int NRED = NWV * MT * NT * 2 * 256;    // floats: the waves' MFMA results
   static constexpr int NQ = CG * GP;                      // float2: one chunk of Q
   // with several chunks the window stays in buf until the last one
   static constexpr bool IN_BUF = !MC && NRED * 4 + NQ * 8 <= CG * ST * 8;
@@ -430,13 +436,14 @@ struct CspecShape {
 // The spectral column pass of box-column block cb of frame bl (within the
 // launch, frames from b0), pol p, from `in` (that frame and pol's t1; loads
 // with cache policy T1AUX); LDS arrays of CspecShape's sizes.
-template <int NY, int WY, int CG, int NT, bool MC, int T1AUX>
+template <int NY, int WY, int CG, int NT, bool MC, int T1AUX, int NWV = 4>
 __device__ __forceinline__ void cspec_block(const KArgs& A, int b0, int cb, int p, int bl, const float2* in,
                                             float2* buf, float2* twy, int2* s_mrow, float2* s_x, float* s_pw,
                                             float2* s_spill, int tid) {
-  using SH = CspecShape<NY, WY, CG, NT, MC>;
+  using SH = CspecShape<NY, WY, CG, NT, MC, NWV>;
   using LN = Lds<NY>;
-  using Q = Pass1<NY, CG, kTPB>;
+  constexpr int TPB = SH::TPB, RS = SH::RS;
+  using Q = Pass1<NY, CG, TPB>;
   constexpr int ST = SH::ST, MT = SH::MT, WYP = SH::WYP, KSW = SH::KSW, GP = SH::GP, GPM = SH::GPM;
   constexpr int NRED = SH::NRED, NQ = SH::NQ;
   constexpr bool IN_BUF = SH::IN_BUF, TWG = SH::TWG, ROT = SH::ROT;
@@ -448,27 +455,27 @@ __device__ __forceinline__ void cspec_block(const KArgs& A, int b0, int cb, int 
   const int gpt = MC ? A.gp : GP;                  // table row stride (mode columns)
   const int nch = MC ? gpt / GP : 1;               // chunks of NT mode tiles
   // tables first: their loads are in flight with the column loads
-  Staged<float2, TWG ? 1 : twn<NY>(), kTPB> stwy;
-  Staged<int2, WYP, kTPB> smr;
-  Staged<float2, CG * GPM, kTPB> sx;
+  Staged<float2, TWG ? 1 : twn<NY>(), TPB> stwy;
+  Staged<int2, WYP, TPB> smr;
+  Staged<float2, CG * GPM, TPB> sx;
   if constexpr (!TWG) stwy.load(A.tw_ny, twn<NY>(), tid);
   smr.load(P.mrow, A.by, tid);
   const int ncx = A.bx - jc0 < CG ? A.bx - jc0 : CG;
   sx.load(P.xs + (size_t)jc0 * gpt, ncx * gpt, tid);
-  // this wave's B operands: steps s = wv + 4 t, box rows i = 4 s + lane / 16;
-  // the ys table has 16 KSW rows (wy rounded up to 16), zero from row by on.
+  // this wave's B operands: steps s = wv + NWV t, box rows i = 4 s + lane / 16;
+  // the ys table has at least WYP rows, zero from row by on.
   // The first DB steps' operands are loaded before the column FFT, the rest
   // DB steps ahead of their use (DB = KSW where they all fit in registers)
-  // (up to 48 steps x tiles held where the LDS already limits the CU to two
-  // workgroups, so the registers are there)
-  constexpr int DB = KSW * NT <= (SH::WG_PER_CU <= 2 ? 48 : 24) ? KSW : 12 / NT;
+  // (up to 48 steps x tiles held where the LDS already limits a SIMD to two
+  // waves, so the registers are there)
+  constexpr int DB = KSW * NT <= (SH::WG_PER_CU * NWV / 4 <= 2 ? 48 : 24) ? KSW : 12 / NT;
   float bre[KSW][NT], bim[KSW][NT];
   const float2* yrow = P.ys + (4 * wv + (lane >> 4)) * gpt + (lane & 15);
 #pragma unroll
   for (int t = 0; t < DB; ++t)
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
-      const float2 y = yrow[t * 16 * gpt + nt * 16];
+      const float2 y = yrow[t * RS * gpt + nt * 16];
       bre[t][nt] = y.x;
       bim[t][nt] = y.y;
     }
@@ -480,9 +487,9 @@ __device__ __forceinline__ void cspec_block(const KArgs& A, int b0, int cb, int 
     const __amdgpu_buffer_rsrc_t rt = make_rsrc(in, (unsigned)(A.bx * NY * 8));
 #pragma unroll
     for (int it = 0; it < Q::IT; ++it) {
-      const int g = tid + it * kTPB;
+      const int g = tid + it * TPB;
       const int c = g / Q::NB, b = g % Q::NB;
-      const int j = (Q::TOTAL % kTPB == 0 || g < Q::TOTAL) && jc0 + c < A.bx ? jc0 + c : 0;
+      const int j = (Q::TOTAL % TPB == 0 || g < Q::TOTAL) && jc0 + c < A.bx ? jc0 + c : 0;
       if constexpr (Q::NB % 16 == 0) {
         const int voff = ((b >> 4) * A.bx + j) * 128 + (b & 15) * 8;
         const int rstride = (Q::NB / 16) * A.bx * 128;
@@ -496,7 +503,7 @@ __device__ __forceinline__ void cspec_block(const KArgs& A, int b0, int cb, int 
     if constexpr (!TWG) stwy.store(twy, twn<NY>(), make_float2(0.f, 0.f), tid);
     smr.store(s_mrow, A.by, make_int2(1, 0), tid);
     sx.store(s_x, ncx * gpt, make_float2(0.f, 0.f), tid);
-    fft_pass1_regs<NY, CG, ST, kTPB>(v, buf, tid);
+    fft_pass1_regs<NY, CG, ST, TPB>(v, buf, tid);
   }
   // window row i is bin (ky0 + i) mod NY; with ROT at slot rb + i
   int kyn = P.ky0 % NY;
@@ -504,21 +511,21 @@ __device__ __forceinline__ void cspec_block(const KArgs& A, int b0, int cb, int 
   const int rrot = kyn / last_ns<NY>(), rb = kyn - rrot * last_ns<NY>();
   if constexpr (ROT) {
     if constexpr (TWG)
-      fft_rest_rot<NY, CG, ST, kTPB>(buf, as_global(A.tw_ny), tid, rrot);
+      fft_rest_rot<NY, CG, ST, TPB>(buf, as_global(A.tw_ny), tid, rrot);
     else
-      fft_rest_rot<NY, CG, ST, kTPB>(buf, static_cast<const float2*>(twy), tid, rrot);
+      fft_rest_rot<NY, CG, ST, TPB>(buf, static_cast<const float2*>(twy), tid, rrot);
   } else {
     if constexpr (TWG)
-      fft_rest<NY, CG, ST, kTPB>(buf, as_global(A.tw_ny), tid);
+      fft_rest<NY, CG, ST, TPB>(buf, as_global(A.tw_ny), tid);
     else
-      fft_rest<NY, CG, ST, kTPB>(buf, static_cast<const float2*>(twy), tid);
+      fft_rest<NY, CG, ST, TPB>(buf, static_cast<const float2*>(twy), tid);
   }
   if (A.window) {
     // window = M * I~ = conj(val) (-1)^(u+v) Nx Ny at (v mod wy, u mod wx), as in k_col
     float2* win = A.window + ((size_t)(b0 + bl) * A.npol + p) * A.wy * A.wx;
     // the block's columns fastest across the threads: neighbouring box columns
     // are neighbouring cells of one window row (CG cells per row and lane group)
-    for (int e = tid; e < CG * WY; e += kTPB) {
+    for (int e = tid; e < CG * WY; e += TPB) {
       const int c = e % CG, q = e / CG;
       const int j = jc0 + c;
       const int i = box_of(-P.ky0, q, WY, P.byq);
@@ -545,7 +552,7 @@ __device__ __forceinline__ void cspec_block(const KArgs& A, int b0, int cb, int 
       for (int t = 0; t < DB; ++t)
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
-          const float2 y = yrow[t * 16 * gpt + ch * GP + nt * 16];
+          const float2 y = yrow[t * RS * gpt + ch * GP + nt * 16];
           bre[t][nt] = y.x;
           bim[t][nt] = y.y;
         }
@@ -578,13 +585,13 @@ __device__ __forceinline__ void cspec_block(const KArgs& A, int b0, int cb, int 
         if (t < KSW) {                              // read step t (compile-time after unrolling)
           mv[t] = s_mrow[i];                        // i < 16 KSW = WYP
           if constexpr (ROT) {
-            fr[t] = bfl[32 * t];
+            fr[t] = bfl[2 * RS * t];
           } else {
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) fv[t][mt] = buf[((mt * 16 + (lane & 15)) % CG) * ST + LN::at(vv)];
           }
-          i += 16;
-          vv += 16;
+          i += RS;
+          vv += RS;
           if (vv >= NY) vv -= NY;
         }
         const int u = t - DA;                       // step whose MFMAs run now
@@ -592,7 +599,7 @@ __device__ __forceinline__ void cspec_block(const KArgs& A, int b0, int cb, int 
           if (u + DB < KSW) {
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
-              const float2 y = yrow[(u + DB) * 16 * gpt + ch * GP + nt * 16];
+              const float2 y = yrow[(u + DB) * RS * gpt + ch * GP + nt * 16];
               bre[u + DB][nt] = y.x;
               bim[u + DB][nt] = y.y;
             }
@@ -636,14 +643,14 @@ __device__ __forceinline__ void cspec_block(const KArgs& A, int b0, int cb, int 
       if (lane == 0) s_pw[wv] = pw;
     }
     __syncthreads();
-    // Q[j][ch GP + n], the four waves summed in order
-    for (int e = tid; e < NQ; e += kTPB) {
+    // Q[j][ch GP + n], the waves summed in order
+    for (int e = tid; e < NQ; e += TPB) {
       const int j = e / GP, n = e % GP;
       const int nt = n >> 4, nn = n & 15;
       const int r0 = j, r1 = CG + j;              // rows of Re S and Im S
       float qr = 0.f, qi = 0.f;
 #pragma unroll
-      for (int w = 0; w < 4; ++w) {
+      for (int w = 0; w < NWV; ++w) {
         const float* b0r = red + (((w * MT + (r0 >> 4)) * NT + nt) * 2) * 256 + (r0 & 15) * 16 + nn;
         const float* b1r = red + (((w * MT + (r1 >> 4)) * NT + nt) * 2) * 256 + (r1 & 15) * 16 + nn;
         qr += b0r[0] + b1r[256];                  // a c + b d
@@ -655,9 +662,13 @@ __device__ __forceinline__ void cspec_block(const KArgs& A, int b0, int cb, int 
   }
   const int pstride = A.nmodes + 1;
   float2* part = A.partial + ((size_t)(bl * A.nblk + cb) * A.npol + p) * pstride;
-  if (tid == 0)
-    part[A.nmodes] = make_float2(A.capt ? (((s_pw[0] + s_pw[1]) + s_pw[2]) + s_pw[3]) * A.spow : 0.f, 0.f);
-  for (int e = tid; e < A.nmodes; e += kTPB) {
+  if (tid == 0) {
+    float pwt = 0.f;
+#pragma unroll
+    for (int w = 0; w < NWV; ++w) pwt += s_pw[w];
+    part[A.nmodes] = make_float2(A.capt ? pwt * A.spow : 0.f, 0.f);
+  }
+  for (int e = tid; e < A.nmodes; e += TPB) {
     const short2 mn = A.modes[e];
     float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
@@ -666,19 +677,19 @@ __device__ __forceinline__ void cspec_block(const KArgs& A, int b0, int cb, int 
   }
 }
 
-template <int NY, int WY, int CG, int NT, bool MC>
-__global__ void __launch_bounds__(kTPB) k_cspec(KArgs A, int b0) {
-  using SH = CspecShape<NY, WY, CG, NT, MC>;
+template <int NY, int WY, int CG, int NT, bool MC, int NWV>
+__global__ void __launch_bounds__(64 * NWV) k_cspec(KArgs A, int b0) {
+  using SH = CspecShape<NY, WY, CG, NT, MC, NWV>;
   __shared__ float2 buf[SH::BUF];
   __shared__ float2 twy[SH::TWY];
   __shared__ int2 s_mrow[SH::MROW];
   __shared__ float2 s_x[SH::SX];                 // xs rows of the block's columns
-  __shared__ float s_pw[4];
+  __shared__ float s_pw[NWV];
   __shared__ float2 s_spill[SH::SPILL];
   const int p = blockIdx.y, bl = blockIdx.z;
   const float2* in = A.t1 + ((size_t)(bl * A.npol + p) * A.bx) * NY;
-  cspec_block<NY, WY, CG, NT, MC, kT1Nt ? 2 : 0>(A, b0, blockIdx.x, p, bl, in, buf, twy, s_mrow, s_x, s_pw, s_spill,
-                                                 threadIdx.x);
+  cspec_block<NY, WY, CG, NT, MC, kT1Nt ? 2 : 0, NWV>(A, b0, blockIdx.x, p, bl, in, buf, twy, s_mrow, s_x, s_pw,
+                                                      s_spill, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1215,6 +1226,10 @@ template <int N> constexpr int col_cg() { return N >= 2048 ? 4 : N >= 1024 ? 4 :
 // whole ys table (WY x gp) from L2, so fewer, wider workgroups read it less
 // often (C5-shaped batch: 2.40 -> 2.31 ms per 1000 frames)
 template <int N, int NT, bool MC = false> constexpr int cspec_cg() { return N == 1024 && !MC ? 8 : col_cg<N>(); }
+// waves per spectral column workgroup: 8 from 1024 points, where the LDS
+// leaves room for two workgroups per CU (16 waves instead of 8; C5-shaped
+// batch 2.29 -> 2.20 ms per 1000 frames, the 1024^2 and 2048^2 cameras 3-4 %)
+template <int N> constexpr int cspec_waves() { return N >= 1024 ? 8 : 4; }
 
 template <int NX>
 static hipError_t row_n(const KArgs& a, const void* frames, int u16, int b0, int nb, hipStream_t s) {
@@ -1354,8 +1369,9 @@ template <int NY, int WY, int NT, bool MC>
 static hipError_t cspec_nwt(const KArgs& a, int b0, int nb, hipStream_t s) {
   if constexpr (cspec_fits<NY, WY, NT>()) {
     constexpr int CG = cspec_cg<NY, NT, MC>();
+    constexpr int NWV = cspec_waves<NY>();
     dim3 grid((a.bx + CG - 1) / CG, a.npol, nb);
-    hipLaunchKernelGGL((k_cspec<NY, WY, CG, NT, MC>), grid, dim3(kTPB), 0, s, a, b0);
+    hipLaunchKernelGGL((k_cspec<NY, WY, CG, NT, MC, NWV>), grid, dim3(64 * NWV), 0, s, a, b0);
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;
