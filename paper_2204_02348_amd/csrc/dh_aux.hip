@@ -248,7 +248,7 @@ __global__ void __launch_bounds__(kHeigThreads) k_heig(double2* __restrict__ g, 
   __shared__ double2 s_u[NV], s_w[NV];
   __shared__ double s_d[NV], s_e2[NV];
   __shared__ double s_red[2][2 * NW];
-  __shared__ double s_mm[3][NW];
+  __shared__ double s_mm[4][NW];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   double2* a = IN_LDS ? lds : g;
   // the Hermitian part, both triangles (each pair read and written by one thread)
@@ -378,30 +378,37 @@ __global__ void __launch_bounds__(kHeigThreads) k_heig(double2* __restrict__ g, 
   __syncthreads();
   // Gershgorin interval of the tridiagonal: each thread its rows, then the
   // workgroup's extremes (every thread gets them)
-  double lo = HUGE_VAL, hi = -HUGE_VAL, emax = 0.0;
+  // (fmin and fmax pass over NaN, so entries that are not finite are flagged
+  // on their own)
+  double lo = HUGE_VAL, hi = -HUGE_VAL, emax = 0.0, bad = 0.0;
   for (int i = tid; i < n; i += kHeigThreads) {
     const double el = i > 0 ? sqrt(s_e2[i - 1]) : 0.0, er = i + 1 < n ? sqrt(s_e2[i]) : 0.0;
     lo = fmin(lo, s_d[i] - el - er);
     hi = fmax(hi, s_d[i] + el + er);
     if (i + 1 < n) emax = fmax(emax, s_e2[i]);
+    const double e2 = i + 1 < n ? s_e2[i] : 0.0;
+    if (!(s_d[i] - s_d[i] == 0.0) || !(e2 - e2 == 0.0)) bad = 1.0;
   }
   for (int off = 32; off > 0; off >>= 1) {
     lo = fmin(lo, __shfl_xor(lo, off, 64));
     hi = fmax(hi, __shfl_xor(hi, off, 64));
     emax = fmax(emax, __shfl_xor(emax, off, 64));
+    bad = fmax(bad, __shfl_xor(bad, off, 64));
   }
   if (lane == 0) {
     s_mm[0][wv] = lo;
     s_mm[1][wv] = hi;
     s_mm[2][wv] = emax;
+    s_mm[3][wv] = bad;
   }
   __syncthreads();
   for (int k = 0; k < NW; ++k) {
     lo = fmin(lo, s_mm[0][k]);
     hi = fmax(hi, s_mm[1][k]);
     emax = fmax(emax, s_mm[2][k]);
+    bad = fmax(bad, s_mm[3][k]);
   }
-  const bool finite = lo - lo == 0.0 && hi - hi == 0.0;
+  const bool finite = bad == 0.0 && lo - lo == 0.0 && hi - hi == 0.0;
   // a pivot never smaller than this (keeps the Sturm recurrence finite)
   const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax);
   const double span = fmax(fabs(lo), fabs(hi));

@@ -51,6 +51,35 @@ def test_hermitian_eigenvalues_planted_spectrum(n, rank):
     assert np.all(err[big] <= 1e-5 * lam[big])
 
 
+@pytest.mark.parametrize("n", [5, 90, 130])
+def test_hermitian_eigenvalues_use_the_hermitian_part(n):
+    """A matrix that is not Hermitian: the eigenvalues are those of its
+    Hermitian part (A + A^H) / 2 (numpy's eigvalsh of that part), in the
+    LDS form and in the global-memory form."""
+    _torch()
+    import paper_2204_02348_amd as dh
+    rng = np.random.default_rng(500 + n)
+    a = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    _say(f"eigenvalues of the Hermitian part, n={n}")
+    w = dh.hermitian_eigenvalues(a)
+    ref = np.linalg.eigvalsh(0.5 * (a + a.conj().T))
+    assert np.abs(w - ref).max() <= 1e-12 * np.abs(ref).max(), np.abs(w - ref).max()
+
+
+def test_hermitian_eigenvalues_not_finite():
+    """Entries that are not finite: DH_ERR_ERROR (the kernel flags the
+    tridiagonal as not finite instead of returning numbers)."""
+    _torch()
+    import paper_2204_02348_amd as dh
+    a = np.eye(6, dtype=np.complex128)
+    a[2, 3] = np.nan
+    a[3, 2] = np.nan
+    _say("eigenvalues of a matrix with NaN entries")
+    with pytest.raises(dh.DhError) as e:
+        dh.hermitian_eigenvalues(a)
+    assert e.value.code == dh.ERR_ERROR
+
+
 def test_hermitian_eigenvalues_rejects():
     _torch()
     import paper_2204_02348_amd as dh
