@@ -169,6 +169,42 @@ def test_frame_alone_equals_frame_in_batch():
     assert np.array_equal(alone["coefs_norm"][0], batch["coefs_norm"][3])
 
 
+def _small_cfg(kind):
+    """128x128 transforms: recipe 0 (G=4), recipe 2 (G=20, two mode tiles),
+    a 256x128 frame with two pols (G=9), and recipe 0 as uint16 (G=6)."""
+    from dh_synth.holograms import _base_params
+    if kind == "g4":
+        return dh_synth.config(0)
+    if kind == "g20":
+        return dh_synth.config(2)
+    cfg = dict(dh_synth.config(0))
+    if kind == "2pol":
+        p = _base_params(256, 128, 2, 128, 128, 200e-6, 9)
+    else:
+        p = _base_params(128, 128, 1, 128, 128, 200e-6, 6, dtype="u16")
+    cfg.update(params=p, truth=dict(p), dtype=p["input_dtype"])
+    return cfg
+
+
+@pytest.mark.parametrize("kind", ["g4", "g20", "2pol", "u16"])
+def test_small_frames_alone_equal_in_batch(kind):
+    """128-point transforms (one pol, two pols, one and two mode tiles, f32
+    and uint16): every frame of a 20-frame batch equals the same frame
+    processed alone, bit for bit (window too), and the frames match the
+    oracle."""
+    cfg = _small_cfg(kind)
+    f, _ = dh_synth.make_frames(cfg, n_frames=20)
+    p = cfg["params"]
+    _say(f"small frames {kind}: batch of 20 vs alone")
+    big = run_gpu(p, f, keep=True, path="spectral")
+    for i in (0, 7, 19):
+        alone = run_gpu(p, f[i:i + 1], keep=True, path="spectral")
+        assert np.array_equal(big["coefs"][i], alone["coefs"][0]), i
+        assert np.array_equal(big["coefs_norm"][i], alone["coefs_norm"][0]), i
+        assert np.array_equal(big["window"][i], alone["window"][0]), i
+    check_frames(p, f, big, [0, 19])
+
+
 @pytest.mark.parametrize("path", ["field", "spectral"])
 @pytest.mark.parametrize("idx", [0, 1])
 def test_largest_group_count(idx, path):
