@@ -267,7 +267,8 @@ def serving_bench(dh, torch, workers, seconds=10.0, warm=1.0, rate=5000.0, seed=
     camera from resident pools of 64 frames, continuous batching (lanes admitted
     by a 16 GiB budget, hipGraph launches). Latency = completion - arrival for
     requests arriving after the warm-up; plus the saturated rate (all requests
-    at once) next to a loop that processes one request at a time."""
+    at once, the second of two back-to-back runs) next to a loop that processes
+    one request at a time and to static batching through the plain batch path."""
     cams = [dh_synth.config(3, c) for c in range(4)]
     pools = []
     for cfg in cams:
@@ -304,9 +305,13 @@ def serving_bench(dh, torch, workers, seconds=10.0, warm=1.0, rate=5000.0, seed=
                                   "p99_ms": round(float(np.percentile(lat[m & (cam == c)], 99)), 4),
                                   "frames": int((m & (cam == c)).sum())} for c in range(4)}
     out["mean_batch"] = round(f / max(b, 1), 2)
-    # saturation: every request of a 20000-request trace present at once
+    # saturation: every request of a 20000-request trace present at once. The
+    # first such run after the light Poisson load is 10-20 % slower (lane
+    # workspaces first filled at full batch size, engine clock ramping), so
+    # one untimed run comes first, here and for the plain batch path below
     n = 20000
     tz = np.zeros(n)
+    srv.replay(tz, cam[:n], ptr[:n])
     done = srv.replay(tz, cam[:n], ptr[:n])
     out["saturated_frames_per_s"] = round(n / float(done.max()), 1)
     srv.destroy()
@@ -329,6 +334,7 @@ def serving_bench(dh, torch, workers, seconds=10.0, warm=1.0, rate=5000.0, seed=
         "frames_per_s": round(float(m.sum() / (done_b[m].max() - warm)), 1),
         "p50_ms": round(float(np.percentile(lat_b[m], 50)), 4), "p99_ms": round(float(np.percentile(lat_b[m], 99)), 4),
         "rounds": nb_rounds}
+    static_batching(dh, torch, plans, pools, np.zeros(n), cam[:n], max_batch=256)
     done_b, nb_rounds = static_batching(dh, torch, plans, pools, np.zeros(n), cam[:n], max_batch=256)
     out["static_batching"]["saturated_frames_per_s"] = round(n / float(done_b.max()), 1)
     for p in plans:
