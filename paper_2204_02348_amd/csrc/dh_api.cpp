@@ -1614,8 +1614,12 @@ int snap_plane(Plan* pl, const void* frames, int nb, hipStream_t s, double tilt[
                   dh::launch_psum(spec, nb, np, plane, pw, s) == hipSuccess &&
                   hipMemcpyAsync(hp.data(), pw, hp.size() * 4, hipMemcpyDeviceToHost, s) == hipSuccess &&
                   hipStreamSynchronize(s) == hipSuccess;
+  if (!ok) (void)hipStreamSynchronize(s);          // nothing still uses mem or hp when they go
   (void)hipFree(mem);
-  if (!ok) return DH_ERR_ERROR;
+  if (!ok) {
+    (void)hipGetLastError();
+    return DH_ERR_ERROR;
+  }
   const double binx = p.wavelength / (nx * p.pixel_size) / kDeg, biny = p.wavelength / (ny * p.pixel_size) / kDeg;
   auto sgn = [](int k, int n) { return k < n / 2 ? k : k - n; };        // signed bin of index k
   auto idx = [](int k, int n) { return ((k % n) + n) % n; };            // index of signed bin k
@@ -2051,8 +2055,12 @@ extern "C" int dh_hermitian_eigenvalues(const double* a_host, int n, double* w_h
                   hipMemcpyAsync(w.data(), mem + mb, (size_t)n * 8, hipMemcpyDeviceToHost, s) == hipSuccess &&
                   hipMemcpyAsync(&info, mem + mb + wb, sizeof(int), hipMemcpyDeviceToHost, s) == hipSuccess &&
                   hipStreamSynchronize(s) == hipSuccess;
+  if (!ok) (void)hipStreamSynchronize(s);          // nothing still reads mem when it is freed
   (void)hipFree(mem);
-  if (!ok) return DH_ERR_ERROR;
+  if (!ok) {
+    (void)hipGetLastError();
+    return DH_ERR_ERROR;
+  }
   if (info < 0) return DH_ERR_ERROR;
   std::memcpy(w_host, w.data(), (size_t)n * 8);     // ascending, as the kernel writes them
   return DH_SUCCESS;
