@@ -138,6 +138,77 @@ def test_config4_alignment_shape():
     check_frames(cfg["truth"], f, gpu, range(3))
 
 
+def run_gpu_tiled(params, pool, n):
+    """Process n frames (frame i = pool[i % len(pool)], tiled on the device)
+    in one dh_process_batch call with max_batch = n, as the benchmark launches
+    them (the library's own launch chunks); returns the coefficients."""
+    torch = _torch()
+    import paper_2204_02348_amd as dh
+    plan = dh.Plan(dict(params, keep_window=0, keep_fields=0), max_batch=n)
+    dev = torch.from_numpy(np.ascontiguousarray(pool)).cuda()
+    ft = dev.repeat(-(-n // pool.shape[0]), *([1] * (dev.dim() - 1)))[:n].contiguous()
+    del dev
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    plan.process(ft, n, s)
+    out = dict(coefs=plan.coefs(False), coefs_norm=plan.coefs(True), chunk=plan.info.chunk)
+    torch.cuda.synchronize()
+    plan.destroy()
+    del ft
+    return out
+
+
+def check_tiled(params, pool, gpu, idx, tol=TOL):
+    """Sampled frames of a tiled batch against the oracle (each distinct pool
+    frame computed once)."""
+    worst, refs = {}, {}
+    for i in idx:
+        q = i % pool.shape[0]
+        if q not in refs:
+            refs[q] = oracle.process_frame(pool[q].astype(np.float64), params)
+        for k in ("coefs", "coefs_norm"):
+            for pol in range(params["pol_count"]):
+                worst[k] = max(worst.get(k, 0.0), _rel(gpu[k][i][pol].astype(np.complex128), refs[q][k][pol]))
+    _say("worst rel-L2", {k: f"{v:.2e}" for k, v in worst.items()})
+    for k, v in worst.items():
+        assert v <= tol, (k, v)
+
+
+def test_config2_g20_full_batch_sampled():
+    """The G = 20 throughput form at the 640x512 batch shape: 1000 frames in
+    one call, as timed by the benchmark."""
+    cfg, pool, _ = _frames(1, n=10)
+    params = dict(cfg["params"], max_mg=20)
+    _say("640x512 2 pols G=20 batch 1000 (benchmark launch), sampled frames")
+    gpu = run_gpu_tiled(params, pool, 1000)
+    check_tiled(params, pool, gpu, [0, 1, 499, 500, 998, 999])
+
+
+@pytest.mark.parametrize("cam", [0, 1, 2, 3])
+def test_config3_cameras_full_batch_sampled(cam):
+    """Each camera's batch as the benchmark times it (256 frames, 64 for the
+    2048 x 2048 camera), uint16 pixels."""
+    cfg, pool, _ = _frames(3, cam=cam, n=4 if cam < 3 else 2)
+    n = 256 if cam < 3 else 64
+    _say("camera", cam, "batch", n, "(benchmark launch), sampled frames")
+    gpu = run_gpu_tiled(cfg["params"], pool, n)
+    check_tiled(cfg["params"], pool, gpu, [0, 1, n // 2 + 1, n - 1])
+
+
+def test_config4_decomposition_full_batch_sampled():
+    """The 5000-frame 1024x1024 two-pol G = 30 decomposition in one call: the
+    library splits it into launch chunks (2 GiB of workspace each); frames on
+    both sides of every chunk boundary against the oracle."""
+    cfg, pool, _ = _frames(4, n=3)
+    n = 5000
+    _say("1024x1024 2 pols G=30 batch 5000 (benchmark launch), frames at the chunk boundaries")
+    gpu = run_gpu_tiled(cfg["truth"], pool, n)
+    c = gpu["chunk"]
+    assert 0 < c < n, c
+    idx = sorted({0, n - 1} | {i for k in range(c, n, c) for i in (k - 1, k)})
+    check_tiled(cfg["truth"], pool, gpu, idx)
+
+
 def test_subpixel_centre_defocus_and_per_pol_tilt():
     cfg = dh_synth.config(1)
     # 256x256 windows inside the 320x512 halves, so the beam centres can move
