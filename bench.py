@@ -384,7 +384,7 @@ def static_batching(dh, torch, plans, pools, t, cam, max_batch=256):
     return done, rounds
 
 
-def camera_batches(dh, torch, workers, batch=256, steps=10, warmup=10):
+def camera_batches(dh, torch, workers, batch=256, steps=40, warmup=10, settle_s=0.1):
     """Batch throughput of each serving camera's plan on its own (uint16
     frames, 1 pol), with the fraction of the binding ceiling."""
     out = {}
@@ -395,8 +395,16 @@ def camera_batches(dh, torch, workers, batch=256, steps=10, warmup=10):
         ft = torch.from_numpy(dh_synth.tile_pool(pool, b)).to("cuda:0")
         plan = dh.Plan(cfg["params"], max_batch=b)
         stream = torch.cuda.Stream()
-        for _ in range(warmup):
+        # warm-up by elapsed time, not by a step count: a step here is 0.04-0.7 ms,
+        # and the VALU-bound column passes run slower until the engine clock has
+        # ramped under ~20 ms of sustained work
+        t0 = time.perf_counter()
+        k = 0
+        while k < warmup or time.perf_counter() - t0 < settle_s:
             plan.process(ft, b, stream)
+            k += 1
+            if k % 8 == 0:
+                stream.synchronize()
         stream.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
