@@ -119,6 +119,21 @@ def counter_traffic(stage, info, frames_per_launch):
     return None
 
 
+def warm(plan, ft, n, stream, min_steps, min_s=0.06):
+    """Untimed steps until at least min_steps have run and min_s of wall time
+    has passed: the VALU-bound column passes run slower until the engine
+    clock has ramped under ~20 ms of sustained work, and a count of short
+    steps alone can end inside that ramp."""
+    t0 = time.perf_counter()
+    k = 0
+    while k < min_steps or time.perf_counter() - t0 < min_s:
+        plan.process(ft, n, stream)
+        k += 1
+        if k % 8 == 0:
+            stream.synchronize()
+    stream.synchronize()
+
+
 def time_forms(dh, torch, cfg, ft, B, stream, steps=20, warmup=20):
     """frames/s and per-stage time of the coefficient forms on the same frames,
     at G=9 and G=20: plain FP32 on the field path and (where it applies) on
@@ -135,19 +150,22 @@ def time_forms(dh, torch, cfg, ft, B, stream, steps=20, warmup=20):
             if dh.plan_check(d, B)[0] != dh.SUCCESS:
                 continue
             plan = dh.Plan(d, max_batch=B)
-            for _ in range(warmup):
-                plan.process(ft, B, stream)
-            stream.synchronize()
-            plan.set_stage_timing(True)
+            warm(plan, ft, B, stream, warmup)
+            # frames/s from a window without per-launch events, then the
+            # stage times from a second window with them
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
             for _ in range(steps):
                 plan.process(ft, B, stream)
             e1.record(stream)
             torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            plan.set_stage_timing(True)
+            for _ in range(steps):
+                plan.process(ft, B, stream)
+            torch.cuda.synchronize()
             st = plan.stage_times()
             plan.destroy()
-            ms = e0.elapsed_time(e1)
             name = f"G{groups}_{prec}_{path}" + ("" if mode else "_mode0") + ("_fields" if fields else "")
             out[name] = {
                 "frames_per_s": round(steps * B / (ms / 1e3), 1),
@@ -175,9 +193,7 @@ def time_variants(dh, torch, cfg, ft, B, stream, steps=20, warmup=10):
             n_out = B // 4
         else:
             plan.set_basis(dh.BASIS_LG)
-        for _ in range(warmup):
-            plan.process(ft, n_out, stream)
-        stream.synchronize()
+        warm(plan, ft, n_out, stream, warmup)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         for _ in range(steps):
@@ -395,17 +411,7 @@ def camera_batches(dh, torch, workers, batch=256, steps=40, warmup=10, settle_s=
         ft = torch.from_numpy(dh_synth.tile_pool(pool, b)).to("cuda:0")
         plan = dh.Plan(cfg["params"], max_batch=b)
         stream = torch.cuda.Stream()
-        # warm-up by elapsed time, not by a step count: a step here is 0.04-0.7 ms,
-        # and the VALU-bound column passes run slower until the engine clock has
-        # ramped under ~20 ms of sustained work
-        t0 = time.perf_counter()
-        k = 0
-        while k < warmup or time.perf_counter() - t0 < settle_s:
-            plan.process(ft, b, stream)
-            k += 1
-            if k % 8 == 0:
-                stream.synchronize()
-        stream.synchronize()
+        warm(plan, ft, b, stream, warmup, settle_s)    # a step here is 0.04-0.7 ms
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         for _ in range(steps):
