@@ -210,6 +210,7 @@ hipError_t launch_tm_diag(const double2* g, int n, double* out, hipStream_t s) {
 constexpr int kHeigLds = 96;
 constexpr int kHeigMaxN = 2048;
 constexpr int kHeigThreads = 1024;
+constexpr int kHeigParts = 4;        // column ranges of the in-LDS matrix-vector product
 
 __device__ __forceinline__ double2 zmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -249,6 +250,8 @@ __global__ void __launch_bounds__(kHeigThreads) k_heig(double2* __restrict__ g, 
   __shared__ double s_d[NV], s_e2[NV];
   __shared__ double s_red[2][2 * NW];
   __shared__ double s_mm[4][NW];
+  __shared__ double2 s_part[IN_LDS ? kHeigParts : 1][IN_LDS ? 128 : 1];   // matrix-vector product, by column range
+  __shared__ double s_nrm;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   double2* a = IN_LDS ? lds : g;
   // the Hermitian part, both triangles (each pair read and written by one thread)
@@ -266,13 +269,19 @@ __global__ void __launch_bounds__(kHeigThreads) k_heig(double2* __restrict__ g, 
   }
   __syncthreads();
   int rb = 0;                                    // s_red half for the next sum
+  // squared norm of the first column's part below the subdiagonal; later
+  // steps get it from the wave that updates that column
+  double ss_next;
+  {
+    double2 part = make_double2(0.0, 0.0);
+    for (int i = 2 + tid; i < n; i += kHeigThreads) part.x += a[i].x * a[i].x + a[i].y * a[i].y;
+    ss_next = heig_sum<NW>(part, s_red[rb], tid).x;
+    rb ^= 1;
+  }
   for (int k = 0; k + 2 < n; ++k) {
     const int k1 = k + 1, m = n - k1;
     const double2* col = a + k1 + (size_t)k * n;   // x = A(k1 .., k), m entries
-    double2 part = make_double2(0.0, 0.0);
-    for (int i = 1 + tid; i < m; i += kHeigThreads) part.x += col[i].x * col[i].x + col[i].y * col[i].y;
-    const double ss = heig_sum<NW>(part, s_red[rb], tid).x;
-    rb ^= 1;
+    const double ss = ss_next;
     const double2 x0 = col[0];
     // every thread forms the same reflector from the same values
     const bool ident = ss == 0.0 && x0.y == 0.0;
@@ -282,7 +291,14 @@ __global__ void __launch_bounds__(kHeigThreads) k_heig(double2* __restrict__ g, 
       s_d[k] = a[k + (size_t)k * n].x;
       s_e2[k] = beta * beta;
     }
-    if (ident) continue;                          // H = I (uniform across the workgroup)
+    if (ident) {                                  // H = I (uniform across the workgroup)
+      double2 part = make_double2(0.0, 0.0);
+      const double2* nx = a + k1 + (size_t)k1 * n;  // the next column, unchanged
+      for (int i = 2 + tid; i < m; i += kHeigThreads) part.x += nx[i].x * nx[i].x + nx[i].y * nx[i].y;
+      ss_next = heig_sum<NW>(part, s_red[rb], tid).x;
+      rb ^= 1;
+      continue;
+    }
     const double2 tau = make_double2((beta - x0.x) / beta, -x0.y / beta);
     // u = x / (x0 - beta), u(0) = 1
     const double2 den = make_double2(x0.x - beta, x0.y);
@@ -290,48 +306,82 @@ __global__ void __launch_bounds__(kHeigThreads) k_heig(double2* __restrict__ g, 
     const double2 sc = make_double2(den.x / dd, -den.y / dd);
     for (int i = tid; i < m; i += kHeigThreads) s_u[i] = i == 0 ? make_double2(1.0, 0.0) : zmul(col[i], sc);
     __syncthreads();
-    // p = tau A22 u: thread i sums row i, the lanes of a wave reading
-    // consecutive rows of each column (both triangles are stored)
-    for (int i = tid; i < m; i += kHeigThreads) {
-      const double2* ri = a + k1 + i + (size_t)k1 * n;
-      // (unrolled so that several loads are in flight; two partial sums)
-      double2 acc = make_double2(0.0, 0.0), acc2 = make_double2(0.0, 0.0);
-      int j = 0;
-      for (; j + 8 <= m; j += 8) {
+    // p = tau A22 u (into s_w) and the partial sums of p^H u. Rows across the
+    // lanes of a wave (consecutive rows of each column: both triangles are
+    // stored); in LDS the columns are split into kHeigParts ranges summed by
+    // separate threads, then added in range order.
+    double2 kp = make_double2(0.0, 0.0);
+    if constexpr (IN_LDS) {
+      const int i = tid & 127, part = tid >> 7;
+      const int q = (m + kHeigParts - 1) / kHeigParts, j0 = part * q, j1 = j0 + q < m ? j0 + q : m;
+      if (part < kHeigParts && i < m) {
+        const double2* ri = a + k1 + i + (size_t)k1 * n;
+        double2 acc = make_double2(0.0, 0.0), acc2 = make_double2(0.0, 0.0);
+        int j = j0;
+        for (; j + 4 <= j1; j += 4) {
 #pragma unroll
-        for (int q = 0; q < 8; q += 2) {
-          const double2 t = zmul(ri[(size_t)(j + q) * n], s_u[j + q]);
-          const double2 t2 = zmul(ri[(size_t)(j + q + 1) * n], s_u[j + q + 1]);
+          for (int t = 0; t < 4; t += 2) {
+            const double2 x = zmul(ri[(size_t)(j + t) * n], s_u[j + t]);
+            const double2 x2 = zmul(ri[(size_t)(j + t + 1) * n], s_u[j + t + 1]);
+            acc.x += x.x;
+            acc.y += x.y;
+            acc2.x += x2.x;
+            acc2.y += x2.y;
+          }
+        }
+        for (; j < j1; ++j) {
+          const double2 x = zmul(ri[(size_t)j * n], s_u[j]);
+          acc.x += x.x;
+          acc.y += x.y;
+        }
+        s_part[part][i] = make_double2(acc.x + acc2.x, acc.y + acc2.y);
+      }
+      __syncthreads();
+      if (tid < m) {
+        double2 pr = s_part[0][tid];
+#pragma unroll
+        for (int q2 = 1; q2 < kHeigParts; ++q2) pr = make_double2(pr.x + s_part[q2][tid].x, pr.y + s_part[q2][tid].y);
+        const double2 pw = zmul(tau, pr);
+        s_w[tid] = pw;
+        kp = zcmul(pw, s_u[tid]);
+      }
+    } else {
+      for (int i = tid; i < m; i += kHeigThreads) {
+        const double2* ri = a + k1 + i + (size_t)k1 * n;
+        // (unrolled so that several loads are in flight; two partial sums)
+        double2 acc = make_double2(0.0, 0.0), acc2 = make_double2(0.0, 0.0);
+        int j = 0;
+        for (; j + 8 <= m; j += 8) {
+#pragma unroll
+          for (int q = 0; q < 8; q += 2) {
+            const double2 t = zmul(ri[(size_t)(j + q) * n], s_u[j + q]);
+            const double2 t2 = zmul(ri[(size_t)(j + q + 1) * n], s_u[j + q + 1]);
+            acc.x += t.x;
+            acc.y += t.y;
+            acc2.x += t2.x;
+            acc2.y += t2.y;
+          }
+        }
+        for (; j < m; ++j) {
+          const double2 t = zmul(ri[(size_t)j * n], s_u[j]);
           acc.x += t.x;
           acc.y += t.y;
-          acc2.x += t2.x;
-          acc2.y += t2.y;
         }
+        const double2 pw = zmul(tau, make_double2(acc.x + acc2.x, acc.y + acc2.y));
+        s_w[i] = pw;
+        const double2 t = zcmul(pw, s_u[i]);
+        kp.x += t.x;
+        kp.y += t.y;
       }
-      for (; j < m; ++j) {
-        const double2 t = zmul(ri[(size_t)j * n], s_u[j]);
-        acc.x += t.x;
-        acc.y += t.y;
-      }
-      s_w[i] = zmul(tau, make_double2(acc.x + acc2.x, acc.y + acc2.y));
     }
-    __syncthreads();
-    // w = p - (tau / 2) (p^H u) u
-    double2 kp = make_double2(0.0, 0.0);
-    for (int i = tid; i < m; i += kHeigThreads) {
-      const double2 t = zcmul(s_w[i], s_u[i]);
-      kp.x += t.x;
-      kp.y += t.y;
-    }
+    // w = p - (tau / 2) (p^H u) u, formed where it is used
     const double2 K = heig_sum<NW>(kp, s_red[rb], tid);
     rb ^= 1;
     const double2 al = zmul(make_double2(-0.5 * tau.x, -0.5 * tau.y), K);
-    for (int i = tid; i < m; i += kHeigThreads) {
-      const double2 t = zmul(al, s_u[i]);
-      s_w[i] = make_double2(s_w[i].x + t.x, s_w[i].y + t.y);
-    }
-    __syncthreads();
-    // A22 <- A22 - u w^H - w u^H, column by column, rows across the lanes
+    // A22 <- A22 - u w^H - w u^H, column by column, rows across the lanes; the
+    // wave of column 0 also sums the squared moduli of its new entries below
+    // row 1, the next step's norm
+    double nx2 = 0.0;
     if constexpr (IN_LDS) {
       // each lane's u_i and w_i (at most two rows) held in registers across the columns
       constexpr int RI = (kHeigLds + 63) / 64;
@@ -340,32 +390,46 @@ __global__ void __launch_bounds__(kHeigThreads) k_heig(double2* __restrict__ g, 
       for (int r = 0; r < RI; ++r) {
         const int i = lane + 64 * r;
         ur[r] = i < m ? s_u[i] : make_double2(0.0, 0.0);
-        wr[r] = i < m ? s_w[i] : make_double2(0.0, 0.0);
+        const double2 t = zmul(al, ur[r]);
+        wr[r] = i < m ? make_double2(s_w[i].x + t.x, s_w[i].y + t.y) : make_double2(0.0, 0.0);
       }
 #pragma unroll 2
       for (int j = wv; j < m; j += NW) {
-        const double2 cw = make_double2(s_w[j].x, -s_w[j].y), cu = make_double2(s_u[j].x, -s_u[j].y);
+        const double2 uj = s_u[j], tj = zmul(al, uj);
+        const double2 cw = make_double2(s_w[j].x + tj.x, -(s_w[j].y + tj.y)), cu = make_double2(uj.x, -uj.y);
         double2* cj = a + k1 + (size_t)(k1 + j) * n;
 #pragma unroll
         for (int r = 0; r < RI; ++r) {
           const int i = lane + 64 * r;
           if (i < m) {
             const double2 t1 = zmul(ur[r], cw), t2 = zmul(wr[r], cu);
-            cj[i] = make_double2(cj[i].x - t1.x - t2.x, cj[i].y - t1.y - t2.y);
+            const double2 nv = make_double2(cj[i].x - t1.x - t2.x, cj[i].y - t1.y - t2.y);
+            cj[i] = nv;
+            if (j == 0 && i >= 2) nx2 += nv.x * nv.x + nv.y * nv.y;
           }
         }
       }
     } else {
       for (int j = wv; j < m; j += NW) {
-        const double2 cw = make_double2(s_w[j].x, -s_w[j].y), cu = make_double2(s_u[j].x, -s_u[j].y);
+        const double2 uj = s_u[j], tj = zmul(al, uj);
+        const double2 cw = make_double2(s_w[j].x + tj.x, -(s_w[j].y + tj.y)), cu = make_double2(uj.x, -uj.y);
         double2* cj = a + k1 + (size_t)(k1 + j) * n;
         for (int i = lane; i < m; i += 64) {
-          const double2 t1 = zmul(s_u[i], cw), t2 = zmul(s_w[i], cu);
-          cj[i] = make_double2(cj[i].x - t1.x - t2.x, cj[i].y - t1.y - t2.y);
+          const double2 ui = s_u[i], ti = zmul(al, ui);
+          const double2 wi = make_double2(s_w[i].x + ti.x, s_w[i].y + ti.y);
+          const double2 t1 = zmul(ui, cw), t2 = zmul(wi, cu);
+          const double2 nv = make_double2(cj[i].x - t1.x - t2.x, cj[i].y - t1.y - t2.y);
+          cj[i] = nv;
+          if (j == 0 && i >= 2) nx2 += nv.x * nv.x + nv.y * nv.y;
         }
       }
     }
+    if (wv == 0) {
+      for (int off = 32; off > 0; off >>= 1) nx2 += __shfl_xor(nx2, off, 64);
+      if (lane == 0) s_nrm = nx2;
+    }
     __syncthreads();
+    ss_next = s_nrm;
   }
   if (tid == 0) {
     if (n >= 2) {
