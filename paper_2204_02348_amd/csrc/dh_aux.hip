@@ -246,12 +246,17 @@ __global__ void __launch_bounds__(kHeigThreads) k_heig(double2* __restrict__ g, 
   constexpr int NV = IN_LDS ? kHeigLds : kHeigMaxN;
   constexpr int NW = kHeigThreads / 64;
   __shared__ double2 lds[IN_LDS ? kHeigLds * kHeigLds : 1];
-  __shared__ double2 s_u[NV], s_w[NV];
+  // u of this step and (in LDS) of the next. The in-global form keeps one:
+  // its larger LDS allocation measured 45-55 % slower at n = 97 .. 250
+  __shared__ double2 s_u[IN_LDS ? 2 : 1][NV], s_w[NV];
   __shared__ double s_d[NV], s_e2[NV];
   __shared__ double s_red[2][2 * NW];
   __shared__ double s_mm[4][NW];
-  __shared__ double2 s_part[IN_LDS ? kHeigParts : 1][IN_LDS ? 128 : 1];   // matrix-vector product, by column range
+  __shared__ double2 s_part[IN_LDS ? kHeigParts : 1][IN_LDS ? kHeigLds : 1];  // matrix-vector product, by column range
   __shared__ double s_nrm;
+  __shared__ double2 s_ref;                        // the next step's tau, when s_rdy
+  __shared__ double s_beta;
+  __shared__ int s_rdy;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   double2* a = IN_LDS ? lds : g;
   // the Hermitian part, both triangles (each pair read and written by one thread)
@@ -278,15 +283,29 @@ __global__ void __launch_bounds__(kHeigThreads) k_heig(double2* __restrict__ g, 
     ss_next = heig_sum<NW>(part, s_red[rb], tid).x;
     rb ^= 1;
   }
+  // In LDS the wave that updates column 0 of the trailing block also forms
+  // the next step's reflector (its u in the other half of s_u, beta and tau in
+  // s_beta, s_ref); `ready` (uniform) says this step's reflector is there.
+  bool ready = false;
+  int ub = 0;                                    // s_u half of this step
   for (int k = 0; k + 2 < n; ++k) {
     const int k1 = k + 1, m = n - k1;
     const double2* col = a + k1 + (size_t)k * n;   // x = A(k1 .., k), m entries
-    const double ss = ss_next;
-    const double2 x0 = col[0];
-    // every thread forms the same reflector from the same values
-    const bool ident = ss == 0.0 && x0.y == 0.0;
-    const double nrm = sqrt(x0.x * x0.x + x0.y * x0.y + ss);
-    const double beta = ident ? x0.x : (x0.x >= 0.0 ? -nrm : nrm);
+    double beta;
+    double2 tau;
+    bool ident = false;
+    if (ready) {
+      beta = s_beta;
+      tau = s_ref;
+    } else {
+      // every thread forms the same reflector from the same values
+      const double ss = ss_next;
+      const double2 x0 = col[0];
+      ident = ss == 0.0 && x0.y == 0.0;
+      const double nrm = sqrt(x0.x * x0.x + x0.y * x0.y + ss);
+      beta = ident ? x0.x : (x0.x >= 0.0 ? -nrm : nrm);
+      tau = make_double2((beta - x0.x) / beta, -x0.y / beta);
+    }
     if (tid == 0) {
       s_d[k] = a[k + (size_t)k * n].x;
       s_e2[k] = beta * beta;
@@ -299,13 +318,16 @@ __global__ void __launch_bounds__(kHeigThreads) k_heig(double2* __restrict__ g, 
       rb ^= 1;
       continue;
     }
-    const double2 tau = make_double2((beta - x0.x) / beta, -x0.y / beta);
-    // u = x / (x0 - beta), u(0) = 1
-    const double2 den = make_double2(x0.x - beta, x0.y);
-    const double dd = den.x * den.x + den.y * den.y;
-    const double2 sc = make_double2(den.x / dd, -den.y / dd);
-    for (int i = tid; i < m; i += kHeigThreads) s_u[i] = i == 0 ? make_double2(1.0, 0.0) : zmul(col[i], sc);
-    __syncthreads();
+    double2* su = s_u[IN_LDS ? ub : 0];
+    if (!ready) {
+      // u = x / (x0 - beta), u(0) = 1
+      const double2 x0 = col[0];
+      const double2 den = make_double2(x0.x - beta, x0.y);
+      const double dd = den.x * den.x + den.y * den.y;
+      const double2 sc = make_double2(den.x / dd, -den.y / dd);
+      for (int i = tid; i < m; i += kHeigThreads) su[i] = i == 0 ? make_double2(1.0, 0.0) : zmul(col[i], sc);
+      __syncthreads();
+    }
     // p = tau A22 u (into s_w) and the partial sums of p^H u. Rows across the
     // lanes of a wave (consecutive rows of each column: both triangles are
     // stored); in LDS the columns are split into kHeigParts ranges summed by
@@ -321,8 +343,8 @@ __global__ void __launch_bounds__(kHeigThreads) k_heig(double2* __restrict__ g, 
         for (; j + 4 <= j1; j += 4) {
 #pragma unroll
           for (int t = 0; t < 4; t += 2) {
-            const double2 x = zmul(ri[(size_t)(j + t) * n], s_u[j + t]);
-            const double2 x2 = zmul(ri[(size_t)(j + t + 1) * n], s_u[j + t + 1]);
+            const double2 x = zmul(ri[(size_t)(j + t) * n], su[j + t]);
+            const double2 x2 = zmul(ri[(size_t)(j + t + 1) * n], su[j + t + 1]);
             acc.x += x.x;
             acc.y += x.y;
             acc2.x += x2.x;
@@ -330,7 +352,7 @@ __global__ void __launch_bounds__(kHeigThreads) k_heig(double2* __restrict__ g, 
           }
         }
         for (; j < j1; ++j) {
-          const double2 x = zmul(ri[(size_t)j * n], s_u[j]);
+          const double2 x = zmul(ri[(size_t)j * n], su[j]);
           acc.x += x.x;
           acc.y += x.y;
         }
@@ -343,7 +365,7 @@ __global__ void __launch_bounds__(kHeigThreads) k_heig(double2* __restrict__ g, 
         for (int q2 = 1; q2 < kHeigParts; ++q2) pr = make_double2(pr.x + s_part[q2][tid].x, pr.y + s_part[q2][tid].y);
         const double2 pw = zmul(tau, pr);
         s_w[tid] = pw;
-        kp = zcmul(pw, s_u[tid]);
+        kp = zcmul(pw, su[tid]);
       }
     } else {
       for (int i = tid; i < m; i += kHeigThreads) {
@@ -354,8 +376,8 @@ __global__ void __launch_bounds__(kHeigThreads) k_heig(double2* __restrict__ g, 
         for (; j + 8 <= m; j += 8) {
 #pragma unroll
           for (int q = 0; q < 8; q += 2) {
-            const double2 t = zmul(ri[(size_t)(j + q) * n], s_u[j + q]);
-            const double2 t2 = zmul(ri[(size_t)(j + q + 1) * n], s_u[j + q + 1]);
+            const double2 t = zmul(ri[(size_t)(j + q) * n], su[j + q]);
+            const double2 t2 = zmul(ri[(size_t)(j + q + 1) * n], su[j + q + 1]);
             acc.x += t.x;
             acc.y += t.y;
             acc2.x += t2.x;
@@ -363,13 +385,13 @@ __global__ void __launch_bounds__(kHeigThreads) k_heig(double2* __restrict__ g, 
           }
         }
         for (; j < m; ++j) {
-          const double2 t = zmul(ri[(size_t)j * n], s_u[j]);
+          const double2 t = zmul(ri[(size_t)j * n], su[j]);
           acc.x += t.x;
           acc.y += t.y;
         }
         const double2 pw = zmul(tau, make_double2(acc.x + acc2.x, acc.y + acc2.y));
         s_w[i] = pw;
-        const double2 t = zcmul(pw, s_u[i]);
+        const double2 t = zcmul(pw, su[i]);
         kp.x += t.x;
         kp.y += t.y;
       }
@@ -389,13 +411,57 @@ __global__ void __launch_bounds__(kHeigThreads) k_heig(double2* __restrict__ g, 
 #pragma unroll
       for (int r = 0; r < RI; ++r) {
         const int i = lane + 64 * r;
-        ur[r] = i < m ? s_u[i] : make_double2(0.0, 0.0);
+        ur[r] = i < m ? su[i] : make_double2(0.0, 0.0);
         const double2 t = zmul(al, ur[r]);
         wr[r] = i < m ? make_double2(s_w[i].x + t.x, s_w[i].y + t.y) : make_double2(0.0, 0.0);
       }
+      if (wv == 0) {
+        // column 0 first, then the next step's reflector from its rows 1 ..
+        // (x0 = row 1, norm over rows 2 ..), with the same formulas as above
+        const double2 cw = make_double2(wr[0].x, -wr[0].y);   // w_0 and u_0 = 1 sit in lane 0
+        const double2 w0 = make_double2(__shfl(cw.x, 0, 64), __shfl(cw.y, 0, 64));
+        const double2 cu = make_double2(1.0, 0.0);
+        double2 nv[RI];
+#pragma unroll
+        for (int r = 0; r < RI; ++r) {
+          const int i = lane + 64 * r;
+          nv[r] = make_double2(0.0, 0.0);
+          if (i < m) {
+            double2* c0 = a + k1 + (size_t)k1 * n;
+            const double2 t1 = zmul(ur[r], w0), t2 = zmul(wr[r], cu);
+            nv[r] = make_double2(c0[i].x - t1.x - t2.x, c0[i].y - t1.y - t2.y);
+            c0[i] = nv[r];
+            if (i >= 2) nx2 += nv[r].x * nv[r].x + nv[r].y * nv[r].y;
+          }
+        }
+        for (int off = 32; off > 0; off >>= 1) nx2 += __shfl_xor(nx2, off, 64);
+        const double2 x0n = make_double2(__shfl(nv[0].x, 1, 64), __shfl(nv[0].y, 1, 64));
+        const bool next = k + 3 < n && !(nx2 == 0.0 && x0n.y == 0.0);
+        if (next) {
+          const double nrm = sqrt(x0n.x * x0n.x + x0n.y * x0n.y + nx2);
+          const double bn = x0n.x >= 0.0 ? -nrm : nrm;
+          const double2 den = make_double2(x0n.x - bn, x0n.y);
+          const double dd = den.x * den.x + den.y * den.y;
+          const double2 sc = make_double2(den.x / dd, -den.y / dd);
+          double2* un = s_u[IN_LDS ? ub ^ 1 : 0];
+#pragma unroll
+          for (int r = 0; r < RI; ++r) {
+            const int i = lane + 64 * r;
+            if (i >= 1 && i < m) un[i - 1] = i == 1 ? make_double2(1.0, 0.0) : zmul(nv[r], sc);
+          }
+          if (lane == 0) {
+            s_beta = bn;
+            s_ref = make_double2((bn - x0n.x) / bn, -x0n.y / bn);
+          }
+        }
+        if (lane == 0) {
+          s_nrm = nx2;
+          s_rdy = next;
+        }
+      }
 #pragma unroll 2
-      for (int j = wv; j < m; j += NW) {
-        const double2 uj = s_u[j], tj = zmul(al, uj);
+      for (int j = wv == 0 ? NW : wv; j < m; j += NW) {
+        const double2 uj = su[j], tj = zmul(al, uj);
         const double2 cw = make_double2(s_w[j].x + tj.x, -(s_w[j].y + tj.y)), cu = make_double2(uj.x, -uj.y);
         double2* cj = a + k1 + (size_t)(k1 + j) * n;
 #pragma unroll
@@ -403,19 +469,17 @@ __global__ void __launch_bounds__(kHeigThreads) k_heig(double2* __restrict__ g, 
           const int i = lane + 64 * r;
           if (i < m) {
             const double2 t1 = zmul(ur[r], cw), t2 = zmul(wr[r], cu);
-            const double2 nv = make_double2(cj[i].x - t1.x - t2.x, cj[i].y - t1.y - t2.y);
-            cj[i] = nv;
-            if (j == 0 && i >= 2) nx2 += nv.x * nv.x + nv.y * nv.y;
+            cj[i] = make_double2(cj[i].x - t1.x - t2.x, cj[i].y - t1.y - t2.y);
           }
         }
       }
     } else {
       for (int j = wv; j < m; j += NW) {
-        const double2 uj = s_u[j], tj = zmul(al, uj);
+        const double2 uj = su[j], tj = zmul(al, uj);
         const double2 cw = make_double2(s_w[j].x + tj.x, -(s_w[j].y + tj.y)), cu = make_double2(uj.x, -uj.y);
         double2* cj = a + k1 + (size_t)(k1 + j) * n;
         for (int i = lane; i < m; i += 64) {
-          const double2 ui = s_u[i], ti = zmul(al, ui);
+          const double2 ui = su[i], ti = zmul(al, ui);
           const double2 wi = make_double2(s_w[i].x + ti.x, s_w[i].y + ti.y);
           const double2 t1 = zmul(ui, cw), t2 = zmul(wi, cu);
           const double2 nv = make_double2(cj[i].x - t1.x - t2.x, cj[i].y - t1.y - t2.y);
@@ -423,13 +487,18 @@ __global__ void __launch_bounds__(kHeigThreads) k_heig(double2* __restrict__ g, 
           if (j == 0 && i >= 2) nx2 += nv.x * nv.x + nv.y * nv.y;
         }
       }
-    }
-    if (wv == 0) {
-      for (int off = 32; off > 0; off >>= 1) nx2 += __shfl_xor(nx2, off, 64);
-      if (lane == 0) s_nrm = nx2;
+      if (wv == 0) {
+        for (int off = 32; off > 0; off >>= 1) nx2 += __shfl_xor(nx2, off, 64);
+        if (lane == 0) {
+          s_nrm = nx2;
+          s_rdy = 0;
+        }
+      }
     }
     __syncthreads();
     ss_next = s_nrm;
+    ready = s_rdy != 0;
+    if (ready) ub ^= 1;
   }
   if (tid == 0) {
     if (n >= 2) {
