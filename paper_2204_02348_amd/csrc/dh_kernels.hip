@@ -226,10 +226,28 @@ __device__ __forceinline__ void row_tiles(const KArgs& A, const TIn* __restrict_
   }
 }
 
+// Resident row-pass workgroups. The f32 two-tile passes measured faster with
+// fewer of them in flight per CU; the uint16 passes measured slower.
+//  - 320 points (640-wide two-pol frames): compiled for three waves per SIMD,
+//    so the compiler keeps all 64 frame loads of a thread in registers (129
+//    VGPRs instead of 89) and a CU runs four workgroups instead of six (1000
+//    frames: 0.378 -> 0.368 ms).
+//  - 512 points (1024-wide two-pol frames): the LDS footprint is raised so
+//    that two workgroups fit on a CU instead of four; the register budget
+//    alone does not limit residency (543 frames: 0.686 -> 0.613 ms).
+template <int NX, typename TIn, int TT> constexpr int row_wpe() {
+  return NX == 320 && TT == 2 && sizeof(TIn) == 4 ? 3 : 8;
+}
+template <int NX, typename TIn, int TT> constexpr int row_lds_floor() {   // bytes
+  return NX == 512 && TT == 2 && sizeof(TIn) == 4 ? 56 * 1024 : 0;
+}
+
 template <int NX, int TR, typename TIn, int TT>
-__global__ void __launch_bounds__(TR * NX / FftPlan<NX>::R0) k_row(KArgs A, const TIn* __restrict__ frames, int b0) {
+__global__ void __launch_bounds__(TR * NX / FftPlan<NX>::R0) __attribute__((amdgpu_waves_per_eu(1, row_wpe<NX, TIn, TT>())))
+k_row(KArgs A, const TIn* __restrict__ frames, int b0) {
   using RS = RowShape<NX, TR>;
-  __shared__ float2 buf[RS::BUF];
+  constexpr int FLOOR = (row_lds_floor<NX, TIn, TT>() - RS::TWS * 8) / 8;
+  __shared__ float2 buf[RS::BUF > FLOOR ? RS::BUF : FLOOR];
   __shared__ float2 tws[RS::TWS];
   const int p = blockIdx.y, bl = blockIdx.z;
   float2* out = A.t1 + (size_t)(bl * A.npol + p) * A.bx * A.ny;
